@@ -1,0 +1,321 @@
+/*
+ * rtm.h -- C ABI of the MI355X (gfx950) reverse-time-migration library.
+ *
+ * The library computes the data-parallel hot path of arXiv:2001.06444
+ * ("A workflow for seismic imaging with quantified uncertainty"):
+ *   - the acoustic isotropic two-way wave equation (Eq. 4), discretised
+ *     2nd order in time and 8th order in space (Sec. 3, Stage 2), with a
+ *     Cerjan absorbing sponge around each job's grid;
+ *   - the forward source wavefield, driven by the wavelet (Sec. 2.2);
+ *   - the source wavefield kept as snapshots (FP32, or BF16/FP16 with a
+ *     per-snapshot power-of-two scale) or rebuilt backward from saved
+ *     boundary rings (time reversal);
+ *   - the backward receiver wavefield, driven by the seismogram (Sec. 2.2),
+ *     computed as the exact discrete adjoint of the forward recursion
+ *     (Sec. 3: the reverse problem is kept coercive, after Givoli 2014);
+ *   - the zero-lag cross-correlation image (numerator of Eq. 5), optional
+ *     source illumination (denominator of Eq. 5), stacking over shots
+ *     (Fig. 2 caption), and running FP64 mean / standard deviation maps
+ *     over velocity samples (Sec. 2.3, Stage 3);
+ *   - the Stage-3 maps built from those statistics: the confidence index
+ *     (Eq. 6) and the std/mean ratio (Eq. 7), and the post-stack Laplacian
+ *     filter (Sec. 3, Stage 2).
+ *
+ * Discretisation (shared by every entry point):
+ *   u^{n+1} = G (2u^n + c (L u^n + f^n)) - G^2 u^{n-1},   c = v^2 dt^2,
+ * L the 17-point 8th-order Laplacian, G = g(d_z) g(d_x) with
+ * g(d) = exp(-(a d)^2), d the number of cells outside the physical window.
+ * Source term: f^n = w^n / (dx dz) at the source node.  Traces: d[n][r] =
+ * u^n(r), n = 0..nt-1 (d[0] = 0).  Receiver wavefield: R^{nt} = R^{nt+1} = 0,
+ * R^m = G(2R^{m+1} + c(L R^{m+1} + d[m] at receivers)) - G^2 R^{m+2}.
+ * Image: I = k sum_{n in N} S^n R^{n+1}, N = {0, k, 2k, ...}, n <= nt-2,
+ * over the physical window (k = snapshot stride; 1 in reconstruct mode).
+ *
+ * Conventions:
+ *   - Arrays are row-major [z][x] with x contiguous; traces are [t][receiver].
+ *   - Every pointer whose name ends in _dev is a caller-owned device pointer
+ *     on the context's device; _host pointers are host memory.  The library
+ *     never frees caller memory.
+ *   - Calls that take a context enqueue work on the context stream and
+ *     return before the work completes (stream-ordered), unless stated.
+ *   - Every function returns RTM_OK (0) or a negative RTM_E_* code.  A call
+ *     rejected by validation has done no device work.  rtm_last_error()
+ *     gives a human-readable detail for the calling thread's last failure.
+ */
+#ifndef RTM_H
+#define RTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+enum {
+    RTM_OK = 0,
+    RTM_E_INVAL = -1,     /* invalid argument or geometry */
+    RTM_E_CFL = -2,       /* v_max dt sqrt(1/dx^2 + 1/dz^2) above the stability limit */
+    RTM_E_NOMEM = -3,     /* arena too small for the request */
+    RTM_E_AGAIN = -4,     /* queue full; retry later */
+    RTM_E_NOTFOUND = -5,  /* unknown ticket or realization */
+    RTM_E_NONFINITE = -6, /* a wavefield became non-finite */
+    RTM_E_DEVICE = -7,    /* a HIP runtime call failed */
+    RTM_E_CANCELLED = -8  /* the job was cancelled */
+};
+
+/* ---- enumerations ---------------------------------------------------- */
+enum { RTM_SNAP_FP32 = 0, RTM_SNAP_BF16 = 1, RTM_SNAP_FP16 = 2 };
+enum { RTM_SRC_STORE = 0, RTM_SRC_RECONSTRUCT = 1 };
+enum { RTM_IMG_ILLUM = 1u };
+enum { RTM_JOB_QUEUED = 0, RTM_JOB_RUNNING = 1, RTM_JOB_DONE = 2, RTM_JOB_FAILED = 3,
+       RTM_JOB_CANCELLED = 4 };
+
+typedef struct rtm_ctx rtm_ctx;
+
+/* Physical model grid and time axis. */
+typedef struct {
+    int32_t nz, nx;  /* model rows (depth) and columns */
+    int32_t nb;      /* sponge width in cells, added on all four sides of a job window */
+    int32_t nt;      /* time samples (>= 2) */
+    float dz, dx;    /* grid spacing (m) */
+    float dt;        /* time step (s) */
+    float sponge_a;  /* Cerjan constant a; <= 0 selects 0.3 / nb */
+} rtm_grid;
+
+/* An on-grid node in model coordinates (row iz, column ix). */
+typedef struct {
+    int32_t iz, ix;
+} rtm_point;
+
+/* Source-wavefield handling and imaging options. */
+typedef struct {
+    int32_t src_mode;    /* RTM_SRC_STORE or RTM_SRC_RECONSTRUCT */
+    int32_t snap_dtype;  /* RTM_SNAP_*; store mode only */
+    int32_t snap_stride; /* k >= 1; store mode only (reconstruct images every step) */
+    uint32_t flags;      /* RTM_IMG_ILLUM: also accumulate sum k (S^n)^2 */
+} rtm_img_opts;
+
+/* ---- library-level helpers ------------------------------------------- */
+
+/* Static description of a status code. */
+const char *rtm_status_str(int status);
+
+/* Detail text of the calling thread's last failed call ("" if none). */
+const char *rtm_last_error(void);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int rtm_version(void);
+
+/* Courant number v_max dt sqrt(1/dx^2 + 1/dz^2) of a grid (host only). */
+double rtm_cfl_number(float v_max, float dt, float dz, float dx);
+
+/* Largest stable Courant number of the scheme (von Neumann limit,
+ * 2 / sqrt(|sum of the 1-D stencil symbol at the Nyquist wavenumber|)),
+ * about 0.78437; calls above it are rejected with RTM_E_CFL (Sec. 3: each
+ * migration checks its own CFL condition).  Host only. */
+double rtm_cfl_limit(void);
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.
+ *   arena_dev, arena_bytes: caller-owned device buffer the library
+ *     sub-allocates all its working memory from (wavefields, snapshot and
+ *     boundary storage, per-job images, statistics).  It must stay alive
+ *     until rtm_ctx_destroy.  arena_dev == NULL makes the library allocate
+ *     arena_bytes itself (freed at destroy).
+ *   hip_stream: hipStream_t the stream-ordered calls enqueue on (NULL =
+ *     the device's null stream).
+ *   flags: reserved, pass 0.
+ * On success *out receives the context. */
+int rtm_ctx_create(rtm_ctx **out, int device, void *arena_dev, size_t arena_bytes,
+                   void *hip_stream, uint32_t flags);
+
+/* Stop the scheduler, wait for all work, release the context. */
+int rtm_ctx_destroy(rtm_ctx *ctx);
+
+/* Wait until all work the context enqueued on its stream has finished. */
+int rtm_ctx_synchronize(rtm_ctx *ctx);
+
+/* ---- plain path (one launch per time step) --------------------------- */
+
+/* Forward modelling of one shot over the whole model (Eq. 4 with the
+ * wavelet as source term; Sec. 2.2).
+ *   vel_dev [nz][nx] velocity (m/s); wavelet_dev [nt] source samples w^n;
+ *   src: source node; rec_host [nrec]: receiver nodes (copied at call time);
+ *   traces_dev [nt][nrec] out: d[n][r] = u^n(r);
+ *   final_field_dev [nz][nx] out (nullable): u^{nt-1} on the model grid.
+ * Errors: RTM_E_INVAL (bad sizes/nodes), RTM_E_CFL, RTM_E_NOMEM. */
+int rtm_propagate(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
+                  const float *wavelet_dev, rtm_point src, int32_t nrec,
+                  const rtm_point *rec_host, float *traces_dev, float *final_field_dev);
+
+/* Reverse time migration of one shot on the aperture window
+ * [ix0, ix0 + width) of the model (Sec. 2.2, Eq. 5 numerator; Listing 1's
+ * per-shot forward + adjoint pair).
+ *   vel_dev [nz][nx]: migration velocity; the window's sponge takes the
+ *     window's edge velocities.
+ *   data_dev [nt][nrec]: seismogram injected at the receivers.
+ *   src, rec_host: nodes inside the window (model coordinates).
+ *   opts: source-wavefield mode, snapshot dtype and stride, flags.
+ *   image_dev [nz][nx]: the shot image is ADDED into columns [ix0, ix0+width)
+ *     (stack over shots).  illum_dev likewise (nullable; needs RTM_IMG_ILLUM).
+ * Errors: RTM_E_INVAL, RTM_E_CFL, RTM_E_NOMEM. */
+int rtm_migrate_shot(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
+                     const float *wavelet_dev, rtm_point src, int32_t nrec,
+                     const rtm_point *rec_host, const float *data_dev, int32_t ix0,
+                     int32_t width, const rtm_img_opts *opts, float *image_dev,
+                     float *illum_dev);
+
+/* ---- batched path ---------------------------------------------------- */
+
+/* One shot of a batch: source, window, receivers and its seismogram. */
+typedef struct {
+    rtm_point src;
+    int32_t ix0, width;        /* aperture window in model columns */
+    int32_t nrec;
+    const rtm_point *rec_host; /* [nrec], model coordinates */
+    const float *data_dev;     /* [nt][nrec] */
+} rtm_shot_desc;
+
+/* Migrate nshots shots of one model together: every time step of every
+ * shot advances in the same kernel launch, launches are replayed from a
+ * captured HIP graph, and the tile shape comes from the autotuner.
+ * Each shot's image is added into image_dev in shot order after all shots
+ * finish (deterministic stack).  Same argument meaning as
+ * rtm_migrate_shot; image_dev/illum_dev [nz][nx].
+ * Errors: RTM_E_INVAL, RTM_E_CFL, RTM_E_NOMEM (the whole batch must fit). */
+int rtm_migrate_batch(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
+                      const float *wavelet_dev, int32_t nshots, const rtm_shot_desc *shots_host,
+                      const rtm_img_opts *opts, float *image_dev, float *illum_dev);
+
+/* ---- ensemble / serving path ----------------------------------------- */
+
+/* Register velocity sample `realization` (copied into the arena; v_max is
+ * cached for the per-job CFL check).  Model size must equal the context's
+ * first registered model.  Re-registering a realization replaces it (only
+ * when no job of it is queued or running). */
+int rtm_model_register(rtm_ctx *ctx, int32_t realization, const float *vel_dev, int32_t nz,
+                       int32_t nx, const rtm_grid *grid);
+
+/* One RTM job of a stream (velocity sample x shot x aperture x nt). */
+typedef struct {
+    int32_t realization;
+    rtm_point src;             /* model coordinates */
+    int32_t ix0, width;        /* aperture window; receivers on every window
+                                  column at row rec_iz */
+    int32_t rec_iz;
+    int32_t nt;                /* time samples of this job (>= 2) */
+    const float *wavelet_dev;  /* [nt] */
+    const float *data_dev;     /* [nt][width]; must stay alive until DONE */
+    rtm_img_opts img;
+    uint32_t flags;            /* RTM_JOB_* accumulation flags below */
+    uint64_t user_tag;
+} rtm_job;
+
+enum {
+    RTM_JOB_ACC_STATS = 1u, /* add the job image to its realization's running mean/std */
+    RTM_JOB_ACC_STACK = 2u  /* add the job image to its realization's FP32 stack */
+};
+
+/* Queue a job (non-blocking).  Validation and the CFL check (cached v_max)
+ * happen here; a job larger than the whole arena returns RTM_E_NOMEM, a
+ * full queue RTM_E_AGAIN.  Memory pressure only delays admission. */
+int rtm_ensemble_submit(rtm_ctx *ctx, const rtm_job *job, uint64_t *ticket);
+
+/* Job state and timing. */
+typedef struct {
+    int32_t state;   /* RTM_JOB_* state */
+    int32_t status;  /* RTM_OK or the failure code */
+    double t_submit, t_admit, t_done; /* host monotonic seconds */
+    uint64_t grid_updates;            /* point updates the job performs */
+    uint64_t alg_bytes;               /* algorithmic HBM bytes of the job */
+    uint64_t user_tag;
+} rtm_job_info;
+
+/* Non-blocking status query.  When the job is DONE and image_dev is not
+ * NULL, its [nz][width] image is copied there (stream-ordered on the
+ * context stream).  A DONE/FAILED/CANCELLED job is forgotten after a poll
+ * that passes release = 1. */
+int rtm_ensemble_poll(rtm_ctx *ctx, uint64_t ticket, rtm_job_info *info, float *image_dev,
+                      int32_t release);
+
+/* Cancel a queued job (running jobs finish).  RTM_E_NOTFOUND if unknown. */
+int rtm_ensemble_cancel(rtm_ctx *ctx, uint64_t ticket);
+
+/* Block until every submitted job has finished (DONE, FAILED or CANCELLED). */
+int rtm_ensemble_drain(rtm_ctx *ctx);
+
+/* Running per-pixel statistics of a realization's job images (FP64
+ * Welford; a pixel's samples are the images whose window covers it).
+ *   mean_dev, std_dev [nz][nx] double (nullable), count_dev [nz][nx] int32
+ *   (nullable).  std is the sample standard deviation (n - 1); 0 where
+ *   count < 2.  Stream-ordered after every finished job's update. */
+int rtm_ensemble_stats(rtm_ctx *ctx, int32_t realization, double *mean_dev, double *std_dev,
+                       int32_t *count_dev);
+
+/* FP32 shot stack of a realization (sum of its RTM_JOB_ACC_STACK job
+ * images, window-placed) copied to stack_dev [nz][nx]. */
+int rtm_ensemble_stack(rtm_ctx *ctx, int32_t realization, float *stack_dev);
+
+/* ---- ensemble statistics over explicit images (Sec. 2.3) ------------- */
+
+/* FP64 Welford accumulator over [nz][nx] images (one per velocity sample). */
+typedef struct rtm_stats rtm_stats;
+
+int rtm_stats_create(rtm_ctx *ctx, rtm_stats **out, int32_t nz, int32_t nx);
+int rtm_stats_destroy(rtm_ctx *ctx, rtm_stats *st);
+/* Add one FP32 image [nz][width] whose columns are [ix0, ix0 + width). */
+int rtm_stats_add(rtm_ctx *ctx, rtm_stats *st, const float *image_dev, int32_t ix0,
+                  int32_t width);
+/* mean/std (double, nullable), count (int32, nullable) as in rtm_ensemble_stats. */
+int rtm_stats_get(rtm_ctx *ctx, rtm_stats *st, double *mean_dev, double *std_dev,
+                  int32_t *count_dev);
+
+/* ---- Stage-3 maps and post-stack filter ------------------------------ */
+
+/* Confidence index (Eq. 6): c = (s_max - s) / (s_max - s_min), s_min and
+ * s_max the extremes of std over pixels with count >= min_count; pixels
+ * below min_count get 0.  conf_dev [n] out (double). */
+int rtm_confidence_map(rtm_ctx *ctx, const double *std_dev, const int32_t *count_dev,
+                       int32_t n, int32_t min_count, double *conf_dev);
+
+/* Ratio map (Eq. 7): r = std / mean where |mean| > eps, else 0.
+ * ratio_dev [n] out (double). */
+int rtm_ratio_map(rtm_ctx *ctx, const double *std_dev, const double *mean_dev, int32_t n,
+                  double eps, double *ratio_dev);
+
+/* Post-stack Laplacian filter (Sec. 3: attenuates the low-frequency
+ * artefacts of the brute stack): out = -(8th-order Laplacian of img) with
+ * zero values outside the image.  img_dev/out_dev [nz][nx] float. */
+int rtm_laplacian_filter(rtm_ctx *ctx, const float *img_dev, int32_t nz, int32_t nx, float dz,
+                         float dx, float *out_dev);
+
+/* ---- observability --------------------------------------------------- */
+
+typedef struct {
+    uint64_t jobs_submitted, jobs_done, jobs_failed, jobs_cancelled;
+    uint64_t steps_launched;     /* time-step kernel launches */
+    uint64_t graph_replays;      /* hipGraph launches */
+    uint64_t grid_updates;       /* point updates performed by finished jobs */
+    uint64_t alg_bytes;          /* algorithmic HBM bytes of finished jobs */
+    uint64_t arena_bytes, arena_used, arena_peak;
+    int32_t tile_z;              /* tile height in use */
+    int32_t active_jobs, queued_jobs;
+    int32_t pad_;
+    /* last rtm_migrate_batch call: HIP-event time of its forward and backward
+     * phases (all launches of each, on the library's work stream), launch
+     * counts, and algorithmic HBM bytes of one launch of each phase */
+    float last_fwd_ms, last_bwd_ms;
+    int32_t last_fwd_launches, last_bwd_launches;
+    uint64_t last_fwd_launch_bytes, last_bwd_launch_bytes;
+} rtm_ctx_stats_t;
+
+int rtm_ctx_stats(rtm_ctx *ctx, rtm_ctx_stats_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTM_H */

@@ -289,3 +289,37 @@ def nthreads() -> int:
     if env and env.isdigit():
         return int(env)
     return os.cpu_count() or 1
+
+
+# ---------------------------------------------------------------------------
+# Stage-3 maps and the post-stack filter (Sec. 2.3, Eq. 6 and Eq. 7; Sec. 3)
+# ---------------------------------------------------------------------------
+
+def confidence_index(std, count=None, min_count=2):
+    """Eq. 6: c = (s_max - s) / (s_max - s_min), extremes over pixels with
+    count >= min_count (all pixels when count is None); 0 elsewhere and when
+    s_max == s_min."""
+    s = np.asarray(std, dtype=np.float64)
+    mask = np.ones(s.shape, bool) if count is None else np.asarray(count) >= min_count
+    out = np.zeros_like(s)
+    if not mask.any():
+        return out
+    lo, hi = s[mask].min(), s[mask].max()
+    if hi > lo:
+        out[mask] = (hi - s[mask]) / (hi - lo)
+    return out
+
+
+def ratio_map(std, mean, eps=0.0):
+    """Eq. 7: r = std / mean where |mean| > eps, else 0."""
+    s = np.asarray(std, dtype=np.float64)
+    m = np.asarray(mean, dtype=np.float64)
+    out = np.zeros_like(s)
+    ok = np.abs(m) > eps
+    out[ok] = s[ok] / m[ok]
+    return out
+
+
+def laplacian_filter(img, dz, dx):
+    """Post-stack Laplacian filter: -(8th-order Laplacian), zero outside the image."""
+    return -laplacian(img, dz, dx)

@@ -1,0 +1,105 @@
+// rtm_internal.h -- device-side job and tile descriptors shared by the HIP
+// kernels (rtm_kernels.hip) and the host runtime (rtm_runtime.hip).
+//
+// Memory layout of a job (all in the context arena, HBM):
+//   A job runs on its own padded grid: the physical aperture window
+//   (nz rows x nx columns) plus nb sponge cells on each side, nzp = nz + 2nb
+//   rows by nxp = nx + 2nb columns.  Each wavefield array is stored row-major
+//   with a row pitch `pitch` = roundup(nxp + 4, 64) floats (256-byte rows), so
+//   every row starts on a 256-byte boundary and ends with >= 4 zero columns
+//   that double as the left/right ghost cells of the 8th-order stencil.
+//   Five zero rows precede row 0 and the allocation extends to
+//   roundup(nzp, 64) + 5 rows, which covers the top/bottom ghost rows and the
+//   halo of the last tile row.  Points outside [0,nzp) x [0,nxp) are zero and
+//   are never written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtm {
+
+constexpr int kTileX = 64;       // tile width: one 64-lane wavefront per row
+constexpr int kHalo = 4;         // stencil radius
+constexpr int kLdsW = kTileX + 2 * kHalo;  // 72 floats per LDS row
+constexpr int kTopRows = 5;      // zero rows before padded row 0
+constexpr int kRowAlign = 64;    // rows rounded up to the tallest tile
+constexpr int kThreads = 256;    // 4 wavefronts per workgroup
+
+enum JobMode : int32_t { kModeModel = 0, kModeStore = 1, kModeRecon = 2 };
+enum PhaseSet : int { kPhFwd = 1, kPhBwd = 2, kPhAny = 3 };
+
+// Device descriptor of one job.  Read-only for the step kernel except the
+// arrays it points to.
+struct alignas(16) DevJob {
+  int32_t nzp, nxp, pitch, nz;     // padded rows/cols, row pitch, physical rows
+  int32_t nx, nb, nt, mode;        // physical cols, sponge width, time samples, JobMode
+  int32_t snap_dtype, snap_stride, flags, nsteps;  // snapshots; RTM_IMG_*; steps of the job
+  int32_t src_z, src_x, nrec, ring_len;            // padded source node; receivers; ring size
+  int32_t start_tick, tiles_x, tiles_z, pad0;      // first global tick; tile grid
+  float inv_cell, c0, kfac, pad1;  // 1/(dx dz); a0 (1/dz^2 + 1/dx^2); imaging weight k
+  float cz[4], cx[4];              // a_k / dz^2, a_k / dx^2, k = 1..4
+  const float* c;                  // v^2 dt^2, padded grid (field layout)
+  const float* gz;                 // sponge profile per padded row [nzp]
+  const float* gx;                 // sponge profile per padded column [nxp]
+  float* f[2];                     // source wavefield: S^n / u^n in f[n & 1]
+  float* r[2];                     // receiver wavefield: R^m in r[m & 1]
+  const float* wavelet;            // [nt]
+  const float* data;               // [nt][nrec] injected at receivers (migration)
+  float* traces;                   // [nt][nrec] sampled at receivers (modelling)
+  void* snap;                      // [nsnap][nz][nx] stored S^n (store mode)
+  float* ring;                     // [nt][ring_len] boundary ring of S^n (reconstruct)
+  uint32_t* maxbits;               // [nt] max |u^n| over the physical window (float bits)
+  float* image;                    // [nz][nx]
+  float* illum;                    // [nz][nx] or null
+  const int2* recs;                // receivers sorted by tile: {local index, receiver id}
+  uint32_t* health;                // [1] bit 0: a non-finite value was seen
+};
+
+// One tile of one job: rows [z0, z0+TZ), columns [x0, x0+64) of its padded grid.
+struct alignas(16) Tile {
+  int32_t job, z0, x0, rec_begin;
+  int32_t rec_count, pad0, pad1, pad2;
+};
+
+// Launch control block for graph-replayed launches: a launch's global step
+// is ctl->tick + its own offset; k_advance moves ctl->tick after each group.
+struct alignas(16) StepCtl {
+  int32_t tick;    // global step base; job step = tick + offset - start_tick
+  int32_t pad0;
+  int32_t ntiles;  // active tiles (read when a launch passes ntiles < 0)
+  int32_t pad1;
+};
+
+inline int64_t field_rows(int nzp) { return ((nzp + kRowAlign - 1) / kRowAlign) * kRowAlign + 2 * kTopRows; }
+inline int32_t field_pitch(int nxp) { return ((nxp + kHalo + 63) / 64) * 64; }
+inline int64_t field_floats(int nzp, int nxp) { return field_rows(nzp) * field_pitch(nxp); }
+inline int64_t field_origin(int nxp) { return (int64_t)kTopRows * field_pitch(nxp); }
+inline int32_t ring_len_of(int nz, int nx) { return 8 * (nz + nx - 8); }
+
+// ---- kernel launchers (rtm_kernels.hip) ----
+hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
+                       int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
+                       hipStream_t s);
+hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s);
+hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* host_job,
+                       float* c, float* gz, float* gx, float dt, float sponge_a, hipStream_t s);
+hipError_t launch_vmax(const float* vel, int nz, int model_nx, int ix0, int width,
+                       uint32_t* out_bits, hipStream_t s);
+hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int nz, int width,
+                        hipStream_t s);
+hipError_t launch_copy_phys(float* dst, const float* field, int nz, int nx, int nb, int pitch,
+                            hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model, const float* img,
+                          int nz, int width, int ix0, hipStream_t s);
+hipError_t launch_stats_out(const double* mean, const double* m2, const int32_t* count, int64_t n,
+                            double* mean_out, double* std_out, int32_t* count_out, hipStream_t s);
+hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int min_count,
+                             double* out, double* scratch2, hipStream_t s);
+hipError_t launch_ratio(const double* sd, const double* mean, int n, double eps, double* out,
+                        hipStream_t s);
+hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx, float* out,
+                            hipStream_t s);
+
+}  // namespace rtm

@@ -1,0 +1,694 @@
+// rtm_kernels.hip -- gfx950 kernels of the RTM hot path.
+//
+// The time-step kernel is the whole per-step work of every job in a launch
+// (arXiv:2001.06444, Sec. 2.2 and Sec. 3, Stage 2):
+//   forward step n:   u^{n+1} = G (2u^n + c (L u^n + w^n e_s/(dx dz))) - G^2 u^{n-1}
+//                     + boundary-ring save (reconstruct mode), snapshot write with
+//                       per-snapshot power-of-two scale (store mode), or trace
+//                       sampling (modelling);
+//   backward step m:  R^m = G (2R^{m+1} + c (L R^{m+1} + d^m at receivers)) - G^2 R^{m+2}
+//                     + source-wavefield S^m (time reversal of the forward recursion
+//                       on the physical interior with the ring restored, or the
+//                       decoded snapshot) + imaging I += k S^m R^{m+1} (Eq. 5 numerator).
+// The stencil is HBM-bound (~2 flop/byte), so it runs on the vector ALUs: a
+// workgroup owns a 64-column x TZ-row tile, stages the stencil operand with
+// its 4-cell halo in LDS using 16-byte loads, and each thread marches down a
+// column with the z-neighbours in registers.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rtm_internal.h"
+
+namespace rtm {
+
+// ---------------------------------------------------------------------------
+// 16-bit snapshot codec: q = RNE(x * s), x = q / s with s = 2^(15 - e) where
+// max|S^n| = f 2^e, f in [1/2, 1).  The scale is a power of two, so encoding
+// and decoding add no rounding beyond the 16-bit cast itself.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float snap_scale_from_bits(uint32_t maxbits) {
+  float m = __uint_as_float(maxbits);
+  if (!(m > 0.0f)) return 1.0f;
+  int e = ilogbf(m) + 1;  // m = f 2^e, f in [1/2, 1)
+  return ldexpf(1.0f, 15 - e);
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round half to even on the dropped 16 bits
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ uint16_t fp16_rne(float x) { return __half_as_ushort(__float2half_rn(x)); }
+
+__device__ __forceinline__ float fp16_to_f32(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+
+// ---------------------------------------------------------------------------
+// LDS staging of a (TZ + 8) x 72 tile with its halo, as 16-byte loads.  The
+// loads land in registers first (load()) and go to LDS later (store()), so
+// the caller can issue every global load of the step before waiting on any.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int TZ>
+struct TileStage {
+  static constexpr int kRows = TZ + 2 * kHalo;
+  static constexpr int kVec = kLdsW / 4;  // 18 float4 per row
+  static constexpr int kN = kRows * kVec;
+  static constexpr int kIt = (kN + kThreads - 1) / kThreads;
+  f32x4 v[kIt];
+
+  __device__ __forceinline__ void load(const float* __restrict__ fld, int pitch, int z0, int x0) {
+    const float* base = fld + (int64_t)(z0 - kHalo) * pitch + (x0 - kHalo);
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int i = threadIdx.x + it * kThreads;
+      if (i < kN) {
+        const int r = i / kVec, q = i - r * kVec;
+        v[it] = *reinterpret_cast<const f32x4*>(base + (int64_t)r * pitch + q * 4);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(float* __restrict__ lds) const {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int i = threadIdx.x + it * kThreads;
+      if (i < kN) {
+        const int r = i / kVec, q = i - r * kVec;
+        *reinterpret_cast<f32x4*>(lds + r * kLdsW + q * 4) = v[it];
+      }
+    }
+  }
+};
+
+// 8th-order Laplacian at LDS row `row` (centre) of column `col` (LDS coords),
+// z-neighbours from the register window zw[k .. k+8] (zw[k+4] is the centre).
+template <int RZ>
+__device__ __forceinline__ float lap8(const float* __restrict__ lds, int row, int col,
+                                      const float (&zw)[RZ + 8], int k, float c0,
+                                      const float (&cz)[4], const float (&cx)[4]) {
+  const float* rp = lds + row * kLdsW + col;
+  float s = c0 * zw[k + 4];
+  s = fmaf(cz[0], zw[k + 3] + zw[k + 5], s);
+  s = fmaf(cx[0], rp[-1] + rp[1], s);
+  s = fmaf(cz[1], zw[k + 2] + zw[k + 6], s);
+  s = fmaf(cx[1], rp[-2] + rp[2], s);
+  s = fmaf(cz[2], zw[k + 1] + zw[k + 7], s);
+  s = fmaf(cx[2], rp[-3] + rp[3], s);
+  s = fmaf(cz[3], zw[k + 0] + zw[k + 8], s);
+  s = fmaf(cx[3], rp[-4] + rp[4], s);
+  return s;
+}
+
+// Index of a physical node (pz, px) in the boundary ring: the 4-cell band
+// inside the physical perimeter, ordered top band, bottom band, then the
+// left/right bands row by row.  Returns -1 for interior nodes.
+__device__ __forceinline__ int ring_slot(int pz, int px, int nz, int nx) {
+  if (pz < 4) return pz * nx + px;
+  if (pz >= nz - 4) return 4 * nx + (pz - (nz - 4)) * nx + px;
+  int q = pz - 4;
+  if (px < 4) return 8 * nx + q * 8 + px;
+  if (px >= nx - 4) return 8 * nx + q * 8 + 4 + (px - (nx - 4));
+  return -1;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Workgroup max of v (>= 0 or NaN) to one global atomic (float bits, unsigned
+// compare is monotone for non-negative floats; NaN bits sort above +inf).
+__device__ __forceinline__ void wg_atomic_max(float v, uint32_t* dst, float* red) {
+  v = wave_max(v);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    atomicMax(dst, __float_as_uint(m));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The time-step kernel
+// ---------------------------------------------------------------------------
+template <int TZ, bool kHasB>
+struct StepSmem {
+  float a[(TZ + 2 * kHalo) * kLdsW];             // stencil operand (u^n or R^{m+1})
+  float b[kHasB ? (TZ + 2 * kHalo) * kLdsW : 4];  // S^{m+1} for reconstruction
+  float inj[TZ * kTileX];                        // receiver injection / trace staging
+  float red[4];
+};
+
+template <int TZ, class Smem>
+__device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, int n, Smem& sm) {
+  constexpr int RZ = TZ / 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int pitch = J.pitch;
+  const float* __restrict__ cur = J.f[n & 1];
+  float* __restrict__ nxt = J.f[(n + 1) & 1];  // holds u^{n-1}; overwritten with u^{n+1}
+  const float* __restrict__ cc = J.c;
+  const int x = tl.x0 + lane;
+  const int z0 = tl.z0 + w * RZ;
+  const bool colok = x < J.nxp;
+
+  // ---- issue every global load of the step first ----
+  TileStage<TZ> st;
+  st.load(cur, pitch, tl.z0, tl.x0);
+  float cv[RZ], pv[RZ];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < RZ; ++k) {
+    const int z = z0 + k;
+    const bool ok = colok && z < J.nzp;
+    const int64_t idx = (int64_t)z * pitch + x;
+    cv[k] = ok ? cc[idx] : 0.0f;
+    pv[k] = ok ? nxt[idx] : 0.0f;
+  }
+  const float gxv = colok ? J.gx[x] : 0.0f;
+  st.store(sm.a);
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
+  const float wsrc = J.wavelet[n] * J.inv_cell;
+  const int mode = J.mode;
+  const bool snap_now = mode == kModeStore && (n % J.snap_stride) == 0;
+  const bool want_max = mode == kModeStore && J.snap_dtype != 0 && ((n + 1) % J.snap_stride) == 0 &&
+                        (n + 1) <= J.nt - 2;
+  const float sc = (snap_now && J.snap_dtype != 0) ? snap_scale_from_bits(J.maxbits[n]) : 1.0f;
+  const int px = x - J.nb;
+  const bool colphys = px >= 0 && px < J.nx;
+
+  float zw[RZ + 8];
+#pragma unroll
+  for (int j = 0; j < RZ + 8; ++j) zw[j] = sm.a[(w * RZ + j) * kLdsW + lane + kHalo];
+
+  float vmax = 0.0f;
+#pragma clang loop unroll(full)
+  for (int k = 0; k < RZ; ++k) {
+    const int lz = w * RZ + k;
+    const int z = z0 + k;
+    if (colok && z < J.nzp) {
+      const int64_t idx = (int64_t)z * pitch + x;
+      float lap = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zw, k, c0, cz, cx);
+      if (z == J.src_z && x == J.src_x) lap += wsrc;
+      const float G = J.gz[z] * gxv;
+      const float u = zw[k + 4];
+      const float un = G * fmaf(cv[k], lap, 2.0f * u) - (G * G) * pv[k];
+      nxt[idx] = un;
+      const int pz = z - J.nb;
+      const bool phys = colphys && pz >= 0 && pz < J.nz;
+      if (mode == kModeModel) {
+        sm.inj[lz * kTileX + lane] = un;
+      } else if (phys) {
+        if (mode == kModeRecon) {
+          int slot = ring_slot(pz, px, J.nz, J.nx);
+          if (slot >= 0) J.ring[(int64_t)(n + 1) * J.ring_len + slot] = un;
+        } else {
+          if (snap_now) {
+            int64_t off = ((int64_t)(n / J.snap_stride) * J.nz + pz) * J.nx + px;
+            if (J.snap_dtype == 0)
+              reinterpret_cast<float*>(J.snap)[off] = u;
+            else if (J.snap_dtype == 1)
+              reinterpret_cast<uint16_t*>(J.snap)[off] = bf16_rne(u * sc);
+            else
+              reinterpret_cast<uint16_t*>(J.snap)[off] = fp16_rne(u * sc);
+          }
+          vmax = fmaxf(vmax, fabsf(un));
+        }
+      }
+    }
+  }
+  if (want_max) wg_atomic_max(vmax, &J.maxbits[n + 1], sm.red);
+  if (mode == kModeModel && tl.rec_count > 0) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
+      int2 r = J.recs[tl.rec_begin + i];
+      J.traces[(int64_t)(n + 1) * J.nrec + r.y] = sm.inj[r.x];
+    }
+  }
+}
+
+template <int TZ, class Smem>
+__device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, int m, Smem& sm) {
+  constexpr int RZ = TZ / 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int pitch = J.pitch;
+  const int nt = J.nt;
+  const float* __restrict__ rcur = J.r[(m + 1) & 1];  // R^{m+1}
+  float* __restrict__ rout = J.r[m & 1];              // R^{m+2} -> R^m
+  const float* __restrict__ scur = J.f[(m + 1) & 1];  // S^{m+1}
+  float* __restrict__ sout = J.f[m & 1];              // S^{m+2} -> S^m (S^m itself when m >= nt-2)
+  float* __restrict__ image = J.image;
+  const float* __restrict__ cc = J.c;
+  const int mode = J.mode;
+  const int x = tl.x0 + lane;
+  const int z0 = tl.z0 + w * RZ;
+  const bool colok = x < J.nxp;
+  const int px = x - J.nb;
+  const bool colphys = px >= 0 && px < J.nx;
+
+  // Does this tile touch the physical window?  Which source-side work runs?
+  const int pz0 = tl.z0 - J.nb, px0 = tl.x0 - J.nb;
+  const bool tile_phys = pz0 < J.nz && pz0 + TZ > 0 && px0 < J.nx && px0 + kTileX > 0;
+  const bool imaging = tile_phys && m <= nt - 2 &&
+                       (mode == kModeRecon || (m % J.snap_stride) == 0);
+  const bool recon = imaging && mode == kModeRecon && m <= nt - 3;
+
+  // ---- issue every global load of the step first ----
+  TileStage<TZ> sa;
+  sa.load(rcur, pitch, tl.z0, tl.x0);
+  TileStage<TZ> sb;
+  if (recon) sb.load(scur, pitch, tl.z0, tl.x0);
+  float cv[RZ], pv[RZ], iv[RZ], sv[RZ];
+  bool ring_pt[RZ];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < RZ; ++k) {
+    const int z = z0 + k;
+    const bool ok = colok && z < J.nzp;
+    const int64_t idx = (int64_t)z * pitch + x;
+    cv[k] = ok ? cc[idx] : 0.0f;
+    pv[k] = ok ? rout[idx] : 0.0f;
+    iv[k] = 0.0f;
+    sv[k] = 0.0f;
+    ring_pt[k] = false;
+    const int pz = z - J.nb;
+    if (imaging && ok && colphys && pz >= 0 && pz < J.nz) {
+      iv[k] = image[(int64_t)pz * J.nx + px];
+      if (mode == kModeRecon) {
+        if (recon) {
+          const int slot = ring_slot(pz, px, J.nz, J.nx);
+          ring_pt[k] = slot >= 0;
+          // ring nodes are restored from storage; interior nodes need S^{m+2}
+          sv[k] = slot >= 0 ? J.ring[(int64_t)m * J.ring_len + slot] : sout[idx];
+        } else {
+          sv[k] = sout[idx];  // S^{nt-2}, left by the forward pass
+        }
+      } else {
+        const int64_t off = ((int64_t)(m / J.snap_stride) * J.nz + pz) * J.nx + px;
+        if (J.snap_dtype == 0)
+          sv[k] = reinterpret_cast<const float*>(J.snap)[off];
+        else if (J.snap_dtype == 1)
+          sv[k] = bf16_to_f32(reinterpret_cast<const uint16_t*>(J.snap)[off]);
+        else
+          sv[k] = fp16_to_f32(reinterpret_cast<const uint16_t*>(J.snap)[off]);
+      }
+    }
+  }
+  const float gxv = colok ? J.gx[x] : 0.0f;
+  sa.store(sm.a);
+  if (recon) sb.store(sm.b);
+  if (tl.rec_count > 0) {
+    for (int i = threadIdx.x; i < TZ * kTileX; i += kThreads) sm.inj[i] = 0.0f;
+    __syncthreads();
+    const float* dm = J.data + (int64_t)m * J.nrec;
+    for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
+      int2 r = J.recs[tl.rec_begin + i];
+      atomicAdd(&sm.inj[r.x], dm[r.y]);
+    }
+  }
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
+  const bool has_inj = tl.rec_count > 0;
+  const float kfac = J.kfac;
+  const float wsrc = (recon ? J.wavelet[m + 1] : 0.0f) * J.inv_cell;
+  float dsc = 1.0f;
+  if (imaging && mode == kModeStore && J.snap_dtype != 0)
+    dsc = 1.0f / snap_scale_from_bits(J.maxbits[m]);  // exact: power of two
+
+  float zr[RZ + 8];
+#pragma unroll
+  for (int j = 0; j < RZ + 8; ++j) zr[j] = sm.a[(w * RZ + j) * kLdsW + lane + kHalo];
+  float zs[RZ + 8];
+  if (recon) {
+#pragma unroll
+    for (int j = 0; j < RZ + 8; ++j) zs[j] = sm.b[(w * RZ + j) * kLdsW + lane + kHalo];
+  }
+
+#pragma clang loop unroll(full)
+  for (int k = 0; k < RZ; ++k) {
+    const int lz = w * RZ + k;
+    const int z = z0 + k;
+    if (colok && z < J.nzp) {
+      const int64_t idx = (int64_t)z * pitch + x;
+      float lap = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zr, k, c0, cz, cx);
+      if (has_inj) lap += sm.inj[lz * kTileX + lane];
+      const float G = J.gz[z] * gxv;
+      const float r1 = zr[k + 4];  // R^{m+1}
+      rout[idx] = G * fmaf(cv[k], lap, 2.0f * r1) - (G * G) * pv[k];
+      const int pz = z - J.nb;
+      if (imaging && colphys && pz >= 0 && pz < J.nz) {
+        float s;
+        if (mode == kModeRecon) {
+          if (recon) {
+            if (ring_pt[k]) {
+              s = sv[k];
+            } else {
+              float ls = lap8<RZ>(sm.b, lz + kHalo, lane + kHalo, zs, k, c0, cz, cx);
+              if (z == J.src_z && x == J.src_x) ls += wsrc;
+              s = fmaf(cv[k], ls, 2.0f * zs[k + 4]) - sv[k];
+            }
+            sout[idx] = s;
+          } else {
+            s = sv[k];
+          }
+        } else {
+          s = sv[k] * dsc;
+        }
+        const int64_t io = (int64_t)pz * J.nx + px;
+        image[io] = fmaf(kfac * s, r1, iv[k]);
+        if (J.illum) J.illum[io] = fmaf(kfac * s, s, J.illum[io]);
+      }
+    }
+  }
+}
+
+template <int TZ, int PH>
+__global__ __launch_bounds__(kThreads) void k_step(const DevJob* __restrict__ jobs,
+                                                    const Tile* __restrict__ tiles,
+                                                    const StepCtl* __restrict__ ctl, int ntiles_arg,
+                                                    int use_ctl_tick, int tick_off) {
+  __shared__ StepSmem<TZ, (PH & kPhBwd) != 0> sm;
+  // Global step: a base read from the control block (advanced by k_advance
+  // after every group of graph-replayed launches) plus this launch's offset.
+  const int ntiles = ntiles_arg >= 0 ? ntiles_arg : ctl->ntiles;
+  const int tick = (use_ctl_tick ? ctl->tick : 0) + tick_off;
+  // XCD-aware mapping: workgroups are dealt round-robin to the 8 XCDs, so
+  // give XCD k (blockIdx % 8) a contiguous run of tiles; neighbouring tiles,
+  // and the halo rows they share, then meet in the same L2.  The grid may be
+  // sized for more tiles than are active (graph replays).
+  const int per = (ntiles + 7) >> 3;
+  const int local = (int)(blockIdx.x >> 3);
+  const int t = (blockIdx.x & 7) * per + local;
+  if (local >= per || t >= ntiles) return;
+  const Tile tl = tiles[t];
+  const DevJob& J = jobs[tl.job];
+  const int s = tick - J.start_tick;
+  if (s < 0 || s >= J.nsteps) return;
+  const int nf = (J.mode == kModeModel) ? J.nsteps : J.nt - 1;  // forward steps
+  if (s < nf) {
+    if (PH & kPhFwd) forward_tile<TZ>(J, tl, s, sm);
+  } else {
+    if (PH & kPhBwd) backward_tile<TZ>(J, tl, J.nt - 1 - (s - nf), sm);
+  }
+}
+
+__global__ void k_advance(StepCtl* ctl, int k) { ctl->tick += k; }
+
+hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, ctl, k);
+  return hipGetLastError();
+}
+
+template <int TZ>
+static hipError_t launch_step_tz(int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
+                                 int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
+                                 hipStream_t s) {
+  const int per = (grid_tiles + 7) / 8;
+  dim3 grid(8 * per), block(kThreads);
+  if (phases == kPhFwd)
+    hipLaunchKernelGGL((k_step<TZ, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+  else if (phases == kPhBwd)
+    hipLaunchKernelGGL((k_step<TZ, kPhBwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+  else
+    hipLaunchKernelGGL((k_step<TZ, kPhAny>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
+                       int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
+                       hipStream_t s) {
+  switch (tz) {
+    case 16: return launch_step_tz<16>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, s);
+    case 32: return launch_step_tz<32>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, s);
+    case 64: return launch_step_tz<64>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Job set-up: c = v^2 dt^2 on the padded window (velocity edge-replicated into
+// the sponge) and the sponge profiles g(d) = exp(-(a d)^2).
+// ---------------------------------------------------------------------------
+__global__ void k_prep(const float* __restrict__ vel, int model_nx, int ix0, int nz, int nx, int nb,
+                       int nzp, int nxp, int pitch, float dt2, float a, float* __restrict__ c,
+                       float* __restrict__ gz, float* __restrict__ gx) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (x >= nxp || z >= nzp) return;
+  int vz = min(max(z - nb, 0), nz - 1);
+  int vx = min(max(x - nb, 0), nx - 1);
+  float v = vel[(int64_t)vz * model_nx + ix0 + vx];
+  c[(int64_t)z * pitch + x] = v * v * dt2;
+  if (z == 0) {
+    int d = x < nb ? nb - x : (x >= nb + nx ? x - (nb + nx - 1) : 0);
+    float ad = a * (float)d;
+    gx[x] = expf(-ad * ad);
+  }
+  if (x == 0) {
+    int d = z < nb ? nb - z : (z >= nb + nz ? z - (nb + nz - 1) : 0);
+    float ad = a * (float)d;
+    gz[z] = expf(-ad * ad);
+  }
+}
+
+hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* hj, float* c,
+                       float* gz, float* gx, float dt, float sponge_a, hipStream_t s) {
+  dim3 block(256), grid((hj->nxp + 255) / 256, hj->nzp);
+  float a = sponge_a > 0.0f ? sponge_a : (hj->nb > 0 ? 0.3f / (float)hj->nb : 0.0f);
+  hipLaunchKernelGGL(k_prep, grid, block, 0, s, vel, model_nx, ix0, hj->nz, hj->nx, hj->nb,
+                     hj->nzp, hj->nxp, hj->pitch, dt * dt, a, c, gz, gx);
+  return hipGetLastError();
+}
+
+// max |v| over a window (float bits; the output must be zeroed first)
+__global__ void k_vmax(const float* __restrict__ vel, int nz, int model_nx, int ix0, int width,
+                       uint32_t* out) {
+  __shared__ float red[4];
+  float m = 0.0f;
+  const int64_t n = (int64_t)nz * width;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t z = i / width, x = i - z * width;
+    float v = fabsf(vel[z * model_nx + ix0 + x]);
+    m = (v != v) ? v : fmaxf(m, v);  // propagate NaN
+  }
+  wg_atomic_max(m, out, red);
+}
+
+hipError_t launch_vmax(const float* vel, int nz, int model_nx, int ix0, int width, uint32_t* out,
+                       hipStream_t s) {
+  int64_t n = (int64_t)nz * width;
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_vmax, dim3(blocks), dim3(256), 0, s, vel, nz, model_nx, ix0, width, out);
+  return hipGetLastError();
+}
+
+// Stack: dst[z][ix0 + x] += img[z][x]
+__global__ void k_stack(float* __restrict__ dst, int dst_nx, int ix0, const float* __restrict__ img,
+                        int nz, int width) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (x < width && z < nz) dst[(int64_t)z * dst_nx + ix0 + x] += img[(int64_t)z * width + x];
+}
+
+hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int nz, int width,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_stack, dim3((width + 255) / 256, nz), dim3(256), 0, s, dst, dst_nx, ix0, img,
+                     nz, width);
+  return hipGetLastError();
+}
+
+// Physical region of a padded field -> dense [nz][nx]
+__global__ void k_copy_phys(float* __restrict__ dst, const float* __restrict__ fld, int nz, int nx,
+                            int nb, int pitch) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (x < nx && z < nz) dst[(int64_t)z * nx + x] = fld[(int64_t)(z + nb) * pitch + nb + x];
+}
+
+hipError_t launch_copy_phys(float* dst, const float* fld, int nz, int nx, int nb, int pitch,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_phys, dim3((nx + 255) / 256, nz), dim3(256), 0, s, dst, fld, nz, nx, nb,
+                     pitch);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble statistics (Sec. 2.3 / Stage 3): per-pixel FP64 Welford update
+//   n += 1; d = x - mean; mean += d / n; M2 += d (x - mean)
+// over the window [ix0, ix0 + width) of an [nz][nx_model] state.
+// ---------------------------------------------------------------------------
+__global__ void k_welford(double* __restrict__ mean, double* __restrict__ m2,
+                          int32_t* __restrict__ count, int nx_model, const float* __restrict__ img,
+                          int nz, int width, int ix0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (x >= width || z >= nz) return;
+  const int64_t o = (int64_t)z * nx_model + ix0 + x;
+  const double v = (double)img[(int64_t)z * width + x];
+  const int32_t n = count[o] + 1;
+  const double d = v - mean[o];
+  const double mu = mean[o] + d / (double)n;
+  m2[o] += d * (v - mu);
+  mean[o] = mu;
+  count[o] = n;
+}
+
+hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model, const float* img,
+                          int nz, int width, int ix0, hipStream_t s) {
+  hipLaunchKernelGGL(k_welford, dim3((width + 255) / 256, nz), dim3(256), 0, s, mean, m2, count,
+                     nx_model, img, nz, width, ix0);
+  return hipGetLastError();
+}
+
+__global__ void k_stats_out(const double* __restrict__ mean, const double* __restrict__ m2,
+                            const int32_t* __restrict__ count, int64_t n, double* mean_out,
+                            double* std_out, int32_t* count_out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t c = count[i];
+    if (mean_out) mean_out[i] = c > 0 ? mean[i] : 0.0;
+    if (std_out) std_out[i] = c > 1 ? sqrt(m2[i] / (double)(c - 1)) : 0.0;
+    if (count_out) count_out[i] = c;
+  }
+}
+
+hipError_t launch_stats_out(const double* mean, const double* m2, const int32_t* count, int64_t n,
+                            double* mean_out, double* std_out, int32_t* count_out, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_stats_out, dim3(blocks), dim3(256), 0, s, mean, m2, count, n, mean_out,
+                     std_out, count_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage-3 maps.  Confidence index (Eq. 6): two passes, min/max of std over
+// pixels with enough samples, then the normalisation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t order_bits(double v) {
+  // monotone map of a non-negative double onto uint64
+  return (uint64_t)__double_as_longlong(v);
+}
+
+__global__ void k_minmax(const double* __restrict__ sd, const int32_t* __restrict__ count, int n,
+                         int min_count, unsigned long long* mm) {
+  double lo = INFINITY, hi = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (count && count[i] < min_count) continue;
+    double v = sd[i];
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[0], (unsigned long long)order_bits(lo));
+    atomicMax(&mm[1], (unsigned long long)order_bits(hi));
+  }
+}
+
+__global__ void k_confidence(const double* __restrict__ sd, const int32_t* __restrict__ count,
+                             int n, int min_count, const unsigned long long* mm, double* out) {
+  const double lo = __longlong_as_double((long long)mm[0]);
+  const double hi = __longlong_as_double((long long)mm[1]);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if ((count && count[i] < min_count) || !(hi > lo)) {
+      out[i] = 0.0;
+      continue;
+    }
+    out[i] = (hi - sd[i]) / (hi - lo);
+  }
+}
+
+__global__ void k_init_minmax(unsigned long long* mm) {
+  mm[0] = (unsigned long long)order_bits(INFINITY);
+  mm[1] = 0ull;
+}
+
+hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int min_count,
+                             double* out, double* scratch2, hipStream_t s) {
+  auto* mm = reinterpret_cast<unsigned long long*>(scratch2);
+  hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm);
+  int blocks = std::max(1, std::min((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm);
+  hipLaunchKernelGGL(k_confidence, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm, out);
+  return hipGetLastError();
+}
+
+// Ratio map (Eq. 7): r = std / mean, 0 where |mean| <= eps
+__global__ void k_ratio(const double* __restrict__ sd, const double* __restrict__ mean, int n,
+                        double eps, double* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double mu = mean[i];
+    out[i] = fabs(mu) > eps ? sd[i] / mu : 0.0;
+  }
+}
+
+hipError_t launch_ratio(const double* sd, const double* mean, int n, double eps, double* out,
+                        hipStream_t s) {
+  int blocks = std::max(1, std::min((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_ratio, dim3(blocks), dim3(256), 0, s, sd, mean, n, eps, out);
+  return hipGetLastError();
+}
+
+// Post-stack Laplacian filter: out = -L img, zero outside the image.
+__global__ void k_lapfilter(const float* __restrict__ img, int nz, int nx, float c0, float4 czv,
+                            float4 cxv, float* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (x >= nx || z >= nz) return;
+  const float cz[4] = {czv.x, czv.y, czv.z, czv.w};
+  const float cx[4] = {cxv.x, cxv.y, cxv.z, cxv.w};
+  auto at = [&](int zz, int xx) -> float {
+    return (zz >= 0 && zz < nz && xx >= 0 && xx < nx) ? img[(int64_t)zz * nx + xx] : 0.0f;
+  };
+  float s = c0 * at(z, x);
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+    s = fmaf(cz[k - 1], at(z - k, x) + at(z + k, x), s);
+    s = fmaf(cx[k - 1], at(z, x - k) + at(z, x + k), s);
+  }
+  out[(int64_t)z * nx + x] = -s;
+}
+
+hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx, float* out,
+                            hipStream_t s) {
+  const double a[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+  const double iz2 = 1.0 / ((double)dz * dz), ix2 = 1.0 / ((double)dx * dx);
+  float c0 = (float)(a[0] * (iz2 + ix2));
+  float4 czv = make_float4((float)(a[1] * iz2), (float)(a[2] * iz2), (float)(a[3] * iz2),
+                           (float)(a[4] * iz2));
+  float4 cxv = make_float4((float)(a[1] * ix2), (float)(a[2] * ix2), (float)(a[3] * ix2),
+                           (float)(a[4] * ix2));
+  hipLaunchKernelGGL(k_lapfilter, dim3((nx + 255) / 256, nz), dim3(256), 0, s, img, nz, nx, c0, czv,
+                     cxv, out);
+  return hipGetLastError();
+}
+
+}  // namespace rtm

@@ -1,0 +1,1545 @@
+// rtm_runtime.hip -- host runtime and C ABI of the RTM library (include/rtm.h).
+//
+// Pieces:
+//   Arena      first-fit sub-allocator over the caller's device buffer, with
+//              frees deferred until the stream work that used the blocks is done
+//   HostJob    one migration / modelling job: geometry, arena blocks, tiles,
+//              device descriptor (rtm_internal.h)
+//   plain      rtm_propagate / rtm_migrate_shot: one kernel launch per step
+//   batched    rtm_migrate_batch: all shots of a model advance in each launch,
+//              launches replayed from a captured hipGraph, device-side tick
+//   ensemble   rtm_ensemble_*: a scheduler thread admits queued jobs by arena
+//              footprint, runs every active job (any phase, any size) in the
+//              same launches, finalises finished jobs (stack, FP64 Welford) and
+//              admits new ones between graph replays (continuous batching)
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdarg.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/rtm.h"
+#include "rtm_internal.h"
+
+using namespace rtm;
+
+// ===========================================================================
+// errors
+// ===========================================================================
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(RTM_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                  __FILE__, __LINE__);                                                     \
+  } while (0)
+
+static double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// 8th-order central weights of the 2nd derivative; a0 + 2 sum a_k = 0.
+static const double kA[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+// ===========================================================================
+// Arena
+// ===========================================================================
+struct Block {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+class Arena {
+ public:
+  void init(void* base, size_t size) {
+    base_ = static_cast<char*>(base);
+    size_ = size;
+    free_.clear();
+    free_[0] = size;
+    used_ = peak_ = 0;
+  }
+  void* alloc(size_t n) {
+    std::lock_guard<std::mutex> lk(mu_);
+    n = align256(n ? n : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        size_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > n) free_[off + n] = sz - n;
+        used_ += n;
+        peak_ = std::max(peak_, used_);
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(void* p, size_t n) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    n = align256(n ? n : 1);
+    size_t off = static_cast<char*>(p) - base_;
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t size() const { return size_; }
+  size_t used() {
+    std::lock_guard<std::mutex> lk(mu_);
+    return used_;
+  }
+  size_t peak() {
+    std::lock_guard<std::mutex> lk(mu_);
+    return peak_;
+  }
+
+ private:
+  std::mutex mu_;
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0, peak_ = 0;
+};
+
+// Blocks (and host staging, graphs) released once an event has completed.
+struct Deferred {
+  hipEvent_t ev = nullptr;
+  std::vector<Block> blocks;
+  std::vector<std::shared_ptr<void>> keep;  // host-side objects kept alive
+  std::vector<hipGraphExec_t> graphs;
+};
+
+// ===========================================================================
+// Jobs
+// ===========================================================================
+struct JobGeom {
+  int nz = 0, model_nx = 0, ix0 = 0, width = 0, nb = 0, nt = 0;
+  float dz = 0, dx = 0, dt = 0, sponge_a = 0;
+  int mode = kModeModel;
+  int snap_dtype = 0, snap_stride = 1;
+  uint32_t flags = 0;
+  int nrec = 0;
+};
+
+static int snap_bytes(int dtype) { return dtype == RTM_SNAP_FP32 ? 4 : 2; }
+static int nsnap_of(int nt, int k) { return (nt - 2) / k + 1; }
+
+struct Footprint {
+  size_t field = 0, total = 0;
+};
+
+static Footprint footprint(const JobGeom& g) {
+  Footprint f;
+  const int nzp = g.nz + 2 * g.nb, nxp = g.width + 2 * g.nb;
+  f.field = align256((size_t)field_floats(nzp, nxp) * 4);
+  size_t t = 0;
+  t += f.field;                                  // c
+  t += 2 * f.field;                              // f[2]
+  if (g.mode != kModeModel) t += 2 * f.field;    // r[2]
+  t += align256((size_t)nzp * 4) + align256((size_t)nxp * 4);
+  if (g.mode != kModeModel) {
+    t += align256((size_t)g.nz * g.width * 4);   // image
+    if (g.flags & RTM_IMG_ILLUM) t += align256((size_t)g.nz * g.width * 4);
+  }
+  if (g.mode == kModeRecon) t += align256((size_t)g.nt * ring_len_of(g.nz, g.width) * 4);
+  if (g.mode == kModeStore)
+    t += align256((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * g.width * snap_bytes(g.snap_dtype));
+  t += align256((size_t)g.nt * 4);               // maxbits
+  t += align256((size_t)std::max(g.nrec, 1) * 8);  // receivers
+  t += 256;                                      // health
+  f.total = t;
+  return f;
+}
+
+struct HostJob {
+  JobGeom g;
+  DevJob d{};
+  std::vector<Tile> tiles;       // job-local (job field set when a table is built)
+  std::vector<int2> recs;        // sorted by tile
+  std::vector<Block> blocks;     // arena blocks of the job's working set
+  Block image_blk;               // the per-job image (kept after the job for polling)
+  uint64_t updates = 0, alg_bytes = 0;
+};
+
+static void count_work(HostJob& j) {
+  const JobGeom& g = j.g;
+  const uint64_t Npad = (uint64_t)(g.nz + 2 * g.nb) * (g.width + 2 * g.nb);
+  const uint64_t Nph = (uint64_t)g.nz * g.width;
+  const uint64_t ring = (uint64_t)ring_len_of(g.nz, g.width);
+  const uint64_t nt = g.nt;
+  if (g.mode == kModeModel) {
+    j.updates = (nt - 1) * Npad;
+    j.alg_bytes = (nt - 1) * (Npad * 16 + (uint64_t)g.nrec * 4);
+    return;
+  }
+  j.updates = (nt - 1) * Npad + nt * Npad;
+  uint64_t b = (nt - 1) * Npad * 16 + nt * Npad * 16 + nt * (uint64_t)g.nrec * 4;
+  if (g.mode == kModeRecon) {
+    j.updates += (nt >= 2 ? nt - 2 : 0) * Nph;
+    b += (nt - 1) * ring * 4;                 // ring save
+    b += (nt - 2) * (Nph * 12 + ring * 4);    // reconstruct S (interior 12 B, ring 4 B)
+    b += (nt - 1) * Nph * 8;                  // image read-modify-write
+  } else {
+    const uint64_t ns = nsnap_of(g.nt, g.snap_stride), sb = snap_bytes(g.snap_dtype);
+    b += ns * Nph * (2 * sb + 8);             // snapshot write + read, image RMW
+  }
+  if (g.flags & RTM_IMG_ILLUM) b += (g.mode == kModeRecon ? (nt - 1) : nsnap_of(g.nt, g.snap_stride)) * Nph * 8;
+  j.alg_bytes = b;
+}
+
+// ===========================================================================
+// Context
+// ===========================================================================
+struct Model {
+  int nz = 0, nx = 0;
+  rtm_grid grid{};
+  Block vel;
+  float vmax = 0;
+  // statistics (allocated on first use)
+  Block mean, m2, count, stack;
+  int active = 0;  // queued + running jobs of this model
+};
+
+struct EnsJob {
+  uint64_t ticket = 0;
+  rtm_job spec{};
+  int state = RTM_JOB_QUEUED;
+  int status = RTM_OK;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  std::unique_ptr<HostJob> job;
+  int bypassed = 0;
+};
+
+struct StatsAcc {
+  int nz = 0, nx = 0;
+  Block mean, m2, count;
+};
+
+struct rtm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;        // caller's stream (plain / batched / copies)
+  hipStream_t sched_stream = nullptr;  // scheduler thread's stream
+  hipStream_t work_stream = nullptr;   // batched path (graph capture needs a non-null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // phase timing of the last batched call (events on work_stream)
+  hipEvent_t ph_ev[3] = {nullptr, nullptr, nullptr};
+  int ph_launches[2] = {0, 0};
+  uint64_t ph_bytes[2] = {0, 0};
+  bool ph_valid = false;
+  Arena arena;
+  void* own_arena = nullptr;
+  std::mutex defer_mu;
+  std::deque<Deferred> deferred;
+  int tile_z = 0;                      // autotuned tile height
+  int tune_nxp = 0;
+  // counters
+  std::atomic<uint64_t> steps_launched{0}, graph_replays{0}, grid_updates{0}, alg_bytes{0};
+  std::atomic<uint64_t> jobs_submitted{0}, jobs_done{0}, jobs_failed{0}, jobs_cancelled{0};
+  // ensemble
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::map<int, Model> models;
+  std::unordered_map<uint64_t, std::unique_ptr<EnsJob>> jobs;
+  std::deque<uint64_t> queue;
+  std::vector<uint64_t> running;
+  uint64_t next_ticket = 1;
+  int queue_cap = 1 << 16;
+  bool stop = false;
+  std::thread sched;
+  bool sched_started = false;
+  int active_jobs = 0, queued_jobs = 0;
+  uint32_t* scratch_u32 = nullptr;     // small device scratch (vmax etc.)
+  double* scratch_f64 = nullptr;
+};
+
+// ---- deferred frees ----
+static void reap(rtm_ctx* ctx, bool wait_one) {
+  std::vector<Deferred> done;
+  {
+    std::lock_guard<std::mutex> lk(ctx->defer_mu);
+    while (!ctx->deferred.empty()) {
+      Deferred& d = ctx->deferred.front();
+      hipError_t q = hipEventQuery(d.ev);
+      if (q == hipErrorNotReady) {
+        if (!wait_one) break;
+        (void)hipEventSynchronize(d.ev);
+        wait_one = false;
+      }
+      done.push_back(std::move(d));
+      ctx->deferred.pop_front();
+    }
+  }
+  for (auto& d : done) {
+    for (auto& b : d.blocks) ctx->arena.release(b.p, b.n);
+    for (auto g : d.graphs) (void)hipGraphExecDestroy(g);
+    (void)hipEventDestroy(d.ev);
+  }
+}
+
+static int defer(rtm_ctx* ctx, hipStream_t s, Deferred&& d) {
+  HIP_OK(hipEventCreateWithFlags(&d.ev, hipEventDisableTiming));
+  HIP_OK(hipEventRecord(d.ev, s));
+  std::lock_guard<std::mutex> lk(ctx->defer_mu);
+  ctx->deferred.push_back(std::move(d));
+  return RTM_OK;
+}
+
+static void* arena_alloc(rtm_ctx* ctx, size_t n) {
+  reap(ctx, false);
+  for (;;) {
+    void* p = ctx->arena.alloc(n);
+    if (p) return p;
+    bool pending;
+    {
+      std::lock_guard<std::mutex> lk(ctx->defer_mu);
+      pending = !ctx->deferred.empty();
+    }
+    if (!pending) return nullptr;
+    reap(ctx, true);
+  }
+}
+
+static bool alloc_block(rtm_ctx* ctx, std::vector<Block>& list, size_t n, void** out) {
+  void* p = arena_alloc(ctx, n);
+  if (!p) return false;
+  list.push_back({p, align256(n)});
+  *out = p;
+  return true;
+}
+
+static void release_blocks(rtm_ctx* ctx, std::vector<Block>& list) {
+  for (auto& b : list) ctx->arena.release(b.p, b.n);
+  list.clear();
+}
+
+// ===========================================================================
+// Validation
+// ===========================================================================
+extern "C" double rtm_cfl_limit(void) {
+  // |symbol| of the 1-D stencil at the Nyquist wavenumber: -(a0 + 2 sum (-1)^k a_k)
+  double s = kA[0];
+  for (int k = 1; k <= 4; ++k) s += 2.0 * ((k & 1) ? -kA[k] : kA[k]);
+  return 2.0 / sqrt(-s);
+}
+
+extern "C" double rtm_cfl_number(float v_max, float dt, float dz, float dx) {
+  return (double)v_max * dt * sqrt(1.0 / ((double)dx * dx) + 1.0 / ((double)dz * dz));
+}
+
+static int check_grid(const rtm_grid* g) {
+  if (!g) return fail(RTM_E_INVAL, "grid is NULL");
+  if (g->nz < 1 || g->nx < 1) return fail(RTM_E_INVAL, "nz, nx must be >= 1 (got %d, %d)", g->nz, g->nx);
+  if (g->nb < 0 || g->nb > 4096) return fail(RTM_E_INVAL, "nb out of range (%d)", g->nb);
+  if (g->nt < 2) return fail(RTM_E_INVAL, "nt must be >= 2 (got %d)", g->nt);
+  if (!(g->dz > 0) || !(g->dx > 0) || !(g->dt > 0))
+    return fail(RTM_E_INVAL, "dz, dx, dt must be > 0");
+  return RTM_OK;
+}
+
+static int check_cfl(float vmax, float dt, float dz, float dx) {
+  if (!std::isfinite(vmax) || !(vmax > 0)) return fail(RTM_E_NONFINITE, "velocity max is %g", (double)vmax);
+  double cn = rtm_cfl_number(vmax, dt, dz, dx), lim = rtm_cfl_limit();
+  if (cn > lim)
+    return fail(RTM_E_CFL, "Courant number %.5f exceeds the stability limit %.5f (v_max %.1f)", cn, lim,
+                (double)vmax);
+  return RTM_OK;
+}
+
+static int device_vmax(rtm_ctx* ctx, hipStream_t s, const float* vel, int nz, int model_nx, int ix0,
+                       int width, float* out) {
+  HIP_OK(hipMemsetAsync(ctx->scratch_u32, 0, 4, s));
+  HIP_OK(launch_vmax(vel, nz, model_nx, ix0, width, ctx->scratch_u32, s));
+  uint32_t bits = 0;
+  HIP_OK(hipMemcpyAsync(&bits, ctx->scratch_u32, 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  memcpy(out, &bits, 4);
+  return RTM_OK;
+}
+
+// ===========================================================================
+// Job construction
+// ===========================================================================
+static int choose_tz(rtm_ctx* ctx) {
+  if (ctx->tile_z) return ctx->tile_z;
+  const char* e = getenv("RTM_TILE_Z");
+  int tz = e ? atoi(e) : 32;
+  if (tz != 16 && tz != 32 && tz != 64) tz = 32;
+  return tz;
+}
+
+// Allocates the job's working set and enqueues its set-up on stream s.
+// src/recs are in model coordinates.  On failure nothing stays allocated.
+static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, const float* vel,
+                     const float* wavelet, rtm_point src, const rtm_point* recs, const float* data,
+                     float* traces, HostJob& j) {
+  j.g = g;
+  const int nzp = g.nz + 2 * g.nb, nxp = g.width + 2 * g.nb;
+  DevJob& d = j.d;
+  memset(&d, 0, sizeof d);
+  d.nzp = nzp;
+  d.nxp = nxp;
+  d.pitch = field_pitch(nxp);
+  d.nz = g.nz;
+  d.nx = g.width;
+  d.nb = g.nb;
+  d.nt = g.nt;
+  d.mode = g.mode;
+  d.snap_dtype = g.snap_dtype;
+  d.snap_stride = g.mode == kModeStore ? g.snap_stride : 1;
+  d.flags = g.flags;
+  d.nsteps = g.mode == kModeModel ? g.nt - 1 : 2 * g.nt - 1;
+  d.src_z = src.iz + g.nb;
+  d.src_x = src.ix - g.ix0 + g.nb;
+  d.nrec = g.nrec;
+  d.ring_len = ring_len_of(g.nz, g.width);
+  d.start_tick = 0;
+  d.tiles_x = (nxp + kTileX - 1) / kTileX;
+  d.tiles_z = (nzp + tz - 1) / tz;
+  d.inv_cell = (float)(1.0 / ((double)g.dx * g.dz));
+  const double iz2 = 1.0 / ((double)g.dz * g.dz), ix2 = 1.0 / ((double)g.dx * g.dx);
+  d.c0 = (float)(kA[0] * (iz2 + ix2));
+  for (int k = 0; k < 4; ++k) {
+    d.cz[k] = (float)(kA[k + 1] * iz2);
+    d.cx[k] = (float)(kA[k + 1] * ix2);
+  }
+  d.kfac = (float)d.snap_stride;
+
+  // ---- arena blocks ----
+  Footprint fp = footprint(g);
+  const size_t F = fp.field;
+  void* p = nullptr;
+  bool ok = true;
+  auto A = [&](size_t n) -> void* {
+    if (!ok) return nullptr;
+    void* q = nullptr;
+    if (!alloc_block(ctx, j.blocks, n, &q)) ok = false;
+    return q;
+  };
+  const int64_t org = field_origin(nxp);
+  float* cbuf = static_cast<float*>(A(F));
+  float* fb0 = static_cast<float*>(A(F));
+  float* fb1 = static_cast<float*>(A(F));
+  float *rb0 = nullptr, *rb1 = nullptr;
+  if (g.mode != kModeModel) {
+    rb0 = static_cast<float*>(A(F));
+    rb1 = static_cast<float*>(A(F));
+  }
+  float* gz = static_cast<float*>(A((size_t)nzp * 4));
+  float* gx = static_cast<float*>(A((size_t)nxp * 4));
+  float* illum = nullptr;
+  if (g.mode != kModeModel && (g.flags & RTM_IMG_ILLUM)) illum = static_cast<float*>(A((size_t)g.nz * g.width * 4));
+  float* ring = nullptr;
+  void* snap = nullptr;
+  if (g.mode == kModeRecon) ring = static_cast<float*>(A((size_t)g.nt * d.ring_len * 4));
+  if (g.mode == kModeStore)
+    snap = A((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * g.width * snap_bytes(g.snap_dtype));
+  uint32_t* maxbits = static_cast<uint32_t*>(A((size_t)g.nt * 4));
+  int2* recd = static_cast<int2*>(A((size_t)std::max(g.nrec, 1) * 8));
+  uint32_t* health = static_cast<uint32_t*>(A(256));
+  float* image = nullptr;
+  if (ok && g.mode != kModeModel) {
+    image = static_cast<float*>(arena_alloc(ctx, (size_t)g.nz * g.width * 4));
+    if (!image) ok = false;
+    else j.image_blk = {image, align256((size_t)g.nz * g.width * 4)};
+  }
+  (void)p;
+  if (!ok) {
+    release_blocks(ctx, j.blocks);
+    return fail(RTM_E_NOMEM, "arena exhausted: job needs %zu bytes, arena %zu used of %zu", fp.total,
+                ctx->arena.used(), ctx->arena.size());
+  }
+  d.c = cbuf + org;
+  d.gz = gz;
+  d.gx = gx;
+  d.f[0] = fb0 + org;
+  d.f[1] = fb1 + org;
+  if (rb0) {
+    d.r[0] = rb0 + org;
+    d.r[1] = rb1 + org;
+  }
+  d.wavelet = wavelet;
+  d.data = data;
+  d.traces = traces;
+  d.snap = snap;
+  d.ring = ring;
+  d.maxbits = maxbits;
+  d.image = image;
+  d.illum = illum;
+  d.recs = recd;
+  d.health = health;
+
+  // ---- tiles and receivers ----
+  std::vector<std::pair<int, int2>> keyed;
+  keyed.reserve(g.nrec);
+  for (int r = 0; r < g.nrec; ++r) {
+    int z = recs[r].iz + g.nb, x = recs[r].ix - g.ix0 + g.nb;
+    int t = (z / tz) * d.tiles_x + x / kTileX;
+    int local = (z % tz) * kTileX + (x % kTileX);
+    keyed.push_back({t, make_int2(local, r)});
+  }
+  std::stable_sort(keyed.begin(), keyed.end(),
+                   [](const std::pair<int, int2>& a, const std::pair<int, int2>& b) { return a.first < b.first; });
+  j.recs.resize(g.nrec);
+  for (int r = 0; r < g.nrec; ++r) j.recs[r] = keyed[r].second;
+  j.tiles.clear();
+  size_t kk = 0;
+  for (int tzi = 0; tzi < d.tiles_z; ++tzi)
+    for (int txi = 0; txi < d.tiles_x; ++txi) {
+      int t = tzi * d.tiles_x + txi;
+      Tile tl{};
+      tl.job = 0;
+      tl.z0 = tzi * tz;
+      tl.x0 = txi * kTileX;
+      tl.rec_begin = (int)kk;
+      while (kk < keyed.size() && keyed[kk].first == t) ++kk;
+      tl.rec_count = (int)kk - tl.rec_begin;
+      j.tiles.push_back(tl);
+    }
+
+  // ---- device set-up ----
+  const size_t fb = (size_t)field_floats(nzp, nxp) * 4;
+  HIP_OK(hipMemsetAsync(fb0, 0, fb, s));
+  HIP_OK(hipMemsetAsync(fb1, 0, fb, s));
+  if (rb0) {
+    HIP_OK(hipMemsetAsync(rb0, 0, fb, s));
+    HIP_OK(hipMemsetAsync(rb1, 0, fb, s));
+  }
+  HIP_OK(hipMemsetAsync(cbuf, 0, fb, s));
+  if (image) HIP_OK(hipMemsetAsync(image, 0, (size_t)g.nz * g.width * 4, s));
+  if (illum) HIP_OK(hipMemsetAsync(illum, 0, (size_t)g.nz * g.width * 4, s));
+  if (ring) HIP_OK(hipMemsetAsync(ring, 0, (size_t)d.ring_len * 4, s));  // ring of u^0 = 0
+  HIP_OK(hipMemsetAsync(maxbits, 0, (size_t)g.nt * 4, s));
+  HIP_OK(hipMemsetAsync(health, 0, 4, s));
+  if (traces) HIP_OK(hipMemsetAsync(traces, 0, (size_t)g.nrec * 4, s));  // d[0] = u^0 = 0
+  if (g.nrec) HIP_OK(hipMemcpyAsync(recd, j.recs.data(), (size_t)g.nrec * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(launch_prep(vel, g.model_nx, g.ix0, &d, cbuf + org, gz, gx, g.dt, g.sponge_a, s));
+  count_work(j);
+  return RTM_OK;
+}
+
+// Validation of a job's geometry (model coordinates).
+static int check_job(const JobGeom& g, rtm_point src, const rtm_point* recs) {
+  if (g.width < 1 || g.ix0 < 0 || g.ix0 + g.width > g.model_nx)
+    return fail(RTM_E_INVAL, "window [%d, %d) outside the model's %d columns", g.ix0, g.ix0 + g.width,
+                g.model_nx);
+  if (g.nt < 2) return fail(RTM_E_INVAL, "nt must be >= 2");
+  if (g.mode == kModeRecon && (g.nz < 9 || g.width < 9))
+    return fail(RTM_E_INVAL, "reconstruct mode needs a window of at least 9 x 9 (got %d x %d)", g.nz, g.width);
+  if (g.mode == kModeStore) {
+    if (g.snap_stride < 1) return fail(RTM_E_INVAL, "snap_stride must be >= 1");
+    if (g.snap_dtype < 0 || g.snap_dtype > 2) return fail(RTM_E_INVAL, "unknown snap_dtype %d", g.snap_dtype);
+  }
+  auto inside = [&](rtm_point p) {
+    return p.iz >= 0 && p.iz < g.nz && p.ix >= g.ix0 && p.ix < g.ix0 + g.width;
+  };
+  if (!inside(src)) return fail(RTM_E_INVAL, "source (%d, %d) outside the window", src.iz, src.ix);
+  if (g.nrec < 0 || (g.nrec > 0 && !recs)) return fail(RTM_E_INVAL, "bad receiver list");
+  for (int r = 0; r < g.nrec; ++r)
+    if (!inside(recs[r]))
+      return fail(RTM_E_INVAL, "receiver %d (%d, %d) outside the window", r, recs[r].iz, recs[r].ix);
+  return RTM_OK;
+}
+
+// ===========================================================================
+// Job tables on the device
+// ===========================================================================
+struct Table {
+  DevJob* jobs = nullptr;
+  Tile* tiles = nullptr;
+  StepCtl* ctl = nullptr;
+  int ntiles = 0;
+  std::vector<Block> blocks;
+  std::shared_ptr<std::vector<DevJob>> hjobs;
+  std::shared_ptr<std::vector<Tile>> htiles;
+};
+
+static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, Table& t) {
+  t.hjobs = std::make_shared<std::vector<DevJob>>();
+  t.htiles = std::make_shared<std::vector<Tile>>();
+  for (size_t i = 0; i < js.size(); ++i) {
+    t.hjobs->push_back(js[i]->d);
+    for (Tile tl : js[i]->tiles) {
+      tl.job = (int)i;
+      t.htiles->push_back(tl);
+    }
+  }
+  t.ntiles = (int)t.htiles->size();
+  void* p;
+  if (!alloc_block(ctx, t.blocks, t.hjobs->size() * sizeof(DevJob), &p)) return fail(RTM_E_NOMEM, "arena exhausted (job table)");
+  t.jobs = static_cast<DevJob*>(p);
+  if (!alloc_block(ctx, t.blocks, std::max<size_t>(t.htiles->size(), 1) * sizeof(Tile), &p)) {
+    release_blocks(ctx, t.blocks);
+    return fail(RTM_E_NOMEM, "arena exhausted (tile table)");
+  }
+  t.tiles = static_cast<Tile*>(p);
+  if (!alloc_block(ctx, t.blocks, sizeof(StepCtl), &p)) {
+    release_blocks(ctx, t.blocks);
+    return fail(RTM_E_NOMEM, "arena exhausted (control block)");
+  }
+  t.ctl = static_cast<StepCtl*>(p);
+  HIP_OK(hipMemcpyAsync(t.jobs, t.hjobs->data(), t.hjobs->size() * sizeof(DevJob), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(t.tiles, t.htiles->data(), t.htiles->size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+  StepCtl c{};
+  c.ntiles = t.ntiles;
+  HIP_OK(hipMemcpyAsync(t.ctl, &c, sizeof c, hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));  // host-side staging copies are complete
+  return RTM_OK;
+}
+
+// ===========================================================================
+// C ABI: helpers and context
+// ===========================================================================
+extern "C" const char* rtm_status_str(int st) {
+  switch (st) {
+    case RTM_OK: return "ok";
+    case RTM_E_INVAL: return "invalid argument";
+    case RTM_E_CFL: return "CFL stability limit exceeded";
+    case RTM_E_NOMEM: return "arena exhausted";
+    case RTM_E_AGAIN: return "queue full, retry";
+    case RTM_E_NOTFOUND: return "not found";
+    case RTM_E_NONFINITE: return "non-finite value";
+    case RTM_E_DEVICE: return "HIP runtime error";
+    case RTM_E_CANCELLED: return "cancelled";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* rtm_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int rtm_version(void) { return 10000; }
+
+static void sched_main(rtm_ctx* ctx);
+
+extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t arena_bytes,
+                              void* hip_stream, uint32_t flags) {
+  (void)flags;
+  if (!out) return fail(RTM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (arena_bytes < (1u << 20)) return fail(RTM_E_INVAL, "arena must be at least 1 MiB");
+  int ndev = 0;
+  HIP_OK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(RTM_E_INVAL, "device %d not present (%d devices)", device, ndev);
+  HIP_OK(hipSetDevice(device));
+  auto ctx = std::make_unique<rtm_ctx>();
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (!arena_dev) {
+    HIP_OK(hipMalloc(&ctx->own_arena, arena_bytes));
+    arena_dev = ctx->own_arena;
+  }
+  if ((reinterpret_cast<uintptr_t>(arena_dev) & 255) != 0)
+    return fail(RTM_E_INVAL, "arena must be 256-byte aligned");
+  ctx->arena.init(arena_dev, arena_bytes);
+  HIP_OK(hipStreamCreateWithFlags(&ctx->sched_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamCreateWithFlags(&ctx->work_stream, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+  for (auto& e : ctx->ph_ev) HIP_OK(hipEventCreate(&e));
+  ctx->scratch_u32 = static_cast<uint32_t*>(ctx->arena.alloc(256));
+  ctx->scratch_f64 = static_cast<double*>(ctx->arena.alloc(256));
+  *out = ctx.release();
+  return RTM_OK;
+}
+
+extern "C" int rtm_ctx_synchronize(rtm_ctx* ctx) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  reap(ctx, false);
+  return RTM_OK;
+}
+
+extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
+  if (!ctx) return RTM_OK;
+  (void)hipSetDevice(ctx->device);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stop = true;
+  }
+  ctx->cv.notify_all();
+  if (ctx->sched.joinable()) ctx->sched.join();
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->sched_stream);
+  reap(ctx, false);
+  while (true) {
+    bool empty;
+    {
+      std::lock_guard<std::mutex> lk(ctx->defer_mu);
+      empty = ctx->deferred.empty();
+    }
+    if (empty) break;
+    reap(ctx, true);
+  }
+  (void)hipStreamSynchronize(ctx->work_stream);
+  reap(ctx, false);
+  (void)hipStreamDestroy(ctx->sched_stream);
+  (void)hipStreamDestroy(ctx->work_stream);
+  (void)hipEventDestroy(ctx->ev_in);
+  (void)hipEventDestroy(ctx->ev_out);
+  for (auto e : ctx->ph_ev) (void)hipEventDestroy(e);
+  if (ctx->own_arena) (void)hipFree(ctx->own_arena);
+  delete ctx;
+  return RTM_OK;
+}
+
+// ===========================================================================
+// Plain path
+// ===========================================================================
+static int run_plain(rtm_ctx* ctx, hipStream_t s, HostJob& j, int tz, Table& t) {
+  std::vector<HostJob*> js{&j};
+  int rc = upload_table(ctx, s, js, t);
+  if (rc) return rc;
+  const int nsteps = j.d.nsteps;
+  const int nf = j.g.mode == kModeModel ? nsteps : j.g.nt - 1;
+  for (int st = 0; st < nsteps; ++st) {
+    HIP_OK(launch_step(tz, st < nf ? kPhFwd : kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 0, st, s));
+  }
+  ctx->steps_launched += nsteps;
+  return RTM_OK;
+}
+
+static void finish_job_deferred(rtm_ctx* ctx, hipStream_t s, HostJob& j, Table& t, bool keep_image) {
+  Deferred d;
+  d.blocks = std::move(j.blocks);
+  for (auto& b : t.blocks) d.blocks.push_back(b);
+  t.blocks.clear();
+  if (!keep_image && j.image_blk.p) d.blocks.push_back(j.image_blk);
+  d.keep.push_back(t.hjobs);
+  d.keep.push_back(t.htiles);
+  defer(ctx, s, std::move(d));
+}
+
+extern "C" int rtm_propagate(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev,
+                             const float* wavelet_dev, rtm_point src, int32_t nrec,
+                             const rtm_point* rec_host, float* traces_dev, float* final_field_dev) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!vel_dev || !wavelet_dev) return fail(RTM_E_INVAL, "vel_dev and wavelet_dev are required");
+  if (nrec > 0 && !traces_dev) return fail(RTM_E_INVAL, "traces_dev is required when nrec > 0");
+  JobGeom g;
+  g.nz = grid->nz;
+  g.model_nx = grid->nx;
+  g.ix0 = 0;
+  g.width = grid->nx;
+  g.nb = grid->nb;
+  g.nt = grid->nt;
+  g.dz = grid->dz;
+  g.dx = grid->dx;
+  g.dt = grid->dt;
+  g.sponge_a = grid->sponge_a;
+  g.mode = kModeModel;
+  g.nrec = nrec;
+  if ((rc = check_job(g, src, rec_host))) return rc;
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  float vmax = 0;
+  if ((rc = device_vmax(ctx, s, vel_dev, g.nz, g.model_nx, 0, g.width, &vmax))) return rc;
+  if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
+  const int tz = choose_tz(ctx);
+  HostJob j;
+  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, nullptr, traces_dev, j))) return rc;
+  Table t;
+  if ((rc = run_plain(ctx, s, j, tz, t))) {
+    finish_job_deferred(ctx, s, j, t, false);
+    return rc;
+  }
+  if (final_field_dev)
+    HIP_OK(launch_copy_phys(final_field_dev, j.d.f[(g.nt - 1) & 1], g.nz, g.width, g.nb, j.d.pitch, s));
+  ctx->grid_updates += j.updates;
+  ctx->alg_bytes += j.alg_bytes;
+  finish_job_deferred(ctx, s, j, t, false);
+  return RTM_OK;
+}
+
+static int fill_geom_rtm(const rtm_grid* grid, int32_t ix0, int32_t width, const rtm_img_opts* opts, int nrec,
+                         JobGeom& g) {
+  g.nz = grid->nz;
+  g.model_nx = grid->nx;
+  g.ix0 = ix0;
+  g.width = width;
+  g.nb = grid->nb;
+  g.nt = grid->nt;
+  g.dz = grid->dz;
+  g.dx = grid->dx;
+  g.dt = grid->dt;
+  g.sponge_a = grid->sponge_a;
+  rtm_img_opts o{};
+  o.src_mode = RTM_SRC_RECONSTRUCT;
+  o.snap_stride = 1;
+  if (opts) o = *opts;
+  if (o.src_mode == RTM_SRC_RECONSTRUCT) {
+    g.mode = kModeRecon;
+    g.snap_stride = 1;
+  } else if (o.src_mode == RTM_SRC_STORE) {
+    g.mode = kModeStore;
+    g.snap_stride = o.snap_stride;
+    g.snap_dtype = o.snap_dtype;
+  } else {
+    return fail(RTM_E_INVAL, "unknown src_mode %d", o.src_mode);
+  }
+  g.flags = o.flags;
+  g.nrec = nrec;
+  return RTM_OK;
+}
+
+extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev,
+                                const float* wavelet_dev, rtm_point src, int32_t nrec,
+                                const rtm_point* rec_host, const float* data_dev, int32_t ix0,
+                                int32_t width, const rtm_img_opts* opts, float* image_dev,
+                                float* illum_dev) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!vel_dev || !wavelet_dev || !image_dev) return fail(RTM_E_INVAL, "vel_dev, wavelet_dev, image_dev are required");
+  if (nrec > 0 && !data_dev) return fail(RTM_E_INVAL, "data_dev is required when nrec > 0");
+  JobGeom g;
+  if ((rc = fill_geom_rtm(grid, ix0, width, opts, nrec, g))) return rc;
+  if (illum_dev && !(g.flags & RTM_IMG_ILLUM)) g.flags |= RTM_IMG_ILLUM;
+  if ((rc = check_job(g, src, rec_host))) return rc;
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  float vmax = 0;
+  if ((rc = device_vmax(ctx, s, vel_dev, g.nz, g.model_nx, ix0, width, &vmax))) return rc;
+  if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
+  const int tz = choose_tz(ctx);
+  HostJob j;
+  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, data_dev, nullptr, j))) return rc;
+  Table t;
+  rc = run_plain(ctx, s, j, tz, t);
+  if (!rc) {
+    HIP_OK(launch_stack(image_dev, g.model_nx, ix0, j.d.image, g.nz, width, s));
+    if (illum_dev && j.d.illum) HIP_OK(launch_stack(illum_dev, g.model_nx, ix0, j.d.illum, g.nz, width, s));
+    ctx->grid_updates += j.updates;
+    ctx->alg_bytes += j.alg_bytes;
+  }
+  finish_job_deferred(ctx, s, j, t, false);
+  return rc;
+}
+
+// ===========================================================================
+// Batched path: all shots in every launch, hipGraph replays of K steps
+// ===========================================================================
+// Runs nsteps launches of the step kernel: whole groups of K as replays of a
+// captured graph (K step nodes with offsets 0..K-1, then one k_advance node),
+// the remainder as direct launches followed by one k_advance.
+static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, int nsteps, int K,
+                       std::vector<hipGraphExec_t>& graphs) {
+  int done = 0;
+  if (nsteps >= K && K > 1) {
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < K && e == hipSuccess; ++i)
+      e = launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, i, s);
+    if (e == hipSuccess) e = launch_advance(t.ctl, K, s);
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(RTM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(RTM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    graphs.push_back(ex);
+    for (; done + K <= nsteps; done += K) {
+      HIP_OK(hipGraphLaunch(ex, s));
+      ctx->graph_replays++;
+    }
+  }
+  if (done < nsteps) {
+    for (int i = 0; done + i < nsteps; ++i)
+      HIP_OK(launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, i, s));
+    HIP_OK(launch_advance(t.ctl, nsteps - done, s));
+  }
+  ctx->steps_launched += nsteps;
+  return RTM_OK;
+}
+
+static int graph_k() {
+  const char* e = getenv("RTM_GRAPH_STEPS");
+  int k = e ? atoi(e) : 64;
+  return k < 1 ? 1 : k;
+}
+
+extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev,
+                                 const float* wavelet_dev, int32_t nshots, const rtm_shot_desc* shots,
+                                 const rtm_img_opts* opts, float* image_dev, float* illum_dev) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (nshots < 1 || !shots) return fail(RTM_E_INVAL, "need at least one shot");
+  if (!vel_dev || !wavelet_dev || !image_dev) return fail(RTM_E_INVAL, "vel_dev, wavelet_dev, image_dev are required");
+  std::vector<JobGeom> geoms(nshots);
+  for (int i = 0; i < nshots; ++i) {
+    if ((rc = fill_geom_rtm(grid, shots[i].ix0, shots[i].width, opts, shots[i].nrec, geoms[i]))) return rc;
+    if (illum_dev) geoms[i].flags |= RTM_IMG_ILLUM;
+    if ((rc = check_job(geoms[i], shots[i].src, shots[i].rec_host))) return rc;
+    if (shots[i].nrec > 0 && !shots[i].data_dev) return fail(RTM_E_INVAL, "shot %d has no data", i);
+  }
+  size_t need = 0;
+  for (auto& g : geoms) need += footprint(g).total;
+  if (need > ctx->arena.size())
+    return fail(RTM_E_NOMEM, "batch needs %zu bytes, arena holds %zu", need, ctx->arena.size());
+  HIP_OK(hipSetDevice(ctx->device));
+  // All batch work runs on the library's work stream, ordered after and
+  // before the caller's stream by events (capture is not allowed on the
+  // legacy null stream).
+  hipStream_t s = ctx->work_stream;
+  HIP_OK(hipEventRecord(ctx->ev_in, ctx->stream));
+  HIP_OK(hipStreamWaitEvent(s, ctx->ev_in, 0));
+  float vmax = 0;
+  if ((rc = device_vmax(ctx, s, vel_dev, grid->nz, grid->nx, 0, grid->nx, &vmax))) return rc;
+  if ((rc = check_cfl(vmax, grid->dt, grid->dz, grid->dx))) return rc;
+  const int tz = choose_tz(ctx);
+  std::vector<std::unique_ptr<HostJob>> jobs;
+  std::vector<HostJob*> ptrs;
+  auto cleanup = [&]() {
+    for (auto& j : jobs) {
+      release_blocks(ctx, j->blocks);
+      if (j->image_blk.p) ctx->arena.release(j->image_blk.p, j->image_blk.n);
+    }
+  };
+  for (int i = 0; i < nshots; ++i) {
+    auto j = std::make_unique<HostJob>();
+    rc = build_job(ctx, s, geoms[i], tz, vel_dev, wavelet_dev, shots[i].src, shots[i].rec_host,
+                   shots[i].data_dev, nullptr, *j);
+    if (rc) {
+      (void)hipStreamSynchronize(s);
+      cleanup();
+      return rc;
+    }
+    ptrs.push_back(j.get());
+    jobs.push_back(std::move(j));
+  }
+  Table t;
+  if ((rc = upload_table(ctx, s, ptrs, t))) {
+    cleanup();
+    return rc;
+  }
+  const int nt = grid->nt, K = graph_k();
+  std::vector<hipGraphExec_t> graphs;
+  HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
+  rc = graph_steps(ctx, s, tz, kPhFwd, t, nt - 1, K, graphs);
+  if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
+  if (!rc) rc = graph_steps(ctx, s, tz, kPhBwd, t, nt, K, graphs);
+  if (!rc) rc = hipEventRecord(ctx->ph_ev[2], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
+  if (!rc) {
+    // algorithmic bytes of one forward / one backward launch over all shots
+    uint64_t bf = 0, bb = 0;
+    for (auto& j : jobs) {
+      const JobGeom& g = j->g;
+      const uint64_t Npad = (uint64_t)(g.nz + 2 * g.nb) * (g.width + 2 * g.nb), Nph = (uint64_t)g.nz * g.width;
+      const uint64_t ring = ring_len_of(g.nz, g.width);
+      bf += Npad * 16 + (g.mode == kModeRecon ? ring * 4 : 0);
+      bb += Npad * 16 + (uint64_t)g.nrec * 4;
+      if (g.mode == kModeRecon) bb += Nph * 20 - ring * 8;  // interior S 12 B + image 8 B; ring S 4 B + image 8 B
+    }
+    ctx->ph_launches[0] = nt - 1;
+    ctx->ph_launches[1] = nt;
+    ctx->ph_bytes[0] = bf;
+    ctx->ph_bytes[1] = bb;
+    ctx->ph_valid = true;
+  }
+  if (!rc) {
+    for (int i = 0; i < nshots && !rc; ++i) {
+      hipError_t e = launch_stack(image_dev, grid->nx, geoms[i].ix0, jobs[i]->d.image, grid->nz, geoms[i].width, s);
+      if (e == hipSuccess && illum_dev)
+        e = launch_stack(illum_dev, grid->nx, geoms[i].ix0, jobs[i]->d.illum, grid->nz, geoms[i].width, s);
+      if (e != hipSuccess) rc = fail(RTM_E_DEVICE, "stack launch failed: %s", hipGetErrorString(e));
+    }
+  }
+  Deferred d;
+  for (auto& j : jobs) {
+    for (auto& b : j->blocks) d.blocks.push_back(b);
+    j->blocks.clear();
+    if (j->image_blk.p) d.blocks.push_back(j->image_blk);
+    ctx->grid_updates += rc ? 0 : j->updates;
+    ctx->alg_bytes += rc ? 0 : j->alg_bytes;
+  }
+  for (auto& b : t.blocks) d.blocks.push_back(b);
+  d.keep.push_back(t.hjobs);
+  d.keep.push_back(t.htiles);
+  d.graphs = graphs;
+  int rc2 = defer(ctx, s, std::move(d));
+  HIP_OK(hipEventRecord(ctx->ev_out, s));
+  HIP_OK(hipStreamWaitEvent(ctx->stream, ctx->ev_out, 0));
+  return rc ? rc : rc2;
+}
+
+// ===========================================================================
+// Ensemble path: model bank, job queue, scheduler thread
+// ===========================================================================
+extern "C" int rtm_model_register(rtm_ctx* ctx, int32_t realization, const float* vel_dev, int32_t nz,
+                                  int32_t nx, const rtm_grid* grid) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!vel_dev || nz != grid->nz || nx != grid->nx)
+    return fail(RTM_E_INVAL, "velocity [%d][%d] does not match the grid [%d][%d]", nz, nx, grid->nz, grid->nx);
+  HIP_OK(hipSetDevice(ctx->device));
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  if (!ctx->models.empty()) {
+    const Model& m0 = ctx->models.begin()->second;
+    if (m0.nz != nz || m0.nx != nx)
+      return fail(RTM_E_INVAL, "all registered models must share one size (%d x %d)", m0.nz, m0.nx);
+  }
+  auto it = ctx->models.find(realization);
+  if (it != ctx->models.end() && it->second.active > 0)
+    return fail(RTM_E_AGAIN, "realization %d has jobs in flight", realization);
+  lk.unlock();
+  Block vb;
+  vb.n = align256((size_t)nz * nx * 4);
+  vb.p = arena_alloc(ctx, vb.n);
+  if (!vb.p) return fail(RTM_E_NOMEM, "arena exhausted (velocity bank)");
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipMemcpyAsync(vb.p, vel_dev, (size_t)nz * nx * 4, hipMemcpyDeviceToDevice, s);
+  float vmax = 0;
+  if (e != hipSuccess || (rc = device_vmax(ctx, s, static_cast<float*>(vb.p), nz, nx, 0, nx, &vmax))) {
+    ctx->arena.release(vb.p, vb.n);
+    return e != hipSuccess ? fail(RTM_E_DEVICE, "copy failed: %s", hipGetErrorString(e)) : rc;
+  }
+  lk.lock();
+  Model& m = ctx->models[realization];
+  if (m.vel.p) ctx->arena.release(m.vel.p, m.vel.n);
+  m.nz = nz;
+  m.nx = nx;
+  m.grid = *grid;
+  m.vel = vb;
+  m.vmax = vmax;
+  return RTM_OK;
+}
+
+extern "C" int rtm_ensemble_submit(rtm_ctx* ctx, const rtm_job* job, uint64_t* ticket) {
+  if (!ctx || !job || !ticket) return fail(RTM_E_INVAL, "ctx, job and ticket are required");
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  auto it = ctx->models.find(job->realization);
+  if (it == ctx->models.end()) return fail(RTM_E_NOTFOUND, "realization %d is not registered", job->realization);
+  Model& m = it->second;
+  rtm_grid gr = m.grid;
+  gr.nt = job->nt;
+  int rc = check_grid(&gr);
+  if (rc) return rc;
+  if (!job->wavelet_dev || !job->data_dev) return fail(RTM_E_INVAL, "wavelet_dev and data_dev are required");
+  JobGeom g;
+  if ((rc = fill_geom_rtm(&gr, job->ix0, job->width, &job->img, job->width, g))) return rc;
+  // receivers: every window column at row rec_iz
+  if (job->rec_iz < 0 || job->rec_iz >= gr.nz) return fail(RTM_E_INVAL, "rec_iz %d outside the model", job->rec_iz);
+  rtm_point probe{job->rec_iz, job->ix0};
+  g.nrec = 0;
+  if ((rc = check_job(g, job->src, &probe))) return rc;
+  g.nrec = job->width;
+  if ((rc = check_cfl(m.vmax, gr.dt, gr.dz, gr.dx))) return rc;
+  if (footprint(g).total + 4096 > ctx->arena.size())
+    return fail(RTM_E_NOMEM, "job needs %zu bytes, larger than the whole arena (%zu)", footprint(g).total,
+                ctx->arena.size());
+  if ((int)ctx->queue.size() >= ctx->queue_cap) return fail(RTM_E_AGAIN, "queue full (%d)", ctx->queue_cap);
+  auto ej = std::make_unique<EnsJob>();
+  ej->ticket = ctx->next_ticket++;
+  ej->spec = *job;
+  ej->t_submit = now_s();
+  *ticket = ej->ticket;
+  ctx->queue.push_back(ej->ticket);
+  ctx->jobs.emplace(ej->ticket, std::move(ej));
+  m.active++;
+  ctx->jobs_submitted++;
+  ctx->queued_jobs = (int)ctx->queue.size();
+  if (!ctx->sched_started) {
+    ctx->sched_started = true;
+    ctx->sched = std::thread(sched_main, ctx);
+  }
+  lk.unlock();
+  ctx->cv.notify_all();
+  return RTM_OK;
+}
+
+static int ensure_stats(rtm_ctx* ctx, hipStream_t s, Model& m, bool stats, bool stack) {
+  const size_t n = (size_t)m.nz * m.nx;
+  if (stats && !m.mean.p) {
+    m.mean = {arena_alloc(ctx, n * 8), align256(n * 8)};
+    m.m2 = {arena_alloc(ctx, n * 8), align256(n * 8)};
+    m.count = {arena_alloc(ctx, n * 4), align256(n * 4)};
+    if (!m.mean.p || !m.m2.p || !m.count.p) return fail(RTM_E_NOMEM, "arena exhausted (statistics)");
+    HIP_OK(hipMemsetAsync(m.mean.p, 0, n * 8, s));
+    HIP_OK(hipMemsetAsync(m.m2.p, 0, n * 8, s));
+    HIP_OK(hipMemsetAsync(m.count.p, 0, n * 4, s));
+  }
+  if (stack && !m.stack.p) {
+    m.stack = {arena_alloc(ctx, n * 4), align256(n * 4)};
+    if (!m.stack.p) return fail(RTM_E_NOMEM, "arena exhausted (stack)");
+    HIP_OK(hipMemsetAsync(m.stack.p, 0, n * 4, s));
+  }
+  return RTM_OK;
+}
+
+struct SchedTables {
+  std::vector<Block> blocks;
+  DevJob* jobs = nullptr;
+  Tile* tiles = nullptr;
+  StepCtl* ctl = nullptr;
+  int cap_jobs = 0, cap_tiles = 0;
+  std::map<int, hipGraphExec_t> graphs;  // grid-tile bucket -> K-step graph
+  std::vector<DevJob> hjobs;
+  std::vector<Tile> htiles;
+};
+
+static int tile_bucket(int n) {
+  int b = 256;
+  while (b < n) b <<= 1;
+  return b;
+}
+
+static int sched_cycle(rtm_ctx* ctx, SchedTables& T, std::vector<EnsJob*>& active, bool& changed, int& tick,
+                       int tz, int K) {
+  hipStream_t s = ctx->sched_stream;
+  if (changed) {
+    T.hjobs.clear();
+    T.htiles.clear();
+    for (size_t i = 0; i < active.size(); ++i) {
+      T.hjobs.push_back(active[i]->job->d);
+      for (Tile tl : active[i]->job->tiles) {
+        tl.job = (int)i;
+        T.htiles.push_back(tl);
+      }
+    }
+    const int nj = (int)T.hjobs.size(), ntl = (int)T.htiles.size();
+    if (nj > T.cap_jobs || ntl > T.cap_tiles) {
+      HIP_OK(hipStreamSynchronize(s));
+      for (auto& kv : T.graphs) (void)hipGraphExecDestroy(kv.second);
+      T.graphs.clear();
+      release_blocks(ctx, T.blocks);
+      T.cap_jobs = std::max(64, tile_bucket(nj));
+      T.cap_tiles = tile_bucket(ntl);
+      void* p;
+      if (!alloc_block(ctx, T.blocks, (size_t)T.cap_jobs * sizeof(DevJob), &p)) return fail(RTM_E_NOMEM, "job table");
+      T.jobs = static_cast<DevJob*>(p);
+      if (!alloc_block(ctx, T.blocks, (size_t)T.cap_tiles * sizeof(Tile), &p)) return fail(RTM_E_NOMEM, "tile table");
+      T.tiles = static_cast<Tile*>(p);
+      if (!alloc_block(ctx, T.blocks, sizeof(StepCtl), &p)) return fail(RTM_E_NOMEM, "control block");
+      T.ctl = static_cast<StepCtl*>(p);
+      StepCtl c{};
+      c.tick = tick;
+      HIP_OK(hipMemcpyAsync(T.ctl, &c, sizeof c, hipMemcpyHostToDevice, s));
+    }
+    HIP_OK(hipMemcpyAsync(T.jobs, T.hjobs.data(), T.hjobs.size() * sizeof(DevJob), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(T.tiles, T.htiles.data(), T.htiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+    int ntl_i = ntl;
+    HIP_OK(hipMemcpyAsync(&T.ctl->ntiles, &ntl_i, sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    changed = false;
+  }
+  const int ntl = (int)T.htiles.size();
+  const int bucket = tile_bucket(ntl);
+  auto git = T.graphs.find(bucket);
+  if (git == T.graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e0 = hipSuccess;
+    for (int i = 0; i < K && e0 == hipSuccess; ++i)
+      e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, bucket, T.ctl, 1, i, s);
+    if (e0 == hipSuccess) e0 = launch_advance(T.ctl, K, s);
+    hipError_t e1 = hipStreamEndCapture(s, &g);
+    if (e0 != hipSuccess || e1 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(RTM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e0 != hipSuccess ? e0 : e1));
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(RTM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    git = T.graphs.emplace(bucket, ex).first;
+  }
+  HIP_OK(hipGraphLaunch(git->second, s));
+  ctx->graph_replays++;
+  ctx->steps_launched += K;
+  tick += K;
+  HIP_OK(hipStreamSynchronize(s));
+  return RTM_OK;
+}
+
+static void sched_main(rtm_ctx* ctx) {
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->sched_stream;
+  SchedTables T;
+  std::vector<EnsJob*> active;
+  bool changed = false;
+  int tick = 0;
+  const int tz = choose_tz(ctx);
+  const int K = std::max(1, std::min(graph_k(), 64));
+  const int kMaxBypass = 8;
+  for (;;) {
+    // ---- admission (FIFO with bounded bypass) ----
+    {
+      std::unique_lock<std::mutex> lk(ctx->mu);
+      if (ctx->stop) break;
+      if (active.empty() && ctx->queue.empty()) {
+        ctx->cv_done.notify_all();
+        ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty(); });
+        continue;
+      }
+      bool blocked_head = false;
+      for (auto qi = ctx->queue.begin(); qi != ctx->queue.end();) {
+        EnsJob* ej = ctx->jobs[*qi].get();
+        Model& m = ctx->models[ej->spec.realization];
+        JobGeom g;
+        rtm_grid gr = m.grid;
+        gr.nt = ej->spec.nt;
+        fill_geom_rtm(&gr, ej->spec.ix0, ej->spec.width, &ej->spec.img, ej->spec.width, g);
+        auto hj = std::make_unique<HostJob>();
+        std::vector<rtm_point> recs(ej->spec.width);
+        for (int r = 0; r < ej->spec.width; ++r) recs[r] = {ej->spec.rec_iz, ej->spec.ix0 + r};
+        int rc = RTM_OK;
+        bool st = ej->spec.flags & RTM_JOB_ACC_STATS, sk = ej->spec.flags & RTM_JOB_ACC_STACK;
+        rc = ensure_stats(ctx, s, m, st, sk);
+        if (!rc)
+          rc = build_job(ctx, s, g, tz, static_cast<const float*>(m.vel.p), ej->spec.wavelet_dev, ej->spec.src,
+                         recs.data(), ej->spec.data_dev, nullptr, *hj);
+        if (rc == RTM_E_NOMEM) {
+          if (blocked_head || ++ej->bypassed > kMaxBypass) break;  // keep the head from starving
+          blocked_head = true;
+          ++qi;
+          continue;
+        }
+        if (rc) {
+          ej->state = RTM_JOB_FAILED;
+          ej->status = rc;
+          ej->t_done = now_s();
+          m.active--;
+          ctx->jobs_failed++;
+          qi = ctx->queue.erase(qi);
+          continue;
+        }
+        hj->d.start_tick = tick;
+        ej->job = std::move(hj);
+        ej->state = RTM_JOB_RUNNING;
+        ej->t_admit = now_s();
+        active.push_back(ej);
+        changed = true;
+        qi = ctx->queue.erase(qi);
+      }
+      ctx->active_jobs = (int)active.size();
+      ctx->queued_jobs = (int)ctx->queue.size();
+    }
+    if (active.empty()) {
+      // nothing fits right now: wait for deferred frees, then retry
+      reap(ctx, true);
+      std::this_thread::sleep_for(std::chrono::milliseconds(1));
+      continue;
+    }
+    // ---- K steps of every active job ----
+    int rc = sched_cycle(ctx, T, active, changed, tick, tz, K);
+    // ---- finalise finished jobs ----
+    std::vector<EnsJob*> still;
+    std::vector<EnsJob*> finished;
+    for (EnsJob* ej : active) {
+      if (rc || ej->job->d.start_tick + ej->job->d.nsteps <= tick)
+        finished.push_back(ej);
+      else
+        still.push_back(ej);
+    }
+    if (!finished.empty()) {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      Deferred d;
+      for (EnsJob* ej : finished) {
+        HostJob& j = *ej->job;
+        Model& m = ctx->models[ej->spec.realization];
+        if (!rc) {
+          if ((ej->spec.flags & RTM_JOB_ACC_STATS) && m.mean.p)
+            (void)launch_welford(static_cast<double*>(m.mean.p), static_cast<double*>(m.m2.p),
+                           static_cast<int32_t*>(m.count.p), m.nx, j.d.image, j.g.nz, j.g.width, j.g.ix0, s);
+          if ((ej->spec.flags & RTM_JOB_ACC_STACK) && m.stack.p)
+            (void)launch_stack(static_cast<float*>(m.stack.p), m.nx, j.g.ix0, j.d.image, j.g.nz, j.g.width, s);
+        }
+        for (auto& b : j.blocks) d.blocks.push_back(b);
+        j.blocks.clear();
+        ej->state = rc ? RTM_JOB_FAILED : RTM_JOB_DONE;
+        ej->status = rc;
+        m.active--;
+        if (rc) {
+          ctx->jobs_failed++;
+        } else {
+          ctx->jobs_done++;
+          ctx->grid_updates += j.updates;
+          ctx->alg_bytes += j.alg_bytes;
+        }
+      }
+      (void)hipStreamSynchronize(s);
+      const double t = now_s();
+      for (EnsJob* ej : finished) ej->t_done = t;
+      defer(ctx, s, std::move(d));
+      active.swap(still);
+      changed = true;
+      ctx->active_jobs = (int)active.size();
+    }
+    ctx->cv_done.notify_all();
+  }
+  (void)hipStreamSynchronize(s);
+  for (auto& kv : T.graphs) (void)hipGraphExecDestroy(kv.second);
+  release_blocks(ctx, T.blocks);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (EnsJob* ej : active) {
+    release_blocks(ctx, ej->job->blocks);
+    ej->state = RTM_JOB_CANCELLED;
+    ej->status = RTM_E_CANCELLED;
+  }
+  ctx->cv_done.notify_all();
+}
+
+extern "C" int rtm_ensemble_poll(rtm_ctx* ctx, uint64_t ticket, rtm_job_info* info, float* image_dev,
+                                 int32_t release) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  auto it = ctx->jobs.find(ticket);
+  if (it == ctx->jobs.end()) return fail(RTM_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  EnsJob& ej = *it->second;
+  if (info) {
+    info->state = ej.state;
+    info->status = ej.status;
+    info->t_submit = ej.t_submit;
+    info->t_admit = ej.t_admit;
+    info->t_done = ej.t_done;
+    info->grid_updates = ej.job ? ej.job->updates : 0;
+    info->alg_bytes = ej.job ? ej.job->alg_bytes : 0;
+    info->user_tag = ej.spec.user_tag;
+  }
+  const bool final = ej.state == RTM_JOB_DONE || ej.state == RTM_JOB_FAILED || ej.state == RTM_JOB_CANCELLED;
+  if (ej.state == RTM_JOB_DONE && image_dev && ej.job && ej.job->image_blk.p) {
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipMemcpyAsync(image_dev, ej.job->image_blk.p, (size_t)ej.job->g.nz * ej.job->g.width * 4,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  if (final && release) {
+    Deferred d;
+    if (ej.job && ej.job->image_blk.p) d.blocks.push_back(ej.job->image_blk);
+    ctx->jobs.erase(it);
+    lk.unlock();
+    return defer(ctx, ctx->stream, std::move(d));
+  }
+  return RTM_OK;
+}
+
+extern "C" int rtm_ensemble_cancel(rtm_ctx* ctx, uint64_t ticket) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->jobs.find(ticket);
+  if (it == ctx->jobs.end()) return fail(RTM_E_NOTFOUND, "unknown ticket");
+  EnsJob& ej = *it->second;
+  if (ej.state != RTM_JOB_QUEUED) return fail(RTM_E_INVAL, "job is no longer queued");
+  auto qi = std::find(ctx->queue.begin(), ctx->queue.end(), ticket);
+  if (qi != ctx->queue.end()) ctx->queue.erase(qi);
+  ej.state = RTM_JOB_CANCELLED;
+  ej.status = RTM_E_CANCELLED;
+  ej.t_done = now_s();
+  ctx->models[ej.spec.realization].active--;
+  ctx->jobs_cancelled++;
+  ctx->queued_jobs = (int)ctx->queue.size();
+  ctx->cv_done.notify_all();
+  return RTM_OK;
+}
+
+extern "C" int rtm_ensemble_drain(rtm_ctx* ctx) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  ctx->cv_done.wait(lk, [&] { return ctx->queue.empty() && ctx->active_jobs == 0; });
+  lk.unlock();
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(hipStreamSynchronize(ctx->sched_stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_ensemble_stats(rtm_ctx* ctx, int32_t realization, double* mean_dev, double* std_dev,
+                                  int32_t* count_dev) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->models.find(realization);
+  if (it == ctx->models.end()) return fail(RTM_E_NOTFOUND, "realization %d is not registered", realization);
+  Model& m = it->second;
+  const int64_t n = (int64_t)m.nz * m.nx;
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(hipStreamSynchronize(ctx->sched_stream));
+  if (!m.mean.p) {
+    if (mean_dev) HIP_OK(hipMemsetAsync(mean_dev, 0, n * 8, ctx->stream));
+    if (std_dev) HIP_OK(hipMemsetAsync(std_dev, 0, n * 8, ctx->stream));
+    if (count_dev) HIP_OK(hipMemsetAsync(count_dev, 0, n * 4, ctx->stream));
+    return RTM_OK;
+  }
+  HIP_OK(launch_stats_out(static_cast<double*>(m.mean.p), static_cast<double*>(m.m2.p),
+                          static_cast<int32_t*>(m.count.p), n, mean_dev, std_dev, count_dev, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_ensemble_stack(rtm_ctx* ctx, int32_t realization, float* stack_dev) {
+  if (!ctx || !stack_dev) return fail(RTM_E_INVAL, "ctx and stack_dev are required");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->models.find(realization);
+  if (it == ctx->models.end()) return fail(RTM_E_NOTFOUND, "realization %d is not registered", realization);
+  Model& m = it->second;
+  const size_t n = (size_t)m.nz * m.nx;
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(hipStreamSynchronize(ctx->sched_stream));
+  if (!m.stack.p)
+    HIP_OK(hipMemsetAsync(stack_dev, 0, n * 4, ctx->stream));
+  else
+    HIP_OK(hipMemcpyAsync(stack_dev, m.stack.p, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  return RTM_OK;
+}
+
+// ===========================================================================
+// Explicit-image statistics, Stage-3 maps, post-stack filter
+// ===========================================================================
+struct rtm_stats {
+  int nz = 0, nx = 0;
+  Block mean, m2, count;
+};
+
+extern "C" int rtm_stats_create(rtm_ctx* ctx, rtm_stats** out, int32_t nz, int32_t nx) {
+  if (!ctx || !out || nz < 1 || nx < 1) return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  auto st = std::make_unique<rtm_stats>();
+  st->nz = nz;
+  st->nx = nx;
+  const size_t n = (size_t)nz * nx;
+  st->mean = {arena_alloc(ctx, n * 8), align256(n * 8)};
+  st->m2 = {arena_alloc(ctx, n * 8), align256(n * 8)};
+  st->count = {arena_alloc(ctx, n * 4), align256(n * 4)};
+  if (!st->mean.p || !st->m2.p || !st->count.p) {
+    ctx->arena.release(st->mean.p, st->mean.n);
+    ctx->arena.release(st->m2.p, st->m2.n);
+    ctx->arena.release(st->count.p, st->count.n);
+    return fail(RTM_E_NOMEM, "arena exhausted (statistics)");
+  }
+  HIP_OK(hipMemsetAsync(st->mean.p, 0, n * 8, ctx->stream));
+  HIP_OK(hipMemsetAsync(st->m2.p, 0, n * 8, ctx->stream));
+  HIP_OK(hipMemsetAsync(st->count.p, 0, n * 4, ctx->stream));
+  *out = st.release();
+  return RTM_OK;
+}
+
+extern "C" int rtm_stats_destroy(rtm_ctx* ctx, rtm_stats* st) {
+  if (!ctx || !st) return fail(RTM_E_INVAL, "bad arguments");
+  Deferred d;
+  d.blocks = {st->mean, st->m2, st->count};
+  delete st;
+  return defer(ctx, ctx->stream, std::move(d));
+}
+
+extern "C" int rtm_stats_add(rtm_ctx* ctx, rtm_stats* st, const float* image_dev, int32_t ix0, int32_t width) {
+  if (!ctx || !st || !image_dev) return fail(RTM_E_INVAL, "bad arguments");
+  if (ix0 < 0 || width < 1 || ix0 + width > st->nx) return fail(RTM_E_INVAL, "window outside the image");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_welford(static_cast<double*>(st->mean.p), static_cast<double*>(st->m2.p),
+                        static_cast<int32_t*>(st->count.p), st->nx, image_dev, st->nz, width, ix0, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_stats_get(rtm_ctx* ctx, rtm_stats* st, double* mean_dev, double* std_dev, int32_t* count_dev) {
+  if (!ctx || !st) return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_stats_out(static_cast<double*>(st->mean.p), static_cast<double*>(st->m2.p),
+                          static_cast<int32_t*>(st->count.p), (int64_t)st->nz * st->nx, mean_dev, std_dev,
+                          count_dev, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_confidence_map(rtm_ctx* ctx, const double* std_dev, const int32_t* count_dev, int32_t n,
+                                  int32_t min_count, double* conf_dev) {
+  if (!ctx || !std_dev || !conf_dev || n < 1) return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_confidence(std_dev, count_dev, n, min_count, conf_dev, ctx->scratch_f64, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_ratio_map(rtm_ctx* ctx, const double* std_dev, const double* mean_dev, int32_t n, double eps,
+                             double* ratio_dev) {
+  if (!ctx || !std_dev || !mean_dev || !ratio_dev || n < 1 || !(eps >= 0))
+    return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_ratio(std_dev, mean_dev, n, eps, ratio_dev, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_laplacian_filter(rtm_ctx* ctx, const float* img_dev, int32_t nz, int32_t nx, float dz, float dx,
+                                    float* out_dev) {
+  if (!ctx || !img_dev || !out_dev || nz < 1 || nx < 1 || !(dz > 0) || !(dx > 0))
+    return fail(RTM_E_INVAL, "bad arguments");
+  if (img_dev == out_dev) return fail(RTM_E_INVAL, "the filter cannot run in place");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_lapfilter(img_dev, nz, nx, dz, dx, out_dev, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
+  if (!ctx || !out) return fail(RTM_E_INVAL, "bad arguments");
+  memset(out, 0, sizeof *out);
+  out->jobs_submitted = ctx->jobs_submitted;
+  out->jobs_done = ctx->jobs_done;
+  out->jobs_failed = ctx->jobs_failed;
+  out->jobs_cancelled = ctx->jobs_cancelled;
+  out->steps_launched = ctx->steps_launched;
+  out->graph_replays = ctx->graph_replays;
+  out->grid_updates = ctx->grid_updates;
+  out->alg_bytes = ctx->alg_bytes;
+  out->arena_bytes = ctx->arena.size();
+  out->arena_used = ctx->arena.used();
+  out->arena_peak = ctx->arena.peak();
+  out->tile_z = choose_tz(ctx);
+  if (ctx->ph_valid) {
+    float a = 0, b = 0;
+    if (hipEventSynchronize(ctx->ph_ev[2]) == hipSuccess &&
+        hipEventElapsedTime(&a, ctx->ph_ev[0], ctx->ph_ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&b, ctx->ph_ev[1], ctx->ph_ev[2]) == hipSuccess) {
+      out->last_fwd_ms = a;
+      out->last_bwd_ms = b;
+      out->last_fwd_launches = ctx->ph_launches[0];
+      out->last_bwd_launches = ctx->ph_launches[1];
+      out->last_fwd_launch_bytes = ctx->ph_bytes[0];
+      out->last_bwd_launch_bytes = ctx->ph_bytes[1];
+    }
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  out->active_jobs = ctx->active_jobs;
+  out->queued_jobs = ctx->queued_jobs;
+  return RTM_OK;
+}
