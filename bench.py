@@ -93,8 +93,11 @@ def main():
     ap.add_argument("--shots", type=int, default=100)
     ap.add_argument("--nt", type=int, default=4000)
     ap.add_argument("--plain-shots", type=int, default=2)
-    ap.add_argument("--cpu-nt", type=int, default=800)
+    ap.add_argument("--cpu-nt", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device tensor copy (reference dispatch "
+                         "for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,6 +113,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src_t = torch.ones(1 << 28, device=dev)
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
     sv = inputs.faulted_survey(n_shots=args.shots, nt=args.nt)
     nz, nx, nt, nb, h, dt = sv.nz, sv.nx, sv.nt, sv.nb, sv.h, sv.dt
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
@@ -119,7 +129,7 @@ def main():
     # arena: working set of every shot of the batch plus slack
     field = ((nz + 2 * nb + 63) // 64 * 64 + 10) * ((nx + 2 * nb + 4 + 63) // 64 * 64) * 4
     ring = nt * 8 * (nz + nx - 8) * 4
-    per_shot = 5 * field + ring + nz * nx * 4 + nt * 4 + nx * 8 + 8192
+    per_shot = 5 * field + ring + nz * nx * 4 + nt * 256 + nx * 8 + 8192
     arena = int(len(sv.shots) * per_shot * 1.02) + (256 << 20)
     log(f"[bench] survey {sv.name}: {len(sv.shots)} shots, nt={nt}, arena {arena / 2**30:.1f} GiB")
     ctx = rtm.Context(0, arena_bytes=arena)

@@ -25,6 +25,7 @@ constexpr int kLdsW = kTileX + 2 * kHalo;  // 72 floats per LDS row
 constexpr int kTopRows = 5;      // zero rows before padded row 0
 constexpr int kRowAlign = 64;    // rows rounded up to the tallest tile
 constexpr int kThreads = 256;    // 4 wavefronts per workgroup
+constexpr int kMaxSlots = 64;    // partial max-abs slots per stored step (spreads the atomics)
 
 enum JobMode : int32_t { kModeModel = 0, kModeStore = 1, kModeRecon = 2 };
 enum PhaseSet : int { kPhFwd = 1, kPhBwd = 2, kPhAny = 3 };
@@ -49,7 +50,7 @@ struct alignas(16) DevJob {
   float* traces;                   // [nt][nrec] sampled at receivers (modelling)
   void* snap;                      // [nsnap][nz][nx] stored S^n (store mode)
   float* ring;                     // [nt][ring_len] boundary ring of S^n (reconstruct)
-  uint32_t* maxbits;               // [nt] max |u^n| over the physical window (float bits)
+  uint32_t* maxbits;               // [nt][kMaxSlots] partial max |u^n| over the physical window (float bits)
   float* image;                    // [nz][nx]
   float* illum;                    // [nz][nx] or null
   const int2* recs;                // receivers sorted by tile: {local index, receiver id}

@@ -23,13 +23,18 @@
 
 namespace rtm {
 
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // 16-bit snapshot codec: q = RNE(x * s), x = q / s with s = 2^(15 - e) where
 // max|S^n| = f 2^e, f in [1/2, 1).  The scale is a power of two, so encoding
 // and decoding add no rounding beyond the 16-bit cast itself.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float snap_scale_from_bits(uint32_t maxbits) {
-  float m = __uint_as_float(maxbits);
+__device__ __forceinline__ float snap_scale_from_max(float m) {
   if (!(m > 0.0f)) return 1.0f;
   int e = ilogbf(m) + 1;  // m = f 2^e, f in [1/2, 1)
   return ldexpf(1.0f, 15 - e);
@@ -116,12 +121,6 @@ __device__ __forceinline__ int ring_slot(int pz, int px, int nz, int nx) {
   return -1;
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 // Workgroup max of v (>= 0 or NaN) to one global atomic (float bits, unsigned
 // compare is monotone for non-negative floats; NaN bits sort above +inf).
 __device__ __forceinline__ void wg_atomic_max(float v, uint32_t* dst, float* red) {
@@ -182,7 +181,10 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
   const bool snap_now = mode == kModeStore && (n % J.snap_stride) == 0;
   const bool want_max = mode == kModeStore && J.snap_dtype != 0 && ((n + 1) % J.snap_stride) == 0 &&
                         (n + 1) <= J.nt - 2;
-  const float sc = (snap_now && J.snap_dtype != 0) ? snap_scale_from_bits(J.maxbits[n]) : 1.0f;
+  // per-snapshot scale from the max-abs of u^n, kept as kMaxSlots partial maxima
+  float sc = 1.0f;
+  if (snap_now && J.snap_dtype != 0)
+    sc = snap_scale_from_max(wave_max(__uint_as_float(J.maxbits[(int64_t)n * kMaxSlots + lane])));
   const int px = x - J.nb;
   const bool colphys = px >= 0 && px < J.nx;
 
@@ -226,7 +228,10 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
       }
     }
   }
-  if (want_max) wg_atomic_max(vmax, &J.maxbits[n + 1], sm.red);
+  if (want_max) {
+    const int tile_id = (tl.z0 / TZ) * J.tiles_x + tl.x0 / kTileX;
+    wg_atomic_max(vmax, &J.maxbits[(int64_t)(n + 1) * kMaxSlots + (tile_id & (kMaxSlots - 1))], sm.red);
+  }
   if (mode == kModeModel && tl.rec_count > 0) {
     __syncthreads();
     for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
@@ -323,8 +328,8 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
   const float kfac = J.kfac;
   const float wsrc = (recon ? J.wavelet[m + 1] : 0.0f) * J.inv_cell;
   float dsc = 1.0f;
-  if (imaging && mode == kModeStore && J.snap_dtype != 0)
-    dsc = 1.0f / snap_scale_from_bits(J.maxbits[m]);  // exact: power of two
+  if (imaging && mode == kModeStore && J.snap_dtype != 0)  // exact: power of two
+    dsc = 1.0f / snap_scale_from_max(wave_max(__uint_as_float(J.maxbits[(int64_t)m * kMaxSlots + lane])));
 
   float zr[RZ + 8];
 #pragma unroll

@@ -185,7 +185,7 @@ static Footprint footprint(const JobGeom& g) {
   if (g.mode == kModeRecon) t += align256((size_t)g.nt * ring_len_of(g.nz, g.width) * 4);
   if (g.mode == kModeStore)
     t += align256((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * g.width * snap_bytes(g.snap_dtype));
-  t += align256((size_t)g.nt * 4);               // maxbits
+  t += align256((size_t)g.nt * kMaxSlots * 4);   // maxbits
   t += align256((size_t)std::max(g.nrec, 1) * 8);  // receivers
   t += 256;                                      // health
   f.total = t;
@@ -403,8 +403,8 @@ static int device_vmax(rtm_ctx* ctx, hipStream_t s, const float* vel, int nz, in
 static int choose_tz(rtm_ctx* ctx) {
   if (ctx->tile_z) return ctx->tile_z;
   const char* e = getenv("RTM_TILE_Z");
-  int tz = e ? atoi(e) : 32;
-  if (tz != 16 && tz != 32 && tz != 64) tz = 32;
+  int tz = e ? atoi(e) : 16;
+  if (tz != 16 && tz != 32 && tz != 64) tz = 16;
   return tz;
 }
 
@@ -474,7 +474,7 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   if (g.mode == kModeRecon) ring = static_cast<float*>(A((size_t)g.nt * d.ring_len * 4));
   if (g.mode == kModeStore)
     snap = A((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * g.width * snap_bytes(g.snap_dtype));
-  uint32_t* maxbits = static_cast<uint32_t*>(A((size_t)g.nt * 4));
+  uint32_t* maxbits = static_cast<uint32_t*>(A((size_t)g.nt * kMaxSlots * 4));
   int2* recd = static_cast<int2*>(A((size_t)std::max(g.nrec, 1) * 8));
   uint32_t* health = static_cast<uint32_t*>(A(256));
   float* image = nullptr;
@@ -549,7 +549,7 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   if (image) HIP_OK(hipMemsetAsync(image, 0, (size_t)g.nz * g.width * 4, s));
   if (illum) HIP_OK(hipMemsetAsync(illum, 0, (size_t)g.nz * g.width * 4, s));
   if (ring) HIP_OK(hipMemsetAsync(ring, 0, (size_t)d.ring_len * 4, s));  // ring of u^0 = 0
-  HIP_OK(hipMemsetAsync(maxbits, 0, (size_t)g.nt * 4, s));
+  HIP_OK(hipMemsetAsync(maxbits, 0, (size_t)g.nt * kMaxSlots * 4, s));
   HIP_OK(hipMemsetAsync(health, 0, 4, s));
   if (traces) HIP_OK(hipMemsetAsync(traces, 0, (size_t)g.nrec * 4, s));  // d[0] = u^0 = 0
   if (g.nrec) HIP_OK(hipMemcpyAsync(recd, j.recs.data(), (size_t)g.nrec * 8, hipMemcpyHostToDevice, s));
@@ -1263,9 +1263,29 @@ static void sched_main(rtm_ctx* ctx) {
       ctx->queued_jobs = (int)ctx->queue.size();
     }
     if (active.empty()) {
-      // nothing fits right now: wait for deferred frees, then retry
-      reap(ctx, true);
-      std::this_thread::sleep_for(std::chrono::milliseconds(1));
+      bool pending;
+      {
+        std::lock_guard<std::mutex> lk(ctx->defer_mu);
+        pending = !ctx->deferred.empty();
+      }
+      if (pending) {  // memory is on its way back: wait for it, then retry
+        reap(ctx, true);
+        continue;
+      }
+      // Nothing runs and nothing is being freed, yet the head job does not
+      // fit (the arena is held by results not yet released): fail it rather
+      // than wait forever.
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      if (!ctx->queue.empty()) {
+        EnsJob* ej = ctx->jobs[ctx->queue.front()].get();
+        ej->state = RTM_JOB_FAILED;
+        ej->status = RTM_E_NOMEM;
+        ej->t_done = now_s();
+        ctx->models[ej->spec.realization].active--;
+        ctx->jobs_failed++;
+        ctx->queue.pop_front();
+        ctx->queued_jobs = (int)ctx->queue.size();
+      }
       continue;
     }
     // ---- K steps of every active job ----

@@ -1,0 +1,214 @@
+"""The ensemble / serving path (rtm_ensemble_*) and the statistics calls on
+the GPU: results of a job are the same alone and in a mix of other jobs,
+admission waits for memory instead of failing, running FP64 statistics
+match a two-pass computation, and the Stage-3 maps and the post-stack
+filter match the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_06444_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NZ, NX, NB, H, DT = 48, 260, 10, 10.0, 1e-3
+
+
+@pytest.fixture(scope="module")
+def rtm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_06444_amd import rtm as _rtm
+
+    return _rtm
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _models(n):
+    base = inputs.two_layer(NZ, NX, H, z_interface=250.0)
+    return [inputs.realization(r, base, H, smooth_sigma_m=30.0) for r in range(n)]
+
+
+def _jobs(n, seed=0):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for j in range(n):
+        w = int(rng.integers(40, 200))
+        ix = int(rng.integers(0, NX))
+        ix0 = inputs.window_for(ix, w, NX)
+        nt = int(rng.integers(60, 160))
+        mode = ["reconstruct", "store"][j % 2]
+        dtype = ["fp32", "bf16", "fp16"][j % 3] if mode == "store" else "fp32"
+        d = rng.standard_normal((nt, w)) * 1e-3
+        jobs.append(dict(r=j % 3, src=(1, ix), ix0=ix0, w=w, nt=nt, mode=mode, dtype=dtype,
+                         stride=1 + j % 3, data=d))
+    return jobs
+
+
+def _opts(rtm, j):
+    return rtm.img_opts(j["mode"], j["dtype"], j["stride"] if j["mode"] == "store" else 1)
+
+
+def _alone(rtm, ctx, vel, j):
+    g = rtm.make_grid(NZ, NX, NB, j["nt"], H, H, DT)
+    img = torch.zeros(NZ, NX, device="cuda")
+    rec = [(1, x) for x in range(j["ix0"], j["ix0"] + j["w"])]
+    ctx.migrate_shot(g, dev(vel), dev(inputs.ricker(j["nt"], DT, 25.0)), j["src"], rec,
+                     dev(j["data"]), j["ix0"], j["w"], _opts(rtm, j), img)
+    return host(img)[:, j["ix0"]:j["ix0"] + j["w"]]
+
+
+def _submit_all(rtm, ctx, jobs, flags):
+    keep, tickets = [], []
+    for j in jobs:
+        w = dev(inputs.ricker(j["nt"], DT, 25.0))
+        d = dev(j["data"])
+        keep += [w, d]
+        tickets.append(ctx.submit(j["r"], j["src"], j["ix0"], j["w"], 1, j["nt"], w, d,
+                                  _opts(rtm, j), flags=flags, tag=len(tickets)))
+    return tickets, keep
+
+
+def test_ensemble_mix_equals_alone_and_statistics(rtm):
+    vels = _models(3)
+    jobs = _jobs(9)
+    with rtm.Context(0, arena_bytes=2 << 30) as ctx:
+        g = rtm.make_grid(NZ, NX, NB, 100, H, H, DT)
+        for r, v in enumerate(vels):
+            ctx.model_register(r, dev(v), g)
+        tickets, keep = _submit_all(rtm, ctx, jobs, rtm.JOB_ACC_STATS | rtm.JOB_ACC_STACK)
+        ctx.drain()
+        images = []
+        for t, j in zip(tickets, jobs):
+            info = ctx.poll(t)
+            assert info.state == rtm.JOB_DONE and info.status == 0, (info.state, info.status)
+            assert info.t_submit <= info.t_admit <= info.t_done
+            assert info.grid_updates > 0 and info.alg_bytes > 0
+            img = torch.empty(NZ, j["w"], device="cuda")
+            ctx.poll(t, img, release=True)
+            images.append(host(img))
+        st = ctx.stats()
+        assert st.jobs_done == len(jobs) and st.active_jobs == 0 and st.queued_jobs == 0
+        # alone == in the mix, bit for bit (same kernel arithmetic per tile)
+        for j, img in zip(jobs, images):
+            alone = _alone(rtm, ctx, vels[j["r"]], j)
+            assert np.array_equal(alone, img), (j["mode"], j["dtype"], np.abs(alone - img).max())
+        # one job against the oracle
+        j = jobs[0]
+        rec = [(1, x) for x in range(j["ix0"], j["ix0"] + j["w"])]
+        ref = oracle.migrate_window(vels[j["r"]], j["ix0"], j["w"], inputs.ricker(j["nt"], DT, 25.0),
+                                    j["src"], rec, j["data"], dz=H, dx=H, dt=DT, nb=NB)
+        assert oracle.rel_l2(images[0], ref) <= 1e-4
+        # per-realization FP64 running statistics and FP32 stacks
+        for r in range(3):
+            mine = [(im, (j["ix0"], j["w"])) for im, j in zip(images, jobs) if j["r"] == r]
+            mean_ref, std_ref, cnt_ref = oracle.windowed_stats([m[0] for m in mine],
+                                                               [m[1] for m in mine], NZ, NX)
+            mean = torch.empty(NZ, NX, dtype=torch.float64, device="cuda")
+            std = torch.empty_like(mean)
+            cnt = torch.empty(NZ, NX, dtype=torch.int32, device="cuda")
+            ctx.ensemble_stats(r, mean, std, cnt)
+            assert np.array_equal(host(cnt), cnt_ref)
+            scale = np.abs(mean_ref).max()
+            assert np.abs(host(mean) - mean_ref).max() <= 1e-12 * scale
+            assert np.abs(host(std) - std_ref).max() <= 1e-12 * max(np.abs(std_ref).max(), 1e-30)
+            stack = torch.empty(NZ, NX, device="cuda")
+            ctx.ensemble_stack(r, stack)
+            sref = oracle.stack([m[0] for m in mine], [m[1] for m in mine], NX)
+            assert np.abs(host(stack) - sref).max() <= 1e-6 * np.abs(sref).max()
+
+
+def test_admission_waits_for_memory(rtm):
+    """An arena that holds only a couple of jobs at a time still completes
+    every job: memory pressure delays admission, it does not fail jobs."""
+    vels = _models(1)
+    jobs = _jobs(6, seed=1)
+    for j in jobs:
+        j["r"] = 0
+    with rtm.Context(0, arena_bytes=24 << 20) as ctx:
+        g = rtm.make_grid(NZ, NX, NB, 100, H, H, DT)
+        ctx.model_register(0, dev(vels[0]), g)
+        tickets, keep = _submit_all(rtm, ctx, jobs, 0)
+        ctx.drain()
+        for t in tickets:
+            assert ctx.poll(t, release=True).state == rtm.JOB_DONE
+        st = ctx.stats()
+        assert st.arena_peak <= st.arena_bytes
+
+
+def test_submit_errors_and_cancel(rtm):
+    vels = _models(1)
+    with rtm.Context(0, arena_bytes=64 << 20) as ctx:
+        g = rtm.make_grid(NZ, NX, NB, 100, H, H, DT)
+        ctx.model_register(0, dev(vels[0]), g)
+        w = dev(inputs.ricker(100, DT))
+        d = dev(np.zeros((100, 50)))
+        o = rtm.img_opts()
+        with pytest.raises(rtm.RTMError) as e:  # not registered
+            ctx.submit(7, (1, 10), 0, 50, 1, 100, w, d, o)
+        assert e.value.code == -5
+        with pytest.raises(rtm.RTMError) as e:  # window outside the model
+            ctx.submit(0, (1, 10), NX - 20, 50, 1, 100, w, d, o)
+        assert e.value.code == -1
+        with pytest.raises(rtm.RTMError) as e:  # larger than the whole arena
+            big = rtm.img_opts("store", "fp32", 1)
+            ctx.submit(0, (1, 100), 0, NX, 1, 5000, dev(inputs.ricker(5000, DT)),
+                       dev(np.zeros((5000, NX))), big)
+        assert e.value.code == -3
+        # CFL: a too-fast model
+        ctx.model_register(1, dev(np.full((NZ, NX), 9000.0)), g)
+        with pytest.raises(rtm.RTMError) as e:
+            ctx.submit(1, (1, 10), 0, 50, 1, 100, w, d, o)
+        assert e.value.code == -2
+        # cancel: either it was still queued (CANCELLED) or already admitted (finishes DONE)
+        ts = [ctx.submit(0, (1, 10 + k), 0, 50, 1, 100, w, d, o) for k in range(4)]
+        try:
+            ctx.cancel(ts[-1])
+            cancelled = True
+        except rtm.RTMError as err:
+            assert err.code == -1
+            cancelled = False
+        ctx.drain()
+        last = ctx.poll(ts[-1])
+        assert last.state == (rtm.JOB_CANCELLED if cancelled else rtm.JOB_DONE)
+        for t in ts[:-1]:
+            assert ctx.poll(t).state == rtm.JOB_DONE
+
+
+def test_explicit_stats_maps_and_filter(rtm):
+    rng = np.random.default_rng(3)
+    nz, nx = 37, 91
+    imgs = [rng.standard_normal((nz, nx)).astype(np.float32) + 0.5 for _ in range(7)]
+    with rtm.Context(0, arena_bytes=64 << 20) as ctx:
+        st = ctx.stats_create(nz, nx)
+        for im in imgs:
+            ctx.stats_add(st, dev(im))
+        mean = torch.empty(nz, nx, dtype=torch.float64, device="cuda")
+        std = torch.empty_like(mean)
+        cnt = torch.empty(nz, nx, dtype=torch.int32, device="cuda")
+        ctx.stats_get(st, mean, std, cnt)
+        m_ref, s_ref = oracle.ensemble_stats(np.stack(imgs).astype(np.float64))
+        assert np.abs(host(mean) - m_ref).max() <= 1e-12 * np.abs(m_ref).max()
+        assert np.abs(host(std) - s_ref).max() <= 1e-12 * np.abs(s_ref).max()
+        assert (host(cnt) == 7).all()
+        conf = torch.empty_like(mean)
+        ctx.confidence_map(std, cnt, conf, min_count=2)
+        assert np.abs(host(conf) - oracle.confidence_index(s_ref, np.full((nz, nx), 7))).max() <= 1e-12
+        ratio = torch.empty_like(mean)
+        ctx.ratio_map(std, mean, ratio, eps=1e-3)
+        r_ref = oracle.ratio_map(s_ref, m_ref, eps=1e-3)
+        assert np.abs(host(ratio) - r_ref).max() <= 1e-9 * np.abs(r_ref).max()
+        ctx.stats_destroy(st)
+        out = torch.empty(nz, nx, device="cuda")
+        ctx.laplacian_filter(dev(imgs[0]), 10.0, 12.5, out)
+        ref = oracle.laplacian_filter(imgs[0].astype(np.float64), 10.0, 12.5)
+        assert oracle.rel_l2(host(out), ref) <= 1e-6
