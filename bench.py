@@ -85,42 +85,88 @@ def cpu_baseline(sv, nt_sample: int):
     }
 
 
-def main():
+def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["survey", "ensemble", "serve"], default="survey")
     ap.add_argument("--shots", type=int, default=100)
-    ap.add_argument("--nt", type=int, default=4000)
+    ap.add_argument("--nt", type=int, default=None, help="default: 4000 survey, 3000 ensemble")
     ap.add_argument("--plain-shots", type=int, default=2)
     ap.add_argument("--cpu-nt", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device tensor copy (reference dispatch "
                          "for the HBM byte counters)")
-    args = ap.parse_args()
+    ap.add_argument("--realizations", type=int, default=64, help="ensemble workload")
+    ap.add_argument("--serve-jobs", type=int, default=300, help="serve workload: timed jobs")
+    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--rate", type=float, default=20.0, help="serve workload: jobs/s")
+    return ap.parse_args()
 
+
+def main():
+    args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every shot of the "
               "survey is independent, so N GPUs would each migrate a disjoint share of the shots.",
               file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
     import torch
 
-    from paper_2001_06444_amd import inputs, rtm
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
     if args.calibrate_copy:
+        dev = torch.device("cuda:0")
         src_t = torch.ones(1 << 28, device=dev)
         dst_t = torch.empty_like(src_t)
         dst_t.copy_(src_t)
         torch.cuda.synchronize()
         del src_t, dst_t
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
-    sv = inputs.faulted_survey(n_shots=args.shots, nt=args.nt)
+    out = {"survey": run_survey, "ensemble": run_ensemble, "serve": run_serve}[args.workload](args)
+    print(json.dumps(out), flush=True)
+
+
+def _base_record(args, value, ms_per_step, config, unit="grid-pt updates/s"):
+    return {
+        "metric": "RTM grid-pt updates/s + images/s (batched/served vs plain), p99 latency, %HBM roofline",
+        "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config,
+    }
+
+
+def _plain_rate(ctx, grid_for, jobs):
+    """Same jobs through rtm_migrate_shot, one after the other (one launch per step)."""
+    import torch
+
+    if not jobs:
+        return None
+    first = jobs[0]
+    img = torch.zeros(*first["image_shape"], device="cuda:0")
+    ctx.migrate_shot(grid_for(first), first["vel"], first["wav"], first["src"], first["rec"],
+                     first["data"], first["ix0"], first["width"], first["opts"], img)
+    torch.cuda.synchronize()
+    u0 = ctx.stats().grid_updates
+    t0 = time.perf_counter()
+    for j in jobs:
+        ctx.migrate_shot(grid_for(j), j["vel"], j["wav"], j["src"], j["rec"], j["data"], j["ix0"],
+                         j["width"], j["opts"], img)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"updates_per_s": (ctx.stats().grid_updates - u0) / el, "images_per_s": len(jobs) / el,
+            "shots": len(jobs), "ms_per_image": el * 1e3 / len(jobs)}
+
+
+def run_survey(args):
+    import numpy as np
+    import torch
+
+    from paper_2001_06444_amd import inputs, rtm
+
+    dev = torch.device("cuda:0")
+    sv = inputs.faulted_survey(n_shots=args.shots, nt=args.nt or 4000)
     nz, nx, nt, nb, h, dt = sv.nz, sv.nx, sv.nt, sv.nb, sv.h, sv.dt
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
     vel_true, vel_mig, wav = t(sv.vel_true), t(sv.vel_mig), t(sv.wavelet)
@@ -209,37 +255,246 @@ def main():
         log(f"[bench] oracle: {base['value']:.3e} updates/s on {base['cores']} threads")
 
     ctx.close()
-    out = {
-        "metric": "RTM grid-pt updates/s + images/s (batched/served vs plain), p99 latency, %HBM roofline",
-        "value": value,
-        "unit": "grid-pt updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"faulted-layer survey {nz}x{nx} at 10 m, {len(shots)} shots, "
-                               f"nt={nt}, nb={nb}, reconstruct mode, stacked",
-                   "nz": nz, "nx": nx, "nb": nb, "nt": nt, "shots": len(shots),
-                   "src_mode": "reconstruct", "path": "batched (hipGraph, all shots per launch)"},
+    out = _base_record(args, value, ms_per_step, {
+        "workload": f"faulted-layer survey {nz}x{nx} at 10 m, {len(shots)} shots, nt={nt}, "
+                    f"nb={nb}, reconstruct mode, stacked",
+        "nz": nz, "nx": nx, "nb": nb, "nt": nt, "shots": len(shots), "src_mode": "reconstruct",
+        "path": "batched (hipGraph, all shots per launch)", "tile_z": s1.tile_z})
+    out.update({
         "images_per_s": images_per_s,
         "plain": plain,
         "batched_vs_plain": (images_per_s / plain["images_per_s"]) if plain else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(s1.last_bwd_launch_bytes),
-                     "kernel": "k_step<TZ,backward> (receiver step + reconstruct + imaging)",
+                     "kernel": "k_step<TZ,2> backward (receiver step + reconstruct + imaging)",
                      "alg_bytes_per_launch": s1.last_bwd_launch_bytes,
                      "launch_us": bwd_launch_ms * 1e3,
                      "forward_launch": {"achieved": achieved_fwd, "launch_us": fwd_launch_ms * 1e3,
                                         "alg_bytes_per_launch": s1.last_fwd_launch_bytes}},
         "cpu_baseline": base,
-    }
-    print(json.dumps(out), flush=True)
+    })
+    return out
+
+
+
+def _ensemble_setup(nz=351, nx=1701, h=10.0):
+    from paper_2001_06444_amd import inputs
+
+    base = inputs.ensemble_base(nz, nx, h)
+    smooth = inputs.smooth_slowness(base, 40.0, h, h)
+    return base, smooth
+
+
+def _model_window_data(ctx, grid, vel_true, vel_mig, wav, src, ix0, width, nt):
+    """Observed data of one shot on its window columns: true minus smooth model."""
+    import torch
+
+    from paper_2001_06444_amd import rtm
+
+    g = rtm.make_grid(grid.nz, grid.nx, grid.nb, nt, grid.dz, grid.dx, grid.dt)
+    rec = [(1, x) for x in range(ix0, ix0 + width)]
+    a = torch.empty(nt, width, device="cuda:0")
+    b = torch.empty(nt, width, device="cuda:0")
+    ctx.propagate(g, vel_true, wav, src, rec, a)
+    ctx.propagate(g, vel_mig, wav, src, rec, b)
+    a.sub_(b)
+    return a
+
+
+def _job_bytes(nz, width, nb, nt, mode="reconstruct", dtype="fp32", stride=1):
+    field = ((nz + 2 * nb + 63) // 64 * 64 + 10) * ((width + 2 * nb + 4 + 63) // 64 * 64) * 4
+    b = 5 * field + nz * width * 4 + nt * 256 + width * 8 + 16384
+    if mode == "reconstruct":
+        b += nt * 8 * (nz + width - 8) * 4
+    else:
+        b += ((nt - 2) // stride + 1) * nz * width * (4 if dtype == "fp32" else 2)
+    return b
+
+
+def run_ensemble(args):
+    """64 velocity samples x 16 shots with uneven apertures, all submitted at
+    once to the serving engine (continuous batching, graph replays, tuned
+    tiles); per-realization stacks, then FP64 mean/std over the stacks and
+    the Stage-3 maps."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06444_amd import inputs, rtm
+
+    dev = torch.device("cuda:0")
+    nz, nx, h, dt, nb = 351, 1701, 10.0, 1e-3, 50
+    nt = args.nt or 3000
+    R = args.realizations
+    base, smooth = _ensemble_setup(nz, nx, h)
+    shots = inputs.ensemble_shots(16, nx)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    wav = t(inputs.ricker(nt, dt))
+    grid = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    need = sum(_job_bytes(nz, sh.width, nb, nt) for sh in shots) * R
+    free = torch.cuda.mem_get_info()[0]
+    arena = int(min(need * 1.05 + (2 << 30), free - (24 << 30)))
+    log(f"[bench] ensemble: {R} realizations x {len(shots)} shots, nt={nt}; jobs need "
+        f"{need / 2**30:.1f} GiB, arena {arena / 2**30:.1f} GiB")
+    ctx = rtm.Context(0, arena_bytes=arena)
+    vt, vs = t(base), t(smooth)
+    data = [_model_window_data(ctx, grid, vt, vs, wav, sh.src, sh.ix0, sh.width, nt) for sh in shots]
+    for r in range(R):
+        ctx.model_register(r, t(smooth * (1.0 + 0.05 * inputs.grf(r, nz, nx, h))), grid)
+    ctx.model_register(R, vs, grid)  # warm-up model
+    torch.cuda.synchronize()
+    log("[bench] data modelled, velocity bank registered")
+    opts = rtm.img_opts("reconstruct")
+    # warm-up (tile tuning, graph capture) on a model outside the ensemble
+    for sh, d in zip(shots[:2], data[:2]):
+        ctx.submit(R, sh.src, sh.ix0, sh.width, 1, nt, wav, d, opts)
+    ctx.drain()
+    s0 = ctx.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for r in range(R):
+        for sh, d in zip(shots, data):
+            tickets.append(ctx.submit(r, sh.src, sh.ix0, sh.width, 1, nt, wav, d, opts,
+                                      flags=rtm.JOB_ACC_STACK))
+    ctx.drain()
+    t_rtm = time.perf_counter() - t0
+    st = ctx.stats_create(nz, nx)
+    buf = torch.empty(nz, nx, device=dev)
+    for r in range(R):
+        ctx.ensemble_stack(r, buf)
+        ctx.stats_add(st, buf)
+    mean = torch.empty(nz, nx, dtype=torch.float64, device=dev)
+    std = torch.empty_like(mean)
+    cnt = torch.empty(nz, nx, dtype=torch.int32, device=dev)
+    ctx.stats_get(st, mean, std, cnt)
+    conf = torch.empty_like(mean)
+    ctx.confidence_map(std, cnt, conf)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s1 = ctx.stats()
+    n_img = R * len(shots)
+    failed = sum(1 for tk in tickets if ctx.poll(tk, release=True).state != rtm.JOB_DONE)
+    updates = s1.grid_updates - s0.grid_updates
+    log(f"[bench] ensemble: {n_img} RTMs in {el:.2f} s ({n_img / el:.1f} images/s, "
+        f"{updates / el:.3e} updates/s), {failed} failed, tile_z {s1.tile_z}")
+    plain_jobs = [dict(vel=t(smooth), wav=wav, src=sh.src, rec=[(1, x) for x in range(sh.ix0, sh.ix0 + sh.width)],
+                       data=d, ix0=sh.ix0, width=sh.width, opts=opts, image_shape=(nz, nx))
+                  for sh, d in list(zip(shots, data))[: args.plain_shots]]
+    plain = _plain_rate(ctx, lambda j: grid, plain_jobs)
+    ctx.close()
+    out = _base_record(args, updates / el, el * 1e3, {
+        "workload": f"velocity ensemble: {R} realizations x {len(shots)} shots on {nz}x{nx} at 10 m, "
+                    f"apertures 401-1201 columns, nt={nt}, nb={nb}, reconstruct mode, "
+                    f"FP64 mean/std over realization stacks",
+        "realizations": R, "shots": len(shots), "nt": nt, "path": "served engine, all jobs at t=0",
+        "tile_z": s1.tile_z})
+    out.update({"steps": 1, "warmup": 1, "images_per_s": n_img / el,
+                "realization_images_per_s": R / el, "rtm_seconds": t_rtm, "failed_jobs": failed,
+                "plain": plain,
+                "batched_vs_plain": (n_img / el) / plain["images_per_s"] if plain else None,
+                "std_map": {"max": float(std.max()), "mean": float(std.mean())}})
+    return out
+
+
+def run_serve(args):
+    """Poisson stream of RTM jobs (velocity sample, shot, aperture, nt, snapshot
+    dtype) served by continuous batching; latency = completion - arrival,
+    including queueing and the upload of the job's data."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06444_amd import inputs, rtm
+
+    dev = torch.device("cuda:0")
+    nz, nx, h, dt, nb = 351, 1701, 10.0, 1e-3, 50
+    base, smooth = _ensemble_setup(nz, nx, h)
+    n_all = args.serve_warmup + args.serve_jobs
+    stream = inputs.poisson_stream(n_all, rate=args.rate, seed=5, n_real=256, nx=nx)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    ntmax = max(j.nt for j in stream)
+    wav = t(inputs.ricker(ntmax, dt))
+    grid = rtm.make_grid(nz, nx, nb, ntmax, h, h, dt)
+    free = torch.cuda.mem_get_info()[0]
+    arena = int(min(96 << 30, free - (32 << 30)))
+    ctx = rtm.Context(0, arena_bytes=arena)
+    vt, vs = t(base), t(smooth)
+    used = sorted({j.realization for j in stream})
+    for r in used:
+        ctx.model_register(r, t(smooth * (1.0 + 0.05 * inputs.grf(r, nz, nx, h))), grid)
+    log(f"[bench] serve: {n_all} jobs at {args.rate} jobs/s, {len(used)} realizations, "
+        f"arena {arena / 2**30:.1f} GiB")
+    host = []
+    for j in stream:
+        d = _model_window_data(ctx, grid, vt, vs, wav, j.src, j.ix0, j.width, j.nt)
+        hd = torch.empty(d.shape, dtype=torch.float32, pin_memory=True)
+        hd.copy_(d)
+        host.append(hd)
+        del d
+    torch.cuda.synchronize()
+    log("[bench] job data modelled and staged in pinned host memory")
+
+    def opts_of(j):
+        return rtm.img_opts("store", j.dtype, 4)
+
+    def serve(arrivals):
+        pending, done = {}, {}
+        t0 = time.monotonic()
+        for i, j in enumerate(stream):
+            while True:
+                now = time.monotonic()
+                for tk in [tk for tk in list(pending)]:
+                    info = ctx.poll(tk)
+                    if info.state >= rtm.JOB_DONE:
+                        done[pending[tk][0]] = (info.state, info.t_done)
+                        ctx.poll(tk, release=True)
+                        del pending[tk]
+                if now >= t0 + arrivals[i]:
+                    break
+                time.sleep(min(0.002, t0 + arrivals[i] - now))
+            d = host[i].to(dev)
+            tk = ctx.submit(j.realization, j.src, j.ix0, j.width, 1, j.nt, wav, d, opts_of(j),
+                            flags=rtm.JOB_ACC_STATS, tag=i)
+            pending[tk] = (i, d)
+        ctx.drain()
+        for tk, (i, d) in pending.items():
+            info = ctx.poll(tk, release=True)
+            done[i] = (info.state, info.t_done)
+        lat = np.array([done[i][1] - (t0 + arrivals[i]) for i in range(len(stream))])
+        ok = np.array([done[i][0] == rtm.JOB_DONE for i in range(len(stream))])
+        t_end = max(done[i][1] for i in range(len(stream))) - t0
+        return lat, ok, t_end
+
+    arrivals = [j.arrival for j in stream]
+    s0 = ctx.stats()
+    lat, ok, t_end = serve(arrivals)
+    s1 = ctx.stats()
+    timed = slice(args.serve_warmup, n_all)
+    lt = lat[timed]
+    span = t_end - arrivals[args.serve_warmup]
+    served_ips = args.serve_jobs / span
+    p50, p99 = float(np.percentile(lt, 50)), float(np.percentile(lt, 99))
+    log(f"[bench] serve @ {args.rate}/s: p50 {p50 * 1e3:.0f} ms, p99 {p99 * 1e3:.0f} ms, "
+        f"{served_ips:.1f} images/s, {int((~ok).sum())} failed")
+    # saturation: every job arrives at t = 0
+    u0 = ctx.stats().grid_updates
+    lat0, ok0, t_end0 = serve([0.0] * n_all)
+    sat_updates = ctx.stats().grid_updates - u0
+    sat_ips = n_all / t_end0
+    log(f"[bench] saturation: {n_all} jobs in {t_end0:.2f} s, {sat_ips:.1f} images/s, "
+        f"{sat_updates / t_end0:.3e} updates/s")
+    ctx.close()
+    out = _base_record(args, sat_updates / t_end0, t_end0 * 1e3, {
+        "workload": f"served stream: Poisson {args.rate} jobs/s, {args.serve_jobs} timed jobs "
+                    f"(+{args.serve_warmup} warm-up), 256 velocity samples, apertures 301-1701, "
+                    f"nt 2000-4000, store mode stride 4 fp32/bf16, FP64 per-realization mean/std",
+        "rate": args.rate, "jobs": args.serve_jobs, "path": "served engine (continuous batching)"})
+    out.update({"steps": 1, "warmup": 0,
+                "latency_ms": {"p50": p50 * 1e3, "p99": p99 * 1e3, "max": float(lt.max() * 1e3)},
+                "served_images_per_s": served_ips, "saturation_images_per_s": sat_ips,
+                "failed_jobs": int((~ok).sum() + (~ok0).sum()),
+                "value_is": "grid-pt updates/s of the saturation run"})
+    return out
 
 
 if __name__ == "__main__":

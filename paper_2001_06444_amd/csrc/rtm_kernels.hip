@@ -232,7 +232,7 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
     const int tile_id = (tl.z0 / TZ) * J.tiles_x + tl.x0 / kTileX;
     wg_atomic_max(vmax, &J.maxbits[(int64_t)(n + 1) * kMaxSlots + (tile_id & (kMaxSlots - 1))], sm.red);
   }
-  if (mode == kModeModel && tl.rec_count > 0) {
+  if (mode == kModeModel && tl.rec_count > 0 && J.traces != nullptr) {
     __syncthreads();
     for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
       int2 r = J.recs[tl.rec_begin + i];

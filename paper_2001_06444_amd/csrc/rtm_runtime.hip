@@ -271,8 +271,10 @@ struct rtm_ctx {
   void* own_arena = nullptr;
   std::mutex defer_mu;
   std::deque<Deferred> deferred;
-  int tile_z = 0;                      // autotuned tile height
-  int tune_nxp = 0;
+  int tile_z = 0;                      // tile height of the last tuned launch set
+  std::mutex tune_mu;
+  std::map<std::string, int> tune_cache;  // geometry key -> tile height
+  bool tune_file_loaded = false;
   // counters
   std::atomic<uint64_t> steps_launched{0}, graph_replays{0}, grid_updates{0}, alg_bytes{0};
   std::atomic<uint64_t> jobs_submitted{0}, jobs_done{0}, jobs_failed{0}, jobs_cancelled{0};
@@ -400,12 +402,34 @@ static int device_vmax(rtm_ctx* ctx, hipStream_t s, const float* vel, int nz, in
 // ===========================================================================
 // Job construction
 // ===========================================================================
-static int choose_tz(rtm_ctx* ctx) {
-  if (ctx->tile_z) return ctx->tile_z;
+static int env_tz() {
   const char* e = getenv("RTM_TILE_Z");
-  int tz = e ? atoi(e) : 16;
-  if (tz != 16 && tz != 32 && tz != 64) tz = 16;
-  return tz;
+  if (!e) return 0;
+  int tz = atoi(e);
+  return (tz == 16 || tz == 32 || tz == 64) ? tz : 0;
+}
+
+static int choose_tz(rtm_ctx* ctx) {
+  if (int tz = env_tz()) return tz;
+  return ctx->tile_z ? ctx->tile_z : 16;
+}
+
+// Every pointer a job's kernels dereference, for the job's mode, must be set
+// before the job reaches a launch.
+static int check_devjob(const DevJob& d) {
+  const char* miss = nullptr;
+  if (!d.c || !d.gz || !d.gx || !d.f[0] || !d.f[1] || !d.wavelet || !d.maxbits || !d.health) miss = "core arrays";
+  else if (d.nrec > 0 && !d.recs) miss = "receiver table";
+  else if (d.mode == kModeModel && d.nrec > 0 && !d.traces) miss = "traces";
+  else if (d.mode != kModeModel && (!d.r[0] || !d.r[1] || !d.image)) miss = "receiver wavefield or image";
+  else if (d.mode != kModeModel && d.nrec > 0 && !d.data) miss = "receiver data";
+  else if (d.mode == kModeRecon && !d.ring) miss = "ring storage";
+  else if (d.mode == kModeStore && !d.snap) miss = "snapshot storage";
+  else if ((d.flags & RTM_IMG_ILLUM) && d.mode != kModeModel && !d.illum) miss = "illumination";
+  if (miss) return fail(RTM_E_INVAL, "job descriptor is missing its %s", miss);
+  if (d.src_z < 0 || d.src_z >= d.nzp || d.src_x < 0 || d.src_x >= d.nxp)
+    return fail(RTM_E_INVAL, "job source outside its grid");
+  return RTM_OK;
 }
 
 // Allocates the job's working set and enqueues its set-up on stream s.
@@ -508,6 +532,12 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   d.illum = illum;
   d.recs = recd;
   d.health = health;
+  if (int rc = check_devjob(d)) {
+    release_blocks(ctx, j.blocks);
+    if (j.image_blk.p) ctx->arena.release(j.image_blk.p, j.image_blk.n);
+    j.image_blk = {};
+    return rc;
+  }
 
   // ---- tiles and receivers ----
   std::vector<std::pair<int, int2>> keyed;
@@ -582,6 +612,85 @@ static int check_job(const JobGeom& g, rtm_point src, const rtm_point* recs) {
 }
 
 // ===========================================================================
+// Tile-height autotuner
+// ===========================================================================
+// The step kernel is compiled for tile heights 16, 32 and 64 rows.  For a
+// launch set, the tuner builds scratch jobs of the same window, mode and
+// snapshot type (nt = 16, zero data, so nothing real is touched), times a
+// few forward and backward launches of each height with HIP events and keeps
+// the fastest.  Results are cached per geometry key in the context and, if
+// RTM_AUTOTUNE_CACHE names a file, in that JSON file across processes.
+// RTM_TILE_Z forces a height.
+static std::string tune_key(const JobGeom& g, int batch) {
+  int b = batch <= 1 ? 1 : batch <= 4 ? 4 : batch <= 16 ? 16 : 64;
+  char buf[128];
+  snprintf(buf, sizeof buf, "gfx950/nzp%d/nxp%d/mode%d/snap%d/b%d", g.nz + 2 * g.nb, g.width + 2 * g.nb,
+           g.mode, g.mode == kModeStore ? g.snap_dtype : -1, b);
+  return buf;
+}
+
+static void tune_file_load(rtm_ctx* ctx) {
+  ctx->tune_file_loaded = true;
+  const char* path = getenv("RTM_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    char key[400];
+    int tz;
+    if (sscanf(line, " \"%399[^\"]\" : %d", key, &tz) == 2 && (tz == 16 || tz == 32 || tz == 64))
+      ctx->tune_cache[key] = tz;
+  }
+  fclose(f);
+}
+
+static void tune_file_save(rtm_ctx* ctx) {
+  const char* path = getenv("RTM_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto& kv : ctx->tune_cache)
+    fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < ctx->tune_cache.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  (void)rename(tmp.c_str(), path);
+}
+
+static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, const float* vel,
+                     const float* wavelet, rtm_point src, const rtm_point* recs, const float* data,
+                     float* traces, HostJob& j);
+static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, struct Table& t);
+
+static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch, int tz,
+                   float* ms_out);
+
+static int autotune_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch) {
+  if (int tz = env_tz()) return tz;
+  std::lock_guard<std::mutex> lk(ctx->tune_mu);
+  if (!ctx->tune_file_loaded) tune_file_load(ctx);
+  const std::string key = tune_key(g0, batch);
+  auto it = ctx->tune_cache.find(key);
+  if (it != ctx->tune_cache.end()) return ctx->tile_z = it->second;
+  int best = 16;
+  float best_ms = 1e30f;
+  for (int tz : {16, 32, 64}) {
+    float ms = 0;
+    if (time_tz(ctx, s, g0, vel, batch, tz, &ms) != RTM_OK) continue;  // e.g. no room: skip height
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = tz;
+    }
+  }
+  ctx->tune_cache[key] = best;
+  tune_file_save(ctx);
+  return ctx->tile_z = best;
+}
+
+// ===========================================================================
 // Job tables on the device
 // ===========================================================================
 struct Table {
@@ -625,6 +734,75 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   HIP_OK(hipMemcpyAsync(t.ctl, &c, sizeof c, hipMemcpyHostToDevice, s));
   HIP_OK(hipStreamSynchronize(s));  // host-side staging copies are complete
   return RTM_OK;
+}
+
+// One timing trial of the tuner: B scratch jobs (B = min(batch, 8)), nt = 16.
+static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch, int tz,
+                   float* ms_out) {
+  const int B = std::max(1, std::min(batch, 8));
+  JobGeom g = g0;
+  g.nt = 16;
+  g.nrec = g.width;
+  g.flags = 0;
+  const bool model = g.mode == kModeModel;
+  const int nsteps = model ? g.nt - 1 : 2 * g.nt - 1;
+  std::vector<Block> scratch;
+  void *zero = nullptr, *traces = nullptr;
+  if (!alloc_block(ctx, scratch, (size_t)g.nt * g.width * 4 + 256, &zero)) return RTM_E_NOMEM;
+  HIP_OK(hipMemsetAsync(zero, 0, (size_t)g.nt * g.width * 4 + 256, s));
+  if (g.mode == kModeModel) {  // modelling trials sample traces: give them somewhere to go
+    if (!alloc_block(ctx, scratch, (size_t)B * g.nt * g.width * 4, &traces)) {
+      release_blocks(ctx, scratch);
+      return RTM_E_NOMEM;
+    }
+  }
+  std::vector<rtm_point> recs(g.width);
+  for (int r = 0; r < g.width; ++r) recs[r] = {0, g.ix0 + r};
+  rtm_point src{g.nz / 2, g.ix0 + g.width / 2};
+  std::vector<std::unique_ptr<HostJob>> jobs;
+  std::vector<HostJob*> ptrs;
+  int rc = RTM_OK;
+  for (int b = 0; b < B && rc == RTM_OK; ++b) {
+    auto j = std::make_unique<HostJob>();
+    float* tr = traces ? static_cast<float*>(traces) + (size_t)b * g.nt * g.width : nullptr;
+    rc = build_job(ctx, s, g, tz, vel, static_cast<const float*>(zero), src, recs.data(),
+                   static_cast<const float*>(zero), tr, *j);
+    if (rc == RTM_OK) {
+      ptrs.push_back(j.get());
+      jobs.push_back(std::move(j));
+    }
+  }
+  Table t;
+  if (rc == RTM_OK) rc = upload_table(ctx, s, ptrs, t);
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  if (rc == RTM_OK) {
+    for (auto& ev : e) (void)hipEventCreate(&ev);
+    const int nf = g.nt - 1;
+    for (int st = 0; st < nsteps && rc == RTM_OK; ++st) {
+      if (st == 2) (void)hipEventRecord(e[0], s);
+      if (st == nf - 1 && model) (void)hipEventRecord(e[1], s);
+      if (st == nf && !model) (void)hipEventRecord(e[1], s);
+      if (launch_step(tz, st < nf ? kPhFwd : kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 0, st, s) !=
+          hipSuccess)
+        rc = fail(RTM_E_DEVICE, "tuning launch failed");
+    }
+    (void)hipEventRecord(e[2], s);
+    (void)hipStreamSynchronize(s);
+    float a = 0, b = 0;
+    if (rc == RTM_OK && hipEventElapsedTime(&a, e[0], e[1]) == hipSuccess &&
+        hipEventElapsedTime(&b, e[1], e[2]) == hipSuccess)
+      *ms_out = model ? a / (nf - 3) : a / (nf - 2) + b / g.nt;  // one forward (+ one backward) launch
+    for (auto ev : e)
+      if (ev) (void)hipEventDestroy(ev);
+  }
+  (void)hipStreamSynchronize(s);
+  for (auto& j : jobs) {
+    release_blocks(ctx, j->blocks);
+    if (j->image_blk.p) ctx->arena.release(j->image_blk.p, j->image_blk.n);
+  }
+  release_blocks(ctx, t.blocks);
+  release_blocks(ctx, scratch);
+  return rc;
 }
 
 // ===========================================================================
@@ -777,7 +955,7 @@ extern "C" int rtm_propagate(rtm_ctx* ctx, const rtm_grid* grid, const float* ve
   float vmax = 0;
   if ((rc = device_vmax(ctx, s, vel_dev, g.nz, g.model_nx, 0, g.width, &vmax))) return rc;
   if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
-  const int tz = choose_tz(ctx);
+  const int tz = autotune_tz(ctx, s, g, vel_dev, 1);
   HostJob j;
   if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, nullptr, traces_dev, j))) return rc;
   Table t;
@@ -843,7 +1021,7 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
   float vmax = 0;
   if ((rc = device_vmax(ctx, s, vel_dev, g.nz, g.model_nx, ix0, width, &vmax))) return rc;
   if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
-  const int tz = choose_tz(ctx);
+  const int tz = autotune_tz(ctx, s, g, vel_dev, 1);
   HostJob j;
   if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, data_dev, nullptr, j))) return rc;
   Table t;
@@ -933,7 +1111,11 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   float vmax = 0;
   if ((rc = device_vmax(ctx, s, vel_dev, grid->nz, grid->nx, 0, grid->nx, &vmax))) return rc;
   if ((rc = check_cfl(vmax, grid->dt, grid->dz, grid->dx))) return rc;
-  const int tz = choose_tz(ctx);
+  // tile height for the widest window of the batch
+  int widest = 0;
+  for (int i = 1; i < nshots; ++i)
+    if (geoms[i].width > geoms[widest].width) widest = i;
+  const int tz = autotune_tz(ctx, s, geoms[widest], vel_dev, nshots);
   std::vector<std::unique_ptr<HostJob>> jobs;
   std::vector<HostJob*> ptrs;
   auto cleanup = [&]() {
@@ -1206,7 +1388,7 @@ static void sched_main(rtm_ctx* ctx) {
   std::vector<EnsJob*> active;
   bool changed = false;
   int tick = 0;
-  const int tz = choose_tz(ctx);
+  int tz = 0;  // tuned on the first admitted job; every job of the scheduler shares it
   const int K = std::max(1, std::min(graph_k(), 64));
   const int kMaxBypass = 8;
   for (;;) {
@@ -1233,6 +1415,7 @@ static void sched_main(rtm_ctx* ctx) {
         int rc = RTM_OK;
         bool st = ej->spec.flags & RTM_JOB_ACC_STATS, sk = ej->spec.flags & RTM_JOB_ACC_STACK;
         rc = ensure_stats(ctx, s, m, st, sk);
+        if (!rc && tz == 0) tz = autotune_tz(ctx, s, g, static_cast<const float*>(m.vel.p), 16);
         if (!rc)
           rc = build_job(ctx, s, g, tz, static_cast<const float*>(m.vel.p), ej->spec.wavelet_dev, ej->spec.src,
                          recs.data(), ej->spec.data_dev, nullptr, *hj);
