@@ -48,11 +48,11 @@ struct alignas(16) DevJob {
   const float* wavelet;            // [nt]
   const float* data;               // [nt][nrec] injected at receivers (migration)
   float* traces;                   // [nt][nrec] sampled at receivers (modelling)
-  void* snap;                      // [nsnap][nz][nx] stored S^n (store mode)
+  void* snap;                      // [nsnap][nz][pitch] stored S^n at padded columns (store mode)
   float* ring;                     // [nt][ring_len] boundary ring of S^n (reconstruct)
   uint32_t* maxbits;               // [nt][kMaxSlots] partial max |u^n| over the physical window (float bits)
-  float* image;                    // [nz][nx]
-  float* illum;                    // [nz][nx] or null
+  float* image;                    // [nz][pitch]: physical (pz, px) at pz * pitch + px + nb
+  float* illum;                    // same layout, or null
   const int2* recs;                // receivers sorted by tile: {local index, receiver id}
   uint32_t* health;                // [1] bit 0: a non-finite value was seen
 };
@@ -87,13 +87,13 @@ hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* ho
                        float* c, float* gz, float* gx, float dt, float sponge_a, hipStream_t s);
 hipError_t launch_vmax(const float* vel, int nz, int model_nx, int ix0, int width,
                        uint32_t* out_bits, hipStream_t s);
-hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int nz, int width,
-                        hipStream_t s);
+hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int img_pitch, int nz,
+                        int width, hipStream_t s);
 hipError_t launch_copy_phys(float* dst, const float* field, int nz, int nx, int nb, int pitch,
                             hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model, const float* img,
-                          int nz, int width, int ix0, hipStream_t s);
+                          int img_pitch, int nz, int width, int ix0, hipStream_t s);
 hipError_t launch_stats_out(const double* mean, const double* m2, const int32_t* count, int64_t n,
                             double* mean_out, double* std_out, int32_t* count_out, hipStream_t s);
 hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int min_count,

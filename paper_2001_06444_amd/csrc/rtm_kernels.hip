@@ -23,6 +23,47 @@
 
 namespace rtm {
 
+// Streaming hints: outputs of a step are not read again within the step, and
+// pointwise operands are read exactly once per step.
+#ifndef RTM_NT_STORE
+#define RTM_NT_STORE 1
+#endif
+#ifndef RTM_NT_LOAD
+#define RTM_NT_LOAD 1
+#endif
+
+// Pointers read from a job descriptor are generic; tagging them with the
+// global address space lets the compiler issue global_load/global_store
+// (vector-memory counter only) instead of flat accesses, whose waits also
+// drain the LDS counter and serialise the loads issued up front.
+#define RTM_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ RTM_GLOBAL T* gp(T* p) {
+  return (RTM_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const RTM_GLOBAL T* gp(const T* p) {
+  return (const RTM_GLOBAL T*)p;
+}
+
+template <class T>
+__device__ __forceinline__ void st_stream(RTM_GLOBAL T* p, T v) {
+#if RTM_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const RTM_GLOBAL T* p) {
+#if RTM_NT_LOAD
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
@@ -67,15 +108,15 @@ struct TileStage {
   static constexpr int kIt = (kN + kThreads - 1) / kThreads;
   f32x4 v[kIt];
 
-  __device__ __forceinline__ void load(const float* __restrict__ fld, int pitch, int z0, int x0) {
-    const float* base = fld + (int64_t)(z0 - kHalo) * pitch + (x0 - kHalo);
+  __device__ __forceinline__ void load(const RTM_GLOBAL float* __restrict__ fld, int pitch, int z0, int x0) {
+    const RTM_GLOBAL float* base = fld + (int64_t)(z0 - kHalo) * pitch + (x0 - kHalo);
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
-      const int i = threadIdx.x + it * kThreads;
-      if (i < kN) {
-        const int r = i / kVec, q = i - r * kVec;
-        v[it] = *reinterpret_cast<const f32x4*>(base + (int64_t)r * pitch + q * 4);
-      }
+      // surplus threads of the last round re-load the last vector (no branch
+      // around the load, so no wait at a join); store() skips them
+      const int i = min(threadIdx.x + it * kThreads, kN - 1);
+      const int r = i / kVec, q = i - r * kVec;
+      v[it] = *(const RTM_GLOBAL f32x4*)(base + (int64_t)r * pitch + q * 4);
     }
   }
   __device__ __forceinline__ void store(float* __restrict__ lds) const {
@@ -112,13 +153,15 @@ __device__ __forceinline__ float lap8(const float* __restrict__ lds, int row, in
 // Index of a physical node (pz, px) in the boundary ring: the 4-cell band
 // inside the physical perimeter, ordered top band, bottom band, then the
 // left/right bands row by row.  Returns -1 for interior nodes.
+// Written with selects only, so callers can use it between loads without
+// creating divergent branches.
 __device__ __forceinline__ int ring_slot(int pz, int px, int nz, int nx) {
-  if (pz < 4) return pz * nx + px;
-  if (pz >= nz - 4) return 4 * nx + (pz - (nz - 4)) * nx + px;
-  int q = pz - 4;
-  if (px < 4) return 8 * nx + q * 8 + px;
-  if (px >= nx - 4) return 8 * nx + q * 8 + 4 + (px - (nx - 4));
-  return -1;
+  const int band = pz < 4 ? pz : pz - (nz - 8);              // row within the top/bottom bands
+  const int s_tb = band * nx + px;                            // top: rows 0-3, bottom: rows 4-7
+  const int s_lr = 8 * nx + (pz - 4) * 8 + (px < 4 ? px : px - (nx - 8));
+  const bool tb = pz < 4 || pz >= nz - 4;
+  const bool lr = px < 4 || px >= nx - 4;
+  return tb ? s_tb : (lr ? s_lr : -1);
 }
 
 // Workgroup max of v (>= 0 or NaN) to one global atomic (float bits, unsigned
@@ -150,9 +193,11 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
   constexpr int RZ = TZ / 4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pitch = J.pitch;
-  const float* __restrict__ cur = J.f[n & 1];
-  float* __restrict__ nxt = J.f[(n + 1) & 1];  // holds u^{n-1}; overwritten with u^{n+1}
-  const float* __restrict__ cc = J.c;
+  const RTM_GLOBAL float* __restrict__ cur = gp(J.f[n & 1]);
+  RTM_GLOBAL float* __restrict__ nxt = gp(J.f[(n + 1) & 1]);  // holds u^{n-1}; overwritten with u^{n+1}
+  const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
+  const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
+  const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
   const int x = tl.x0 + lane;
   const int z0 = tl.z0 + w * RZ;
   const bool colok = x < J.nxp;
@@ -160,23 +205,20 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
   // ---- issue every global load of the step first ----
   TileStage<TZ> st;
   st.load(cur, pitch, tl.z0, tl.x0);
-  float cv[RZ], pv[RZ];
-#pragma clang loop unroll(full)
+  // Pointwise operands: every lane loads (addresses clamped into the grid, so
+  // there is no branch around a load); lanes outside the grid never use them.
+  float cv[RZ], pv[RZ], gzv[RZ];
+  const int xcl = min(x, J.nxp - 1);
+#pragma unroll
   for (int k = 0; k < RZ; ++k) {
-    const int z = z0 + k;
-    const bool ok = colok && z < J.nzp;
-    const int64_t idx = (int64_t)z * pitch + x;
-    cv[k] = ok ? cc[idx] : 0.0f;
-    pv[k] = ok ? nxt[idx] : 0.0f;
+    const int zc = min(z0 + k, J.nzp - 1);
+    const int64_t idx = (int64_t)zc * pitch + xcl;
+    cv[k] = ld_stream(cc + idx);
+    pv[k] = ld_stream((const RTM_GLOBAL float*)nxt + idx);
+    gzv[k] = gz[zc];
   }
-  const float gxv = colok ? J.gx[x] : 0.0f;
-  st.store(sm.a);
-  __syncthreads();
-
-  const float c0 = J.c0;
-  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
-  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
-  const float wsrc = J.wavelet[n] * J.inv_cell;
+  const float gxv = colok ? gx[xcl] : 0.0f;
+  const float wsrc = gp(J.wavelet)[n] * J.inv_cell;
   const int mode = J.mode;
   const bool snap_now = mode == kModeStore && (n % J.snap_stride) == 0;
   const bool want_max = mode == kModeStore && J.snap_dtype != 0 && ((n + 1) % J.snap_stride) == 0 &&
@@ -184,7 +226,13 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
   // per-snapshot scale from the max-abs of u^n, kept as kMaxSlots partial maxima
   float sc = 1.0f;
   if (snap_now && J.snap_dtype != 0)
-    sc = snap_scale_from_max(wave_max(__uint_as_float(J.maxbits[(int64_t)n * kMaxSlots + lane])));
+    sc = snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)n * kMaxSlots + lane])));
+  st.store(sm.a);
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
   const int px = x - J.nb;
   const bool colphys = px >= 0 && px < J.nx;
 
@@ -201,10 +249,10 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
       const int64_t idx = (int64_t)z * pitch + x;
       float lap = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zw, k, c0, cz, cx);
       if (z == J.src_z && x == J.src_x) lap += wsrc;
-      const float G = J.gz[z] * gxv;
+      const float G = gzv[k] * gxv;
       const float u = zw[k + 4];
       const float un = G * fmaf(cv[k], lap, 2.0f * u) - (G * G) * pv[k];
-      nxt[idx] = un;
+      st_stream(nxt + idx, un);
       const int pz = z - J.nb;
       const bool phys = colphys && pz >= 0 && pz < J.nz;
       if (mode == kModeModel) {
@@ -212,16 +260,16 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
       } else if (phys) {
         if (mode == kModeRecon) {
           int slot = ring_slot(pz, px, J.nz, J.nx);
-          if (slot >= 0) J.ring[(int64_t)(n + 1) * J.ring_len + slot] = un;
+          if (slot >= 0) st_stream(gp(J.ring) + (int64_t)(n + 1) * J.ring_len + slot, un);
         } else {
           if (snap_now) {
-            int64_t off = ((int64_t)(n / J.snap_stride) * J.nz + pz) * J.nx + px;
+            const int64_t off = ((int64_t)(n / J.snap_stride) * J.nz + pz) * pitch + x;
             if (J.snap_dtype == 0)
-              reinterpret_cast<float*>(J.snap)[off] = u;
+              st_stream(gp(reinterpret_cast<float*>(J.snap)) + off, u);
             else if (J.snap_dtype == 1)
-              reinterpret_cast<uint16_t*>(J.snap)[off] = bf16_rne(u * sc);
+              st_stream(gp(reinterpret_cast<uint16_t*>(J.snap)) + off, bf16_rne(u * sc));
             else
-              reinterpret_cast<uint16_t*>(J.snap)[off] = fp16_rne(u * sc);
+              st_stream(gp(reinterpret_cast<uint16_t*>(J.snap)) + off, fp16_rne(u * sc));
           }
           vmax = fmaxf(vmax, fabsf(un));
         }
@@ -236,7 +284,7 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
     __syncthreads();
     for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
       int2 r = J.recs[tl.rec_begin + i];
-      J.traces[(int64_t)(n + 1) * J.nrec + r.y] = sm.inj[r.x];
+      gp(J.traces)[(int64_t)(n + 1) * J.nrec + r.y] = sm.inj[r.x];
     }
   }
 }
@@ -247,12 +295,15 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pitch = J.pitch;
   const int nt = J.nt;
-  const float* __restrict__ rcur = J.r[(m + 1) & 1];  // R^{m+1}
-  float* __restrict__ rout = J.r[m & 1];              // R^{m+2} -> R^m
-  const float* __restrict__ scur = J.f[(m + 1) & 1];  // S^{m+1}
-  float* __restrict__ sout = J.f[m & 1];              // S^{m+2} -> S^m (S^m itself when m >= nt-2)
-  float* __restrict__ image = J.image;
-  const float* __restrict__ cc = J.c;
+  const RTM_GLOBAL float* __restrict__ rcur = gp(J.r[(m + 1) & 1]);  // R^{m+1}
+  RTM_GLOBAL float* __restrict__ rout = gp(J.r[m & 1]);              // R^{m+2} -> R^m
+  const RTM_GLOBAL float* __restrict__ scur = gp(J.f[(m + 1) & 1]);  // S^{m+1}
+  RTM_GLOBAL float* __restrict__ sout = gp(J.f[m & 1]);  // S^{m+2} -> S^m (S^m itself when m >= nt-2)
+  RTM_GLOBAL float* __restrict__ image = gp(J.image);
+  RTM_GLOBAL float* __restrict__ illum = gp(J.illum);
+  const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
+  const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
+  const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
   const int mode = J.mode;
   const int x = tl.x0 + lane;
   const int z0 = tl.z0 + w * RZ;
@@ -272,48 +323,77 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
   sa.load(rcur, pitch, tl.z0, tl.x0);
   TileStage<TZ> sb;
   if (recon) sb.load(scur, pitch, tl.z0, tl.x0);
-  float cv[RZ], pv[RZ], iv[RZ], sv[RZ];
+  // Pointwise operands, loaded by every lane from addresses clamped into the
+  // grid / the physical window (no branch around a load; only wavefront-
+  // uniform branches on the mode); lanes outside never use their values.
+  float cv[RZ], pv[RZ], iv[RZ], sv[RZ], gzv[RZ];
   bool ring_pt[RZ];
-#pragma clang loop unroll(full)
+  const int xcl = min(x, J.nxp - 1);
+  const int xph = min(max(x, J.nb), J.nb + J.nx - 1);  // padded column clamped to the window
+#pragma unroll
   for (int k = 0; k < RZ; ++k) {
-    const int z = z0 + k;
-    const bool ok = colok && z < J.nzp;
-    const int64_t idx = (int64_t)z * pitch + x;
-    cv[k] = ok ? cc[idx] : 0.0f;
-    pv[k] = ok ? rout[idx] : 0.0f;
+    const int zc = min(z0 + k, J.nzp - 1);
+    const int64_t idx = (int64_t)zc * pitch + xcl;
+    cv[k] = ld_stream(cc + idx);
+    pv[k] = ld_stream((const RTM_GLOBAL float*)rout + idx);
+    gzv[k] = gz[zc];
     iv[k] = 0.0f;
     sv[k] = 0.0f;
     ring_pt[k] = false;
-    const int pz = z - J.nb;
-    if (imaging && ok && colphys && pz >= 0 && pz < J.nz) {
-      iv[k] = image[(int64_t)pz * J.nx + px];
-      if (mode == kModeRecon) {
-        if (recon) {
-          const int slot = ring_slot(pz, px, J.nz, J.nx);
-          ring_pt[k] = slot >= 0;
-          // ring nodes are restored from storage; interior nodes need S^{m+2}
-          sv[k] = slot >= 0 ? J.ring[(int64_t)m * J.ring_len + slot] : sout[idx];
-        } else {
-          sv[k] = sout[idx];  // S^{nt-2}, left by the forward pass
-        }
+  }
+  if (imaging) {
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) {
+      const int pzc = min(max(z0 + k - J.nb, 0), J.nz - 1);
+      iv[k] = ld_stream((const RTM_GLOBAL float*)image + (int64_t)pzc * pitch + xph);
+    }
+    if (recon) {
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        const int pzc = min(max(z0 + k - J.nb, 0), J.nz - 1);
+        const int slot = ring_slot(pzc, xph - J.nb, J.nz, J.nx);
+        ring_pt[k] = slot >= 0;
+        // ring nodes are restored from storage; interior nodes need S^{m+2}
+        const RTM_GLOBAL float* sp =
+            slot >= 0 ? gp(J.ring) + (int64_t)m * J.ring_len + slot
+                      : (const RTM_GLOBAL float*)sout + (int64_t)(pzc + J.nb) * pitch + xph;
+        sv[k] = ld_stream(sp);
+      }
+    } else if (mode == kModeRecon) {
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {  // S^{nt-2}, left by the forward pass
+        const int pzc = min(max(z0 + k - J.nb, 0), J.nz - 1);
+        sv[k] = ld_stream((const RTM_GLOBAL float*)sout + (int64_t)(pzc + J.nb) * pitch + xph);
+      }
+    } else {
+      const int64_t base = (int64_t)(m / J.snap_stride) * J.nz;
+      if (J.snap_dtype == 0) {
+        const RTM_GLOBAL float* sp = gp(reinterpret_cast<const float*>(J.snap));
+#pragma unroll
+        for (int k = 0; k < RZ; ++k)
+          sv[k] = ld_stream(sp + (base + min(max(z0 + k - J.nb, 0), J.nz - 1)) * pitch + xph);
       } else {
-        const int64_t off = ((int64_t)(m / J.snap_stride) * J.nz + pz) * J.nx + px;
-        if (J.snap_dtype == 0)
-          sv[k] = reinterpret_cast<const float*>(J.snap)[off];
-        else if (J.snap_dtype == 1)
-          sv[k] = bf16_to_f32(reinterpret_cast<const uint16_t*>(J.snap)[off]);
-        else
-          sv[k] = fp16_to_f32(reinterpret_cast<const uint16_t*>(J.snap)[off]);
+        const RTM_GLOBAL uint16_t* sp = gp(reinterpret_cast<const uint16_t*>(J.snap));
+        const bool bf = J.snap_dtype == 1;
+#pragma unroll
+        for (int k = 0; k < RZ; ++k) {
+          const uint16_t q = ld_stream(sp + (base + min(max(z0 + k - J.nb, 0), J.nz - 1)) * pitch + xph);
+          sv[k] = bf ? bf16_to_f32(q) : fp16_to_f32(q);
+        }
       }
     }
   }
-  const float gxv = colok ? J.gx[x] : 0.0f;
+  const float gxv = colok ? gx[xcl] : 0.0f;
+  const float wsrc = (recon ? gp(J.wavelet)[m + 1] : 0.0f) * J.inv_cell;
+  float dsc = 1.0f;
+  if (imaging && mode == kModeStore && J.snap_dtype != 0)  // exact: power of two
+    dsc = 1.0f / snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)m * kMaxSlots + lane])));
   sa.store(sm.a);
   if (recon) sb.store(sm.b);
   if (tl.rec_count > 0) {
     for (int i = threadIdx.x; i < TZ * kTileX; i += kThreads) sm.inj[i] = 0.0f;
     __syncthreads();
-    const float* dm = J.data + (int64_t)m * J.nrec;
+    const RTM_GLOBAL float* dm = gp(J.data) + (int64_t)m * J.nrec;
     for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
       int2 r = J.recs[tl.rec_begin + i];
       atomicAdd(&sm.inj[r.x], dm[r.y]);
@@ -326,10 +406,6 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
   const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
   const bool has_inj = tl.rec_count > 0;
   const float kfac = J.kfac;
-  const float wsrc = (recon ? J.wavelet[m + 1] : 0.0f) * J.inv_cell;
-  float dsc = 1.0f;
-  if (imaging && mode == kModeStore && J.snap_dtype != 0)  // exact: power of two
-    dsc = 1.0f / snap_scale_from_max(wave_max(__uint_as_float(J.maxbits[(int64_t)m * kMaxSlots + lane])));
 
   float zr[RZ + 8];
 #pragma unroll
@@ -348,9 +424,9 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
       const int64_t idx = (int64_t)z * pitch + x;
       float lap = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zr, k, c0, cz, cx);
       if (has_inj) lap += sm.inj[lz * kTileX + lane];
-      const float G = J.gz[z] * gxv;
+      const float G = gzv[k] * gxv;
       const float r1 = zr[k + 4];  // R^{m+1}
-      rout[idx] = G * fmaf(cv[k], lap, 2.0f * r1) - (G * G) * pv[k];
+      st_stream(rout + idx, G * fmaf(cv[k], lap, 2.0f * r1) - (G * G) * pv[k]);
       const int pz = z - J.nb;
       if (imaging && colphys && pz >= 0 && pz < J.nz) {
         float s;
@@ -363,16 +439,16 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
               if (z == J.src_z && x == J.src_x) ls += wsrc;
               s = fmaf(cv[k], ls, 2.0f * zs[k + 4]) - sv[k];
             }
-            sout[idx] = s;
+            st_stream(sout + idx, s);
           } else {
             s = sv[k];
           }
         } else {
           s = sv[k] * dsc;
         }
-        const int64_t io = (int64_t)pz * J.nx + px;
-        image[io] = fmaf(kfac * s, r1, iv[k]);
-        if (J.illum) J.illum[io] = fmaf(kfac * s, s, J.illum[io]);
+        const int64_t io = (int64_t)pz * pitch + x;
+        st_stream(image + io, fmaf(kfac * s, r1, iv[k]));
+        if (illum) illum[io] = fmaf(kfac * s, s, illum[io]);
       }
     }
   }
@@ -501,16 +577,16 @@ hipError_t launch_vmax(const float* vel, int nz, int model_nx, int ix0, int widt
 
 // Stack: dst[z][ix0 + x] += img[z][x]
 __global__ void k_stack(float* __restrict__ dst, int dst_nx, int ix0, const float* __restrict__ img,
-                        int nz, int width) {
+                        int img_pitch, int nz, int width) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int z = blockIdx.y;
-  if (x < width && z < nz) dst[(int64_t)z * dst_nx + ix0 + x] += img[(int64_t)z * width + x];
+  if (x < width && z < nz) dst[(int64_t)z * dst_nx + ix0 + x] += img[(int64_t)z * img_pitch + x];
 }
 
-hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int nz, int width,
-                        hipStream_t s) {
+hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int img_pitch, int nz,
+                        int width, hipStream_t s) {
   hipLaunchKernelGGL(k_stack, dim3((width + 255) / 256, nz), dim3(256), 0, s, dst, dst_nx, ix0, img,
-                     nz, width);
+                     img_pitch, nz, width);
   return hipGetLastError();
 }
 
@@ -549,12 +625,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 // ---------------------------------------------------------------------------
 __global__ void k_welford(double* __restrict__ mean, double* __restrict__ m2,
                           int32_t* __restrict__ count, int nx_model, const float* __restrict__ img,
-                          int nz, int width, int ix0) {
+                          int img_pitch, int nz, int width, int ix0) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int z = blockIdx.y;
   if (x >= width || z >= nz) return;
   const int64_t o = (int64_t)z * nx_model + ix0 + x;
-  const double v = (double)img[(int64_t)z * width + x];
+  const double v = (double)img[(int64_t)z * img_pitch + x];
   const int32_t n = count[o] + 1;
   const double d = v - mean[o];
   const double mu = mean[o] + d / (double)n;
@@ -564,9 +640,9 @@ __global__ void k_welford(double* __restrict__ mean, double* __restrict__ m2,
 }
 
 hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model, const float* img,
-                          int nz, int width, int ix0, hipStream_t s) {
+                          int img_pitch, int nz, int width, int ix0, hipStream_t s) {
   hipLaunchKernelGGL(k_welford, dim3((width + 255) / 256, nz), dim3(256), 0, s, mean, m2, count,
-                     nx_model, img, nz, width, ix0);
+                     nx_model, img, img_pitch, nz, width, ix0);
   return hipGetLastError();
 }
 

@@ -179,12 +179,12 @@ static Footprint footprint(const JobGeom& g) {
   if (g.mode != kModeModel) t += 2 * f.field;    // r[2]
   t += align256((size_t)nzp * 4) + align256((size_t)nxp * 4);
   if (g.mode != kModeModel) {
-    t += align256((size_t)g.nz * g.width * 4);   // image
-    if (g.flags & RTM_IMG_ILLUM) t += align256((size_t)g.nz * g.width * 4);
+    t += align256((size_t)g.nz * field_pitch(nxp) * 4);  // image (field-aligned rows)
+    if (g.flags & RTM_IMG_ILLUM) t += align256((size_t)g.nz * field_pitch(nxp) * 4);
   }
   if (g.mode == kModeRecon) t += align256((size_t)g.nt * ring_len_of(g.nz, g.width) * 4);
   if (g.mode == kModeStore)
-    t += align256((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * g.width * snap_bytes(g.snap_dtype));
+    t += align256((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * field_pitch(nxp) * snap_bytes(g.snap_dtype));
   t += align256((size_t)g.nt * kMaxSlots * 4);   // maxbits
   t += align256((size_t)std::max(g.nrec, 1) * 8);  // receivers
   t += 256;                                      // health
@@ -492,20 +492,21 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   float* gz = static_cast<float*>(A((size_t)nzp * 4));
   float* gx = static_cast<float*>(A((size_t)nxp * 4));
   float* illum = nullptr;
-  if (g.mode != kModeModel && (g.flags & RTM_IMG_ILLUM)) illum = static_cast<float*>(A((size_t)g.nz * g.width * 4));
+  const size_t img_bytes = (size_t)g.nz * field_pitch(nxp) * 4;
+  if (g.mode != kModeModel && (g.flags & RTM_IMG_ILLUM)) illum = static_cast<float*>(A(img_bytes));
   float* ring = nullptr;
   void* snap = nullptr;
   if (g.mode == kModeRecon) ring = static_cast<float*>(A((size_t)g.nt * d.ring_len * 4));
   if (g.mode == kModeStore)
-    snap = A((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * g.width * snap_bytes(g.snap_dtype));
+    snap = A((size_t)nsnap_of(g.nt, g.snap_stride) * g.nz * field_pitch(nxp) * snap_bytes(g.snap_dtype));
   uint32_t* maxbits = static_cast<uint32_t*>(A((size_t)g.nt * kMaxSlots * 4));
   int2* recd = static_cast<int2*>(A((size_t)std::max(g.nrec, 1) * 8));
   uint32_t* health = static_cast<uint32_t*>(A(256));
   float* image = nullptr;
   if (ok && g.mode != kModeModel) {
-    image = static_cast<float*>(arena_alloc(ctx, (size_t)g.nz * g.width * 4));
+    image = static_cast<float*>(arena_alloc(ctx, img_bytes));
     if (!image) ok = false;
-    else j.image_blk = {image, align256((size_t)g.nz * g.width * 4)};
+    else j.image_blk = {image, align256(img_bytes)};
   }
   (void)p;
   if (!ok) {
@@ -576,8 +577,8 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
     HIP_OK(hipMemsetAsync(rb1, 0, fb, s));
   }
   HIP_OK(hipMemsetAsync(cbuf, 0, fb, s));
-  if (image) HIP_OK(hipMemsetAsync(image, 0, (size_t)g.nz * g.width * 4, s));
-  if (illum) HIP_OK(hipMemsetAsync(illum, 0, (size_t)g.nz * g.width * 4, s));
+  if (image) HIP_OK(hipMemsetAsync(image, 0, img_bytes, s));
+  if (illum) HIP_OK(hipMemsetAsync(illum, 0, img_bytes, s));
   if (ring) HIP_OK(hipMemsetAsync(ring, 0, (size_t)d.ring_len * 4, s));  // ring of u^0 = 0
   HIP_OK(hipMemsetAsync(maxbits, 0, (size_t)g.nt * kMaxSlots * 4, s));
   HIP_OK(hipMemsetAsync(health, 0, 4, s));
@@ -1027,8 +1028,9 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
   Table t;
   rc = run_plain(ctx, s, j, tz, t);
   if (!rc) {
-    HIP_OK(launch_stack(image_dev, g.model_nx, ix0, j.d.image, g.nz, width, s));
-    if (illum_dev && j.d.illum) HIP_OK(launch_stack(illum_dev, g.model_nx, ix0, j.d.illum, g.nz, width, s));
+    HIP_OK(launch_stack(image_dev, g.model_nx, ix0, j.d.image + g.nb, j.d.pitch, g.nz, width, s));
+    if (illum_dev && j.d.illum)
+      HIP_OK(launch_stack(illum_dev, g.model_nx, ix0, j.d.illum + g.nb, j.d.pitch, g.nz, width, s));
     ctx->grid_updates += j.updates;
     ctx->alg_bytes += j.alg_bytes;
   }
@@ -1167,9 +1169,11 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   }
   if (!rc) {
     for (int i = 0; i < nshots && !rc; ++i) {
-      hipError_t e = launch_stack(image_dev, grid->nx, geoms[i].ix0, jobs[i]->d.image, grid->nz, geoms[i].width, s);
+      const DevJob& d = jobs[i]->d;
+      hipError_t e = launch_stack(image_dev, grid->nx, geoms[i].ix0, d.image + d.nb, d.pitch, grid->nz,
+                                  geoms[i].width, s);
       if (e == hipSuccess && illum_dev)
-        e = launch_stack(illum_dev, grid->nx, geoms[i].ix0, jobs[i]->d.illum, grid->nz, geoms[i].width, s);
+        e = launch_stack(illum_dev, grid->nx, geoms[i].ix0, d.illum + d.nb, d.pitch, grid->nz, geoms[i].width, s);
       if (e != hipSuccess) rc = fail(RTM_E_DEVICE, "stack launch failed: %s", hipGetErrorString(e));
     }
   }
@@ -1491,9 +1495,11 @@ static void sched_main(rtm_ctx* ctx) {
         if (!rc) {
           if ((ej->spec.flags & RTM_JOB_ACC_STATS) && m.mean.p)
             (void)launch_welford(static_cast<double*>(m.mean.p), static_cast<double*>(m.m2.p),
-                           static_cast<int32_t*>(m.count.p), m.nx, j.d.image, j.g.nz, j.g.width, j.g.ix0, s);
+                                 static_cast<int32_t*>(m.count.p), m.nx, j.d.image + j.g.nb, j.d.pitch,
+                                 j.g.nz, j.g.width, j.g.ix0, s);
           if ((ej->spec.flags & RTM_JOB_ACC_STACK) && m.stack.p)
-            (void)launch_stack(static_cast<float*>(m.stack.p), m.nx, j.g.ix0, j.d.image, j.g.nz, j.g.width, s);
+            (void)launch_stack(static_cast<float*>(m.stack.p), m.nx, j.g.ix0, j.d.image + j.g.nb, j.d.pitch,
+                               j.g.nz, j.g.width, s);
         }
         for (auto& b : j.blocks) d.blocks.push_back(b);
         j.blocks.clear();
@@ -1550,8 +1556,9 @@ extern "C" int rtm_ensemble_poll(rtm_ctx* ctx, uint64_t ticket, rtm_job_info* in
   const bool final = ej.state == RTM_JOB_DONE || ej.state == RTM_JOB_FAILED || ej.state == RTM_JOB_CANCELLED;
   if (ej.state == RTM_JOB_DONE && image_dev && ej.job && ej.job->image_blk.p) {
     HIP_OK(hipSetDevice(ctx->device));
-    HIP_OK(hipMemcpyAsync(image_dev, ej.job->image_blk.p, (size_t)ej.job->g.nz * ej.job->g.width * 4,
-                          hipMemcpyDeviceToDevice, ctx->stream));
+    const HostJob& hj = *ej.job;
+    HIP_OK(hipMemcpy2DAsync(image_dev, (size_t)hj.g.width * 4, hj.d.image + hj.g.nb, (size_t)hj.d.pitch * 4,
+                            (size_t)hj.g.width * 4, hj.g.nz, hipMemcpyDeviceToDevice, ctx->stream));
   }
   if (final && release) {
     Deferred d;
@@ -1673,7 +1680,8 @@ extern "C" int rtm_stats_add(rtm_ctx* ctx, rtm_stats* st, const float* image_dev
   if (ix0 < 0 || width < 1 || ix0 + width > st->nx) return fail(RTM_E_INVAL, "window outside the image");
   HIP_OK(hipSetDevice(ctx->device));
   HIP_OK(launch_welford(static_cast<double*>(st->mean.p), static_cast<double*>(st->m2.p),
-                        static_cast<int32_t*>(st->count.p), st->nx, image_dev, st->nz, width, ix0, ctx->stream));
+                        static_cast<int32_t*>(st->count.p), st->nx, image_dev, width, st->nz, width, ix0,
+                        ctx->stream));
   return RTM_OK;
 }
 
