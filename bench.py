@@ -37,7 +37,8 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for p in ("paper_2001_06444_amd/csrc/rtm_kernels.hip", "paper_2001_06444_amd/csrc/rtm_internal.h"):
+    for p in ("paper_2001_06444_amd/csrc/rtm_kernels.hip", "paper_2001_06444_amd/csrc/rtm_device.h",
+              "paper_2001_06444_amd/csrc/rtm_internal.h"):
         h.update((ROOT / p).read_bytes())
     return h.hexdigest()[:16]
 

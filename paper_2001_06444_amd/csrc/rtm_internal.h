@@ -91,6 +91,7 @@ hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int i
                         int width, hipStream_t s);
 hipError_t launch_copy_phys(float* dst, const float* field, int nz, int nx, int nb, int pitch,
                             hipStream_t s);
+hipError_t launch_nonfinite(const float* img, int pitch, int nz, int width, uint32_t* flag, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model, const float* img,
                           int img_pitch, int nz, int width, int ix0, hipStream_t s);

@@ -19,6 +19,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "rtm_device.h"
 #include "rtm_internal.h"
 
 namespace rtm {
@@ -62,12 +63,6 @@ __device__ __forceinline__ T ld_stream(const RTM_GLOBAL T* p) {
 #else
   return *p;
 #endif
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -162,19 +157,6 @@ __device__ __forceinline__ int ring_slot(int pz, int px, int nz, int nx) {
   const bool tb = pz < 4 || pz >= nz - 4;
   const bool lr = px < 4 || px >= nx - 4;
   return tb ? s_tb : (lr ? s_lr : -1);
-}
-
-// Workgroup max of v (>= 0 or NaN) to one global atomic (float bits, unsigned
-// compare is monotone for non-negative floats; NaN bits sort above +inf).
-__device__ __forceinline__ void wg_atomic_max(float v, uint32_t* dst, float* red) {
-  v = wave_max(v);
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    atomicMax(dst, __float_as_uint(m));
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -515,261 +497,6 @@ hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles
     case 64: return launch_step_tz<64>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-// ---------------------------------------------------------------------------
-// Job set-up: c = v^2 dt^2 on the padded window (velocity edge-replicated into
-// the sponge) and the sponge profiles g(d) = exp(-(a d)^2).
-// ---------------------------------------------------------------------------
-__global__ void k_prep(const float* __restrict__ vel, int model_nx, int ix0, int nz, int nx, int nb,
-                       int nzp, int nxp, int pitch, float dt2, float a, float* __restrict__ c,
-                       float* __restrict__ gz, float* __restrict__ gx) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int z = blockIdx.y;
-  if (x >= nxp || z >= nzp) return;
-  int vz = min(max(z - nb, 0), nz - 1);
-  int vx = min(max(x - nb, 0), nx - 1);
-  float v = vel[(int64_t)vz * model_nx + ix0 + vx];
-  c[(int64_t)z * pitch + x] = v * v * dt2;
-  if (z == 0) {
-    int d = x < nb ? nb - x : (x >= nb + nx ? x - (nb + nx - 1) : 0);
-    float ad = a * (float)d;
-    gx[x] = expf(-ad * ad);
-  }
-  if (x == 0) {
-    int d = z < nb ? nb - z : (z >= nb + nz ? z - (nb + nz - 1) : 0);
-    float ad = a * (float)d;
-    gz[z] = expf(-ad * ad);
-  }
-}
-
-hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* hj, float* c,
-                       float* gz, float* gx, float dt, float sponge_a, hipStream_t s) {
-  dim3 block(256), grid((hj->nxp + 255) / 256, hj->nzp);
-  float a = sponge_a > 0.0f ? sponge_a : (hj->nb > 0 ? 0.3f / (float)hj->nb : 0.0f);
-  hipLaunchKernelGGL(k_prep, grid, block, 0, s, vel, model_nx, ix0, hj->nz, hj->nx, hj->nb,
-                     hj->nzp, hj->nxp, hj->pitch, dt * dt, a, c, gz, gx);
-  return hipGetLastError();
-}
-
-// max |v| over a window (float bits; the output must be zeroed first)
-__global__ void k_vmax(const float* __restrict__ vel, int nz, int model_nx, int ix0, int width,
-                       uint32_t* out) {
-  __shared__ float red[4];
-  float m = 0.0f;
-  const int64_t n = (int64_t)nz * width;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t z = i / width, x = i - z * width;
-    float v = fabsf(vel[z * model_nx + ix0 + x]);
-    m = (v != v) ? v : fmaxf(m, v);  // propagate NaN
-  }
-  wg_atomic_max(m, out, red);
-}
-
-hipError_t launch_vmax(const float* vel, int nz, int model_nx, int ix0, int width, uint32_t* out,
-                       hipStream_t s) {
-  int64_t n = (int64_t)nz * width;
-  int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_vmax, dim3(blocks), dim3(256), 0, s, vel, nz, model_nx, ix0, width, out);
-  return hipGetLastError();
-}
-
-// Stack: dst[z][ix0 + x] += img[z][x]
-__global__ void k_stack(float* __restrict__ dst, int dst_nx, int ix0, const float* __restrict__ img,
-                        int img_pitch, int nz, int width) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int z = blockIdx.y;
-  if (x < width && z < nz) dst[(int64_t)z * dst_nx + ix0 + x] += img[(int64_t)z * img_pitch + x];
-}
-
-hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int img_pitch, int nz,
-                        int width, hipStream_t s) {
-  hipLaunchKernelGGL(k_stack, dim3((width + 255) / 256, nz), dim3(256), 0, s, dst, dst_nx, ix0, img,
-                     img_pitch, nz, width);
-  return hipGetLastError();
-}
-
-// Physical region of a padded field -> dense [nz][nx]
-__global__ void k_copy_phys(float* __restrict__ dst, const float* __restrict__ fld, int nz, int nx,
-                            int nb, int pitch) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int z = blockIdx.y;
-  if (x < nx && z < nz) dst[(int64_t)z * nx + x] = fld[(int64_t)(z + nb) * pitch + nb + x];
-}
-
-hipError_t launch_copy_phys(float* dst, const float* fld, int nz, int nx, int nb, int pitch,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_phys, dim3((nx + 255) / 256, nz), dim3(256), 0, s, dst, fld, nz, nx, nb,
-                     pitch);
-  return hipGetLastError();
-}
-
-__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, v, n);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Ensemble statistics (Sec. 2.3 / Stage 3): per-pixel FP64 Welford update
-//   n += 1; d = x - mean; mean += d / n; M2 += d (x - mean)
-// over the window [ix0, ix0 + width) of an [nz][nx_model] state.
-// ---------------------------------------------------------------------------
-__global__ void k_welford(double* __restrict__ mean, double* __restrict__ m2,
-                          int32_t* __restrict__ count, int nx_model, const float* __restrict__ img,
-                          int img_pitch, int nz, int width, int ix0) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int z = blockIdx.y;
-  if (x >= width || z >= nz) return;
-  const int64_t o = (int64_t)z * nx_model + ix0 + x;
-  const double v = (double)img[(int64_t)z * img_pitch + x];
-  const int32_t n = count[o] + 1;
-  const double d = v - mean[o];
-  const double mu = mean[o] + d / (double)n;
-  m2[o] += d * (v - mu);
-  mean[o] = mu;
-  count[o] = n;
-}
-
-hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model, const float* img,
-                          int img_pitch, int nz, int width, int ix0, hipStream_t s) {
-  hipLaunchKernelGGL(k_welford, dim3((width + 255) / 256, nz), dim3(256), 0, s, mean, m2, count,
-                     nx_model, img, img_pitch, nz, width, ix0);
-  return hipGetLastError();
-}
-
-__global__ void k_stats_out(const double* __restrict__ mean, const double* __restrict__ m2,
-                            const int32_t* __restrict__ count, int64_t n, double* mean_out,
-                            double* std_out, int32_t* count_out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t c = count[i];
-    if (mean_out) mean_out[i] = c > 0 ? mean[i] : 0.0;
-    if (std_out) std_out[i] = c > 1 ? sqrt(m2[i] / (double)(c - 1)) : 0.0;
-    if (count_out) count_out[i] = c;
-  }
-}
-
-hipError_t launch_stats_out(const double* mean, const double* m2, const int32_t* count, int64_t n,
-                            double* mean_out, double* std_out, int32_t* count_out, hipStream_t s) {
-  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_stats_out, dim3(blocks), dim3(256), 0, s, mean, m2, count, n, mean_out,
-                     std_out, count_out);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Stage-3 maps.  Confidence index (Eq. 6): two passes, min/max of std over
-// pixels with enough samples, then the normalisation.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t order_bits(double v) {
-  // monotone map of a non-negative double onto uint64
-  return (uint64_t)__double_as_longlong(v);
-}
-
-__global__ void k_minmax(const double* __restrict__ sd, const int32_t* __restrict__ count, int n,
-                         int min_count, unsigned long long* mm) {
-  double lo = INFINITY, hi = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (count && count[i] < min_count) continue;
-    double v = sd[i];
-    lo = fmin(lo, v);
-    hi = fmax(hi, v);
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o, 64));
-    hi = fmax(hi, __shfl_xor(hi, o, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMin(&mm[0], (unsigned long long)order_bits(lo));
-    atomicMax(&mm[1], (unsigned long long)order_bits(hi));
-  }
-}
-
-__global__ void k_confidence(const double* __restrict__ sd, const int32_t* __restrict__ count,
-                             int n, int min_count, const unsigned long long* mm, double* out) {
-  const double lo = __longlong_as_double((long long)mm[0]);
-  const double hi = __longlong_as_double((long long)mm[1]);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if ((count && count[i] < min_count) || !(hi > lo)) {
-      out[i] = 0.0;
-      continue;
-    }
-    out[i] = (hi - sd[i]) / (hi - lo);
-  }
-}
-
-__global__ void k_init_minmax(unsigned long long* mm) {
-  mm[0] = (unsigned long long)order_bits(INFINITY);
-  mm[1] = 0ull;
-}
-
-hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int min_count,
-                             double* out, double* scratch2, hipStream_t s) {
-  auto* mm = reinterpret_cast<unsigned long long*>(scratch2);
-  hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm);
-  int blocks = std::max(1, std::min((n + 255) / 256, 1024));
-  hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm);
-  hipLaunchKernelGGL(k_confidence, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm, out);
-  return hipGetLastError();
-}
-
-// Ratio map (Eq. 7): r = std / mean, 0 where |mean| <= eps
-__global__ void k_ratio(const double* __restrict__ sd, const double* __restrict__ mean, int n,
-                        double eps, double* out) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    double mu = mean[i];
-    out[i] = fabs(mu) > eps ? sd[i] / mu : 0.0;
-  }
-}
-
-hipError_t launch_ratio(const double* sd, const double* mean, int n, double eps, double* out,
-                        hipStream_t s) {
-  int blocks = std::max(1, std::min((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_ratio, dim3(blocks), dim3(256), 0, s, sd, mean, n, eps, out);
-  return hipGetLastError();
-}
-
-// Post-stack Laplacian filter: out = -L img, zero outside the image.
-__global__ void k_lapfilter(const float* __restrict__ img, int nz, int nx, float c0, float4 czv,
-                            float4 cxv, float* __restrict__ out) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int z = blockIdx.y;
-  if (x >= nx || z >= nz) return;
-  const float cz[4] = {czv.x, czv.y, czv.z, czv.w};
-  const float cx[4] = {cxv.x, cxv.y, cxv.z, cxv.w};
-  auto at = [&](int zz, int xx) -> float {
-    return (zz >= 0 && zz < nz && xx >= 0 && xx < nx) ? img[(int64_t)zz * nx + xx] : 0.0f;
-  };
-  float s = c0 * at(z, x);
-#pragma unroll
-  for (int k = 1; k <= 4; ++k) {
-    s = fmaf(cz[k - 1], at(z - k, x) + at(z + k, x), s);
-    s = fmaf(cx[k - 1], at(z, x - k) + at(z, x + k), s);
-  }
-  out[(int64_t)z * nx + x] = -s;
-}
-
-hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx, float* out,
-                            hipStream_t s) {
-  const double a[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-  const double iz2 = 1.0 / ((double)dz * dz), ix2 = 1.0 / ((double)dx * dx);
-  float c0 = (float)(a[0] * (iz2 + ix2));
-  float4 czv = make_float4((float)(a[1] * iz2), (float)(a[2] * iz2), (float)(a[3] * iz2),
-                           (float)(a[4] * iz2));
-  float4 cxv = make_float4((float)(a[1] * ix2), (float)(a[2] * ix2), (float)(a[3] * ix2),
-                           (float)(a[4] * ix2));
-  hipLaunchKernelGGL(k_lapfilter, dim3((nx + 255) / 256, nz), dim3(256), 0, s, img, nz, nx, c0, czv,
-                     cxv, out);
-  return hipGetLastError();
 }
 
 }  // namespace rtm

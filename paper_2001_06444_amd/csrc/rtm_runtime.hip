@@ -864,6 +864,7 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   for (auto& e : ctx->ph_ev) HIP_OK(hipEventCreate(&e));
   ctx->scratch_u32 = static_cast<uint32_t*>(ctx->arena.alloc(256));
   ctx->scratch_f64 = static_cast<double*>(ctx->arena.alloc(256));
+  HIP_OK(hipMemset(ctx->scratch_u32, 0, 256));
   *out = ctx.release();
   return RTM_OK;
 }
@@ -873,6 +874,14 @@ extern "C" int rtm_ctx_synchronize(rtm_ctx* ctx) {
   HIP_OK(hipSetDevice(ctx->device));
   HIP_OK(hipStreamSynchronize(ctx->stream));
   reap(ctx, false);
+  // images of plain / batched calls are checked for non-finite values as they
+  // finish; report (and clear) the flag here
+  uint32_t flag = 0;
+  HIP_OK(hipMemcpy(&flag, ctx->scratch_u32 + 1, 4, hipMemcpyDeviceToHost));
+  if (flag) {
+    HIP_OK(hipMemset(ctx->scratch_u32 + 1, 0, 4));
+    return fail(RTM_E_NONFINITE, "a migrated image contained non-finite values since the last synchronize");
+  }
   return RTM_OK;
 }
 
@@ -1036,6 +1045,7 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
   rc = run_plain(ctx, s, j, tz, t);
   if (!rc) {
     HIP_OK(launch_stack(image_dev, g.model_nx, ix0, j.d.image + g.nb, j.d.pitch, g.nz, width, s));
+    HIP_OK(launch_nonfinite(j.d.image + g.nb, j.d.pitch, g.nz, width, ctx->scratch_u32 + 1, s));
     if (illum_dev && j.d.illum)
       HIP_OK(launch_stack(illum_dev, g.model_nx, ix0, j.d.illum + g.nb, j.d.pitch, g.nz, width, s));
     ctx->grid_updates += j.updates;
@@ -1180,6 +1190,8 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
       const DevJob& d = jobs[i]->d;
       hipError_t e = launch_stack(image_dev, grid->nx, geoms[i].ix0, d.image + d.nb, d.pitch, grid->nz,
                                   geoms[i].width, s);
+      if (e == hipSuccess)
+        e = launch_nonfinite(d.image + d.nb, d.pitch, grid->nz, geoms[i].width, ctx->scratch_u32 + 1, s);
       if (e == hipSuccess && illum_dev)
         e = launch_stack(illum_dev, grid->nx, geoms[i].ix0, d.illum + d.nb, d.pitch, grid->nz, geoms[i].width, s);
       if (e != hipSuccess) rc = fail(RTM_E_DEVICE, "stack launch failed: %s", hipGetErrorString(e));
@@ -1495,12 +1507,24 @@ static void sched_main(rtm_ctx* ctx) {
         still.push_back(ej);
     }
     if (!finished.empty()) {
+      // non-finite check of every finished image before it reaches the statistics
+      std::vector<uint32_t> health(finished.size(), 0);
+      if (!rc) {
+        for (size_t i = 0; i < finished.size(); ++i) {
+          const HostJob& j = *finished[i]->job;
+          (void)launch_nonfinite(j.d.image + j.g.nb, j.d.pitch, j.g.nz, j.g.width, j.d.health, s);
+          (void)hipMemcpyAsync(&health[i], j.d.health, 4, hipMemcpyDeviceToHost, s);
+        }
+        (void)hipStreamSynchronize(s);
+      }
       std::lock_guard<std::mutex> lk(ctx->mu);
       Deferred d;
-      for (EnsJob* ej : finished) {
+      for (size_t fi = 0; fi < finished.size(); ++fi) {
+        EnsJob* ej = finished[fi];
         HostJob& j = *ej->job;
         Model& m = ctx->models[ej->spec.realization];
-        if (!rc) {
+        const int jrc = rc ? rc : (health[fi] ? RTM_E_NONFINITE : RTM_OK);
+        if (!jrc) {
           if ((ej->spec.flags & RTM_JOB_ACC_STATS) && m.mean.p)
             (void)launch_welford(static_cast<double*>(m.mean.p), static_cast<double*>(m.m2.p),
                                  static_cast<int32_t*>(m.count.p), m.nx, j.d.image + j.g.nb, j.d.pitch,
@@ -1511,10 +1535,10 @@ static void sched_main(rtm_ctx* ctx) {
         }
         for (auto& b : j.blocks) d.blocks.push_back(b);
         j.blocks.clear();
-        ej->state = rc ? RTM_JOB_FAILED : RTM_JOB_DONE;
-        ej->status = rc;
+        ej->state = jrc ? RTM_JOB_FAILED : RTM_JOB_DONE;
+        ej->status = jrc;
         m.active--;
-        if (rc) {
+        if (jrc) {
           ctx->jobs_failed++;
         } else {
           ctx->jobs_done++;

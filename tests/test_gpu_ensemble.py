@@ -212,3 +212,48 @@ def test_explicit_stats_maps_and_filter(rtm):
         ctx.laplacian_filter(dev(imgs[0]), 10.0, 12.5, out)
         ref = oracle.laplacian_filter(imgs[0].astype(np.float64), 10.0, 12.5)
         assert oracle.rel_l2(host(out), ref) <= 1e-6
+
+
+def test_nonfinite_fails_only_its_job(rtm):
+    """A job whose data hold a NaN fails with RTM_E_NONFINITE; the jobs around
+    it finish normally.  A NaN velocity is refused at submit.  On the plain
+    path the failure is reported by the next synchronize."""
+    vels = _models(1)
+    with rtm.Context(0, arena_bytes=256 << 20) as ctx:
+        g = rtm.make_grid(NZ, NX, NB, 100, H, H, DT)
+        ctx.model_register(0, dev(vels[0]), g)
+        w = dev(inputs.ricker(100, DT))
+        good = dev(np.random.default_rng(1).standard_normal((100, 60)) * 1e-3)
+        bad_np = np.random.default_rng(2).standard_normal((100, 60)) * 1e-3
+        bad_np[50, 30] = np.nan
+        bad = dev(bad_np)
+        o = rtm.img_opts()
+        t1 = ctx.submit(0, (1, 30), 0, 60, 1, 100, w, good, o, flags=rtm.JOB_ACC_STATS)
+        t2 = ctx.submit(0, (1, 30), 0, 60, 1, 100, w, bad, o, flags=rtm.JOB_ACC_STATS)
+        t3 = ctx.submit(0, (1, 100), 70, 60, 1, 100, w, good, o, flags=rtm.JOB_ACC_STATS)
+        ctx.drain()
+        i1, i2, i3 = ctx.poll(t1), ctx.poll(t2), ctx.poll(t3)
+        assert i1.state == rtm.JOB_DONE and i3.state == rtm.JOB_DONE
+        assert i2.state == rtm.JOB_FAILED and i2.status == -6
+        # the failed job did not reach the running statistics
+        cnt = torch.empty(NZ, NX, dtype=torch.int32, device="cuda")
+        mean = torch.empty(NZ, NX, dtype=torch.float64, device="cuda")
+        ctx.ensemble_stats(0, mean, None, cnt)
+        c = host(cnt)
+        assert c[:, :60].max() == 1 and np.isfinite(host(mean)).all()
+        # NaN velocity: refused at submit
+        vnan = vels[0].copy()
+        vnan[10, 10] = np.nan
+        ctx.model_register(1, dev(vnan), g)
+        with pytest.raises(rtm.RTMError) as e:
+            ctx.submit(1, (1, 30), 0, 60, 1, 100, w, good, o)
+        assert e.value.code == -6
+        # plain path: reported at the next synchronize, then cleared
+        img = torch.zeros(NZ, NX, device="cuda")
+        rec = [(1, x) for x in range(60)]
+        ctx.migrate_shot(g, dev(vels[0]), w, (1, 30), rec, bad, 0, 60, o, img)
+        with pytest.raises(rtm.RTMError) as e:
+            ctx.synchronize()
+        assert e.value.code == -6
+        ctx.migrate_shot(g, dev(vels[0]), w, (1, 30), rec, good, 0, 60, o, img.zero_())
+        ctx.synchronize()
