@@ -151,6 +151,17 @@ int rtm_propagate(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
                   const float *wavelet_dev, rtm_point src, int32_t nrec,
                   const rtm_point *rec_host, float *traces_dev, float *final_field_dev);
 
+/* Born (single-scattering) modelling of one shot over the whole model: the
+ * linearisation of Eq. 4 that migration is the exact adjoint of (Sec. 3,
+ * reverse problem).  Background u0 as in rtm_propagate and
+ *   du^{n+1} = G (2du^n + c (L du^n + m u0^n)) - G^2 du^{n-1},
+ * dtraces[n][r] = du^n(r).  mpert_dev [nz][nx]: perturbation m (zero in the
+ * sponge by construction); other arguments as in rtm_propagate.
+ * Errors: RTM_E_INVAL, RTM_E_CFL, RTM_E_NOMEM. */
+int rtm_born(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev, const float *wavelet_dev,
+             rtm_point src, const float *mpert_dev, int32_t nrec, const rtm_point *rec_host,
+             float *dtraces_dev);
+
 /* Reverse time migration of one shot on the aperture window
  * [ix0, ix0 + width) of the model (Sec. 2.2, Eq. 5 numerator; Listing 1's
  * per-shot forward + adjoint pair).
@@ -273,7 +284,20 @@ int rtm_stats_add(rtm_ctx *ctx, rtm_stats *st, const float *image_dev, int32_t i
 int rtm_stats_get(rtm_ctx *ctx, rtm_stats *st, double *mean_dev, double *std_dev,
                   int32_t *count_dev);
 
+/* Chan merge of two accumulators of the same size: dst becomes the
+ * statistics of the union of both sample sets (per pixel n = na + nb,
+ * d = mb - ma, mean = ma + d nb/n, M2 = M2a + M2b + d^2 na nb/n).  This is
+ * the combine step for statistics kept on several devices or streams. */
+int rtm_stats_merge(rtm_ctx *ctx, rtm_stats *dst, const rtm_stats *src);
+
 /* ---- Stage-3 maps and post-stack filter ------------------------------ */
+
+/* Source-normalised image (Eq. 5): out = image / (illum + eps_rel *
+ * max(illum)), with image and illum the numerator and denominator sums of a
+ * migration run with RTM_IMG_ILLUM.  All arrays [n] float. */
+int rtm_normalize_image(rtm_ctx *ctx, const float *image_dev, const float *illum_dev, int32_t n,
+                        float eps_rel, float *out_dev);
+
 
 /* Confidence index (Eq. 6): c = (s_max - s) / (s_max - s_min), s_min and
  * s_max the extremes of std over pixels with count >= min_count; pixels

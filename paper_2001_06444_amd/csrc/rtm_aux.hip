@@ -285,4 +285,67 @@ hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Source-normalised image (Eq. 5): out = I / (illum + eps_rel * max illum)
+// ---------------------------------------------------------------------------
+__global__ void k_max_nonneg(const float* __restrict__ a, int n, uint32_t* out) {
+  __shared__ float red[4];
+  float m = 0.0f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) m = fmaxf(m, a[i]);
+  wg_atomic_max(m, out, red);
+}
+
+__global__ void k_normalize(const float* __restrict__ img, const float* __restrict__ illum, int n,
+                            float eps_rel, const uint32_t* maxbits, float* __restrict__ out) {
+  const float eps = eps_rel * __uint_as_float(*maxbits);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float d = illum[i] + eps;
+    out[i] = d > 0.0f ? img[i] / d : 0.0f;
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
+hipError_t launch_normalize(const float* img, const float* illum, int n, float eps_rel, float* out,
+                            uint32_t* scratch, hipStream_t s) {
+  const int blocks = std::max(1, std::min((n + 255) / 256, 2048));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, scratch);
+  hipLaunchKernelGGL(k_max_nonneg, dim3(blocks), dim3(256), 0, s, illum, n, scratch);
+  hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, s, img, illum, n, eps_rel, scratch, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Chan et al. merge of two running (count, mean, M2) states, per pixel:
+//   n = na + nb, d = mb - ma, mean = ma + d nb / n, M2 = M2a + M2b + d^2 na nb / n
+// (combines per-GPU or per-stream statistics into one).
+// ---------------------------------------------------------------------------
+__global__ void k_chan_merge(double* __restrict__ ma, double* __restrict__ m2a, int32_t* __restrict__ na,
+                             const double* __restrict__ mb, const double* __restrict__ m2b,
+                             const int32_t* __restrict__ nb, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = na[i], b = nb[i];
+    if (b == 0) continue;
+    if (a == 0) {
+      ma[i] = mb[i];
+      m2a[i] = m2b[i];
+      na[i] = b;
+      continue;
+    }
+    const double nn = (double)a + (double)b;
+    const double d = mb[i] - ma[i];
+    ma[i] = ma[i] + d * ((double)b / nn);
+    m2a[i] = m2a[i] + m2b[i] + d * d * ((double)a * (double)b / nn);
+    na[i] = a + b;
+  }
+}
+
+hipError_t launch_chan_merge(double* mean_a, double* m2_a, int32_t* n_a, const double* mean_b,
+                             const double* m2_b, const int32_t* n_b, int64_t n, hipStream_t s) {
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_chan_merge, dim3(blocks), dim3(256), 0, s, mean_a, m2_a, n_a, mean_b, m2_b, n_b, n);
+  return hipGetLastError();
+}
+
 }  // namespace rtm

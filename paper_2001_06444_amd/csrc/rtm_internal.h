@@ -27,8 +27,8 @@ constexpr int kRowAlign = 64;    // rows rounded up to the tallest tile
 constexpr int kThreads = 256;    // 4 wavefronts per workgroup
 constexpr int kMaxSlots = 64;    // partial max-abs slots per stored step (spreads the atomics)
 
-enum JobMode : int32_t { kModeModel = 0, kModeStore = 1, kModeRecon = 2 };
-enum PhaseSet : int { kPhFwd = 1, kPhBwd = 2, kPhAny = 3 };
+enum JobMode : int32_t { kModeModel = 0, kModeStore = 1, kModeRecon = 2, kModeBorn = 3 };
+enum PhaseSet : int { kPhFwd = 1, kPhBwd = 2, kPhAny = 3, kPhBorn = 4 };
 
 // Device descriptor of one job.  Read-only for the step kernel except the
 // arrays it points to.
@@ -44,7 +44,7 @@ struct alignas(16) DevJob {
   const float* gz;                 // sponge profile per padded row [nzp]
   const float* gx;                 // sponge profile per padded column [nxp]
   float* f[2];                     // source wavefield: S^n / u^n in f[n & 1]
-  float* r[2];                     // receiver wavefield: R^m in r[m & 1]
+  float* r[2];                     // receiver wavefield R^m in r[m & 1] (Born: scattered field du^n)
   const float* wavelet;            // [nt]
   const float* data;               // [nt][nrec] injected at receivers (migration)
   float* traces;                   // [nt][nrec] sampled at receivers (modelling)
@@ -52,6 +52,7 @@ struct alignas(16) DevJob {
   float* ring;                     // [nt][ring_len] boundary ring of S^n (reconstruct)
   uint32_t* maxbits;               // [nt][kMaxSlots] partial max |u^n| over the physical window (float bits)
   float* image;                    // [nz][pitch]: physical (pz, px) at pz * pitch + px + nb
+                                   // (Born modelling: the perturbation m, same layout)
   float* illum;                    // same layout, or null
   const int2* recs;                // receivers sorted by tile: {local index, receiver id}
   uint32_t* health;                // [1] bit 0: a non-finite value was seen
@@ -92,6 +93,10 @@ hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int i
 hipError_t launch_copy_phys(float* dst, const float* field, int nz, int nx, int nb, int pitch,
                             hipStream_t s);
 hipError_t launch_nonfinite(const float* img, int pitch, int nz, int width, uint32_t* flag, hipStream_t s);
+hipError_t launch_normalize(const float* img, const float* illum, int n, float eps_rel, float* out,
+                            uint32_t* scratch, hipStream_t s);
+hipError_t launch_chan_merge(double* mean_a, double* m2_a, int32_t* n_a, const double* mean_b,
+                             const double* m2_b, const int32_t* n_b, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model, const float* img,
                           int img_pitch, int nz, int width, int ix0, hipStream_t s);

@@ -436,12 +436,98 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
   }
 }
 
+template <int TZ, class Smem>
+__device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n, Smem& sm) {
+  // Born (single-scattering) modelling, step n, background and scattered
+  // field in lockstep:
+  //   u0^{n+1} = G(2u0^n + c(L u0^n + w^n e_s/(dx dz))) - G^2 u0^{n-1}
+  //   du^{n+1} = G(2du^n + c(L du^n + m u0^n)) - G^2 du^{n-1},  dd[n+1][r] = du^{n+1}(r)
+  // m is the velocity-model perturbation on the physical window (zero in the
+  // sponge); u0^n is the centre value the background stencil already holds.
+  constexpr int RZ = TZ / 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int pitch = J.pitch;
+  const RTM_GLOBAL float* __restrict__ ucur = gp(J.f[n & 1]);
+  RTM_GLOBAL float* __restrict__ unxt = gp(J.f[(n + 1) & 1]);
+  const RTM_GLOBAL float* __restrict__ dcur = gp(J.r[n & 1]);
+  RTM_GLOBAL float* __restrict__ dnxt = gp(J.r[(n + 1) & 1]);
+  const RTM_GLOBAL float* __restrict__ mp = gp(J.image);
+  const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
+  const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
+  const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
+  const int x = tl.x0 + lane;
+  const int z0 = tl.z0 + w * RZ;
+  const bool colok = x < J.nxp;
+  const int px = x - J.nb;
+  const bool colphys = px >= 0 && px < J.nx;
+
+  TileStage<TZ> sa, sb;
+  sa.load(ucur, pitch, tl.z0, tl.x0);
+  sb.load(dcur, pitch, tl.z0, tl.x0);
+  float cv[RZ], pv[RZ], qv[RZ], mv[RZ], gzv[RZ];
+  const int xcl = min(x, J.nxp - 1);
+  const int xph = min(max(x, J.nb), J.nb + J.nx - 1);
+#pragma unroll
+  for (int k = 0; k < RZ; ++k) {
+    const int zc = min(z0 + k, J.nzp - 1);
+    const int64_t idx = (int64_t)zc * pitch + xcl;
+    cv[k] = ld_stream(cc + idx);
+    pv[k] = ld_stream((const RTM_GLOBAL float*)unxt + idx);
+    qv[k] = ld_stream((const RTM_GLOBAL float*)dnxt + idx);
+    gzv[k] = gz[zc];
+    const int pzc = min(max(z0 + k - J.nb, 0), J.nz - 1);
+    mv[k] = ld_stream(mp + (int64_t)pzc * pitch + xph);
+  }
+  const float gxv = colok ? gx[xcl] : 0.0f;
+  const float wsrc = gp(J.wavelet)[n] * J.inv_cell;
+  sa.store(sm.a);
+  sb.store(sm.b);
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
+  float zu[RZ + 8], zd[RZ + 8];
+#pragma unroll
+  for (int j = 0; j < RZ + 8; ++j) {
+    zu[j] = sm.a[(w * RZ + j) * kLdsW + lane + kHalo];
+    zd[j] = sm.b[(w * RZ + j) * kLdsW + lane + kHalo];
+  }
+#pragma clang loop unroll(full)
+  for (int k = 0; k < RZ; ++k) {
+    const int lz = w * RZ + k;
+    const int z = z0 + k;
+    if (colok && z < J.nzp) {
+      const int64_t idx = (int64_t)z * pitch + x;
+      const int pz = z - J.nb;
+      const bool phys = colphys && pz >= 0 && pz < J.nz;
+      const float G = gzv[k] * gxv;
+      const float u = zu[k + 4];
+      float lu = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zu, k, c0, cz, cx);
+      if (z == J.src_z && x == J.src_x) lu += wsrc;
+      st_stream(unxt + idx, G * fmaf(cv[k], lu, 2.0f * u) - (G * G) * pv[k]);
+      float ld = lap8<RZ>(sm.b, lz + kHalo, lane + kHalo, zd, k, c0, cz, cx);
+      if (phys) ld = fmaf(mv[k], u, ld);
+      const float dn = G * fmaf(cv[k], ld, 2.0f * zd[k + 4]) - (G * G) * qv[k];
+      st_stream(dnxt + idx, dn);
+      sm.inj[lz * kTileX + lane] = dn;
+    }
+  }
+  if (tl.rec_count > 0 && J.traces != nullptr) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
+      int2 r = J.recs[tl.rec_begin + i];
+      gp(J.traces)[(int64_t)(n + 1) * J.nrec + r.y] = sm.inj[r.x];
+    }
+  }
+}
+
 template <int TZ, int PH>
 __global__ __launch_bounds__(kThreads) void k_step(const DevJob* __restrict__ jobs,
                                                     const Tile* __restrict__ tiles,
                                                     const StepCtl* __restrict__ ctl, int ntiles_arg,
                                                     int use_ctl_tick, int tick_off) {
-  __shared__ StepSmem<TZ, (PH & kPhBwd) != 0> sm;
+  __shared__ StepSmem<TZ, (PH & (kPhBwd | kPhBorn)) != 0> sm;
   // Global step: a base read from the control block (advanced by k_advance
   // after every group of graph-replayed launches) plus this launch's offset.
   const int ntiles = ntiles_arg >= 0 ? ntiles_arg : ctl->ntiles;
@@ -458,6 +544,10 @@ __global__ __launch_bounds__(kThreads) void k_step(const DevJob* __restrict__ jo
   const DevJob& J = jobs[tl.job];
   const int s = tick - J.start_tick;
   if (s < 0 || s >= J.nsteps) return;
+  if (J.mode == kModeBorn) {
+    if (PH & kPhBorn) born_tile<TZ>(J, tl, s, sm);
+    return;
+  }
   const int nf = (J.mode == kModeModel) ? J.nsteps : J.nt - 1;  // forward steps
   if (s < nf) {
     if (PH & kPhFwd) forward_tile<TZ>(J, tl, s, sm);
@@ -483,6 +573,8 @@ static hipError_t launch_step_tz(int phases, const DevJob* jobs, const Tile* til
     hipLaunchKernelGGL((k_step<TZ, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
   else if (phases == kPhBwd)
     hipLaunchKernelGGL((k_step<TZ, kPhBwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+  else if (phases == kPhBorn)
+    hipLaunchKernelGGL((k_step<TZ, kPhBorn>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
   else
     hipLaunchKernelGGL((k_step<TZ, kPhAny>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
   return hipGetLastError();

@@ -213,6 +213,11 @@ static void count_work(HostJob& j) {
     j.alg_bytes = (nt - 1) * (Npad * 16 + (uint64_t)g.nrec * 4);
     return;
   }
+  if (g.mode == kModeBorn) {  // background and scattered field: 2 x 16 B, c shared, + m
+    j.updates = 2 * (nt - 1) * Npad;
+    j.alg_bytes = (nt - 1) * (Npad * 28 + Nph * 4 + (uint64_t)g.nrec * 4);
+    return;
+  }
   j.updates = (nt - 1) * Npad + nt * Npad;
   uint64_t b = (nt - 1) * Npad * 16 + nt * Npad * 16 + nt * (uint64_t)g.nrec * 4;
   if (g.mode == kModeRecon) {
@@ -420,9 +425,9 @@ static int check_devjob(const DevJob& d) {
   const char* miss = nullptr;
   if (!d.c || !d.gz || !d.gx || !d.f[0] || !d.f[1] || !d.wavelet || !d.maxbits || !d.health) miss = "core arrays";
   else if (d.nrec > 0 && !d.recs) miss = "receiver table";
-  else if (d.mode == kModeModel && d.nrec > 0 && !d.traces) miss = "traces";
-  else if (d.mode != kModeModel && (!d.r[0] || !d.r[1] || !d.image)) miss = "receiver wavefield or image";
-  else if (d.mode != kModeModel && d.nrec > 0 && !d.data) miss = "receiver data";
+  else if ((d.mode == kModeModel || d.mode == kModeBorn) && d.nrec > 0 && !d.traces) miss = "traces";
+  else if (d.mode != kModeModel && (!d.r[0] || !d.r[1] || !d.image)) miss = "second wavefield or image";
+  else if ((d.mode == kModeStore || d.mode == kModeRecon) && d.nrec > 0 && !d.data) miss = "receiver data";
   else if (d.mode == kModeRecon && !d.ring) miss = "ring storage";
   else if (d.mode == kModeStore && !d.snap) miss = "snapshot storage";
   else if ((d.flags & RTM_IMG_ILLUM) && d.mode != kModeModel && !d.illum) miss = "illumination";
@@ -452,7 +457,7 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   d.snap_dtype = g.snap_dtype;
   d.snap_stride = g.mode == kModeStore ? g.snap_stride : 1;
   d.flags = g.flags;
-  d.nsteps = g.mode == kModeModel ? g.nt - 1 : 2 * g.nt - 1;
+  d.nsteps = (g.mode == kModeModel || g.mode == kModeBorn) ? g.nt - 1 : 2 * g.nt - 1;
   d.src_z = src.iz + g.nb;
   d.src_x = src.ix - g.ix0 + g.nb;
   d.nrec = g.nrec;
@@ -752,13 +757,13 @@ static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* 
   g.nt = 16;
   g.nrec = g.width;
   g.flags = 0;
-  const bool model = g.mode == kModeModel;
+  const bool model = g.mode == kModeModel || g.mode == kModeBorn;  // forward-only job kinds
   const int nsteps = model ? g.nt - 1 : 2 * g.nt - 1;
   std::vector<Block> scratch;
   void *zero = nullptr, *traces = nullptr;
   if (!alloc_block(ctx, scratch, (size_t)g.nt * g.width * 4 + 256, &zero)) return RTM_E_NOMEM;
   HIP_OK(hipMemsetAsync(zero, 0, (size_t)g.nt * g.width * 4 + 256, s));
-  if (g.mode == kModeModel) {  // modelling trials sample traces: give them somewhere to go
+  if (model) {  // modelling trials sample traces: give them somewhere to go
     if (!alloc_block(ctx, scratch, (size_t)B * g.nt * g.width * 4, &traces)) {
       release_blocks(ctx, scratch);
       return RTM_E_NOMEM;
@@ -790,8 +795,8 @@ static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* 
       if (st == 2) (void)hipEventRecord(e[0], s);
       if (st == nf - 1 && model) (void)hipEventRecord(e[1], s);
       if (st == nf && !model) (void)hipEventRecord(e[1], s);
-      if (launch_step(tz, st < nf ? kPhFwd : kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 0, st, s) !=
-          hipSuccess)
+      const int ph = g.mode == kModeBorn ? kPhBorn : (st < nf ? kPhFwd : kPhBwd);
+      if (launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 0, st, s) != hipSuccess)
         rc = fail(RTM_E_DEVICE, "tuning launch failed");
     }
     (void)hipEventRecord(e[2], s);
@@ -928,7 +933,8 @@ static int run_plain(rtm_ctx* ctx, hipStream_t s, HostJob& j, int tz, Table& t) 
   const int nsteps = j.d.nsteps;
   const int nf = j.g.mode == kModeModel ? nsteps : j.g.nt - 1;
   for (int st = 0; st < nsteps; ++st) {
-    HIP_OK(launch_step(tz, st < nf ? kPhFwd : kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 0, st, s));
+    const int ph = j.g.mode == kModeBorn ? kPhBorn : (st < nf ? kPhFwd : kPhBwd);
+    HIP_OK(launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 0, st, s));
   }
   ctx->steps_launched += nsteps;
   return RTM_OK;
@@ -982,6 +988,50 @@ extern "C" int rtm_propagate(rtm_ctx* ctx, const rtm_grid* grid, const float* ve
   }
   if (final_field_dev)
     HIP_OK(launch_copy_phys(final_field_dev, j.d.f[(g.nt - 1) & 1], g.nz, g.width, g.nb, j.d.pitch, s));
+  ctx->grid_updates += j.updates;
+  ctx->alg_bytes += j.alg_bytes;
+  finish_job_deferred(ctx, s, j, t, false);
+  return RTM_OK;
+}
+
+extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev, const float* wavelet_dev,
+                        rtm_point src, const float* mpert_dev, int32_t nrec, const rtm_point* rec_host,
+                        float* dtraces_dev) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!vel_dev || !wavelet_dev || !mpert_dev) return fail(RTM_E_INVAL, "vel_dev, wavelet_dev, mpert_dev are required");
+  if (nrec > 0 && !dtraces_dev) return fail(RTM_E_INVAL, "dtraces_dev is required when nrec > 0");
+  JobGeom g;
+  g.nz = grid->nz;
+  g.model_nx = grid->nx;
+  g.ix0 = 0;
+  g.width = grid->nx;
+  g.nb = grid->nb;
+  g.nt = grid->nt;
+  g.dz = grid->dz;
+  g.dx = grid->dx;
+  g.dt = grid->dt;
+  g.sponge_a = grid->sponge_a;
+  g.mode = kModeBorn;
+  g.nrec = nrec;
+  if ((rc = check_job(g, src, rec_host))) return rc;
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  float vmax = 0;
+  if ((rc = device_vmax(ctx, s, vel_dev, g.nz, g.model_nx, 0, g.width, &vmax))) return rc;
+  if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
+  const int tz = autotune_tz(ctx, s, g, vel_dev, 1);
+  HostJob j;
+  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, nullptr, dtraces_dev, j))) return rc;
+  // the perturbation goes into the job's image buffer (field-aligned rows, padded columns)
+  HIP_OK(hipMemcpy2DAsync(j.d.image + g.nb, (size_t)j.d.pitch * 4, mpert_dev, (size_t)g.width * 4,
+                          (size_t)g.width * 4, g.nz, hipMemcpyDeviceToDevice, s));
+  Table t;
+  if ((rc = run_plain(ctx, s, j, tz, t))) {
+    finish_job_deferred(ctx, s, j, t, false);
+    return rc;
+  }
   ctx->grid_updates += j.updates;
   ctx->alg_bytes += j.alg_bytes;
   finish_job_deferred(ctx, s, j, t, false);
@@ -1750,6 +1800,26 @@ extern "C" int rtm_laplacian_filter(rtm_ctx* ctx, const float* img_dev, int32_t 
   if (img_dev == out_dev) return fail(RTM_E_INVAL, "the filter cannot run in place");
   HIP_OK(hipSetDevice(ctx->device));
   HIP_OK(launch_lapfilter(img_dev, nz, nx, dz, dx, out_dev, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_normalize_image(rtm_ctx* ctx, const float* image_dev, const float* illum_dev, int32_t n,
+                                   float eps_rel, float* out_dev) {
+  if (!ctx || !image_dev || !illum_dev || !out_dev || n < 1 || !(eps_rel >= 0))
+    return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_normalize(image_dev, illum_dev, n, eps_rel, out_dev, ctx->scratch_u32 + 2, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_stats_merge(rtm_ctx* ctx, rtm_stats* dst, const rtm_stats* src) {
+  if (!ctx || !dst || !src || dst == src) return fail(RTM_E_INVAL, "bad arguments");
+  if (dst->nz != src->nz || dst->nx != src->nx) return fail(RTM_E_INVAL, "statistics of different sizes");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_chan_merge(static_cast<double*>(dst->mean.p), static_cast<double*>(dst->m2.p),
+                           static_cast<int32_t*>(dst->count.p), static_cast<const double*>(src->mean.p),
+                           static_cast<const double*>(src->m2.p), static_cast<const int32_t*>(src->count.p),
+                           (int64_t)dst->nz * dst->nx, ctx->stream));
   return RTM_OK;
 }
 

@@ -88,6 +88,9 @@ SIGNATURES = {
     "rtm_ctx_destroy": ([_V], ctypes.c_int),
     "rtm_ctx_synchronize": ([_V], ctypes.c_int),
     "rtm_propagate": ([_V, _P(Grid), _V, _V, Point, _I32, _P(Point), _V, _V], ctypes.c_int),
+    "rtm_born": ([_V, _P(Grid), _V, _V, Point, _V, _I32, _P(Point), _V], ctypes.c_int),
+    "rtm_stats_merge": ([_V, _V, _V], ctypes.c_int),
+    "rtm_normalize_image": ([_V, _V, _V, _I32, _F, _V], ctypes.c_int),
     "rtm_migrate_shot": ([_V, _P(Grid), _V, _V, Point, _I32, _P(Point), _V, _I32, _I32,
                           _P(ImgOpts), _V, _V], ctypes.c_int),
     "rtm_migrate_batch": ([_V, _P(Grid), _V, _V, _I32, _P(ShotDesc), _P(ImgOpts), _V, _V],
@@ -212,6 +215,11 @@ class Context:
         _check(lib().rtm_propagate(self.h, ctypes.byref(grid), _ptr(vel), _ptr(wavelet),
                                    Point(*src), n, recs, _ptr(traces), _ptr(final)))
 
+    def born(self, grid: Grid, vel, wavelet, src, mpert, rec, dtraces):
+        recs, n = _points(rec)
+        _check(lib().rtm_born(self.h, ctypes.byref(grid), _ptr(vel), _ptr(wavelet), Point(*src),
+                              _ptr(mpert), n, recs, _ptr(dtraces)))
+
     def migrate_shot(self, grid: Grid, vel, wavelet, src, rec, data, ix0, width, opts: ImgOpts,
                      image, illum=None):
         recs, n = _points(rec)
@@ -283,6 +291,13 @@ class Context:
 
     def stats_get(self, st, mean=None, std=None, count=None):
         _check(lib().rtm_stats_get(self.h, st, _ptr(mean), _ptr(std), _ptr(count)))
+
+    def stats_merge(self, dst, src):
+        _check(lib().rtm_stats_merge(self.h, dst, src))
+
+    def normalize_image(self, image, illum, out, eps_rel=1e-6):
+        _check(lib().rtm_normalize_image(self.h, _ptr(image), _ptr(illum), image.numel(),
+                                         float(eps_rel), _ptr(out)))
 
     def confidence_map(self, std, count, out, min_count=2):
         _check(lib().rtm_confidence_map(self.h, _ptr(std), _ptr(count), std.numel(),

@@ -1,0 +1,122 @@
+"""GPU Born modelling (the linearised operator migration is the adjoint of),
+the Eq. 5 source-normalised image, and the Chan merge of statistics."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_06444_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rtm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_06444_amd import rtm as _rtm
+
+    return _rtm
+
+
+@pytest.fixture(scope="module")
+def ctx(rtm):
+    c = rtm.Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _model(seed=0, nz=40, nx=150):
+    rng = np.random.default_rng(seed)
+    vel = np.where(np.arange(nz)[:, None] < 17, 1500.0, 2300.0) * np.ones((1, nx))
+    return vel * (1 + 0.1 * rng.random((nz, nx)))
+
+
+def test_born_matches_oracle(rtm, ctx):
+    vel = _model()
+    nz, nx = vel.shape
+    nt, h, dt, nb = 300, 10.0, 1e-3, 10
+    w = inputs.ricker(nt, dt, fp=25)
+    m = np.random.default_rng(3).standard_normal((nz, nx))
+    rec = [(1, i) for i in range(0, nx, 2)]
+    ref = oracle.born(vel, w, (3, 70), m, rec, dz=h, dx=h, dt=dt, nb=nb, nt=nt)
+    g = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    dd = torch.empty(nt, len(rec), device="cuda")
+    ctx.born(g, dev(vel), dev(w), (3, 70), dev(m), rec, dd)
+    e = oracle.rel_l2(host(dd), ref)
+    print(f"Born traces rel L2 {e:.3e}")
+    assert e <= 5e-5
+
+
+@pytest.mark.parametrize("mode", ["store", "reconstruct"])
+def test_gpu_only_dot_product(rtm, ctx, mode):
+    """<Born_gpu m, d> = <m, Mig_gpu d> with both operators on the GPU."""
+    vel = _model(seed=1)
+    nz, nx = vel.shape
+    nt, h, dt, nb = 300, 10.0, 1e-3, 10
+    w = inputs.ricker(nt, dt, fp=25)
+    rng = np.random.default_rng(4)
+    m = rng.standard_normal((nz, nx))
+    rec = [(1, i) for i in range(nx)]
+    d = rng.standard_normal((nt, nx))
+    g = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    dd = torch.empty(nt, nx, device="cuda")
+    ctx.born(g, dev(vel), dev(w), (3, 11), dev(m), rec, dd)
+    img = torch.zeros(nz, nx, device="cuda")
+    ctx.migrate_shot(g, dev(vel), dev(w), (3, 11), rec, dev(d), 0, nx, rtm.img_opts(mode, "fp32", 1), img)
+    lhs, rhs = (host(dd) * d).sum(), (m * host(img)).sum()
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+
+
+def test_source_normalised_image(rtm, ctx):
+    vel = _model(seed=2)
+    nz, nx = vel.shape
+    nt, h, dt, nb = 300, 10.0, 1e-3, 10
+    w = inputs.ricker(nt, dt, fp=25)
+    rec = [(1, i) for i in range(nx)]
+    d = np.random.default_rng(5).standard_normal((nt, nx)) * 1e-3
+    ref_i, ref_l = oracle.rtm_shot(vel, w, (3, 70), rec, d, dz=h, dx=h, dt=dt, nb=nb, illum=True)
+    g = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    img = torch.zeros(nz, nx, device="cuda")
+    ill = torch.zeros(nz, nx, device="cuda")
+    ctx.migrate_shot(g, dev(vel), dev(w), (3, 70), rec, dev(d), 0, nx,
+                     rtm.img_opts("reconstruct", illum=True), img, ill)
+    assert oracle.rel_l2(host(ill), ref_l) <= 1e-4
+    out = torch.empty_like(img)
+    ctx.normalize_image(img, ill, out, eps_rel=1e-3)
+    ref = ref_i / (ref_l + 1e-3 * ref_l.max())
+    assert oracle.rel_l2(host(out), ref) <= 2e-4
+
+
+def test_chan_merge_equals_two_pass_over_the_union(rtm, ctx):
+    rng = np.random.default_rng(6)
+    nz, nx = 23, 57
+    a = [rng.standard_normal((nz, nx)).astype(np.float32) * 3 + 1 for _ in range(5)]
+    b = [rng.standard_normal((nz, nx)).astype(np.float32) - 2 for _ in range(8)]
+    sa, sb = ctx.stats_create(nz, nx), ctx.stats_create(nz, nx)
+    for im in a:
+        ctx.stats_add(sa, dev(im))
+    for im in b:
+        ctx.stats_add(sb, dev(im[:, :40]), 10, 40)  # b: dense [nz][40] images on columns 10..49
+    ctx.stats_merge(sa, sb)
+    mean = torch.empty(nz, nx, dtype=torch.float64, device="cuda")
+    std = torch.empty_like(mean)
+    cnt = torch.empty(nz, nx, dtype=torch.int32, device="cuda")
+    ctx.stats_get(sa, mean, std, cnt)
+    imgs = a + [im[:, :40] for im in b]
+    wins = [(0, nx)] * len(a) + [(10, 40)] * len(b)
+    m_ref, s_ref, c_ref = oracle.windowed_stats([i.astype(np.float64) for i in imgs], wins, nz, nx)
+    assert np.array_equal(host(cnt), c_ref)
+    assert np.abs(host(mean) - m_ref).max() <= 1e-12 * np.abs(m_ref).max()
+    assert np.abs(host(std) - s_ref).max() <= 1e-12 * np.abs(s_ref).max()
+    ctx.stats_destroy(sa)
+    ctx.stats_destroy(sb)
