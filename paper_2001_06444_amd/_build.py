@@ -10,7 +10,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "librtm.so"
 SOURCES = [CSRC / "rtm_kernels.hip", CSRC / "rtm_aux.hip", CSRC / "rtm_runtime.hip"]
-HEADERS = [CSRC / "rtm_internal.h", CSRC / "rtm_device.h", ROOT / "include" / "rtm.h"]
+HEADERS = [CSRC / "rtm_internal.h", CSRC / "rtm_device.h", CSRC / "rtm_arena.h", ROOT / "include" / "rtm.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

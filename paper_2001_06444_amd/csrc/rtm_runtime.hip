@@ -34,9 +34,11 @@
 #include <vector>
 
 #include "../../include/rtm.h"
+#include "rtm_arena.h"
 #include "rtm_internal.h"
 
 using namespace rtm;
+using rtm::Arena;
 
 // ===========================================================================
 // errors
@@ -67,7 +69,7 @@ static double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+using rtm::align256;
 
 // 8th-order central weights of the 2nd derivative; a0 + 2 sum a_k = 0.
 static const double kA[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
@@ -78,68 +80,6 @@ static const double kA[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, 
 struct Block {
   void* p = nullptr;
   size_t n = 0;
-};
-
-class Arena {
- public:
-  void init(void* base, size_t size) {
-    base_ = static_cast<char*>(base);
-    size_ = size;
-    free_.clear();
-    free_[0] = size;
-    used_ = peak_ = 0;
-  }
-  void* alloc(size_t n) {
-    std::lock_guard<std::mutex> lk(mu_);
-    n = align256(n ? n : 1);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        size_t off = it->first, sz = it->second;
-        free_.erase(it);
-        if (sz > n) free_[off + n] = sz - n;
-        used_ += n;
-        peak_ = std::max(peak_, used_);
-        return base_ + off;
-      }
-    }
-    return nullptr;
-  }
-  void release(void* p, size_t n) {
-    if (!p) return;
-    std::lock_guard<std::mutex> lk(mu_);
-    n = align256(n ? n : 1);
-    size_t off = static_cast<char*>(p) - base_;
-    used_ -= n;
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t size() const { return size_; }
-  size_t used() {
-    std::lock_guard<std::mutex> lk(mu_);
-    return used_;
-  }
-  size_t peak() {
-    std::lock_guard<std::mutex> lk(mu_);
-    return peak_;
-  }
-
- private:
-  std::mutex mu_;
-  char* base_ = nullptr;
-  size_t size_ = 0;
-  std::map<size_t, size_t> free_;
-  size_t used_ = 0, peak_ = 0;
 };
 
 // Blocks (and host staging, graphs) released once an event has completed.
