@@ -91,7 +91,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["survey", "ensemble", "serve"], default="survey")
+    ap.add_argument("--workload", choices=["survey", "ensemble", "serve", "small", "born"],
+                    default="survey")
     ap.add_argument("--shots", type=int, default=100)
     ap.add_argument("--nt", type=int, default=None, help="default: 4000 survey, 3000 ensemble")
     ap.add_argument("--plain-shots", type=int, default=2)
@@ -125,7 +126,8 @@ def main():
         torch.cuda.synchronize()
         del src_t, dst_t
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
-    out = {"survey": run_survey, "ensemble": run_ensemble, "serve": run_serve}[args.workload](args)
+    out = {"survey": run_survey, "ensemble": run_ensemble, "serve": run_serve,
+           "small": run_small, "born": run_born}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 
@@ -497,6 +499,106 @@ def run_serve(args):
                 "value_is": "grid-pt updates/s of the saturation run"})
     return out
 
+
+
+def run_small(args):
+    """The small two-layer survey (101 x 201, nt 1000), where one shot is ~2000
+    tiny launches: many shots batched per launch from graph replays versus
+    one rtm_migrate_shot per shot."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06444_amd import inputs, rtm
+
+    dev = torch.device("cuda:0")
+    sv = inputs.two_layer_shot_survey(nt=args.nt or 1000)
+    nz, nx, nt, nb, h, dt = sv.nz, sv.nx, sv.nt, sv.nb, sv.h, sv.dt
+    n = args.shots if args.shots != 100 else 256
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    vt, vm, wav = t(sv.vel_true), t(sv.vel_mig), t(sv.wavelet)
+    grid = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    ctx = rtm.Context(0, arena_bytes=int(n * _job_bytes(nz, nx, nb, nt) * 1.1) + (256 << 20))
+    xs = np.linspace(5, nx - 6, n).round().astype(int)
+    rec = [(1, x) for x in range(nx)]
+    data = []
+    for x in xs:
+        a = torch.empty(nt, nx, device=dev)
+        b = torch.empty(nt, nx, device=dev)
+        ctx.propagate(grid, vt, wav, (1, int(x)), rec, a)
+        ctx.propagate(grid, vm, wav, (1, int(x)), rec, b)
+        data.append(a.sub_(b))
+    shots = [((1, int(x)), 0, nx, rec, d) for x, d in zip(xs, data)]
+    opts = rtm.img_opts("reconstruct")
+    image = torch.zeros(nz, nx, device=dev)
+    for _ in range(args.warmup):
+        ctx.migrate_batch(grid, vm, wav, shots, opts, image)
+    torch.cuda.synchronize()
+    u0 = ctx.stats().grid_updates
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        image.zero_()
+        ctx.migrate_batch(grid, vm, wav, shots, opts, image)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    upd = ctx.stats().grid_updates - u0
+    ips = n * args.steps / el
+    plain_jobs = [dict(vel=vm, wav=wav, src=s[0], rec=rec, data=s[4], ix0=0, width=nx, opts=opts,
+                       image_shape=(nz, nx)) for s in shots[: max(args.plain_shots, 4)]]
+    plain = _plain_rate(ctx, lambda j: grid, plain_jobs)
+    log(f"[bench] small: {n} shots batched {ips:.0f} images/s ({upd / el:.3e} updates/s); plain "
+        f"{plain['images_per_s']:.0f} images/s ({plain['ms_per_image']:.2f} ms/image)")
+    ctx.close()
+    out = _base_record(args, upd / el, el * 1e3 / args.steps, {
+        "workload": f"two-layer survey {nz}x{nx} at 10 m, nt={nt}, nb={nb}, {n} shots per batch, "
+                    f"reconstruct mode", "shots": n, "nt": nt, "path": "batched (hipGraph)"})
+    out.update({"images_per_s": ips, "plain": plain, "batched_vs_plain": ips / plain["images_per_s"]})
+    return out
+
+
+def run_born(args):
+    """Born modelling of survey shots at full size (plain path, one launch per
+    step advancing background and scattered field together)."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06444_amd import inputs, rtm
+
+    dev = torch.device("cuda:0")
+    sv = inputs.faulted_survey(n_shots=100, nt=args.nt or 4000)
+    nz, nx, nt, nb, h, dt = sv.nz, sv.nx, sv.nt, sv.nb, sv.h, sv.dt
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    vm, wav = t(sv.vel_mig), t(sv.wavelet)
+    mpert = t(sv.vel_true - sv.vel_mig)
+    grid = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    ctx = rtm.Context(0, arena_bytes=2 << 30)
+    shots = sv.shots[:: max(1, len(sv.shots) // max(args.shots if args.shots != 100 else 4, 1))][:4]
+    dd = torch.empty(nt, nx, device=dev)
+    ctx.born(grid, vm, wav, shots[0].src, mpert, shots[0].rec, dd)  # warm-up (tiles tuned)
+    torch.cuda.synchronize()
+    u0 = ctx.stats().grid_updates
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for sh in shots:
+        ctx.born(grid, vm, wav, sh.src, mpert, sh.rec, dd)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    upd = ctx.stats().grid_updates - u0
+    npad, nph = (nz + 2 * nb) * (nx + 2 * nb), nz * nx
+    launch_bytes = npad * 28 + nph * 4 + nx * 4
+    launch_us = ms * 1e3 / (len(shots) * (nt - 1))
+    gbs = launch_bytes / (launch_us * 1e-6) / 1e9
+    log(f"[bench] born: {len(shots)} shots, {upd / (ms * 1e-3):.3e} updates/s, {launch_us:.1f} us/launch, "
+        f"{gbs:.0f} GB/s (working set of one shot: {npad * 4 * 5 / 2**20:.0f} MiB, cache-resident)")
+    ctx.close()
+    out = _base_record(args, upd / (ms * 1e-3), ms / len(shots), {
+        "workload": f"Born modelling, faulted-layer survey {nz}x{nx}, nt={nt}, nb={nb}, "
+                    f"{len(shots)} shots one after the other", "path": "plain (one launch per step)"})
+    out.update({"steps": len(shots), "warmup": 1,
+                "launch": {"us": launch_us, "alg_bytes": launch_bytes, "GB_per_s": gbs,
+                           "note": "events around whole calls, launch gaps included; one shot's "
+                                   "working set fits the 256 MB Infinity Cache"}})
+    return out
 
 if __name__ == "__main__":
     main()
