@@ -245,3 +245,64 @@ def poisson_stream(n_jobs: int, rate: float = 20.0, seed: int = 5, n_real: int =
         dt_ = "bf16" if rng.uniform() < 0.5 else "fp32"
         jobs.append(StreamJob(float(t[j]), r, (1, ix), window_for(ix, w, nx), w, nt, dt_))
     return jobs
+
+
+# ---------------------------------------------------------------------------
+# Arrays for the compression stage (Sec. 4.2 compresses velocity samples,
+# migrated images and seismograms of the Marmousi2 study; these stand in)
+# ---------------------------------------------------------------------------
+def velocity_bank(n: int, nz: int = 351, nx: int = 1701, h: float = 10.0) -> np.ndarray:
+    """n velocity samples [n][nz][nx] float32: realizations 0..n-1 of the
+    smoothed faulted-layer model times (1 + 0.05 GRF)."""
+    base = faulted_layers(nz, nx, h)
+    return np.stack([realization(r, base, h) for r in range(n)]).astype(np.float32)
+
+
+def image_like(seed: int = 0, nz: int = 351, nx: int = 1701, h: float = 10.0, fp: float = 15.0,
+               v_ref: float = 2500.0, noise: float = 0.02) -> np.ndarray:
+    """Stand-in for a migrated image [nz][nx] float32, peak amplitude about 1.
+
+    The faulted-layer model's reflectivity (relative contrast of log velocity
+    between adjacent rows) convolved along depth with a Ricker pulse whose
+    depth wavelength is v_ref / fp, plus white noise (default_rng(seed)) of
+    `noise` times the peak, and a smooth low-frequency background like the
+    artefacts of an unfiltered stack."""
+    v = faulted_layers(nz, nx, h)
+    refl = np.zeros((nz, nx))
+    refl[1:] = np.diff(np.log(v), axis=0)
+    n = int(round(2.0 * v_ref / fp / h))
+    zz = (np.arange(-n, n + 1) * h) / v_ref
+    a = (math.pi * fp * zz) ** 2
+    pulse = (1.0 - 2.0 * a) * np.exp(-a)
+    img = np.apply_along_axis(lambda c: np.convolve(c, pulse, mode="same"), 0, refl)
+    img /= np.abs(img).max()
+    rng = np.random.default_rng(seed)
+    img += noise * rng.standard_normal((nz, nx))
+    zc, xc = np.mgrid[0:nz, 0:nx]
+    img += 0.1 * np.exp(-((zc - 20.0) ** 2) / (2 * 30.0 ** 2)) * np.cos(2 * math.pi * xc / 400.0)
+    return img.astype(np.float32)
+
+
+def seismogram_like(seed: int = 0, nt: int = 4000, nrec: int = 1701, dt: float = 1e-3,
+                    h: float = 10.0, fp: float = 15.0, noise: float = 1e-3) -> np.ndarray:
+    """Stand-in for a shot record [nt][nrec] float32: a direct arrival and six
+    reflection hyperbolas t(x) = sqrt(t0^2 + (x - xs)^2 / v^2) carrying a
+    Ricker pulse with 1/sqrt(t) spreading, source position, t0 and v drawn from
+    default_rng(seed), plus white noise of `noise` times the peak."""
+    rng = np.random.default_rng(seed)
+    xs = rng.uniform(0.0, nrec * h)
+    x = np.arange(nrec) * h
+    t = np.arange(nt)[:, None] * dt
+    events = [(0.0, 1500.0, 1.0)]
+    for k in range(6):
+        events.append((rng.uniform(0.3 + 0.5 * k, 0.6 + 0.5 * k), rng.uniform(1600.0, 3500.0),
+                       rng.uniform(0.1, 0.4) * (-1.0 if rng.uniform() < 0.3 else 1.0)))
+    rec = np.zeros((nt, nrec))
+    t_shift = 1.5 / fp
+    for t0, vel, amp in events:
+        tt = np.sqrt(t0 ** 2 + ((x - xs) / vel) ** 2)[None, :] + t_shift
+        a = (math.pi * fp * (t - tt)) ** 2
+        rec += amp * (1.0 - 2.0 * a) * np.exp(-a) / np.sqrt(np.maximum(tt, 0.05))
+    rec /= np.abs(rec).max()
+    rec += noise * rng.standard_normal((nt, nrec))
+    return rec.astype(np.float32)
