@@ -316,6 +316,63 @@ int rtm_ratio_map(rtm_ctx *ctx, const double *std_dev, const double *mean_dev, i
 int rtm_laplacian_filter(rtm_ctx *ctx, const float *img_dev, int32_t nz, int32_t nx, float dz,
                          float dx, float *out_dev);
 
+/* ---- codec: fixed-accuracy / lossless compression of float32 arrays ----
+ *
+ * The workflow compresses velocity models, migrated images and seismograms
+ * between its stages with an error-bounded block-transform coder, in a lossy
+ * fixed-accuracy setting and a lossless one (Sec. 3, data-compression
+ * paragraph; Sec. 4.2, Tables 1 and 2).  This coder is the library's own
+ * design for that job:
+ *   - 8 x 8 blocks (edge rows / columns repeated), in the order
+ *     (array, block row, block column);
+ *   - fixed accuracy: q = rint(x / (2 tol)) (float64, ties to even), so every
+ *     decoded value is within tol (1 + 2^-26) + 2^-24 |x'| of the input (the
+ *     last term is the float32 rounding of the decoded value x');
+ *     lossless: q = the float32 bit pattern as an order-preserving int32;
+ *   - three levels of a 2-D integer Haar lifting (modulo 2^32, exactly
+ *     invertible), zig-zag, five sub-bands each stored in its own bit width.
+ * Stream (32-bit words): [0..7] magic 0x315A5452, mode, count, rows, cols,
+ * blocks per chunk (256), tol (float64; 0 if lossless); chunk table
+ * [nchunks + 1]; block headers [nblocks]; payload.  The stream is
+ * self-describing and position independent.
+ *
+ * Arrays are dense [count][rows][cols] float32 (cols contiguous), caller
+ * owned, on the context's device.  Both calls are stream-ordered on the
+ * context stream and return after that stream has finished them (the encoder
+ * must report the stream length, the decoder its validation result). */
+enum { RTM_CODEC_TOL = 0, RTM_CODEC_LOSSLESS = 1 };
+
+/* Largest stream the encoder can produce for this shape (64 words per block
+ * plus the index), or -1 for a shape that is empty or exceeds 2^26 - 1
+ * blocks per stream. */
+int64_t rtm_codec_max_bytes(int32_t count, int32_t rows, int32_t cols);
+
+/* Encode x_dev [count][rows][cols] into stream_dev (capacity_bytes, 4-byte
+ * aligned).  mode RTM_CODEC_TOL needs a finite tol > 0; RTM_CODEC_LOSSLESS
+ * ignores tol.  *stream_bytes receives the stream length, also when the
+ * buffer is too small.
+ * Errors: RTM_E_INVAL (bad shape or mode; a non-finite value or
+ * |x| / (2 tol) > 2^31 - 1 in fixed-accuracy mode), RTM_E_NOMEM (capacity
+ * below the length: nothing past capacity_bytes is written; arena
+ * exhausted), RTM_E_DEVICE. */
+int rtm_codec_encode(rtm_ctx *ctx, const float *x_dev, int32_t count, int32_t rows, int32_t cols,
+                     int32_t mode, double tol, void *stream_dev, int64_t capacity_bytes,
+                     int64_t *stream_bytes);
+
+/* Read and validate a stream's header (copies its first 32 bytes to the
+ * host).  Any output pointer may be NULL.  Errors: RTM_E_INVAL (not a codec
+ * stream, bad header, stream shorter than its index). */
+int rtm_codec_info(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes, int32_t *mode,
+                   int32_t *count, int32_t *rows, int32_t *cols, double *tol);
+
+/* Decode stream_dev (stream_bytes long) into x_dev, which must hold
+ * count * rows * cols floats (capacity_floats).  Reads never leave the
+ * stream; a stream whose widths, chunk table or length disagree returns
+ * RTM_E_INVAL (x_dev then holds partial output).  RTM_E_NOMEM: x_dev too
+ * small. */
+int rtm_codec_decode(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes, float *x_dev,
+                     int64_t capacity_floats);
+
 /* ---- observability --------------------------------------------------- */
 
 typedef struct {
@@ -334,6 +391,11 @@ typedef struct {
     float last_fwd_ms, last_bwd_ms;
     int32_t last_fwd_launches, last_bwd_launches;
     uint64_t last_fwd_launch_bytes, last_bwd_launch_bytes;
+    /* last codec call: HIP-event time of its kernel, 1 encode / 2 decode, and
+     * its algorithmic HBM bytes (4 per value plus the stream length) */
+    float last_codec_ms;
+    int32_t last_codec_op;
+    uint64_t last_codec_bytes;
 } rtm_ctx_stats_t;
 
 int rtm_ctx_stats(rtm_ctx *ctx, rtm_ctx_stats_t *out);

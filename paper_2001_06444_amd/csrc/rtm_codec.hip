@@ -1,0 +1,330 @@
+// rtm_codec.hip -- block-transform codec for float32 arrays (fixed accuracy or
+// lossless), the data-compression stage of the workflow (Sec. 3, data
+// compression; Sec. 4.2, Tables 1-2).
+//
+// Stream format and arithmetic (the host runtime writes nothing but the
+// launch parameters; every word of the stream is written here):
+//   words [0..7]   magic, mode, count, rows, cols, blocks per chunk, tol (f64)
+//   chunk table    [nchunks + 1] payload word offset of each chunk, then the total
+//   block headers  [nblocks] five 6-bit sub-band widths
+//   payload        per block, its 64 coefficients in their sub-band widths,
+//                  least-significant bit first, padded to a 32-bit word
+// Per block: 8 x 8 values (edge rows/columns repeated) -> int32 (fixed
+// accuracy: rint(x / (2 tol)); lossless: order-preserving bit key) -> three
+// levels of the 2-D integer Haar lifting (d = a - b, s = b + (d >> 1), modulo
+// 2^32) -> zig-zag -> widths of the five sub-bands -> packed bits.
+//
+// Launch shape: one 64-lane wavefront handles 64 blocks, one block per lane,
+// with the block's 64 values in registers; a 256-thread workgroup is one
+// chunk of 256 blocks.  The encoder finds each chunk's payload offset with a
+// single-pass decoupled look-back over the chunks (chunk order taken from an
+// atomic ticket, so every chunk waits only on chunks that are already
+// running); the wait is bounded and reports an error instead of hanging.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rtm_codec.h"
+
+namespace rtm {
+namespace {
+
+constexpr int kB = 8;
+constexpr uint64_t kAgg = 1ull << 62;   // status: chunk aggregate published
+constexpr uint64_t kInc = 2ull << 62;   // status: inclusive prefix published
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr int kSpinLimit = 1 << 22;
+
+// sub-band of position (z, x) of the 8 x 8 coefficient layout
+__host__ __device__ constexpr int band_of(int z, int x) {
+  return (z < 2 && x < 2) ? 0 : (z < 4 && x < 4) ? 1 : (z < 4) ? 2 : (x < 4) ? 3 : 4;
+}
+
+__device__ inline int32_t wsub(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
+__device__ inline int32_t wadd(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
+
+// One level of the forward lifting on the top-left n x n corner.
+template <int N>
+__device__ inline void lift_level(int32_t (&v)[64]) {
+  constexpr int H = N / 2;
+  int32_t t[N * N];
+#pragma unroll
+  for (int z = 0; z < N; ++z)
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int32_t d = wsub(v[z * kB + 2 * k], v[z * kB + 2 * k + 1]);
+      t[z * N + k] = wadd(v[z * kB + 2 * k + 1], d >> 1);
+      t[z * N + H + k] = d;
+    }
+#pragma unroll
+  for (int k = 0; k < H; ++k)
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      const int32_t d = wsub(t[(2 * k) * N + x], t[(2 * k + 1) * N + x]);
+      v[k * kB + x] = wadd(t[(2 * k + 1) * N + x], d >> 1);
+      v[(H + k) * kB + x] = d;
+    }
+}
+
+// Inverse of lift_level<N>.
+template <int N>
+__device__ inline void unlift_level(int32_t (&v)[64]) {
+  constexpr int H = N / 2;
+  int32_t t[N * N];
+#pragma unroll
+  for (int k = 0; k < H; ++k)
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      const int32_t s = v[k * kB + x], d = v[(H + k) * kB + x];
+      const int32_t b = wsub(s, d >> 1);
+      t[(2 * k) * N + x] = wadd(d, b);
+      t[(2 * k + 1) * N + x] = b;
+    }
+#pragma unroll
+  for (int z = 0; z < N; ++z)
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int32_t s = t[z * N + k], d = t[z * N + H + k];
+      const int32_t b = wsub(s, d >> 1);
+      v[z * kB + 2 * k] = wadd(d, b);
+      v[z * kB + 2 * k + 1] = b;
+    }
+}
+
+__device__ inline uint32_t zigzag(int32_t v) { return ((uint32_t)v << 1) ^ (uint32_t)(v >> 31); }
+__device__ inline int32_t unzigzag(uint32_t u) { return (int32_t)(u >> 1) ^ -(int32_t)(u & 1u); }
+__device__ inline int32_t float_key(float f) {
+  const int32_t k = __float_as_int(f);
+  return k ^ ((k >> 31) & 0x7fffffff);
+}
+__device__ inline float key_float(int32_t k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+__device__ inline int bitlen(uint32_t u) { return 32 - __clz(u); }
+
+// Exclusive scan of one value per thread over a 256-thread workgroup;
+// returns the exclusive prefix and writes the workgroup total to *total.
+__device__ inline uint32_t wg_exclusive_scan(uint32_t v, uint32_t* lds4, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) lds4[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) base += (w < wave) ? lds4[w] : 0u;
+  *total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+  return base + inc - v;
+}
+
+// Grid position of the first value of block b.
+struct BlockPos {
+  int32_t a, z0, x0;
+};
+__device__ inline BlockPos block_pos(int32_t b, int32_t bz, int32_t bx) {
+  const int32_t per = bz * bx;
+  const int32_t a = b / per, rem = b - a * per;
+  const int32_t r = rem / bx;
+  return {a, r * kB, (rem - r * bx) * kB};
+}
+
+}  // namespace
+
+template <int MODE>
+__global__ __launch_bounds__(kZcChunk) void k_zc_encode(ZcParams p) {
+  __shared__ uint32_t s_scan[4];
+  __shared__ uint32_t s_chunk;
+  __shared__ uint64_t s_excl;
+  if (threadIdx.x == 0) s_chunk = atomicAdd(p.ticket, 1u);
+  __syncthreads();
+  const int32_t chunk = (int32_t)s_chunk;
+  const int32_t b = chunk * kZcChunk + (int32_t)threadIdx.x;
+  const bool active = b < p.nblocks;
+  const BlockPos bp = block_pos(active ? b : p.nblocks - 1, p.bz, p.bx);
+  const float* __restrict__ img = p.x + (int64_t)bp.a * p.rows * p.cols;
+
+  // values -> integers
+  int32_t v[64];
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < kB; ++i) {
+    const float* row = img + (int64_t)min(bp.z0 + i, p.rows - 1) * p.cols;
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const float f = __builtin_nontemporal_load(row + min(bp.x0 + j, p.cols - 1));
+      if (MODE == 0) {
+        const double q = __builtin_rint((double)f * p.r);
+        const bool ok = fabs(q) <= 2147483647.0;
+        bad |= !ok;
+        v[i * kB + j] = ok ? (int32_t)q : 0;
+      } else {
+        v[i * kB + j] = float_key(f);
+      }
+    }
+  }
+  lift_level<8>(v);
+  lift_level<4>(v);
+  lift_level<2>(v);
+
+  uint32_t u[64];
+  uint32_t orb[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    u[c] = zigzag(v[c]);
+    orb[band_of(c / kB, c % kB)] |= u[c];
+  }
+  int w[5];
+#pragma unroll
+  for (int g = 0; g < 5; ++g) w[g] = bitlen(orb[g]);
+  const uint32_t header = (uint32_t)(w[0] | w[1] << 6 | w[2] << 12 | w[3] << 18 | w[4] << 24);
+  const uint32_t bits = 4u * w[0] + 12u * w[1] + 16u * (w[2] + w[3] + w[4]);
+  const uint32_t nwords = active ? (bits + 31u) >> 5 : 0u;
+  if (active && bad) atomicOr(p.flags, kZcRange);
+
+  uint32_t agg;
+  const uint32_t local = wg_exclusive_scan(nwords, s_scan, &agg);
+
+  // decoupled look-back: chunk prefix from the chunks before this one
+  if (threadIdx.x == 0) {
+    uint64_t excl = 0;
+    if (chunk == 0) {
+      __hip_atomic_store(p.status, kInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(p.status + chunk, kAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int j = chunk - 1, spins = 0;
+      while (j >= 0) {
+        const uint64_t s = __hip_atomic_load(p.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((s >> 62) == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(p.flags, kZcSpin);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += s & kValMask;
+        if ((s >> 62) == 2) break;
+        --j;
+      }
+      __hip_atomic_store(p.status + chunk, kInc | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_excl = excl;
+    p.out[8 + chunk] = (uint32_t)excl;
+    if (chunk == p.nchunks - 1) {
+      p.out[8 + p.nchunks] = (uint32_t)(excl + agg);
+      p.result[0] = (uint32_t)(excl + agg);
+    }
+    if (chunk == 0) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) p.out[k] = p.head[k];
+    }
+    if ((int64_t)(p.pay_base + excl + agg) > p.cap_words) atomicOr(p.flags, kZcCapacity);
+  }
+  __syncthreads();
+  if (!active) return;
+  p.out[p.hdr_base + b] = header;
+
+  // pack the coefficients at the block's final payload position
+  int64_t wp = p.pay_base + (int64_t)s_excl + local;
+  const int64_t cap = p.cap_words;
+  uint64_t acc = 0;
+  int nb = 0;
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    const int wc = w[band_of(c / kB, c % kB)];
+    acc |= (uint64_t)u[c] << nb;
+    nb += wc;
+    if (nb >= 32) {
+      if (wp < cap) p.out[wp] = (uint32_t)acc;
+      ++wp;
+      acc >>= 32;
+      nb -= 32;
+    }
+  }
+  if (nb > 0 && wp < cap) p.out[wp] = (uint32_t)acc;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kZcChunk) void k_zc_decode(ZcParams p) {
+  __shared__ uint32_t s_scan[4];
+  const int32_t chunk = blockIdx.x;
+  const int32_t b = chunk * kZcChunk + (int32_t)threadIdx.x;
+  const bool active = b < p.nblocks;
+  const uint32_t* __restrict__ in = p.in;
+  const uint32_t header = active ? in[p.hdr_base + b] : 0u;
+  int w[5];
+  bool bad = false;
+#pragma unroll
+  for (int g = 0; g < 5; ++g) {
+    const int wg = (header >> (6 * g)) & 63;
+    bad |= wg > 32;
+    w[g] = min(wg, 32);
+  }
+  const uint32_t bits = 4u * w[0] + 12u * w[1] + 16u * (w[2] + w[3] + w[4]);
+  const uint32_t nwords = (bits + 31u) >> 5;
+  uint32_t agg;
+  const uint32_t local = wg_exclusive_scan(nwords, s_scan, &agg);
+  const uint32_t c0 = in[8 + chunk], c1 = in[8 + chunk + 1];
+  if (threadIdx.x == 0 && (c1 < c0 || c1 - c0 != agg)) atomicOr(p.flags, kZcCorrupt);
+  if (!active) return;
+  if (bad) atomicOr(p.flags, kZcCorrupt);
+
+  int64_t wp = p.pay_base + (int64_t)c0 + local;
+  const int64_t limit = p.cap_words;  // words of the stream the caller handed in
+  uint64_t buf = 0;
+  int have = 0;
+  int32_t v[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    const int wc = w[band_of(c / kB, c % kB)];
+    if (have < wc) {
+      const uint32_t word = (wp < limit) ? in[wp] : 0u;
+      ++wp;
+      buf |= (uint64_t)word << have;
+      have += 32;
+    }
+    const uint32_t uc = (uint32_t)(buf & ((1ull << wc) - 1ull));
+    buf >>= wc;
+    have -= wc;
+    v[c] = unzigzag(uc);
+  }
+  if (wp > limit) atomicOr(p.flags, kZcCorrupt);
+  unlift_level<2>(v);
+  unlift_level<4>(v);
+  unlift_level<8>(v);
+
+  const BlockPos bp = block_pos(b, p.bz, p.bx);
+  float* __restrict__ img = p.y + (int64_t)bp.a * p.rows * p.cols;
+#pragma unroll
+  for (int i = 0; i < kB; ++i) {
+    float* row = img + (int64_t)(bp.z0 + i) * p.cols;
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      if (bp.z0 + i < p.rows && bp.x0 + j < p.cols) {
+        const float f = MODE == 0 ? (float)((double)v[i * kB + j] * p.step) : key_float(v[i * kB + j]);
+        __builtin_nontemporal_store(f, row + bp.x0 + j);
+      }
+    }
+  }
+}
+
+hipError_t launch_zc_encode(const ZcParams& p, hipStream_t s) {
+  if (p.nchunks < 1) return hipErrorInvalidValue;
+  if (p.mode == 0)
+    k_zc_encode<0><<<p.nchunks, kZcChunk, 0, s>>>(p);
+  else
+    k_zc_encode<1><<<p.nchunks, kZcChunk, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_zc_decode(const ZcParams& p, hipStream_t s) {
+  if (p.nchunks < 1) return hipErrorInvalidValue;
+  if (p.mode == 0)
+    k_zc_decode<0><<<p.nchunks, kZcChunk, 0, s>>>(p);
+  else
+    k_zc_decode<1><<<p.nchunks, kZcChunk, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace rtm

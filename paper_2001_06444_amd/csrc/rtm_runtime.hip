@@ -35,6 +35,7 @@
 
 #include "../../include/rtm.h"
 #include "rtm_arena.h"
+#include "rtm_codec.h"
 #include "rtm_internal.h"
 
 using namespace rtm;
@@ -238,6 +239,10 @@ struct rtm_ctx {
   int active_jobs = 0, queued_jobs = 0;
   uint32_t* scratch_u32 = nullptr;     // small device scratch (vmax etc.)
   double* scratch_f64 = nullptr;
+  // last codec call: HIP events around its kernel, algorithmic bytes, 1 encode / 2 decode
+  hipEvent_t zc_ev[2] = {nullptr, nullptr};
+  int zc_op = 0;
+  uint64_t zc_bytes = 0;
 };
 
 // ---- deferred frees ----
@@ -807,6 +812,7 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
   for (auto& e : ctx->ph_ev) HIP_OK(hipEventCreate(&e));
+  for (auto& e : ctx->zc_ev) HIP_OK(hipEventCreate(&e));
   ctx->scratch_u32 = static_cast<uint32_t*>(ctx->arena.alloc(256));
   ctx->scratch_f64 = static_cast<double*>(ctx->arena.alloc(256));
   HIP_OK(hipMemset(ctx->scratch_u32, 0, 256));
@@ -858,6 +864,7 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
   (void)hipEventDestroy(ctx->ev_in);
   (void)hipEventDestroy(ctx->ev_out);
   for (auto e : ctx->ph_ev) (void)hipEventDestroy(e);
+  for (auto e : ctx->zc_ev) (void)hipEventDestroy(e);
   if (ctx->own_arena) (void)hipFree(ctx->own_arena);
   delete ctx;
   return RTM_OK;
@@ -1763,6 +1770,171 @@ extern "C" int rtm_stats_merge(rtm_ctx* ctx, rtm_stats* dst, const rtm_stats* sr
   return RTM_OK;
 }
 
+// ===========================================================================
+// Codec (fixed-accuracy / lossless block-transform coder of float32 arrays)
+// ===========================================================================
+static int64_t zc_index_words(int64_t nblk) {
+  return kZcHeaderWords + (nblk + kZcChunk - 1) / kZcChunk + 1 + nblk;
+}
+
+static int zc_geometry(int32_t count, int32_t rows, int32_t cols, ZcParams& p) {
+  if (count < 1 || rows < 1 || cols < 1) return fail(RTM_E_INVAL, "count, rows and cols must be >= 1");
+  const int64_t bz = (rows + 7) / 8, bx = (cols + 7) / 8, nblk = (int64_t)count * bz * bx;
+  if (nblk > kZcMaxBlocks)
+    return fail(RTM_E_INVAL, "%lld blocks exceed the limit of %lld per stream", (long long)nblk,
+                (long long)kZcMaxBlocks);
+  p.count = count;
+  p.rows = rows;
+  p.cols = cols;
+  p.bz = (int32_t)bz;
+  p.bx = (int32_t)bx;
+  p.nblocks = (int32_t)nblk;
+  p.nchunks = (int32_t)((nblk + kZcChunk - 1) / kZcChunk);
+  p.hdr_base = kZcHeaderWords + p.nchunks + 1;
+  p.pay_base = p.hdr_base + nblk;
+  return RTM_OK;
+}
+
+extern "C" int64_t rtm_codec_max_bytes(int32_t count, int32_t rows, int32_t cols) {
+  if (count < 1 || rows < 1 || cols < 1) return -1;
+  const int64_t nblk = (int64_t)count * ((rows + 7) / 8) * ((cols + 7) / 8);
+  if (nblk > kZcMaxBlocks) return -1;
+  return 4 * (zc_index_words(nblk) + 64 * nblk);
+}
+
+extern "C" int rtm_codec_encode(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows, int32_t cols,
+                                int32_t mode, double tol, void* stream_dev, int64_t capacity_bytes,
+                                int64_t* stream_bytes) {
+  if (!ctx || !x_dev || !stream_dev || !stream_bytes) return fail(RTM_E_INVAL, "bad arguments");
+  *stream_bytes = 0;
+  if (reinterpret_cast<uintptr_t>(stream_dev) & 3) return fail(RTM_E_INVAL, "stream must be 4-byte aligned");
+  if (reinterpret_cast<uintptr_t>(x_dev) & 3) return fail(RTM_E_INVAL, "array must be 4-byte aligned");
+  ZcParams p{};
+  if (mode == RTM_CODEC_TOL) {
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(RTM_E_INVAL, "the tolerance must be finite and > 0");
+    p.r = 1.0 / (2.0 * tol);
+    p.step = 2.0 * tol;
+    if (!std::isfinite(p.r)) return fail(RTM_E_INVAL, "the tolerance is too small");
+  } else if (mode == RTM_CODEC_LOSSLESS) {
+    tol = 0.0;
+  } else {
+    return fail(RTM_E_INVAL, "unknown codec mode %d", mode);
+  }
+  p.mode = mode;
+  if (int st = zc_geometry(count, rows, cols, p)) return st;
+  if (capacity_bytes < 4 * p.pay_base)
+    return fail(RTM_E_NOMEM, "stream capacity %lld bytes is below the %lld-byte index",
+                (long long)capacity_bytes, (long long)(4 * p.pay_base));
+  p.cap_words = capacity_bytes / 4;
+  HIP_OK(hipSetDevice(ctx->device));
+  const size_t scratch_bytes = 8 * (size_t)p.nchunks + 64;
+  void* scratch = arena_alloc(ctx, scratch_bytes);
+  if (!scratch) return fail(RTM_E_NOMEM, "arena exhausted (codec look-back state)");
+  uint32_t* tail = reinterpret_cast<uint32_t*>(static_cast<char*>(scratch) + 8 * (size_t)p.nchunks);
+  p.x = x_dev;
+  p.out = static_cast<uint32_t*>(stream_dev);
+  p.status = static_cast<uint64_t*>(scratch);
+  p.ticket = tail;
+  p.flags = tail + 1;
+  p.result = tail + 2;
+  uint32_t tw[2];
+  memcpy(tw, &tol, 8);
+  const uint32_t head[8] = {kZcMagic, (uint32_t)mode, (uint32_t)count, (uint32_t)rows,
+                            (uint32_t)cols, (uint32_t)kZcChunk, tw[0], tw[1]};
+  memcpy(p.head, head, sizeof head);
+  hipStream_t s = ctx->stream;
+  uint32_t res[4] = {0, 0, 0, 0};
+  hipError_t e = launch_fill_u32(static_cast<uint32_t*>(scratch), 0, (int64_t)scratch_bytes / 4, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[0], s);
+  if (e == hipSuccess) e = launch_zc_encode(p, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[1], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(res, tail, 16, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ctx->arena.release(scratch, align256(scratch_bytes));
+  if (e != hipSuccess) return fail(RTM_E_DEVICE, "codec encode: %s", hipGetErrorString(e));
+  const uint32_t flags = res[1];
+  if (flags & kZcSpin) return fail(RTM_E_DEVICE, "codec encode: a chunk prefix did not arrive in time");
+  if (flags & kZcRange)
+    return fail(RTM_E_INVAL, "a value is non-finite or |x| / (2 tol) exceeds 2^31 - 1; use a larger "
+                             "tolerance or the lossless mode");
+  const int64_t bytes = 4 * (p.pay_base + (int64_t)res[2]);
+  *stream_bytes = bytes;
+  ctx->zc_op = 1;
+  ctx->zc_bytes = 4 * (uint64_t)count * rows * cols + (uint64_t)bytes;
+  if (flags & kZcCapacity)
+    return fail(RTM_E_NOMEM, "the stream needs %lld bytes, the buffer holds %lld", (long long)bytes,
+                (long long)capacity_bytes);
+  return RTM_OK;
+}
+
+extern "C" int rtm_codec_info(rtm_ctx* ctx, const void* stream_dev, int64_t stream_bytes, int32_t* mode,
+                              int32_t* count, int32_t* rows, int32_t* cols, double* tol) {
+  if (!ctx || !stream_dev) return fail(RTM_E_INVAL, "bad arguments");
+  if (reinterpret_cast<uintptr_t>(stream_dev) & 3) return fail(RTM_E_INVAL, "stream must be 4-byte aligned");
+  if (stream_bytes < 4 * kZcHeaderWords) return fail(RTM_E_INVAL, "stream shorter than its header");
+  HIP_OK(hipSetDevice(ctx->device));
+  uint32_t h[8];
+  HIP_OK(hipMemcpyAsync(h, stream_dev, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  if (h[0] != kZcMagic) return fail(RTM_E_INVAL, "not a codec stream (magic %08x)", h[0]);
+  if (h[1] > 1) return fail(RTM_E_INVAL, "unknown codec mode %u", h[1]);
+  if (h[5] != (uint32_t)kZcChunk) return fail(RTM_E_INVAL, "unsupported chunk size %u", h[5]);
+  if (h[2] - 1 > 0x7ffffffeu || h[3] - 1 > 0x7ffffffeu || h[4] - 1 > 0x7ffffffeu)
+    return fail(RTM_E_INVAL, "bad array shape in the stream header");
+  double t;
+  memcpy(&t, h + 6, 8);
+  if (h[1] == RTM_CODEC_TOL && (!(t > 0) || !std::isfinite(t) || !std::isfinite(1.0 / (2.0 * t))))
+    return fail(RTM_E_INVAL, "bad tolerance in the stream header");
+  ZcParams p{};
+  if (int st = zc_geometry((int32_t)h[2], (int32_t)h[3], (int32_t)h[4], p)) return st;
+  if (stream_bytes < 4 * p.pay_base) return fail(RTM_E_INVAL, "stream shorter than its index");
+  if (mode) *mode = (int32_t)h[1];
+  if (count) *count = p.count;
+  if (rows) *rows = p.rows;
+  if (cols) *cols = p.cols;
+  if (tol) *tol = t;
+  return RTM_OK;
+}
+
+extern "C" int rtm_codec_decode(rtm_ctx* ctx, const void* stream_dev, int64_t stream_bytes, float* x_dev,
+                                int64_t capacity_floats) {
+  if (!ctx || !stream_dev || !x_dev) return fail(RTM_E_INVAL, "bad arguments");
+  if (reinterpret_cast<uintptr_t>(x_dev) & 3) return fail(RTM_E_INVAL, "array must be 4-byte aligned");
+  int32_t mode = 0, count = 0, rows = 0, cols = 0;
+  double tol = 0;
+  if (int st = rtm_codec_info(ctx, stream_dev, stream_bytes, &mode, &count, &rows, &cols, &tol)) return st;
+  ZcParams p{};
+  if (int st = zc_geometry(count, rows, cols, p)) return st;
+  const int64_t n = (int64_t)count * rows * cols;
+  if (capacity_floats < n)
+    return fail(RTM_E_NOMEM, "the array holds %lld floats, the stream decodes to %lld",
+                (long long)capacity_floats, (long long)n);
+  void* scratch = arena_alloc(ctx, 64);
+  if (!scratch) return fail(RTM_E_NOMEM, "arena exhausted (codec flags)");
+  p.mode = mode;
+  p.step = 2.0 * tol;
+  p.in = static_cast<const uint32_t*>(stream_dev);
+  p.y = x_dev;
+  p.flags = static_cast<uint32_t*>(scratch);
+  p.cap_words = stream_bytes / 4;
+  hipStream_t s = ctx->stream;
+  uint32_t flags = 0;
+  hipError_t e = launch_fill_u32(p.flags, 0, 16, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[0], s);
+  if (e == hipSuccess) e = launch_zc_decode(p, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[1], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ctx->arena.release(scratch, align256(64));
+  if (e != hipSuccess) return fail(RTM_E_DEVICE, "codec decode: %s", hipGetErrorString(e));
+  ctx->zc_op = 2;
+  // payload words actually used: the chunk table's last entry is not read back,
+  // so count the stream as handed in
+  ctx->zc_bytes = (uint64_t)stream_bytes + 4 * (uint64_t)n;
+  if (flags) return fail(RTM_E_INVAL, "corrupt codec stream (widths, chunk table or length)");
+  return RTM_OK;
+}
+
 extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
   if (!ctx || !out) return fail(RTM_E_INVAL, "bad arguments");
   memset(out, 0, sizeof *out);
@@ -1789,6 +1961,15 @@ extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
       out->last_bwd_launches = ctx->ph_launches[1];
       out->last_fwd_launch_bytes = ctx->ph_bytes[0];
       out->last_bwd_launch_bytes = ctx->ph_bytes[1];
+    }
+  }
+  if (ctx->zc_op) {
+    float ms = 0;
+    if (hipEventSynchronize(ctx->zc_ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, ctx->zc_ev[0], ctx->zc_ev[1]) == hipSuccess) {
+      out->last_codec_ms = ms;
+      out->last_codec_op = ctx->zc_op;
+      out->last_codec_bytes = ctx->zc_bytes;
     }
   }
   std::lock_guard<std::mutex> lk(ctx->mu);

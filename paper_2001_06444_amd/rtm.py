@@ -18,6 +18,7 @@ STATUS = {0: "RTM_OK", -1: "RTM_E_INVAL", -2: "RTM_E_CFL", -3: "RTM_E_NOMEM", -4
 SNAP = {"fp32": 0, "bf16": 1, "fp16": 2}
 SRC_STORE, SRC_RECONSTRUCT = 0, 1
 IMG_ILLUM = 1
+CODEC_TOL, CODEC_LOSSLESS = 0, 1
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = range(5)
 JOB_ACC_STATS, JOB_ACC_STACK = 1, 2
 
@@ -71,7 +72,9 @@ class CtxStats(ctypes.Structure):
         ("queued_jobs", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("last_fwd_ms", ctypes.c_float), ("last_bwd_ms", ctypes.c_float),
         ("last_fwd_launches", ctypes.c_int32), ("last_bwd_launches", ctypes.c_int32),
-        ("last_fwd_launch_bytes", ctypes.c_uint64), ("last_bwd_launch_bytes", ctypes.c_uint64)]
+        ("last_fwd_launch_bytes", ctypes.c_uint64), ("last_bwd_launch_bytes", ctypes.c_uint64),
+        ("last_codec_ms", ctypes.c_float), ("last_codec_op", ctypes.c_int32),
+        ("last_codec_bytes", ctypes.c_uint64)]
 
 
 # exported symbols and their C signatures (argtypes, restype)
@@ -109,6 +112,12 @@ SIGNATURES = {
     "rtm_confidence_map": ([_V, _V, _V, _I32, _I32, _V], ctypes.c_int),
     "rtm_ratio_map": ([_V, _V, _V, _I32, _D, _V], ctypes.c_int),
     "rtm_laplacian_filter": ([_V, _V, _I32, _I32, _F, _F, _V], ctypes.c_int),
+    "rtm_codec_max_bytes": ([_I32, _I32, _I32], ctypes.c_int64),
+    "rtm_codec_encode": ([_V, _V, _I32, _I32, _I32, _I32, _D, _V, ctypes.c_int64,
+                          _P(ctypes.c_int64)], ctypes.c_int),
+    "rtm_codec_info": ([_V, _V, ctypes.c_int64, _P(_I32), _P(_I32), _P(_I32), _P(_I32), _P(_D)],
+                       ctypes.c_int),
+    "rtm_codec_decode": ([_V, _V, ctypes.c_int64, _V, ctypes.c_int64], ctypes.c_int),
     "rtm_ctx_stats": ([_V, _P(CtxStats)], ctypes.c_int),
 }
 
@@ -311,6 +320,48 @@ class Context:
         nz, nx = img.shape
         _check(lib().rtm_laplacian_filter(self.h, _ptr(img), nz, nx, float(dz), float(dx),
                                           _ptr(out)))
+
+    # ---- codec ----
+    def codec_max_bytes(self, count, rows, cols) -> int:
+        return int(lib().rtm_codec_max_bytes(int(count), int(rows), int(cols)))
+
+    def codec_encode(self, x, tol=None, lossless=False, out=None):
+        """Encode a float32 [rows][cols] or [count][rows][cols] device tensor.
+
+        Returns the stream as a uint8 device tensor (a view of `out` when given)."""
+        import torch
+        if x.dtype != torch.float32:
+            raise ValueError("float32 tensor expected")
+        count, rows, cols = (1, *x.shape) if x.dim() == 2 else tuple(x.shape)
+        if out is None:
+            cap = self.codec_max_bytes(count, rows, cols)
+            if cap < 0:
+                raise ValueError("shape outside the codec's limits")
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        n = ctypes.c_int64(0)
+        mode = CODEC_LOSSLESS if lossless else CODEC_TOL
+        _check(lib().rtm_codec_encode(self.h, _ptr(x), count, rows, cols, mode,
+                                      float(tol if tol is not None else 0.0), _ptr(out), out.numel(),
+                                      ctypes.byref(n)))
+        return out[: n.value]
+
+    def codec_info(self, stream):
+        m, c, r, k, t = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                         ctypes.c_double())
+        _check(lib().rtm_codec_info(self.h, _ptr(stream), stream.numel(), ctypes.byref(m),
+                                    ctypes.byref(c), ctypes.byref(r), ctypes.byref(k),
+                                    ctypes.byref(t)))
+        return {"mode": m.value, "count": c.value, "rows": r.value, "cols": k.value, "tol": t.value}
+
+    def codec_decode(self, stream, out=None):
+        """Decode a stream (uint8 device tensor) into float32 [count][rows][cols]."""
+        import torch
+        info = self.codec_info(stream)
+        shape = (info["count"], info["rows"], info["cols"])
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=stream.device)
+        _check(lib().rtm_codec_decode(self.h, _ptr(stream), stream.numel(), _ptr(out), out.numel()))
+        return out
 
     def stats(self) -> CtxStats:
         s = CtxStats()
