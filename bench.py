@@ -35,26 +35,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+STEP_SOURCES = ("paper_2001_06444_amd/csrc/rtm_kernels.hip", "paper_2001_06444_amd/csrc/rtm_device.h",
+                "paper_2001_06444_amd/csrc/rtm_internal.h")
+CODEC_SOURCES = ("paper_2001_06444_amd/csrc/rtm_codec.hip", "paper_2001_06444_amd/csrc/rtm_codec.h")
+
+
+def kernel_source_hash(sources=STEP_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in ("paper_2001_06444_amd/csrc/rtm_kernels.hip", "paper_2001_06444_amd/csrc/rtm_device.h",
-              "paper_2001_06444_amd/csrc/rtm_internal.h"):
+    for p in sources:
         h.update((ROOT / p).read_bytes())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_alg_bytes):
-    """HBM bytes per dominant-kernel launch from the committed rocprofv3
-    counter summary, or None if it is missing or was taken on other code."""
-    f = ROOT / "profiles" / "traffic_backward_step.json"
+def measured_traffic(record="traffic_backward_step.json", sources=STEP_SOURCES, key=None):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary, or None if it is missing or was taken on other code."""
+    f = ROOT / "profiles" / record
     if not f.exists():
         return None
     try:
         rec = json.loads(f.read_text())
     except ValueError:
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(sources):
         return None
+    if key is not None:
+        rec = rec.get("kernels", {}).get(key, {})
     return rec.get("hbm_bytes_per_launch")
 
 
@@ -91,7 +97,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["survey", "ensemble", "serve", "small", "born"],
+    ap.add_argument("--workload", choices=["survey", "ensemble", "serve", "small", "born", "codec"],
                     default="survey")
     ap.add_argument("--shots", type=int, default=100)
     ap.add_argument("--nt", type=int, default=None, help="default: 4000 survey, 3000 ensemble")
@@ -101,7 +107,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device tensor copy (reference dispatch "
                          "for the HBM byte counters)")
-    ap.add_argument("--realizations", type=int, default=64, help="ensemble workload")
+    ap.add_argument("--realizations", type=int, default=64, help="ensemble / codec workload")
+    ap.add_argument("--seismograms", type=int, default=16, help="codec workload")
     ap.add_argument("--serve-jobs", type=int, default=300, help="serve workload: timed jobs")
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: jobs/s")
@@ -127,7 +134,7 @@ def main():
         del src_t, dst_t
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
     out = {"survey": run_survey, "ensemble": run_ensemble, "serve": run_serve,
-           "small": run_small, "born": run_born}[args.workload](args)
+           "small": run_small, "born": run_born, "codec": run_codec}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 
@@ -269,7 +276,7 @@ def run_survey(args):
         "batched_vs_plain": (images_per_s / plain["images_per_s"]) if plain else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(s1.last_bwd_launch_bytes),
+                     "traffic": measured_traffic(),
                      "kernel": "k_step<TZ,2> backward (receiver step + reconstruct + imaging)",
                      "alg_bytes_per_launch": s1.last_bwd_launch_bytes,
                      "launch_us": bwd_launch_ms * 1e3,
@@ -599,6 +606,133 @@ def run_born(args):
                            "note": "events around whole calls, launch gaps included; one shot's "
                                    "working set fits the 256 MB Infinity Cache"}})
     return out
+
+CODEC_SETTINGS = {"velocity": (1e-4, 1e-1, None), "image": (1e-4, 1e-1, None), "seismogram": (1e-4, None)}
+
+
+def _codec_label(kind, tol):
+    return f"{kind} {'lossless' if tol is None else f'tol {tol:g}'}"
+
+
+def codec_cpu_baseline(banks, budget_s=12.0):
+    """The codec oracle (NumPy) on the first arrays of each bank, every setting,
+    until the time budget is spent."""
+    import numpy as np
+
+    from oracle import codec as zc
+
+    done_bytes, el, arrays = 0, 0.0, []
+    for i in range(max(len(b) for b in banks.values())):
+        for kind, bank in banks.items():
+            if i >= len(bank) or el >= budget_s:
+                continue
+            for tol in CODEC_SETTINGS[kind]:
+                t0 = time.perf_counter()
+                w = zc.encode(bank[i], tol=tol) if tol else zc.encode(bank[i], mode=zc.MODE_LOSSLESS)
+                zc.decode(w)
+                el += time.perf_counter() - t0
+                done_bytes += 2 * bank[i].nbytes
+            arrays.append(f"{kind}[{i}]")
+        if el >= budget_s:
+            break
+    return {"value": done_bytes / el / 1e9, "unit": "GB/s (uncompressed bytes encoded + decoded)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{len(arrays)} arrays ({', '.join(arrays[:6])}{', ...' if len(arrays) > 6 else ''}) "
+                      f"in every setting of their bank, encode + decode, {el:.1f} s"}
+
+
+def run_codec(args):
+    """Compression stage (Sec. 3 / Sec. 4.2): encode and decode banks of
+    velocity samples, migrated images and seismograms at the paper's error
+    bounds (1e-4, 1e-1) and losslessly.  One step = every bank in every
+    setting, encoded then decoded."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06444_amd import inputs, rtm
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    banks = {"velocity": inputs.velocity_bank(args.realizations),
+             "image": inputs.image_bank(args.realizations),
+             "seismogram": inputs.seismogram_bank(args.seismograms)}
+    log(f"[bench] codec inputs in {time.perf_counter() - t0:.1f} s: " +
+        ", ".join(f"{k} {tuple(v.shape)}" for k, v in banks.items()))
+    ctx = rtm.Context(0, arena_bytes=64 << 20)
+    xs = {k: torch.as_tensor(v, device=dev) for k, v in banks.items()}
+    bufs = {k: torch.empty(ctx.codec_max_bytes(*v.shape), dtype=torch.uint8, device=dev) for k, v in banks.items()}
+    outs = {k: torch.empty_like(v) for k, v in xs.items()}
+    runs = {}
+
+    def step(keep):
+        for kind, x in xs.items():
+            for tol in CODEC_SETTINGS[kind]:
+                s = ctx.codec_encode(x, tol=tol, lossless=tol is None, out=bufs[kind])
+                st = ctx.stats()
+                enc = (st.last_codec_ms, st.last_codec_bytes)
+                ctx.codec_decode(s, out=outs[kind])
+                st = ctx.stats()
+                dec = (st.last_codec_ms, st.last_codec_bytes)
+                if keep:
+                    r = runs.setdefault(_codec_label(kind, tol), {"enc_ms": [], "dec_ms": [], "bytes_in": x.numel() * 4,
+                                                                  "stream_bytes": s.numel(), "enc_alg_bytes": enc[1],
+                                                                  "dec_alg_bytes": dec[1]})
+                    r["enc_ms"].append(enc[0])
+                    r["dec_ms"].append(dec[0])
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    step_bytes = sum(2 * x.numel() * 4 * len(CODEC_SETTINGS[k]) for k, x in xs.items())
+    # the round trip is exact for lossless and within the bound otherwise
+    for kind, x in xs.items():
+        y = ctx.codec_decode(ctx.codec_encode(x, tol=1e-4, out=bufs[kind]), out=outs[kind])
+        err = (y.double() - x.double()).abs() - (1e-4 * (1 + 2.0 ** -26) + y.double().abs() * 2.0 ** -24)
+        assert float(err.max()) <= 0.0, f"{kind}: error bound violated"
+    table, dominant = {}, None
+    for label, r in runs.items():
+        e_ms, d_ms = float(np.median(r["enc_ms"])), float(np.median(r["dec_ms"]))
+        row = {"ratio": r["bytes_in"] / r["stream_bytes"], "stream_MB": r["stream_bytes"] / 1e6,
+               "encode_us": e_ms * 1e3, "decode_us": d_ms * 1e3,
+               "encode_GBps_alg": r["enc_alg_bytes"] / (e_ms * 1e-3) / 1e9,
+               "decode_GBps_alg": r["dec_alg_bytes"] / (d_ms * 1e-3) / 1e9}
+        table[label] = row
+        for op, ms, ab in (("encode", e_ms, r["enc_alg_bytes"]), ("decode", d_ms, r["dec_alg_bytes"])):
+            if dominant is None or ms > dominant[1]:
+                dominant = (f"{op} {label}", ms, ab, op, label)
+        log(f"[bench] {label:24s} ratio {row['ratio']:6.2f}  encode {row['encode_us']:8.1f} us "
+            f"{row['encode_GBps_alg']:7.0f} GB/s  decode {row['decode_us']:8.1f} us {row['decode_GBps_alg']:7.0f} GB/s")
+    name, ms, ab, op, label = dominant
+    achieved = ab / (ms * 1e-3) / 1e9
+    traffic = measured_traffic("traffic_codec.json", CODEC_SOURCES, key=f"{op} {label}")
+    cpu = None if args.no_cpu_baseline else codec_cpu_baseline(
+        {k: v[: 4] for k, v in banks.items()})
+    ctx.close()
+    out = _base_record(args, step_bytes / (el / args.steps) / 1e9, el * 1e3 / args.steps, {
+        "workload": f"compression stage: {args.realizations} velocity samples and {args.realizations} images "
+                    f"351x1701, {args.seismograms} seismograms 4000x1701; fixed accuracy 1e-4 and 1e-1 (velocity, "
+                    f"image), 1e-4 (seismogram), lossless; encode + decode per step",
+        "path": "rtm_codec_encode / rtm_codec_decode, one call per bank and setting"},
+        unit="GB/s (uncompressed bytes encoded + decoded)")
+    out["metric"] = "codec throughput: uncompressed GB/s encoded + decoded; compression ratios"
+    out["dtype"] = "f32 in, int32 transform"
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": None if traffic is None else traffic * 1.0,
+                       "kernel": f"k_zc_{op} ({label})",
+                       "alg_bytes_per_launch": ab,
+                       "note": "algorithmic bytes: 4 B per value plus the stream length; HIP events "
+                               "around the launch on the library's stream"}
+    out["codec"] = table
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    return out
+
 
 if __name__ == "__main__":
     main()

@@ -16,7 +16,10 @@
 //
 // Launch shape: one 64-lane wavefront handles 64 blocks, one block per lane,
 // with the block's 64 values in registers; a 256-thread workgroup is one
-// chunk of 256 blocks.  The encoder finds each chunk's payload offset with a
+// chunk of 256 blocks.  Array rows and payload words move between HBM and
+// a 16 KB LDS region per wave in runs of 64 consecutive 4-byte words, so
+// every global load and store is coalesced; the per-lane block layout exists
+// only in LDS and registers.  The encoder finds each chunk's payload offset with a
 // single-pass decoupled look-back over the chunks (chunk order taken from an
 // atomic ticket, so every chunk waits only on chunks that are already
 // running); the wait is bounded and reports an error instead of hanging.
@@ -33,6 +36,25 @@ constexpr uint64_t kAgg = 1ull << 62;   // status: chunk aggregate published
 constexpr uint64_t kInc = 2ull << 62;   // status: inclusive prefix published
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr int kSpinLimit = 1 << 22;
+
+#ifndef RTM_ZC_NT_LOAD
+#define RTM_ZC_NT_LOAD 0
+#endif
+#ifndef RTM_ZC_NT_STORE
+#define RTM_ZC_NT_STORE 0
+#endif
+template <typename T>
+__device__ inline T ld(const T* p) {
+  if (RTM_ZC_NT_LOAD) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <typename T>
+__device__ inline void st(T v, T* p) {
+  if (RTM_ZC_NT_STORE)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
 
 // sub-band of position (z, x) of the 8 x 8 coefficient layout
 __host__ __device__ constexpr int band_of(int z, int x) {
@@ -131,36 +153,76 @@ __device__ inline BlockPos block_pos(int32_t b, int32_t bz, int32_t bx) {
 
 }  // namespace
 
+// Per-wave LDS region: 64 blocks x 64 values, or up to 64 x 64 payload words.
+// Values of block `blk` sit at blk * 64 + (c ^ (blk & 31)): a lane reading its
+// own block's value c and a wave storing a row segment both avoid bank
+// conflicts.
+constexpr int kWaveWords = 64 * 64;
+__device__ inline int swz(int blk, int c) { return blk * 64 + (c ^ (blk & 31)); }
+
+// Element offsets of the eight blocks a lane touches in the wave's
+// cooperative row loads / stores: block blk = 8 k + lane / 8, k = 0..7.
+struct WaveBlocks {
+  int64_t img[8];
+  int32_t z0[8], x0[8];
+  bool live[8];
+};
+__device__ inline void wave_blocks(const ZcParams& p, int32_t b0, int lane, WaveBlocks& wb) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int32_t b = b0 + 8 * k + (lane >> 3);
+    wb.live[k] = b < p.nblocks;
+    const BlockPos bp = block_pos(min(b, p.nblocks - 1), p.bz, p.bx);
+    wb.img[k] = (int64_t)bp.a * p.rows * p.cols;
+    wb.z0[k] = bp.z0;
+    wb.x0[k] = bp.x0;
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kZcChunk) void k_zc_encode(ZcParams p) {
+  __shared__ uint32_t s_buf[4][kWaveWords];
   __shared__ uint32_t s_scan[4];
   __shared__ uint32_t s_chunk;
   __shared__ uint64_t s_excl;
   if (threadIdx.x == 0) s_chunk = atomicAdd(p.ticket, 1u);
   __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t* buf = s_buf[wave];
   const int32_t chunk = (int32_t)s_chunk;
-  const int32_t b = chunk * kZcChunk + (int32_t)threadIdx.x;
+  const int32_t b0 = chunk * kZcChunk + wave * 64;  // first block of this wave
+  const int32_t b = b0 + lane;                       // this lane's block
   const bool active = b < p.nblocks;
-  const BlockPos bp = block_pos(active ? b : p.nblocks - 1, p.bz, p.bx);
-  const float* __restrict__ img = p.x + (int64_t)bp.a * p.rows * p.cols;
 
-  // values -> integers
+  // rows of the wave's 64 blocks -> LDS, 64 consecutive floats per load
+  {
+    WaveBlocks wb;
+    wave_blocks(p, b0, lane, wb);
+    const int j = lane & 7;
+#pragma unroll
+    for (int i = 0; i < kB; ++i)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int64_t off = wb.img[k] + (int64_t)min(wb.z0[k] + i, p.rows - 1) * p.cols +
+                            min(wb.x0[k] + j, p.cols - 1);
+        buf[swz(8 * k + (lane >> 3), i * kB + j)] = __float_as_uint(ld(p.x + off));
+      }
+  }
+  __syncthreads();
+
+  // this lane's block -> integers -> transform
   int32_t v[64];
   bool bad = false;
 #pragma unroll
-  for (int i = 0; i < kB; ++i) {
-    const float* row = img + (int64_t)min(bp.z0 + i, p.rows - 1) * p.cols;
-#pragma unroll
-    for (int j = 0; j < kB; ++j) {
-      const float f = __builtin_nontemporal_load(row + min(bp.x0 + j, p.cols - 1));
-      if (MODE == 0) {
-        const double q = __builtin_rint((double)f * p.r);
-        const bool ok = fabs(q) <= 2147483647.0;
-        bad |= !ok;
-        v[i * kB + j] = ok ? (int32_t)q : 0;
-      } else {
-        v[i * kB + j] = float_key(f);
-      }
+  for (int c = 0; c < 64; ++c) {
+    const float f = __uint_as_float(buf[swz(lane, c)]);
+    if (MODE == 0) {
+      const double q = __builtin_rint((double)f * p.r);
+      const bool ok = fabs(q) <= 2147483647.0;
+      bad |= !ok;
+      v[c] = ok ? (int32_t)q : 0;
+    } else {
+      v[c] = float_key(f);
     }
   }
   lift_level<8>(v);
@@ -184,72 +246,98 @@ __global__ __launch_bounds__(kZcChunk) void k_zc_encode(ZcParams p) {
 
   uint32_t agg;
   const uint32_t local = wg_exclusive_scan(nwords, s_scan, &agg);
+  const uint32_t wave_base = __shfl(local, 0, 64);
+  const uint32_t wave_total = __shfl(local + nwords, 63, 64) - wave_base;
 
-  // decoupled look-back: chunk prefix from the chunks before this one
-  if (threadIdx.x == 0) {
+  // decoupled look-back, one wave wide: wave 0 reads the status of up to 64
+  // preceding chunks per round, sums them down to the nearest one whose
+  // inclusive prefix is published, and repeats further back if none is
+  if (wave == 0) {
+    if (lane == 0)
+      __hip_atomic_store(p.status + chunk, (chunk == 0 ? kInc : kAgg) | agg, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
-    if (chunk == 0) {
-      __hip_atomic_store(p.status, kInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(p.status + chunk, kAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int j = chunk - 1, spins = 0;
-      while (j >= 0) {
-        const uint64_t s = __hip_atomic_load(p.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((s >> 62) == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(p.flags, kZcSpin);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+    int32_t end_j = chunk;  // chunks [0, end_j) are still to be summed
+    int spins = 0;
+    while (end_j > 0) {
+      const int32_t j = end_j - 1 - lane;
+      const uint64_t st = j >= 0 ? __hip_atomic_load(p.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : kInc;  // before chunk 0: an inclusive prefix of 0
+      const uint64_t inc = __ballot((st >> 62) == 2);
+      const int first = inc ? __builtin_ctzll(inc) : 64;  // nearest published prefix
+      const uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+      if (__ballot((st >> 62) == 0) & upto) {  // a chunk in range has published nothing yet
+        if (++spins > kSpinLimit) {
+          if (lane == 0) atomicOr(p.flags, kZcSpin);
+          break;
         }
-        excl += s & kValMask;
-        if ((s >> 62) == 2) break;
-        --j;
+        __builtin_amdgcn_s_sleep(1);
+        continue;
       }
-      __hip_atomic_store(p.status + chunk, kInc | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_excl = excl;
-    p.out[8 + chunk] = (uint32_t)excl;
-    if (chunk == p.nchunks - 1) {
-      p.out[8 + p.nchunks] = (uint32_t)(excl + agg);
-      p.result[0] = (uint32_t)(excl + agg);
-    }
-    if (chunk == 0) {
+      uint64_t part = lane <= first ? (st & kValMask) : 0ull;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) p.out[k] = p.head[k];
+      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      excl += part;
+      if (first < 64) break;
+      end_j -= 64;
     }
-    if ((int64_t)(p.pay_base + excl + agg) > p.cap_words) atomicOr(p.flags, kZcCapacity);
+    if (lane == 0) {
+      if (chunk > 0)
+        __hip_atomic_store(p.status + chunk, kInc | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = excl;
+      p.out[8 + chunk] = (uint32_t)excl;
+      if (chunk == p.nchunks - 1) {
+        p.out[8 + p.nchunks] = (uint32_t)(excl + agg);
+        p.result[0] = (uint32_t)(excl + agg);
+      }
+      if (chunk == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p.out[k] = p.head[k];
+      }
+      if ((int64_t)(p.pay_base + excl + agg) > p.cap_words) atomicOr(p.flags, kZcCapacity);
+    }
+  }
+  __syncthreads();  // also: every lane has read its values out of buf
+  if (active) p.out[p.hdr_base + b] = header;
+
+  // pack this lane's coefficients into the wave's LDS region (lanes past the
+  // last block hold a copy of it and own no words: they write nothing)
+  if (active) {
+    uint32_t wo = local - wave_base;
+    uint64_t acc = 0;
+    int nb = 0;
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+      const int wc = w[band_of(c / kB, c % kB)];
+      acc |= (uint64_t)u[c] << nb;
+      nb += wc;
+      if (nb >= 32) {
+        buf[wo++] = (uint32_t)acc;
+        acc >>= 32;
+        nb -= 32;
+      }
+    }
+    if (nb > 0) buf[wo] = (uint32_t)acc;
   }
   __syncthreads();
-  if (!active) return;
-  p.out[p.hdr_base + b] = header;
 
-  // pack the coefficients at the block's final payload position
-  int64_t wp = p.pay_base + (int64_t)s_excl + local;
-  const int64_t cap = p.cap_words;
-  uint64_t acc = 0;
-  int nb = 0;
-#pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    const int wc = w[band_of(c / kB, c % kB)];
-    acc |= (uint64_t)u[c] << nb;
-    nb += wc;
-    if (nb >= 32) {
-      if (wp < cap) p.out[wp] = (uint32_t)acc;
-      ++wp;
-      acc >>= 32;
-      nb -= 32;
-    }
+  // the wave's payload words -> their final place, 64 consecutive words per store
+  const int64_t dst0 = p.pay_base + (int64_t)s_excl + wave_base;
+  for (uint32_t k = lane; k < wave_total; k += 64) {
+    const int64_t d = dst0 + k;
+    if (d < p.cap_words) st(buf[k], p.out + d);
   }
-  if (nb > 0 && wp < cap) p.out[wp] = (uint32_t)acc;
 }
 
 template <int MODE>
 __global__ __launch_bounds__(kZcChunk) void k_zc_decode(ZcParams p) {
+  __shared__ uint32_t s_buf[4][kWaveWords];
   __shared__ uint32_t s_scan[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t* buf = s_buf[wave];
   const int32_t chunk = blockIdx.x;
-  const int32_t b = chunk * kZcChunk + (int32_t)threadIdx.x;
+  const int32_t b0 = chunk * kZcChunk + wave * 64;
+  const int32_t b = b0 + lane;
   const bool active = b < p.nblocks;
   const uint32_t* __restrict__ in = p.in;
   const uint32_t header = active ? in[p.hdr_base + b] : 0u;
@@ -261,52 +349,73 @@ __global__ __launch_bounds__(kZcChunk) void k_zc_decode(ZcParams p) {
     bad |= wg > 32;
     w[g] = min(wg, 32);
   }
+  if (bad) atomicOr(p.flags, kZcCorrupt);
   const uint32_t bits = 4u * w[0] + 12u * w[1] + 16u * (w[2] + w[3] + w[4]);
   const uint32_t nwords = (bits + 31u) >> 5;
   uint32_t agg;
   const uint32_t local = wg_exclusive_scan(nwords, s_scan, &agg);
+  const uint32_t wave_base = __shfl(local, 0, 64);
+  const uint32_t wave_total = __shfl(local + nwords, 63, 64) - wave_base;
   const uint32_t c0 = in[8 + chunk], c1 = in[8 + chunk + 1];
   if (threadIdx.x == 0 && (c1 < c0 || c1 - c0 != agg)) atomicOr(p.flags, kZcCorrupt);
-  if (!active) return;
-  if (bad) atomicOr(p.flags, kZcCorrupt);
 
-  int64_t wp = p.pay_base + (int64_t)c0 + local;
-  const int64_t limit = p.cap_words;  // words of the stream the caller handed in
-  uint64_t buf = 0;
-  int have = 0;
-  int32_t v[64];
-#pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    const int wc = w[band_of(c / kB, c % kB)];
-    if (have < wc) {
-      const uint32_t word = (wp < limit) ? in[wp] : 0u;
-      ++wp;
-      buf |= (uint64_t)word << have;
-      have += 32;
-    }
-    const uint32_t uc = (uint32_t)(buf & ((1ull << wc) - 1ull));
-    buf >>= wc;
-    have -= wc;
-    v[c] = unzigzag(uc);
+  // the wave's payload -> LDS, 64 consecutive words per load
+  const int64_t src0 = p.pay_base + (int64_t)c0 + wave_base;
+  for (uint32_t k = lane; k < wave_total; k += 64) {
+    const int64_t sidx = src0 + k;
+    buf[k] = sidx < p.cap_words ? ld(in + sidx) : 0u;
   }
-  if (wp > limit) atomicOr(p.flags, kZcCorrupt);
+  if (lane == 0 && src0 + wave_total > p.cap_words) atomicOr(p.flags, kZcCorrupt);
+  __syncthreads();
+
+  // unpack this lane's block (its words are buf[local - wave_base ...])
+  int32_t v[64];
+  {
+    // the block's words are buf[local - wave_base, + nwords); one word is
+    // always read ahead so the LDS latency overlaps the unpacking
+    uint32_t rp = local - wave_base;
+    const uint32_t rend = rp + nwords;
+    uint32_t next = nwords ? buf[rp] : 0u;
+    uint64_t acc = 0;
+    int have = 0;
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+      const int wc = w[band_of(c / kB, c % kB)];
+      if (have < wc) {
+        acc |= (uint64_t)next << have;
+        have += 32;
+        ++rp;
+        next = rp < rend ? buf[rp] : 0u;
+      }
+      const uint32_t uc = (uint32_t)(acc & ((1ull << wc) - 1ull));
+      acc >>= wc;
+      have -= wc;
+      v[c] = unzigzag(uc);
+    }
+  }
   unlift_level<2>(v);
   unlift_level<4>(v);
   unlift_level<8>(v);
-
-  const BlockPos bp = block_pos(b, p.bz, p.bx);
-  float* __restrict__ img = p.y + (int64_t)bp.a * p.rows * p.cols;
+  __syncthreads();  // every lane has read its payload out of buf
 #pragma unroll
-  for (int i = 0; i < kB; ++i) {
-    float* row = img + (int64_t)(bp.z0 + i) * p.cols;
-#pragma unroll
-    for (int j = 0; j < kB; ++j) {
-      if (bp.z0 + i < p.rows && bp.x0 + j < p.cols) {
-        const float f = MODE == 0 ? (float)((double)v[i * kB + j] * p.step) : key_float(v[i * kB + j]);
-        __builtin_nontemporal_store(f, row + bp.x0 + j);
-      }
-    }
+  for (int c = 0; c < 64; ++c) {
+    const float f = MODE == 0 ? (float)((double)v[c] * p.step) : key_float(v[c]);
+    buf[swz(lane, c)] = __float_as_uint(f);
   }
+  __syncthreads();
+
+  // rows of the wave's blocks -> the array, 64 consecutive floats per store
+  WaveBlocks wb;
+  wave_blocks(p, b0, lane, wb);
+  const int j = lane & 7;
+#pragma unroll
+  for (int i = 0; i < kB; ++i)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int32_t z = wb.z0[k] + i, x = wb.x0[k] + j;
+      if (wb.live[k] && z < p.rows && x < p.cols)
+        st(__uint_as_float(buf[swz(8 * k + (lane >> 3), i * kB + j)]), p.y + wb.img[k] + (int64_t)z * p.cols + x);
+    }
 }
 
 hipError_t launch_zc_encode(const ZcParams& p, hipStream_t s) {

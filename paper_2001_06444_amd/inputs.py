@@ -258,15 +258,7 @@ def velocity_bank(n: int, nz: int = 351, nx: int = 1701, h: float = 10.0) -> np.
     return np.stack([realization(r, base, h) for r in range(n)]).astype(np.float32)
 
 
-def image_like(seed: int = 0, nz: int = 351, nx: int = 1701, h: float = 10.0, fp: float = 15.0,
-               v_ref: float = 2500.0, noise: float = 0.02) -> np.ndarray:
-    """Stand-in for a migrated image [nz][nx] float32, peak amplitude about 1.
-
-    The faulted-layer model's reflectivity (relative contrast of log velocity
-    between adjacent rows) convolved along depth with a Ricker pulse whose
-    depth wavelength is v_ref / fp, plus white noise (default_rng(seed)) of
-    `noise` times the peak, and a smooth low-frequency background like the
-    artefacts of an unfiltered stack."""
+def _image_clean(nz: int, nx: int, h: float, fp: float, v_ref: float) -> np.ndarray:
     v = faulted_layers(nz, nx, h)
     refl = np.zeros((nz, nx))
     refl[1:] = np.diff(np.log(v), axis=0)
@@ -276,11 +268,28 @@ def image_like(seed: int = 0, nz: int = 351, nx: int = 1701, h: float = 10.0, fp
     pulse = (1.0 - 2.0 * a) * np.exp(-a)
     img = np.apply_along_axis(lambda c: np.convolve(c, pulse, mode="same"), 0, refl)
     img /= np.abs(img).max()
-    rng = np.random.default_rng(seed)
-    img += noise * rng.standard_normal((nz, nx))
     zc, xc = np.mgrid[0:nz, 0:nx]
-    img += 0.1 * np.exp(-((zc - 20.0) ** 2) / (2 * 30.0 ** 2)) * np.cos(2 * math.pi * xc / 400.0)
-    return img.astype(np.float32)
+    return img + 0.1 * np.exp(-((zc - 20.0) ** 2) / (2 * 30.0 ** 2)) * np.cos(2 * math.pi * xc / 400.0)
+
+
+def image_like(seed: int = 0, nz: int = 351, nx: int = 1701, h: float = 10.0, fp: float = 15.0,
+               v_ref: float = 2500.0, noise: float = 0.02) -> np.ndarray:
+    """Stand-in for a migrated image [nz][nx] float32, peak amplitude about 1.
+
+    The faulted-layer model's reflectivity (relative contrast of log velocity
+    between adjacent rows) convolved along depth with a Ricker pulse whose
+    depth wavelength is v_ref / fp, a smooth shallow background like the
+    low-frequency artefacts of an unfiltered stack, and white noise
+    (default_rng(seed)) of `noise` times the reflectivity peak."""
+    img = _image_clean(nz, nx, h, fp, v_ref)
+    return (img + noise * np.random.default_rng(seed).standard_normal((nz, nx))).astype(np.float32)
+
+
+def image_bank(n: int, nz: int = 351, nx: int = 1701, h: float = 10.0) -> np.ndarray:
+    """n images [n][nz][nx] float32: image_like(s) for s = 0..n-1."""
+    clean = _image_clean(nz, nx, h, 15.0, 2500.0)
+    return np.stack([(clean + 0.02 * np.random.default_rng(s).standard_normal((nz, nx)))
+                     for s in range(n)]).astype(np.float32)
 
 
 def seismogram_like(seed: int = 0, nt: int = 4000, nrec: int = 1701, dt: float = 1e-3,
@@ -306,3 +315,8 @@ def seismogram_like(seed: int = 0, nt: int = 4000, nrec: int = 1701, dt: float =
     rec /= np.abs(rec).max()
     rec += noise * rng.standard_normal((nt, nrec))
     return rec.astype(np.float32)
+
+
+def seismogram_bank(n: int, nt: int = 4000, nrec: int = 1701) -> np.ndarray:
+    """n shot records [n][nt][nrec] float32: seismogram_like(s) for s = 0..n-1."""
+    return np.stack([seismogram_like(s, nt, nrec) for s in range(n)])
