@@ -16,10 +16,11 @@
 //
 // Launch shape: one 64-lane wavefront handles 64 blocks, one block per lane,
 // with the block's 64 values in registers; a 256-thread workgroup is one
-// chunk of 256 blocks.  Array rows and payload words move between HBM and
-// a 16 KB LDS region per wave in runs of 64 consecutive 4-byte words, so
-// every global load and store is coalesced; the per-lane block layout exists
-// only in LDS and registers.  The encoder finds each chunk's payload offset with a
+// chunk of 256 blocks.  Array rows move between HBM and a row buffer in LDS
+// in runs of 64 consecutive floats, and payload words through the same LDS
+// area in runs of 64 consecutive words, so every global load and store is
+// coalesced (a decoder wave whose payload exceeds the area reads it from
+// the stream directly).  The encoder finds each chunk's payload offset with a
 // single-pass decoupled look-back over the chunks (chunk order taken from an
 // atomic ticket, so every chunk waits only on chunks that are already
 // running); the wait is bounded and reports an error instead of hanging.
@@ -59,6 +60,14 @@ __device__ inline void st(T v, T* p) {
 // sub-band of position (z, x) of the 8 x 8 coefficient layout
 __host__ __device__ constexpr int band_of(int z, int x) {
   return (z < 2 && x < 2) ? 0 : (z < 4 && x < 4) ? 1 : (z < 4) ? 2 : (x < 4) ? 3 : 4;
+}
+
+// number of positions before c (row-major) that belong to sub-band g: the bit
+// offset of coefficient c in its block is sum_g count_before(c, g) * w_g
+__host__ __device__ constexpr int count_before(int c, int g) {
+  int n = 0;
+  for (int i = 0; i < c; ++i) n += band_of(i / 8, i % 8) == g ? 1 : 0;
+  return n;
 }
 
 __device__ inline int32_t wsub(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
@@ -153,15 +162,20 @@ __device__ inline BlockPos block_pos(int32_t b, int32_t bz, int32_t bx) {
 
 }  // namespace
 
-// Per-wave LDS region: 64 blocks x 64 values, or up to 64 x 64 payload words.
-// Values of block `blk` sit at blk * 64 + (c ^ (blk & 31)): a lane reading its
-// own block's value c and a wave storing a row segment both avoid bank
-// conflicts.
-constexpr int kWaveWords = 64 * 64;
-__device__ inline int swz(int blk, int c) { return blk * 64 + (c ^ (blk & 31)); }
+// Array rows move through a 512-word LDS row buffer per wave: one row of
+// the wave's 64 blocks (64 x 8 consecutive floats when the blocks share a
+// block row).  Element m of the buffer is column m % 8 of block m / 8, so the
+// wave's global loads and stores of a row touch 64 consecutive floats per
+// instruction and a lane finds its block's eight values at [8 lane, 8 lane + 8).
+constexpr int kRowWords = 64 * kB;
+// Each wave owns kStageWords of LDS: its row buffer while array rows move,
+// and the staging area of its payload words.  Three 256-thread workgroups
+// (the register limit) fit the 160 KB of LDS per CU.
+constexpr int kStageWords = 3328;
+static_assert(kStageWords >= kRowWords, "the LDS area must hold one row of the wave's blocks");
 
 // Element offsets of the eight blocks a lane touches in the wave's
-// cooperative row loads / stores: block blk = 8 k + lane / 8, k = 0..7.
+// cooperative row loads / stores: block 8 k + lane / 8, k = 0..7.
 struct WaveBlocks {
   int64_t img[8];
   int32_t z0[8], x0[8];
@@ -180,49 +194,60 @@ __device__ inline void wave_blocks(const ZcParams& p, int32_t b0, int lane, Wave
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kZcChunk) void k_zc_encode(ZcParams p) {
-  __shared__ uint32_t s_buf[4][kWaveWords];
+__global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
+  __shared__ __attribute__((aligned(16))) uint32_t s_stage[4][kStageWords];
   __shared__ uint32_t s_scan[4];
+  __shared__ uint32_t s_rounds[4];
   __shared__ uint32_t s_chunk;
   __shared__ uint64_t s_excl;
   if (threadIdx.x == 0) s_chunk = atomicAdd(p.ticket, 1u);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t* buf = s_buf[wave];
+  uint32_t* row = s_stage[wave];
   const int32_t chunk = (int32_t)s_chunk;
   const int32_t b0 = chunk * kZcChunk + wave * 64;  // first block of this wave
   const int32_t b = b0 + lane;                       // this lane's block
   const bool active = b < p.nblocks;
 
-  // rows of the wave's 64 blocks -> LDS, 64 consecutive floats per load
-  {
-    WaveBlocks wb;
-    wave_blocks(p, b0, lane, wb);
-    const int j = lane & 7;
-#pragma unroll
-    for (int i = 0; i < kB; ++i)
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int64_t off = wb.img[k] + (int64_t)min(wb.z0[k] + i, p.rows - 1) * p.cols +
-                            min(wb.x0[k] + j, p.cols - 1);
-        buf[swz(8 * k + (lane >> 3), i * kB + j)] = __float_as_uint(ld(p.x + off));
-      }
-  }
-  __syncthreads();
-
-  // this lane's block -> integers -> transform
+  // rows of the wave's 64 blocks, one at a time, into this lane's block values
   int32_t v[64];
   bool bad = false;
+  {
+    // all 64 loads are issued before the first row goes through LDS, so the
+    // workgroup waits for memory once
+    uint32_t lv[kB][8];
+    {
+      WaveBlocks wb;
+      wave_blocks(p, b0, lane, wb);
+      const int j = lane & 7;
 #pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    const float f = __uint_as_float(buf[swz(lane, c)]);
-    if (MODE == 0) {
-      const double q = __builtin_rint((double)f * p.r);
-      const bool ok = fabs(q) <= 2147483647.0;
-      bad |= !ok;
-      v[c] = ok ? (int32_t)q : 0;
-    } else {
-      v[c] = float_key(f);
+      for (int i = 0; i < kB; ++i)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          lv[i][k] = __float_as_uint(ld(p.x + wb.img[k] + (int64_t)min(wb.z0[k] + i, p.rows - 1) * p.cols +
+                                        min(wb.x0[k] + j, p.cols - 1)));
+    }
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) row[64 * k + lane] = lv[i][k];
+      __syncthreads();
+      const uint4 r0 = reinterpret_cast<const uint4*>(row)[2 * lane];
+      const uint4 r1 = reinterpret_cast<const uint4*>(row)[2 * lane + 1];
+      const uint32_t e[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+      for (int jj = 0; jj < kB; ++jj) {
+        const float f = __uint_as_float(e[jj]);
+        if (MODE == 0) {
+          const double q = __builtin_rint((double)f * p.r);
+          const bool ok = fabs(q) <= 2147483647.0;
+          bad |= !ok;
+          v[i * kB + jj] = ok ? (int32_t)q : 0;
+        } else {
+          v[i * kB + jj] = float_key(f);
+        }
+      }
+      __syncthreads();
     }
   }
   lift_level<8>(v);
@@ -248,6 +273,8 @@ __global__ __launch_bounds__(kZcChunk) void k_zc_encode(ZcParams p) {
   const uint32_t local = wg_exclusive_scan(nwords, s_scan, &agg);
   const uint32_t wave_base = __shfl(local, 0, 64);
   const uint32_t wave_total = __shfl(local + nwords, 63, 64) - wave_base;
+  const uint32_t my_rounds = (wave_total + kStageWords - 1) / kStageWords;
+  if (lane == 0) s_rounds[wave] = my_rounds;
 
   // decoupled look-back, one wave wide: wave 0 reads the status of up to 64
   // preceding chunks per round, sums them down to the nearest one whose
@@ -297,44 +324,71 @@ __global__ __launch_bounds__(kZcChunk) void k_zc_encode(ZcParams p) {
       if ((int64_t)(p.pay_base + excl + agg) > p.cap_words) atomicOr(p.flags, kZcCapacity);
     }
   }
-  __syncthreads();  // also: every lane has read its values out of buf
+  __syncthreads();
   if (active) p.out[p.hdr_base + b] = header;
+  const uint32_t rounds = max(max(s_rounds[0], s_rounds[1]), max(s_rounds[2], s_rounds[3]));
 
-  // pack this lane's coefficients into the wave's LDS region (lanes past the
-  // last block hold a copy of it and own no words: they write nothing)
-  if (active) {
-    uint32_t wo = local - wave_base;
-    uint64_t acc = 0;
-    int nb = 0;
+  // payload words: packed into the wave's LDS area kStageWords at a time
+  // (more than one round only for nearly incompressible blocks), then
+  // stored 64 consecutive words per instruction
+  const int64_t dst0 = p.pay_base + (int64_t)s_excl + wave_base;
+  const uint32_t my0 = local - wave_base;  // this block's first word, wave-relative
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t w0 = r * kStageWords, w1 = w0 + kStageWords;
+    if (active && r < my_rounds && my0 < w1 && my0 + nwords > w0) {
+      uint32_t wo = my0;
+      uint64_t acc = 0;
+      int nb = 0;
 #pragma unroll
-    for (int c = 0; c < 64; ++c) {
-      const int wc = w[band_of(c / kB, c % kB)];
-      acc |= (uint64_t)u[c] << nb;
-      nb += wc;
-      if (nb >= 32) {
-        buf[wo++] = (uint32_t)acc;
-        acc >>= 32;
-        nb -= 32;
+      for (int c = 0; c < 64; ++c) {
+        const int wc = w[band_of(c / kB, c % kB)];
+        acc |= (uint64_t)u[c] << nb;
+        nb += wc;
+        if (nb >= 32) {
+          if (wo >= w0 && wo < w1) row[wo - w0] = (uint32_t)acc;
+          ++wo;
+          acc >>= 32;
+          nb -= 32;
+        }
+      }
+      if (nb > 0 && wo >= w0 && wo < w1) row[wo - w0] = (uint32_t)acc;
+    }
+    __syncthreads();
+    const uint32_t n = wave_total > w0 ? min(wave_total - w0, (uint32_t)kStageWords) : 0u;
+    for (uint32_t k0 = 0; k0 < n; k0 += 8 * 64) {
+      uint32_t t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t k = k0 + q * 64 + lane;
+        t[q] = k < n ? row[k] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t k = k0 + q * 64 + lane;
+        const int64_t d = dst0 + w0 + k;
+        if (k < n && d < p.cap_words) st(t[q], p.out + d);
       }
     }
-    if (nb > 0) buf[wo] = (uint32_t)acc;
-  }
-  __syncthreads();
-
-  // the wave's payload words -> their final place, 64 consecutive words per store
-  const int64_t dst0 = p.pay_base + (int64_t)s_excl + wave_base;
-  for (uint32_t k = lane; k < wave_total; k += 64) {
-    const int64_t d = dst0 + k;
-    if (d < p.cap_words) st(buf[k], p.out + d);
+    __syncthreads();
   }
 }
 
+// Word i of a decoder wave's payload: from the LDS area when staged, else
+// from the stream; 0 past the block's own words (end) or the stream.
+__device__ __attribute__((always_inline)) inline uint32_t payload_word(const uint32_t* row, const uint32_t* in,
+                                                                      uint32_t i, uint32_t end, uint32_t nstaged,
+                                                                      int64_t src0, int64_t cap_words) {
+  if (i >= end) return 0u;
+  if (i < nstaged) return row[i];
+  return src0 + i < cap_words ? ld(in + src0 + i) : 0u;
+}
+
 template <int MODE>
-__global__ __launch_bounds__(kZcChunk) void k_zc_decode(ZcParams p) {
-  __shared__ uint32_t s_buf[4][kWaveWords];
+__global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
+  __shared__ __attribute__((aligned(16))) uint32_t s_stage[4][kStageWords];
   __shared__ uint32_t s_scan[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t* buf = s_buf[wave];
+  uint32_t* row = s_stage[wave];
   const int32_t chunk = blockIdx.x;
   const int32_t b0 = chunk * kZcChunk + wave * 64;
   const int32_t b = b0 + lane;
@@ -359,23 +413,51 @@ __global__ __launch_bounds__(kZcChunk) void k_zc_decode(ZcParams p) {
   const uint32_t c0 = in[8 + chunk], c1 = in[8 + chunk + 1];
   if (threadIdx.x == 0 && (c1 < c0 || c1 - c0 != agg)) atomicOr(p.flags, kZcCorrupt);
 
-  // the wave's payload -> LDS, 64 consecutive words per load
+  // the wave's payload -> LDS, 64 consecutive words per load, all loads in
+  // flight together; words past the LDS area (nearly incompressible blocks
+  // only) are read from the stream
   const int64_t src0 = p.pay_base + (int64_t)c0 + wave_base;
-  for (uint32_t k = lane; k < wave_total; k += 64) {
-    const int64_t sidx = src0 + k;
-    buf[k] = sidx < p.cap_words ? ld(in + sidx) : 0u;
-  }
   if (lane == 0 && src0 + wave_total > p.cap_words) atomicOr(p.flags, kZcCorrupt);
+  const uint32_t nstaged = min(wave_total, (uint32_t)kStageWords);
+  {
+    constexpr int kPer = kStageWords / 64;  // 52 words per lane
+    uint32_t t[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t k = q * 64 + lane;
+      t[q] = (k < nstaged && src0 + k < p.cap_words) ? ld(in + src0 + k) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t k = q * 64 + lane;
+      if (k < nstaged) row[k] = t[q];
+    }
+  }
   __syncthreads();
 
-  // unpack this lane's block (its words are buf[local - wave_base ...])
+  // unpack this lane's block
   int32_t v[64];
-  {
-    // the block's words are buf[local - wave_base, + nwords); one word is
-    // always read ahead so the LDS latency overlaps the unpacking
-    uint32_t rp = local - wave_base;
-    const uint32_t rend = rp + nwords;
-    uint32_t next = nwords ? buf[rp] : 0u;
+  const uint32_t my0 = local - wave_base, my1 = my0 + nwords;
+  if (wave_total <= (uint32_t)kStageWords) {
+    // the whole payload is in LDS: every coefficient is extracted on its own
+    // from its bit offset, so no read waits for another
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+      const int wc = w[band_of(c / kB, c % kB)];
+      const uint32_t pos = count_before(c, 0) * w[0] + count_before(c, 1) * w[1] + count_before(c, 2) * w[2] +
+                           count_before(c, 3) * w[3] + count_before(c, 4) * w[4];
+      const uint32_t wi = my0 + (pos >> 5);
+      const uint32_t lo = row[min(wi, (uint32_t)kStageWords - 1)];
+      const uint32_t hi = row[min(wi + 1, (uint32_t)kStageWords - 1)];
+      const uint64_t both = (uint64_t)(wi < my1 ? lo : 0u) | ((uint64_t)(wi + 1 < my1 ? hi : 0u) << 32);
+      v[c] = unzigzag((uint32_t)((both >> (pos & 31)) & ((1ull << wc) - 1ull)));
+      if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);  // one row of reads in flight at a time
+    }
+  } else {
+    // nearly incompressible: words past the LDS area come from the stream;
+    // one word is read ahead
+    uint32_t k = 0;
+    uint32_t next = payload_word(row, in, my0, my1, nstaged, src0, p.cap_words);
     uint64_t acc = 0;
     int have = 0;
 #pragma unroll
@@ -384,8 +466,7 @@ __global__ __launch_bounds__(kZcChunk) void k_zc_decode(ZcParams p) {
       if (have < wc) {
         acc |= (uint64_t)next << have;
         have += 32;
-        ++rp;
-        next = rp < rend ? buf[rp] : 0u;
+        next = payload_word(row, in, my0 + (++k), my1, nstaged, src0, p.cap_words);
       }
       const uint32_t uc = (uint32_t)(acc & ((1ull << wc) - 1ull));
       acc >>= wc;
@@ -396,26 +477,29 @@ __global__ __launch_bounds__(kZcChunk) void k_zc_decode(ZcParams p) {
   unlift_level<2>(v);
   unlift_level<4>(v);
   unlift_level<8>(v);
-  __syncthreads();  // every lane has read its payload out of buf
-#pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    const float f = MODE == 0 ? (float)((double)v[c] * p.step) : key_float(v[c]);
-    buf[swz(lane, c)] = __float_as_uint(f);
-  }
-  __syncthreads();
+  __syncthreads();  // every lane has read its payload out of the LDS area
 
-  // rows of the wave's blocks -> the array, 64 consecutive floats per store
+  // this lane's block rows -> the row buffer -> the array, one row at a time
   WaveBlocks wb;
   wave_blocks(p, b0, lane, wb);
   const int j = lane & 7;
 #pragma unroll
-  for (int i = 0; i < kB; ++i)
+  for (int i = 0; i < kB; ++i) {
+    uint32_t e[8];
+#pragma unroll
+    for (int jj = 0; jj < kB; ++jj)
+      e[jj] = __float_as_uint(MODE == 0 ? (float)((double)v[i * kB + jj] * p.step) : key_float(v[i * kB + jj]));
+    reinterpret_cast<uint4*>(row)[2 * lane] = make_uint4(e[0], e[1], e[2], e[3]);
+    reinterpret_cast<uint4*>(row)[2 * lane + 1] = make_uint4(e[4], e[5], e[6], e[7]);
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int32_t z = wb.z0[k] + i, x = wb.x0[k] + j;
       if (wb.live[k] && z < p.rows && x < p.cols)
-        st(__uint_as_float(buf[swz(8 * k + (lane >> 3), i * kB + j)]), p.y + wb.img[k] + (int64_t)z * p.cols + x);
+        st(__uint_as_float(row[64 * k + lane]), p.y + wb.img[k] + (int64_t)z * p.cols + x);
     }
+    __syncthreads();
+  }
 }
 
 hipError_t launch_zc_encode(const ZcParams& p, hipStream_t s) {
