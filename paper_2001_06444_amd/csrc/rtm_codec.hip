@@ -130,6 +130,14 @@ __device__ inline int32_t float_key(float f) {
 __device__ inline float key_float(int32_t k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
 __device__ inline int bitlen(uint32_t u) { return 32 - __clz(u); }
 
+// Orders the LDS accesses of one wave around this point (each wave owns its
+// own LDS area, so the other waves need not wait).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exclusive scan of one value per thread over a 256-thread workgroup;
 // returns the exclusive prefix and writes the workgroup total to *total.
 __device__ inline uint32_t wg_exclusive_scan(uint32_t v, uint32_t* lds4, uint32_t* total) {
@@ -182,14 +190,28 @@ struct WaveBlocks {
   bool live[8];
 };
 __device__ inline void wave_blocks(const ZcParams& p, int32_t b0, int lane, WaveBlocks& wb) {
+  // the first block by division, the next seven by stepping 8 blocks along the
+  // block order; blocks past the end take the last block's position
+  const int32_t first = b0 + (lane >> 3);
+  const BlockPos last = block_pos(p.nblocks - 1, p.bz, p.bx);
+  const int32_t per = p.bz * p.bx, bf = min(first, p.nblocks - 1);
+  int32_t a = bf / per, rem = bf - a * per, r = rem / p.bx, c = rem - r * p.bx;
+  const int64_t plane = (int64_t)p.rows * p.cols;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int32_t b = b0 + 8 * k + (lane >> 3);
-    wb.live[k] = b < p.nblocks;
-    const BlockPos bp = block_pos(min(b, p.nblocks - 1), p.bz, p.bx);
-    wb.img[k] = (int64_t)bp.a * p.rows * p.cols;
-    wb.z0[k] = bp.z0;
-    wb.x0[k] = bp.x0;
+    const bool live = first + 8 * k < p.nblocks;
+    wb.live[k] = live;
+    wb.img[k] = (int64_t)(live ? a : last.a) * plane;
+    wb.z0[k] = live ? r * kB : last.z0;
+    wb.x0[k] = live ? c * kB : last.x0;
+    c += 8;
+    while (c >= p.bx) {
+      c -= p.bx;
+      if (++r == p.bz) {
+        r = 0;
+        ++a;
+      }
+    }
   }
 }
 
@@ -197,7 +219,6 @@ template <int MODE>
 __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
   __shared__ __attribute__((aligned(16))) uint32_t s_stage[4][kStageWords];
   __shared__ uint32_t s_scan[4];
-  __shared__ uint32_t s_rounds[4];
   __shared__ uint32_t s_chunk;
   __shared__ uint64_t s_excl;
   if (threadIdx.x == 0) s_chunk = atomicAdd(p.ticket, 1u);
@@ -231,7 +252,7 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
     for (int i = 0; i < kB; ++i) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) row[64 * k + lane] = lv[i][k];
-      __syncthreads();
+      wave_sync();
       const uint4 r0 = reinterpret_cast<const uint4*>(row)[2 * lane];
       const uint4 r1 = reinterpret_cast<const uint4*>(row)[2 * lane + 1];
       const uint32_t e[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
@@ -247,7 +268,7 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
           v[i * kB + jj] = float_key(f);
         }
       }
-      __syncthreads();
+      wave_sync();
     }
   }
   lift_level<8>(v);
@@ -274,7 +295,6 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
   const uint32_t wave_base = __shfl(local, 0, 64);
   const uint32_t wave_total = __shfl(local + nwords, 63, 64) - wave_base;
   const uint32_t my_rounds = (wave_total + kStageWords - 1) / kStageWords;
-  if (lane == 0) s_rounds[wave] = my_rounds;
 
   // decoupled look-back, one wave wide: wave 0 reads the status of up to 64
   // preceding chunks per round, sums them down to the nearest one whose
@@ -326,16 +346,15 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
   }
   __syncthreads();
   if (active) p.out[p.hdr_base + b] = header;
-  const uint32_t rounds = max(max(s_rounds[0], s_rounds[1]), max(s_rounds[2], s_rounds[3]));
 
   // payload words: packed into the wave's LDS area kStageWords at a time
   // (more than one round only for nearly incompressible blocks), then
   // stored 64 consecutive words per instruction
   const int64_t dst0 = p.pay_base + (int64_t)s_excl + wave_base;
   const uint32_t my0 = local - wave_base;  // this block's first word, wave-relative
-  for (uint32_t r = 0; r < rounds; ++r) {
+  for (uint32_t r = 0; r < my_rounds; ++r) {
     const uint32_t w0 = r * kStageWords, w1 = w0 + kStageWords;
-    if (active && r < my_rounds && my0 < w1 && my0 + nwords > w0) {
+    if (active && my0 < w1 && my0 + nwords > w0) {
       uint32_t wo = my0;
       uint64_t acc = 0;
       int nb = 0;
@@ -353,7 +372,7 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
       }
       if (nb > 0 && wo >= w0 && wo < w1) row[wo - w0] = (uint32_t)acc;
     }
-    __syncthreads();
+    wave_sync();
     const uint32_t n = wave_total > w0 ? min(wave_total - w0, (uint32_t)kStageWords) : 0u;
     for (uint32_t k0 = 0; k0 < n; k0 += 8 * 64) {
       uint32_t t[8];
@@ -369,7 +388,7 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
         if (k < n && d < p.cap_words) st(t[q], p.out + d);
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -433,7 +452,7 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
       if (k < nstaged) row[k] = t[q];
     }
   }
-  __syncthreads();
+  wave_sync();
 
   // unpack this lane's block
   int32_t v[64];
@@ -477,12 +496,17 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
   unlift_level<2>(v);
   unlift_level<4>(v);
   unlift_level<8>(v);
-  __syncthreads();  // every lane has read its payload out of the LDS area
+  wave_sync();  // every lane has read its payload out of the LDS area
 
   // this lane's block rows -> the row buffer -> the array, one row at a time
+  // (no bounds tests when all 64 blocks of the wave lie inside the array)
   WaveBlocks wb;
   wave_blocks(p, b0, lane, wb);
   const int j = lane & 7;
+  bool inside = true;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) inside &= wb.live[k] && wb.z0[k] + kB <= p.rows && wb.x0[k] + kB <= p.cols;
+  const bool all_inside = __all(inside);
 #pragma unroll
   for (int i = 0; i < kB; ++i) {
     uint32_t e[8];
@@ -491,14 +515,20 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
       e[jj] = __float_as_uint(MODE == 0 ? (float)((double)v[i * kB + jj] * p.step) : key_float(v[i * kB + jj]));
     reinterpret_cast<uint4*>(row)[2 * lane] = make_uint4(e[0], e[1], e[2], e[3]);
     reinterpret_cast<uint4*>(row)[2 * lane + 1] = make_uint4(e[4], e[5], e[6], e[7]);
-    __syncthreads();
+    wave_sync();
+    if (all_inside) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int32_t z = wb.z0[k] + i, x = wb.x0[k] + j;
-      if (wb.live[k] && z < p.rows && x < p.cols)
-        st(__uint_as_float(row[64 * k + lane]), p.y + wb.img[k] + (int64_t)z * p.cols + x);
+      for (int k = 0; k < 8; ++k)
+        st(__uint_as_float(row[64 * k + lane]), p.y + wb.img[k] + (int64_t)(wb.z0[k] + i) * p.cols + wb.x0[k] + j);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int32_t z = wb.z0[k] + i, x = wb.x0[k] + j;
+        if (wb.live[k] && z < p.rows && x < p.cols)
+          st(__uint_as_float(row[64 * k + lane]), p.y + wb.img[k] + (int64_t)z * p.cols + x);
+      }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
