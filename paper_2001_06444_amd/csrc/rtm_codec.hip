@@ -296,13 +296,42 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
   const uint32_t wave_total = __shfl(local + nwords, 63, 64) - wave_base;
   const uint32_t my_rounds = (wave_total + kStageWords - 1) / kStageWords;
 
+  // payload words are packed into the wave's LDS area kStageWords at a time
+  // (more than one round only for nearly incompressible blocks) and stored
+  // 64 consecutive words per instruction.  The first round is packed before
+  // the look-back: it needs only offsets within the wave.
+  const uint32_t my0 = local - wave_base;  // this block's first word, wave-relative
+  auto pack = [&](uint32_t r) __attribute__((always_inline)) {
+    const uint32_t w0 = r * kStageWords, w1 = w0 + kStageWords;
+    if (active && my0 < w1 && my0 + nwords > w0) {
+      uint32_t wo = my0;
+      uint64_t acc = 0;
+      int nb = 0;
+#pragma unroll
+      for (int c = 0; c < 64; ++c) {
+        const int wc = w[band_of(c / kB, c % kB)];
+        acc |= (uint64_t)u[c] << nb;
+        nb += wc;
+        if (nb >= 32) {
+          if (wo >= w0 && wo < w1) row[wo - w0] = (uint32_t)acc;
+          ++wo;
+          acc >>= 32;
+          nb -= 32;
+        }
+      }
+      if (nb > 0 && wo >= w0 && wo < w1) row[wo - w0] = (uint32_t)acc;
+    }
+    wave_sync();
+  };
+  if (wave == 0 && lane == 0)
+    __hip_atomic_store(p.status + chunk, (chunk == 0 ? kInc : kAgg) | agg, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  pack(0);
+
   // decoupled look-back, one wave wide: wave 0 reads the status of up to 64
   // preceding chunks per round, sums them down to the nearest one whose
   // inclusive prefix is published, and repeats further back if none is
   if (wave == 0) {
-    if (lane == 0)
-      __hip_atomic_store(p.status + chunk, (chunk == 0 ? kInc : kAgg) | agg, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
     int32_t end_j = chunk;  // chunks [0, end_j) are still to be summed
     int spins = 0;
@@ -347,32 +376,10 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_encode(ZcParams p) {
   __syncthreads();
   if (active) p.out[p.hdr_base + b] = header;
 
-  // payload words: packed into the wave's LDS area kStageWords at a time
-  // (more than one round only for nearly incompressible blocks), then
-  // stored 64 consecutive words per instruction
   const int64_t dst0 = p.pay_base + (int64_t)s_excl + wave_base;
-  const uint32_t my0 = local - wave_base;  // this block's first word, wave-relative
   for (uint32_t r = 0; r < my_rounds; ++r) {
-    const uint32_t w0 = r * kStageWords, w1 = w0 + kStageWords;
-    if (active && my0 < w1 && my0 + nwords > w0) {
-      uint32_t wo = my0;
-      uint64_t acc = 0;
-      int nb = 0;
-#pragma unroll
-      for (int c = 0; c < 64; ++c) {
-        const int wc = w[band_of(c / kB, c % kB)];
-        acc |= (uint64_t)u[c] << nb;
-        nb += wc;
-        if (nb >= 32) {
-          if (wo >= w0 && wo < w1) row[wo - w0] = (uint32_t)acc;
-          ++wo;
-          acc >>= 32;
-          nb -= 32;
-        }
-      }
-      if (nb > 0 && wo >= w0 && wo < w1) row[wo - w0] = (uint32_t)acc;
-    }
-    wave_sync();
+    if (r > 0) pack(r);
+    const uint32_t w0 = r * kStageWords;
     const uint32_t n = wave_total > w0 ? min(wave_total - w0, (uint32_t)kStageWords) : 0u;
     for (uint32_t k0 = 0; k0 < n; k0 += 8 * 64) {
       uint32_t t[8];
@@ -402,9 +409,12 @@ __device__ __attribute__((always_inline)) inline uint32_t payload_word(const uin
   return src0 + i < cap_words ? ld(in + src0 + i) : 0u;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
-  __shared__ __attribute__((aligned(16))) uint32_t s_stage[4][kStageWords];
+// STAGE words of LDS per wave at MINW waves per SIMD: the host takes the
+// smaller area and a fourth wave when the stream's payload mostly fits it.
+template <int MODE, int STAGE, int MINW>
+__global__ __launch_bounds__(kZcChunk, MINW) void k_zc_decode(ZcParams p) {
+  static_assert(STAGE >= kRowWords && STAGE % 64 == 0, "the LDS area must hold one row of the wave's blocks");
+  __shared__ __attribute__((aligned(16))) uint32_t s_stage[4][STAGE];
   __shared__ uint32_t s_scan[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* row = s_stage[wave];
@@ -437,9 +447,9 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
   // only) are read from the stream
   const int64_t src0 = p.pay_base + (int64_t)c0 + wave_base;
   if (lane == 0 && src0 + wave_total > p.cap_words) atomicOr(p.flags, kZcCorrupt);
-  const uint32_t nstaged = min(wave_total, (uint32_t)kStageWords);
+  const uint32_t nstaged = min(wave_total, (uint32_t)STAGE);
   {
-    constexpr int kPer = kStageWords / 64;  // 52 words per lane
+    constexpr int kPer = STAGE / 64;
     uint32_t t[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -457,7 +467,7 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
   // unpack this lane's block
   int32_t v[64];
   const uint32_t my0 = local - wave_base, my1 = my0 + nwords;
-  if (wave_total <= (uint32_t)kStageWords) {
+  if (wave_total <= (uint32_t)STAGE) {
     // the whole payload is in LDS: every coefficient is extracted on its own
     // from its bit offset, so no read waits for another
 #pragma unroll
@@ -466,8 +476,8 @@ __global__ __launch_bounds__(kZcChunk, 3) void k_zc_decode(ZcParams p) {
       const uint32_t pos = count_before(c, 0) * w[0] + count_before(c, 1) * w[1] + count_before(c, 2) * w[2] +
                            count_before(c, 3) * w[3] + count_before(c, 4) * w[4];
       const uint32_t wi = my0 + (pos >> 5);
-      const uint32_t lo = row[min(wi, (uint32_t)kStageWords - 1)];
-      const uint32_t hi = row[min(wi + 1, (uint32_t)kStageWords - 1)];
+      const uint32_t lo = row[min(wi, (uint32_t)STAGE - 1)];
+      const uint32_t hi = row[min(wi + 1, (uint32_t)STAGE - 1)];
       const uint64_t both = (uint64_t)(wi < my1 ? lo : 0u) | ((uint64_t)(wi + 1 < my1 ? hi : 0u) << 32);
       v[c] = unzigzag((uint32_t)((both >> (pos & 31)) & ((1ull << wc) - 1ull)));
       if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);  // one row of reads in flight at a time
@@ -543,10 +553,22 @@ hipError_t launch_zc_encode(const ZcParams& p, hipStream_t s) {
 
 hipError_t launch_zc_decode(const ZcParams& p, hipStream_t s) {
   if (p.nchunks < 1) return hipErrorInvalidValue;
-  if (p.mode == 0)
-    k_zc_decode<0><<<p.nchunks, kZcChunk, 0, s>>>(p);
-  else
-    k_zc_decode<1><<<p.nchunks, kZcChunk, 0, s>>>(p);
+  // mean payload words per wave decide the LDS area (the last chunk may be
+  // partial; the estimate only picks a variant)
+  constexpr int kSmall = 2496;
+  const int64_t words = p.cap_words - p.pay_base;
+  const bool small = words <= (int64_t)p.nchunks * 4 * (kSmall * 9 / 10);
+  if (small) {
+    if (p.mode == 0)
+      k_zc_decode<0, kSmall, 4><<<p.nchunks, kZcChunk, 0, s>>>(p);
+    else
+      k_zc_decode<1, kSmall, 4><<<p.nchunks, kZcChunk, 0, s>>>(p);
+  } else {
+    if (p.mode == 0)
+      k_zc_decode<0, kStageWords, 3><<<p.nchunks, kZcChunk, 0, s>>>(p);
+    else
+      k_zc_decode<1, kStageWords, 3><<<p.nchunks, kZcChunk, 0, s>>>(p);
+  }
   return hipGetLastError();
 }
 
