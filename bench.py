@@ -711,7 +711,7 @@ def run_codec(args):
     achieved = ab / (ms * 1e-3) / 1e9
     traffic = measured_traffic("traffic_codec.json", CODEC_SOURCES, key=f"{op} {label}")
     cpu = None if args.no_cpu_baseline else codec_cpu_baseline(
-        {k: v[: 4] for k, v in banks.items()})
+        {k: v[: 8] for k, v in banks.items()}, budget_s=15.0)
     ctx.close()
     out = _base_record(args, step_bytes / (el / args.steps) / 1e9, el * 1e3 / args.steps, {
         "workload": f"compression stage: {args.realizations} velocity samples and {args.realizations} images "
