@@ -1,4 +1,4 @@
-"""Build step for the oracle's C source (gcc, FP64, OpenMP, no fast-math).
+"""Build step for the oracle's C sources (gcc, no fast-math, no contraction).
 
 Test infrastructure: compiled by the package build step so the checker is
 ready, and called only by tests, the smoke check and the CPU baseline.
@@ -9,7 +9,7 @@ import pathlib
 import subprocess
 
 HERE = pathlib.Path(__file__).resolve().parent
-SRC = HERE / "rtm_oracle.c"
+SRCS = [HERE / "rtm_oracle.c", HERE / "bet_oracle.c"]
 OUT = HERE / "liboracle.so"
 
 CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
@@ -17,9 +17,10 @@ CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off"
 
 
 def build(force: bool = False) -> pathlib.Path:
-    if force or not OUT.exists() or OUT.stat().st_mtime < SRC.stat().st_mtime:
+    newest = max(s.stat().st_mtime for s in SRCS)
+    if force or not OUT.exists() or OUT.stat().st_mtime < newest:
         tmp = OUT.with_suffix(".so.tmp")
-        subprocess.run(["gcc", *CFLAGS, str(SRC), "-o", str(tmp), "-lm"], check=True)
+        subprocess.run(["gcc", *CFLAGS, *map(str, SRCS), "-o", str(tmp), "-lm"], check=True)
         tmp.replace(OUT)
     return OUT
 
