@@ -30,7 +30,7 @@ class _Cfg(ctypes.Structure):
                 ("p_birth", ctypes.c_double), ("p_death", ctypes.c_double),
                 ("move_dz", ctypes.c_double), ("move_dx", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("burn_in", ctypes.c_int32), ("thin", ctypes.c_int32),
-                ("single", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("single", ctypes.c_int32), ("chain0", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -51,10 +51,13 @@ def _lib():
         L.orc_voronoi.argtypes = [i32, i32, d, i32, P(d), P(d), P(ctypes.c_int32)]
         L.orc_eikonal_f64.argtypes = [i32, i32, d, P(d), i32, i32, P(d)]
         L.orc_eikonal_f32.argtypes = [i32, i32, ctypes.c_float, P(ctypes.c_float), i32, i32, P(ctypes.c_float)]
+        L.orc_eikonal_fsm_f32.argtypes = [i32, i32, ctypes.c_float, P(ctypes.c_float), i32, i32,
+                                          P(ctypes.c_float)]
         L.orc_eikonal_table.argtypes = [P(_Cfg), P(d), P(ctypes.c_int32), P(ctypes.c_int32), P(d)]
         L.orc_bet_run.argtypes = [P(_Cfg), P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_float), i32,
                                   P(d), P(d), P(d), P(_Info), P(d), P(d), P(ctypes.c_int64), P(ctypes.c_int8)]
-        for f in ("orc_voronoi", "orc_eikonal_f64", "orc_eikonal_f32", "orc_eikonal_table", "orc_bet_run"):
+        for f in ("orc_voronoi", "orc_eikonal_f64", "orc_eikonal_f32", "orc_eikonal_fsm_f32", "orc_eikonal_table",
+                  "orc_bet_run"):
             getattr(L, f).restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
@@ -85,11 +88,12 @@ class BetConfig:
     burn_in: int = 0
     thin: int = 1
     single: bool = True
+    chain0: int = 0  # run chains chain0 .. chain0 + chains - 1
 
     def c(self, nsrc, nrec):
         return _Cfg(self.nz, self.nx, self.h, nsrc, nrec, self.chains, self.k_min, self.k_max, self.k_init,
                     self.v_min, self.v_max, self.p_birth, self.p_death, self.move_dz, self.move_dx,
-                    self.sigma, self.seed, self.burn_in, self.thin, int(self.single), 0)
+                    self.sigma, self.seed, self.burn_in, self.thin, int(self.single), self.chain0)
 
 
 def sm64_at(seed: int, n: int) -> int:
@@ -111,8 +115,16 @@ def voronoi(nz, nx, h, zs, xs):
     return out
 
 
-def eikonal(slowness, h, src, single=False):
-    """First-arrival times on the grid from source node src = (iz, ix) (fast marching)."""
+def eikonal(slowness, h, src, single=False, sweep=False):
+    """First-arrival times on the grid from source node src = (iz, ix): fast
+    marching (FP64, or FP32 with single=True), or fast sweeping in FP32
+    (sweep=True; returns (T, passes))."""
+    if sweep:
+        s = np.ascontiguousarray(slowness, dtype=np.float32)
+        T = np.empty_like(s)
+        passes = _lib().orc_eikonal_fsm_f32(s.shape[0], s.shape[1], np.float32(h), _p(s, ctypes.c_float), src[0],
+                                            src[1], _p(T, ctypes.c_float))
+        return T, passes
     if single:
         s = np.ascontiguousarray(slowness, dtype=np.float32)
         T = np.empty_like(s)
@@ -131,7 +143,8 @@ def _pts(pts):
 
 
 def travel_times(vel, h, srcs, recs, single=False):
-    """[nsrc][nrec] first-arrival times of the velocity grid vel (m/s)."""
+    """[nsrc][nrec] first-arrival times of the velocity grid vel (m/s): fast
+    marching in FP64, or fast sweeping in FP32 with single=True."""
     vel = np.ascontiguousarray(vel, dtype=np.float64)
     s, r = _pts(srcs), _pts(recs)
     cfg = BetConfig(vel.shape[0], vel.shape[1], h, single=single).c(len(s), len(r))

@@ -21,9 +21,11 @@
  * Random numbers: the counter form of splitmix64 (Steele, Lea and Flood,
  * 2014): output n of a stream seeded with s is mix(s + (n + 1) gamma).
  *
- * The travel-time solver exists in double precision and in a single-precision
- * variant with the same operation order (for the accept decisions, which are
- * taken in the precision of the device solver).
+ * Travel times come from fast marching in double precision, or, for accept
+ * decisions taken in the precision of the device solver, from fast sweeping
+ * in single precision (in single precision the two algorithms reach fixed
+ * points that can differ in the last bits; sweeps in the same directions
+ * reach the same one).
  */
 #include <math.h>
 #include <stdint.h>
@@ -194,6 +196,44 @@ int orc_eikonal_f32(int nz, int nx, float hh, const float* s, int sz, int sx, fl
     FMM_BODY(float, godunov_f, INFINITY)
 }
 
+/* ---- Eikonal: fast sweeping (single precision) ----------------------
+ * Gauss-Seidel sweeps of the same Godunov update in four orderings per pass
+ * (i up / j up, i down / j up, i down / j down, i up / j down), every node
+ * taking the current times of its four neighbours, repeated until a pass
+ * changes nothing (Zhao 2005).  Within one ordering a node sees its two
+ * upwind neighbours already swept and its two downwind neighbours from
+ * before, whatever the order of independent nodes, so any sweep order that
+ * respects the direction gives the same times.  Returns the passes used
+ * (256: gave up). */
+int orc_eikonal_fsm_f32(int nz, int nx, float hh, const float* s, int sz, int sx, float* T) {
+    const int n = nz * nx;
+    for (int q = 0; q < n; ++q) T[q] = INFINITY;
+    T[sz * nx + sx] = 0.0f;
+    int pass = 0;
+    for (; pass < 256; ++pass) {
+        int changed = 0;
+        for (int o = 0; o < 4; ++o) {
+            const int fi = (o == 0 || o == 3), fj = (o < 2);
+            for (int ii = 0; ii < nz; ++ii) {
+                const int i = fi ? ii : nz - 1 - ii;
+                for (int jj = 0; jj < nx; ++jj) {
+                    const int j = fj ? jj : nx - 1 - jj;
+                    const int m = i * nx + j;
+                    const float up = i > 0 ? T[m - nx] : INFINITY, dn = i + 1 < nz ? T[m + nx] : INFINITY;
+                    const float lf = j > 0 ? T[m - 1] : INFINITY, rt = j + 1 < nx ? T[m + 1] : INFINITY;
+                    const float t = godunov_f(up < dn ? up : dn, lf < rt ? lf : rt, s[m] * hh);
+                    if (t < T[m]) {
+                        T[m] = t;
+                        changed = 1;
+                    }
+                }
+            }
+        }
+        if (!changed) break;
+    }
+    return pass;
+}
+
 /* ---- the chains ----------------------------------------------------- */
 typedef struct {
     int32_t nz, nx;
@@ -206,8 +246,8 @@ typedef struct {
     double sigma;
     uint64_t seed;
     int32_t burn_in, thin;
-    int32_t single; /* 1: travel times in single precision (the device's) */
-    int32_t pad_;
+    int32_t single; /* 1: travel times by single-precision fast sweeping (the device's) */
+    int32_t chain0; /* chains chain0 .. chain0 + chains - 1 */
 } orc_bet_cfg;
 
 typedef struct {
@@ -230,7 +270,7 @@ static double model_misfit(const orc_bet_cfg* c, int k, const double* zs, const 
     double phi = 0.0;
     for (int e = 0; e < c->nsrc; ++e) {
         if (c->single)
-            orc_eikonal_f32(c->nz, c->nx, (float)c->h, sf, src[2 * e], src[2 * e + 1], Tf);
+            orc_eikonal_fsm_f32(c->nz, c->nx, (float)c->h, sf, src[2 * e], src[2 * e + 1], Tf);
         else
             orc_eikonal_f64(c->nz, c->nx, c->h, sd, src[2 * e], src[2 * e + 1], Td);
         for (int r = 0; r < c->nrec; ++r) {
@@ -259,7 +299,7 @@ int orc_eikonal_table(const orc_bet_cfg* c, const double* vel, const int32_t* sr
     }
     for (int e = 0; e < c->nsrc; ++e) {
         if (c->single)
-            orc_eikonal_f32(c->nz, c->nx, (float)c->h, sf, src[2 * e], src[2 * e + 1], Tf);
+            orc_eikonal_fsm_f32(c->nz, c->nx, (float)c->h, sf, src[2 * e], src[2 * e + 1], Tf);
         else
             orc_eikonal_f64(c->nz, c->nx, c->h, sd, src[2 * e], src[2 * e + 1], Td);
         for (int r = 0; r < c->nrec; ++r) {
@@ -305,7 +345,7 @@ int orc_bet_run(const orc_bet_cfg* c, const int32_t* src, const int32_t* rec, co
         double* zs = state_z + (size_t)ch * K;
         double* xs = state_x + (size_t)ch * K;
         double* vs = state_v + (size_t)ch * K;
-        init_model(c, ch, zs, xs, vs);
+        init_model(c, c->chain0 + ch, zs, xs, vs);
         memset(&info[ch], 0, sizeof info[ch]);
         info[ch].k = c->k_init;
         info[ch].misfit = model_misfit(c, c->k_init, zs, xs, vs, src, rec, tt_obs, NULL, cell, sd, sf, Td, Tf);
@@ -321,11 +361,11 @@ int orc_bet_run(const orc_bet_cfg* c, const int32_t* src, const int32_t* rec, co
             double* xs = state_x + (size_t)ch * K;
             double* vs = state_v + (size_t)ch * K;
             const int k = info[ch].k;
-            const double u0 = unit_open0(orc_bet_draw(c->seed, ch, t, 0));
-            const double u1 = unit_open0(orc_bet_draw(c->seed, ch, t, 1));
-            const double u2 = unit_open0(orc_bet_draw(c->seed, ch, t, 2));
-            const double u3 = unit_open0(orc_bet_draw(c->seed, ch, t, 3));
-            const double ua = unit_open1(orc_bet_draw(c->seed, ch, t, 4));
+            const double u0 = unit_open0(orc_bet_draw(c->seed, c->chain0 + ch, t, 0));
+            const double u1 = unit_open0(orc_bet_draw(c->seed, c->chain0 + ch, t, 1));
+            const double u2 = unit_open0(orc_bet_draw(c->seed, c->chain0 + ch, t, 2));
+            const double u3 = unit_open0(orc_bet_draw(c->seed, c->chain0 + ch, t, 3));
+            const double ua = unit_open1(orc_bet_draw(c->seed, c->chain0 + ch, t, 4));
             const int type = u0 < c->p_birth ? 0 : (u0 < c->p_birth + c->p_death ? 1 : 2);
             int kk = k, valid = 1;
             memcpy(pz, zs, sizeof(double) * k);

@@ -117,6 +117,31 @@ def test_fast_marching_equals_fixed_point(seed):
     assert np.all(T[mask] > nb[mask])
 
 
+def test_fast_sweeping_single_precision():
+    # the FP32 sweeping solver: the hand-worked 3 x 3 values, a single row
+    # exactly, and agreement with FP64 fast marching to FP32 rounding on a
+    # Voronoi model; a homogeneous grid converges in one pass plus a check
+    T, passes = bet.eikonal(np.ones((3, 3), np.float32), 1.0, (0, 0), sweep=True)
+    t11 = (2.0 + math.sqrt(2.0)) / 2.0
+    assert T[0, 2] == 2.0 and abs(T[1, 1] - t11) < 1e-6 and passes == 1
+    rng = np.random.default_rng(1)
+    s1 = rng.uniform(1 / 5000, 1 / 1500, size=(1, 40)).astype(np.float32)
+    T1, _ = bet.eikonal(s1, 25.0, (0, 7), sweep=True)
+    want = np.zeros(40, np.float32)
+    for j in range(8, 40):
+        want[j] = want[j - 1] + np.float32(s1[0, j] * np.float32(25.0))
+    for j in range(6, -1, -1):
+        want[j] = want[j + 1] + np.float32(s1[0, j] * np.float32(25.0))
+    np.testing.assert_array_equal(T1[0], want)
+    nz, nx, h = 36, 171, 100.0
+    zs, xs = rng.uniform(0, 3500, 25), rng.uniform(0, 17000, 25)
+    vs = rng.uniform(1500, 4700, 25)
+    s = 1.0 / vs[bet.voronoi(nz, nx, h, zs, xs)]
+    Ts, passes = bet.eikonal(s.astype(np.float32), h, (3, 100), sweep=True)
+    np.testing.assert_allclose(Ts, bet.eikonal(s, h, (3, 100)), rtol=2e-6, atol=1e-7)
+    assert 2 <= passes < 20
+
+
 def test_single_precision_variant_agrees():
     rng = np.random.default_rng(4)
     nz, nx, h = 36, 171, 100.0
