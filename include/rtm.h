@@ -373,6 +373,86 @@ int rtm_codec_info(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes, i
 int rtm_codec_decode(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes, float *x_dev,
                      int64_t capacity_floats);
 
+/* ---- Stage 1: Bayesian Eikonal tomography ------------------------------
+ *
+ * Sec. 2.1 (Eq. 1-3): travel times are the Eikonal equation's first
+ * arrivals; velocity samples come from reversible-jump Markov chains over
+ * Voronoi tessellations with a constant velocity per cell; the likelihood is
+ * exp(-Phi / 2), Phi = sum over sources and receivers of ((T - d) / sigma)^2.
+ *   - Travel times: first-order Godunov upwind scheme on a square grid of
+ *     spacing h (m), point sources and receivers at grid nodes, solved by
+ *     fast sweeping in single precision until a pass changes nothing.
+ *   - Model: k nuclei (k_min <= k <= k_max <= 64) with positions in
+ *     [0, (nz-1) h] x [0, (nx-1) h] and velocities; a node takes the velocity
+ *     of the nearest nucleus (ties: lowest index).
+ *   - Each iteration a chain proposes, with probabilities p_birth, p_death
+ *     and 1 - p_birth - p_death, to add a nucleus (position and velocity
+ *     drawn from the uniform prior), delete a uniformly chosen one, or move one
+ *     by a uniform step of half-widths (move_dz, move_dx); proposals leaving
+ *     the bounds are rejected; the rest are accepted with probability
+ *     min(1, exp(-(Phi' - Phi) / 2)).
+ *   - Random numbers: splitmix64 in counter form; chain c's stream is seeded
+ *     by output c of the stream seeded with `seed`; iteration t (t = -1 for
+ *     the initial model) uses its outputs (t + 1) * 256 + k.  Initial model:
+ *     k_init nuclei from the prior.
+ *   - After burn_in iterations, every thin-th iteration adds every chain's
+ *     velocity grid (chains in order) to a pooled FP64 Welford mean / M2 per
+ *     node: the velocity uncertainty maps of Stage 3.
+ * Grids have at most 12800 nodes. */
+typedef struct {
+    int32_t nz, nx;                 /* grid nodes */
+    int32_t chains;                 /* chains advanced together */
+    int32_t k_min, k_max, k_init;   /* Voronoi cells: bounds and initial count */
+    int32_t burn_in, thin;          /* sampling of the velocity statistics */
+    double h;                       /* node spacing (m) */
+    double v_min, v_max;            /* uniform velocity prior (m/s) */
+    double p_birth, p_death;        /* proposal probabilities; a move otherwise */
+    double move_dz, move_dx;        /* half-widths of a nucleus move (m) */
+    double sigma;                   /* travel-time noise standard deviation (s) */
+    uint64_t seed;
+} rtm_bet_config;
+
+typedef struct {
+    int32_t k;                      /* cells of the current model */
+    int32_t pad_;
+    double misfit;                  /* Phi of the current model */
+    int64_t proposed[3], accepted[3];  /* birth, death, move (valid proposals) */
+} rtm_bet_chain_info;
+
+typedef struct rtm_bet rtm_bet;
+
+/* Travel times tt_dev [nsrc][nrec] (s, float) of the velocity grid vel_dev
+ * [nz][nx] (m/s, float) for sources src_host[nsrc] and receivers
+ * rec_host[nrec] (grid nodes).  Synchronous.  Errors: RTM_E_INVAL (shape,
+ * points outside the grid, more than 12800 nodes), RTM_E_DEVICE (a solve did
+ * not converge). */
+int rtm_eikonal(rtm_ctx *ctx, const float *vel_dev, int32_t nz, int32_t nx, float h, int32_t nsrc,
+                const rtm_point *src_host, int32_t nrec, const rtm_point *rec_host, float *tt_dev);
+
+/* Creates the sampler: copies the observed travel times tt_obs_dev
+ * [nsrc][nrec] (s), draws every chain's initial model and computes its
+ * misfit (stream-ordered).  Errors: RTM_E_INVAL (bad configuration),
+ * RTM_E_NOMEM (arena). */
+int rtm_bet_create(rtm_ctx *ctx, const rtm_bet_config *cfg, int32_t nsrc, const rtm_point *src_host,
+                   int32_t nrec, const rtm_point *rec_host, const float *tt_obs_dev, rtm_bet **out);
+
+/* Advances every chain by `iterations` (stream-ordered, returns after
+ * enqueue).  log_dev (nullable) receives [iterations][chains] outcomes:
+ * -1 invalid proposal, 0 rejected, 1 birth / 2 death / 3 move accepted. */
+int rtm_bet_run(rtm_ctx *ctx, rtm_bet *bet, int32_t iterations, int8_t *log_dev);
+
+/* Copies chain `chain`'s state to the host (synchronous): info, and the
+ * nuclei z/x/v (k_max doubles each, nullable).  RTM_E_DEVICE if any solve
+ * since creation hit the sweep limit. */
+int rtm_bet_chain(rtm_ctx *ctx, rtm_bet *bet, int32_t chain, rtm_bet_chain_info *info, double *z_host,
+                  double *x_host, double *v_host);
+
+/* Pooled velocity statistics so far: mean_dev, std_dev (sample std) [nz][nx]
+ * double and count_dev [nz][nx] int32, each nullable (stream-ordered). */
+int rtm_bet_stats(rtm_ctx *ctx, rtm_bet *bet, double *mean_dev, double *std_dev, int32_t *count_dev);
+
+int rtm_bet_destroy(rtm_ctx *ctx, rtm_bet *bet);
+
 /* ---- observability --------------------------------------------------- */
 
 typedef struct {

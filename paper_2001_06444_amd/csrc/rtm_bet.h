@@ -1,0 +1,54 @@
+// rtm_bet.h -- device state and launchers of the Stage-1 sampler
+// (rtm_bet.hip), shared with the host runtime (rtm_runtime.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtm {
+
+constexpr int kBetMaxCells = 64;     // Voronoi nuclei per model
+constexpr int kBetMaxNodes = 12800;  // Eikonal grid nodes (LDS: 5 B per node per wavefront)
+constexpr int kBetMaxSweeps = 256;   // fast-sweeping passes (4 orderings each) before giving up
+
+// error bits raised by the kernels in BetDev::flags
+constexpr uint32_t kBetNoConverge = 1u;  // a travel-time solve hit the sweep limit
+
+struct BetDev {
+  // grid, data
+  int32_t nz, nx, nsrc, nrec;
+  double h;  // node spacing (m); the travel-time sweeps use it rounded to float
+  int32_t chains, k_min, k_max, k_init;
+  int32_t burn_in, thin, pad0, pad1;
+  double v_min, v_max, p_birth, p_death, move_dz, move_dx, sigma;
+  uint64_t seed;
+  const int2* src;      // [nsrc] (iz, ix)
+  const int2* rec;      // [nrec]
+  const float* tt_obs;  // [nsrc][nrec]
+  // chain state [chains][k_max] / [chains]
+  int32_t* k;
+  double *z, *x, *v, *misfit;
+  // proposal
+  int32_t *pk, *valid, *ptype;
+  double *pz, *px, *pv, *ua;
+  uint8_t* cell;   // [chains][nz*nx] nearest nucleus of the proposal
+  float* tt;       // [chains][nsrc][nrec] travel times of the proposal
+  // counters [chains][3] (birth, death, move)
+  int64_t *proposed, *accepted;
+  // pooled post-burn-in statistics of the velocity grid
+  double *mean, *m2;
+  int32_t* count;
+  uint32_t* flags;
+};
+
+hipError_t launch_bet_propose(const BetDev& d, int t, int init, hipStream_t s);
+hipError_t launch_bet_raster(const BetDev& d, hipStream_t s);
+hipError_t launch_bet_eikonal(const BetDev& d, hipStream_t s);
+// log_row (nullable): [chains] outcome of this iteration (-1 invalid, 0 rejected, 1 + move type)
+hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, hipStream_t s);
+hipError_t launch_bet_sample(const BetDev& d, hipStream_t s);
+// travel times of one velocity grid (m/s) for every source: tt [nsrc][nrec]
+hipError_t launch_eikonal_grid(const float* vel, int nz, int nx, float h, const int2* src, int nsrc,
+                               const int2* rec, int nrec, float* tt, uint32_t* flags, hipStream_t s);
+
+}  // namespace rtm

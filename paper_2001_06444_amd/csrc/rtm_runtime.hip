@@ -35,6 +35,7 @@
 
 #include "../../include/rtm.h"
 #include "rtm_arena.h"
+#include "rtm_bet.h"
 #include "rtm_codec.h"
 #include "rtm_internal.h"
 
@@ -1933,6 +1934,208 @@ extern "C" int rtm_codec_decode(rtm_ctx* ctx, const void* stream_dev, int64_t st
   ctx->zc_bytes = (uint64_t)stream_bytes + 4 * (uint64_t)n;
   if (flags) return fail(RTM_E_INVAL, "corrupt codec stream (widths, chunk table or length)");
   return RTM_OK;
+}
+
+// ===========================================================================
+// Stage 1: Bayesian Eikonal tomography
+// ===========================================================================
+struct rtm_bet {
+  BetDev d{};
+  std::vector<Block> blocks;
+  int t = 0;  // iterations done
+};
+
+static int bet_points(const rtm_point* pts, int n, int nz, int nx, const char* what, std::vector<int2>& out) {
+  if (n < 1 || !pts) return fail(RTM_E_INVAL, "no %s", what);
+  out.resize(n);
+  for (int i = 0; i < n; ++i) {
+    if (pts[i].iz < 0 || pts[i].iz >= nz || pts[i].ix < 0 || pts[i].ix >= nx)
+      return fail(RTM_E_INVAL, "%s %d at (%d, %d) is outside the %d x %d grid", what, i, pts[i].iz, pts[i].ix, nz,
+                  nx);
+    out[i] = make_int2(pts[i].iz, pts[i].ix);
+  }
+  return RTM_OK;
+}
+
+extern "C" int rtm_eikonal(rtm_ctx* ctx, const float* vel_dev, int32_t nz, int32_t nx, float h, int32_t nsrc,
+                           const rtm_point* src_host, int32_t nrec, const rtm_point* rec_host, float* tt_dev) {
+  if (!ctx || !vel_dev || !tt_dev) return fail(RTM_E_INVAL, "bad arguments");
+  if (nz < 1 || nx < 1 || (int64_t)nz * nx > kBetMaxNodes || !(h > 0) || !std::isfinite(h))
+    return fail(RTM_E_INVAL, "grid %d x %d, h %g: need 1..%d nodes and h > 0", nz, nx, (double)h, kBetMaxNodes);
+  std::vector<int2> src, rec;
+  if (int st = bet_points(src_host, nsrc, nz, nx, "source", src)) return st;
+  if (int st = bet_points(rec_host, nrec, nz, nx, "receiver", rec)) return st;
+  HIP_OK(hipSetDevice(ctx->device));
+  const size_t bs = align256(8 * (size_t)nsrc), br = align256(8 * (size_t)nrec);
+  char* buf = static_cast<char*>(arena_alloc(ctx, bs + br + 256));
+  if (!buf) return fail(RTM_E_NOMEM, "arena exhausted (travel-time geometry)");
+  hipStream_t s = ctx->stream;
+  uint32_t* flags = reinterpret_cast<uint32_t*>(buf + bs + br);
+  uint32_t flag = 0;
+  hipError_t e = hipMemcpyAsync(buf, src.data(), 8 * (size_t)nsrc, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf + bs, rec.data(), 8 * (size_t)nrec, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_u32(flags, 0, 1, s);
+  if (e == hipSuccess)
+    e = launch_eikonal_grid(vel_dev, nz, nx, h, reinterpret_cast<int2*>(buf), nsrc, reinterpret_cast<int2*>(buf + bs),
+                            nrec, tt_dev, flags, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flag, flags, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ctx->arena.release(buf, align256(bs + br + 256));
+  if (e != hipSuccess) return fail(RTM_E_DEVICE, "travel times: %s", hipGetErrorString(e));
+  if (flag & kBetNoConverge) return fail(RTM_E_DEVICE, "a travel-time solve did not converge");
+  return RTM_OK;
+}
+
+extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t nsrc, const rtm_point* src_host,
+                              int32_t nrec, const rtm_point* rec_host, const float* tt_obs_dev, rtm_bet** out) {
+  if (!ctx || !cfg || !tt_obs_dev || !out) return fail(RTM_E_INVAL, "bad arguments");
+  *out = nullptr;
+  const rtm_bet_config& c = *cfg;
+  if (c.nz < 2 || c.nx < 2 || (int64_t)c.nz * c.nx > kBetMaxNodes || !(c.h > 0) || !std::isfinite(c.h))
+    return fail(RTM_E_INVAL, "grid %d x %d, h %g: need 2..%d nodes per side product and h > 0", c.nz, c.nx, c.h,
+                kBetMaxNodes);
+  if (c.chains < 1 || c.k_min < 1 || c.k_init < c.k_min || c.k_max < c.k_init || c.k_max > kBetMaxCells)
+    return fail(RTM_E_INVAL, "need chains >= 1 and 1 <= k_min <= k_init <= k_max <= %d", kBetMaxCells);
+  if (!(c.v_min > 0) || !(c.v_max > c.v_min) || !std::isfinite(c.v_max))
+    return fail(RTM_E_INVAL, "need 0 < v_min < v_max");
+  if (!(c.p_birth >= 0) || !(c.p_death >= 0) || !(c.p_birth + c.p_death <= 1.0))
+    return fail(RTM_E_INVAL, "need p_birth, p_death >= 0 with p_birth + p_death <= 1");
+  if (!(c.move_dz >= 0) || !(c.move_dx >= 0) || !(c.sigma > 0) || !std::isfinite(c.sigma) || c.burn_in < 0 ||
+      c.thin < 1)
+    return fail(RTM_E_INVAL, "need move half-widths >= 0, sigma > 0, burn_in >= 0, thin >= 1");
+  std::vector<int2> src, rec;
+  if (int st = bet_points(src_host, nsrc, c.nz, c.nx, "source", src)) return st;
+  if (int st = bet_points(rec_host, nrec, c.nz, c.nx, "receiver", rec)) return st;
+  HIP_OK(hipSetDevice(ctx->device));
+  auto b = std::make_unique<rtm_bet>();
+  BetDev& d = b->d;
+  d.nz = c.nz;
+  d.nx = c.nx;
+  d.nsrc = nsrc;
+  d.nrec = nrec;
+  d.h = c.h;
+  d.chains = c.chains;
+  d.k_min = c.k_min;
+  d.k_max = c.k_max;
+  d.k_init = c.k_init;
+  d.burn_in = c.burn_in;
+  d.thin = c.thin;
+  d.v_min = c.v_min;
+  d.v_max = c.v_max;
+  d.p_birth = c.p_birth;
+  d.p_death = c.p_death;
+  d.move_dz = c.move_dz;
+  d.move_dx = c.move_dx;
+  d.sigma = c.sigma;
+  d.seed = c.seed;
+  const size_t C = c.chains, K = c.k_max, n = (size_t)c.nz * c.nx, nd = (size_t)nsrc * nrec;
+  bool ok = true;
+  auto get = [&](size_t bytes) -> void* {
+    void* q = nullptr;
+    if (ok && !alloc_block(ctx, b->blocks, bytes, &q)) ok = false;
+    return q;
+  };
+  d.src = static_cast<const int2*>(get(8 * (size_t)nsrc));
+  d.rec = static_cast<const int2*>(get(8 * (size_t)nrec));
+  d.tt_obs = static_cast<const float*>(get(4 * nd));
+  d.k = static_cast<int32_t*>(get(4 * C));
+  d.z = static_cast<double*>(get(8 * C * K));
+  d.x = static_cast<double*>(get(8 * C * K));
+  d.v = static_cast<double*>(get(8 * C * K));
+  d.misfit = static_cast<double*>(get(8 * C));
+  d.pk = static_cast<int32_t*>(get(4 * C));
+  d.valid = static_cast<int32_t*>(get(4 * C));
+  d.ptype = static_cast<int32_t*>(get(4 * C));
+  d.pz = static_cast<double*>(get(8 * C * K));
+  d.px = static_cast<double*>(get(8 * C * K));
+  d.pv = static_cast<double*>(get(8 * C * K));
+  d.ua = static_cast<double*>(get(8 * C));
+  d.cell = static_cast<uint8_t*>(get(C * n));
+  d.tt = static_cast<float*>(get(4 * C * nd));
+  d.proposed = static_cast<int64_t*>(get(8 * 3 * C));
+  d.accepted = static_cast<int64_t*>(get(8 * 3 * C));
+  d.mean = static_cast<double*>(get(8 * n));
+  d.m2 = static_cast<double*>(get(8 * n));
+  d.count = static_cast<int32_t*>(get(4 * n));
+  d.flags = static_cast<uint32_t*>(get(256));
+  if (!ok) {
+    release_blocks(ctx, b->blocks);
+    return fail(RTM_E_NOMEM, "arena exhausted (sampler state)");
+  }
+  hipStream_t s = ctx->stream;
+  HIP_OK(hipMemcpyAsync(const_cast<int2*>(d.src), src.data(), 8 * (size_t)nsrc, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(const_cast<int2*>(d.rec), rec.data(), 8 * (size_t)nrec, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(const_cast<float*>(d.tt_obs), tt_obs_dev, 4 * nd, hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipMemsetAsync(d.proposed, 0, 8 * 3 * C, s));
+  HIP_OK(hipMemsetAsync(d.accepted, 0, 8 * 3 * C, s));
+  HIP_OK(hipMemsetAsync(d.mean, 0, 8 * n, s));
+  HIP_OK(hipMemsetAsync(d.m2, 0, 8 * n, s));
+  HIP_OK(hipMemsetAsync(d.count, 0, 4 * n, s));
+  HIP_OK(hipMemsetAsync(d.flags, 0, 256, s));
+  // the initial model of every chain and its misfit
+  HIP_OK(launch_bet_propose(d, -1, 1, s));
+  HIP_OK(launch_bet_raster(d, s));
+  HIP_OK(launch_bet_eikonal(d, s));
+  HIP_OK(launch_bet_accept(d, 1, nullptr, s));
+  // the host vectors above are copied from before this call returns
+  HIP_OK(hipStreamSynchronize(s));
+  *out = b.release();
+  return RTM_OK;
+}
+
+extern "C" int rtm_bet_run(rtm_ctx* ctx, rtm_bet* bet, int32_t iterations, int8_t* log_dev) {
+  if (!ctx || !bet || iterations < 0) return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const BetDev& d = bet->d;
+  for (int it = 0; it < iterations; ++it) {
+    const int t = bet->t + it;
+    HIP_OK(launch_bet_propose(d, t, 0, s));
+    HIP_OK(launch_bet_raster(d, s));
+    HIP_OK(launch_bet_eikonal(d, s));
+    HIP_OK(launch_bet_accept(d, 0, log_dev ? log_dev + (size_t)it * d.chains : nullptr, s));
+    if (t >= d.burn_in && (t - d.burn_in) % d.thin == 0) HIP_OK(launch_bet_sample(d, s));
+  }
+  bet->t += iterations;
+  return RTM_OK;
+}
+
+extern "C" int rtm_bet_chain(rtm_ctx* ctx, rtm_bet* bet, int32_t chain, rtm_bet_chain_info* info, double* z_host,
+                             double* x_host, double* v_host) {
+  if (!ctx || !bet || !info || chain < 0 || chain >= bet->d.chains) return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  const BetDev& d = bet->d;
+  hipStream_t s = ctx->stream;
+  const size_t K = d.k_max;
+  uint32_t flag = 0;
+  memset(info, 0, sizeof *info);
+  HIP_OK(hipMemcpyAsync(&info->k, d.k + chain, 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&info->misfit, d.misfit + chain, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(info->proposed, d.proposed + 3 * (size_t)chain, 24, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(info->accepted, d.accepted + 3 * (size_t)chain, 24, hipMemcpyDeviceToHost, s));
+  if (z_host) HIP_OK(hipMemcpyAsync(z_host, d.z + chain * K, 8 * K, hipMemcpyDeviceToHost, s));
+  if (x_host) HIP_OK(hipMemcpyAsync(x_host, d.x + chain * K, 8 * K, hipMemcpyDeviceToHost, s));
+  if (v_host) HIP_OK(hipMemcpyAsync(v_host, d.v + chain * K, 8 * K, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&flag, d.flags, 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (flag & kBetNoConverge) return fail(RTM_E_DEVICE, "a travel-time solve did not converge");
+  return RTM_OK;
+}
+
+extern "C" int rtm_bet_stats(rtm_ctx* ctx, rtm_bet* bet, double* mean_dev, double* std_dev, int32_t* count_dev) {
+  if (!ctx || !bet) return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  const BetDev& d = bet->d;
+  HIP_OK(launch_stats_out(d.mean, d.m2, d.count, (int64_t)d.nz * d.nx, mean_dev, std_dev, count_dev, ctx->stream));
+  return RTM_OK;
+}
+
+extern "C" int rtm_bet_destroy(rtm_ctx* ctx, rtm_bet* bet) {
+  if (!ctx || !bet) return fail(RTM_E_INVAL, "bad arguments");
+  Deferred dd;
+  dd.blocks = std::move(bet->blocks);
+  delete bet;
+  return defer(ctx, ctx->stream, std::move(dd));
 }
 
 extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {

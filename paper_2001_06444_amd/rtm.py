@@ -77,6 +77,18 @@ class CtxStats(ctypes.Structure):
         ("last_codec_bytes", ctypes.c_uint64)]
 
 
+class BetConfig(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("nz", "nx", "chains", "k_min", "k_max", "k_init", "burn_in",
+                                              "thin")] + \
+               [(n, ctypes.c_double) for n in ("h", "v_min", "v_max", "p_birth", "p_death", "move_dz",
+                                               "move_dx", "sigma")] + [("seed", ctypes.c_uint64)]
+
+
+class BetChainInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("pad_", ctypes.c_int32), ("misfit", ctypes.c_double),
+                ("proposed", ctypes.c_int64 * 3), ("accepted", ctypes.c_int64 * 3)]
+
+
 # exported symbols and their C signatures (argtypes, restype)
 _P, _V, _I32, _U32, _U64, _F, _D = (ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float,
@@ -118,6 +130,12 @@ SIGNATURES = {
     "rtm_codec_info": ([_V, _V, ctypes.c_int64, _P(_I32), _P(_I32), _P(_I32), _P(_I32), _P(_D)],
                        ctypes.c_int),
     "rtm_codec_decode": ([_V, _V, ctypes.c_int64, _V, ctypes.c_int64], ctypes.c_int),
+    "rtm_eikonal": ([_V, _V, _I32, _I32, _F, _I32, _P(Point), _I32, _P(Point), _V], ctypes.c_int),
+    "rtm_bet_create": ([_V, _P(BetConfig), _I32, _P(Point), _I32, _P(Point), _V, _P(_V)], ctypes.c_int),
+    "rtm_bet_run": ([_V, _V, _I32, _V], ctypes.c_int),
+    "rtm_bet_chain": ([_V, _V, _I32, _P(BetChainInfo), _V, _V, _V], ctypes.c_int),
+    "rtm_bet_stats": ([_V, _V, _V, _V, _V], ctypes.c_int),
+    "rtm_bet_destroy": ([_V, _V], ctypes.c_int),
     "rtm_ctx_stats": ([_V, _P(CtxStats)], ctypes.c_int),
 }
 
@@ -362,6 +380,50 @@ class Context:
             out = torch.empty(shape, dtype=torch.float32, device=stream.device)
         _check(lib().rtm_codec_decode(self.h, _ptr(stream), stream.numel(), _ptr(out), out.numel()))
         return out
+
+    # ---- Stage 1: Bayesian Eikonal tomography ----
+    def eikonal(self, vel, h, srcs, recs, out=None):
+        """First-arrival times [nsrc][nrec] of the velocity grid `vel` (float32 device tensor)."""
+        import torch
+        nz, nx = vel.shape
+        sp, ns = _points(srcs)
+        rp, nr = _points(recs)
+        if out is None:
+            out = torch.empty(ns, nr, dtype=torch.float32, device=vel.device)
+        _check(lib().rtm_eikonal(self.h, _ptr(vel), nz, nx, float(h), ns, sp, nr, rp, _ptr(out)))
+        return out
+
+    def bet_create(self, srcs, recs, tt_obs, **cfg):
+        """Sampler over the observed travel times tt_obs [nsrc][nrec] (device tensor).
+        cfg: nz, nx, h, chains, k_min, k_max, k_init, burn_in, thin, v_min, v_max,
+        p_birth, p_death, move_dz, move_dx, sigma, seed."""
+        c = BetConfig()
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        sp, ns = _points(srcs)
+        rp, nr = _points(recs)
+        h = ctypes.c_void_p()
+        _check(lib().rtm_bet_create(self.h, ctypes.byref(c), ns, sp, nr, rp, _ptr(tt_obs), ctypes.byref(h)))
+        return h
+
+    def bet_run(self, bet, iterations, log=None):
+        _check(lib().rtm_bet_run(self.h, bet, int(iterations), _ptr(log)))
+
+    def bet_chain(self, bet, chain, k_max):
+        import numpy as np
+        info = BetChainInfo()
+        z, x, v = (np.zeros(k_max) for _ in range(3))
+        _check(lib().rtm_bet_chain(self.h, bet, int(chain), ctypes.byref(info),
+                                   z.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p),
+                                   v.ctypes.data_as(ctypes.c_void_p)))
+        return {"k": info.k, "misfit": info.misfit, "proposed": list(info.proposed),
+                "accepted": list(info.accepted), "z": z, "x": x, "v": v}
+
+    def bet_stats(self, bet, mean=None, std=None, count=None):
+        _check(lib().rtm_bet_stats(self.h, bet, _ptr(mean), _ptr(std), _ptr(count)))
+
+    def bet_destroy(self, bet):
+        _check(lib().rtm_bet_destroy(self.h, bet))
 
     def stats(self) -> CtxStats:
         s = CtxStats()
