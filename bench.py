@@ -97,7 +97,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["survey", "ensemble", "serve", "small", "born", "codec"],
+    ap.add_argument("--workload", choices=["survey", "ensemble", "serve", "small", "born", "codec", "bet"],
                     default="survey")
     ap.add_argument("--shots", type=int, default=100)
     ap.add_argument("--nt", type=int, default=None, help="default: 4000 survey, 3000 ensemble")
@@ -109,6 +109,8 @@ def parse():
                          "for the HBM byte counters)")
     ap.add_argument("--realizations", type=int, default=64, help="ensemble / codec workload")
     ap.add_argument("--seismograms", type=int, default=16, help="codec workload")
+    ap.add_argument("--chains", type=int, default=64, help="bet workload")
+    ap.add_argument("--bet-iters", type=int, default=20, help="bet workload: iterations per step")
     ap.add_argument("--serve-jobs", type=int, default=300, help="serve workload: timed jobs")
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: jobs/s")
@@ -134,7 +136,7 @@ def main():
         del src_t, dst_t
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
     out = {"survey": run_survey, "ensemble": run_ensemble, "serve": run_serve,
-           "small": run_small, "born": run_born, "codec": run_codec}[args.workload](args)
+           "small": run_small, "born": run_born, "codec": run_codec, "bet": run_bet}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 
@@ -729,6 +731,111 @@ def run_codec(args):
                        "note": "algorithmic bytes: 4 B per value plus the stream length; HIP events "
                                "around the launch on the library's stream"}
     out["codec"] = table
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    return out
+
+
+FLOP_PER_NODE_UPDATE = 10  # Godunov update: 3 min, d, compare, q, q + q, d d, difference, sqrt, sum, halving
+
+
+def bet_cpu_baseline(p, tt_obs, budget_s=12.0):
+    """The Stage-1 oracle running chain 0 alone (single thread) for a bounded time."""
+    from oracle import bet as obet
+
+    c = p["cfg"]
+    cfg = obet.BetConfig(nz=c["nz"], nx=c["nx"], h=c["h"], chains=1, k_min=c["k_min"], k_max=c["k_max"],
+                         k_init=c["k_init"], v_min=c["v_min"], v_max=c["v_max"], p_birth=c["p_birth"],
+                         p_death=c["p_death"], move_dz=c["move_dz"], move_dx=c["move_dx"], sigma=c["sigma"],
+                         seed=c["seed"], burn_in=c["burn_in"], thin=c["thin"], single=True)
+    iters, el = 10, 0.0
+    while True:
+        t0 = time.perf_counter()
+        obet.run(cfg, p["srcs"], p["recs"], tt_obs, iters)
+        el = time.perf_counter() - t0
+        if el >= budget_s / 3 or iters >= 4000:
+            break
+        iters *= 2
+    return {"value": iters / el, "unit": "chain iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"chain 0 alone, {iters} iterations from its initial model (34 FP32 fast-sweeping "
+                      f"solves per valid proposal), {el:.1f} s"}
+
+
+def run_bet(args):
+    """Stage 1 (Sec. 2.1): reversible-jump chains over Voronoi velocity models
+    with Eikonal travel times.  One step = --bet-iters iterations of every chain."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06444_amd import inputs, rtm
+
+    p = inputs.bet_problem(args.chains)
+    c = p["cfg"]
+    n = c["nz"] * c["nx"]
+    ctx = rtm.Context(0, arena_bytes=256 << 20)
+    true = torch.as_tensor(p["true"], dtype=torch.float32, device="cuda")
+    tt_obs = ctx.eikonal(true, p["h"], p["srcs"], p["recs"])
+    b = ctx.bet_create(p["srcs"], p["recs"], tt_obs, **c)
+
+    def work():
+        tot = np.zeros(2, dtype=np.int64)
+        info = []
+        for ch in range(c["chains"]):
+            g = ctx.bet_chain(b, ch, c["k_max"])
+            tot += (g["solves"], g["sweep_passes"])
+            info.append(g)
+        return tot, info
+
+    for _ in range(args.warmup):
+        ctx.bet_run(b, args.bet_iters)
+    torch.cuda.synchronize()
+    w0, _ = work()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.bet_run(b, args.bet_iters)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    w1, info = work()
+    st = ctx.stats()
+    iters = args.bet_iters * args.steps
+    solves, passes = (w1 - w0).tolist()
+    node_updates = passes * 4 * n
+    per_iter_updates = node_updates / iters
+    eik_ms = st.last_bet_eikonal_ms
+    achieved = per_iter_updates * FLOP_PER_NODE_UPDATE / (eik_ms * 1e-3) / 1e12
+    mean = torch.empty(n, dtype=torch.float64, device="cuda")
+    std = torch.empty_like(mean)
+    ctx.bet_stats(b, mean, std)
+    misfits = np.array([g["misfit"] for g in info])
+    prop = sum(sum(g["proposed"]) for g in info)
+    acc = sum(sum(g["accepted"]) for g in info)
+    log(f"[bench] bet: {c['chains']} chains x {iters} iterations in {el:.3f} s; {solves} solves, "
+        f"{passes / max(solves, 1):.2f} passes per solve; travel-time launch {eik_ms:.3f} ms of "
+        f"{st.last_bet_iteration_ms:.3f} ms per iteration; acceptance {acc / max(prop, 1):.3f}; "
+        f"median misfit per datum {np.median(misfits) / (len(p['srcs']) * len(p['recs'])):.2f}")
+    cpu = None if args.no_cpu_baseline else bet_cpu_baseline(p, tt_obs.cpu().numpy())
+    ctx.bet_destroy(b)
+    ctx.close()
+    out = _base_record(args, c["chains"] * iters / el, el * 1e3 / args.steps, {
+        "workload": f"Bayesian Eikonal tomography: {c['chains']} reversible-jump chains, Voronoi models "
+                    f"(k {c['k_min']}..{c['k_max']}) on {c['nz']}x{c['nx']} nodes at {c['h']:g} m, "
+                    f"{len(p['srcs'])} surface sources x {len(p['recs'])} receivers, {args.bet_iters} "
+                    f"iterations per step",
+        "path": "rtm_bet_run (propose, raster, travel times, accept, sample per iteration)"},
+        unit="chain iterations/s")
+    out["metric"] = "Stage-1 chain iterations/s (each: one model, 34 travel-time solves)"
+    out["dtype"] = "f32 travel times, f64 misfit and statistics"
+    out["solves_per_s"] = solves / el
+    out["node_updates_per_s"] = node_updates / el
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                       "frac": achieved / 157.3, "traffic": None, "kernel": "k_bet_eikonal",
+                       "launch_us": eik_ms * 1e3,
+                       "note": f"{FLOP_PER_NODE_UPDATE} FP32 operations per node update x node updates of one "
+                               "launch (solves x sweep passes x 4 x nodes, averaged over the timed iterations) "
+                               "/ the launch's HIP-event time; FP32 vector peak 256 CUs x 2.4 GHz x 256; "
+                               "the sweeps are bound by the latency of dependent diagonals in LDS"}
+    out["acceptance"] = acc / max(prop, 1)
+    out["velocity_std_mean"] = float(std.mean())
     if cpu is not None:
         out["cpu_baseline"] = cpu
     return out

@@ -417,6 +417,8 @@ typedef struct {
     int32_t pad_;
     double misfit;                  /* Phi of the current model */
     int64_t proposed[3], accepted[3];  /* birth, death, move (valid proposals) */
+    int64_t solves;                 /* travel-time solves (one per source per valid proposal) */
+    int64_t sweep_passes;           /* fast-sweeping passes of those solves (4 sweeps each) */
 } rtm_bet_chain_info;
 
 typedef struct rtm_bet rtm_bet;
@@ -476,6 +478,9 @@ typedef struct {
     float last_codec_ms;
     int32_t last_codec_op;
     uint64_t last_codec_bytes;
+    /* last rtm_bet_run call: HIP-event time of the travel-time launch and of
+     * all launches of its last iteration */
+    float last_bet_eikonal_ms, last_bet_iteration_ms;
 } rtm_ctx_stats_t;
 
 int rtm_ctx_stats(rtm_ctx *ctx, rtm_ctx_stats_t *out);

@@ -33,8 +33,10 @@ struct BetDev {
   double *pz, *px, *pv, *ua;
   uint8_t* cell;   // [chains][nz*nx] nearest nucleus of the proposal
   float* tt;       // [chains][nsrc][nrec] travel times of the proposal
-  // counters [chains][3] (birth, death, move)
+  // counters [chains][3] (birth, death, move); work [chains][2]: travel-time
+  // solves, sweep passes
   int64_t *proposed, *accepted;
+  unsigned long long* work;
   // pooled post-burn-in statistics of the velocity grid
   double *mean, *m2;
   int32_t* count;

@@ -104,7 +104,85 @@ __device__ int fsm_solve(float* T, int nz, int nx, float h, int si, int sj, Slow
   return pass;
 }
 
-__device__ inline size_t bet_lds_t_bytes(int n) { return ((size_t)n * 4 + 15) & ~(size_t)15; }
+// The same sweeps with one row per lane (nz <= 64): in ordering (fi, fj) lane
+// l owns the l-th row in sweep order and handles its column jj at step l + jj,
+// which is the anti-diagonal schedule above.  A node's upwind neighbours were
+// updated one step earlier -- the one in its row by this lane (kept in a
+// register), the one in the previous row by lane l - 1 (a lane shift) -- and
+// its downwind neighbours still hold their values from before this sweep
+// (LDS that no lane overwrites before it has been read).  A step has no
+// branches: reads use clamped in-bounds nodes and selects drop what lies
+// outside the grid.
+// lane l receives lane l - 1's value (lane 0 receives `edge`): a DPP wave
+// shift, no LDS round trip
+__device__ inline float from_lane_below(float v, float edge) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138 /* wave_shr:1 */,
+                                                    0xF, 0xF, false));
+}
+
+// Godunov value without branches: both forms computed, one selected (the
+// same value as godunov())
+__device__ inline float godunov_sel(float a, float b, float sh) {
+  const float lo = a > b ? b : a, hi = a > b ? a : b;
+  const float d = hi - lo;
+  const float q = sh * sh;
+  const float two = ((lo + hi) + sqrtf((q + q) - d * d)) * 0.5f;
+  return !(d < sh) ? lo + sh : two;
+}
+
+template <class Slow>
+__device__ int fsm_solve_rows(float* T, int nz, int nx, float h, int si, int sj, Slow slow) {
+  const int lane = threadIdx.x & 63;
+  const int n = nz * nx;
+  for (int p = lane; p < n; p += 64) T[p] = INFINITY;
+  wave_sync();
+  if (lane == 0) T[si * nx + sj] = 0.0f;
+  wave_sync();
+  const bool row_ok = lane < nz;
+  const bool has_dn = lane + 1 < nz;
+  int pass = 0;
+  for (; pass < kBetMaxSweeps; ++pass) {
+    bool changed = false;
+    for (int o = 0; o < 4; ++o) {
+      const bool fi = (o == 0 || o == 3), fj = (o < 2);
+      // lanes past the last row read row 0 and never change it
+      const int i = row_ok ? (fi ? lane : nz - 1 - lane) : 0;
+      const int idn = has_dn ? (fi ? i + 1 : i - 1) : i;  // the next row in sweep order
+      float cur = INFINITY;  // this lane's node of the previous step
+      for (int step = 0; step <= nz + nx - 2; ++step) {
+        const int jj = step - lane;
+        const bool active = row_ok && jj >= 0 && jj < nx;
+        const int jc = jj < 0 ? 0 : (jj >= nx ? nx - 1 : jj);
+        const int j = fj ? jc : nx - 1 - jc;
+        const int p = i * nx + j;
+        const int pr = jc + 1 < nx ? (fj ? p + 1 : p - 1) : p;
+        const float dn_v = T[idn * nx + j], rt_v = T[pr], old = T[p];
+        const float sl = slow(p);
+        const float above = from_lane_below(cur, INFINITY);
+        // up/left are this sweep's upwind times, dn/rt the downwind ones
+        const float up = lane > 0 ? above : INFINITY;
+        const float dn = has_dn ? dn_v : INFINITY;
+        const float rt = jc + 1 < nx ? rt_v : INFINITY;
+        const float left = jj > 0 ? cur : INFINITY;
+        const float a = fi ? (up < dn ? up : dn) : (dn < up ? dn : up);
+        const float b = fj ? (left < rt ? left : rt) : (rt < left ? rt : left);
+        const float t = godunov_sel(a, b, sl * h);
+        const bool better = active && t < old;
+        cur = better ? t : old;
+        // a lane with a row stores its own node (unchanged when inactive); a
+        // lane past the last row stores to the discard slot T[n]
+        T[row_ok ? p : n] = cur;
+        changed |= better;
+      }
+      wave_sync();
+    }
+    if (!__any(changed)) break;
+  }
+  return pass;
+}
+
+// T[n + 1]: the grid's times and a discard slot
+__device__ inline size_t bet_lds_t_bytes(int n) { return ((size_t)(n + 1) * 4 + 15) & ~(size_t)15; }
 __device__ inline size_t bet_lds_c_bytes(int n) { return ((size_t)n + 15) & ~(size_t)15; }
 
 }  // namespace
@@ -223,8 +301,14 @@ __global__ __launch_bounds__(64) void k_bet_eikonal(BetDev d) {
   for (int q = lane; q < kk; q += 64) stab[q] = (float)(1.0 / d.pv[(size_t)c * d.k_max + q]);
   wave_sync();
   const int2 s = d.src[e];
-  const int passes = fsm_solve(T, d.nz, d.nx, (float)d.h, s.x, s.y, [&](int p) { return stab[cid[p]]; });
-  if (passes >= kBetMaxSweeps && lane == 0) atomicOr(d.flags, kBetNoConverge);
+  auto slow = [&](int p) { return stab[cid[p]]; };
+  const int passes = d.nz <= 64 ? fsm_solve_rows(T, d.nz, d.nx, (float)d.h, s.x, s.y, slow)
+                                : fsm_solve(T, d.nz, d.nx, (float)d.h, s.x, s.y, slow);
+  if (lane == 0) {
+    if (passes >= kBetMaxSweeps) atomicOr(d.flags, kBetNoConverge);
+    atomicAdd(d.work + 2 * (size_t)c, 1ull);
+    atomicAdd(d.work + 2 * (size_t)c + 1, (unsigned long long)min(passes + 1, kBetMaxSweeps));
+  }
   float* out = d.tt + ((size_t)c * d.nsrc + e) * d.nrec;
   for (int r = lane; r < d.nrec; r += 64) {
     const int2 q = d.rec[r];
@@ -323,7 +407,8 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
   for (int p = lane; p < n; p += 64) S[p] = (float)(1.0 / (double)vel[p]);
   wave_sync();
   const int2 s = src[e];
-  const int passes = fsm_solve(T, nz, nx, h, s.x, s.y, [&](int p) { return S[p]; });
+  auto slow = [&](int p) { return S[p]; };
+  const int passes = nz <= 64 ? fsm_solve_rows(T, nz, nx, h, s.x, s.y, slow) : fsm_solve(T, nz, nx, h, s.x, s.y, slow);
   if (passes >= kBetMaxSweeps && lane == 0) atomicOr(flags, kBetNoConverge);
   for (int r = lane; r < nrec; r += 64) {
     const int2 q = rec[r];
@@ -331,8 +416,10 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
   }
 }
 
-static size_t lds_bet(int n) { return (((size_t)n * 4 + 15) & ~(size_t)15) + (((size_t)n + 15) & ~(size_t)15) + 4 * kBetMaxCells; }
-static size_t lds_grid(int n) { return 2 * (((size_t)n * 4 + 15) & ~(size_t)15); }
+static size_t lds_bet(int n) {
+  return (((size_t)(n + 1) * 4 + 15) & ~(size_t)15) + (((size_t)n + 15) & ~(size_t)15) + 4 * kBetMaxCells;
+}
+static size_t lds_grid(int n) { return (((size_t)(n + 1) * 4 + 15) & ~(size_t)15) + (((size_t)n * 4 + 15) & ~(size_t)15); }
 
 hipError_t launch_bet_propose(const BetDev& d, int t, int init, hipStream_t s) {
   k_bet_propose<<<(d.chains + 63) / 64, 64, 0, s>>>(d, t, init);

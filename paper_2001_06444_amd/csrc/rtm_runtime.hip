@@ -244,6 +244,10 @@ struct rtm_ctx {
   hipEvent_t zc_ev[2] = {nullptr, nullptr};
   int zc_op = 0;
   uint64_t zc_bytes = 0;
+  // last rtm_bet_run call: events around its last iteration (start, before and
+  // after the travel-time launch, end)
+  hipEvent_t bet_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool bet_valid = false;
 };
 
 // ---- deferred frees ----
@@ -814,6 +818,7 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
   for (auto& e : ctx->ph_ev) HIP_OK(hipEventCreate(&e));
   for (auto& e : ctx->zc_ev) HIP_OK(hipEventCreate(&e));
+  for (auto& e : ctx->bet_ev) HIP_OK(hipEventCreate(&e));
   ctx->scratch_u32 = static_cast<uint32_t*>(ctx->arena.alloc(256));
   ctx->scratch_f64 = static_cast<double*>(ctx->arena.alloc(256));
   HIP_OK(hipMemset(ctx->scratch_u32, 0, 256));
@@ -866,6 +871,7 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
   (void)hipEventDestroy(ctx->ev_out);
   for (auto e : ctx->ph_ev) (void)hipEventDestroy(e);
   for (auto e : ctx->zc_ev) (void)hipEventDestroy(e);
+  for (auto e : ctx->bet_ev) (void)hipEventDestroy(e);
   if (ctx->own_arena) (void)hipFree(ctx->own_arena);
   delete ctx;
   return RTM_OK;
@@ -2054,6 +2060,7 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   d.tt = static_cast<float*>(get(4 * C * nd));
   d.proposed = static_cast<int64_t*>(get(8 * 3 * C));
   d.accepted = static_cast<int64_t*>(get(8 * 3 * C));
+  d.work = static_cast<unsigned long long*>(get(8 * 2 * C));
   d.mean = static_cast<double*>(get(8 * n));
   d.m2 = static_cast<double*>(get(8 * n));
   d.count = static_cast<int32_t*>(get(4 * n));
@@ -2068,6 +2075,7 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   HIP_OK(hipMemcpyAsync(const_cast<float*>(d.tt_obs), tt_obs_dev, 4 * nd, hipMemcpyDeviceToDevice, s));
   HIP_OK(hipMemsetAsync(d.proposed, 0, 8 * 3 * C, s));
   HIP_OK(hipMemsetAsync(d.accepted, 0, 8 * 3 * C, s));
+  HIP_OK(hipMemsetAsync(d.work, 0, 8 * 2 * C, s));
   HIP_OK(hipMemsetAsync(d.mean, 0, 8 * n, s));
   HIP_OK(hipMemsetAsync(d.m2, 0, 8 * n, s));
   HIP_OK(hipMemsetAsync(d.count, 0, 4 * n, s));
@@ -2090,12 +2098,18 @@ extern "C" int rtm_bet_run(rtm_ctx* ctx, rtm_bet* bet, int32_t iterations, int8_
   const BetDev& d = bet->d;
   for (int it = 0; it < iterations; ++it) {
     const int t = bet->t + it;
+    const bool last = it == iterations - 1;
+    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[0], s));
     HIP_OK(launch_bet_propose(d, t, 0, s));
     HIP_OK(launch_bet_raster(d, s));
+    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[1], s));
     HIP_OK(launch_bet_eikonal(d, s));
+    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[2], s));
     HIP_OK(launch_bet_accept(d, 0, log_dev ? log_dev + (size_t)it * d.chains : nullptr, s));
     if (t >= d.burn_in && (t - d.burn_in) % d.thin == 0) HIP_OK(launch_bet_sample(d, s));
+    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[3], s));
   }
+  if (iterations > 0) ctx->bet_valid = true;
   bet->t += iterations;
   return RTM_OK;
 }
@@ -2113,6 +2127,7 @@ extern "C" int rtm_bet_chain(rtm_ctx* ctx, rtm_bet* bet, int32_t chain, rtm_bet_
   HIP_OK(hipMemcpyAsync(&info->misfit, d.misfit + chain, 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(info->proposed, d.proposed + 3 * (size_t)chain, 24, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(info->accepted, d.accepted + 3 * (size_t)chain, 24, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&info->solves, d.work + 2 * (size_t)chain, 16, hipMemcpyDeviceToHost, s));
   if (z_host) HIP_OK(hipMemcpyAsync(z_host, d.z + chain * K, 8 * K, hipMemcpyDeviceToHost, s));
   if (x_host) HIP_OK(hipMemcpyAsync(x_host, d.x + chain * K, 8 * K, hipMemcpyDeviceToHost, s));
   if (v_host) HIP_OK(hipMemcpyAsync(v_host, d.v + chain * K, 8 * K, hipMemcpyDeviceToHost, s));
@@ -2164,6 +2179,15 @@ extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
       out->last_bwd_launches = ctx->ph_launches[1];
       out->last_fwd_launch_bytes = ctx->ph_bytes[0];
       out->last_bwd_launch_bytes = ctx->ph_bytes[1];
+    }
+  }
+  if (ctx->bet_valid) {
+    float a = 0, b = 0;
+    if (hipEventSynchronize(ctx->bet_ev[3]) == hipSuccess &&
+        hipEventElapsedTime(&a, ctx->bet_ev[1], ctx->bet_ev[2]) == hipSuccess &&
+        hipEventElapsedTime(&b, ctx->bet_ev[0], ctx->bet_ev[3]) == hipSuccess) {
+      out->last_bet_eikonal_ms = a;
+      out->last_bet_iteration_ms = b;
     }
   }
   if (ctx->zc_op) {

@@ -74,7 +74,8 @@ class CtxStats(ctypes.Structure):
         ("last_fwd_launches", ctypes.c_int32), ("last_bwd_launches", ctypes.c_int32),
         ("last_fwd_launch_bytes", ctypes.c_uint64), ("last_bwd_launch_bytes", ctypes.c_uint64),
         ("last_codec_ms", ctypes.c_float), ("last_codec_op", ctypes.c_int32),
-        ("last_codec_bytes", ctypes.c_uint64)]
+        ("last_codec_bytes", ctypes.c_uint64),
+        ("last_bet_eikonal_ms", ctypes.c_float), ("last_bet_iteration_ms", ctypes.c_float)]
 
 
 class BetConfig(ctypes.Structure):
@@ -86,7 +87,8 @@ class BetConfig(ctypes.Structure):
 
 class BetChainInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("pad_", ctypes.c_int32), ("misfit", ctypes.c_double),
-                ("proposed", ctypes.c_int64 * 3), ("accepted", ctypes.c_int64 * 3)]
+                ("proposed", ctypes.c_int64 * 3), ("accepted", ctypes.c_int64 * 3),
+                ("solves", ctypes.c_int64), ("sweep_passes", ctypes.c_int64)]
 
 
 # exported symbols and their C signatures (argtypes, restype)
@@ -417,7 +419,8 @@ class Context:
                                    z.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p),
                                    v.ctypes.data_as(ctypes.c_void_p)))
         return {"k": info.k, "misfit": info.misfit, "proposed": list(info.proposed),
-                "accepted": list(info.accepted), "z": z, "x": x, "v": v}
+                "accepted": list(info.accepted), "solves": info.solves, "sweep_passes": info.sweep_passes,
+                "z": z, "x": x, "v": v}
 
     def bet_stats(self, bet, mean=None, std=None, count=None):
         _check(lib().rtm_bet_stats(self.h, bet, _ptr(mean), _ptr(std), _ptr(count)))
