@@ -343,7 +343,7 @@ def bet_problem(chains: int = 64) -> dict:
         "true": bet_true_model(nz, nx, h), "h": h,
         "srcs": [(0, 2 + 5 * k) for k in range(34)],
         "recs": [(0, j) for j in range(nx)],
-        "cfg": dict(nz=nz, nx=nx, h=h, chains=chains, k_min=4, k_max=48, k_init=12, burn_in=200, thin=10,
+        "cfg": dict(nz=nz, nx=nx, h=h, chains=chains, k_min=4, k_max=48, k_init=12, burn_in=20, thin=5,
                     v_min=1400.0, v_max=5000.0, p_birth=0.25, p_death=0.25, move_dz=300.0, move_dx=1500.0,
                     sigma=0.005, seed=2001),
     }
