@@ -782,7 +782,7 @@ def run_bet(args):
         info = []
         for ch in range(c["chains"]):
             g = ctx.bet_chain(b, ch, c["k_max"])
-            tot += (g["solves"], g["sweep_passes"])
+            tot += (g["solves"], g["sweeps"])
             info.append(g)
         return tot, info
 
@@ -798,8 +798,8 @@ def run_bet(args):
     w1, info = work()
     st = ctx.stats()
     iters = args.bet_iters * args.steps
-    solves, passes = (w1 - w0).tolist()
-    node_updates = passes * 4 * n
+    solves, sweeps = (w1 - w0).tolist()
+    node_updates = sweeps * n
     per_iter_updates = node_updates / iters
     eik_ms = st.last_bet_eikonal_ms
     achieved = per_iter_updates * FLOP_PER_NODE_UPDATE / (eik_ms * 1e-3) / 1e12
@@ -810,7 +810,7 @@ def run_bet(args):
     prop = sum(sum(g["proposed"]) for g in info)
     acc = sum(sum(g["accepted"]) for g in info)
     log(f"[bench] bet: {c['chains']} chains x {iters} iterations in {el:.3f} s; {solves} solves, "
-        f"{passes / max(solves, 1):.2f} passes per solve; travel-time launch {eik_ms:.3f} ms of "
+        f"{sweeps / max(solves, 1):.2f} sweeps per solve; travel-time launch {eik_ms:.3f} ms of "
         f"{st.last_bet_iteration_ms:.3f} ms per iteration; acceptance {acc / max(prop, 1):.3f}; "
         f"median misfit per datum {np.median(misfits) / (len(p['srcs']) * len(p['recs'])):.2f}")
     cpu = None if args.no_cpu_baseline else bet_cpu_baseline(p, tt_obs.cpu().numpy())
@@ -831,7 +831,7 @@ def run_bet(args):
                        "frac": achieved / 157.3, "traffic": None, "kernel": "k_bet_eikonal",
                        "launch_us": eik_ms * 1e3,
                        "note": f"{FLOP_PER_NODE_UPDATE} FP32 operations per node update x node updates of one "
-                               "launch (solves x sweep passes x 4 x nodes, averaged over the timed iterations) "
+                               "launch (sweeps x nodes, averaged over the timed iterations) "
                                "/ the launch's HIP-event time; FP32 vector peak 256 CUs x 2.4 GHz x 256; "
                                "the sweeps are bound by the latency of dependent diagonals in LDS"}
     out["acceptance"] = acc / max(prop, 1)

@@ -381,7 +381,10 @@ int rtm_codec_decode(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes,
  * exp(-Phi / 2), Phi = sum over sources and receivers of ((T - d) / sigma)^2.
  *   - Travel times: first-order Godunov upwind scheme on a square grid of
  *     spacing h (m), point sources and receivers at grid nodes, solved by
- *     fast sweeping in single precision until a pass changes nothing.
+ *     fast sweeping in single precision: Gauss-Seidel sweeps in the four
+ *     orderings in turn until four in a row change nothing (the times of
+ *     repeating passes of four until a pass changes nothing), at most 1024
+ *     sweeps.
  *   - Model: k nuclei (k_min <= k <= k_max <= 64) with positions in
  *     [0, (nz-1) h] x [0, (nx-1) h] and velocities; a node takes the velocity
  *     of the nearest nucleus (ties: lowest index).
@@ -418,7 +421,7 @@ typedef struct {
     double misfit;                  /* Phi of the current model */
     int64_t proposed[3], accepted[3];  /* birth, death, move (valid proposals) */
     int64_t solves;                 /* travel-time solves (one per source per valid proposal) */
-    int64_t sweep_passes;           /* fast-sweeping passes of those solves (4 sweeps each) */
+    int64_t sweeps;                 /* fast sweeps (one ordering each) of those solves */
 } rtm_bet_chain_info;
 
 typedef struct rtm_bet rtm_bet;

@@ -8,8 +8,28 @@
 namespace rtm {
 
 constexpr int kBetMaxCells = 64;     // Voronoi nuclei per model
-constexpr int kBetMaxNodes = 12800;  // Eikonal grid nodes (LDS: 5 B per node per wavefront)
-constexpr int kBetMaxSweeps = 256;   // fast-sweeping passes (4 orderings each) before giving up
+constexpr int kBetMaxNodes = 12800;  // Eikonal grid nodes (LDS: 4 B per node per wavefront)
+// Fast sweeps before giving up: the solvers stop at the first sweep that
+// changes nothing, and a quiet sweep within 1021 sweeps is exactly a quiet
+// whole pass (four orderings) within 256 passes.
+constexpr int kBetMaxSweeps = 1021;
+
+// Layout of the grids a travel-time solve reads (times in LDS, the node
+// slowness in global memory).  Up to 64 rows (the row-per-lane sweeps) the
+// row stride ld leaves at least one pad column after each row, and is even:
+// a step touches addresses l (ld - 1) + c or l (ld + 1) + c over the lanes l,
+// and an odd multiplier sends the lanes to distinct LDS banks.  kBetGuard
+// entries before row 0 and 64 after the last row keep the reads of lanes
+// outside the grid in bounds.
+constexpr int kBetGuard = 68;
+__host__ __device__ inline int bet_ld(int nz, int nx) { return nz <= 64 ? (nx + 1) + ((nx + 1) & 1) : nx; }
+__host__ __device__ inline int bet_grid_entries(int nz, int nx) { return kBetGuard + nz * bet_ld(nz, nx) + 64; }
+
+// sh = slowness * h and q2 = sh sh + sh sh of a node, in single precision:
+// the two terms of the Godunov update that depend on the node alone
+struct BetSlowness {
+  float sh, q2;
+};
 
 // error bits raised by the kernels in BetDev::flags
 constexpr uint32_t kBetNoConverge = 1u;  // a travel-time solve hit the sweep limit
@@ -31,10 +51,10 @@ struct BetDev {
   // proposal
   int32_t *pk, *valid, *ptype;
   double *pz, *px, *pv, *ua;
-  uint8_t* cell;   // [chains][nz*nx] nearest nucleus of the proposal
+  BetSlowness* node;  // [chains][bet_grid_entries]: the proposal's node slowness terms (guards and pads: 0)
   float* tt;       // [chains][nsrc][nrec] travel times of the proposal
   // counters [chains][3] (birth, death, move); work [chains][2]: travel-time
-  // solves, sweep passes
+  // solves, fast sweeps (one ordering each)
   int64_t *proposed, *accepted;
   unsigned long long* work;
   // pooled post-burn-in statistics of the velocity grid

@@ -11,10 +11,11 @@
 // ratio.  Random numbers: the counter form of splitmix64.
 //
 // One iteration of every chain is five launches: propose (a thread per
-// chain), raster (nearest nucleus per node), eikonal (a wavefront per chain
-// and source: fast sweeping over anti-diagonals in LDS), accept (a workgroup
-// per chain: FP64 misfit, Metropolis test) and, on sampling iterations,
-// sample (FP64 Welford of the chains' velocity grids per node).
+// chain), raster (nearest nucleus per node, stored as the node's slowness
+// terms), eikonal (a wavefront per chain and source: fast sweeping over
+// anti-diagonals, times in LDS), accept (a workgroup per chain: FP64 misfit,
+// Metropolis test) and, on sampling iterations, sample (FP64 Welford of the
+// chains' velocity grids per node).
 //
 // Arithmetic that decides a discrete outcome (positions, nearest nuclei,
 // travel times, accept tests) is written without contraction, in the order
@@ -53,66 +54,82 @@ __device__ inline void wave_sync() {
 }
 
 // Godunov upwind value from the smaller z-neighbour and x-neighbour times
-// and sh = slowness * h: one-sided lo + sh when hi - lo >= sh, else
-// ((lo + hi) + sqrt((q + q) - d d)) / 2 with q = sh sh, d = hi - lo.
-// (plain operators: this file turns contraction off, and sqrtf is the
-// correctly rounded square root)
-__device__ inline float godunov(float a, float b, float sh) {
+// and the node's sh = slowness * h, q2 = sh sh + sh sh: one-sided lo + sh
+// when hi - lo >= sh, else ((lo + hi) + sqrt(q2 - d d)) / 2 with d = hi - lo.
+// Both forms are computed and one selected, without branches.  (Plain
+// operators: this file turns contraction off, and sqrtf is the correctly
+// rounded square root.)
+__device__ inline BetSlowness slowness_h(float slow, float h) {
+  const float sh = slow * h;
+  const float q = sh * sh;
+  return {sh, q + q};
+}
+__device__ inline float godunov(float a, float b, BetSlowness s) {
   const float lo = a > b ? b : a, hi = a > b ? a : b;
   const float d = hi - lo;
-  if (!(d < sh)) return lo + sh;
-  const float q = sh * sh;
-  return ((lo + hi) + sqrtf((q + q) - d * d)) * 0.5f;
+  const float two = ((lo + hi) + sqrtf(s.q2 - d * d)) * 0.5f;
+  return !(d < s.sh) ? lo + s.sh : two;
 }
 
-// Fast sweeping by one wavefront on T[nz*nx] in LDS: the four orderings of
-// Gauss-Seidel sweeps, each over anti-diagonals (the nodes of one diagonal are
-// not neighbours, so a wavefront updates them together), repeated until a
-// whole pass changes nothing.  Returns the passes used (kBetMaxSweeps: gave up).
+// bytes of one float grid with its guards
+__host__ __device__ inline size_t bet_lds_bytes(int nz, int nx) {
+  return ((size_t)bet_grid_entries(nz, nx) * 4 + 15) & ~(size_t)15;
+}
+
+// The node terms a solve reads: precomputed per node in global memory
+// (Stage-1 models), or from the node slowness in LDS (a velocity grid).
+struct NodeSlowness {
+  const BetSlowness* S;
+  __device__ BetSlowness at(int p) const { return S[p]; }
+};
+struct GridSlowness {
+  const float* S;
+  float h;
+  __device__ BetSlowness at(int p) const { return slowness_h(S[p], h); }
+};
+
+// Both solvers run Gauss-Seidel sweeps of the four orderings in turn until a
+// sweep changes nothing.  Such a sweep has updated every node from neighbours
+// that did not change, so the times are a fixed point of every ordering: the
+// times of repeating whole passes of four until a pass changes nothing.
+// They return the sweeps used, negated when kBetMaxSweeps came first.
+__device__ inline bool ordering_fi(int o) { return o == 0 || o == 3; }
+
+// Fast sweeping by one wavefront over anti-diagonals (the nodes of one
+// diagonal are not neighbours, so a wavefront updates them together), for
+// any number of rows; T has row stride ld.
 template <class Slow>
-__device__ int fsm_solve(float* T, int nz, int nx, float h, int si, int sj, Slow slow) {
+__device__ int fsm_solve(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
   const int lane = threadIdx.x & 63;
-  const int n = nz * nx;
-  for (int p = lane; p < n; p += 64) T[p] = INFINITY;
+  for (int p = lane; p < nz * ld; p += 64) T[p] = INFINITY;
   wave_sync();
-  if (lane == 0) T[si * nx + sj] = 0.0f;
+  if (lane == 0) T[si * ld + sj] = 0.0f;
   wave_sync();
-  int pass = 0;
-  for (; pass < kBetMaxSweeps; ++pass) {
+  for (int sweeps = 0, o = 0; sweeps < kBetMaxSweeps; o = (o + 1) & 3) {
+    const bool fi = ordering_fi(o), fj = (o < 2);
     bool changed = false;
-    for (int o = 0; o < 4; ++o) {
-      const bool fi = (o == 0 || o == 3), fj = (o < 2);
-      for (int dg = 0; dg <= nz + nx - 2; ++dg) {
-        const int ilo = max(0, dg - (nx - 1)), ihi = min(dg, nz - 1);
-        for (int ii = ilo + lane; ii <= ihi; ii += 64) {
-          const int jj = dg - ii;
-          const int i = fi ? ii : nz - 1 - ii, j = fj ? jj : nx - 1 - jj;
-          const int p = i * nx + j;
-          const float up = i > 0 ? T[p - nx] : INFINITY, dn = i + 1 < nz ? T[p + nx] : INFINITY;
-          const float lf = j > 0 ? T[p - 1] : INFINITY, rt = j + 1 < nx ? T[p + 1] : INFINITY;
-          const float t = godunov(up < dn ? up : dn, lf < rt ? lf : rt, slow(p) * h);
-          if (t < T[p]) {
-            T[p] = t;
-            changed = true;
-          }
+    for (int dg = 0; dg <= nz + nx - 2; ++dg) {
+      const int ilo = max(0, dg - (nx - 1)), ihi = min(dg, nz - 1);
+      for (int ii = ilo + lane; ii <= ihi; ii += 64) {
+        const int jj = dg - ii;
+        const int i = fi ? ii : nz - 1 - ii, j = fj ? jj : nx - 1 - jj;
+        const int p = i * ld + j;
+        const float up = i > 0 ? T[p - ld] : INFINITY, dn = i + 1 < nz ? T[p + ld] : INFINITY;
+        const float lf = j > 0 ? T[p - 1] : INFINITY, rt = j + 1 < nx ? T[p + 1] : INFINITY;
+        const float t = godunov(up < dn ? up : dn, lf < rt ? lf : rt, sl.at(p));
+        if (t < T[p]) {
+          T[p] = t;
+          changed = true;
         }
-        wave_sync();
       }
+      wave_sync();
     }
-    if (!__any(changed)) break;
+    ++sweeps;
+    if (!__any(changed)) return sweeps;
   }
-  return pass;
+  return -kBetMaxSweeps;
 }
 
-// The same sweeps with one row per lane (nz <= 64): in ordering (fi, fj) lane
-// l owns the l-th row in sweep order and handles its column jj at step l + jj,
-// which is the anti-diagonal schedule above.  A node's upwind neighbours were
-// updated one step earlier -- the one in its row by this lane (kept in a
-// register), the one in the previous row by lane l - 1 (a lane shift) -- and
-// its downwind neighbours still hold their values from before this sweep
-// (LDS that no lane overwrites before it has been read).  A step has no
-// branches: reads use clamped in-bounds nodes and selects drop what lies
-// outside the grid.
 // lane l receives lane l - 1's value (lane 0 receives `edge`): a DPP wave
 // shift, no LDS round trip
 __device__ inline float from_lane_below(float v, float edge) {
@@ -120,70 +137,101 @@ __device__ inline float from_lane_below(float v, float edge) {
                                                     0xF, 0xF, false));
 }
 
-// Godunov value without branches: both forms computed, one selected (the
-// same value as godunov())
-__device__ inline float godunov_sel(float a, float b, float sh) {
-  const float lo = a > b ? b : a, hi = a > b ? a : b;
-  const float d = hi - lo;
-  const float q = sh * sh;
-  const float two = ((lo + hi) + sqrtf((q + q) - d * d)) * 0.5f;
-  return !(d < sh) ? lo + sh : two;
+// One sweep with one row per lane (nz <= 64): lane l owns the l-th row in
+// sweep order (row: its first entry; lanes past the last row use row 0 and
+// never store) and handles its column jj at step l + jj, which is the
+// anti-diagonal schedule.  A node's upwind neighbours were updated one step
+// earlier -- the one in its row by this lane (kept in a register), the one
+// in the previous row by lane l - 1 (a lane shift) -- and every time a step
+// reads from LDS is from before this sweep: its own node, the next node of
+// its row (written by this lane a step later) and the node below it in the
+// next row (written by lane l + 1 two steps later).  So the times of step
+// s + 1 are read during step s, and the node terms of step s + 2 as well,
+// leaving only the arithmetic on the chain from step to step.  Steps have
+// no branches: outside its row a lane reads guard, pad or neighbouring-row
+// entries, whose values are never used except the +inf of the pad (or
+// guard) entry on either side of the row, and stores to its discard slot.
+// Returns whether a node changed.
+template <bool FJ, class Slow>
+__device__ bool sweep_rows(float* T, int nx, int last, int row, int below, bool has_dn, unsigned nx_own,
+                           float* discard, Slow sl) {
+  const int lane = threadIdx.x & 63;
+  constexpr int dir = FJ ? 1 : -1;
+  // node of sweep index jj in this lane's row (column jj or nx - 1 - jj)
+  const int p0 = FJ ? row - lane : row + (nx - 1) + lane;  // jj = -lane at step 0
+  const int to_dn = below - row;
+  struct Stage {
+    float old, rt, dn;
+    BetSlowness s;
+  };
+  bool changed = false;
+  float cur = INFINITY;  // this lane's node of the previous step
+  // Three sets rotate (this step's, the next step's, the one after), so no
+  // value is copied between registers while its read is in flight.
+  auto body = [&](int jj, int p, const Stage& P, Stage& Q, Stage& R) {
+    // the reads first, then the arithmetic: the scheduler may not move
+    // either across (work of the next step moved up, or reads moved down,
+    // would wait on reads just issued)
+    __builtin_amdgcn_sched_barrier(0);
+    Q.old = T[p + dir];
+    Q.rt = T[p + 2 * dir];
+    Q.dn = T[p + to_dn + dir];
+    R.s = sl.at(p + 2 * dir);
+    __builtin_amdgcn_sched_barrier(0);
+    const bool active = (unsigned)jj < nx_own;
+    // up (lane l - 1's node of the previous step) and left (this lane's) are
+    // this sweep's upwind times, dn and rt the downwind ones
+    const float up = from_lane_below(cur, INFINITY);
+    const float dn = has_dn ? P.dn : INFINITY;
+    const float a = up < dn ? up : dn;
+    const float b = cur < P.rt ? cur : P.rt;
+    const float t = godunov(a, b, P.s);
+    const bool better = active && t < P.old;
+    cur = better ? t : P.old;
+    *(active ? T + p : discard) = cur;
+    changed |= better;
+  };
+  Stage A, B, C;
+  A.old = T[p0];
+  A.rt = T[p0 + dir];
+  A.dn = T[p0 + to_dn];
+  A.s = sl.at(p0);
+  B.s = sl.at(p0 + dir);
+  int step = 0, jj = -lane, p = p0;
+  for (; step + 2 <= last; step += 3, jj += 3, p += 3 * dir) {
+    body(jj, p, A, B, C);
+    body(jj + 1, p + dir, B, C, A);
+    body(jj + 2, p + 2 * dir, C, A, B);
+  }
+  if (step <= last) body(jj, p, A, B, C);
+  if (step + 1 <= last) body(jj + 1, p + dir, B, C, A);
+  return changed;
 }
 
 template <class Slow>
-__device__ int fsm_solve_rows(float* T, int nz, int nx, float h, int si, int sj, Slow slow) {
+__device__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
   const int lane = threadIdx.x & 63;
-  const int n = nz * nx;
-  for (int p = lane; p < n; p += 64) T[p] = INFINITY;
+  // rows, pads and guards: +inf (the discard slots are in the first guard)
+  for (int p = lane - kBetGuard; p < nz * ld + 64; p += 64) T[p] = INFINITY;
   wave_sync();
-  if (lane == 0) T[si * nx + sj] = 0.0f;
+  if (lane == 0) T[si * ld + sj] = 0.0f;
   wave_sync();
-  const bool row_ok = lane < nz;
-  const bool has_dn = lane + 1 < nz;
-  int pass = 0;
-  for (; pass < kBetMaxSweeps; ++pass) {
-    bool changed = false;
-    for (int o = 0; o < 4; ++o) {
-      const bool fi = (o == 0 || o == 3), fj = (o < 2);
-      // lanes past the last row read row 0 and never change it
-      const int i = row_ok ? (fi ? lane : nz - 1 - lane) : 0;
-      const int idn = has_dn ? (fi ? i + 1 : i - 1) : i;  // the next row in sweep order
-      float cur = INFINITY;  // this lane's node of the previous step
-      for (int step = 0; step <= nz + nx - 2; ++step) {
-        const int jj = step - lane;
-        const bool active = row_ok && jj >= 0 && jj < nx;
-        const int jc = jj < 0 ? 0 : (jj >= nx ? nx - 1 : jj);
-        const int j = fj ? jc : nx - 1 - jc;
-        const int p = i * nx + j;
-        const int pr = jc + 1 < nx ? (fj ? p + 1 : p - 1) : p;
-        const float dn_v = T[idn * nx + j], rt_v = T[pr], old = T[p];
-        const float sl = slow(p);
-        const float above = from_lane_below(cur, INFINITY);
-        // up/left are this sweep's upwind times, dn/rt the downwind ones
-        const float up = lane > 0 ? above : INFINITY;
-        const float dn = has_dn ? dn_v : INFINITY;
-        const float rt = jc + 1 < nx ? rt_v : INFINITY;
-        const float left = jj > 0 ? cur : INFINITY;
-        const float a = fi ? (up < dn ? up : dn) : (dn < up ? dn : up);
-        const float b = fj ? (left < rt ? left : rt) : (rt < left ? rt : left);
-        const float t = godunov_sel(a, b, sl * h);
-        const bool better = active && t < old;
-        cur = better ? t : old;
-        // a lane with a row stores its own node (unchanged when inactive); a
-        // lane past the last row stores to the discard slot T[n]
-        T[row_ok ? p : n] = cur;
-        changed |= better;
-      }
-      wave_sync();
-    }
-    if (!__any(changed)) break;
+  float* const discard = T - kBetGuard + lane;  // entries -68 .. -5: never read for a value that is used
+  const bool row_ok = lane < nz, has_dn = lane + 1 < nz;
+  const unsigned nx_own = row_ok ? (unsigned)nx : 0u;
+  const int last = nz + nx - 2;
+  for (int sweeps = 0, o = 0; sweeps < kBetMaxSweeps; o = (o + 1) & 3) {
+    const bool fi = ordering_fi(o);
+    const int i = row_ok ? (fi ? lane : nz - 1 - lane) : 0;
+    const int idn = has_dn ? (fi ? i + 1 : i - 1) : i;  // the next row in sweep order
+    const bool changed = o < 2 ? sweep_rows<true>(T, nx, last, i * ld, idn * ld, has_dn, nx_own, discard, sl)
+                               : sweep_rows<false>(T, nx, last, i * ld, idn * ld, has_dn, nx_own, discard, sl);
+    wave_sync();
+    ++sweeps;
+    if (!__any(changed)) return sweeps;
   }
-  return pass;
+  return -kBetMaxSweeps;
 }
-
-// T[n + 1]: the grid's times and a discard slot
-__device__ inline size_t bet_lds_t_bytes(int n) { return ((size_t)(n + 1) * 4 + 15) & ~(size_t)15; }
-__device__ inline size_t bet_lds_c_bytes(int n) { return ((size_t)n + 15) & ~(size_t)15; }
 
 }  // namespace
 
@@ -264,55 +312,54 @@ __global__ __launch_bounds__(64) void k_bet_propose(BetDev d, int t, int init) {
 __global__ __launch_bounds__(256) void k_bet_raster(BetDev d) {
   const int c = blockIdx.y;
   if (!d.valid[c]) return;
-  const int n = d.nz * d.nx;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;
-  const int i = p / d.nx, j = p - (p / d.nx) * d.nx;
-  const double z = (double)i * d.h, x = (double)j * d.h;
-  const double* pz = d.pz + (size_t)c * d.k_max;
-  const double* px = d.px + (size_t)c * d.k_max;
-  const int kk = d.pk[c];
-  int best = 0;
-  double bd = INFINITY;
-  for (int q = 0; q < kk; ++q) {
-    const double dz = z - pz[q], dx = x - px[q];
-    const double d2 = dz * dz + dx * dx;
-    if (d2 < bd) {
-      bd = d2;
-      best = q;
+  const int nz = d.nz, nx = d.nx, ld = bet_ld(nz, nx);
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= bet_grid_entries(nz, nx)) return;
+  const int e = q - kBetGuard, i = e / ld, j = e - (e / ld) * ld;
+  BetSlowness out{0.0f, 0.0f};  // guards and pads
+  if (e >= 0 && i < nz && j < nx) {
+    const double z = (double)i * d.h, x = (double)j * d.h;
+    const double* pz = d.pz + (size_t)c * d.k_max;
+    const double* px = d.px + (size_t)c * d.k_max;
+    const int kk = d.pk[c];
+    int best = 0;
+    double bd = INFINITY;
+    for (int k = 0; k < kk; ++k) {
+      const double dz = z - pz[k], dx = x - px[k];
+      const double d2 = dz * dz + dx * dx;
+      if (d2 < bd) {
+        bd = d2;
+        best = k;
+      }
     }
+    out = slowness_h((float)(1.0 / d.pv[(size_t)c * d.k_max + best]), (float)d.h);
   }
-  d.cell[(size_t)c * n + p] = (uint8_t)best;
+  d.node[(size_t)c * bet_grid_entries(nz, nx) + q] = out;
 }
 
-// travel times of the proposal from source blockIdx.x of chain blockIdx.y
+// travel times of the proposal of chain c from source e.  Blocks map to
+// (c, e) so that all of a chain's solves run on one XCD (blocks go to the
+// XCDs in turn), whose L2 then holds that chain's node terms.
 __global__ __launch_bounds__(64) void k_bet_eikonal(BetDev d) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int e = blockIdx.x, c = blockIdx.y;
-  if (!d.valid[c]) return;
+  const int xcd = blockIdx.x & 7, r = blockIdx.x >> 3;
+  const int e = r % d.nsrc, c = (r / d.nsrc) * 8 + xcd;
+  if (c >= d.chains || !d.valid[c]) return;
   const int lane = threadIdx.x;
-  const int n = d.nz * d.nx;
-  float* T = reinterpret_cast<float*>(smem);
-  uint8_t* cid = smem + bet_lds_t_bytes(n);
-  float* stab = reinterpret_cast<float*>(smem + bet_lds_t_bytes(n) + bet_lds_c_bytes(n));
-  const uint8_t* cell = d.cell + (size_t)c * n;
-  for (int p = lane; p < n; p += 64) cid[p] = cell[p];
-  const int kk = d.pk[c];
-  for (int q = lane; q < kk; q += 64) stab[q] = (float)(1.0 / d.pv[(size_t)c * d.k_max + q]);
-  wave_sync();
+  const int nz = d.nz, nx = d.nx, ld = bet_ld(nz, nx);
+  float* T = reinterpret_cast<float*>(smem) + kBetGuard;  // times, with guards
+  const NodeSlowness sl{d.node + (size_t)c * bet_grid_entries(nz, nx) + kBetGuard};
   const int2 s = d.src[e];
-  auto slow = [&](int p) { return stab[cid[p]]; };
-  const int passes = d.nz <= 64 ? fsm_solve_rows(T, d.nz, d.nx, (float)d.h, s.x, s.y, slow)
-                                : fsm_solve(T, d.nz, d.nx, (float)d.h, s.x, s.y, slow);
+  const int sweeps = nz <= 64 ? fsm_solve_rows(T, nz, nx, ld, s.x, s.y, sl) : fsm_solve(T, nz, nx, ld, s.x, s.y, sl);
   if (lane == 0) {
-    if (passes >= kBetMaxSweeps) atomicOr(d.flags, kBetNoConverge);
+    if (sweeps < 0) atomicOr(d.flags, kBetNoConverge);
     atomicAdd(d.work + 2 * (size_t)c, 1ull);
-    atomicAdd(d.work + 2 * (size_t)c + 1, (unsigned long long)min(passes + 1, kBetMaxSweeps));
+    atomicAdd(d.work + 2 * (size_t)c + 1, (unsigned long long)(sweeps < 0 ? -sweeps : sweeps));
   }
   float* out = d.tt + ((size_t)c * d.nsrc + e) * d.nrec;
-  for (int r = lane; r < d.nrec; r += 64) {
-    const int2 q = d.rec[r];
-    out[r] = T[q.x * d.nx + q.y];
+  for (int q = lane; q < d.nrec; q += 64) {
+    const int2 m = d.rec[q];
+    out[q] = T[m.x * ld + m.y];
   }
 }
 
@@ -401,25 +448,29 @@ __global__ __launch_bounds__(256) void k_bet_sample(BetDev d) {
 __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, int nx, float h, const int2* src,
                                                      const int2* rec, int nrec, float* tt, uint32_t* flags) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int e = blockIdx.x, lane = threadIdx.x, n = nz * nx;
-  float* T = reinterpret_cast<float*>(smem);
-  float* S = reinterpret_cast<float*>(smem + bet_lds_t_bytes(n));
-  for (int p = lane; p < n; p += 64) S[p] = (float)(1.0 / (double)vel[p]);
+  const int e = blockIdx.x, lane = threadIdx.x, ld = bet_ld(nz, nx);
+  // LDS: times and slowness, both with guards and row stride ld
+  float* T = reinterpret_cast<float*>(smem) + kBetGuard;
+  float* S = reinterpret_cast<float*>(smem + bet_lds_bytes(nz, nx)) + kBetGuard;
+  for (int q = lane - kBetGuard; q < nz * ld + 64; q += 64) {  // pads and guards: slowness 0
+    const int i = q / ld, j = q - i * ld;
+    S[q] = (q >= 0 && i < nz && j < nx) ? (float)(1.0 / (double)vel[i * nx + j]) : 0.0f;
+  }
   wave_sync();
   const int2 s = src[e];
-  auto slow = [&](int p) { return S[p]; };
-  const int passes = nz <= 64 ? fsm_solve_rows(T, nz, nx, h, s.x, s.y, slow) : fsm_solve(T, nz, nx, h, s.x, s.y, slow);
-  if (passes >= kBetMaxSweeps && lane == 0) atomicOr(flags, kBetNoConverge);
+  const GridSlowness sl{S, h};
+  const int sweeps = nz <= 64 ? fsm_solve_rows(T, nz, nx, ld, s.x, s.y, sl) : fsm_solve(T, nz, nx, ld, s.x, s.y, sl);
+  if (sweeps < 0 && lane == 0) atomicOr(flags, kBetNoConverge);
   for (int r = lane; r < nrec; r += 64) {
     const int2 q = rec[r];
-    tt[(size_t)e * nrec + r] = T[q.x * nx + q.y];
+    tt[(size_t)e * nrec + r] = T[q.x * ld + q.y];
   }
 }
 
-static size_t lds_bet(int n) {
-  return (((size_t)(n + 1) * 4 + 15) & ~(size_t)15) + (((size_t)n + 15) & ~(size_t)15) + 4 * kBetMaxCells;
-}
-static size_t lds_grid(int n) { return (((size_t)(n + 1) * 4 + 15) & ~(size_t)15) + (((size_t)n * 4 + 15) & ~(size_t)15); }
+// LDS of the Stage-1 solve: times; of a velocity grid's solve: times and
+// slowness
+static size_t lds_bet(int nz, int nx) { return bet_lds_bytes(nz, nx); }
+static size_t lds_grid(int nz, int nx) { return 2 * bet_lds_bytes(nz, nx); }
 
 hipError_t launch_bet_propose(const BetDev& d, int t, int init, hipStream_t s) {
   k_bet_propose<<<(d.chains + 63) / 64, 64, 0, s>>>(d, t, init);
@@ -427,21 +478,22 @@ hipError_t launch_bet_propose(const BetDev& d, int t, int init, hipStream_t s) {
 }
 
 hipError_t launch_bet_raster(const BetDev& d, hipStream_t s) {
-  const int n = d.nz * d.nx;
-  k_bet_raster<<<dim3((n + 255) / 256, d.chains), 256, 0, s>>>(d);
+  const int m = bet_grid_entries(d.nz, d.nx);
+  k_bet_raster<<<dim3((m + 255) / 256, d.chains), 256, 0, s>>>(d);
   return hipGetLastError();
 }
 
 hipError_t launch_bet_eikonal(const BetDev& d, hipStream_t s) {
   const int n = d.nz * d.nx;
   if (n > kBetMaxNodes || d.k_max > kBetMaxCells) return hipErrorInvalidValue;
-  const size_t lds = lds_bet(n);
+  const size_t lds = lds_bet(d.nz, d.nx);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bet_eikonal),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k_bet_eikonal<<<dim3(d.nsrc, d.chains), 64, lds, s>>>(d);
+  // 8 blocks (one per XCD) per source and group of 8 chains
+  k_bet_eikonal<<<8 * d.nsrc * ((d.chains + 7) / 8), 64, lds, s>>>(d);
   return hipGetLastError();
 }
 
@@ -460,7 +512,7 @@ hipError_t launch_eikonal_grid(const float* vel, int nz, int nx, float h, const 
                                const int2* rec, int nrec, float* tt, uint32_t* flags, hipStream_t s) {
   const int n = nz * nx;
   if (n > kBetMaxNodes) return hipErrorInvalidValue;
-  const size_t lds = lds_grid(n);
+  const size_t lds = lds_grid(nz, nx);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eikonal_grid),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -2056,7 +2056,7 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   d.px = static_cast<double*>(get(8 * C * K));
   d.pv = static_cast<double*>(get(8 * C * K));
   d.ua = static_cast<double*>(get(8 * C));
-  d.cell = static_cast<uint8_t*>(get(C * n));
+  d.node = static_cast<BetSlowness*>(get(sizeof(BetSlowness) * C * (size_t)bet_grid_entries(c.nz, c.nx)));
   d.tt = static_cast<float*>(get(4 * C * nd));
   d.proposed = static_cast<int64_t*>(get(8 * 3 * C));
   d.accepted = static_cast<int64_t*>(get(8 * 3 * C));

@@ -88,7 +88,7 @@ class BetConfig(ctypes.Structure):
 class BetChainInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("pad_", ctypes.c_int32), ("misfit", ctypes.c_double),
                 ("proposed", ctypes.c_int64 * 3), ("accepted", ctypes.c_int64 * 3),
-                ("solves", ctypes.c_int64), ("sweep_passes", ctypes.c_int64)]
+                ("solves", ctypes.c_int64), ("sweeps", ctypes.c_int64)]
 
 
 # exported symbols and their C signatures (argtypes, restype)
@@ -419,7 +419,7 @@ class Context:
                                    z.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p),
                                    v.ctypes.data_as(ctypes.c_void_p)))
         return {"k": info.k, "misfit": info.misfit, "proposed": list(info.proposed),
-                "accepted": list(info.accepted), "solves": info.solves, "sweep_passes": info.sweep_passes,
+                "accepted": list(info.accepted), "solves": info.solves, "sweeps": info.sweeps,
                 "z": z, "x": x, "v": v}
 
     def bet_stats(self, bet, mean=None, std=None, count=None):
