@@ -429,14 +429,16 @@ typedef struct rtm_bet rtm_bet;
 /* Travel times tt_dev [nsrc][nrec] (s, float) of the velocity grid vel_dev
  * [nz][nx] (m/s, float) for sources src_host[nsrc] and receivers
  * rec_host[nrec] (grid nodes).  Synchronous.  Errors: RTM_E_INVAL (shape,
- * points outside the grid, more than 12800 nodes), RTM_E_DEVICE (a solve did
- * not converge). */
+ * points outside the grid, more than 12800 nodes, or a node where
+ * h / v, in single precision, lies outside [1e-9, 1e18] s -- velocities must
+ * be positive and finite), RTM_E_DEVICE (a solve did not converge). */
 int rtm_eikonal(rtm_ctx *ctx, const float *vel_dev, int32_t nz, int32_t nx, float h, int32_t nsrc,
                 const rtm_point *src_host, int32_t nrec, const rtm_point *rec_host, float *tt_dev);
 
 /* Creates the sampler: copies the observed travel times tt_obs_dev
  * [nsrc][nrec] (s), draws every chain's initial model and computes its
- * misfit (stream-ordered).  Errors: RTM_E_INVAL (bad configuration),
+ * misfit (stream-ordered).  Errors: RTM_E_INVAL (bad configuration,
+ * including h / v outside [1e-9, 1e18] s for v in [v_min, v_max]),
  * RTM_E_NOMEM (arena). */
 int rtm_bet_create(rtm_ctx *ctx, const rtm_bet_config *cfg, int32_t nsrc, const rtm_point *src_host,
                    int32_t nrec, const rtm_point *rec_host, const float *tt_obs_dev, rtm_bet **out);

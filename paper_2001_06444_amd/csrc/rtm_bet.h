@@ -33,6 +33,11 @@ struct BetSlowness {
 
 // error bits raised by the kernels in BetDev::flags
 constexpr uint32_t kBetNoConverge = 1u;  // a travel-time solve hit the sweep limit
+constexpr uint32_t kBetBadSlowness = 2u; // a node's slowness * h outside [kBetShMin, kBetShMax]
+
+// Range of sh = slowness * h (s, single precision) in which the Godunov
+// update is evaluated: its square root then only sees normal arguments.
+constexpr float kBetShMin = 1e-9f, kBetShMax = 1e18f;
 
 struct BetDev {
   // grid, data

@@ -53,21 +53,43 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Correctly rounded single-precision square root of x in [2^-60, 2^126],
+// by Tuckerman's rounding test (Markstein, IBM J. Res. Dev. 34(1), 1990): the
+// hardware estimate y is within one ulp of sqrt(x), and y is the rounded
+// root exactly when pred(y) y < x <= y succ(y).  The two residuals come from
+// fused multiply-adds, exact in sign over this range, and select pred(y), y
+// or succ(y).  (Without the scaling and special cases of the library
+// routine, which this range does not need.)
+__device__ inline float sqrt_rn(float x) {
+  const float y = __builtin_amdgcn_sqrtf(x);
+  const float yd = __int_as_float(__float_as_int(y) - 1), yu = __int_as_float(__float_as_int(y) + 1);
+  const float rd = __builtin_fmaf(-yd, y, x), ru = __builtin_fmaf(-yu, y, x);
+  const float r = rd <= 0.0f ? yd : y;
+  return ru > 0.0f ? yu : r;
+}
+
 // Godunov upwind value from the smaller z-neighbour and x-neighbour times
 // and the node's sh = slowness * h, q2 = sh sh + sh sh: one-sided lo + sh
 // when hi - lo >= sh, else ((lo + hi) + sqrt(q2 - d d)) / 2 with d = hi - lo.
-// Both forms are computed and one selected, without branches.  (Plain
-// operators: this file turns contraction off, and sqrtf is the correctly
-// rounded square root.)
+// Both forms are computed and one selected, without branches.  Plain
+// operators (this file turns contraction off); with sh in [kBetShMin,
+// kBetShMax] the square root's argument in the two-sided case lies in
+// [sh^2, 2 sh^2], inside the range of sqrt_rn.
 __device__ inline BetSlowness slowness_h(float slow, float h) {
   const float sh = slow * h;
   const float q = sh * sh;
   return {sh, q + q};
 }
+// min and max as the median of three: one instruction each, no compare
+// (the same values as a comparison for the times here, which are never NaN
+// or -0 where used)
+__device__ inline float min_t(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -INFINITY); }
+__device__ inline float max_t(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
+
 __device__ inline float godunov(float a, float b, BetSlowness s) {
-  const float lo = a > b ? b : a, hi = a > b ? a : b;
+  const float lo = min_t(a, b), hi = max_t(a, b);
   const float d = hi - lo;
-  const float two = ((lo + hi) + sqrtf(s.q2 - d * d)) * 0.5f;
+  const float two = ((lo + hi) + sqrt_rn(s.q2 - d * d)) * 0.5f;
   return !(d < s.sh) ? lo + s.sh : two;
 }
 
@@ -183,8 +205,8 @@ __device__ bool sweep_rows(float* T, int nx, int last, int row, int below, bool 
     // this sweep's upwind times, dn and rt the downwind ones
     const float up = from_lane_below(cur, INFINITY);
     const float dn = has_dn ? P.dn : INFINITY;
-    const float a = up < dn ? up : dn;
-    const float b = cur < P.rt ? cur : P.rt;
+    const float a = min_t(up, dn);
+    const float b = min_t(cur, P.rt);
     const float t = godunov(a, b, P.s);
     const bool better = active && t < P.old;
     cur = better ? t : P.old;
@@ -452,9 +474,20 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
   // LDS: times and slowness, both with guards and row stride ld
   float* T = reinterpret_cast<float*>(smem) + kBetGuard;
   float* S = reinterpret_cast<float*>(smem + bet_lds_bytes(nz, nx)) + kBetGuard;
+  bool bad = false;
   for (int q = lane - kBetGuard; q < nz * ld + 64; q += 64) {  // pads and guards: slowness 0
     const int i = q / ld, j = q - i * ld;
-    S[q] = (q >= 0 && i < nz && j < nx) ? (float)(1.0 / (double)vel[i * nx + j]) : 0.0f;
+    float sl = 0.0f;
+    if (q >= 0 && i < nz && j < nx) {
+      sl = (float)(1.0 / (double)vel[i * nx + j]);
+      const float sh = sl * h;
+      bad |= !(sh >= kBetShMin && sh <= kBetShMax);
+    }
+    S[q] = sl;
+  }
+  if (__any(bad)) {  // the solve would leave the square root's range
+    if (lane == 0) atomicOr(flags, kBetBadSlowness);
+    return;
   }
   wave_sync();
   const int2 s = src[e];

@@ -1988,6 +1988,9 @@ extern "C" int rtm_eikonal(rtm_ctx* ctx, const float* vel_dev, int32_t nz, int32
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   ctx->arena.release(buf, align256(bs + br + 256));
   if (e != hipSuccess) return fail(RTM_E_DEVICE, "travel times: %s", hipGetErrorString(e));
+  if (flag & kBetBadSlowness)
+    return fail(RTM_E_INVAL, "velocity grid: h / v must lie in [%g, %g] s at every node", (double)kBetShMin,
+                (double)kBetShMax);
   if (flag & kBetNoConverge) return fail(RTM_E_DEVICE, "a travel-time solve did not converge");
   return RTM_OK;
 }
@@ -2004,6 +2007,12 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
     return fail(RTM_E_INVAL, "need chains >= 1 and 1 <= k_min <= k_init <= k_max <= %d", kBetMaxCells);
   if (!(c.v_min > 0) || !(c.v_max > c.v_min) || !std::isfinite(c.v_max))
     return fail(RTM_E_INVAL, "need 0 < v_min < v_max");
+  {  // the node terms the solves will see, as the device computes them
+    const float sh_lo = (float)(1.0 / c.v_max) * (float)c.h, sh_hi = (float)(1.0 / c.v_min) * (float)c.h;
+    if (!(sh_lo >= kBetShMin && sh_hi <= kBetShMax))
+      return fail(RTM_E_INVAL, "h / v must lie in [%g, %g] s over [v_min, v_max]", (double)kBetShMin,
+                  (double)kBetShMax);
+  }
   if (!(c.p_birth >= 0) || !(c.p_death >= 0) || !(c.p_birth + c.p_death <= 1.0))
     return fail(RTM_E_INVAL, "need p_birth, p_death >= 0 with p_birth + p_death <= 1");
   if (!(c.move_dz >= 0) || !(c.move_dx >= 0) || !(c.sigma > 0) || !std::isfinite(c.sigma) || c.burn_in < 0 ||

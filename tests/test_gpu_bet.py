@@ -44,9 +44,13 @@ def ulps(a, b):
     return np.abs(ia - ib)
 
 
-@pytest.mark.parametrize("nz,nx,h,seed", [(36, 171, 100.0, 0), (70, 90, 50.0, 1), (2, 2, 10.0, 2), (9, 5, 25.0, 3)])
-def test_travel_times_match_oracle(ctx, nz, nx, h, seed):
-    vel = voronoi_velocity(nz, nx, h, seed)
+@pytest.mark.parametrize("nz,nx,h,seed,scale", [(36, 171, 100.0, 0, 1.0), (70, 90, 50.0, 1, 1.0), (2, 2, 10.0, 2, 1.0),
+                                                 (9, 5, 25.0, 3, 1.0), (20, 33, 5e-6, 4, 1.0),
+                                                 (20, 33, 1e6, 5, 1e-14)])
+def test_travel_times_match_oracle(ctx, nz, nx, h, seed, scale):
+    # h / v spans 1.1e-9 .. 6.7e16 s over the cases (the accepted range is
+    # [1e-9, 1e18]): square-root arguments from about 2^-59 to 2^113
+    vel = voronoi_velocity(nz, nx, h, seed) * np.float32(scale)
     rng = np.random.default_rng(seed + 10)
     srcs = [(0, 0), (nz - 1, nx - 1)] + [(int(rng.integers(nz)), int(rng.integers(nx))) for _ in range(4)]
     recs = [(i, j) for i in range(nz) for j in range(nx)][:: max(1, nz * nx // 400)]
@@ -126,13 +130,20 @@ def test_bet_rejects(ctx, rtm):
     cfg, srcs, recs, tt_obs = _small_problem()
     t = dev(tt_obs)
     for bad in (dict(k_max=65), dict(k_min=0), dict(k_init=30), dict(v_max=1000.0), dict(p_birth=0.8),
-                dict(sigma=0.0), dict(thin=0), dict(nz=200, nx=200)):
+                dict(sigma=0.0), dict(thin=0), dict(nz=200, nx=200), dict(h=1e-6), dict(v_min=1e-20)):
         with pytest.raises(rtm.RTMError):
             ctx.bet_create(srcs, recs, t, **{**cfg, **bad})
     with pytest.raises(rtm.RTMError):
         ctx.bet_create([(0, 60)], recs, t, **cfg)
     with pytest.raises(rtm.RTMError):
         ctx.eikonal(dev(np.full((4, 4), 2000.0)), 10.0, [(4, 0)], [(0, 0)])
+    # velocities that leave h / v outside [1e-9, 1e18] s: zero, negative, not finite
+    for v in (0.0, -1500.0, np.inf, np.nan):
+        vel = np.full((4, 4), 2000.0)
+        vel[2, 1] = v
+        with pytest.raises(rtm.RTMError):
+            ctx.eikonal(dev(vel), 10.0, [(0, 0)], [(3, 3)])
+    ctx.eikonal(dev(np.full((4, 4), 2000.0)), 10.0, [(0, 0)], [(3, 3)])  # still usable
 
 
 def test_full_size_chains_sampled(ctx, rtm):
