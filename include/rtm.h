@@ -460,6 +460,15 @@ int rtm_bet_stats(rtm_ctx *ctx, rtm_bet *bet, double *mean_dev, double *std_dev,
 
 int rtm_bet_destroy(rtm_ctx *ctx, rtm_bet *bet);
 
+/* Self-check of the travel-time arithmetic: counts into *mismatches the
+ * float bit patterns in [lo_bits, hi_bits) whose square root, as the
+ * travel-time solves evaluate it (a hardware estimate corrected by
+ * Tuckerman's rounding test), differs from the correctly rounded square
+ * root.  Over [2^-60, 2^126] (bit patterns 0x21800000 to 0x7E800000), which
+ * holds every argument the solves use within the accepted h / v range, the
+ * count is 0.  Synchronous.  Errors: RTM_E_INVAL (lo_bits >= hi_bits). */
+int rtm_sqrt_check(rtm_ctx *ctx, uint32_t lo_bits, uint32_t hi_bits, uint64_t *mismatches);
+
 /* ---- observability --------------------------------------------------- */
 
 typedef struct {

@@ -19,11 +19,14 @@ constexpr int kBetMaxSweeps = 1021;
 // row stride ld leaves at least one pad column after each row, and is even:
 // a step touches addresses l (ld - 1) + c or l (ld + 1) + c over the lanes l,
 // and an odd multiplier sends the lanes to distinct LDS banks.  kBetGuard
-// entries before row 0 and 64 after the last row keep the reads of lanes
+// entries before row 0, one more row after the last (+inf in the times: the
+// row below the grid) and 64 entries after that keep the reads of lanes
 // outside the grid in bounds.
 constexpr int kBetGuard = 68;
 __host__ __device__ inline int bet_ld(int nz, int nx) { return nz <= 64 ? (nx + 1) + ((nx + 1) & 1) : nx; }
-__host__ __device__ inline int bet_grid_entries(int nz, int nx) { return kBetGuard + nz * bet_ld(nz, nx) + 64; }
+__host__ __device__ inline int bet_grid_entries(int nz, int nx) {
+  return kBetGuard + (nz + 1) * bet_ld(nz, nx) + 64;
+}
 
 // sh = slowness * h and q2 = sh sh + sh sh of a node, in single precision:
 // the two terms of the Godunov update that depend on the node alone
@@ -74,6 +77,9 @@ hipError_t launch_bet_eikonal(const BetDev& d, hipStream_t s);
 // log_row (nullable): [chains] outcome of this iteration (-1 invalid, 0 rejected, 1 + move type)
 hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, hipStream_t s);
 hipError_t launch_bet_sample(const BetDev& d, hipStream_t s);
+// mismatches (added to *bad) of the solver's square root against the
+// correctly rounded one over the float bit patterns [lo, hi), lo < hi
+hipError_t launch_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad, hipStream_t s);
 // travel times of one velocity grid (m/s) for every source: tt [nsrc][nrec]
 hipError_t launch_eikonal_grid(const float* vel, int nz, int nx, float h, const int2* src, int nsrc,
                                const int2* rec, int nrec, float* tt, uint32_t* flags, hipStream_t s);

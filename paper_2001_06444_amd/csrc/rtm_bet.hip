@@ -80,11 +80,12 @@ __device__ inline BetSlowness slowness_h(float slow, float h) {
   const float q = sh * sh;
   return {sh, q + q};
 }
-// min and max as the median of three: one instruction each, no compare
-// (the same values as a comparison for the times here, which are never NaN
-// or -0 where used)
-__device__ inline float min_t(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -INFINITY); }
-__device__ inline float max_t(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, INFINITY); }
+// min and max of two times by their bit patterns: for non-negative floats
+// (+inf included) the patterns order as integers the way the values do, and
+// the times compared here are never negative or NaN where the result is
+// used -- one integer instruction, the same value as a float comparison
+__device__ inline float min_t(float a, float b) { return __int_as_float(min(__float_as_int(a), __float_as_int(b))); }
+__device__ inline float max_t(float a, float b) { return __int_as_float(max(__float_as_int(a), __float_as_int(b))); }
 
 __device__ inline float godunov(float a, float b, BetSlowness s) {
   const float lo = min_t(a, b), hi = max_t(a, b);
@@ -161,7 +162,8 @@ __device__ inline float from_lane_below(float v, float edge) {
 
 // One sweep with one row per lane (nz <= 64): lane l owns the l-th row in
 // sweep order (row: its first entry; lanes past the last row use row 0 and
-// never store) and handles its column jj at step l + jj, which is the
+// never store; below: the next row in sweep order, the +inf row after the
+// grid for the last) and handles its column jj at step l + jj, which is the
 // anti-diagonal schedule.  A node's upwind neighbours were updated one step
 // earlier -- the one in its row by this lane (kept in a register), the one
 // in the previous row by lane l - 1 (a lane shift) -- and every time a step
@@ -175,8 +177,8 @@ __device__ inline float from_lane_below(float v, float edge) {
 // guard) entry on either side of the row, and stores to its discard slot.
 // Returns whether a node changed.
 template <bool FJ, class Slow>
-__device__ bool sweep_rows(float* T, int nx, int last, int row, int below, bool has_dn, unsigned nx_own,
-                           float* discard, Slow sl) {
+__device__ bool sweep_rows(float* T, int nx, int last, int row, int below, unsigned nx_own, float* discard,
+                           Slow sl) {
   const int lane = threadIdx.x & 63;
   constexpr int dir = FJ ? 1 : -1;
   // node of sweep index jj in this lane's row (column jj or nx - 1 - jj)
@@ -203,9 +205,9 @@ __device__ bool sweep_rows(float* T, int nx, int last, int row, int below, bool 
     const bool active = (unsigned)jj < nx_own;
     // up (lane l - 1's node of the previous step) and left (this lane's) are
     // this sweep's upwind times, dn and rt the downwind ones
-    const float up = from_lane_below(cur, INFINITY);
-    const float dn = has_dn ? P.dn : INFINITY;
-    const float a = min_t(up, dn);
+    // (lane 0 has no upwind row: it takes dn in place of +inf, the same min)
+    const float up = from_lane_below(cur, P.dn);
+    const float a = min_t(up, P.dn);
     const float b = min_t(cur, P.rt);
     const float t = godunov(a, b, P.s);
     const bool better = active && t < P.old;
@@ -233,8 +235,9 @@ __device__ bool sweep_rows(float* T, int nx, int last, int row, int below, bool 
 template <class Slow>
 __device__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
   const int lane = threadIdx.x & 63;
-  // rows, pads and guards: +inf (the discard slots are in the first guard)
-  for (int p = lane - kBetGuard; p < nz * ld + 64; p += 64) T[p] = INFINITY;
+  // rows, pads, the row below the grid and guards: +inf (the discard slots
+  // are in the first guard)
+  for (int p = lane - kBetGuard; p < (nz + 1) * ld + 64; p += 64) T[p] = INFINITY;
   wave_sync();
   if (lane == 0) T[si * ld + sj] = 0.0f;
   wave_sync();
@@ -245,9 +248,9 @@ __device__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, 
   for (int sweeps = 0, o = 0; sweeps < kBetMaxSweeps; o = (o + 1) & 3) {
     const bool fi = ordering_fi(o);
     const int i = row_ok ? (fi ? lane : nz - 1 - lane) : 0;
-    const int idn = has_dn ? (fi ? i + 1 : i - 1) : i;  // the next row in sweep order
-    const bool changed = o < 2 ? sweep_rows<true>(T, nx, last, i * ld, idn * ld, has_dn, nx_own, discard, sl)
-                               : sweep_rows<false>(T, nx, last, i * ld, idn * ld, has_dn, nx_own, discard, sl);
+    const int idn = has_dn ? (fi ? i + 1 : i - 1) : nz;  // the next row in sweep order, or the +inf row
+    const bool changed = o < 2 ? sweep_rows<true>(T, nx, last, i * ld, idn * ld, nx_own, discard, sl)
+                               : sweep_rows<false>(T, nx, last, i * ld, idn * ld, nx_own, discard, sl);
     wave_sync();
     ++sweeps;
     if (!__any(changed)) return sweeps;
@@ -475,7 +478,7 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
   float* T = reinterpret_cast<float*>(smem) + kBetGuard;
   float* S = reinterpret_cast<float*>(smem + bet_lds_bytes(nz, nx)) + kBetGuard;
   bool bad = false;
-  for (int q = lane - kBetGuard; q < nz * ld + 64; q += 64) {  // pads and guards: slowness 0
+  for (int q = lane - kBetGuard; q < (nz + 1) * ld + 64; q += 64) {  // pads and guards: slowness 0
     const int i = q / ld, j = q - i * ld;
     float sl = 0.0f;
     if (q >= 0 && i < nz && j < nx) {
@@ -498,6 +501,26 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
     const int2 q = rec[r];
     tt[(size_t)e * nrec + r] = T[q.x * ld + q.y];
   }
+}
+
+// Counts the float bit patterns in [lo, hi) where sqrt_rn differs from the
+// correctly rounded square root (a thread per 256 patterns).
+__global__ __launch_bounds__(256) void k_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad) {
+  const uint64_t b0 = (uint64_t)lo + ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 256;
+  unsigned long long nb = 0;
+  for (uint32_t q = 0; q < 256; ++q) {
+    const uint64_t b = b0 + q;
+    if (b >= hi) break;
+    const float x = __uint_as_float((uint32_t)b);
+    nb += __float_as_uint(sqrt_rn(x)) != __float_as_uint(sqrtf(x));
+  }
+  if (nb) atomicAdd(bad, nb);
+}
+
+hipError_t launch_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad, hipStream_t s) {
+  const uint64_t threads = ((uint64_t)(hi - lo) + 255) / 256;
+  k_sqrt_check<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(lo, hi, bad);
+  return hipGetLastError();
 }
 
 // LDS of the Stage-1 solve: times; of a velocity grid's solve: times and

@@ -2162,6 +2162,23 @@ extern "C" int rtm_bet_destroy(rtm_ctx* ctx, rtm_bet* bet) {
   return defer(ctx, ctx->stream, std::move(dd));
 }
 
+extern "C" int rtm_sqrt_check(rtm_ctx* ctx, uint32_t lo_bits, uint32_t hi_bits, uint64_t* mismatches) {
+  if (!ctx || !mismatches || !(lo_bits < hi_bits)) return fail(RTM_E_INVAL, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  unsigned long long* bad = static_cast<unsigned long long*>(arena_alloc(ctx, 256));
+  if (!bad) return fail(RTM_E_NOMEM, "arena exhausted");
+  hipStream_t s = ctx->stream;
+  unsigned long long n = 0;
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(bad), 0, 2, s);
+  if (e == hipSuccess) e = launch_sqrt_check(lo_bits, hi_bits, bad, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&n, bad, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ctx->arena.release(bad, 256);
+  if (e != hipSuccess) return fail(RTM_E_DEVICE, "square-root check: %s", hipGetErrorString(e));
+  *mismatches = n;
+  return RTM_OK;
+}
+
 extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
   if (!ctx || !out) return fail(RTM_E_INVAL, "bad arguments");
   memset(out, 0, sizeof *out);

@@ -138,6 +138,7 @@ SIGNATURES = {
     "rtm_bet_chain": ([_V, _V, _I32, _P(BetChainInfo), _V, _V, _V], ctypes.c_int),
     "rtm_bet_stats": ([_V, _V, _V, _V, _V], ctypes.c_int),
     "rtm_bet_destroy": ([_V, _V], ctypes.c_int),
+    "rtm_sqrt_check": ([_V, ctypes.c_uint32, ctypes.c_uint32, _P(ctypes.c_uint64)], ctypes.c_int),
     "rtm_ctx_stats": ([_V, _P(CtxStats)], ctypes.c_int),
 }
 
@@ -427,6 +428,13 @@ class Context:
 
     def bet_destroy(self, bet):
         _check(lib().rtm_bet_destroy(self.h, bet))
+
+    def sqrt_check(self, lo_bits: int, hi_bits: int) -> int:
+        """Float bit patterns in [lo_bits, hi_bits) where the travel-time
+        solves' square root differs from the correctly rounded one."""
+        n = ctypes.c_uint64(0)
+        _check(lib().rtm_sqrt_check(self.h, lo_bits, hi_bits, ctypes.byref(n)))
+        return n.value
 
     def stats(self) -> CtxStats:
         s = CtxStats()

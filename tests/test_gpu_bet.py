@@ -162,3 +162,13 @@ def test_full_size_chains_sampled(ctx, rtm):
         np.testing.assert_array_equal(glog[:, c], ref["log"][:, 0])
         _compare_chains(ctx, b, ref, [c], cfg["k_max"], first=c)
     ctx.bet_destroy(b)
+
+
+def test_square_root_correctly_rounded(ctx, rtm):
+    """Every argument the travel-time solves take the square root of lies in
+    [2^-60, 2^126] (h / v in [1e-9, 1e18] s); over all of it the solver's
+    root equals the correctly rounded one (all 1.56e9 bit patterns)."""
+    lo, hi = np.float32(2.0 ** -60).view(np.uint32), np.float32(2.0 ** 126).view(np.uint32)
+    assert ctx.sqrt_check(int(lo), int(hi) + 1) == 0
+    with pytest.raises(rtm.RTMError):
+        ctx.sqrt_check(5, 5)
