@@ -802,7 +802,10 @@ def run_bet(args):
     node_updates = sweeps * n
     per_iter_updates = node_updates / iters
     eik_ms = st.last_bet_eikonal_ms
-    achieved = per_iter_updates * FLOP_PER_NODE_UPDATE / (eik_ms * 1e-3) / 1e12
+    # the chain groups' travel-time launches overlap on their streams, so the
+    # rate is taken over the whole timed region: every launch's operations /
+    # its wall time (which also holds the other, small kernels)
+    achieved = node_updates * FLOP_PER_NODE_UPDATE / el / 1e12
     mean = torch.empty(n, dtype=torch.float64, device="cuda")
     std = torch.empty_like(mean)
     ctx.bet_stats(b, mean, std)
@@ -810,8 +813,9 @@ def run_bet(args):
     prop = sum(sum(g["proposed"]) for g in info)
     acc = sum(sum(g["accepted"]) for g in info)
     log(f"[bench] bet: {c['chains']} chains x {iters} iterations in {el:.3f} s; {solves} solves, "
-        f"{sweeps / max(solves, 1):.2f} sweeps per solve; travel-time launch {eik_ms:.3f} ms of "
-        f"{st.last_bet_iteration_ms:.3f} ms per iteration; acceptance {acc / max(prop, 1):.3f}; "
+        f"{sweeps / max(solves, 1):.2f} sweeps per solve; {per_iter_updates * FLOP_PER_NODE_UPDATE / 1e9:.3f} GFLOP "
+        f"of travel times per iteration; first chain group's travel-time launch {eik_ms:.3f} ms of its "
+        f"{st.last_bet_iteration_ms:.3f} ms iteration; acceptance {acc / max(prop, 1):.3f}; "
         f"median misfit per datum {np.median(misfits) / (len(p['srcs']) * len(p['recs'])):.2f}")
     cpu = None if args.no_cpu_baseline else bet_cpu_baseline(p, tt_obs.cpu().numpy())
     ctx.bet_destroy(b)
@@ -821,7 +825,8 @@ def run_bet(args):
                     f"(k {c['k_min']}..{c['k_max']}) on {c['nz']}x{c['nx']} nodes at {c['h']:g} m, "
                     f"{len(p['srcs'])} surface sources x {len(p['recs'])} receivers, {args.bet_iters} "
                     f"iterations per step",
-        "path": "rtm_bet_run (propose, raster, travel times, accept, sample per iteration)"},
+        "path": "rtm_bet_run (per chain group and stream: propose, raster, travel times, accept; "
+                "pooled statistics at sampling iterations)"},
         unit="chain iterations/s")
     out["metric"] = "Stage-1 chain iterations/s (each: one model, 34 travel-time solves)"
     out["dtype"] = "f32 travel times, f64 misfit and statistics"
@@ -830,10 +835,11 @@ def run_bet(args):
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
                        "frac": achieved / 157.3, "traffic": None, "kernel": "k_bet_eikonal",
                        "launch_us": eik_ms * 1e3,
-                       "note": f"{FLOP_PER_NODE_UPDATE} FP32 operations per node update x node updates of one "
-                               "launch (sweeps x nodes, averaged over the timed iterations) "
-                               "/ the launch's HIP-event time; FP32 vector peak 256 CUs x 2.4 GHz x 256; "
-                               "the sweeps are bound by the latency of dependent diagonals in LDS"}
+                       "note": f"{FLOP_PER_NODE_UPDATE} FP32 operations per node update x node updates (sweeps "
+                               "x nodes) of all travel-time launches in the timed region / its wall time: the "
+                               "launches of the chain groups overlap on their streams (launch_us: the first "
+                               "group's last launch, HIP events); FP32 vector peak 256 CUs x 2.4 GHz x 256; "
+                               "the sweeps are bound by the latency of dependent steps"}
     out["acceptance"] = acc / max(prop, 1)
     out["velocity_std_mean"] = float(std.mean())
     if cpu is not None:

@@ -13,6 +13,8 @@ constexpr int kBetMaxNodes = 12800;  // Eikonal grid nodes (LDS: 4 B per node pe
 // changes nothing, and a quiet sweep within 1021 sweeps is exactly a quiet
 // whole pass (four orderings) within 256 passes.
 constexpr int kBetMaxSweeps = 1021;
+// chain states recorded per sampling iteration before they are pooled
+constexpr int kBetSnapSlots = 16;
 
 // Layout of the grids a travel-time solve reads (times in LDS, the node
 // slowness in global memory).  Up to 64 rows (the row-per-lane sweeps) the
@@ -65,18 +67,25 @@ struct BetDev {
   // solves, fast sweeps (one ordering each)
   int64_t *proposed, *accepted;
   unsigned long long* work;
+  // chain states at sampling iterations: snap_k [kBetSnapSlots][chains],
+  // snap_z/x/v [kBetSnapSlots][chains][k_max]
+  int32_t* snap_k;
+  double *snap_z, *snap_x, *snap_v;
   // pooled post-burn-in statistics of the velocity grid
   double *mean, *m2;
   int32_t* count;
   uint32_t* flags;
 };
 
-hipError_t launch_bet_propose(const BetDev& d, int t, int init, hipStream_t s);
-hipError_t launch_bet_raster(const BetDev& d, hipStream_t s);
-hipError_t launch_bet_eikonal(const BetDev& d, hipStream_t s);
-// log_row (nullable): [chains] outcome of this iteration (-1 invalid, 0 rejected, 1 + move type)
-hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, hipStream_t s);
-hipError_t launch_bet_sample(const BetDev& d, hipStream_t s);
+// Each step of an iteration works on the chains c0 .. c0 + cn - 1.
+hipError_t launch_bet_propose(const BetDev& d, int t, int init, int c0, int cn, hipStream_t s);
+hipError_t launch_bet_raster(const BetDev& d, int c0, int cn, hipStream_t s);
+hipError_t launch_bet_eikonal(const BetDev& d, int c0, int cn, hipStream_t s);
+// log_row (nullable): [chains] outcome of this iteration (-1 invalid, 0 rejected, 1 + move type);
+// slot >= 0: also record the chains' states in snapshot slot `slot`
+hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, int c0, int cn, int slot, hipStream_t s);
+// adds the states of snapshot slot `slot` (every chain, in order) to the pooled statistics
+hipError_t launch_bet_sample(const BetDev& d, int slot, hipStream_t s);
 // mismatches (added to *bad) of the solver's square root against the
 // correctly rounded one over the float bit patterns [lo, hi), lo < hi
 hipError_t launch_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad, hipStream_t s);

@@ -260,9 +260,10 @@ __device__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, 
 
 }  // namespace
 
-__global__ __launch_bounds__(64) void k_bet_propose(BetDev d, int t, int init) {
-  const int c = blockIdx.x * 64 + threadIdx.x;
-  if (c >= d.chains) return;
+__global__ __launch_bounds__(64) void k_bet_propose(BetDev d, int t, int init, int c0, int cn) {
+  const int lc = blockIdx.x * 64 + threadIdx.x;
+  if (lc >= cn) return;
+  const int c = c0 + lc;
   const int K = d.k_max;
   const double Z = (double)(d.nz - 1) * d.h, X = (double)(d.nx - 1) * d.h;
   double* pz = d.pz + (size_t)c * K;
@@ -334,8 +335,8 @@ __global__ __launch_bounds__(64) void k_bet_propose(BetDev d, int t, int init) {
 }
 
 // nearest nucleus of the proposal at every node (ties: lowest index)
-__global__ __launch_bounds__(256) void k_bet_raster(BetDev d) {
-  const int c = blockIdx.y;
+__global__ __launch_bounds__(256) void k_bet_raster(BetDev d, int c0) {
+  const int c = c0 + blockIdx.y;
   if (!d.valid[c]) return;
   const int nz = d.nz, nx = d.nx, ld = bet_ld(nz, nx);
   const int q = blockIdx.x * 256 + threadIdx.x;
@@ -362,14 +363,16 @@ __global__ __launch_bounds__(256) void k_bet_raster(BetDev d) {
   d.node[(size_t)c * bet_grid_entries(nz, nx) + q] = out;
 }
 
-// travel times of the proposal of chain c from source e.  Blocks map to
-// (c, e) so that all of a chain's solves run on one XCD (blocks go to the
+// travel times of the proposal of chain c0 + lc from source e.  Blocks map
+// to (lc, e) so that all of a chain's solves run on one XCD (blocks go to the
 // XCDs in turn), whose L2 then holds that chain's node terms.
-__global__ __launch_bounds__(64) void k_bet_eikonal(BetDev d) {
+__global__ __launch_bounds__(64) void k_bet_eikonal(BetDev d, int c0, int cn) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int xcd = blockIdx.x & 7, r = blockIdx.x >> 3;
-  const int e = r % d.nsrc, c = (r / d.nsrc) * 8 + xcd;
-  if (c >= d.chains || !d.valid[c]) return;
+  const int e = r % d.nsrc, lc = (r / d.nsrc) * 8 + xcd;
+  if (lc >= cn) return;
+  const int c = c0 + lc;
+  if (!d.valid[c]) return;
   const int lane = threadIdx.x;
   const int nz = d.nz, nx = d.nx, ld = bet_ld(nz, nx);
   float* T = reinterpret_cast<float*>(smem) + kBetGuard;  // times, with guards
@@ -389,10 +392,10 @@ __global__ __launch_bounds__(64) void k_bet_eikonal(BetDev d) {
 }
 
 // misfit of the proposal and the Metropolis test (a workgroup per chain)
-__global__ __launch_bounds__(256) void k_bet_accept(BetDev d, int init, int8_t* log_row) {
+__global__ __launch_bounds__(256) void k_bet_accept(BetDev d, int init, int8_t* log_row, int c0, int slot) {
   __shared__ double red[256];
   __shared__ int s_acc;
-  const int c = blockIdx.x, tid = threadIdx.x;
+  const int c = c0 + blockIdx.x, tid = threadIdx.x;
   const int valid = d.valid[c];
   const int type = d.ptype[c];
   if (valid) {
@@ -433,10 +436,21 @@ __global__ __launch_bounds__(256) void k_bet_accept(BetDev d, int init, int8_t* 
     }
   }
   if (tid == 0 && log_row && !init) log_row[c] = (int8_t)(valid ? (s_acc ? 1 + type : 0) : -1);
+  if (slot >= 0) {  // a sampling iteration: the chain's state after this decision
+    __syncthreads();
+    const int k = d.k[c], K = d.k_max;
+    const size_t o = ((size_t)slot * d.chains + c) * K;
+    if (tid == 0) d.snap_k[(size_t)slot * d.chains + c] = k;
+    for (int q = tid; q < k; q += 256) {
+      d.snap_z[o + q] = d.z[(size_t)c * K + q];
+      d.snap_x[o + q] = d.x[(size_t)c * K + q];
+      d.snap_v[o + q] = d.v[(size_t)c * K + q];
+    }
+  }
 }
 
 // pooled FP64 Welford of every chain's current velocity grid (chains in order)
-__global__ __launch_bounds__(256) void k_bet_sample(BetDev d) {
+__global__ __launch_bounds__(256) void k_bet_sample(BetDev d, int slot) {
   const int n = d.nz * d.nx;
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
@@ -444,10 +458,12 @@ __global__ __launch_bounds__(256) void k_bet_sample(BetDev d) {
   const double z = (double)i * d.h, x = (double)j * d.h;
   double mean = d.mean[p], m2 = d.m2[p];
   int32_t cnt = d.count[p];
+  // the chains' states recorded at this sampling iteration, in chain order
+  const size_t o = (size_t)slot * d.chains;
   for (int c = 0; c < d.chains; ++c) {
-    const double* zs = d.z + (size_t)c * d.k_max;
-    const double* xs = d.x + (size_t)c * d.k_max;
-    const int k = d.k[c];
+    const double* zs = d.snap_z + (o + c) * d.k_max;
+    const double* xs = d.snap_x + (o + c) * d.k_max;
+    const int k = d.snap_k[o + c];
     int best = 0;
     double bd = INFINITY;
     for (int q = 0; q < k; ++q) {
@@ -458,7 +474,7 @@ __global__ __launch_bounds__(256) void k_bet_sample(BetDev d) {
         best = q;
       }
     }
-    const double v = d.v[(size_t)c * d.k_max + best];
+    const double v = d.snap_v[(o + c) * d.k_max + best];
     ++cnt;
     const double delta = v - mean;
     mean += delta / (double)cnt;
@@ -528,18 +544,18 @@ hipError_t launch_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad, 
 static size_t lds_bet(int nz, int nx) { return bet_lds_bytes(nz, nx); }
 static size_t lds_grid(int nz, int nx) { return 2 * bet_lds_bytes(nz, nx); }
 
-hipError_t launch_bet_propose(const BetDev& d, int t, int init, hipStream_t s) {
-  k_bet_propose<<<(d.chains + 63) / 64, 64, 0, s>>>(d, t, init);
+hipError_t launch_bet_propose(const BetDev& d, int t, int init, int c0, int cn, hipStream_t s) {
+  k_bet_propose<<<(cn + 63) / 64, 64, 0, s>>>(d, t, init, c0, cn);
   return hipGetLastError();
 }
 
-hipError_t launch_bet_raster(const BetDev& d, hipStream_t s) {
+hipError_t launch_bet_raster(const BetDev& d, int c0, int cn, hipStream_t s) {
   const int m = bet_grid_entries(d.nz, d.nx);
-  k_bet_raster<<<dim3((m + 255) / 256, d.chains), 256, 0, s>>>(d);
+  k_bet_raster<<<dim3((m + 255) / 256, cn), 256, 0, s>>>(d, c0);
   return hipGetLastError();
 }
 
-hipError_t launch_bet_eikonal(const BetDev& d, hipStream_t s) {
+hipError_t launch_bet_eikonal(const BetDev& d, int c0, int cn, hipStream_t s) {
   const int n = d.nz * d.nx;
   if (n > kBetMaxNodes || d.k_max > kBetMaxCells) return hipErrorInvalidValue;
   const size_t lds = lds_bet(d.nz, d.nx);
@@ -549,18 +565,18 @@ hipError_t launch_bet_eikonal(const BetDev& d, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   // 8 blocks (one per XCD) per source and group of 8 chains
-  k_bet_eikonal<<<8 * d.nsrc * ((d.chains + 7) / 8), 64, lds, s>>>(d);
+  k_bet_eikonal<<<8 * d.nsrc * ((cn + 7) / 8), 64, lds, s>>>(d, c0, cn);
   return hipGetLastError();
 }
 
-hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, hipStream_t s) {
-  k_bet_accept<<<d.chains, 256, 0, s>>>(d, init, log_row);
+hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, int c0, int cn, int slot, hipStream_t s) {
+  k_bet_accept<<<cn, 256, 0, s>>>(d, init, log_row, c0, slot);
   return hipGetLastError();
 }
 
-hipError_t launch_bet_sample(const BetDev& d, hipStream_t s) {
+hipError_t launch_bet_sample(const BetDev& d, int slot, hipStream_t s) {
   const int n = d.nz * d.nx;
-  k_bet_sample<<<(n + 255) / 256, 256, 0, s>>>(d);
+  k_bet_sample<<<(n + 255) / 256, 256, 0, s>>>(d, slot);
   return hipGetLastError();
 }
 

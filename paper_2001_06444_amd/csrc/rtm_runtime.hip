@@ -1945,10 +1945,33 @@ extern "C" int rtm_codec_decode(rtm_ctx* ctx, const void* stream_dev, int64_t st
 // ===========================================================================
 // Stage 1: Bayesian Eikonal tomography
 // ===========================================================================
+// Chains are independent, so groups of them advance on streams of their own
+// (the context stream and kBetGroups - 1 more): one group's last solves of
+// an iteration overlap the other group's next iteration instead of idling
+// the GPU at a per-iteration barrier.  Two groups: a process has few
+// hardware queues (4 by default, shared with the context's other streams),
+// and groups that share one run in turn.
+constexpr int kBetGroups = 2;
+
 struct rtm_bet {
   BetDev d{};
   std::vector<Block> blocks;
   int t = 0;  // iterations done
+  int groups = 1;
+  hipStream_t gs[kBetGroups] = {};     // gs[0] = the context stream (not owned)
+  hipEvent_t fork = nullptr, join[kBetGroups] = {};
+  ~rtm_bet() {
+    for (int g = 1; g < kBetGroups; ++g)
+      if (gs[g]) {
+        (void)hipStreamSynchronize(gs[g]);
+        (void)hipStreamDestroy(gs[g]);
+      }
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto e : join)
+      if (e) (void)hipEventDestroy(e);
+  }
+  int c0(int g) const { return (int)((int64_t)d.chains * g / groups); }
+  int cn(int g) const { return c0(g + 1) - c0(g); }
 };
 
 static int bet_points(const rtm_point* pts, int n, int nz, int nx, const char* what, std::vector<int2>& out) {
@@ -2070,6 +2093,10 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   d.proposed = static_cast<int64_t*>(get(8 * 3 * C));
   d.accepted = static_cast<int64_t*>(get(8 * 3 * C));
   d.work = static_cast<unsigned long long*>(get(8 * 2 * C));
+  d.snap_k = static_cast<int32_t*>(get(4 * (size_t)kBetSnapSlots * C));
+  d.snap_z = static_cast<double*>(get(8 * (size_t)kBetSnapSlots * C * K));
+  d.snap_x = static_cast<double*>(get(8 * (size_t)kBetSnapSlots * C * K));
+  d.snap_v = static_cast<double*>(get(8 * (size_t)kBetSnapSlots * C * K));
   d.mean = static_cast<double*>(get(8 * n));
   d.m2 = static_cast<double*>(get(8 * n));
   d.count = static_cast<int32_t*>(get(4 * n));
@@ -2079,6 +2106,19 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
     return fail(RTM_E_NOMEM, "arena exhausted (sampler state)");
   }
   hipStream_t s = ctx->stream;
+  b->groups = std::min(kBetGroups, c.chains);
+  b->gs[0] = s;
+  {
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int g = 0; g < b->groups && e == hipSuccess; ++g) {
+      if (g > 0) e = hipStreamCreateWithFlags(&b->gs[g], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[g], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      release_blocks(ctx, b->blocks);
+      return fail(RTM_E_DEVICE, "sampler streams: %s", hipGetErrorString(e));
+    }
+  }
   HIP_OK(hipMemcpyAsync(const_cast<int2*>(d.src), src.data(), 8 * (size_t)nsrc, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(const_cast<int2*>(d.rec), rec.data(), 8 * (size_t)nrec, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(const_cast<float*>(d.tt_obs), tt_obs_dev, 4 * nd, hipMemcpyDeviceToDevice, s));
@@ -2090,10 +2130,10 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   HIP_OK(hipMemsetAsync(d.count, 0, 4 * n, s));
   HIP_OK(hipMemsetAsync(d.flags, 0, 256, s));
   // the initial model of every chain and its misfit
-  HIP_OK(launch_bet_propose(d, -1, 1, s));
-  HIP_OK(launch_bet_raster(d, s));
-  HIP_OK(launch_bet_eikonal(d, s));
-  HIP_OK(launch_bet_accept(d, 1, nullptr, s));
+  HIP_OK(launch_bet_propose(d, -1, 1, 0, C, s));
+  HIP_OK(launch_bet_raster(d, 0, C, s));
+  HIP_OK(launch_bet_eikonal(d, 0, C, s));
+  HIP_OK(launch_bet_accept(d, 1, nullptr, 0, C, -1, s));
   // the host vectors above are copied from before this call returns
   HIP_OK(hipStreamSynchronize(s));
   *out = b.release();
@@ -2105,18 +2145,42 @@ extern "C" int rtm_bet_run(rtm_ctx* ctx, rtm_bet* bet, int32_t iterations, int8_
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const BetDev& d = bet->d;
-  for (int it = 0; it < iterations; ++it) {
-    const int t = bet->t + it;
-    const bool last = it == iterations - 1;
-    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[0], s));
-    HIP_OK(launch_bet_propose(d, t, 0, s));
-    HIP_OK(launch_bet_raster(d, s));
-    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[1], s));
-    HIP_OK(launch_bet_eikonal(d, s));
-    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[2], s));
-    HIP_OK(launch_bet_accept(d, 0, log_dev ? log_dev + (size_t)it * d.chains : nullptr, s));
-    if (t >= d.burn_in && (t - d.burn_in) % d.thin == 0) HIP_OK(launch_bet_sample(d, s));
-    if (last) HIP_OK(hipEventRecord(ctx->bet_ev[3], s));
+  const int G = bet->groups;
+  auto sampling = [&](int t) { return t >= d.burn_in && (t - d.burn_in) % d.thin == 0; };
+  // Segments of iterations holding at most kBetSnapSlots sampling iterations:
+  // every group runs the segment on its stream, recording the chains' states
+  // at sampling iterations; then the context stream pools them, chain by
+  // chain in order, exactly as one stream would.
+  for (int it = 0; it < iterations;) {
+    int end = it, slots = 0;
+    while (end < iterations && !(slots == kBetSnapSlots && sampling(bet->t + end))) slots += sampling(bet->t + end++);
+    HIP_OK(hipEventRecord(bet->fork, s));  // the groups start after earlier work on the context stream
+    for (int g = 1; g < G; ++g) HIP_OK(hipStreamWaitEvent(bet->gs[g], bet->fork, 0));
+    // iteration by iteration, so that groups sharing a hardware queue alternate
+    for (int q = it, slot = 0; q < end; ++q) {
+      const int t = bet->t + q;
+      for (int g = 0; g < G; ++g) {
+        hipStream_t gs = bet->gs[g];
+        const int c0 = bet->c0(g), cn = bet->cn(g);
+        const bool timed = g == 0 && q == iterations - 1;  // the last iteration of the first group
+        if (timed) HIP_OK(hipEventRecord(ctx->bet_ev[0], gs));
+        HIP_OK(launch_bet_propose(d, t, 0, c0, cn, gs));
+        HIP_OK(launch_bet_raster(d, c0, cn, gs));
+        if (timed) HIP_OK(hipEventRecord(ctx->bet_ev[1], gs));
+        HIP_OK(launch_bet_eikonal(d, c0, cn, gs));
+        if (timed) HIP_OK(hipEventRecord(ctx->bet_ev[2], gs));
+        HIP_OK(launch_bet_accept(d, 0, log_dev ? log_dev + (size_t)q * d.chains : nullptr, c0, cn,
+                                 sampling(t) ? slot : -1, gs));
+        if (timed) HIP_OK(hipEventRecord(ctx->bet_ev[3], gs));
+      }
+      slot += sampling(t);
+    }
+    for (int g = 1; g < G; ++g) {
+      HIP_OK(hipEventRecord(bet->join[g], bet->gs[g]));
+      HIP_OK(hipStreamWaitEvent(s, bet->join[g], 0));
+    }
+    for (int slot = 0; slot < slots; ++slot) HIP_OK(launch_bet_sample(d, slot, s));
+    it = end;
   }
   if (iterations > 0) ctx->bet_valid = true;
   bet->t += iterations;
@@ -2158,7 +2222,7 @@ extern "C" int rtm_bet_destroy(rtm_ctx* ctx, rtm_bet* bet) {
   if (!ctx || !bet) return fail(RTM_E_INVAL, "bad arguments");
   Deferred dd;
   dd.blocks = std::move(bet->blocks);
-  delete bet;
+  delete bet;  // its streams have no work the context stream does not already wait for
   return defer(ctx, ctx->stream, std::move(dd));
 }
 

@@ -100,8 +100,13 @@ def _compare_chains(ctx, b, ref, chains, K, first=0):
         assert g["proposed"] == list(ref["proposed"][o]) and g["accepted"] == list(ref["accepted"][o])
 
 
-def test_chains_match_oracle(ctx, rtm):
+@pytest.mark.parametrize("chains", [8, 3])
+def test_chains_match_oracle(ctx, rtm, chains):
+    # chains advance in two groups on separate streams (8 chains: four and
+    # four; 3 chains: one and two); the sampling iterations (every third from
+    # 40) exceed the 16 state snapshots of one segment in both calls
     cfg, srcs, recs, tt_obs = _small_problem()
+    cfg["chains"] = chains
     iters = 150
     b = ctx.bet_create(srcs, recs, dev(tt_obs), **cfg)
     log = torch.full((iters, cfg["chains"]), 99, dtype=torch.int8, device="cuda")
