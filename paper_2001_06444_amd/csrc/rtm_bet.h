@@ -71,6 +71,7 @@ struct BetDev {
   // snap_z/x/v [kBetSnapSlots][chains][k_max]
   int32_t* snap_k;
   double *snap_z, *snap_x, *snap_v;
+  double* sample_v;  // [chains][nz*nx] velocities of one snapshot slot
   // pooled post-burn-in statistics of the velocity grid
   double *mean, *m2;
   int32_t* count;

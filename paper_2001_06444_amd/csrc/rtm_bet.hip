@@ -450,31 +450,41 @@ __global__ __launch_bounds__(256) void k_bet_accept(BetDev d, int init, int8_t* 
 }
 
 // pooled FP64 Welford of every chain's current velocity grid (chains in order)
-__global__ __launch_bounds__(256) void k_bet_sample(BetDev d, int slot) {
-  const int n = d.nz * d.nx;
+// velocity of every chain's recorded state at every node (a thread per node
+// and chain): the nearest nucleus, ties to the lowest index
+__global__ __launch_bounds__(256) void k_bet_sample_vel(BetDev d, int slot) {
+  const int n = d.nz * d.nx, c = blockIdx.y;
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
   const int i = p / d.nx, j = p - (p / d.nx) * d.nx;
   const double z = (double)i * d.h, x = (double)j * d.h;
+  const size_t o = (size_t)slot * d.chains + c;
+  const double* zs = d.snap_z + o * d.k_max;
+  const double* xs = d.snap_x + o * d.k_max;
+  const int k = d.snap_k[o];
+  int best = 0;
+  double bd = INFINITY;
+  for (int q = 0; q < k; ++q) {
+    const double dz = z - zs[q], dx = x - xs[q];
+    const double d2 = dz * dz + dx * dx;
+    if (d2 < bd) {
+      bd = d2;
+      best = q;
+    }
+  }
+  d.sample_v[(size_t)c * n + p] = d.snap_v[o * d.k_max + best];
+}
+
+// pooled FP64 Welford update of every node with the chains' velocities, in
+// chain order (a thread per node)
+__global__ __launch_bounds__(256) void k_bet_sample(BetDev d) {
+  const int n = d.nz * d.nx;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
   double mean = d.mean[p], m2 = d.m2[p];
   int32_t cnt = d.count[p];
-  // the chains' states recorded at this sampling iteration, in chain order
-  const size_t o = (size_t)slot * d.chains;
   for (int c = 0; c < d.chains; ++c) {
-    const double* zs = d.snap_z + (o + c) * d.k_max;
-    const double* xs = d.snap_x + (o + c) * d.k_max;
-    const int k = d.snap_k[o + c];
-    int best = 0;
-    double bd = INFINITY;
-    for (int q = 0; q < k; ++q) {
-      const double dz = z - zs[q], dx = x - xs[q];
-      const double d2 = dz * dz + dx * dx;
-      if (d2 < bd) {
-        bd = d2;
-        best = q;
-      }
-    }
-    const double v = d.snap_v[(o + c) * d.k_max + best];
+    const double v = d.sample_v[(size_t)c * n + p];
     ++cnt;
     const double delta = v - mean;
     mean += delta / (double)cnt;
@@ -576,7 +586,8 @@ hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, int c0,
 
 hipError_t launch_bet_sample(const BetDev& d, int slot, hipStream_t s) {
   const int n = d.nz * d.nx;
-  k_bet_sample<<<(n + 255) / 256, 256, 0, s>>>(d, slot);
+  k_bet_sample_vel<<<dim3((n + 255) / 256, d.chains), 256, 0, s>>>(d, slot);
+  k_bet_sample<<<(n + 255) / 256, 256, 0, s>>>(d);
   return hipGetLastError();
 }
 

@@ -2097,6 +2097,7 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   d.snap_z = static_cast<double*>(get(8 * (size_t)kBetSnapSlots * C * K));
   d.snap_x = static_cast<double*>(get(8 * (size_t)kBetSnapSlots * C * K));
   d.snap_v = static_cast<double*>(get(8 * (size_t)kBetSnapSlots * C * K));
+  d.sample_v = static_cast<double*>(get(8 * C * n));
   d.mean = static_cast<double*>(get(8 * n));
   d.m2 = static_cast<double*>(get(8 * n));
   d.count = static_cast<int32_t*>(get(4 * n));
