@@ -114,6 +114,9 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=300, help="serve workload: timed jobs")
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: jobs/s")
+    ap.add_argument("--default-serve-jobs", type=int, default=100,
+                    help="survey workload: timed jobs of the short served stream reported beside it")
+    ap.add_argument("--no-serve", action="store_true", help="survey workload: skip the short served stream")
     return ap.parse_args()
 
 
@@ -286,6 +289,15 @@ def run_survey(args):
                                         "alg_bytes_per_launch": s1.last_fwd_launch_bytes}},
         "cpu_baseline": base,
     })
+    if not args.no_serve:
+        # the served path on the same GPU: a shorter Poisson stream than
+        # --workload serve runs (percentiles from its timed jobs only)
+        del ctx
+        torch.cuda.empty_cache()
+        res = _serve(args, 10, args.default_serve_jobs, saturation=False)
+        res["workload"] = (f"served stream: Poisson {args.rate} jobs/s, 256 velocity samples, apertures "
+                           "301-1701, nt 2000-4000, store mode stride 4 fp32/bf16")
+        out["served"] = res
     return out
 
 
@@ -409,10 +421,12 @@ def run_ensemble(args):
     return out
 
 
-def run_serve(args):
+def _serve(args, n_warm, n_timed, saturation):
     """Poisson stream of RTM jobs (velocity sample, shot, aperture, nt, snapshot
     dtype) served by continuous batching; latency = completion - arrival,
-    including queueing and the upload of the job's data."""
+    including queueing and the upload of the job's data.  Returns the
+    latency percentiles and served rate of the timed jobs, and with
+    `saturation` also a run with every job arriving at t = 0."""
     import numpy as np
     import torch
 
@@ -421,7 +435,7 @@ def run_serve(args):
     dev = torch.device("cuda:0")
     nz, nx, h, dt, nb = 351, 1701, 10.0, 1e-3, 50
     base, smooth = _ensemble_setup(nz, nx, h)
-    n_all = args.serve_warmup + args.serve_jobs
+    n_all = n_warm + n_timed
     stream = inputs.poisson_stream(n_all, rate=args.rate, seed=5, n_real=256, nx=nx)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
     ntmax = max(j.nt for j in stream)
@@ -478,36 +492,43 @@ def run_serve(args):
         return lat, ok, t_end
 
     arrivals = [j.arrival for j in stream]
-    s0 = ctx.stats()
     lat, ok, t_end = serve(arrivals)
-    s1 = ctx.stats()
-    timed = slice(args.serve_warmup, n_all)
-    lt = lat[timed]
-    span = t_end - arrivals[args.serve_warmup]
-    served_ips = args.serve_jobs / span
-    p50, p99 = float(np.percentile(lt, 50)), float(np.percentile(lt, 99))
-    log(f"[bench] serve @ {args.rate}/s: p50 {p50 * 1e3:.0f} ms, p99 {p99 * 1e3:.0f} ms, "
-        f"{served_ips:.1f} images/s, {int((~ok).sum())} failed")
-    # saturation: every job arrives at t = 0
-    u0 = ctx.stats().grid_updates
-    lat0, ok0, t_end0 = serve([0.0] * n_all)
-    sat_updates = ctx.stats().grid_updates - u0
-    sat_ips = n_all / t_end0
-    log(f"[bench] saturation: {n_all} jobs in {t_end0:.2f} s, {sat_ips:.1f} images/s, "
-        f"{sat_updates / t_end0:.3e} updates/s")
+    lt = lat[n_warm:]
+    span = t_end - arrivals[n_warm]
+    res = {"rate": args.rate, "jobs": n_timed, "warmup_jobs": n_warm,
+           "latency_ms": {"p50": float(np.percentile(lt, 50)) * 1e3, "p99": float(np.percentile(lt, 99)) * 1e3,
+                          "max": float(lt.max()) * 1e3},
+           "images_per_s": n_timed / span, "failed_jobs": int((~ok).sum())}
+    log(f"[bench] serve @ {args.rate}/s: p50 {res['latency_ms']['p50']:.0f} ms, "
+        f"p99 {res['latency_ms']['p99']:.0f} ms, {res['images_per_s']:.1f} images/s, "
+        f"{res['failed_jobs']} failed")
+    if saturation:  # every job arrives at t = 0
+        u0 = ctx.stats().grid_updates
+        lat0, ok0, t_end0 = serve([0.0] * n_all)
+        res["saturation"] = {"seconds": t_end0, "images_per_s": n_all / t_end0,
+                             "updates_per_s": (ctx.stats().grid_updates - u0) / t_end0,
+                             "failed_jobs": int((~ok0).sum())}
+        log(f"[bench] saturation: {n_all} jobs in {t_end0:.2f} s, {n_all / t_end0:.1f} images/s, "
+            f"{res['saturation']['updates_per_s']:.3e} updates/s")
     ctx.close()
-    out = _base_record(args, sat_updates / t_end0, t_end0 * 1e3, {
+    return res
+
+
+def run_serve(args):
+    """The served stream at full length, plus its saturation run."""
+    res = _serve(args, args.serve_warmup, args.serve_jobs, saturation=True)
+    sat = res["saturation"]
+    out = _base_record(args, sat["updates_per_s"], sat["seconds"] * 1e3, {
         "workload": f"served stream: Poisson {args.rate} jobs/s, {args.serve_jobs} timed jobs "
                     f"(+{args.serve_warmup} warm-up), 256 velocity samples, apertures 301-1701, "
                     f"nt 2000-4000, store mode stride 4 fp32/bf16, FP64 per-realization mean/std",
         "rate": args.rate, "jobs": args.serve_jobs, "path": "served engine (continuous batching)"})
     out.update({"steps": 1, "warmup": 0,
-                "latency_ms": {"p50": p50 * 1e3, "p99": p99 * 1e3, "max": float(lt.max() * 1e3)},
-                "served_images_per_s": served_ips, "saturation_images_per_s": sat_ips,
-                "failed_jobs": int((~ok).sum() + (~ok0).sum()),
+                "latency_ms": res["latency_ms"],
+                "served_images_per_s": res["images_per_s"], "saturation_images_per_s": sat["images_per_s"],
+                "failed_jobs": res["failed_jobs"] + sat["failed_jobs"],
                 "value_is": "grid-pt updates/s of the saturation run"})
     return out
-
 
 
 def run_small(args):
