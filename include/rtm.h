@@ -437,15 +437,19 @@ int rtm_eikonal(rtm_ctx *ctx, const float *vel_dev, int32_t nz, int32_t nx, floa
 
 /* Creates the sampler: copies the observed travel times tt_obs_dev
  * [nsrc][nrec] (s), draws every chain's initial model and computes its
- * misfit (stream-ordered).  Errors: RTM_E_INVAL (bad configuration,
- * including h / v outside [1e-9, 1e18] s for v in [v_min, v_max]),
+ * misfit (stream-ordered).  Errors: RTM_E_INVAL (bad configuration:
+ * chains outside 1..65535, k bounds outside 1..64, h / v outside
+ * [1e-9, 1e18] s for v in [v_min, v_max], ...),
  * RTM_E_NOMEM (arena). */
 int rtm_bet_create(rtm_ctx *ctx, const rtm_bet_config *cfg, int32_t nsrc, const rtm_point *src_host,
                    int32_t nrec, const rtm_point *rec_host, const float *tt_obs_dev, rtm_bet **out);
 
 /* Advances every chain by `iterations` (stream-ordered, returns after
- * enqueue).  log_dev (nullable) receives [iterations][chains] outcomes:
- * -1 invalid proposal, 0 rejected, 1 birth / 2 death / 3 move accepted. */
+ * enqueue: the chains advance in two groups on streams the sampler owns,
+ * which start after the context stream's earlier work and which the context
+ * stream waits for).  log_dev (nullable) receives [iterations][chains]
+ * outcomes: -1 invalid proposal, 0 rejected, 1 birth / 2 death / 3 move
+ * accepted.  Calls on one sampler must not overlap. */
 int rtm_bet_run(rtm_ctx *ctx, rtm_bet *bet, int32_t iterations, int8_t *log_dev);
 
 /* Copies chain `chain`'s state to the host (synchronous): info, and the

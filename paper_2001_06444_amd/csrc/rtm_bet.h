@@ -8,6 +8,7 @@
 namespace rtm {
 
 constexpr int kBetMaxCells = 64;     // Voronoi nuclei per model
+constexpr int kBetMaxChains = 65535; // chains per sampler (a launch dimension)
 constexpr int kBetMaxNodes = 12800;  // Eikonal grid nodes (LDS: 4 B per node per wavefront)
 // Fast sweeps before giving up: the solvers stop at the first sweep that
 // changes nothing, and a quiet sweep within 1021 sweeps is exactly a quiet

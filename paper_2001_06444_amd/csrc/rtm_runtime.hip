@@ -2026,8 +2026,10 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   if (c.nz < 2 || c.nx < 2 || (int64_t)c.nz * c.nx > kBetMaxNodes || !(c.h > 0) || !std::isfinite(c.h))
     return fail(RTM_E_INVAL, "grid %d x %d, h %g: need 2..%d nodes per side product and h > 0", c.nz, c.nx, c.h,
                 kBetMaxNodes);
-  if (c.chains < 1 || c.k_min < 1 || c.k_init < c.k_min || c.k_max < c.k_init || c.k_max > kBetMaxCells)
-    return fail(RTM_E_INVAL, "need chains >= 1 and 1 <= k_min <= k_init <= k_max <= %d", kBetMaxCells);
+  if (c.chains < 1 || c.chains > kBetMaxChains || c.k_min < 1 || c.k_init < c.k_min || c.k_max < c.k_init ||
+      c.k_max > kBetMaxCells)
+    return fail(RTM_E_INVAL, "need 1 <= chains <= %d and 1 <= k_min <= k_init <= k_max <= %d", kBetMaxChains,
+                kBetMaxCells);
   if (!(c.v_min > 0) || !(c.v_max > c.v_min) || !std::isfinite(c.v_max))
     return fail(RTM_E_INVAL, "need 0 < v_min < v_max");
   {  // the node terms the solves will see, as the device computes them

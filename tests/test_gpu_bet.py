@@ -135,7 +135,8 @@ def test_bet_rejects(ctx, rtm):
     cfg, srcs, recs, tt_obs = _small_problem()
     t = dev(tt_obs)
     for bad in (dict(k_max=65), dict(k_min=0), dict(k_init=30), dict(v_max=1000.0), dict(p_birth=0.8),
-                dict(sigma=0.0), dict(thin=0), dict(nz=200, nx=200), dict(h=1e-6), dict(v_min=1e-20)):
+                dict(sigma=0.0), dict(thin=0), dict(nz=200, nx=200), dict(h=1e-6), dict(v_min=1e-20),
+                dict(chains=0), dict(chains=65536)):
         with pytest.raises(rtm.RTMError):
             ctx.bet_create(srcs, recs, t, **{**cfg, **bad})
     with pytest.raises(rtm.RTMError):
