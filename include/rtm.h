@@ -462,6 +462,15 @@ int rtm_bet_chain(rtm_ctx *ctx, rtm_bet *bet, int32_t chain, rtm_bet_chain_info 
  * double and count_dev [nz][nx] int32, each nullable (stream-ordered). */
 int rtm_bet_stats(rtm_ctx *ctx, rtm_bet *bet, double *mean_dev, double *std_dev, int32_t *count_dev);
 
+/* The velocity grid vel_dev [nz][nx] (m/s, float) of chain `chain`'s current
+ * model sampled at nodes (i h, j h): each node takes the velocity of its
+ * nearest nucleus (ties: lowest index), the model definition of Sec. 2.1, at
+ * any spacing -- how a sample of Stage 1 becomes a velocity model for the
+ * migrations of Stage 2 (e.g. nz, nx, h of the RTM grid covering the same
+ * extent).  Stream-ordered.  Errors: RTM_E_INVAL (chain out of range, sizes
+ * not positive or above 2^31 nodes, h not positive). */
+int rtm_bet_model(rtm_ctx *ctx, rtm_bet *bet, int32_t chain, int32_t nz, int32_t nx, double h, float *vel_dev);
+
 int rtm_bet_destroy(rtm_ctx *ctx, rtm_bet *bet);
 
 /* Self-check of the travel-time arithmetic: counts into *mismatches the

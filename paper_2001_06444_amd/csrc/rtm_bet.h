@@ -88,6 +88,8 @@ hipError_t launch_bet_eikonal(const BetDev& d, int c0, int cn, hipStream_t s);
 hipError_t launch_bet_accept(const BetDev& d, int init, int8_t* log_row, int c0, int cn, int slot, hipStream_t s);
 // adds the states of snapshot slot `slot` (every chain, in order) to the pooled statistics
 hipError_t launch_bet_sample(const BetDev& d, int slot, hipStream_t s);
+// velocity grid [nz][nx] (float) of chain c's current model at nodes (i h, j h)
+hipError_t launch_bet_model(const BetDev& d, int c, int nz, int nx, double h, float* vel, hipStream_t s);
 // mismatches (added to *bad) of the solver's square root against the
 // correctly rounded one over the float bit patterns [lo, hi), lo < hi
 hipError_t launch_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad, hipStream_t s);

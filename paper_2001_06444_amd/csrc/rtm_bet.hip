@@ -529,6 +529,36 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
   }
 }
 
+// Velocity grid [nz][nx] of chain c's current model sampled at nodes
+// (i h, j h): the nearest nucleus's velocity (FP64 distances, ties to the
+// lowest index), as float.
+__global__ __launch_bounds__(256) void k_bet_model(BetDev d, int c, int nz, int nx, double h, float* vel) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (int64_t)nz * nx) return;
+  const int i = (int)(p / nx), j = (int)(p - (p / nx) * nx);
+  const double z = (double)i * h, x = (double)j * h;
+  const double* zs = d.z + (size_t)c * d.k_max;
+  const double* xs = d.x + (size_t)c * d.k_max;
+  const int k = d.k[c];
+  int best = 0;
+  double bd = INFINITY;
+  for (int q = 0; q < k; ++q) {
+    const double dz = z - zs[q], dx = x - xs[q];
+    const double d2 = dz * dz + dx * dx;
+    if (d2 < bd) {
+      bd = d2;
+      best = q;
+    }
+  }
+  vel[p] = (float)d.v[(size_t)c * d.k_max + best];
+}
+
+hipError_t launch_bet_model(const BetDev& d, int c, int nz, int nx, double h, float* vel, hipStream_t s) {
+  const int64_t n = (int64_t)nz * nx;
+  k_bet_model<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d, c, nz, nx, h, vel);
+  return hipGetLastError();
+}
+
 // Counts the float bit patterns in [lo, hi) where sqrt_rn differs from the
 // correctly rounded square root (a thread per 256 patterns).
 __global__ __launch_bounds__(256) void k_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad) {

@@ -2221,6 +2221,16 @@ extern "C" int rtm_bet_stats(rtm_ctx* ctx, rtm_bet* bet, double* mean_dev, doubl
   return RTM_OK;
 }
 
+extern "C" int rtm_bet_model(rtm_ctx* ctx, rtm_bet* bet, int32_t chain, int32_t nz, int32_t nx, double h,
+                             float* vel_dev) {
+  if (!ctx || !bet || !vel_dev || chain < 0 || chain >= bet->d.chains) return fail(RTM_E_INVAL, "bad arguments");
+  if (nz < 1 || nx < 1 || (int64_t)nz * nx > ((int64_t)1 << 31) || !(h > 0) || !std::isfinite(h))
+    return fail(RTM_E_INVAL, "grid %d x %d, h %g: need positive sizes, at most 2^31 nodes, h > 0", nz, nx, h);
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(launch_bet_model(bet->d, chain, nz, nx, h, vel_dev, ctx->stream));
+  return RTM_OK;
+}
+
 extern "C" int rtm_bet_destroy(rtm_ctx* ctx, rtm_bet* bet) {
   if (!ctx || !bet) return fail(RTM_E_INVAL, "bad arguments");
   Deferred dd;

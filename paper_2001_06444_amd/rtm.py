@@ -137,6 +137,7 @@ SIGNATURES = {
     "rtm_bet_run": ([_V, _V, _I32, _V], ctypes.c_int),
     "rtm_bet_chain": ([_V, _V, _I32, _P(BetChainInfo), _V, _V, _V], ctypes.c_int),
     "rtm_bet_stats": ([_V, _V, _V, _V, _V], ctypes.c_int),
+    "rtm_bet_model": ([_V, _V, _I32, _I32, _I32, _D, _V], ctypes.c_int),
     "rtm_bet_destroy": ([_V, _V], ctypes.c_int),
     "rtm_sqrt_check": ([_V, ctypes.c_uint32, ctypes.c_uint32, _P(ctypes.c_uint64)], ctypes.c_int),
     "rtm_ctx_stats": ([_V, _P(CtxStats)], ctypes.c_int),
@@ -425,6 +426,12 @@ class Context:
 
     def bet_stats(self, bet, mean=None, std=None, count=None):
         _check(lib().rtm_bet_stats(self.h, bet, _ptr(mean), _ptr(std), _ptr(count)))
+
+    def bet_model(self, bet, chain: int, vel_out, h: float):
+        """Chain `chain`'s current model sampled on vel_out's [nz][nx] grid at
+        spacing h (stream-ordered)."""
+        nz, nx = vel_out.shape
+        _check(lib().rtm_bet_model(self.h, bet, chain, nz, nx, float(h), _ptr(vel_out)))
 
     def bet_destroy(self, bet):
         _check(lib().rtm_bet_destroy(self.h, bet))

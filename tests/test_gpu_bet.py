@@ -178,3 +178,25 @@ def test_square_root_correctly_rounded(ctx, rtm):
     assert ctx.sqrt_check(int(lo), int(hi) + 1) == 0
     with pytest.raises(rtm.RTMError):
         ctx.sqrt_check(5, 5)
+
+
+def test_chain_model_on_a_finer_grid(ctx, rtm):
+    """A chain's model sampled for migration: the nearest nucleus on a grid ten
+    times finer than the tomography's (same extent), equal to the oracle's
+    Voronoi cells node for node."""
+    cfg, srcs, recs, tt_obs = _small_problem()
+    b = ctx.bet_create(srcs, recs, dev(tt_obs), **cfg)
+    ctx.bet_run(b, 30)
+    nz, nx, h = (cfg["nz"] - 1) * 10 + 1, (cfg["nx"] - 1) * 10 + 1, cfg["h"] / 10
+    for c in (0, cfg["chains"] - 1):
+        g = ctx.bet_chain(b, c, cfg["k_max"])
+        vel = torch.empty(nz, nx, dtype=torch.float32, device="cuda")
+        ctx.bet_model(b, c, vel, h)
+        k = g["k"]
+        cell = obet.voronoi(nz, nx, h, g["z"][:k], g["x"][:k])
+        np.testing.assert_array_equal(vel.cpu().numpy(), np.asarray(g["v"][:k])[cell].astype(np.float32))
+    with pytest.raises(rtm.RTMError):
+        ctx.bet_model(b, cfg["chains"], torch.empty(4, 4, device="cuda"), 10.0)
+    with pytest.raises(rtm.RTMError):
+        ctx.bet_model(b, 0, torch.empty(4, 4, device="cuda"), 0.0)
+    ctx.bet_destroy(b)
