@@ -200,3 +200,25 @@ def test_chain_model_on_a_finer_grid(ctx, rtm):
     with pytest.raises(rtm.RTMError):
         ctx.bet_model(b, 0, torch.empty(4, 4, device="cuda"), 0.0)
     ctx.bet_destroy(b)
+
+
+def test_chains_on_a_tall_grid_match_oracle(ctx, rtm):
+    """More than 64 rows: the sampler's solves take the anti-diagonal sweep
+    (node terms from global memory); every accept decision and final state
+    equal the oracle's."""
+    nz, nx, h = 70, 20, 50.0
+    # the faulted-layer model (10 m) sampled every 5th node: 3.5 km deep
+    true = np.ascontiguousarray(inputs.faulted_layers()[::5, ::5][:nz, :nx]).astype(np.float64)
+    srcs = [(0, 2), (0, 10), (69, 17)]
+    recs = [(0, j) for j in range(nx)] + [(i, nx - 1) for i in range(0, nz, 5)]
+    tt_obs = obet.travel_times(true, h, srcs, recs, single=True).astype(np.float32)
+    cfg = dict(nz=nz, nx=nx, h=h, chains=3, k_min=2, k_max=16, k_init=5, burn_in=5, thin=2, v_min=1400.0,
+               v_max=5000.0, p_birth=0.3, p_death=0.3, move_dz=300.0, move_dx=200.0, sigma=0.01, seed=77)
+    iters = 25
+    b = ctx.bet_create(srcs, recs, dev(tt_obs), **cfg)
+    log = torch.full((iters, cfg["chains"]), 99, dtype=torch.int8, device="cuda")
+    ctx.bet_run(b, iters, log)
+    ref = obet.run(_oracle_cfg(cfg), srcs, recs, tt_obs, iters, log=True)
+    assert (log.cpu().numpy() == ref["log"]).all()
+    _compare_chains(ctx, b, ref, range(cfg["chains"]), cfg["k_max"])
+    ctx.bet_destroy(b)
