@@ -18,18 +18,27 @@ constexpr int kBetMaxSweeps = 1021;
 constexpr int kBetSnapSlots = 16;
 
 // Layout of the grids a travel-time solve reads (times in LDS, the node
-// slowness in global memory).  Up to 64 rows (the row-per-lane sweeps) the
-// row stride ld leaves at least one pad column after each row, and is even:
-// a step touches addresses l (ld - 1) + c or l (ld + 1) + c over the lanes l,
-// and an odd multiplier sends the lanes to distinct LDS banks.  kBetGuard
-// entries before row 0, one more row after the last (+inf in the times: the
-// row below the grid) and 64 entries after that keep the reads of lanes
-// outside the grid in bounds.
-constexpr int kBetGuard = 68;
-__host__ __device__ inline int bet_ld(int nz, int nx) { return nz <= 64 ? (nx + 1) + ((nx + 1) & 1) : nx; }
+// slowness in global memory).  Up to 128 rows (the row-per-lane sweeps, one
+// or two rows per lane) the row stride ld leaves at least one pad column
+// after each row, and is even: a step touches addresses l (ld - 1) + c or
+// l (ld + 1) + c over the lanes l, and an odd multiplier sends the lanes to
+// distinct LDS banks.  kBetGuard entries before row 0, one more row after
+// the last (+inf in the times: the row below the grid) and kBetTail entries
+// after that keep the reads of lanes outside the grid in bounds (a lane's
+// second row starts 127 columns before the grid at most).
+constexpr int kBetGuard = 132, kBetTail = 132;
+__host__ __device__ inline int bet_ld(int nz, int nx) { return nz <= 128 ? (nx + 1) + ((nx + 1) & 1) : nx; }
 __host__ __device__ inline int bet_grid_entries(int nz, int nx) {
-  return kBetGuard + (nz + 1) * bet_ld(nz, nx) + 64;
+  return kBetGuard + (nz + 1) * bet_ld(nz, nx) + kBetTail;
 }
+// LDS of one solve: the times (a sampler's solve) or the times and the node
+// slowness (a velocity grid's solve); a grid must fit the CU's 160 KB
+constexpr size_t kBetMaxLds = 163840;
+__host__ __device__ inline size_t bet_lds_bytes(int nz, int nx) {
+  return ((size_t)bet_grid_entries(nz, nx) * 4 + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t bet_lds_sampler(int nz, int nx) { return bet_lds_bytes(nz, nx); }
+__host__ __device__ inline size_t bet_lds_grid(int nz, int nx) { return 2 * bet_lds_bytes(nz, nx); }
 
 // sh = slowness * h and q2 = sh sh + sh sh of a node, in single precision:
 // the two terms of the Godunov update that depend on the node alone

@@ -94,21 +94,21 @@ __device__ inline float godunov(float a, float b, BetSlowness s) {
   return !(d < s.sh) ? lo + s.sh : two;
 }
 
-// bytes of one float grid with its guards
-__host__ __device__ inline size_t bet_lds_bytes(int nz, int nx) {
-  return ((size_t)bet_grid_entries(nz, nx) * 4 + 15) & ~(size_t)15;
-}
-
 // The node terms a solve reads: precomputed per node in global memory
 // (Stage-1 models), or from the node slowness in LDS (a velocity grid).
+// (`ptr`/`at_ptr`: the same through a pointer a sweep steps along a row)
 struct NodeSlowness {
   const BetSlowness* S;
   __device__ BetSlowness at(int p) const { return S[p]; }
+  __device__ const BetSlowness* ptr(int p) const { return S + p; }
+  __device__ BetSlowness at_ptr(const BetSlowness* q, int k) const { return q[k]; }
 };
 struct GridSlowness {
   const float* S;
   float h;
   __device__ BetSlowness at(int p) const { return slowness_h(S[p], h); }
+  __device__ const float* ptr(int p) const { return S + p; }
+  __device__ BetSlowness at_ptr(const float* q, int k) const { return slowness_h(q[k], h); }
 };
 
 // Both solvers run Gauss-Seidel sweeps of the four orderings in turn until a
@@ -159,103 +159,175 @@ __device__ inline float from_lane_below(float v, float edge) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138 /* wave_shr:1 */,
                                                     0xF, 0xF, false));
 }
+// lane l receives lane l - 1's value, lane 0 lane 63's: a DPP wave rotation
+__device__ inline float from_lane_below_rot(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x13C /* wave_ror:1 */,
+                                                    0xF, 0xF, false));
+}
 
-// One sweep with one row per lane (nz <= 64): lane l owns the l-th row in
-// sweep order (row: its first entry; lanes past the last row use row 0 and
-// never store; below: the next row in sweep order, the +inf row after the
-// grid for the last) and handles its column jj at step l + jj, which is the
-// anti-diagonal schedule.  A node's upwind neighbours were updated one step
-// earlier -- the one in its row by this lane (kept in a register), the one
-// in the previous row by lane l - 1 (a lane shift) -- and every time a step
-// reads from LDS is from before this sweep: its own node, the next node of
-// its row (written by this lane a step later) and the node below it in the
-// next row (written by lane l + 1 two steps later).  So the times of step
-// s + 1 are read during step s, and the node terms of step s + 2 as well,
-// leaving only the arithmetic on the chain from step to step.  Steps have
-// no branches: outside its row a lane reads guard, pad or neighbouring-row
-// entries, whose values are never used except the +inf of the pad (or
-// guard) entry on either side of the row, and stores to its discard slot.
-// Returns whether a node changed.
-template <bool FJ, class Slow>
-__device__ bool sweep_rows(float* T, int nx, int last, int row, int below, unsigned nx_own, float* discard,
-                           Slow sl) {
+// One sweep with R rows per lane (nz <= 64 R): lane l owns the rows l,
+// l + 64, ... in sweep order (row[r]: its first entry; a lane without an r-th
+// row reads row 0 and never stores; below[r]: the next row in sweep order,
+// the +inf row after the grid for the last) and handles column jj of its
+// r-th row at step l + 64 r + jj, which is the anti-diagonal schedule.  A
+// node's upwind neighbours were updated one step earlier -- the one in its
+// row by this lane (kept in a register), the one in the previous row by lane
+// l - 1 (a lane shift; for lane 0's r-th row, lane 63's (r - 1)-th row, a
+// rotation) -- and every time a step reads from LDS is from before this
+// sweep: its own node, the next node of its row (written by this lane a step
+// later) and the node below it in the next row (written two steps later).
+// So the times of step s + 1 are read during step s, and the node terms of
+// step s + 2 as well, leaving only the arithmetic on the chain from step to
+// step.  Steps have no branches: outside its row a lane reads guard, pad or
+// neighbouring-row entries, whose values are never used except the +inf of
+// the pad (or guard) entry on either side of the row, and stores to its
+// discard slot.  Returns whether a node changed.
+template <bool FJ, int R, class Slow>
+__device__ bool sweep_rows(float* T, int nx, int last, const int (&row)[R], const int (&below)[R],
+                           const unsigned (&nx_own)[R], float* discard, Slow sl) {
   const int lane = threadIdx.x & 63;
   constexpr int dir = FJ ? 1 : -1;
-  // node of sweep index jj in this lane's row (column jj or nx - 1 - jj)
-  const int p0 = FJ ? row - lane : row + (nx - 1) + lane;  // jj = -lane at step 0
-  const int to_dn = below - row;
+  // node of sweep index jj in the r-th row (column jj or nx - 1 - jj), at
+  // step 0 (jj = -lane - 64 r), and the offset to the node below
+  int p0[R], to_dn[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int jj0 = -lane - 64 * r;
+    p0[r] = FJ ? row[r] + jj0 : row[r] + (nx - 1) - jj0;
+    to_dn[r] = below[r] - row[r];
+  }
   struct Stage {
-    float old, rt, dn;
-    BetSlowness s;
+    float old[R], rt[R], dn[R];
+    BetSlowness s[R];
   };
   bool changed = false;
-  float cur = INFINITY;  // this lane's node of the previous step
+  float cur[R];  // this lane's nodes of the previous step
+#pragma unroll
+  for (int r = 0; r < R; ++r) cur[r] = INFINITY;
   // Three sets rotate (this step's, the next step's, the one after), so no
   // value is copied between registers while its read is in flight.
-  auto body = [&](int jj, int p, const Stage& P, Stage& Q, Stage& R) {
+  using SPtr = decltype(sl.ptr(0));
+  // pc[r]: node of the r-th row at this step; sc[r]: the same node's terms
+  auto body = [&](int jj, const int (&pc)[R], const SPtr (&sc)[R], const Stage& P, Stage& Q, Stage& Rs) {
     // the reads first, then the arithmetic: the scheduler may not move
     // either across (work of the next step moved up, or reads moved down,
     // would wait on reads just issued)
     __builtin_amdgcn_sched_barrier(0);
-    Q.old = T[p + dir];
-    Q.rt = T[p + 2 * dir];
-    Q.dn = T[p + to_dn + dir];
-    R.s = sl.at(p + 2 * dir);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int p = pc[r];
+      Q.old[r] = T[p + dir];
+      Q.rt[r] = T[p + 2 * dir];
+      Q.dn[r] = T[p + to_dn[r] + dir];
+      Rs.s[r] = sl.at_ptr(sc[r], 2 * dir);
+    }
     __builtin_amdgcn_sched_barrier(0);
-    const bool active = (unsigned)jj < nx_own;
-    // up (lane l - 1's node of the previous step) and left (this lane's) are
-    // this sweep's upwind times, dn and rt the downwind ones
-    // (lane 0 has no upwind row: it takes dn in place of +inf, the same min)
-    const float up = from_lane_below(cur, P.dn);
-    const float a = min_t(up, P.dn);
-    const float b = min_t(cur, P.rt);
-    const float t = godunov(a, b, P.s);
-    const bool better = active && t < P.old;
-    cur = better ? t : P.old;
-    *(active ? T + p : discard) = cur;
-    changed |= better;
+    // up (the previous row's node of the previous step) and left (this
+    // row's) are this sweep's upwind times, dn and rt the downwind ones; the
+    // ups are taken before any of this step's nodes replace `cur`
+    float up[R];
+    // (the first row has no upwind row: it takes dn in place of +inf, the same min)
+    up[0] = from_lane_below(cur[0], P.dn[0]);
+#pragma unroll
+    for (int r = 1; r < R; ++r) up[r] = from_lane_below_rot(lane == 63 ? cur[r - 1] : cur[r]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool active = (unsigned)(jj - 64 * r) < nx_own[r];
+      const float a = min_t(up[r], P.dn[r]);
+      const float b = min_t(cur[r], P.rt[r]);
+      const float t = godunov(a, b, P.s[r]);
+      const bool better = active && t < P.old[r];
+      cur[r] = better ? t : P.old[r];
+      *(active ? T + pc[r] : discard + 64 * r) = cur[r];
+      changed |= better;
+    }
   };
   Stage A, B, C;
-  A.old = T[p0];
-  A.rt = T[p0 + dir];
-  A.dn = T[p0 + to_dn];
-  A.s = sl.at(p0);
-  B.s = sl.at(p0 + dir);
-  int step = 0, jj = -lane, p = p0;
-  for (; step + 2 <= last; step += 3, jj += 3, p += 3 * dir) {
-    body(jj, p, A, B, C);
-    body(jj + 1, p + dir, B, C, A);
-    body(jj + 2, p + 2 * dir, C, A, B);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    A.old[r] = T[p0[r]];
+    A.rt[r] = T[p0[r] + dir];
+    A.dn[r] = T[p0[r] + to_dn[r]];
+    A.s[r] = sl.at(p0[r]);
+    B.s[r] = sl.at(p0[r] + dir);
   }
-  if (step <= last) body(jj, p, A, B, C);
-  if (step + 1 <= last) body(jj + 1, p + dir, B, C, A);
+  int step = 0, jj = -lane;
+  int p[R], p1[R], p2[R];  // this step's node of each row, and the next two steps'
+  SPtr q[R], q1[R], q2[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    p[r] = p0[r];
+    q[r] = sl.ptr(p0[r]);
+  }
+  for (; step + 2 <= last; step += 3, jj += 3) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      p1[r] = p[r] + dir;
+      p2[r] = p[r] + 2 * dir;
+      q1[r] = q[r] + dir;
+      q2[r] = q[r] + 2 * dir;
+    }
+    body(jj, p, q, A, B, C);
+    body(jj + 1, p1, q1, B, C, A);
+    body(jj + 2, p2, q2, C, A, B);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      p[r] += 3 * dir;
+      q[r] += 3 * dir;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    p1[r] = p[r] + dir;
+    q1[r] = q[r] + dir;
+  }
+  if (step <= last) body(jj, p, q, A, B, C);
+  if (step + 1 <= last) body(jj + 1, p1, q1, B, C, A);
   return changed;
 }
 
-template <class Slow>
+template <int R, class Slow>
 __device__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
   const int lane = threadIdx.x & 63;
   // rows, pads, the row below the grid and guards: +inf (the discard slots
   // are in the first guard)
-  for (int p = lane - kBetGuard; p < (nz + 1) * ld + 64; p += 64) T[p] = INFINITY;
+  for (int p = lane - kBetGuard; p < (nz + 1) * ld + kBetTail; p += 64) T[p] = INFINITY;
   wave_sync();
   if (lane == 0) T[si * ld + sj] = 0.0f;
   wave_sync();
-  float* const discard = T - kBetGuard + lane;  // entries -68 .. -5: never read for a value that is used
-  const bool row_ok = lane < nz, has_dn = lane + 1 < nz;
-  const unsigned nx_own = row_ok ? (unsigned)nx : 0u;
+  // 64 discard slots per row block, entries -132 .. -5 of the first guard:
+  // never read for a value that is used
+  float* const discard = T - kBetGuard + lane;
   const int last = nz + nx - 2;
   for (int sweeps = 0, o = 0; sweeps < kBetMaxSweeps; o = (o + 1) & 3) {
     const bool fi = ordering_fi(o);
-    const int i = row_ok ? (fi ? lane : nz - 1 - lane) : 0;
-    const int idn = has_dn ? (fi ? i + 1 : i - 1) : nz;  // the next row in sweep order, or the +inf row
-    const bool changed = o < 2 ? sweep_rows<true>(T, nx, last, i * ld, idn * ld, nx_own, discard, sl)
-                               : sweep_rows<false>(T, nx, last, i * ld, idn * ld, nx_own, discard, sl);
+    int row[R], below[R];
+    unsigned nx_own[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = lane + 64 * r;  // this lane's r-th row in sweep order
+      const bool ok = k < nz, has_dn = k + 1 < nz;
+      const int i = ok ? (fi ? k : nz - 1 - k) : 0;
+      row[r] = i * ld;
+      below[r] = (has_dn ? (fi ? i + 1 : i - 1) : nz) * ld;  // the next row in sweep order, or the +inf row
+      nx_own[r] = ok ? (unsigned)nx : 0u;
+    }
+    const bool changed = o < 2 ? sweep_rows<true, R>(T, nx, last, row, below, nx_own, discard, sl)
+                               : sweep_rows<false, R>(T, nx, last, row, below, nx_own, discard, sl);
     wave_sync();
     ++sweeps;
     if (!__any(changed)) return sweeps;
   }
   return -kBetMaxSweeps;
+}
+
+// the solver for a grid of nz rows: one or two rows per lane up to 128 rows,
+// else the anti-diagonal sweep
+template <class Slow>
+__device__ int fsm_solve_any(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
+  if (nz <= 64) return fsm_solve_rows<1>(T, nz, nx, ld, si, sj, sl);
+  if (nz <= 128) return fsm_solve_rows<2>(T, nz, nx, ld, si, sj, sl);
+  return fsm_solve(T, nz, nx, ld, si, sj, sl);
 }
 
 }  // namespace
@@ -378,7 +450,7 @@ __global__ __launch_bounds__(64) void k_bet_eikonal(BetDev d, int c0, int cn) {
   float* T = reinterpret_cast<float*>(smem) + kBetGuard;  // times, with guards
   const NodeSlowness sl{d.node + (size_t)c * bet_grid_entries(nz, nx) + kBetGuard};
   const int2 s = d.src[e];
-  const int sweeps = nz <= 64 ? fsm_solve_rows(T, nz, nx, ld, s.x, s.y, sl) : fsm_solve(T, nz, nx, ld, s.x, s.y, sl);
+  const int sweeps = fsm_solve_any(T, nz, nx, ld, s.x, s.y, sl);
   if (lane == 0) {
     if (sweeps < 0) atomicOr(d.flags, kBetNoConverge);
     atomicAdd(d.work + 2 * (size_t)c, 1ull);
@@ -504,7 +576,7 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
   float* T = reinterpret_cast<float*>(smem) + kBetGuard;
   float* S = reinterpret_cast<float*>(smem + bet_lds_bytes(nz, nx)) + kBetGuard;
   bool bad = false;
-  for (int q = lane - kBetGuard; q < (nz + 1) * ld + 64; q += 64) {  // pads and guards: slowness 0
+  for (int q = lane - kBetGuard; q < (nz + 1) * ld + kBetTail; q += 64) {  // pads and guards: slowness 0
     const int i = q / ld, j = q - i * ld;
     float sl = 0.0f;
     if (q >= 0 && i < nz && j < nx) {
@@ -521,7 +593,7 @@ __global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, i
   wave_sync();
   const int2 s = src[e];
   const GridSlowness sl{S, h};
-  const int sweeps = nz <= 64 ? fsm_solve_rows(T, nz, nx, ld, s.x, s.y, sl) : fsm_solve(T, nz, nx, ld, s.x, s.y, sl);
+  const int sweeps = fsm_solve_any(T, nz, nx, ld, s.x, s.y, sl);
   if (sweeps < 0 && lane == 0) atomicOr(flags, kBetNoConverge);
   for (int r = lane; r < nrec; r += 64) {
     const int2 q = rec[r];
@@ -579,10 +651,8 @@ hipError_t launch_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad, 
   return hipGetLastError();
 }
 
-// LDS of the Stage-1 solve: times; of a velocity grid's solve: times and
-// slowness
-static size_t lds_bet(int nz, int nx) { return bet_lds_bytes(nz, nx); }
-static size_t lds_grid(int nz, int nx) { return 2 * bet_lds_bytes(nz, nx); }
+static size_t lds_bet(int nz, int nx) { return bet_lds_sampler(nz, nx); }
+static size_t lds_grid(int nz, int nx) { return bet_lds_grid(nz, nx); }
 
 hipError_t launch_bet_propose(const BetDev& d, int t, int init, int c0, int cn, hipStream_t s) {
   k_bet_propose<<<(cn + 63) / 64, 64, 0, s>>>(d, t, init, c0, cn);
@@ -597,8 +667,8 @@ hipError_t launch_bet_raster(const BetDev& d, int c0, int cn, hipStream_t s) {
 
 hipError_t launch_bet_eikonal(const BetDev& d, int c0, int cn, hipStream_t s) {
   const int n = d.nz * d.nx;
-  if (n > kBetMaxNodes || d.k_max > kBetMaxCells) return hipErrorInvalidValue;
   const size_t lds = lds_bet(d.nz, d.nx);
+  if (n > kBetMaxNodes || d.k_max > kBetMaxCells || lds > kBetMaxLds) return hipErrorInvalidValue;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bet_eikonal),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -624,8 +694,8 @@ hipError_t launch_bet_sample(const BetDev& d, int slot, hipStream_t s) {
 hipError_t launch_eikonal_grid(const float* vel, int nz, int nx, float h, const int2* src, int nsrc,
                                const int2* rec, int nrec, float* tt, uint32_t* flags, hipStream_t s) {
   const int n = nz * nx;
-  if (n > kBetMaxNodes) return hipErrorInvalidValue;
   const size_t lds = lds_grid(nz, nx);
+  if (n > kBetMaxNodes || lds > kBetMaxLds) return hipErrorInvalidValue;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eikonal_grid),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

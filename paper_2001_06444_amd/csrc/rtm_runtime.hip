@@ -1991,6 +1991,9 @@ extern "C" int rtm_eikonal(rtm_ctx* ctx, const float* vel_dev, int32_t nz, int32
   if (!ctx || !vel_dev || !tt_dev) return fail(RTM_E_INVAL, "bad arguments");
   if (nz < 1 || nx < 1 || (int64_t)nz * nx > kBetMaxNodes || !(h > 0) || !std::isfinite(h))
     return fail(RTM_E_INVAL, "grid %d x %d, h %g: need 1..%d nodes and h > 0", nz, nx, (double)h, kBetMaxNodes);
+  if (bet_lds_grid(nz, nx) > kBetMaxLds)
+    return fail(RTM_E_INVAL, "grid %d x %d: a solve needs %zu bytes of LDS, at most %zu", nz, nx,
+                bet_lds_grid(nz, nx), kBetMaxLds);
   std::vector<int2> src, rec;
   if (int st = bet_points(src_host, nsrc, nz, nx, "source", src)) return st;
   if (int st = bet_points(rec_host, nrec, nz, nx, "receiver", rec)) return st;
@@ -2023,7 +2026,8 @@ extern "C" int rtm_bet_create(rtm_ctx* ctx, const rtm_bet_config* cfg, int32_t n
   if (!ctx || !cfg || !tt_obs_dev || !out) return fail(RTM_E_INVAL, "bad arguments");
   *out = nullptr;
   const rtm_bet_config& c = *cfg;
-  if (c.nz < 2 || c.nx < 2 || (int64_t)c.nz * c.nx > kBetMaxNodes || !(c.h > 0) || !std::isfinite(c.h))
+  if (c.nz < 2 || c.nx < 2 || (int64_t)c.nz * c.nx > kBetMaxNodes || !(c.h > 0) || !std::isfinite(c.h) ||
+      bet_lds_sampler(c.nz, c.nx) > kBetMaxLds)
     return fail(RTM_E_INVAL, "grid %d x %d, h %g: need 2..%d nodes per side product and h > 0", c.nz, c.nx, c.h,
                 kBetMaxNodes);
   if (c.chains < 1 || c.chains > kBetMaxChains || c.k_min < 1 || c.k_init < c.k_min || c.k_max < c.k_init ||

@@ -46,10 +46,14 @@ def ulps(a, b):
 
 @pytest.mark.parametrize("nz,nx,h,seed,scale", [(36, 171, 100.0, 0, 1.0), (70, 90, 50.0, 1, 1.0), (2, 2, 10.0, 2, 1.0),
                                                  (9, 5, 25.0, 3, 1.0), (20, 33, 5e-6, 4, 1.0),
-                                                 (20, 33, 1e6, 5, 1e-14)])
+                                                 (20, 33, 1e6, 5, 1e-14), (64, 30, 20.0, 6, 1.0),
+                                                 (65, 30, 20.0, 7, 1.0), (128, 40, 25.0, 8, 1.0),
+                                                 (129, 12, 20.0, 9, 1.0), (100, 3, 10.0, 10, 1.0)])
 def test_travel_times_match_oracle(ctx, nz, nx, h, seed, scale):
     # h / v spans 1.1e-9 .. 6.7e16 s over the cases (the accepted range is
-    # [1e-9, 1e18]): square-root arguments from about 2^-59 to 2^113
+    # [1e-9, 1e18]): square-root arguments from about 2^-59 to 2^113.  Rows:
+    # one per lane up to 64, two per lane up to 128 (65, 70, 100, 128), the
+    # anti-diagonal sweep beyond (129)
     vel = voronoi_velocity(nz, nx, h, seed) * np.float32(scale)
     rng = np.random.default_rng(seed + 10)
     srcs = [(0, 0), (nz - 1, nx - 1)] + [(int(rng.integers(nz)), int(rng.integers(nx))) for _ in range(4)]
@@ -150,6 +154,9 @@ def test_bet_rejects(ctx, rtm):
         with pytest.raises(rtm.RTMError):
             ctx.eikonal(dev(vel), 10.0, [(0, 0)], [(3, 3)])
     ctx.eikonal(dev(np.full((4, 4), 2000.0)), 10.0, [(0, 0)], [(3, 3)])  # still usable
+    # a grid whose solve would not fit the LDS of a CU (one row of 12800 nodes)
+    with pytest.raises(rtm.RTMError):
+        ctx.eikonal(dev(np.full((1, 12800), 2000.0)), 10.0, [(0, 0)], [(0, 5)])
 
 
 def test_full_size_chains_sampled(ctx, rtm):
@@ -203,9 +210,9 @@ def test_chain_model_on_a_finer_grid(ctx, rtm):
 
 
 def test_chains_on_a_tall_grid_match_oracle(ctx, rtm):
-    """More than 64 rows: the sampler's solves take the anti-diagonal sweep
-    (node terms from global memory); every accept decision and final state
-    equal the oracle's."""
+    """More than 64 rows: the sampler's solves give each lane two rows (node
+    terms from global memory); every accept decision and final state equal
+    the oracle's."""
     nz, nx, h = 70, 20, 50.0
     # the faulted-layer model (10 m) sampled every 5th node: 3.5 km deep
     true = np.ascontiguousarray(inputs.faulted_layers()[::5, ::5][:nz, :nx]).astype(np.float64)
