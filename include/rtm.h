@@ -401,7 +401,9 @@ int rtm_codec_decode(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes,
  *   - After burn_in iterations, every thin-th iteration adds every chain's
  *     velocity grid (chains in order) to a pooled FP64 Welford mean / M2 per
  *     node: the velocity uncertainty maps of Stage 3.
- * Grids have at most 12800 nodes. */
+ * Grids have at most 40000 nodes, and a solve's times must fit the 160 KB of
+ * LDS of a compute unit: 4 (264 + (nz + 1) ld) bytes, with ld the even number
+ * nx + 1 or nx + 2 up to 128 rows, else nx (e.g. 71 x 341 nodes: 100 KB). */
 typedef struct {
     int32_t nz, nx;                 /* grid nodes */
     int32_t chains;                 /* chains advanced together */
@@ -429,7 +431,7 @@ typedef struct rtm_bet rtm_bet;
 /* Travel times tt_dev [nsrc][nrec] (s, float) of the velocity grid vel_dev
  * [nz][nx] (m/s, float) for sources src_host[nsrc] and receivers
  * rec_host[nrec] (grid nodes).  Synchronous.  Errors: RTM_E_INVAL (shape,
- * points outside the grid, more than 12800 nodes, or a node where
+ * points outside the grid, a grid beyond the limits above, or a node where
  * h / v, in single precision, lies outside [1e-9, 1e18] s -- velocities must
  * be positive and finite), RTM_E_DEVICE (a solve did not converge). */
 int rtm_eikonal(rtm_ctx *ctx, const float *vel_dev, int32_t nz, int32_t nx, float h, int32_t nsrc,

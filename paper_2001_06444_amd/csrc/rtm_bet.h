@@ -9,7 +9,7 @@ namespace rtm {
 
 constexpr int kBetMaxCells = 64;     // Voronoi nuclei per model
 constexpr int kBetMaxChains = 65535; // chains per sampler (a launch dimension)
-constexpr int kBetMaxNodes = 12800;  // Eikonal grid nodes (LDS: 4 B per node per wavefront)
+constexpr int kBetMaxNodes = 40000;  // Eikonal grid nodes (a solve's times in LDS: 4 B per node)
 // Fast sweeps before giving up: the solvers stop at the first sweep that
 // changes nothing, and a quiet sweep within 1021 sweeps is exactly a quiet
 // whole pass (four orderings) within 256 passes.
@@ -31,14 +31,13 @@ __host__ __device__ inline int bet_ld(int nz, int nx) { return nz <= 128 ? (nx +
 __host__ __device__ inline int bet_grid_entries(int nz, int nx) {
   return kBetGuard + (nz + 1) * bet_ld(nz, nx) + kBetTail;
 }
-// LDS of one solve: the times (a sampler's solve) or the times and the node
-// slowness (a velocity grid's solve); a grid must fit the CU's 160 KB
+// LDS of one solve: its times; a grid must fit the CU's 160 KB
 constexpr size_t kBetMaxLds = 163840;
 __host__ __device__ inline size_t bet_lds_bytes(int nz, int nx) {
   return ((size_t)bet_grid_entries(nz, nx) * 4 + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t bet_lds_sampler(int nz, int nx) { return bet_lds_bytes(nz, nx); }
-__host__ __device__ inline size_t bet_lds_grid(int nz, int nx) { return 2 * bet_lds_bytes(nz, nx); }
+__host__ __device__ inline size_t bet_lds_grid(int nz, int nx) { return bet_lds_bytes(nz, nx); }
 
 // sh = slowness * h and q2 = sh sh + sh sh of a node, in single precision:
 // the two terms of the Godunov update that depend on the node alone
@@ -102,8 +101,10 @@ hipError_t launch_bet_model(const BetDev& d, int c, int nz, int nx, double h, fl
 // mismatches (added to *bad) of the solver's square root against the
 // correctly rounded one over the float bit patterns [lo, hi), lo < hi
 hipError_t launch_sqrt_check(uint32_t lo, uint32_t hi, unsigned long long* bad, hipStream_t s);
-// travel times of one velocity grid (m/s) for every source: tt [nsrc][nrec]
+// travel times of one velocity grid (m/s) for every source: tt [nsrc][nrec];
+// node: scratch of bet_grid_entries(nz, nx) node terms
 hipError_t launch_eikonal_grid(const float* vel, int nz, int nx, float h, const int2* src, int nsrc,
-                               const int2* rec, int nrec, float* tt, uint32_t* flags, hipStream_t s);
+                               const int2* rec, int nrec, float* tt, uint32_t* flags, BetSlowness* node,
+                               hipStream_t s);
 
 }  // namespace rtm

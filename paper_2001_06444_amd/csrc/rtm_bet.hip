@@ -94,22 +94,21 @@ __device__ inline float godunov(float a, float b, BetSlowness s) {
   return !(d < s.sh) ? lo + s.sh : two;
 }
 
-// The node terms a solve reads: precomputed per node in global memory
-// (Stage-1 models), or from the node slowness in LDS (a velocity grid).
-// (`ptr`/`at_ptr`: the same through a pointer a sweep steps along a row)
+// The node terms a solve reads, precomputed per node in global memory (for
+// a chain's proposal by k_bet_raster, for a velocity grid by k_grid_terms);
+// `ptr`/`at_ptr` read them through a pointer a sweep steps along a row.
+// (a global-address-space pointer, so the reads are global loads, which
+// count on the vector-memory counter only, not flat ones that also hold the
+// LDS counter)
+typedef const __attribute__((address_space(1))) BetSlowness* GlobalTerms;
 struct NodeSlowness {
-  const BetSlowness* S;
-  __device__ BetSlowness at(int p) const { return S[p]; }
-  __device__ const BetSlowness* ptr(int p) const { return S + p; }
-  __device__ BetSlowness at_ptr(const BetSlowness* q, int k) const { return q[k]; }
+  GlobalTerms S;
+  __device__ NodeSlowness(const BetSlowness* p) : S((GlobalTerms)p) {}
+  __device__ BetSlowness at(int p) const { return {S[p].sh, S[p].q2}; }
+  __device__ GlobalTerms ptr(int p) const { return S + p; }
+  __device__ BetSlowness at_ptr(GlobalTerms q, int k) const { return {q[k].sh, q[k].q2}; }
 };
-struct GridSlowness {
-  const float* S;
-  float h;
-  __device__ BetSlowness at(int p) const { return slowness_h(S[p], h); }
-  __device__ const float* ptr(int p) const { return S + p; }
-  __device__ BetSlowness at_ptr(const float* q, int k) const { return slowness_h(q[k], h); }
-};
+
 
 // Both solvers run Gauss-Seidel sweeps of the four orderings in turn until a
 // sweep changes nothing.  Such a sweep has updated every node from neighbours
@@ -122,7 +121,7 @@ __device__ inline bool ordering_fi(int o) { return o == 0 || o == 3; }
 // diagonal are not neighbours, so a wavefront updates them together), for
 // any number of rows; T has row stride ld.
 template <class Slow>
-__device__ int fsm_solve(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
+__device__ __forceinline__ int fsm_solve(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
   const int lane = threadIdx.x & 63;
   for (int p = lane; p < nz * ld; p += 64) T[p] = INFINITY;
   wave_sync();
@@ -183,7 +182,7 @@ __device__ inline float from_lane_below_rot(float v) {
 // the pad (or guard) entry on either side of the row, and stores to its
 // discard slot.  Returns whether a node changed.
 template <bool FJ, int R, class Slow>
-__device__ bool sweep_rows(float* T, int nx, int last, const int (&row)[R], const int (&below)[R],
+__device__ __forceinline__ bool sweep_rows(float* T, int nx, int last, const int (&row)[R], const int (&below)[R],
                            const unsigned (&nx_own)[R], float* discard, Slow sl) {
   const int lane = threadIdx.x & 63;
   constexpr int dir = FJ ? 1 : -1;
@@ -287,7 +286,7 @@ __device__ bool sweep_rows(float* T, int nx, int last, const int (&row)[R], cons
 }
 
 template <int R, class Slow>
-__device__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
+__device__ __forceinline__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
   const int lane = threadIdx.x & 63;
   // rows, pads, the row below the grid and guards: +inf (the discard slots
   // are in the first guard)
@@ -322,9 +321,10 @@ __device__ int fsm_solve_rows(float* T, int nz, int nx, int ld, int si, int sj, 
 }
 
 // the solver for a grid of nz rows: one or two rows per lane up to 128 rows,
-// else the anti-diagonal sweep
+// else the anti-diagonal sweep (inlined into each kernel, where T is known
+// to be LDS)
 template <class Slow>
-__device__ int fsm_solve_any(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
+__device__ __forceinline__ int fsm_solve_any(float* T, int nz, int nx, int ld, int si, int sj, Slow sl) {
   if (nz <= 64) return fsm_solve_rows<1>(T, nz, nx, ld, si, sj, sl);
   if (nz <= 128) return fsm_solve_rows<2>(T, nz, nx, ld, si, sj, sl);
   return fsm_solve(T, nz, nx, ld, si, sj, sl);
@@ -567,32 +567,34 @@ __global__ __launch_bounds__(256) void k_bet_sample(BetDev d) {
   d.count[p] = cnt;
 }
 
-// travel times of one velocity grid from source blockIdx.x
-__global__ __launch_bounds__(64) void k_eikonal_grid(const float* vel, int nz, int nx, float h, const int2* src,
+// node terms of a velocity grid (a thread per entry of the padded layout;
+// guards and pads: 0), flagging any node whose h / v leaves the range the
+// solves' square root is exact in (velocities not positive and finite
+// included)
+__global__ __launch_bounds__(256) void k_grid_terms(const float* vel, int nz, int nx, float h, BetSlowness* node,
+                                                    uint32_t* flags) {
+  const int ld = bet_ld(nz, nx);
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= bet_grid_entries(nz, nx)) return;
+  const int e = q - kBetGuard, i = e / ld, j = e - (e / ld) * ld;
+  BetSlowness out{0.0f, 0.0f};
+  if (e >= 0 && i < nz && j < nx) {
+    out = slowness_h((float)(1.0 / (double)vel[i * nx + j]), h);
+    if (!(out.sh >= kBetShMin && out.sh <= kBetShMax)) atomicOr(flags, kBetBadSlowness);
+  }
+  node[q] = out;
+}
+
+// travel times of one velocity grid from source blockIdx.x (the node terms
+// from k_grid_terms; nothing is solved if it flagged a node)
+__global__ __launch_bounds__(64) void k_eikonal_grid(const BetSlowness* node, int nz, int nx, const int2* src,
                                                      const int2* rec, int nrec, float* tt, uint32_t* flags) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBetBadSlowness) return;
   const int e = blockIdx.x, lane = threadIdx.x, ld = bet_ld(nz, nx);
-  // LDS: times and slowness, both with guards and row stride ld
-  float* T = reinterpret_cast<float*>(smem) + kBetGuard;
-  float* S = reinterpret_cast<float*>(smem + bet_lds_bytes(nz, nx)) + kBetGuard;
-  bool bad = false;
-  for (int q = lane - kBetGuard; q < (nz + 1) * ld + kBetTail; q += 64) {  // pads and guards: slowness 0
-    const int i = q / ld, j = q - i * ld;
-    float sl = 0.0f;
-    if (q >= 0 && i < nz && j < nx) {
-      sl = (float)(1.0 / (double)vel[i * nx + j]);
-      const float sh = sl * h;
-      bad |= !(sh >= kBetShMin && sh <= kBetShMax);
-    }
-    S[q] = sl;
-  }
-  if (__any(bad)) {  // the solve would leave the square root's range
-    if (lane == 0) atomicOr(flags, kBetBadSlowness);
-    return;
-  }
-  wave_sync();
+  float* T = reinterpret_cast<float*>(smem) + kBetGuard;  // times, with guards
   const int2 s = src[e];
-  const GridSlowness sl{S, h};
+  const NodeSlowness sl{node + kBetGuard};
   const int sweeps = fsm_solve_any(T, nz, nx, ld, s.x, s.y, sl);
   if (sweeps < 0 && lane == 0) atomicOr(flags, kBetNoConverge);
   for (int r = lane; r < nrec; r += 64) {
@@ -692,7 +694,8 @@ hipError_t launch_bet_sample(const BetDev& d, int slot, hipStream_t s) {
 }
 
 hipError_t launch_eikonal_grid(const float* vel, int nz, int nx, float h, const int2* src, int nsrc,
-                               const int2* rec, int nrec, float* tt, uint32_t* flags, hipStream_t s) {
+                               const int2* rec, int nrec, float* tt, uint32_t* flags, BetSlowness* node,
+                               hipStream_t s) {
   const int n = nz * nx;
   const size_t lds = lds_grid(nz, nx);
   if (n > kBetMaxNodes || lds > kBetMaxLds) return hipErrorInvalidValue;
@@ -701,7 +704,9 @@ hipError_t launch_eikonal_grid(const float* vel, int nz, int nx, float h, const 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k_eikonal_grid<<<nsrc, 64, lds, s>>>(vel, nz, nx, h, src, rec, nrec, tt, flags);
+  const int m = bet_grid_entries(nz, nx);
+  k_grid_terms<<<(m + 255) / 256, 256, 0, s>>>(vel, nz, nx, h, node, flags);
+  k_eikonal_grid<<<nsrc, 64, lds, s>>>(node, nz, nx, src, rec, nrec, tt, flags);
   return hipGetLastError();
 }
 

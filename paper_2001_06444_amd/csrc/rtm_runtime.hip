@@ -1999,20 +1999,22 @@ extern "C" int rtm_eikonal(rtm_ctx* ctx, const float* vel_dev, int32_t nz, int32
   if (int st = bet_points(rec_host, nrec, nz, nx, "receiver", rec)) return st;
   HIP_OK(hipSetDevice(ctx->device));
   const size_t bs = align256(8 * (size_t)nsrc), br = align256(8 * (size_t)nrec);
-  char* buf = static_cast<char*>(arena_alloc(ctx, bs + br + 256));
-  if (!buf) return fail(RTM_E_NOMEM, "arena exhausted (travel-time geometry)");
+  const size_t bn = align256(sizeof(BetSlowness) * (size_t)bet_grid_entries(nz, nx));
+  char* buf = static_cast<char*>(arena_alloc(ctx, bs + br + 256 + bn));
+  if (!buf) return fail(RTM_E_NOMEM, "arena exhausted (travel-time geometry and node terms)");
   hipStream_t s = ctx->stream;
   uint32_t* flags = reinterpret_cast<uint32_t*>(buf + bs + br);
+  BetSlowness* node = reinterpret_cast<BetSlowness*>(buf + bs + br + 256);
   uint32_t flag = 0;
   hipError_t e = hipMemcpyAsync(buf, src.data(), 8 * (size_t)nsrc, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(buf + bs, rec.data(), 8 * (size_t)nrec, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_fill_u32(flags, 0, 1, s);
   if (e == hipSuccess)
     e = launch_eikonal_grid(vel_dev, nz, nx, h, reinterpret_cast<int2*>(buf), nsrc, reinterpret_cast<int2*>(buf + bs),
-                            nrec, tt_dev, flags, s);
+                            nrec, tt_dev, flags, node, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&flag, flags, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  ctx->arena.release(buf, align256(bs + br + 256));
+  ctx->arena.release(buf, align256(bs + br + 256 + bn));
   if (e != hipSuccess) return fail(RTM_E_DEVICE, "travel times: %s", hipGetErrorString(e));
   if (flag & kBetBadSlowness)
     return fail(RTM_E_INVAL, "velocity grid: h / v must lie in [%g, %g] s at every node", (double)kBetShMin,

@@ -48,12 +48,14 @@ def ulps(a, b):
                                                  (9, 5, 25.0, 3, 1.0), (20, 33, 5e-6, 4, 1.0),
                                                  (20, 33, 1e6, 5, 1e-14), (64, 30, 20.0, 6, 1.0),
                                                  (65, 30, 20.0, 7, 1.0), (128, 40, 25.0, 8, 1.0),
-                                                 (129, 12, 20.0, 9, 1.0), (100, 3, 10.0, 10, 1.0)])
+                                                 (129, 12, 20.0, 9, 1.0), (100, 3, 10.0, 10, 1.0),
+                                                 (71, 341, 50.0, 11, 1.0)])
 def test_travel_times_match_oracle(ctx, nz, nx, h, seed, scale):
     # h / v spans 1.1e-9 .. 6.7e16 s over the cases (the accepted range is
     # [1e-9, 1e18]): square-root arguments from about 2^-59 to 2^113.  Rows:
-    # one per lane up to 64, two per lane up to 128 (65, 70, 100, 128), the
-    # anti-diagonal sweep beyond (129)
+    # one per lane up to 64, two per lane up to 128 (65, 70, 71, 100, 128),
+    # the anti-diagonal sweep beyond (129); 71 x 341 is the 3.5 km x 17 km
+    # section at 50 m (24211 nodes, 100 KB of LDS per solve)
     vel = voronoi_velocity(nz, nx, h, seed) * np.float32(scale)
     rng = np.random.default_rng(seed + 10)
     srcs = [(0, 0), (nz - 1, nx - 1)] + [(int(rng.integers(nz)), int(rng.integers(nx))) for _ in range(4)]
@@ -139,7 +141,7 @@ def test_bet_rejects(ctx, rtm):
     cfg, srcs, recs, tt_obs = _small_problem()
     t = dev(tt_obs)
     for bad in (dict(k_max=65), dict(k_min=0), dict(k_init=30), dict(v_max=1000.0), dict(p_birth=0.8),
-                dict(sigma=0.0), dict(thin=0), dict(nz=200, nx=200), dict(h=1e-6), dict(v_min=1e-20),
+                dict(sigma=0.0), dict(thin=0), dict(nz=201, nx=200), dict(h=1e-6), dict(v_min=1e-20),
                 dict(chains=0), dict(chains=65536)):
         with pytest.raises(rtm.RTMError):
             ctx.bet_create(srcs, recs, t, **{**cfg, **bad})
@@ -154,9 +156,12 @@ def test_bet_rejects(ctx, rtm):
         with pytest.raises(rtm.RTMError):
             ctx.eikonal(dev(vel), 10.0, [(0, 0)], [(3, 3)])
     ctx.eikonal(dev(np.full((4, 4), 2000.0)), 10.0, [(0, 0)], [(3, 3)])  # still usable
-    # a grid whose solve would not fit the LDS of a CU (one row of 12800 nodes)
+    # a grid whose solve would not fit the LDS of a CU (one row of 39000
+    # nodes: 313 KB with the +inf row below it), and one of too many nodes
     with pytest.raises(rtm.RTMError):
-        ctx.eikonal(dev(np.full((1, 12800), 2000.0)), 10.0, [(0, 0)], [(0, 5)])
+        ctx.eikonal(dev(np.full((1, 39000), 2000.0)), 10.0, [(0, 0)], [(0, 5)])
+    with pytest.raises(rtm.RTMError):
+        ctx.eikonal(dev(np.full((201, 200), 2000.0)), 10.0, [(0, 0)], [(0, 5)])
 
 
 def test_full_size_chains_sampled(ctx, rtm):
