@@ -111,6 +111,8 @@ def parse():
     ap.add_argument("--seismograms", type=int, default=16, help="codec workload")
     ap.add_argument("--chains", type=int, default=64, help="bet workload")
     ap.add_argument("--bet-iters", type=int, default=20, help="bet workload: iterations per step")
+    ap.add_argument("--bet-h", type=float, default=100.0, choices=[100.0, 50.0],
+                    help="bet workload: node spacing (100 m: 36 x 171 nodes, 50 m: 71 x 341)")
     ap.add_argument("--serve-jobs", type=int, default=300, help="serve workload: timed jobs")
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: jobs/s")
@@ -790,7 +792,7 @@ def run_bet(args):
 
     from paper_2001_06444_amd import inputs, rtm
 
-    p = inputs.bet_problem(args.chains)
+    p = inputs.bet_problem(args.chains, args.bet_h)
     c = p["cfg"]
     n = c["nz"] * c["nx"]
     ctx = rtm.Context(0, arena_bytes=256 << 20)

@@ -328,20 +328,25 @@ def seismogram_bank(n: int, nt: int = 4000, nrec: int = 1701) -> np.ndarray:
 # ---------------------------------------------------------------------------
 def bet_true_model(nz: int = 36, nx: int = 171, h: float = 100.0) -> np.ndarray:
     """True velocity of the travel-time problem: the faulted-layer model
-    (351 x 1701 at 10 m) sampled every 10th node (h = 100 m), top-left nz x nx."""
-    if h != 100.0 or nz > 36 or nx > 171:
-        raise ValueError("the coarse model is the 10 m faulted model sampled at 100 m (at most 36 x 171)")
-    return np.ascontiguousarray(faulted_layers()[::10, ::10][:nz, :nx]).astype(np.float64)
+    (351 x 1701 at 10 m) sampled every (h / 10)-th node, h = 100 m (36 x 171)
+    or 50 m (71 x 341), top-left nz x nx."""
+    step = {100.0: 10, 50.0: 5}.get(float(h))
+    if step is None or nz > 350 // step + 1 or nx > 1700 // step + 1:
+        raise ValueError("the coarse model is the 10 m faulted model sampled at 100 m (at most 36 x 171) "
+                         "or 50 m (at most 71 x 341)")
+    return np.ascontiguousarray(faulted_layers()[::step, ::step][:nz, :nx]).astype(np.float64)
 
 
-def bet_problem(chains: int = 64) -> dict:
-    """Stage-1 benchmark problem: 36 x 171 nodes at 100 m (3.5 km x 17 km), 34
-    surface sources every 500 m (ix = 2 + 5k), a receiver at every surface
-    node, and the sampler's prior and proposal settings."""
-    nz, nx, h = 36, 171, 100.0
+def bet_problem(chains: int = 64, h: float = 100.0) -> dict:
+    """Stage-1 benchmark problem on the 3.5 km x 17 km section: 36 x 171
+    nodes at 100 m (or 71 x 341 at 50 m), 34 surface sources every 500 m
+    (x = 200 m + 500 m k), a receiver at every surface node, and the
+    sampler's prior and proposal settings."""
+    step = {100.0: 10, 50.0: 5}[float(h)]
+    nz, nx = 350 // step + 1, 1700 // step + 1
     return {
         "true": bet_true_model(nz, nx, h), "h": h,
-        "srcs": [(0, 2 + 5 * k) for k in range(34)],
+        "srcs": [(0, (200 + 500 * k) // int(h)) for k in range(34)],
         "recs": [(0, j) for j in range(nx)],
         "cfg": dict(nz=nz, nx=nx, h=h, chains=chains, k_min=4, k_max=48, k_init=12, burn_in=20, thin=5,
                     v_min=1400.0, v_max=5000.0, p_birth=0.25, p_death=0.25, move_dz=300.0, move_dx=1500.0,
