@@ -507,8 +507,9 @@ typedef struct {
     float last_codec_ms;
     int32_t last_codec_op;
     uint64_t last_codec_bytes;
-    /* last rtm_bet_run call: HIP-event time of the travel-time launch and of
-     * all launches of its last iteration */
+    /* last rtm_bet_run call: HIP-event times, on the first chain group's
+     * stream, of that group's travel-time launch and of all its launches in
+     * the call's last iteration (the other group's work overlaps them) */
     float last_bet_eikonal_ms, last_bet_iteration_ms;
 } rtm_ctx_stats_t;
 
