@@ -36,7 +36,7 @@ def log(*a):
 
 
 STEP_SOURCES = ("paper_2001_06444_amd/csrc/rtm_kernels.hip", "paper_2001_06444_amd/csrc/rtm_device.h",
-                "paper_2001_06444_amd/csrc/rtm_internal.h")
+                "paper_2001_06444_amd/csrc/rtm_internal.h", "paper_2001_06444_amd/csrc/rtm_runtime.hip")
 CODEC_SOURCES = ("paper_2001_06444_amd/csrc/rtm_codec.hip", "paper_2001_06444_amd/csrc/rtm_codec.h")
 
 

@@ -194,8 +194,9 @@ typedef struct {
  * shot advances in the same kernel launch, launches are replayed from a
  * captured HIP graph, and the tile shape comes from the autotuner.
  * Each shot's image is added into image_dev in shot order after all shots
- * finish (deterministic stack).  Same argument meaning as
- * rtm_migrate_shot; image_dev/illum_dev [nz][nx].
+ * finish (deterministic stack).  Shots with the same window (ix0, width)
+ * share one c = v^2 dt^2 array and its sponge profiles, built once.  Same
+ * argument meaning as rtm_migrate_shot; image_dev/illum_dev [nz][nx].
  * Errors: RTM_E_INVAL, RTM_E_CFL, RTM_E_NOMEM (the whole batch must fit). */
 int rtm_migrate_batch(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
                       const float *wavelet_dev, int32_t nshots, const rtm_shot_desc *shots_host,

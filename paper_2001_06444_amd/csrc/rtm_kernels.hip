@@ -65,6 +65,14 @@ __device__ __forceinline__ T ld_stream(const RTM_GLOBAL T* p) {
 #endif
 }
 
+// c = v^2 dt^2 is read with ordinary loads: the shots of a batch on one
+// window share one c array, and its lines are then served from the caches
+// to the jobs that follow.
+template <class T>
+__device__ __forceinline__ T ld_medium(const RTM_GLOBAL T* p) {
+  return *p;
+}
+
 // ---------------------------------------------------------------------------
 // 16-bit snapshot codec: q = RNE(x * s), x = q / s with s = 2^(15 - e) where
 // max|S^n| = f 2^e, f in [1/2, 1).  The scale is a power of two, so encoding
@@ -195,7 +203,7 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
   for (int k = 0; k < RZ; ++k) {
     const int zc = min(z0 + k, J.nzp - 1);
     const int64_t idx = (int64_t)zc * pitch + xcl;
-    cv[k] = ld_stream(cc + idx);
+    cv[k] = ld_medium(cc + idx);
     pv[k] = ld_stream((const RTM_GLOBAL float*)nxt + idx);
     gzv[k] = gz[zc];
   }
@@ -316,7 +324,7 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
   for (int k = 0; k < RZ; ++k) {
     const int zc = min(z0 + k, J.nzp - 1);
     const int64_t idx = (int64_t)zc * pitch + xcl;
-    cv[k] = ld_stream(cc + idx);
+    cv[k] = ld_medium(cc + idx);
     pv[k] = ld_stream((const RTM_GLOBAL float*)rout + idx);
     gzv[k] = gz[zc];
     iv[k] = 0.0f;
@@ -471,7 +479,7 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
   for (int k = 0; k < RZ; ++k) {
     const int zc = min(z0 + k, J.nzp - 1);
     const int64_t idx = (int64_t)zc * pitch + xcl;
-    cv[k] = ld_stream(cc + idx);
+    cv[k] = ld_medium(cc + idx);
     pv[k] = ld_stream((const RTM_GLOBAL float*)unxt + idx);
     qv[k] = ld_stream((const RTM_GLOBAL float*)dnxt + idx);
     gzv[k] = gz[zc];

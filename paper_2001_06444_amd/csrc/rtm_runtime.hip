@@ -134,6 +134,12 @@ static Footprint footprint(const JobGeom& g) {
   return f;
 }
 
+// Arena bytes of a job's medium (c and the two sponge profiles).
+static size_t medium_bytes(const JobGeom& g) {
+  const int nzp = g.nz + 2 * g.nb, nxp = g.width + 2 * g.nb;
+  return footprint(g).field + align256((size_t)nzp * 4) + align256((size_t)nxp * 4);
+}
+
 struct HostJob {
   JobGeom g;
   DevJob d{};
@@ -142,6 +148,7 @@ struct HostJob {
   std::vector<Block> blocks;     // arena blocks of the job's working set
   Block image_blk;               // the per-job image (kept after the job for polling)
   uint64_t updates = 0, alg_bytes = 0;
+  bool owns_medium = true;       // false: c and the sponge profiles are another job's
 };
 
 static void count_work(HostJob& j) {
@@ -150,18 +157,21 @@ static void count_work(HostJob& j) {
   const uint64_t Nph = (uint64_t)g.nz * g.width;
   const uint64_t ring = (uint64_t)ring_len_of(g.nz, g.width);
   const uint64_t nt = g.nt;
+  // 16 B per update: read u^n, u^{n-1}, c, write u^{n+1}; c is counted only
+  // for the job that owns it when several jobs read one medium.
+  const uint64_t u = j.owns_medium ? 16 : 12;
   if (g.mode == kModeModel) {
     j.updates = (nt - 1) * Npad;
-    j.alg_bytes = (nt - 1) * (Npad * 16 + (uint64_t)g.nrec * 4);
+    j.alg_bytes = (nt - 1) * (Npad * u + (uint64_t)g.nrec * 4);
     return;
   }
   if (g.mode == kModeBorn) {  // background and scattered field: 2 x 16 B, c shared, + m
     j.updates = 2 * (nt - 1) * Npad;
-    j.alg_bytes = (nt - 1) * (Npad * 28 + Nph * 4 + (uint64_t)g.nrec * 4);
+    j.alg_bytes = (nt - 1) * (Npad * (u + 12) + Nph * 4 + (uint64_t)g.nrec * 4);
     return;
   }
   j.updates = (nt - 1) * Npad + nt * Npad;
-  uint64_t b = (nt - 1) * Npad * 16 + nt * Npad * 16 + nt * (uint64_t)g.nrec * 4;
+  uint64_t b = (nt - 1) * Npad * u + nt * Npad * u + nt * (uint64_t)g.nrec * 4;
   if (g.mode == kModeRecon) {
     j.updates += (nt >= 2 ? nt - 2 : 0) * Nph;
     b += (nt - 1) * ring * 4;                 // ring save
@@ -387,11 +397,24 @@ static int check_devjob(const DevJob& d) {
   return RTM_OK;
 }
 
+// The medium of a job: c = v^2 dt^2 on its padded window and the sponge
+// profiles.  Two jobs over the same velocity array with equal window,
+// depth, sponge and time step have identical media.
+static bool same_medium(const JobGeom& a, const JobGeom& b) {
+  return a.nz == b.nz && a.model_nx == b.model_nx && a.ix0 == b.ix0 && a.width == b.width && a.nb == b.nb &&
+         a.dt == b.dt && a.sponge_a == b.sponge_a;
+}
+
 // Allocates the job's working set and enqueues its set-up on stream s.
 // src/recs are in model coordinates.  On failure nothing stays allocated.
+// `medium`, if given, is a job of the same velocity array whose medium is
+// the same (same_medium): the new job reads that job's c and sponge
+// profiles instead of building its own, so a batch of shots on one window
+// streams one c through the caches.  The caller keeps `medium` alive as
+// long as the new job.
 static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, const float* vel,
                      const float* wavelet, rtm_point src, const rtm_point* recs, const float* data,
-                     float* traces, HostJob& j) {
+                     float* traces, HostJob& j, const HostJob* medium) {
   j.g = g;
   const int nzp = g.nz + 2 * g.nb, nxp = g.width + 2 * g.nb;
   DevJob& d = j.d;
@@ -436,7 +459,7 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
     return q;
   };
   const int64_t org = field_origin(nxp);
-  float* cbuf = static_cast<float*>(A(F));
+  float* cbuf = medium ? nullptr : static_cast<float*>(A(F));
   float* fb0 = static_cast<float*>(A(F));
   float* fb1 = static_cast<float*>(A(F));
   float *rb0 = nullptr, *rb1 = nullptr;
@@ -444,8 +467,8 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
     rb0 = static_cast<float*>(A(F));
     rb1 = static_cast<float*>(A(F));
   }
-  float* gz = static_cast<float*>(A((size_t)nzp * 4));
-  float* gx = static_cast<float*>(A((size_t)nxp * 4));
+  float* gz = medium ? nullptr : static_cast<float*>(A((size_t)nzp * 4));
+  float* gx = medium ? nullptr : static_cast<float*>(A((size_t)nxp * 4));
   float* illum = nullptr;
   const size_t img_bytes = (size_t)g.nz * field_pitch(nxp) * 4;
   if (g.mode != kModeModel && (g.flags & RTM_IMG_ILLUM)) illum = static_cast<float*>(A(img_bytes));
@@ -469,9 +492,9 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
     return fail(RTM_E_NOMEM, "arena exhausted: job needs %zu bytes, arena %zu used of %zu", fp.total,
                 ctx->arena.used(), ctx->arena.size());
   }
-  d.c = cbuf + org;
-  d.gz = gz;
-  d.gx = gx;
+  d.c = medium ? medium->d.c : cbuf + org;
+  d.gz = medium ? medium->d.gz : gz;
+  d.gx = medium ? medium->d.gx : gx;
   d.f[0] = fb0 + org;
   d.f[1] = fb1 + org;
   if (rb0) {
@@ -531,7 +554,7 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
     HIP_OK(hipMemsetAsync(rb0, 0, fb, s));
     HIP_OK(hipMemsetAsync(rb1, 0, fb, s));
   }
-  HIP_OK(hipMemsetAsync(cbuf, 0, fb, s));
+  if (cbuf) HIP_OK(hipMemsetAsync(cbuf, 0, fb, s));
   if (image) HIP_OK(hipMemsetAsync(image, 0, img_bytes, s));
   if (illum) HIP_OK(hipMemsetAsync(illum, 0, img_bytes, s));
   if (ring) HIP_OK(hipMemsetAsync(ring, 0, (size_t)d.ring_len * 4, s));  // ring of u^0 = 0
@@ -539,7 +562,8 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   HIP_OK(hipMemsetAsync(health, 0, 4, s));
   if (traces) HIP_OK(hipMemsetAsync(traces, 0, (size_t)g.nrec * 4, s));  // d[0] = u^0 = 0
   if (g.nrec) HIP_OK(hipMemcpyAsync(recd, j.recs.data(), (size_t)g.nrec * 8, hipMemcpyHostToDevice, s));
-  HIP_OK(launch_prep(vel, g.model_nx, g.ix0, &d, cbuf + org, gz, gx, g.dt, g.sponge_a, s));
+  if (cbuf) HIP_OK(launch_prep(vel, g.model_nx, g.ix0, &d, cbuf + org, gz, gx, g.dt, g.sponge_a, s));
+  j.owns_medium = cbuf != nullptr;
   count_work(j);
   return RTM_OK;
 }
@@ -618,7 +642,7 @@ static void tune_file_save(rtm_ctx* ctx) {
 
 static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, const float* vel,
                      const float* wavelet, rtm_point src, const rtm_point* recs, const float* data,
-                     float* traces, HostJob& j);
+                     float* traces, HostJob& j, const HostJob* medium);
 static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, struct Table& t);
 
 static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch, int tz,
@@ -729,7 +753,7 @@ static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* 
     auto j = std::make_unique<HostJob>();
     float* tr = traces ? static_cast<float*>(traces) + (size_t)b * g.nt * g.width : nullptr;
     rc = build_job(ctx, s, g, tz, vel, static_cast<const float*>(zero), src, recs.data(),
-                   static_cast<const float*>(zero), tr, *j);
+                   static_cast<const float*>(zero), tr, *j, jobs.empty() ? nullptr : jobs[0].get());
     if (rc == RTM_OK) {
       ptrs.push_back(j.get());
       jobs.push_back(std::move(j));
@@ -934,7 +958,8 @@ extern "C" int rtm_propagate(rtm_ctx* ctx, const rtm_grid* grid, const float* ve
   if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
   const int tz = autotune_tz(ctx, s, g, vel_dev, 1);
   HostJob j;
-  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, nullptr, traces_dev, j))) return rc;
+  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, nullptr, traces_dev, j, nullptr)))
+    return rc;
   Table t;
   if ((rc = run_plain(ctx, s, j, tz, t))) {
     finish_job_deferred(ctx, s, j, t, false);
@@ -977,7 +1002,8 @@ extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev
   if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
   const int tz = autotune_tz(ctx, s, g, vel_dev, 1);
   HostJob j;
-  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, nullptr, dtraces_dev, j))) return rc;
+  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, nullptr, dtraces_dev, j, nullptr)))
+    return rc;
   // the perturbation goes into the job's image buffer (field-aligned rows, padded columns)
   HIP_OK(hipMemcpy2DAsync(j.d.image + g.nb, (size_t)j.d.pitch * 4, mpert_dev, (size_t)g.width * 4,
                           (size_t)g.width * 4, g.nz, hipMemcpyDeviceToDevice, s));
@@ -1044,7 +1070,8 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
   if ((rc = check_cfl(vmax, g.dt, g.dz, g.dx))) return rc;
   const int tz = autotune_tz(ctx, s, g, vel_dev, 1);
   HostJob j;
-  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, data_dev, nullptr, j))) return rc;
+  if ((rc = build_job(ctx, s, g, tz, vel_dev, wavelet_dev, src, rec_host, data_dev, nullptr, j, nullptr)))
+    return rc;
   Table t;
   rc = run_plain(ctx, s, j, tz, t);
   if (!rc) {
@@ -1121,7 +1148,14 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     if (shots[i].nrec > 0 && !shots[i].data_dev) return fail(RTM_E_INVAL, "shot %d has no data", i);
   }
   size_t need = 0;
-  for (auto& g : geoms) need += footprint(g).total;
+  for (int i = 0; i < nshots; ++i) {
+    need += footprint(geoms[i]).total;
+    for (int k = 0; k < i; ++k)
+      if (same_medium(geoms[k], geoms[i])) {  // reads shot k's medium
+        need -= medium_bytes(geoms[i]);
+        break;
+      }
+  }
   if (need > ctx->arena.size())
     return fail(RTM_E_NOMEM, "batch needs %zu bytes, arena holds %zu", need, ctx->arena.size());
   HIP_OK(hipSetDevice(ctx->device));
@@ -1149,8 +1183,14 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   };
   for (int i = 0; i < nshots; ++i) {
     auto j = std::make_unique<HostJob>();
+    const HostJob* medium = nullptr;
+    for (auto& o : jobs)
+      if (o->owns_medium && same_medium(o->g, geoms[i])) {
+        medium = o.get();
+        break;
+      }
     rc = build_job(ctx, s, geoms[i], tz, vel_dev, wavelet_dev, shots[i].src, shots[i].rec_host,
-                   shots[i].data_dev, nullptr, *j);
+                   shots[i].data_dev, nullptr, *j, medium);
     if (rc) {
       (void)hipStreamSynchronize(s);
       cleanup();
@@ -1178,8 +1218,9 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
       const JobGeom& g = j->g;
       const uint64_t Npad = (uint64_t)(g.nz + 2 * g.nb) * (g.width + 2 * g.nb), Nph = (uint64_t)g.nz * g.width;
       const uint64_t ring = ring_len_of(g.nz, g.width);
-      bf += Npad * 16 + (g.mode == kModeRecon ? ring * 4 : 0);
-      bb += Npad * 16 + (uint64_t)g.nrec * 4;
+      const uint64_t u = j->owns_medium ? 16 : 12;  // c counted once per medium
+      bf += Npad * u + (g.mode == kModeRecon ? ring * 4 : 0);
+      bb += Npad * u + (uint64_t)g.nrec * 4;
       // interior: S^{m+1}, S^{m+2} read + S^m written (12 B) + image (8 B); ring: stored value read + S^m written
       if (g.mode == kModeRecon) bb += Nph * 20 - ring * 4;
     }
@@ -1446,7 +1487,7 @@ static void sched_main(rtm_ctx* ctx) {
         if (!rc && tz == 0) tz = autotune_tz(ctx, s, g, static_cast<const float*>(m.vel.p), 16);
         if (!rc)
           rc = build_job(ctx, s, g, tz, static_cast<const float*>(m.vel.p), ej->spec.wavelet_dev, ej->spec.src,
-                         recs.data(), ej->spec.data_dev, nullptr, *hj);
+                         recs.data(), ej->spec.data_dev, nullptr, *hj, nullptr);
         if (rc == RTM_E_NOMEM) {
           if (blocked_head || ++ej->bypassed > kMaxBypass) break;  // keep the head from starving
           blocked_head = true;

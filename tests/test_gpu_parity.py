@@ -285,7 +285,10 @@ def test_batch_equals_plain_bitwise(rtm, ctx):
     w = inputs.ricker(nt, dt, fp=20)
     g = grid_of(rtm, nz, nx, nb, nt, h, dt)
     shots = []
-    for k, (sx, ix0, width) in enumerate([(30, 0, 100), (115, 40, 150), (200, 130, 100)]):
+    # windows repeat: shots 0, 3, 5 read one shared c, shots 1 and 4 another,
+    # shot 2 its own
+    for k, (sx, ix0, width) in enumerate([(30, 0, 100), (115, 40, 150), (200, 130, 100),
+                                          (60, 0, 100), (150, 40, 150), (95, 0, 100)]):
         rec = [(1, x) for x in range(ix0, ix0 + width)]
         d = dev(rng.standard_normal((nt, width)) * 1e-3)
         shots.append(((1, sx), ix0, width, rec, d))
