@@ -190,10 +190,11 @@ def run_survey(args):
     grid = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
 
     # arena: working set of every shot of the batch plus slack
-    field = ((nz + 2 * nb + 63) // 64 * 64 + 10) * ((nx + 2 * nb + 4 + 63) // 64 * 64) * 4
+    field = ((nz + 2 * nb + 63) // 64 * 64 + 18) * ((nx + 2 * nb + 4 + 63) // 64 * 64) * 4
     ring = nt * 8 * (nz + nx - 8) * 4
-    per_shot = 5 * field + ring + nz * nx * 4 + nt * 256 + nx * 8 + 8192
-    arena = int(len(sv.shots) * per_shot * 1.02) + (256 << 20)
+    # four buffers per wavefield and shot; the shots share one c
+    per_shot = 8 * field + ring + nz * nx * 4 + nt * 256 + nx * 8 + 8192
+    arena = int(len(sv.shots) * per_shot * 1.02) + field + (256 << 20)
     log(f"[bench] survey {sv.name}: {len(sv.shots)} shots, nt={nt}, arena {arena / 2**30:.1f} GiB")
     ctx = rtm.Context(0, arena_bytes=arena)
 
@@ -329,8 +330,8 @@ def _model_window_data(ctx, grid, vel_true, vel_mig, wav, src, ix0, width, nt):
 
 
 def _job_bytes(nz, width, nb, nt, mode="reconstruct", dtype="fp32", stride=1):
-    field = ((nz + 2 * nb + 63) // 64 * 64 + 10) * ((width + 2 * nb + 4 + 63) // 64 * 64) * 4
-    b = 5 * field + nz * width * 4 + nt * 256 + width * 8 + 16384
+    field = ((nz + 2 * nb + 63) // 64 * 64 + 18) * ((width + 2 * nb + 4 + 63) // 64 * 64) * 4
+    b = 9 * field + nz * width * 4 + nt * 256 + width * 8 + 16384  # c and four buffers per wavefield
     if mode == "reconstruct":
         b += nt * 8 * (nz + width - 8) * 4
     else:

@@ -8,10 +8,13 @@
 //   with a row pitch `pitch` = roundup(nxp + 4, 64) floats (256-byte rows), so
 //   every row starts on a 256-byte boundary and ends with >= 4 zero columns
 //   that double as the left/right ghost cells of the 8th-order stencil.
-//   Five zero rows precede row 0 and the allocation extends to
-//   roundup(nzp, 64) + 5 rows, which covers the top/bottom ghost rows and the
-//   halo of the last tile row.  Points outside [0,nzp) x [0,nxp) are zero and
-//   are never written.
+//   Nine zero rows precede row 0 and the allocation extends to
+//   roundup(nzp, 64) + 9 rows, which covers the top/bottom ghost rows and the
+//   8-cell halo a two-step tile reads.  Points outside [0,nzp) x [0,nxp) are
+//   zero and are never written.
+//   Time level n of a wavefield lives in buffer n & 3 of four, so a launch
+//   that advances two steps never overwrites a level a neighbouring tile
+//   still reads.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,10 +25,12 @@ namespace rtm {
 constexpr int kTileX = 64;       // tile width: one 64-lane wavefront per row
 constexpr int kHalo = 4;         // stencil radius
 constexpr int kLdsW = kTileX + 2 * kHalo;  // 72 floats per LDS row
-constexpr int kTopRows = 5;      // zero rows before padded row 0
+constexpr int kTopRows = 9;      // zero rows before padded row 0 (two-step halo + 1)
 constexpr int kRowAlign = 64;    // rows rounded up to the tallest tile
 constexpr int kThreads = 256;    // 4 wavefronts per workgroup
 constexpr int kMaxSlots = 64;    // partial max-abs slots per stored step (spreads the atomics)
+constexpr int kTileX2 = 56;      // output width of a two-step tile: its first step covers
+                                 // 56 + 2 * 4 = 64 columns, one wavefront
 
 enum JobMode : int32_t { kModeModel = 0, kModeStore = 1, kModeRecon = 2, kModeBorn = 3 };
 enum PhaseSet : int { kPhFwd = 1, kPhBwd = 2, kPhAny = 3, kPhBorn = 4 };
@@ -37,14 +42,14 @@ struct alignas(16) DevJob {
   int32_t nx, nb, nt, mode;        // physical cols, sponge width, time samples, JobMode
   int32_t snap_dtype, snap_stride, flags, nsteps;  // snapshots; RTM_IMG_*; steps of the job
   int32_t src_z, src_x, nrec, ring_len;            // padded source node; receivers; ring size
-  int32_t start_tick, tiles_x, tiles_z, pad0;      // first global tick; tile grid
+  int32_t start_tick, tiles_x, tiles_z, tiles_x2;  // first global tick; tile grid; two-step tile columns
   float inv_cell, c0, kfac, pad1;  // 1/(dx dz); a0 (1/dz^2 + 1/dx^2); imaging weight k
   float cz[4], cx[4];              // a_k / dz^2, a_k / dx^2, k = 1..4
   const float* c;                  // v^2 dt^2, padded grid (field layout)
   const float* gz;                 // sponge profile per padded row [nzp]
   const float* gx;                 // sponge profile per padded column [nxp]
-  float* f[2];                     // source wavefield: S^n / u^n in f[n & 1]
-  float* r[2];                     // receiver wavefield R^m in r[m & 1] (Born: scattered field du^n)
+  float* f[4];                     // source wavefield: S^n / u^n in f[n & 3]
+  float* r[4];                     // receiver wavefield R^m in r[m & 3] (Born: scattered field du^n)
   const float* wavelet;            // [nt]
   const float* data;               // [nt][nrec] injected at receivers (migration)
   float* traces;                   // [nt][nrec] sampled at receivers (modelling)
@@ -58,7 +63,8 @@ struct alignas(16) DevJob {
   uint32_t* health;                // [1] bit 0: a non-finite value was seen
 };
 
-// One tile of one job: rows [z0, z0+TZ), columns [x0, x0+64) of its padded grid.
+// One tile of one job: rows [z0, z0+TZ), columns [x0, x0+64) of its padded grid
+// (columns [x0, x0+56) for a two-step tile).
 struct alignas(16) Tile {
   int32_t job, z0, x0, rec_begin;
   int32_t rec_count, pad0, pad1, pad2;
@@ -83,6 +89,8 @@ inline int32_t ring_len_of(int nz, int nx) { return 8 * (nz + nx - 8); }
 hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
                        int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
                        hipStream_t s);
+hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
+                        const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s);
 hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s);
 hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* host_job,
                        float* c, float* gz, float* gx, float dt, float sponge_a, hipStream_t s);

@@ -117,7 +117,7 @@ struct TileStage {
     for (int it = 0; it < kIt; ++it) {
       // surplus threads of the last round re-load the last vector (no branch
       // around the load, so no wait at a join); store() skips them
-      const int i = min(threadIdx.x + it * kThreads, kN - 1);
+      const int i = min((int)threadIdx.x + it * kThreads, kN - 1);
       const int r = i / kVec, q = i - r * kVec;
       v[it] = *(const RTM_GLOBAL f32x4*)(base + (int64_t)r * pitch + q * 4);
     }
@@ -134,13 +134,20 @@ struct TileStage {
   }
 };
 
+// One leapfrog update with the sponge, u_new = G (2u + c lap) - G^2 u_old,
+// written as explicit fused operations so that every kernel that applies it
+// (one step or two per launch) rounds identically.
+__device__ __forceinline__ float leapfrog(float G, float c, float lap, float u, float u_old) {
+  return fmaf(-(G * G), u_old, G * fmaf(c, lap, 2.0f * u));
+}
+
 // 8th-order Laplacian at LDS row `row` (centre) of column `col` (LDS coords),
 // z-neighbours from the register window zw[k .. k+8] (zw[k+4] is the centre).
-template <int RZ>
+template <int RZ, int W = kLdsW>
 __device__ __forceinline__ float lap8(const float* __restrict__ lds, int row, int col,
                                       const float (&zw)[RZ + 8], int k, float c0,
                                       const float (&cz)[4], const float (&cx)[4]) {
-  const float* rp = lds + row * kLdsW + col;
+  const float* rp = lds + row * W + col;
   float s = c0 * zw[k + 4];
   s = fmaf(cz[0], zw[k + 3] + zw[k + 5], s);
   s = fmaf(cx[0], rp[-1] + rp[1], s);
@@ -183,8 +190,9 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
   constexpr int RZ = TZ / 4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pitch = J.pitch;
-  const RTM_GLOBAL float* __restrict__ cur = gp(J.f[n & 1]);
-  RTM_GLOBAL float* __restrict__ nxt = gp(J.f[(n + 1) & 1]);  // holds u^{n-1}; overwritten with u^{n+1}
+  const RTM_GLOBAL float* __restrict__ cur = gp(J.f[n & 3]);
+  const RTM_GLOBAL float* __restrict__ old = gp(J.f[(n + 3) & 3]);  // u^{n-1}
+  RTM_GLOBAL float* __restrict__ nxt = gp(J.f[(n + 1) & 3]);        // u^{n+1}
   const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
   const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
   const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
@@ -204,7 +212,7 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
     const int zc = min(z0 + k, J.nzp - 1);
     const int64_t idx = (int64_t)zc * pitch + xcl;
     cv[k] = ld_medium(cc + idx);
-    pv[k] = ld_stream((const RTM_GLOBAL float*)nxt + idx);
+    pv[k] = ld_stream(old + idx);
     gzv[k] = gz[zc];
   }
   const float gxv = colok ? gx[xcl] : 0.0f;
@@ -241,7 +249,7 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
       if (z == J.src_z && x == J.src_x) lap += wsrc;
       const float G = gzv[k] * gxv;
       const float u = zw[k + 4];
-      const float un = G * fmaf(cv[k], lap, 2.0f * u) - (G * G) * pv[k];
+      const float un = leapfrog(G, cv[k], lap, u, pv[k]);
       st_stream(nxt + idx, un);
       const int pz = z - J.nb;
       const bool phys = colphys && pz >= 0 && pz < J.nz;
@@ -285,10 +293,12 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pitch = J.pitch;
   const int nt = J.nt;
-  const RTM_GLOBAL float* __restrict__ rcur = gp(J.r[(m + 1) & 1]);  // R^{m+1}
-  RTM_GLOBAL float* __restrict__ rout = gp(J.r[m & 1]);              // R^{m+2} -> R^m
-  const RTM_GLOBAL float* __restrict__ scur = gp(J.f[(m + 1) & 1]);  // S^{m+1}
-  RTM_GLOBAL float* __restrict__ sout = gp(J.f[m & 1]);  // S^{m+2} -> S^m (S^m itself when m >= nt-2)
+  const RTM_GLOBAL float* __restrict__ rcur = gp(J.r[(m + 1) & 3]);  // R^{m+1}
+  const RTM_GLOBAL float* __restrict__ rold = gp(J.r[(m + 2) & 3]);  // R^{m+2}
+  RTM_GLOBAL float* __restrict__ rout = gp(J.r[m & 3]);              // R^m
+  const RTM_GLOBAL float* __restrict__ scur = gp(J.f[(m + 1) & 3]);  // S^{m+1}
+  const RTM_GLOBAL float* __restrict__ sold = gp(J.f[(m + 2) & 3]);  // S^{m+2}
+  RTM_GLOBAL float* __restrict__ sout = gp(J.f[m & 3]);  // S^m (left by the forward pass when m >= nt-2)
   RTM_GLOBAL float* __restrict__ image = gp(J.image);
   RTM_GLOBAL float* __restrict__ illum = gp(J.illum);
   const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
@@ -325,7 +335,7 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
     const int zc = min(z0 + k, J.nzp - 1);
     const int64_t idx = (int64_t)zc * pitch + xcl;
     cv[k] = ld_medium(cc + idx);
-    pv[k] = ld_stream((const RTM_GLOBAL float*)rout + idx);
+    pv[k] = ld_stream(rold + idx);
     gzv[k] = gz[zc];
     iv[k] = 0.0f;
     sv[k] = 0.0f;
@@ -346,7 +356,7 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
         // ring nodes are restored from storage; interior nodes need S^{m+2}
         const RTM_GLOBAL float* sp =
             slot >= 0 ? gp(J.ring) + (int64_t)m * J.ring_len + slot
-                      : (const RTM_GLOBAL float*)sout + (int64_t)(pzc + J.nb) * pitch + xph;
+                      : sold + (int64_t)(pzc + J.nb) * pitch + xph;
         sv[k] = ld_stream(sp);
       }
     } else if (mode == kModeRecon) {
@@ -416,7 +426,7 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
       if (has_inj) lap += sm.inj[lz * kTileX + lane];
       const float G = gzv[k] * gxv;
       const float r1 = zr[k + 4];  // R^{m+1}
-      st_stream(rout + idx, G * fmaf(cv[k], lap, 2.0f * r1) - (G * G) * pv[k]);
+      st_stream(rout + idx, leapfrog(G, cv[k], lap, r1, pv[k]));
       const int pz = z - J.nb;
       if (imaging && colphys && pz >= 0 && pz < J.nz) {
         float s;
@@ -455,10 +465,12 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
   constexpr int RZ = TZ / 4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pitch = J.pitch;
-  const RTM_GLOBAL float* __restrict__ ucur = gp(J.f[n & 1]);
-  RTM_GLOBAL float* __restrict__ unxt = gp(J.f[(n + 1) & 1]);
-  const RTM_GLOBAL float* __restrict__ dcur = gp(J.r[n & 1]);
-  RTM_GLOBAL float* __restrict__ dnxt = gp(J.r[(n + 1) & 1]);
+  const RTM_GLOBAL float* __restrict__ ucur = gp(J.f[n & 3]);
+  const RTM_GLOBAL float* __restrict__ uold = gp(J.f[(n + 3) & 3]);
+  RTM_GLOBAL float* __restrict__ unxt = gp(J.f[(n + 1) & 3]);
+  const RTM_GLOBAL float* __restrict__ dcur = gp(J.r[n & 3]);
+  const RTM_GLOBAL float* __restrict__ dold = gp(J.r[(n + 3) & 3]);
+  RTM_GLOBAL float* __restrict__ dnxt = gp(J.r[(n + 1) & 3]);
   const RTM_GLOBAL float* __restrict__ mp = gp(J.image);
   const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
   const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
@@ -480,8 +492,8 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
     const int zc = min(z0 + k, J.nzp - 1);
     const int64_t idx = (int64_t)zc * pitch + xcl;
     cv[k] = ld_medium(cc + idx);
-    pv[k] = ld_stream((const RTM_GLOBAL float*)unxt + idx);
-    qv[k] = ld_stream((const RTM_GLOBAL float*)dnxt + idx);
+    pv[k] = ld_stream(uold + idx);
+    qv[k] = ld_stream(dold + idx);
     gzv[k] = gz[zc];
     const int pzc = min(max(z0 + k - J.nb, 0), J.nz - 1);
     mv[k] = ld_stream(mp + (int64_t)pzc * pitch + xph);
@@ -513,10 +525,10 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
       const float u = zu[k + 4];
       float lu = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zu, k, c0, cz, cx);
       if (z == J.src_z && x == J.src_x) lu += wsrc;
-      st_stream(unxt + idx, G * fmaf(cv[k], lu, 2.0f * u) - (G * G) * pv[k]);
+      st_stream(unxt + idx, leapfrog(G, cv[k], lu, u, pv[k]));
       float ld = lap8<RZ>(sm.b, lz + kHalo, lane + kHalo, zd, k, c0, cz, cx);
       if (phys) ld = fmaf(mv[k], u, ld);
-      const float dn = G * fmaf(cv[k], ld, 2.0f * zd[k + 4]) - (G * G) * qv[k];
+      const float dn = leapfrog(G, cv[k], ld, zd[k + 4], qv[k]);
       st_stream(dnxt + idx, dn);
       sm.inj[lz * kTileX + lane] = dn;
     }
@@ -527,6 +539,195 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
       int2 r = J.recs[tl.rec_begin + i];
       gp(J.traces)[(int64_t)(n + 1) * J.nrec + r.y] = sm.inj[r.x];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per launch (reconstruct mode).  A two-step tile owns output
+// rows [z0, z0 + TZ) and columns [x0, x0 + 56).  Its first step covers the
+// middle region, the tile grown by the stencil radius (rows z0 - 4 ..
+// z0 + TZ + 4, columns x0 - 4 .. x0 + 60: one column per lane), from inputs
+// staged with an 8-cell halo; the second step reads the middle region from
+// LDS.  Middle-region values outside the grid are set to zero, the value the
+// ghost cells hold for a one-step launch, so every node goes through the same
+// operations on the same operands as in two one-step launches and the
+// results agree bit for bit.  Each job then moves its two stepped fields
+// once per two steps instead of once per step.
+// ---------------------------------------------------------------------------
+template <int ROWS>
+struct TileStageW {  // ROWS x 72 floats from (zs, xs), as 16-byte loads
+  static constexpr int kVec = kLdsW / 4;
+  static constexpr int kN = ROWS * kVec;
+  static constexpr int kIt = (kN + kThreads - 1) / kThreads;
+  f32x4 v[kIt];
+
+  __device__ __forceinline__ void load(const RTM_GLOBAL float* __restrict__ fld, int pitch, int zs, int xs) {
+    const RTM_GLOBAL float* base = fld + (int64_t)zs * pitch + xs;
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int i = min((int)threadIdx.x + it * kThreads, kN - 1);
+      const int r = i / kVec, q = i - r * kVec;
+      v[it] = *(const RTM_GLOBAL f32x4*)(base + (int64_t)r * pitch + q * 4);
+    }
+  }
+  __device__ __forceinline__ void store(float* __restrict__ lds) const {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int i = threadIdx.x + it * kThreads;
+      if (i < kN) {
+        const int r = i / kVec, q = i - r * kVec;
+        *reinterpret_cast<f32x4*>(lds + r * kLdsW + q * 4) = v[it];
+      }
+    }
+  }
+};
+
+template <int TZ, bool kBwd>
+struct Step2Smem {
+  float a[(TZ + 4 * kHalo) * kLdsW];              // u^n or R^{m+1}, 8-cell halo
+  float b[kBwd ? (TZ + 4 * kHalo) * kLdsW : 4];   // S^{m+1}
+  float ma[(TZ + 2 * kHalo) * kTileX];            // middle region: u^{n+1} or R^m
+  float mb[kBwd ? (TZ + 2 * kHalo) * kTileX : 4]; // middle region: S^m
+  float inj[kBwd ? (TZ + 2 * kHalo) * kTileX : 4];
+};
+
+// Boundary-ring save of a forward value at level `lev` (reconstruct mode).
+__device__ __forceinline__ void ring_save(const DevJob& J, int z, int x, int lev, float v) {
+  const int pz = z - J.nb, px = x - J.nb;
+  if (pz >= 0 && pz < J.nz && px >= 0 && px < J.nx) {
+    const int slot = ring_slot(pz, px, J.nz, J.nx);
+    if (slot >= 0) st_stream(gp(J.ring) + (int64_t)lev * J.ring_len + slot, v);
+  }
+}
+
+// One two-step forward tile.  kFast: the middle region lies inside the grid
+// and holds neither the source nor a boundary-ring node, so no node needs a
+// zero, a source term or a ring save and the per-node tests drop out; the
+// other tiles take the general path.  Offsets are 32-bit (a field holds
+// fewer than 2^30 floats).
+template <int TZ, bool kFast, class Smem>
+__device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, int n, Smem& sm) {
+  constexpr int RA = (TZ + 2 * kHalo) / 4;  // middle rows per wavefront (first step)
+  constexpr int RB = TZ / 4;                // output rows per wavefront (second step)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int pitch = J.pitch;
+  const RTM_GLOBAL float* __restrict__ u0 = gp(J.f[n & 3]);        // u^n
+  const RTM_GLOBAL float* __restrict__ um = gp(J.f[(n + 3) & 3]);  // u^{n-1}
+  RTM_GLOBAL float* __restrict__ u1 = gp(J.f[(n + 1) & 3]);        // u^{n+1}
+  RTM_GLOBAL float* __restrict__ u2 = gp(J.f[(n + 2) & 3]);        // u^{n+2}
+  const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
+  const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
+  const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
+  const int x = tl.x0 - kHalo + lane;      // this lane's column
+  const int za0 = tl.z0 - kHalo + w * RA;  // first middle row of this wavefront
+  const int zb0 = tl.z0 + w * RB;          // first output row of this wavefront
+  const bool xin = x >= 0 && x < J.nxp;
+  const bool xout = lane >= kHalo && lane < kHalo + kTileX2 && (kFast || x < J.nxp);
+  const uint32_t xcl = (uint32_t)min(max(x, 0), J.nxp - 1);
+
+  // ---- every global load first ----
+  TileStageW<TZ + 4 * kHalo> st;
+  st.load(u0, pitch, tl.z0 - 2 * kHalo, tl.x0 - 2 * kHalo);
+  float cva[RA], pva[RA], gza[RA], cvb[RB], gzb[RB];
+#pragma unroll
+  for (int k = 0; k < RA; ++k) {
+    const int zc = kFast ? za0 + k : min(max(za0 + k, 0), J.nzp - 1);
+    const uint32_t off = (uint32_t)zc * (uint32_t)pitch + xcl;
+    cva[k] = ld_medium(cc + off);
+    pva[k] = ld_stream(um + off);
+    gza[k] = gz[zc];
+  }
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int zc = kFast ? zb0 + k : min(zb0 + k, J.nzp - 1);
+    cvb[k] = ld_medium(cc + ((uint32_t)zc * (uint32_t)pitch + xcl));
+    gzb[k] = gz[zc];
+  }
+  const float gxv = (kFast || xin) ? gx[xcl] : 0.0f;
+  const float w0 = kFast ? 0.0f : gp(J.wavelet)[n] * J.inv_cell;
+  const float w1 = kFast ? 0.0f : gp(J.wavelet)[n + 1] * J.inv_cell;
+  st.store(sm.a);
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
+
+  // ---- first step: u^{n+1} on the middle region ----
+  float zw[RA + 8];
+#pragma unroll
+  for (int j = 0; j < RA + 8; ++j) zw[j] = sm.a[(w * RA + j) * kLdsW + lane + kHalo];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < RA; ++k) {
+    const int r = w * RA + k;  // middle row (wavefront-uniform)
+    const int z = za0 + k;
+    float lap = lap8<RA>(sm.a, r + kHalo, lane + kHalo, zw, k, c0, cz, cx);
+    if (!kFast && z == J.src_z && x == J.src_x) lap += w0;
+    const float G = gza[k] * gxv;
+    float un = leapfrog(G, cva[k], lap, zw[k + 4], pva[k]);
+    if (!kFast) un = (xin && z >= 0 && z < J.nzp) ? un : 0.0f;
+    sm.ma[r * kTileX + lane] = un;
+    if (r >= kHalo && r < TZ + kHalo && (kFast || z < J.nzp) && xout) {  // a node of the output tile
+      st_stream(u1 + ((uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
+      if (!kFast) ring_save(J, z, x, n + 1, un);
+    }
+  }
+  __syncthreads();
+
+  // ---- second step: u^{n+2} on the output tile ----
+  float zm[RB + 8];
+#pragma unroll
+  for (int j = 0; j < RB + 8; ++j) zm[j] = sm.ma[(w * RB + j) * kTileX + lane];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < RB; ++k) {
+    const int z = zb0 + k;
+    float lap = lap8<RB, kTileX>(sm.ma, w * RB + k + kHalo, lane, zm, k, c0, cz, cx);
+    if (!kFast && z == J.src_z && x == J.src_x) lap += w1;
+    const float G = gzb[k] * gxv;
+    const float uold = sm.a[(w * RB + k + 2 * kHalo) * kLdsW + lane + kHalo];  // u^n
+    if (xout && (kFast || z < J.nzp)) {
+      const float un = leapfrog(G, cvb[k], lap, zm[k + 4], uold);
+      st_stream(u2 + ((uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
+      if (!kFast) ring_save(J, z, x, n + 2, un);
+    }
+  }
+}
+
+template <int TZ, class Smem>
+__device__ __forceinline__ void forward2_tile(const DevJob& J, const Tile& tl, int n, Smem& sm) {
+  const int z0 = tl.z0, x0 = tl.x0;
+  const bool inside = z0 >= kHalo && z0 + TZ + kHalo <= J.nzp && x0 >= kHalo && x0 + kTileX2 + kHalo <= J.nxp;
+  const bool src = J.src_z >= z0 - kHalo && J.src_z < z0 + TZ + kHalo && J.src_x >= x0 - kHalo &&
+                   J.src_x < x0 + kTileX2 + kHalo;
+  // output nodes in the physical window but outside its interior hold ring nodes
+  const int pz0 = z0 - J.nb, pz1 = z0 + TZ - J.nb, px0 = x0 - J.nb, px1 = x0 + kTileX2 - J.nb;
+  const bool phys = pz0 < J.nz && pz1 > 0 && px0 < J.nx && px1 > 0;
+  const bool interior = pz0 >= 4 && pz1 <= J.nz - 4 && px0 >= 4 && px1 <= J.nx - 4;
+  if (inside && !src && !(phys && !interior))
+    forward2_body<TZ, true>(J, tl, n, sm);
+  else
+    forward2_body<TZ, false>(J, tl, n, sm);
+}
+
+template <int TZ, int PH>
+__global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ jobs,
+                                                     const Tile* __restrict__ tiles,
+                                                     const StepCtl* __restrict__ ctl, int ntiles,
+                                                     int use_ctl_tick, int tick_off) {
+  __shared__ Step2Smem<TZ, (PH & kPhBwd) != 0> sm;
+  // Steps tick and tick + 1 of every job; same XCD-aware mapping as k_step.
+  const int tick = (use_ctl_tick ? ctl->tick : 0) + tick_off;
+  const int per = (ntiles + 7) >> 3;
+  const int local = (int)(blockIdx.x >> 3);
+  const int t = (blockIdx.x & 7) * per + local;
+  if (local >= per || t >= ntiles) return;
+  const Tile tl = tiles[t];
+  const DevJob& J = jobs[tl.job];
+  const int s = tick - J.start_tick;
+  if (J.mode != kModeRecon || s < 0 || s + 1 >= J.nsteps) return;
+  const int nf = J.nt - 1;  // forward steps
+  if (s + 1 < nf) {
+    if (PH & kPhFwd) forward2_tile<TZ>(J, tl, s, sm);
   }
 }
 
@@ -585,6 +786,24 @@ static hipError_t launch_step_tz(int phases, const DevJob* jobs, const Tile* til
     hipLaunchKernelGGL((k_step<TZ, kPhBorn>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
   else
     hipLaunchKernelGGL((k_step<TZ, kPhAny>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
+                        const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const int per = (ntiles + 7) / 8;
+  dim3 grid(8 * per), block(kThreads);
+  if (phases != kPhFwd) return hipErrorInvalidValue;
+  switch (tz) {
+    case 16:
+      hipLaunchKernelGGL((k_step2<16, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_step2<32, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
