@@ -239,12 +239,18 @@ def run_survey(args):
     log(f"[bench] batched: {ms_per_step:.1f} ms/step, {value:.3e} updates/s, "
         f"{images_per_s:.1f} images/s")
 
-    # dominant kernel: backward step (HIP events around all its launches, work stream)
-    bwd_launch_ms = s1.last_bwd_ms / s1.last_bwd_launches
-    fwd_launch_ms = s1.last_fwd_ms / s1.last_fwd_launches
-    achieved = s1.last_bwd_launch_bytes / (bwd_launch_ms * 1e-3) / 1e9
-    achieved_fwd = s1.last_fwd_launch_bytes / (fwd_launch_ms * 1e-3) / 1e9
-    log(f"[bench] backward launch {bwd_launch_ms * 1e3:.1f} us, {achieved:.0f} GB/s; "
+    # dominant kernel: backward step (HIP events around all its launches, work
+    # stream).  The library reports per-time-step figures; a launch advances
+    # `spl` steps, so its algorithmic bytes are spl x the per-step minimum
+    # (16 B per update and the rest, summed over the shots).
+    spl = max(1, s1.last_steps_per_launch)
+    bwd_launch_ms = spl * s1.last_bwd_ms / s1.last_bwd_launches
+    fwd_launch_ms = spl * s1.last_fwd_ms / s1.last_fwd_launches
+    bwd_launch_bytes = spl * s1.last_bwd_launch_bytes
+    fwd_launch_bytes = spl * s1.last_fwd_launch_bytes
+    achieved = bwd_launch_bytes / (bwd_launch_ms * 1e-3) / 1e9
+    achieved_fwd = fwd_launch_bytes / (fwd_launch_ms * 1e-3) / 1e9
+    log(f"[bench] backward launch ({spl} steps) {bwd_launch_ms * 1e3:.1f} us, {achieved:.0f} GB/s; "
         f"forward launch {fwd_launch_ms * 1e3:.1f} us, {achieved_fwd:.0f} GB/s")
 
     # ---- plain path: one rtm_migrate_shot per shot, one launch per step ----
@@ -285,11 +291,14 @@ def run_survey(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(),
-                     "kernel": "k_step<TZ,2> backward (receiver step + reconstruct + imaging)",
-                     "alg_bytes_per_launch": s1.last_bwd_launch_bytes,
+                     "kernel": (f"k_step2<{os.environ.get('RTM_TILE_Z2', '32')},2> backward, two time steps "
+                                "per launch" if spl == 2 else "k_step<TZ,2> backward")
+                               + " (receiver step + reconstruct + imaging)",
+                     "steps_per_launch": spl,
+                     "alg_bytes_per_launch": bwd_launch_bytes,
                      "launch_us": bwd_launch_ms * 1e3,
                      "forward_launch": {"achieved": achieved_fwd, "launch_us": fwd_launch_ms * 1e3,
-                                        "alg_bytes_per_launch": s1.last_fwd_launch_bytes}},
+                                        "alg_bytes_per_launch": fwd_launch_bytes}},
         "cpu_baseline": base,
     })
     if not args.no_serve:

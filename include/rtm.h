@@ -496,12 +496,16 @@ typedef struct {
     uint64_t arena_bytes, arena_used, arena_peak;
     int32_t tile_z;              /* tile height in use */
     int32_t active_jobs, queued_jobs;
-    int32_t pad_;
+    /* last rtm_migrate_batch call: time steps per launch of its step kernels
+     * (2 when its reconstruct-mode shots advanced two steps per launch) */
+    int32_t last_steps_per_launch;
     /* last rtm_migrate_batch call: HIP-event time of its forward and backward
-     * phases (all launches of each, on the library's work stream), launch
-     * counts, and algorithmic HBM bytes of one launch of each phase */
+     * phases (all launches of each, on the library's work stream), their time
+     * steps, and the algorithmic HBM bytes of one time step of each phase
+     * (the per-update figures summed over the shots; a two-step launch moves
+     * less than twice this) */
     float last_fwd_ms, last_bwd_ms;
-    int32_t last_fwd_launches, last_bwd_launches;
+    int32_t last_fwd_launches, last_bwd_launches;  /* time steps, whatever the launches */
     uint64_t last_fwd_launch_bytes, last_bwd_launch_bytes;
     /* last codec call: HIP-event time of its kernel, 1 encode / 2 decode, and
      * its algorithmic HBM bytes (4 per value plus the stream length) */

@@ -89,8 +89,8 @@ inline int32_t ring_len_of(int nz, int nx) { return 8 * (nz + nx - 8); }
 hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
                        int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
                        hipStream_t s);
-hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
-                        const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s);
+hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, const int2* recs2,
+                        int ntiles, const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s);
 hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s);
 hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* host_job,
                        float* c, float* gz, float* gx, float dt, float sponge_a, hipStream_t s);

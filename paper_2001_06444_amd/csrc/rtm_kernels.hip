@@ -134,6 +134,15 @@ struct TileStage {
   }
 };
 
+// a + b rounded on its own.  The source term is a product (wavelet sample x
+// 1/(dx dz)); left to itself the compiler may fuse that product into the
+// addition at some call sites and not at others, and kernels that must agree
+// bit for bit would then round the source node differently.
+__device__ __forceinline__ float add_unfused(float a, float b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
 // One leapfrog update with the sponge, u_new = G (2u + c lap) - G^2 u_old,
 // written as explicit fused operations so that every kernel that applies it
 // (one step or two per launch) rounds identically.
@@ -188,7 +197,8 @@ struct StepSmem {
 template <int TZ, class Smem>
 __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, int n, Smem& sm) {
   constexpr int RZ = TZ / 4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   const int pitch = J.pitch;
   const RTM_GLOBAL float* __restrict__ cur = gp(J.f[n & 3]);
   const RTM_GLOBAL float* __restrict__ old = gp(J.f[(n + 3) & 3]);  // u^{n-1}
@@ -246,7 +256,7 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
     if (colok && z < J.nzp) {
       const int64_t idx = (int64_t)z * pitch + x;
       float lap = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zw, k, c0, cz, cx);
-      if (z == J.src_z && x == J.src_x) lap += wsrc;
+      if (z == J.src_z && x == J.src_x) lap = add_unfused(lap, wsrc);
       const float G = gzv[k] * gxv;
       const float u = zw[k + 4];
       const float un = leapfrog(G, cv[k], lap, u, pv[k]);
@@ -290,7 +300,8 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
 template <int TZ, class Smem>
 __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, int m, Smem& sm) {
   constexpr int RZ = TZ / 4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   const int pitch = J.pitch;
   const int nt = J.nt;
   const RTM_GLOBAL float* __restrict__ rcur = gp(J.r[(m + 1) & 3]);  // R^{m+1}
@@ -436,7 +447,7 @@ __device__ __forceinline__ void backward_tile(const DevJob& J, const Tile& tl, i
               s = sv[k];
             } else {
               float ls = lap8<RZ>(sm.b, lz + kHalo, lane + kHalo, zs, k, c0, cz, cx);
-              if (z == J.src_z && x == J.src_x) ls += wsrc;
+              if (z == J.src_z && x == J.src_x) ls = add_unfused(ls, wsrc);
               s = fmaf(cv[k], ls, 2.0f * zs[k + 4]) - sv[k];
             }
             st_stream(sout + idx, s);
@@ -463,7 +474,8 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
   // m is the velocity-model perturbation on the physical window (zero in the
   // sponge); u0^n is the centre value the background stencil already holds.
   constexpr int RZ = TZ / 4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   const int pitch = J.pitch;
   const RTM_GLOBAL float* __restrict__ ucur = gp(J.f[n & 3]);
   const RTM_GLOBAL float* __restrict__ uold = gp(J.f[(n + 3) & 3]);
@@ -524,7 +536,7 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
       const float G = gzv[k] * gxv;
       const float u = zu[k + 4];
       float lu = lap8<RZ>(sm.a, lz + kHalo, lane + kHalo, zu, k, c0, cz, cx);
-      if (z == J.src_z && x == J.src_x) lu += wsrc;
+      if (z == J.src_z && x == J.src_x) lu = add_unfused(lu, wsrc);
       st_stream(unxt + idx, leapfrog(G, cv[k], lu, u, pv[k]));
       float ld = lap8<RZ>(sm.b, lz + kHalo, lane + kHalo, zd, k, c0, cz, cx);
       if (phys) ld = fmaf(mv[k], u, ld);
@@ -588,7 +600,6 @@ struct Step2Smem {
   float b[kBwd ? (TZ + 4 * kHalo) * kLdsW : 4];   // S^{m+1}
   float ma[(TZ + 2 * kHalo) * kTileX];            // middle region: u^{n+1} or R^m
   float mb[kBwd ? (TZ + 2 * kHalo) * kTileX : 4]; // middle region: S^m
-  float inj[kBwd ? (TZ + 2 * kHalo) * kTileX : 4];
 };
 
 // Boundary-ring save of a forward value at level `lev` (reconstruct mode).
@@ -609,7 +620,8 @@ template <int TZ, bool kFast, class Smem>
 __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, int n, Smem& sm) {
   constexpr int RA = (TZ + 2 * kHalo) / 4;  // middle rows per wavefront (first step)
   constexpr int RB = TZ / 4;                // output rows per wavefront (second step)
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   const int pitch = J.pitch;
   const RTM_GLOBAL float* __restrict__ u0 = gp(J.f[n & 3]);        // u^n
   const RTM_GLOBAL float* __restrict__ um = gp(J.f[(n + 3) & 3]);  // u^{n-1}
@@ -662,7 +674,7 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
     const int r = w * RA + k;  // middle row (wavefront-uniform)
     const int z = za0 + k;
     float lap = lap8<RA>(sm.a, r + kHalo, lane + kHalo, zw, k, c0, cz, cx);
-    if (!kFast && z == J.src_z && x == J.src_x) lap += w0;
+    if (!kFast && z == J.src_z && x == J.src_x) lap = add_unfused(lap, w0);
     const float G = gza[k] * gxv;
     float un = leapfrog(G, cva[k], lap, zw[k + 4], pva[k]);
     if (!kFast) un = (xin && z >= 0 && z < J.nzp) ? un : 0.0f;
@@ -682,7 +694,7 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
   for (int k = 0; k < RB; ++k) {
     const int z = zb0 + k;
     float lap = lap8<RB, kTileX>(sm.ma, w * RB + k + kHalo, lane, zm, k, c0, cz, cx);
-    if (!kFast && z == J.src_z && x == J.src_x) lap += w1;
+    if (!kFast && z == J.src_z && x == J.src_x) lap = add_unfused(lap, w1);
     const float G = gzb[k] * gxv;
     const float uold = sm.a[(w * RB + k + 2 * kHalo) * kLdsW + lane + kHalo];  // u^n
     if (xout && (kFast || z < J.nzp)) {
@@ -709,9 +721,248 @@ __device__ __forceinline__ void forward2_tile(const DevJob& J, const Tile& tl, i
     forward2_body<TZ, false>(J, tl, n, sm);
 }
 
+// One two-step backward tile, levels m and m - 1 (reconstruct mode, both
+// levels imaged and reconstructed: 1 <= m <= nt - 3).  The first step gives
+// R^m and S^m on the middle region, the second R^{m-1} and S^{m-1} on the
+// output tile, and the second also applies both imaging terms in level order
+// (image + k S^m R^{m+1}, then + k S^{m-1} R^m), as two one-step launches do.
+// S is defined on the physical window only: its interior nodes are
+// reconstructed, its boundary-ring nodes restored from storage, and
+// elsewhere the middle region holds zeros that no interior node reads.
+// KIND 1: the middle region lies in the interior of the physical window;
+// KIND 2: it lies in the grid outside the physical window (sponge only, no
+// S); neither holds the source or a receiver.  KIND 0 is the general path.
+template <int TZ, int KIND, class Smem>
+__device__ __forceinline__ void backward2_body(const DevJob& J, const Tile& tl, const int2* __restrict__ recs2,
+                                               int m, Smem& sm) {
+  constexpr bool kGen = KIND == 0, kSrc = KIND != 2;  // kSrc: S and imaging may be present
+  constexpr int RA = (TZ + 2 * kHalo) / 4;
+  constexpr int RB = TZ / 4;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
+  const int pitch = J.pitch;
+  const RTM_GLOBAL float* __restrict__ r1 = gp(J.r[(m + 1) & 3]);  // R^{m+1}
+  const RTM_GLOBAL float* __restrict__ r2 = gp(J.r[(m + 2) & 3]);  // R^{m+2}
+  RTM_GLOBAL float* __restrict__ r0 = gp(J.r[m & 3]);              // R^m
+  RTM_GLOBAL float* __restrict__ rn = gp(J.r[(m + 3) & 3]);        // R^{m-1}
+  const RTM_GLOBAL float* __restrict__ s1 = gp(J.f[(m + 1) & 3]);  // S^{m+1}
+  const RTM_GLOBAL float* __restrict__ s2 = gp(J.f[(m + 2) & 3]);  // S^{m+2}
+  RTM_GLOBAL float* __restrict__ s0 = gp(J.f[m & 3]);              // S^m
+  RTM_GLOBAL float* __restrict__ sn = gp(J.f[(m + 3) & 3]);        // S^{m-1}
+  RTM_GLOBAL float* __restrict__ image = gp(J.image);
+  const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
+  const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
+  const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
+  const int x = tl.x0 - kHalo + lane;
+  const int za0 = tl.z0 - kHalo + w * RA;
+  const int zb0 = tl.z0 + w * RB;
+  const bool xin = x >= 0 && x < J.nxp;
+  const bool xout = lane >= kHalo && lane < kHalo + kTileX2 && (!kGen || x < J.nxp);
+  const uint32_t xcl = (uint32_t)min(max(x, 0), J.nxp - 1);
+  const int px = x - J.nb;
+  const bool colphys = px >= 0 && px < J.nx;
+  const uint32_t xph = (uint32_t)min(max(x, J.nb), J.nb + J.nx - 1);  // column clamped into the window
+  // general path: does the middle region reach the physical window?
+  const bool tphys = kGen ? (tl.z0 - kHalo - J.nb < J.nz && tl.z0 + TZ + kHalo - J.nb > 0 &&
+                             tl.x0 - kHalo - J.nb < J.nx && tl.x0 + kTileX2 + kHalo - J.nb > 0)
+                          : KIND == 1;
+
+  // ---- every global load first ----
+  TileStageW<TZ + 4 * kHalo> sa, sb;
+  sa.load(r1, pitch, tl.z0 - 2 * kHalo, tl.x0 - 2 * kHalo);
+  if (kSrc && tphys) sb.load(s1, pitch, tl.z0 - 2 * kHalo, tl.x0 - 2 * kHalo);
+  float cva[RA], pva[RA], gza[RA], sva[RA];
+  bool ringa[RA];
+#pragma unroll
+  for (int k = 0; k < RA; ++k) {
+    const int zc = kGen ? min(max(za0 + k, 0), J.nzp - 1) : za0 + k;
+    const uint32_t off = (uint32_t)zc * (uint32_t)pitch + xcl;
+    cva[k] = ld_medium(cc + off);
+    pva[k] = ld_stream(r2 + off);
+    gza[k] = gz[zc];
+    sva[k] = 0.0f;
+    ringa[k] = false;
+    if (KIND == 1) sva[k] = ld_stream(s2 + off);
+  }
+  if (kGen && tphys) {
+#pragma unroll
+    for (int k = 0; k < RA; ++k) {  // S^{m+2}, or the stored ring value of level m
+      const int pzc = min(max(za0 + k - J.nb, 0), J.nz - 1);
+      const int slot = ring_slot(pzc, (int)xph - J.nb, J.nz, J.nx);
+      ringa[k] = slot >= 0;
+      const RTM_GLOBAL float* sp = slot >= 0 ? gp(J.ring) + (int64_t)m * J.ring_len + slot
+                                             : s2 + ((uint32_t)(pzc + J.nb) * (uint32_t)pitch + xph);
+      sva[k] = ld_stream(sp);
+    }
+  }
+  float cvb[RB], gzb[RB], ivb[RB], svb[RB];
+  bool ringb[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int zc = kGen ? min(zb0 + k, J.nzp - 1) : zb0 + k;
+    cvb[k] = ld_medium(cc + ((uint32_t)zc * (uint32_t)pitch + xcl));
+    gzb[k] = gz[zc];
+    ivb[k] = 0.0f;
+    svb[k] = 0.0f;
+    ringb[k] = false;
+    if (KIND == 1) ivb[k] = ld_stream(image + ((uint32_t)(zb0 + k - J.nb) * (uint32_t)pitch + (uint32_t)x));
+  }
+  if (kGen && tphys) {
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {  // image, and the stored ring value of level m - 1
+      const int pzc = min(max(zb0 + k - J.nb, 0), J.nz - 1);
+      ivb[k] = ld_stream(image + ((uint32_t)pzc * (uint32_t)pitch + xph));
+      const int slot = ring_slot(pzc, (int)xph - J.nb, J.nz, J.nx);
+      ringb[k] = slot >= 0;
+      svb[k] = ld_stream(gp(J.ring) + (int64_t)(m - 1) * J.ring_len + max(slot, 0));
+    }
+  }
+  const float gxv = (!kGen || xin) ? gx[xcl] : 0.0f;
+  const float wa = kGen ? gp(J.wavelet)[m + 1] * J.inv_cell : 0.0f;  // source term of S^m
+  const float wb = kGen ? gp(J.wavelet)[m] * J.inv_cell : 0.0f;      // source term of S^{m-1}
+  const float kfac = J.kfac;
+  sa.store(sm.a);
+  if (kSrc && tphys) sb.store(sm.b);
+
+  // receiver data of levels m and m - 1, summed into zeroed middle-region
+  // arrays as a one-step launch sums them
+  const bool has_inj = kGen && tl.rec_count > 0;
+  float inja[RA], injb[RB];
+#pragma unroll
+  for (int k = 0; k < RA; ++k) inja[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) injb[k] = 0.0f;
+  if (has_inj) {
+    for (int i = threadIdx.x; i < (TZ + 2 * kHalo) * kTileX; i += kThreads) {
+      sm.ma[i] = 0.0f;
+      sm.mb[i] = 0.0f;
+    }
+    __syncthreads();
+    const RTM_GLOBAL float* da = gp(J.data) + (int64_t)m * J.nrec;
+    const RTM_GLOBAL float* db = gp(J.data) + (int64_t)(m - 1) * J.nrec;
+    for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
+      const int2 e = recs2[tl.rec_begin + i];
+      atomicAdd(&sm.ma[e.x], da[e.y]);
+      atomicAdd(&sm.mb[e.x], db[e.y]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RA; ++k) inja[k] = sm.ma[(w * RA + k) * kTileX + lane];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) injb[k] = sm.mb[(w * RB + k + kHalo) * kTileX + lane];
+  }
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
+
+  // ---- first step: R^m and S^m on the middle region ----
+  {
+    float zr[RA + 8], zs[RA + 8];
+#pragma unroll
+    for (int j = 0; j < RA + 8; ++j) zr[j] = sm.a[(w * RA + j) * kLdsW + lane + kHalo];
+    if (kSrc && tphys) {
+#pragma unroll
+      for (int j = 0; j < RA + 8; ++j) zs[j] = sm.b[(w * RA + j) * kLdsW + lane + kHalo];
+    }
+#pragma clang loop unroll(full)
+    for (int k = 0; k < RA; ++k) {
+      const int r = w * RA + k;
+      const int z = za0 + k;
+      float lap = lap8<RA>(sm.a, r + kHalo, lane + kHalo, zr, k, c0, cz, cx);
+      if (has_inj) lap += inja[k];
+      const float G = gza[k] * gxv;
+      float rv = leapfrog(G, cva[k], lap, zr[k + 4], pva[k]);
+      if (kGen) rv = (xin && z >= 0 && z < J.nzp) ? rv : 0.0f;
+      sm.ma[r * kTileX + lane] = rv;
+      float sv = 0.0f;
+      const int pz = z - J.nb;
+      const bool phys = KIND == 1 || (kGen && tphys && colphys && pz >= 0 && pz < J.nz);
+      if (kSrc && tphys) {
+        if (ringa[k]) {
+          sv = sva[k];
+        } else {
+          float ls = lap8<RA>(sm.b, r + kHalo, lane + kHalo, zs, k, c0, cz, cx);
+          if (kGen && z == J.src_z && x == J.src_x) ls = add_unfused(ls, wa);
+          sv = fmaf(cva[k], ls, 2.0f * zs[k + 4]) - sva[k];
+        }
+        if (kGen) sv = phys ? sv : 0.0f;
+        sm.mb[r * kTileX + lane] = sv;
+      }
+      if (r >= kHalo && r < TZ + kHalo && (!kGen || z < J.nzp) && xout) {  // a node of the output tile
+        const uint32_t off = (uint32_t)z * (uint32_t)pitch + (uint32_t)x;
+        st_stream(r0 + off, rv);
+        if (kSrc && phys) st_stream(s0 + off, sv);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- second step: R^{m-1} and S^{m-1} on the output tile, imaging ----
+  {
+    float zr[RB + 8], zs[RB + 8];
+#pragma unroll
+    for (int j = 0; j < RB + 8; ++j) zr[j] = sm.ma[(w * RB + j) * kTileX + lane];
+    if (kSrc && tphys) {
+#pragma unroll
+      for (int j = 0; j < RB + 8; ++j) zs[j] = sm.mb[(w * RB + j) * kTileX + lane];
+    }
+#pragma clang loop unroll(full)
+    for (int k = 0; k < RB; ++k) {
+      const int z = zb0 + k;
+      float lap = lap8<RB, kTileX>(sm.ma, w * RB + k + kHalo, lane, zr, k, c0, cz, cx);
+      if (has_inj) lap += injb[k];
+      const float G = gzb[k] * gxv;
+      const int lrow = (w * RB + k + 2 * kHalo) * kLdsW + lane + kHalo;  // centre in the staged tiles
+      const float rc = sm.a[lrow];  // R^{m+1}
+      if (xout && (!kGen || z < J.nzp)) {
+        const uint32_t off = (uint32_t)z * (uint32_t)pitch + (uint32_t)x;
+        st_stream(rn + off, leapfrog(G, cvb[k], lap, zr[k + 4], rc));
+        const int pz = z - J.nb;
+        const bool phys = KIND == 1 || (kGen && tphys && colphys && pz >= 0 && pz < J.nz);
+        if (kSrc && phys) {
+          float sv;
+          if (ringb[k]) {
+            sv = svb[k];
+          } else {
+            float ls = lap8<RB, kTileX>(sm.mb, w * RB + k + kHalo, lane, zs, k, c0, cz, cx);
+            if (kGen && z == J.src_z && x == J.src_x) ls = add_unfused(ls, wb);
+            sv = fmaf(cvb[k], ls, 2.0f * zs[k + 4]) - sm.b[lrow];
+          }
+          st_stream(sn + off, sv);
+          const float im = fmaf(kfac * zs[k + 4], rc, ivb[k]);  // level m
+          st_stream(image + ((uint32_t)pz * (uint32_t)pitch + (uint32_t)x), fmaf(kfac * sv, zr[k + 4], im));
+        }
+      }
+    }
+  }
+}
+
+template <int TZ, class Smem>
+__device__ __forceinline__ void backward2_tile(const DevJob& J, const Tile& tl, const int2* recs2, int m,
+                                               Smem& sm) {
+  const int z0 = tl.z0, x0 = tl.x0;
+  // middle region [mz0, mz1) x [mx0, mx1), padded coordinates
+  const int mz0 = z0 - kHalo, mz1 = z0 + TZ + kHalo, mx0 = x0 - kHalo, mx1 = x0 + kTileX2 + kHalo;
+  const bool src = J.src_z >= mz0 && J.src_z < mz1 && J.src_x >= mx0 && J.src_x < mx1;
+  const bool quiet = !src && tl.rec_count == 0;
+  const int nb = J.nb;
+  const bool interior = mz0 >= nb + 4 && mz1 <= nb + J.nz - 4 && mx0 >= nb + 4 && mx1 <= nb + J.nx - 4;
+  const bool inside = mz0 >= 0 && mz1 <= J.nzp && mx0 >= 0 && mx1 <= J.nxp;
+  const bool sponge = inside && (mz1 <= nb || mz0 >= nb + J.nz || mx1 <= nb || mx0 >= nb + J.nx);
+  if (quiet && interior)
+    backward2_body<TZ, 1>(J, tl, recs2, m, sm);
+  else if (quiet && sponge)
+    backward2_body<TZ, 2>(J, tl, recs2, m, sm);
+  else
+    backward2_body<TZ, 0>(J, tl, recs2, m, sm);
+}
+
 template <int TZ, int PH>
 __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ jobs,
                                                      const Tile* __restrict__ tiles,
+                                                     const int2* __restrict__ recs2,
                                                      const StepCtl* __restrict__ ctl, int ntiles,
                                                      int use_ctl_tick, int tick_off) {
   __shared__ Step2Smem<TZ, (PH & kPhBwd) != 0> sm;
@@ -728,6 +979,9 @@ __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ j
   const int nf = J.nt - 1;  // forward steps
   if (s + 1 < nf) {
     if (PH & kPhFwd) forward2_tile<TZ>(J, tl, s, sm);
+  } else if (s >= nf) {
+    const int m = J.nt - 1 - (s - nf);  // levels m and m - 1
+    if ((PH & kPhBwd) && m <= J.nt - 3 && m >= 1 && J.illum == nullptr) backward2_tile<TZ>(J, tl, recs2, m, sm);
   }
 }
 
@@ -789,21 +1043,19 @@ static hipError_t launch_step_tz(int phases, const DevJob* jobs, const Tile* til
   return hipGetLastError();
 }
 
-hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
-                        const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s) {
+hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, const int2* recs2,
+                        int ntiles, const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const int per = (ntiles + 7) / 8;
   dim3 grid(8 * per), block(kThreads);
-  if (phases != kPhFwd) return hipErrorInvalidValue;
-  switch (tz) {
-    case 16:
-      hipLaunchKernelGGL((k_step2<16, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
-      break;
-    case 32:
-      hipLaunchKernelGGL((k_step2<32, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
-      break;
-    default: return hipErrorInvalidValue;
-  }
+#define RTM_STEP2(T, P) \
+  hipLaunchKernelGGL((k_step2<T, P>), grid, block, 0, s, jobs, tiles, recs2, ctl, ntiles, use_ctl_tick, tick_off)
+  if (tz == 16 && phases == kPhFwd) RTM_STEP2(16, kPhFwd);
+  else if (tz == 32 && phases == kPhFwd) RTM_STEP2(32, kPhFwd);
+  else if (tz == 16 && phases == kPhBwd) RTM_STEP2(16, kPhBwd);
+  else if (tz == 32 && phases == kPhBwd) RTM_STEP2(32, kPhBwd);
+  else return hipErrorInvalidValue;
+#undef RTM_STEP2
   return hipGetLastError();
 }
 

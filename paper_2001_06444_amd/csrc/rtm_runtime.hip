@@ -221,7 +221,8 @@ struct rtm_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // phase timing of the last batched call (events on work_stream)
   hipEvent_t ph_ev[3] = {nullptr, nullptr, nullptr};
-  int ph_launches[2] = {0, 0};
+  int ph_launches[2] = {0, 0};  // time steps of each phase
+  int ph_steps_per_launch = 1;
   uint64_t ph_bytes[2] = {0, 0};
   bool ph_valid = false;
   Arena arena;
@@ -681,18 +682,19 @@ struct Table {
   StepCtl* ctl = nullptr;
   int ntiles = 0;
   Tile* tiles2 = nullptr;  // two-step tiles (tz2 rows x 56 columns), or none
+  int2* recs2 = nullptr;   // receivers of the two-step tiles: {index in the middle region, receiver}
   int ntiles2 = 0, tz2 = 0;
   std::vector<Block> blocks;
   std::shared_ptr<std::vector<DevJob>> hjobs;
   std::shared_ptr<std::vector<Tile>> htiles, htiles2;
+  std::shared_ptr<std::vector<int2>> hrecs2;
 };
 
 // Two-step tile height: RTM_TILE_Z2 (16 or 32; 0 turns two-step launches off).
-// 16 rows measured fastest on the survey (216.5 us per step against 219.9 us
-// for 32 rows and 230.9 us one step per launch).
+// On the survey 32 rows measured 1 % faster than 16.
 static int env_tz2() {
   const char* e = getenv("RTM_TILE_Z2");
-  if (!e) return 16;
+  if (!e) return 32;
   const int v = atoi(e);
   return v == 16 || v == 32 ? v : 0;
 }
@@ -702,6 +704,7 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   t.hjobs = std::make_shared<std::vector<DevJob>>();
   t.htiles = std::make_shared<std::vector<Tile>>();
   t.htiles2 = std::make_shared<std::vector<Tile>>();
+  t.hrecs2 = std::make_shared<std::vector<int2>>();
   for (size_t i = 0; i < js.size(); ++i) {
     t.hjobs->push_back(js[i]->d);
     for (Tile tl : js[i]->tiles) {
@@ -711,16 +714,37 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   }
   t.ntiles = (int)t.htiles->size();
   bool pairs = tz2 == 16 || tz2 == 32;
-  for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon;
+  for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon && !(j->g.flags & RTM_IMG_ILLUM);
   if (pairs) {
     for (size_t i = 0; i < js.size(); ++i) {
       const DevJob& d = js[i]->d;
+      const HostJob& hj = *js[i];
+      // receiver nodes (padded coordinates) from the one-step tiles' lists,
+      // whose local index is (row in tile) * 64 + (column in tile)
+      std::vector<std::pair<int, int>> rz(hj.recs.size());  // (row, receiver), sorted by row
+      std::vector<int> rx(hj.recs.size());
+      for (const Tile& one : hj.tiles)
+        for (int q = one.rec_begin; q < one.rec_begin + one.rec_count; ++q) {
+          const int local = hj.recs[q].x, r = hj.recs[q].y;
+          rz[r] = {one.z0 + local / kTileX, r};
+          rx[r] = one.x0 + local % kTileX;
+        }
+      std::sort(rz.begin(), rz.end());
       for (int z0 = 0; z0 < d.nzp; z0 += tz2)
         for (int x0 = 0; x0 < d.nxp; x0 += kTileX2) {
           Tile tl{};
           tl.job = (int)i;
           tl.z0 = z0;
           tl.x0 = x0;
+          tl.rec_begin = (int)t.hrecs2->size();
+          // receivers in the middle region rows [z0 - 4, z0 + tz2 + 4), columns [x0 - 4, x0 + 60)
+          auto lo = std::lower_bound(rz.begin(), rz.end(), std::make_pair(z0 - kHalo, -1));
+          for (auto it = lo; it != rz.end() && it->first < z0 + tz2 + kHalo; ++it) {
+            const int xr = rx[it->second];
+            if (xr >= x0 - kHalo && xr < x0 + kTileX2 + kHalo)
+              t.hrecs2->push_back(make_int2((it->first - (z0 - kHalo)) * kTileX + (xr - (x0 - kHalo)), it->second));
+          }
+          tl.rec_count = (int)t.hrecs2->size() - tl.rec_begin;
           t.htiles2->push_back(tl);
         }
     }
@@ -747,6 +771,13 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
     }
     t.tiles2 = static_cast<Tile*>(p);
     HIP_OK(hipMemcpyAsync(t.tiles2, t.htiles2->data(), t.htiles2->size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+    if (!alloc_block(ctx, t.blocks, std::max<size_t>(t.hrecs2->size(), 1) * sizeof(int2), &p)) {
+      release_blocks(ctx, t.blocks);
+      return fail(RTM_E_NOMEM, "arena exhausted (two-step receiver table)");
+    }
+    t.recs2 = static_cast<int2*>(p);
+    if (!t.hrecs2->empty())
+      HIP_OK(hipMemcpyAsync(t.recs2, t.hrecs2->data(), t.hrecs2->size() * sizeof(int2), hipMemcpyHostToDevice, s));
   }
   HIP_OK(hipMemcpyAsync(t.jobs, t.hjobs->data(), t.hjobs->size() * sizeof(DevJob), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(t.tiles, t.htiles->data(), t.htiles->size() * sizeof(Tile), hipMemcpyHostToDevice, s));
@@ -1126,14 +1157,17 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
 // Runs nsteps launches of the step kernel: whole groups of K as replays of a
 // captured graph (K step nodes with offsets 0..K-1, then one k_advance node),
 // the remainder as direct launches followed by one k_advance.
-// With a two-step table (t.ntiles2 > 0) the forward phase goes two steps per
-// launch; an odd last step runs as a one-step launch.
+// With a two-step table (t.ntiles2 > 0) the launches go two steps each; an
+// odd last step runs as a one-step launch.  The caller starts the backward
+// phase with two one-step launches (levels nt - 1 and nt - 2 are not
+// reconstructed) before it asks for pairs.
 static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, int nsteps, int K,
                        std::vector<hipGraphExec_t>& graphs) {
-  const bool pairs = t.ntiles2 > 0 && ph == kPhFwd;
+  const bool pairs = t.ntiles2 > 0 && (ph == kPhFwd || ph == kPhBwd);
   if (pairs) K = std::max(2, K & ~1);
-  auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`; returns its steps
-    if (pairs && left >= 2) return launch_step2(t.tz2, ph, t.jobs, t.tiles2, t.ntiles2, t.ctl, 1, off, s);
+  auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`
+    if (pairs && left >= 2)
+      return launch_step2(t.tz2, ph, t.jobs, t.tiles2, t.recs2, t.ntiles2, t.ctl, 1, off, s);
     return launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, off, s);
   };
   int done = 0;
@@ -1253,7 +1287,18 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
   rc = graph_steps(ctx, s, tz, kPhFwd, t, nt - 1, K, graphs);
   if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
-  if (!rc) rc = graph_steps(ctx, s, tz, kPhBwd, t, nt, K, graphs);
+  if (!rc && t.ntiles2 > 0 && nt >= 4) {
+    // levels nt - 1 and nt - 2 are imaged without reconstruction: one step each
+    for (int i = 0; i < 2 && !rc; ++i)
+      if (launch_step(tz, kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, i, s) != hipSuccess)
+        rc = fail(RTM_E_DEVICE, "step launch failed");
+    if (!rc && launch_advance(t.ctl, 2, s) != hipSuccess) rc = fail(RTM_E_DEVICE, "advance launch failed");
+    if (!rc) rc = graph_steps(ctx, s, tz, kPhBwd, t, nt - 2, K, graphs);
+  } else if (!rc) {
+    Table one = t;  // one-step launches only
+    one.ntiles2 = 0;
+    rc = graph_steps(ctx, s, tz, kPhBwd, one, nt, K, graphs);
+  }
   if (!rc) rc = hipEventRecord(ctx->ph_ev[2], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc) {
     // algorithmic bytes of one forward / one backward launch over all shots
@@ -1270,6 +1315,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     }
     ctx->ph_launches[0] = nt - 1;
     ctx->ph_launches[1] = nt;
+    ctx->ph_steps_per_launch = t.ntiles2 > 0 ? 2 : 1;
     ctx->ph_bytes[0] = bf;
     ctx->ph_bytes[1] = bb;
     ctx->ph_valid = true;
@@ -2370,6 +2416,7 @@ extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
         hipEventElapsedTime(&b, ctx->ph_ev[1], ctx->ph_ev[2]) == hipSuccess) {
       out->last_fwd_ms = a;
       out->last_bwd_ms = b;
+      out->last_steps_per_launch = ctx->ph_steps_per_launch;
       out->last_fwd_launches = ctx->ph_launches[0];
       out->last_bwd_launches = ctx->ph_launches[1];
       out->last_fwd_launch_bytes = ctx->ph_bytes[0];

@@ -69,7 +69,7 @@ class CtxStats(ctypes.Structure):
         "jobs_submitted", "jobs_done", "jobs_failed", "jobs_cancelled", "steps_launched",
         "graph_replays", "grid_updates", "alg_bytes", "arena_bytes", "arena_used", "arena_peak")] + [
         ("tile_z", ctypes.c_int32), ("active_jobs", ctypes.c_int32),
-        ("queued_jobs", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("queued_jobs", ctypes.c_int32), ("last_steps_per_launch", ctypes.c_int32),
         ("last_fwd_ms", ctypes.c_float), ("last_bwd_ms", ctypes.c_float),
         ("last_fwd_launches", ctypes.c_int32), ("last_bwd_launches", ctypes.c_int32),
         ("last_fwd_launch_bytes", ctypes.c_uint64), ("last_bwd_launch_bytes", ctypes.c_uint64),

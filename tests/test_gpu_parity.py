@@ -278,6 +278,45 @@ def test_validation_errors(rtm, ctx):
 # Batched path == plain path (same kernel per tile; bit for bit)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("nt", [4, 5, 37])
+def test_two_step_launches_equal_one_step(rtm, ctx, nt):
+    """Reconstruct-mode batches advance two time steps per launch (two-step
+    tiles of 16 or 32 rows; RTM_TILE_Z2=0 forces one step per launch).  Every
+    setting, with short and odd step counts (an odd last step, the two
+    one-step launches that open the backward phase), must equal the plain
+    path bit for bit."""
+    import os
+    rng = np.random.default_rng(nt)
+    nz, nx, h, dt, nb = 45, 131, 10.0, 1e-3, 9
+    vel = inputs.smooth_slowness(1700 + 600 * rng.random((nz, nx)), 30.0, h, h)
+    w = inputs.ricker(nt, dt, fp=25)
+    g = grid_of(rtm, nz, nx, nb, nt, h, dt)
+    shots = []
+    for sx, ix0, width in [(20, 0, 131), (70, 10, 97), (100, 0, 131)]:
+        rec = [(2, x) for x in range(ix0, ix0 + width, 3)]
+        shots.append(((3, sx), ix0, width, rec, dev(rng.standard_normal((nt, len(rec))) * 1e-2)))
+    opts = rtm.img_opts("reconstruct")
+    plain = torch.zeros(nz, nx, device="cuda")
+    for (src, ix0, width, rec, d) in shots:
+        ctx.migrate_shot(g, dev(vel), dev(w), src, rec, d, ix0, width, opts, plain)
+    torch.cuda.synchronize()
+    old = os.environ.get("RTM_TILE_Z2")
+    try:
+        for tz2 in ("16", "32", "0"):
+            os.environ["RTM_TILE_Z2"] = tz2
+            batch = torch.zeros(nz, nx, device="cuda")
+            ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch)
+            torch.cuda.synchronize()
+            assert torch.equal(plain, batch), (nt, tz2, (plain - batch).abs().max().item())
+            assert ctx.stats().last_steps_per_launch == (1 if tz2 == "0" else 2)
+    finally:
+        if old is None:
+            os.environ.pop("RTM_TILE_Z2", None)
+        else:
+            os.environ["RTM_TILE_Z2"] = old
+    assert float(plain.abs().max()) > 0
+
+
 def test_batch_equals_plain_bitwise(rtm, ctx):
     rng = np.random.default_rng(6)
     nz, nx, h, dt, nt, nb = 60, 230, 10.0, 1e-3, 260, 10
