@@ -102,6 +102,7 @@ struct JobGeom {
   int snap_dtype = 0, snap_stride = 1;
   uint32_t flags = 0;
   int nrec = 0;
+  int nbuf = 2;  // buffers per wavefield: 4 for jobs that take two-step launches
 };
 
 static int snap_bytes(int dtype) { return dtype == RTM_SNAP_FP32 ? 4 : 2; }
@@ -117,8 +118,8 @@ static Footprint footprint(const JobGeom& g) {
   f.field = align256((size_t)field_floats(nzp, nxp) * 4);
   size_t t = 0;
   t += f.field;                                  // c
-  t += 4 * f.field;                              // f[4]
-  if (g.mode != kModeModel) t += 4 * f.field;    // r[4]
+  t += g.nbuf * f.field;                             // f
+  if (g.mode != kModeModel) t += g.nbuf * f.field;   // r
   t += align256((size_t)nzp * 4) + align256((size_t)nxp * 4);
   if (g.mode != kModeModel) {
     t += align256((size_t)g.nz * field_pitch(nxp) * 4);  // image (field-aligned rows)
@@ -464,9 +465,12 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   float* cbuf = medium ? nullptr : static_cast<float*>(A(F));
   float* fb[4] = {nullptr, nullptr, nullptr, nullptr};
   float* rb[4] = {nullptr, nullptr, nullptr, nullptr};
-  for (int k = 0; k < 4; ++k) fb[k] = static_cast<float*>(A(F));
+  // Level n lives in buffer n & 3.  A job that only takes one-step launches
+  // needs two buffers: slots 2 and 3 then alias slots 0 and 1.
+  const int nbuf = g.nbuf == 4 ? 4 : 2;
+  for (int k = 0; k < nbuf; ++k) fb[k] = static_cast<float*>(A(F));
   if (g.mode != kModeModel)
-    for (int k = 0; k < 4; ++k) rb[k] = static_cast<float*>(A(F));
+    for (int k = 0; k < nbuf; ++k) rb[k] = static_cast<float*>(A(F));
   float* gz = medium ? nullptr : static_cast<float*>(A((size_t)nzp * 4));
   float* gx = medium ? nullptr : static_cast<float*>(A((size_t)nxp * 4));
   float* illum = nullptr;
@@ -496,8 +500,9 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
   d.gz = medium ? medium->d.gz : gz;
   d.gx = medium ? medium->d.gx : gx;
   for (int k = 0; k < 4; ++k) {
-    d.f[k] = fb[k] + org;
-    if (rb[k]) d.r[k] = rb[k] + org;
+    const int b = k % nbuf;
+    d.f[k] = fb[b] + org;
+    if (rb[b]) d.r[k] = rb[b] + org;
   }
   d.wavelet = wavelet;
   d.data = data;
@@ -546,7 +551,7 @@ static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, cons
 
   // ---- device set-up ----
   const size_t fbytes = (size_t)field_floats(nzp, nxp) * 4;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < nbuf; ++k) {
     HIP_OK(hipMemsetAsync(fb[k], 0, fbytes, s));
     if (rb[k]) HIP_OK(hipMemsetAsync(rb[k], 0, fbytes, s));
   }
@@ -714,7 +719,7 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   }
   t.ntiles = (int)t.htiles->size();
   bool pairs = tz2 == 16 || tz2 == 32;
-  for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon && !(j->g.flags & RTM_IMG_ILLUM);
+  for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon && !(j->g.flags & RTM_IMG_ILLUM) && j->g.nbuf == 4;
   if (pairs) {
     for (size_t i = 0; i < js.size(); ++i) {
       const DevJob& d = js[i]->d;
@@ -1222,6 +1227,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (int i = 0; i < nshots; ++i) {
     if ((rc = fill_geom_rtm(grid, shots[i].ix0, shots[i].width, opts, shots[i].nrec, geoms[i]))) return rc;
     if (illum_dev) geoms[i].flags |= RTM_IMG_ILLUM;
+    if (geoms[i].mode == kModeRecon && !illum_dev && env_tz2() > 0) geoms[i].nbuf = 4;  // two-step launches
     if ((rc = check_job(geoms[i], shots[i].src, shots[i].rec_host))) return rc;
     if (shots[i].nrec > 0 && !shots[i].data_dev) return fail(RTM_E_INVAL, "shot %d has no data", i);
   }
