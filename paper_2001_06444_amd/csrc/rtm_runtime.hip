@@ -1162,13 +1162,13 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
 // Runs nsteps launches of the step kernel: whole groups of K as replays of a
 // captured graph (K step nodes with offsets 0..K-1, then one k_advance node),
 // the remainder as direct launches followed by one k_advance.
-// With a two-step table (t.ntiles2 > 0) the launches go two steps each; an
-// odd last step runs as a one-step launch.  The caller starts the backward
-// phase with two one-step launches (levels nt - 1 and nt - 2 are not
-// reconstructed) before it asks for pairs.
+// With `two_step` and a two-step table (t.ntiles2 > 0) the launches go two
+// steps each; an odd last step runs as a one-step launch.  The caller starts
+// the backward phase with two one-step launches (levels nt - 1 and nt - 2 are
+// not reconstructed) before it asks for pairs.
 static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, int nsteps, int K,
-                       std::vector<hipGraphExec_t>& graphs) {
-  const bool pairs = t.ntiles2 > 0 && (ph == kPhFwd || ph == kPhBwd);
+                       std::vector<hipGraphExec_t>& graphs, bool two_step) {
+  const bool pairs = two_step && t.ntiles2 > 0 && (ph == kPhFwd || ph == kPhBwd);
   if (pairs) K = std::max(2, K & ~1);
   auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`
     if (pairs && left >= 2)
@@ -1291,7 +1291,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   const int nt = grid->nt, K = graph_k();
   std::vector<hipGraphExec_t> graphs;
   HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
-  rc = graph_steps(ctx, s, tz, kPhFwd, t, nt - 1, K, graphs);
+  rc = graph_steps(ctx, s, tz, kPhFwd, t, nt - 1, K, graphs, true);
   if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc && t.ntiles2 > 0 && nt >= 4) {
     // levels nt - 1 and nt - 2 are imaged without reconstruction: one step each
@@ -1299,11 +1299,9 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
       if (launch_step(tz, kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, i, s) != hipSuccess)
         rc = fail(RTM_E_DEVICE, "step launch failed");
     if (!rc && launch_advance(t.ctl, 2, s) != hipSuccess) rc = fail(RTM_E_DEVICE, "advance launch failed");
-    if (!rc) rc = graph_steps(ctx, s, tz, kPhBwd, t, nt - 2, K, graphs);
+    if (!rc) rc = graph_steps(ctx, s, tz, kPhBwd, t, nt - 2, K, graphs, true);
   } else if (!rc) {
-    Table one = t;  // one-step launches only
-    one.ntiles2 = 0;
-    rc = graph_steps(ctx, s, tz, kPhBwd, one, nt, K, graphs);
+    rc = graph_steps(ctx, s, tz, kPhBwd, t, nt, K, graphs, false);  // one step per launch
   }
   if (!rc) rc = hipEventRecord(ctx->ph_ev[2], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc) {
@@ -1321,7 +1319,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     }
     ctx->ph_launches[0] = nt - 1;
     ctx->ph_launches[1] = nt;
-    ctx->ph_steps_per_launch = t.ntiles2 > 0 ? 2 : 1;
+    ctx->ph_steps_per_launch = t.ntiles2 > 0 && nt >= 4 ? 2 : 1;  // both phases ran pairs
     ctx->ph_bytes[0] = bf;
     ctx->ph_bytes[1] = bb;
     ctx->ph_valid = true;

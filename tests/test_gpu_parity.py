@@ -278,7 +278,7 @@ def test_validation_errors(rtm, ctx):
 # Batched path == plain path (same kernel per tile; bit for bit)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("nt", [4, 5, 37])
+@pytest.mark.parametrize("nt", [2, 3, 4, 5, 37])
 def test_two_step_launches_equal_one_step(rtm, ctx, nt):
     """Reconstruct-mode batches advance two time steps per launch (two-step
     tiles of 16 or 32 rows; RTM_TILE_Z2=0 forces one step per launch).  Every
@@ -308,13 +308,14 @@ def test_two_step_launches_equal_one_step(rtm, ctx, nt):
             ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch)
             torch.cuda.synchronize()
             assert torch.equal(plain, batch), (nt, tz2, (plain - batch).abs().max().item())
-            assert ctx.stats().last_steps_per_launch == (1 if tz2 == "0" else 2)
+            assert ctx.stats().last_steps_per_launch == (2 if tz2 != "0" and nt >= 4 else 1)
     finally:
         if old is None:
             os.environ.pop("RTM_TILE_Z2", None)
         else:
             os.environ["RTM_TILE_Z2"] = old
-    assert float(plain.abs().max()) > 0
+    if nt >= 4:  # nt = 2, 3 image only level 0, where S is still zero
+        assert float(plain.abs().max()) > 0
 
 
 def test_batch_equals_plain_bitwise(rtm, ctx):
