@@ -190,9 +190,12 @@ typedef struct {
     const float *data_dev;     /* [nt][nrec] */
 } rtm_shot_desc;
 
-/* Migrate nshots shots of one model together: every time step of every
- * shot advances in the same kernel launch, launches are replayed from a
- * captured HIP graph, and the tile shape comes from the autotuner.
+/* Migrate nshots shots of one model together: every shot advances in the
+ * same kernel launches, two time steps per launch in reconstruct mode
+ * without illumination (RTM_TILE_Z2 = 16 or 32 sets the two-step tile
+ * height, 0 keeps one step per launch; results are the same bit for bit),
+ * launches are replayed from a captured HIP graph, and the one-step tile
+ * shape comes from the autotuner.
  * Each shot's image is added into image_dev in shot order after all shots
  * finish (deterministic stack).  Shots with the same window (ix0, width)
  * share one c = v^2 dt^2 array and its sponge profiles, built once.  Same
