@@ -291,7 +291,7 @@ def run_survey(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(),
-                     "kernel": (f"k_step2<{os.environ.get('RTM_TILE_Z2', '32')},2> backward, two time steps "
+                     "kernel": (f"k_step2<{os.environ.get('RTM_TILE_Z2', '16')},2> backward, two time steps "
                                 "per launch" if spl == 2 else "k_step<TZ,2> backward")
                                + " (receiver step + reconstruct + imaging)",
                      "steps_per_launch": spl,

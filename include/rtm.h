@@ -192,8 +192,9 @@ typedef struct {
 
 /* Migrate nshots shots of one model together: every shot advances in the
  * same kernel launches, two time steps per launch in reconstruct mode
- * without illumination (RTM_TILE_Z2 = 16 or 32 sets the two-step tile
- * height, 0 keeps one step per launch; results are the same bit for bit),
+ * without illumination (two-step tiles of 32 rows forward and 16 rows
+ * backward; RTM_TILE_Z2 = 16 or 32 sets one height for both, 0 keeps one
+ * step per launch; results are the same bit for bit),
  * launches are replayed from a captured HIP graph, and the one-step tile
  * shape comes from the autotuner.
  * Each shot's image is added into image_dev in shot order after all shots

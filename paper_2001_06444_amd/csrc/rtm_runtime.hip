@@ -644,7 +644,8 @@ static void tune_file_save(rtm_ctx* ctx) {
 static int build_job(rtm_ctx* ctx, hipStream_t s, const JobGeom& g, int tz, const float* vel,
                      const float* wavelet, rtm_point src, const rtm_point* recs, const float* data,
                      float* traces, HostJob& j, const HostJob* medium);
-static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, struct Table& t, int tz2);
+static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, struct Table& t, int tz2f,
+                        int tz2b);
 
 static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch, int tz,
                    float* ms_out);
@@ -686,30 +687,39 @@ struct Table {
   Tile* tiles = nullptr;
   StepCtl* ctl = nullptr;
   int ntiles = 0;
-  Tile* tiles2 = nullptr;  // two-step tiles (tz2 rows x 56 columns), or none
-  int2* recs2 = nullptr;   // receivers of the two-step tiles: {index in the middle region, receiver}
-  int ntiles2 = 0, tz2 = 0;
+  // two-step tiles (tz rows x 56 columns) of the forward and the backward
+  // phase, with the receivers of each tile's middle region:
+  // {index in the middle region, receiver}
+  struct TwoStep {
+    Tile* tiles = nullptr;
+    int2* recs = nullptr;
+    int ntiles = 0, tz = 0;
+    std::shared_ptr<std::vector<Tile>> htiles = std::make_shared<std::vector<Tile>>();
+    std::shared_ptr<std::vector<int2>> hrecs = std::make_shared<std::vector<int2>>();
+  } fw, bw;
   std::vector<Block> blocks;
   std::shared_ptr<std::vector<DevJob>> hjobs;
-  std::shared_ptr<std::vector<Tile>> htiles, htiles2;
-  std::shared_ptr<std::vector<int2>> hrecs2;
+  std::shared_ptr<std::vector<Tile>> htiles;
 };
 
 // Two-step tile height: RTM_TILE_Z2 (16 or 32; 0 turns two-step launches off).
 // On the 100-shot 351 x 1701 faulted-layer survey 32 rows measured 1 % faster than 16.
-static int env_tz2() {
+// RTM_TILE_Z2 = 16 or 32 forces one height for both phases.  Measured
+// defaults: 32 rows forward (396 against 407 us per pair) and 16 rows
+// backward (793 against 816 us per pair).
+static int env_tz2(int ph) {
   const char* e = getenv("RTM_TILE_Z2");
-  if (!e) return 32;
+  if (!e) return ph == kPhFwd ? 32 : 16;
   const int v = atoi(e);
   return v == 16 || v == 32 ? v : 0;
 }
 
-// tz2 > 0 also builds the two-step tile table (reconstruct-mode jobs only).
-static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, Table& t, int tz2) {
+// tz2f / tz2b > 0 also build the two-step tile tables of the forward and the
+// backward phase (reconstruct-mode jobs only).
+static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, Table& t, int tz2f,
+                        int tz2b) {
   t.hjobs = std::make_shared<std::vector<DevJob>>();
   t.htiles = std::make_shared<std::vector<Tile>>();
-  t.htiles2 = std::make_shared<std::vector<Tile>>();
-  t.hrecs2 = std::make_shared<std::vector<int2>>();
   for (size_t i = 0; i < js.size(); ++i) {
     t.hjobs->push_back(js[i]->d);
     for (Tile tl : js[i]->tiles) {
@@ -718,9 +728,10 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
     }
   }
   t.ntiles = (int)t.htiles->size();
-  bool pairs = tz2 == 16 || tz2 == 32;
+  bool pairs = true;
   for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon && !(j->g.flags & RTM_IMG_ILLUM) && j->g.nbuf == 4;
-  if (pairs) {
+  for (auto [tw, tz2] : {std::make_pair(&t.fw, tz2f), std::make_pair(&t.bw, tz2b)}) {
+    if (!pairs || (tz2 != 16 && tz2 != 32)) continue;
     for (size_t i = 0; i < js.size(); ++i) {
       const DevJob& d = js[i]->d;
       const HostJob& hj = *js[i];
@@ -741,20 +752,20 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
           tl.job = (int)i;
           tl.z0 = z0;
           tl.x0 = x0;
-          tl.rec_begin = (int)t.hrecs2->size();
+          tl.rec_begin = (int)tw->hrecs->size();
           // receivers in the middle region rows [z0 - 4, z0 + tz2 + 4), columns [x0 - 4, x0 + 60)
           auto lo = std::lower_bound(rz.begin(), rz.end(), std::make_pair(z0 - kHalo, -1));
           for (auto it = lo; it != rz.end() && it->first < z0 + tz2 + kHalo; ++it) {
             const int xr = rx[it->second];
             if (xr >= x0 - kHalo && xr < x0 + kTileX2 + kHalo)
-              t.hrecs2->push_back(make_int2((it->first - (z0 - kHalo)) * kTileX + (xr - (x0 - kHalo)), it->second));
+              tw->hrecs->push_back(make_int2((it->first - (z0 - kHalo)) * kTileX + (xr - (x0 - kHalo)), it->second));
           }
-          tl.rec_count = (int)t.hrecs2->size() - tl.rec_begin;
-          t.htiles2->push_back(tl);
+          tl.rec_count = (int)tw->hrecs->size() - tl.rec_begin;
+          tw->htiles->push_back(tl);
         }
     }
-    t.ntiles2 = (int)t.htiles2->size();
-    t.tz2 = tz2;
+    tw->ntiles = (int)tw->htiles->size();
+    tw->tz = tz2;
   }
   void* p;
   if (!alloc_block(ctx, t.blocks, t.hjobs->size() * sizeof(DevJob), &p)) return fail(RTM_E_NOMEM, "arena exhausted (job table)");
@@ -769,20 +780,21 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
     return fail(RTM_E_NOMEM, "arena exhausted (control block)");
   }
   t.ctl = static_cast<StepCtl*>(p);
-  if (t.ntiles2 > 0) {
-    if (!alloc_block(ctx, t.blocks, t.htiles2->size() * sizeof(Tile), &p)) {
+  for (auto* tw : {&t.fw, &t.bw}) {
+    if (tw->ntiles == 0) continue;
+    if (!alloc_block(ctx, t.blocks, tw->htiles->size() * sizeof(Tile), &p)) {
       release_blocks(ctx, t.blocks);
       return fail(RTM_E_NOMEM, "arena exhausted (two-step tile table)");
     }
-    t.tiles2 = static_cast<Tile*>(p);
-    HIP_OK(hipMemcpyAsync(t.tiles2, t.htiles2->data(), t.htiles2->size() * sizeof(Tile), hipMemcpyHostToDevice, s));
-    if (!alloc_block(ctx, t.blocks, std::max<size_t>(t.hrecs2->size(), 1) * sizeof(int2), &p)) {
+    tw->tiles = static_cast<Tile*>(p);
+    HIP_OK(hipMemcpyAsync(tw->tiles, tw->htiles->data(), tw->htiles->size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+    if (!alloc_block(ctx, t.blocks, std::max<size_t>(tw->hrecs->size(), 1) * sizeof(int2), &p)) {
       release_blocks(ctx, t.blocks);
       return fail(RTM_E_NOMEM, "arena exhausted (two-step receiver table)");
     }
-    t.recs2 = static_cast<int2*>(p);
-    if (!t.hrecs2->empty())
-      HIP_OK(hipMemcpyAsync(t.recs2, t.hrecs2->data(), t.hrecs2->size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    tw->recs = static_cast<int2*>(p);
+    if (!tw->hrecs->empty())
+      HIP_OK(hipMemcpyAsync(tw->recs, tw->hrecs->data(), tw->hrecs->size() * sizeof(int2), hipMemcpyHostToDevice, s));
   }
   HIP_OK(hipMemcpyAsync(t.jobs, t.hjobs->data(), t.hjobs->size() * sizeof(DevJob), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(t.tiles, t.htiles->data(), t.htiles->size() * sizeof(Tile), hipMemcpyHostToDevice, s));
@@ -830,7 +842,7 @@ static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* 
     }
   }
   Table t;
-  if (rc == RTM_OK) rc = upload_table(ctx, s, ptrs, t, 0);
+  if (rc == RTM_OK) rc = upload_table(ctx, s, ptrs, t, 0, 0);
   hipEvent_t e[3] = {nullptr, nullptr, nullptr};
   if (rc == RTM_OK) {
     for (auto& ev : e) (void)hipEventCreate(&ev);
@@ -976,7 +988,7 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
 // ===========================================================================
 static int run_plain(rtm_ctx* ctx, hipStream_t s, HostJob& j, int tz, Table& t) {
   std::vector<HostJob*> js{&j};
-  int rc = upload_table(ctx, s, js, t, 0);
+  int rc = upload_table(ctx, s, js, t, 0, 0);
   if (rc) return rc;
   const int nsteps = j.d.nsteps;
   const int nf = j.g.mode == kModeModel ? nsteps : j.g.nt - 1;
@@ -1162,17 +1174,18 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
 // Runs nsteps launches of the step kernel: whole groups of K as replays of a
 // captured graph (K step nodes with offsets 0..K-1, then one k_advance node),
 // the remainder as direct launches followed by one k_advance.
-// With `two_step` and a two-step table (t.ntiles2 > 0) the launches go two
+// With `two_step` and a two-step table for the phase the launches go two
 // steps each; an odd last step runs as a one-step launch.  The caller starts
 // the backward phase with two one-step launches (levels nt - 1 and nt - 2 are
 // not reconstructed) before it asks for pairs.
 static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, int nsteps, int K,
                        std::vector<hipGraphExec_t>& graphs, bool two_step) {
-  const bool pairs = two_step && t.ntiles2 > 0 && (ph == kPhFwd || ph == kPhBwd);
+  const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
+  const bool pairs = two_step && tw.ntiles > 0 && (ph == kPhFwd || ph == kPhBwd);
   if (pairs) K = std::max(2, K & ~1);
   auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`
     if (pairs && left >= 2)
-      return launch_step2(t.tz2, ph, t.jobs, t.tiles2, t.recs2, t.ntiles2, t.ctl, 1, off, s);
+      return launch_step2(tw.tz, ph, t.jobs, tw.tiles, tw.recs, tw.ntiles, t.ctl, 1, off, s);
     return launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, off, s);
   };
   int done = 0;
@@ -1227,7 +1240,8 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (int i = 0; i < nshots; ++i) {
     if ((rc = fill_geom_rtm(grid, shots[i].ix0, shots[i].width, opts, shots[i].nrec, geoms[i]))) return rc;
     if (illum_dev) geoms[i].flags |= RTM_IMG_ILLUM;
-    if (geoms[i].mode == kModeRecon && !illum_dev && env_tz2() > 0) geoms[i].nbuf = 4;  // two-step launches
+    if (geoms[i].mode == kModeRecon && !illum_dev && (env_tz2(kPhFwd) > 0 || env_tz2(kPhBwd) > 0))
+      geoms[i].nbuf = 4;  // two-step launches
     if ((rc = check_job(geoms[i], shots[i].src, shots[i].rec_host))) return rc;
     if (shots[i].nrec > 0 && !shots[i].data_dev) return fail(RTM_E_INVAL, "shot %d has no data", i);
   }
@@ -1284,7 +1298,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     jobs.push_back(std::move(j));
   }
   Table t;
-  if ((rc = upload_table(ctx, s, ptrs, t, env_tz2()))) {
+  if ((rc = upload_table(ctx, s, ptrs, t, env_tz2(kPhFwd), env_tz2(kPhBwd)))) {
     cleanup();
     return rc;
   }
@@ -1293,7 +1307,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
   rc = graph_steps(ctx, s, tz, kPhFwd, t, nt - 1, K, graphs, true);
   if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
-  if (!rc && t.ntiles2 > 0 && nt >= 4) {
+  if (!rc && t.bw.ntiles > 0 && nt >= 4) {
     // levels nt - 1 and nt - 2 are imaged without reconstruction: one step each
     for (int i = 0; i < 2 && !rc; ++i)
       if (launch_step(tz, kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, i, s) != hipSuccess)
@@ -1319,7 +1333,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     }
     ctx->ph_launches[0] = nt - 1;
     ctx->ph_launches[1] = nt;
-    ctx->ph_steps_per_launch = t.ntiles2 > 0 && nt >= 4 ? 2 : 1;  // both phases ran pairs
+    ctx->ph_steps_per_launch = t.fw.ntiles > 0 && t.bw.ntiles > 0 && nt >= 4 ? 2 : 1;  // both phases ran pairs
     ctx->ph_bytes[0] = bf;
     ctx->ph_bytes[1] = bb;
     ctx->ph_valid = true;
@@ -1347,7 +1361,8 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (auto& b : t.blocks) d.blocks.push_back(b);
   d.keep.push_back(t.hjobs);
   d.keep.push_back(t.htiles);
-  d.keep.push_back(t.htiles2);
+  d.keep.push_back(t.fw.htiles);
+  d.keep.push_back(t.bw.htiles);
   d.graphs = graphs;
   int rc2 = defer(ctx, s, std::move(d));
   HIP_OK(hipEventRecord(ctx->ev_out, s));

@@ -281,7 +281,8 @@ def test_validation_errors(rtm, ctx):
 @pytest.mark.parametrize("nt", [2, 3, 4, 5, 37])
 def test_two_step_launches_equal_one_step(rtm, ctx, nt):
     """Reconstruct-mode batches advance two time steps per launch (two-step
-    tiles of 16 or 32 rows; RTM_TILE_Z2=0 forces one step per launch).  Every
+    tiles of 16 or 32 rows, by default 32 forward and 16 backward;
+    RTM_TILE_Z2=0 forces one step per launch).  Every
     setting, with short and odd step counts (an odd last step, the two
     one-step launches that open the backward phase), must equal the plain
     path bit for bit."""
@@ -302,8 +303,11 @@ def test_two_step_launches_equal_one_step(rtm, ctx, nt):
     torch.cuda.synchronize()
     old = os.environ.get("RTM_TILE_Z2")
     try:
-        for tz2 in ("16", "32", "0"):
-            os.environ["RTM_TILE_Z2"] = tz2
+        for tz2 in ("16", "32", "0", None):  # None: the defaults, 32 rows forward, 16 backward
+            if tz2 is None:
+                os.environ.pop("RTM_TILE_Z2", None)
+            else:
+                os.environ["RTM_TILE_Z2"] = tz2
             batch = torch.zeros(nz, nx, device="cuda")
             ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch)
             torch.cuda.synchronize()
