@@ -283,7 +283,8 @@ def run_survey(args):
         "workload": f"faulted-layer survey {nz}x{nx} at 10 m, {len(shots)} shots, nt={nt}, "
                     f"nb={nb}, reconstruct mode, stacked",
         "nz": nz, "nx": nx, "nb": nb, "nt": nt, "shots": len(shots), "src_mode": "reconstruct",
-        "path": "batched (hipGraph, all shots per launch)", "tile_z": s1.tile_z})
+        "path": "batched (hipGraph, all shots per launch)", "tile_z": s1.tile_z,
+        "tile_z2": {"forward": s1.last_tile_z2_fwd, "backward": s1.last_tile_z2_bwd}})
     out.update({
         "images_per_s": images_per_s,
         "plain": plain,
@@ -291,7 +292,7 @@ def run_survey(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(),
-                     "kernel": (f"k_step2<{os.environ.get('RTM_TILE_Z2', '16')},2> backward, two time steps "
+                     "kernel": (f"k_step2<{s1.last_tile_z2_bwd},2> backward, two time steps "
                                 "per launch" if spl == 2 else "k_step<TZ,2> backward")
                                + " (receiver step + reconstruct + imaging)",
                      "steps_per_launch": spl,

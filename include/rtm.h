@@ -192,9 +192,10 @@ typedef struct {
 
 /* Migrate nshots shots of one model together: every shot advances in the
  * same kernel launches, two time steps per launch in reconstruct mode
- * without illumination (two-step tiles of 32 rows forward and 16 rows
- * backward; RTM_TILE_Z2 = 16 or 32 sets one height for both, 0 keeps one
- * step per launch; results are the same bit for bit),
+ * without illumination (two-step tiles of 24 rows, or 16 where the last
+ * 24-row tile of a shot would read past its field allocation; RTM_TILE_Z2 =
+ * 16, 24 or 32 sets the height, 0 keeps one step per launch; results are the
+ * same bit for bit; rtm_ctx_stats reports the heights used),
  * launches are replayed from a captured HIP graph, and the one-step tile
  * shape comes from the autotuner.
  * Each shot's image is added into image_dev in shot order after all shots
@@ -520,6 +521,10 @@ typedef struct {
      * stream, of that group's travel-time launch and of all its launches in
      * the call's last iteration (the other group's work overlaps them) */
     float last_bet_eikonal_ms, last_bet_iteration_ms;
+    /* last rtm_migrate_batch call: two-step tile height (rows) of its
+     * forward and backward phases, 0 for a phase that ran one step per
+     * launch */
+    int32_t last_tile_z2_fwd, last_tile_z2_bwd;
 } rtm_ctx_stats_t;
 
 int rtm_ctx_stats(rtm_ctx *ctx, rtm_ctx_stats_t *out);

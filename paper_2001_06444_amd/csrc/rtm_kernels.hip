@@ -1070,9 +1070,11 @@ hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tile
   dim3 grid(8 * per), block(kThreads);
 #define RTM_STEP2(T, P) \
   hipLaunchKernelGGL((k_step2<T, P>), grid, block, 0, s, jobs, tiles, recs2, ctl, ntiles, use_ctl_tick, tick_off)
-  if (tz == 16 && phases == kPhFwd) RTM_STEP2(16, kPhFwd);
-  else if (tz == 32 && phases == kPhFwd) RTM_STEP2(32, kPhFwd);
+  if (tz == 24 && phases == kPhFwd) RTM_STEP2(24, kPhFwd);
+  else if (tz == 24 && phases == kPhBwd) RTM_STEP2(24, kPhBwd);
+  else if (tz == 16 && phases == kPhFwd) RTM_STEP2(16, kPhFwd);
   else if (tz == 16 && phases == kPhBwd) RTM_STEP2(16, kPhBwd);
+  else if (tz == 32 && phases == kPhFwd) RTM_STEP2(32, kPhFwd);
   else if (tz == 32 && phases == kPhBwd) RTM_STEP2(32, kPhBwd);
   else return hipErrorInvalidValue;
 #undef RTM_STEP2

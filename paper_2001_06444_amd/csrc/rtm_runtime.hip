@@ -224,6 +224,7 @@ struct rtm_ctx {
   hipEvent_t ph_ev[3] = {nullptr, nullptr, nullptr};
   int ph_launches[2] = {0, 0};  // time steps of each phase
   int ph_steps_per_launch = 1;
+  int ph_tz2[2] = {0, 0};  // two-step tile height of each phase (0: one step per launch)
   uint64_t ph_bytes[2] = {0, 0};
   bool ph_valid = false;
   Arena arena;
@@ -702,16 +703,27 @@ struct Table {
   std::shared_ptr<std::vector<Tile>> htiles;
 };
 
-// Two-step tile height: RTM_TILE_Z2 (16 or 32; 0 turns two-step launches off).
-// On the 100-shot 351 x 1701 faulted-layer survey 32 rows measured 1 % faster than 16.
-// RTM_TILE_Z2 = 16 or 32 forces one height for both phases.  Measured
-// defaults: 32 rows forward (396 against 407 us per pair) and 16 rows
-// backward (793 against 816 us per pair).
-static int env_tz2(int ph) {
+// Two-step tile height of a phase: 24 rows by default (on the 100-shot
+// 351 x 1701 faulted-layer survey, 757 against 776 us per backward pair with
+// 16 rows and 373 against 388 us per forward pair with 32; 20 and 28 rows
+// were no faster).  RTM_TILE_Z2 = 16, 24 or 32 forces one height for both
+// phases; 0 turns two-step launches off.
+static int env_tz2(int) {
   const char* e = getenv("RTM_TILE_Z2");
-  if (!e) return ph == kPhFwd ? 32 : 16;
+  if (!e) return 24;
   const int v = atoi(e);
-  return v == 16 || v == 32 ? v : 0;
+  return v == 16 || v == 24 || v == 32 ? v : 0;
+}
+
+// A two-step tile reads 8 rows past its last row.  Heights that divide the
+// 64-row rounding of the field allocation always stay inside it; a 24-row
+// tile may not, and then the phase takes 16-row tiles.
+static bool tz2_fits(const std::vector<HostJob*>& js, int tz2) {
+  for (auto* j : js) {
+    const int nzp = j->d.nzp, z0last = ((nzp - 1) / tz2) * tz2;
+    if (z0last + tz2 + 2 * kHalo > field_rows(nzp) - kTopRows) return false;
+  }
+  return true;
 }
 
 // tz2f / tz2b > 0 also build the two-step tile tables of the forward and the
@@ -731,7 +743,8 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   bool pairs = true;
   for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon && !(j->g.flags & RTM_IMG_ILLUM) && j->g.nbuf == 4;
   for (auto [tw, tz2] : {std::make_pair(&t.fw, tz2f), std::make_pair(&t.bw, tz2b)}) {
-    if (!pairs || (tz2 != 16 && tz2 != 32)) continue;
+    if (!pairs || (tz2 != 16 && tz2 != 24 && tz2 != 32)) continue;
+    if (!tz2_fits(js, tz2)) tz2 = 16;
     for (size_t i = 0; i < js.size(); ++i) {
       const DevJob& d = js[i]->d;
       const HostJob& hj = *js[i];
@@ -1334,6 +1347,8 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     ctx->ph_launches[0] = nt - 1;
     ctx->ph_launches[1] = nt;
     ctx->ph_steps_per_launch = t.fw.ntiles > 0 && t.bw.ntiles > 0 && nt >= 4 ? 2 : 1;  // both phases ran pairs
+    ctx->ph_tz2[0] = t.fw.ntiles > 0 && nt >= 3 ? t.fw.tz : 0;
+    ctx->ph_tz2[1] = t.bw.ntiles > 0 && nt >= 4 ? t.bw.tz : 0;
     ctx->ph_bytes[0] = bf;
     ctx->ph_bytes[1] = bb;
     ctx->ph_valid = true;
@@ -2436,6 +2451,8 @@ extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
       out->last_fwd_ms = a;
       out->last_bwd_ms = b;
       out->last_steps_per_launch = ctx->ph_steps_per_launch;
+      out->last_tile_z2_fwd = ctx->ph_tz2[0];
+      out->last_tile_z2_bwd = ctx->ph_tz2[1];
       out->last_fwd_launches = ctx->ph_launches[0];
       out->last_bwd_launches = ctx->ph_launches[1];
       out->last_fwd_launch_bytes = ctx->ph_bytes[0];

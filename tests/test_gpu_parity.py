@@ -278,17 +278,20 @@ def test_validation_errors(rtm, ctx):
 # Batched path == plain path (same kernel per tile; bit for bit)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("nb", [9, 10])
 @pytest.mark.parametrize("nt", [2, 3, 4, 5, 37])
-def test_two_step_launches_equal_one_step(rtm, ctx, nt):
+def test_two_step_launches_equal_one_step(rtm, ctx, nt, nb):
     """Reconstruct-mode batches advance two time steps per launch (two-step
-    tiles of 16 or 32 rows, by default 32 forward and 16 backward;
-    RTM_TILE_Z2=0 forces one step per launch).  Every
-    setting, with short and odd step counts (an odd last step, the two
-    one-step launches that open the backward phase), must equal the plain
-    path bit for bit."""
+    tiles of 16, 24 or 32 rows, by default 24, or 16 where the last 24-row
+    tile would read past the field allocation; RTM_TILE_Z2=0 forces one step
+    per launch).  Every setting, with short and odd step counts (an odd last
+    step, the two one-step launches that open the backward phase), must equal
+    the plain path bit for bit.  nb = 9 gives 63 padded rows, allocated as 64,
+    where 24-row tiles do not fit; nb = 10 gives 65 (a ragged last tile of
+    each height)."""
     import os
     rng = np.random.default_rng(nt)
-    nz, nx, h, dt, nb = 45, 131, 10.0, 1e-3, 9
+    nz, nx, h, dt = 45, 131, 10.0, 1e-3
     vel = inputs.smooth_slowness(1700 + 600 * rng.random((nz, nx)), 30.0, h, h)
     w = inputs.ricker(nt, dt, fp=25)
     g = grid_of(rtm, nz, nx, nb, nt, h, dt)
@@ -303,7 +306,7 @@ def test_two_step_launches_equal_one_step(rtm, ctx, nt):
     torch.cuda.synchronize()
     old = os.environ.get("RTM_TILE_Z2")
     try:
-        for tz2 in ("16", "32", "0", None):  # None: the defaults, 32 rows forward, 16 backward
+        for tz2 in ("16", "24", "32", "0", None):  # None: the default height
             if tz2 is None:
                 os.environ.pop("RTM_TILE_Z2", None)
             else:
@@ -312,7 +315,10 @@ def test_two_step_launches_equal_one_step(rtm, ctx, nt):
             ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch)
             torch.cuda.synchronize()
             assert torch.equal(plain, batch), (nt, tz2, (plain - batch).abs().max().item())
-            assert ctx.stats().last_steps_per_launch == (2 if tz2 != "0" and nt >= 4 else 1)
+            st = ctx.stats()
+            assert st.last_steps_per_launch == (2 if tz2 != "0" and nt >= 4 else 1)
+            rows = {"16": 16, "24": 24 if nb == 10 else 16, "32": 32, "0": 0}[tz2 or "24"]
+            assert (st.last_tile_z2_fwd, st.last_tile_z2_bwd) == (rows if nt >= 3 else 0, rows if nt >= 4 else 0)
     finally:
         if old is None:
             os.environ.pop("RTM_TILE_Z2", None)
