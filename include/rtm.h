@@ -74,7 +74,11 @@ enum { RTM_JOB_QUEUED = 0, RTM_JOB_RUNNING = 1, RTM_JOB_DONE = 2, RTM_JOB_FAILED
 
 typedef struct rtm_ctx rtm_ctx;
 
-/* Physical model grid and time axis. */
+/* Physical model grid and time axis.  A job's padded window, (nz + 2 nb)
+ * rows by (window width + 2 nb) columns, must give wavefield arrays of
+ * fewer than 2^30 floats (about 32000 x 32000 nodes; the step kernels
+ * address a field with 32-bit byte offsets); larger windows are rejected
+ * with RTM_E_INVAL before any device work. */
 typedef struct {
     int32_t nz, nx;  /* model rows (depth) and columns */
     int32_t nb;      /* sponge width in cells, added on all four sides of a job window */

@@ -47,6 +47,18 @@ __device__ __forceinline__ const RTM_GLOBAL T* gp(const T* p) {
   return (const RTM_GLOBAL T*)p;
 }
 
+// p + i for an element index 0 <= i < 2^30: the byte offset fits 32 bits, so
+// the access can add a per-lane 32-bit offset to the wavefront-uniform base
+// in scalar registers instead of forming a 64-bit address in each lane.
+template <class T>
+__device__ __forceinline__ RTM_GLOBAL T* at(RTM_GLOBAL T* p, uint32_t i) {
+  return (RTM_GLOBAL T*)((RTM_GLOBAL char*)p + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const RTM_GLOBAL T* at(const RTM_GLOBAL T* p, uint32_t i) {
+  return (const RTM_GLOBAL T*)((const RTM_GLOBAL char*)p + i * (uint32_t)sizeof(T));
+}
+
 template <class T>
 __device__ __forceinline__ void st_stream(RTM_GLOBAL T* p, T v) {
 #if RTM_NT_STORE
@@ -119,7 +131,7 @@ struct TileStage {
       // around the load, so no wait at a join); store() skips them
       const int i = min((int)threadIdx.x + it * kThreads, kN - 1);
       const int r = i / kVec, q = i - r * kVec;
-      v[it] = *(const RTM_GLOBAL f32x4*)(base + (int64_t)r * pitch + q * 4);
+      v[it] = *(const RTM_GLOBAL f32x4*)at(base, (uint32_t)(r * pitch + q * 4));
     }
   }
   __device__ __forceinline__ void store(float* __restrict__ lds) const {
@@ -156,16 +168,21 @@ template <int RZ, int W = kLdsW>
 __device__ __forceinline__ float lap8(const float* __restrict__ lds, int row, int col,
                                       const float (&zw)[RZ + 8], int k, float c0,
                                       const float (&cz)[4], const float (&cx)[4]) {
-  const float* rp = lds + row * W + col;
+  // One address register per call, opaque to the compiler: left to itself
+  // it pairs the neighbour reads into ds_read2 instructions, whose 8-bit
+  // offsets cannot hold the arrays' LDS offsets, and adds a base per pair.
+  typedef __attribute__((address_space(3))) const float lds_f;
+  lds_f* rp = (lds_f*)(lds + row * W + col - kHalo);  // rp[kHalo] is the centre
+  asm("" : "+v"(rp));
   float s = c0 * zw[k + 4];
   s = fmaf(cz[0], zw[k + 3] + zw[k + 5], s);
-  s = fmaf(cx[0], rp[-1] + rp[1], s);
+  s = fmaf(cx[0], rp[3] + rp[5], s);
   s = fmaf(cz[1], zw[k + 2] + zw[k + 6], s);
-  s = fmaf(cx[1], rp[-2] + rp[2], s);
+  s = fmaf(cx[1], rp[2] + rp[6], s);
   s = fmaf(cz[2], zw[k + 1] + zw[k + 7], s);
-  s = fmaf(cx[2], rp[-3] + rp[3], s);
+  s = fmaf(cx[2], rp[1] + rp[7], s);
   s = fmaf(cz[3], zw[k + 0] + zw[k + 8], s);
-  s = fmaf(cx[3], rp[-4] + rp[4], s);
+  s = fmaf(cx[3], rp[0] + rp[8], s);
   return s;
 }
 
@@ -594,7 +611,7 @@ struct TileStageW {  // ROWS x 72 floats from (zs, xs), as 16-byte loads
     for (int it = 0; it < kIt; ++it) {
       const int i = min((int)threadIdx.x + it * kThreads, kN - 1);
       const int r = i / kVec, q = i - r * kVec;
-      v[it] = *(const RTM_GLOBAL f32x4*)(base + (int64_t)r * pitch + q * 4);
+      v[it] = *(const RTM_GLOBAL f32x4*)at(base, (uint32_t)(r * pitch + q * 4));
     }
   }
   __device__ __forceinline__ void store(float* __restrict__ lds) const {
@@ -660,14 +677,14 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
   for (int k = 0; k < RA; ++k) {
     const int zc = kFast ? za0 + k : min(max(za0 + k, 0), J.nzp - 1);
     const uint32_t off = (uint32_t)zc * (uint32_t)pitch + xcl;
-    cva[k] = ld_medium(cc + off);
-    pva[k] = ld_cached(um + off);
+    cva[k] = ld_medium(at(cc, off));
+    pva[k] = ld_cached(at(um, off));
     gza[k] = gz[zc];
   }
 #pragma unroll
   for (int k = 0; k < RB; ++k) {
     const int zc = kFast ? zb0 + k : min(zb0 + k, J.nzp - 1);
-    cvb[k] = ld_medium(cc + ((uint32_t)zc * (uint32_t)pitch + xcl));
+    cvb[k] = ld_medium(at(cc, (uint32_t)zc * (uint32_t)pitch + xcl));
     gzb[k] = gz[zc];
   }
   const float gxv = (kFast || xin) ? gx[xcl] : 0.0f;
@@ -695,7 +712,7 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
     if (!kFast) un = (xin && z >= 0 && z < J.nzp) ? un : 0.0f;
     sm.ma[r * kTileX + lane] = un;
     if (r >= kHalo && r < TZ + kHalo && (kFast || z < J.nzp) && xout) {  // a node of the output tile
-      st_cached(u1 + ((uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
+      st_cached(at(u1, (uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
       if (!kFast) ring_save(J, z, x, n + 1, un);
     }
   }
@@ -714,7 +731,7 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
     const float uold = sm.a[(w * RB + k + 2 * kHalo) * kLdsW + lane + kHalo];  // u^n
     if (xout && (kFast || z < J.nzp)) {
       const float un = leapfrog(G, cvb[k], lap, zm[k + 4], uold);
-      st_cached(u2 + ((uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
+      st_cached(at(u2, (uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
       if (!kFast) ring_save(J, z, x, n + 2, un);
     }
   }
@@ -792,12 +809,12 @@ __device__ __forceinline__ void backward2_body(const DevJob& J, const Tile& tl, 
   for (int k = 0; k < RA; ++k) {
     const int zc = kGen ? min(max(za0 + k, 0), J.nzp - 1) : za0 + k;
     const uint32_t off = (uint32_t)zc * (uint32_t)pitch + xcl;
-    cva[k] = ld_medium(cc + off);
-    pva[k] = ld_cached(r2 + off);
+    cva[k] = ld_medium(at(cc, off));
+    pva[k] = ld_cached(at(r2, off));
     gza[k] = gz[zc];
     sva[k] = 0.0f;
     ringa[k] = false;
-    if (KIND == 1) sva[k] = ld_cached(s2 + off);
+    if (KIND == 1) sva[k] = ld_cached(at(s2, off));
   }
   if (kGen && tphys) {
 #pragma unroll
@@ -815,18 +832,18 @@ __device__ __forceinline__ void backward2_body(const DevJob& J, const Tile& tl, 
 #pragma unroll
   for (int k = 0; k < RB; ++k) {
     const int zc = kGen ? min(zb0 + k, J.nzp - 1) : zb0 + k;
-    cvb[k] = ld_medium(cc + ((uint32_t)zc * (uint32_t)pitch + xcl));
+    cvb[k] = ld_medium(at(cc, (uint32_t)zc * (uint32_t)pitch + xcl));
     gzb[k] = gz[zc];
     ivb[k] = 0.0f;
     svb[k] = 0.0f;
     ringb[k] = false;
-    if (KIND == 1) ivb[k] = ld_cached(image + ((uint32_t)(zb0 + k - J.nb) * (uint32_t)pitch + (uint32_t)x));
+    if (KIND == 1) ivb[k] = ld_cached(at(image, (uint32_t)(zb0 + k - J.nb) * (uint32_t)pitch + (uint32_t)x));
   }
   if (kGen && tphys) {
 #pragma unroll
     for (int k = 0; k < RB; ++k) {  // image, and the stored ring value of level m - 1
       const int pzc = min(max(zb0 + k - J.nb, 0), J.nz - 1);
-      ivb[k] = ld_cached(image + ((uint32_t)pzc * (uint32_t)pitch + xph));
+      ivb[k] = ld_cached(at(image, (uint32_t)pzc * (uint32_t)pitch + xph));
       const int slot = ring_slot(pzc, (int)xph - J.nb, J.nz, J.nx);
       ringb[k] = slot >= 0;
       svb[k] = ld_cached(gp(J.ring) + (int64_t)(m - 1) * J.ring_len + max(slot, 0));
@@ -907,8 +924,8 @@ __device__ __forceinline__ void backward2_body(const DevJob& J, const Tile& tl, 
       }
       if (r >= kHalo && r < TZ + kHalo && (!kGen || z < J.nzp) && xout) {  // a node of the output tile
         const uint32_t off = (uint32_t)z * (uint32_t)pitch + (uint32_t)x;
-        st_cached(r0 + off, rv);
-        if (kSrc && phys) st_cached(s0 + off, sv);
+        st_cached(at(r0, off), rv);
+        if (kSrc && phys) st_cached(at(s0, off), sv);
       }
     }
   }
@@ -933,7 +950,7 @@ __device__ __forceinline__ void backward2_body(const DevJob& J, const Tile& tl, 
       const float rc = sm.a[lrow];  // R^{m+1}
       if (xout && (!kGen || z < J.nzp)) {
         const uint32_t off = (uint32_t)z * (uint32_t)pitch + (uint32_t)x;
-        st_cached(rn + off, leapfrog(G, cvb[k], lap, zr[k + 4], rc));
+        st_cached(at(rn, off), leapfrog(G, cvb[k], lap, zr[k + 4], rc));
         const int pz = z - J.nb;
         const bool phys = KIND == 1 || (kGen && tphys && colphys && pz >= 0 && pz < J.nz);
         if (kSrc && phys) {
@@ -945,9 +962,9 @@ __device__ __forceinline__ void backward2_body(const DevJob& J, const Tile& tl, 
             if (kGen && z == J.src_z && x == J.src_x) ls = add_unfused(ls, wb);
             sv = fmaf(cvb[k], ls, 2.0f * zs[k + 4]) - sm.b[lrow];
           }
-          st_cached(sn + off, sv);
+          st_cached(at(sn, off), sv);
           const float im = fmaf(kfac * zs[k + 4], rc, ivb[k]);  // level m
-          st_cached(image + ((uint32_t)pz * (uint32_t)pitch + (uint32_t)x), fmaf(kfac * sv, zr[k + 4], im));
+          st_cached(at(image, (uint32_t)pz * (uint32_t)pitch + (uint32_t)x), fmaf(kfac * sv, zr[k + 4], im));
         }
       }
     }

@@ -576,6 +576,11 @@ static int check_job(const JobGeom& g, rtm_point src, const rtm_point* recs) {
     return fail(RTM_E_INVAL, "window [%d, %d) outside the model's %d columns", g.ix0, g.ix0 + g.width,
                 g.model_nx);
   if (g.nt < 2) return fail(RTM_E_INVAL, "nt must be >= 2");
+  // the step kernels address a field with 32-bit byte offsets
+  const int64_t nzp = (int64_t)g.nz + 2 * g.nb, nxp = (int64_t)g.width + 2 * g.nb;
+  if (nzp > (1 << 30) || nxp > (1 << 30) || field_floats((int)nzp, (int)nxp) >= ((int64_t)1 << 30))
+    return fail(RTM_E_INVAL, "padded window %lld x %lld too large: a wavefield must hold fewer than 2^30 floats",
+                (long long)nzp, (long long)nxp);
   if (g.mode == kModeRecon && (g.nz < 9 || g.width < 9))
     return fail(RTM_E_INVAL, "reconstruct mode needs a window of at least 9 x 9 (got %d x %d)", g.nz, g.width);
   if (g.mode == kModeStore) {

@@ -272,6 +272,15 @@ def test_validation_errors(rtm, ctx):
         ctx.migrate_shot(ok, vel, w, (5, 5), [(1, 5)], d, 0, 8, rtm.img_opts(), img)
     assert e.value.code == -1
     assert not host(img).any()  # rejected calls did no device work
+    # padded window 8201 x 138192: a wavefield would hold over 2^30 floats,
+    # past what the kernels' 32-bit byte offsets address
+    big = grid_of(rtm, 9, 130000, 4096, 50, 10.0, 1e-3)
+    img_big = torch.zeros(9, 130000, device="cuda")
+    with pytest.raises(rtm.RTMError) as e:
+        ctx.migrate_shot(big, dev(np.full((9, 130000), 2000.0)), w, (1, 5), [(1, 1)], d, 0, 130000,
+                         rtm.img_opts("reconstruct"), img_big)
+    assert e.value.code == -1 and "2^30" in str(e.value)
+    assert not host(img_big).any()
 
 
 # ---------------------------------------------------------------------------
