@@ -720,13 +720,15 @@ static int env_tz2(int) {
   return v == 16 || v == 24 || v == 32 ? v : 0;
 }
 
-// A two-step tile reads 8 rows past its last row.  Heights that divide the
-// 64-row rounding of the field allocation always stay inside it; a 24-row
-// tile may not, and then the phase takes 16-row tiles.
+// A two-step tile reads 8 rows past its last row, and the staged rows of the
+// last tile column run past the row end into the next row: the last tile
+// must end within the 64-row rounding of the field allocation, whose 9 zero
+// rows after it take the halo and that overrun.  Heights that divide 64
+// always do; a 24-row tile may not, and then the phase takes 16-row tiles.
 static bool tz2_fits(const std::vector<HostJob*>& js, int tz2) {
   for (auto* j : js) {
     const int nzp = j->d.nzp, z0last = ((nzp - 1) / tz2) * tz2;
-    if (z0last + tz2 + 2 * kHalo > field_rows(nzp) - kTopRows) return false;
+    if (z0last + tz2 > field_rows(nzp) - 2 * kTopRows) return false;
   }
   return true;
 }
