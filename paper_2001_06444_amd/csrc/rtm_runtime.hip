@@ -708,12 +708,12 @@ struct Table {
   std::shared_ptr<std::vector<Tile>> htiles;
 };
 
-// Two-step tile height of a phase: 24 rows by default (on the 100-shot
+// Two-step tile height, both phases: 24 rows by default (on the 100-shot
 // 351 x 1701 faulted-layer survey, 757 against 776 us per backward pair with
 // 16 rows and 373 against 388 us per forward pair with 32; 20 and 28 rows
-// were no faster).  RTM_TILE_Z2 = 16, 24 or 32 forces one height for both
-// phases; 0 turns two-step launches off.
-static int env_tz2(int) {
+// were no faster).  RTM_TILE_Z2 = 16, 24 or 32 sets the height; 0, or any
+// other value, turns two-step launches off.
+static int env_tz2() {
   const char* e = getenv("RTM_TILE_Z2");
   if (!e) return 24;
   const int v = atoi(e);
@@ -1260,7 +1260,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (int i = 0; i < nshots; ++i) {
     if ((rc = fill_geom_rtm(grid, shots[i].ix0, shots[i].width, opts, shots[i].nrec, geoms[i]))) return rc;
     if (illum_dev) geoms[i].flags |= RTM_IMG_ILLUM;
-    if (geoms[i].mode == kModeRecon && !illum_dev && (env_tz2(kPhFwd) > 0 || env_tz2(kPhBwd) > 0))
+    if (geoms[i].mode == kModeRecon && !illum_dev && env_tz2() > 0)
       geoms[i].nbuf = 4;  // two-step launches
     if ((rc = check_job(geoms[i], shots[i].src, shots[i].rec_host))) return rc;
     if (shots[i].nrec > 0 && !shots[i].data_dev) return fail(RTM_E_INVAL, "shot %d has no data", i);
@@ -1318,7 +1318,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     jobs.push_back(std::move(j));
   }
   Table t;
-  if ((rc = upload_table(ctx, s, ptrs, t, env_tz2(kPhFwd), env_tz2(kPhBwd)))) {
+  if ((rc = upload_table(ctx, s, ptrs, t, env_tz2(), env_tz2()))) {
     cleanup();
     return rc;
   }
