@@ -97,7 +97,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["survey", "ensemble", "serve", "small", "born", "codec", "bet"],
+    ap.add_argument("--workload", choices=["survey", "ensemble", "serve", "small", "born", "codec", "bet", "maps"],
                     default="survey")
     ap.add_argument("--shots", type=int, default=100)
     ap.add_argument("--nt", type=int, default=None, help="default: 4000 survey, 3000 ensemble")
@@ -141,7 +141,8 @@ def main():
         del src_t, dst_t
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
     out = {"survey": run_survey, "ensemble": run_ensemble, "serve": run_serve,
-           "small": run_small, "born": run_born, "codec": run_codec, "bet": run_bet}[args.workload](args)
+           "small": run_small, "born": run_born, "codec": run_codec, "bet": run_bet,
+           "maps": run_maps}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 
@@ -642,6 +643,71 @@ def run_born(args):
                            "note": "events around whole calls, launch gaps included; one shot's "
                                    "working set fits the 256 MB Infinity Cache"}})
     return out
+
+# Algorithmic bytes per pixel of the Stage-3 maps and the filter: every input
+# read once, every output written once.
+MAPS_BYTES = {"confidence": 8 + 4 + 8, "ratio": 8 + 8 + 8, "laplacian_filter": 4 + 4, "normalize": 4 + 4 + 4}
+
+
+def run_maps(args):
+    """The Stage-3 maps (confidence index, std/mean ratio), the post-stack
+    Laplacian filter and the source-normalised image, over one image of the
+    paper's size (351 x 1701) and over a bank of 256 such images side by side
+    (the size of the serving configuration's Welford state; the filter
+    launches one row of workgroups per image row).  Each call
+    is timed with HIP events around 20 calls on the library's stream; the
+    confidence index and the normalised image take two passes (a reduction,
+    then the map), counted in their time but not in their bytes."""
+    import torch
+
+    from paper_2001_06444_amd import rtm
+
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    ctx = rtm.Context(0, arena_bytes=64 << 20)
+    K, rows = 20, {}
+    for label, (rz, rx) in {"image": (351, 1701), "bank": (351, 256 * 1701)}.items():
+        n = rz * rx
+        std = torch.rand(n, dtype=torch.float64, device=dev, generator=gen)
+        mean = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+        cnt = torch.randint(0, 8, (n,), dtype=torch.int32, device=dev, generator=gen)
+        img = torch.randn(rz, rx, device=dev, generator=gen)
+        ill = torch.rand(rz, rx, device=dev, generator=gen)
+        o64 = torch.empty(n, dtype=torch.float64, device=dev)
+        o32 = torch.empty(rz, rx, device=dev)
+        calls = {"confidence": lambda: ctx.confidence_map(std, cnt, o64, min_count=2),
+                 "ratio": lambda: ctx.ratio_map(std, mean, o64, eps=1e-3),
+                 "laplacian_filter": lambda: ctx.laplacian_filter(img, 10.0, 10.0, o32),
+                 "normalize": lambda: ctx.normalize_image(img, ill, o32, eps_rel=1e-3)}
+        for name, fn in calls.items():
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(K):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / K
+            alg = MAPS_BYTES[name] * n
+            rows[f"{name} {label}"] = {"pixels": n, "us": us, "alg_bytes": alg, "GB_per_s": alg / (us * 1e-6) / 1e9}
+            log(f"[bench] maps: {name:16s} {label:5s} {n:10d} px {us:9.1f} us {rows[f'{name} {label}']['GB_per_s']:7.0f} GB/s")
+        del std, mean, cnt, img, ill, o64, o32
+    ctx.close()
+    bank = {k: v for k, v in rows.items() if k.endswith("bank")}
+    tot_b, tot_us = sum(v["alg_bytes"] for v in bank.values()), sum(v["us"] for v in bank.values())
+    dom = max(bank, key=lambda k: bank[k]["us"])
+    out = _base_record(args, tot_b / (tot_us * 1e-6) / 1e9, tot_us * 1e-3, {
+        "workload": "Stage-3 maps + post-stack filter + normalised image over 256 351x1701 images side by side "
+                    "(and one image)", "pixels": bank[dom]["pixels"]}, unit="GB/s")
+    out.update({"metric": "Stage-3 maps: algorithmic GB/s", "steps": K, "warmup": 3, "dtype": "f64/f32",
+                "maps": rows,
+                "roofline": {"bound": "hbm", "achieved": bank[dom]["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": bank[dom]["GB_per_s"] / HBM_PEAK_GBS, "traffic": None,
+                             "kernel": dom.split()[0] + " (bank)"}})
+    return out
+
 
 CODEC_SETTINGS = {"velocity": (1e-4, 1e-1, None), "image": (1e-4, 1e-1, None), "seismogram": (1e-4, None)}
 

@@ -180,57 +180,106 @@ hipError_t launch_stats_out(const double* mean, const double* m2, const int32_t*
 }
 
 // ---------------------------------------------------------------------------
-// Stage-3 maps.  Confidence index (Eq. 6): two passes, min/max of std over
-// pixels with enough samples, then the normalisation.
+// Stage-3 maps.  The reductions they need (extremes of std for the
+// confidence index, the largest illumination for the normalised image) run
+// in two stages: each workgroup of a grid-stride pass writes its partial
+// result and one workgroup folds the partials, so no address is hit by
+// more than one write (with one atomic per wavefront on a single address,
+// the 597k-pixel confidence map spent 95 us in its reduction).  Loads are
+// issued four grid strides at a time, with no branch between a pixel's
+// loads, so each wavefront keeps several in flight.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t order_bits(double v) {
-  // monotone map of a non-negative double onto uint64
-  return (uint64_t)__double_as_longlong(v);
-}
-
-__global__ void k_minmax(const double* __restrict__ sd, const int32_t* __restrict__ count, int n,
-                         int min_count, unsigned long long* mm) {
-  double lo = INFINITY, hi = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (count && count[i] < min_count) continue;
-    double v = sd[i];
-    lo = fmin(lo, v);
-    hi = fmax(hi, v);
-  }
+__device__ __forceinline__ void block_minmax(double& lo, double& hi, double* red) {
   for (int o = 32; o > 0; o >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, o, 64));
     hi = fmax(hi, __shfl_xor(hi, o, 64));
   }
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    atomicMin(&mm[0], (unsigned long long)order_bits(lo));
-    atomicMax(&mm[1], (unsigned long long)order_bits(hi));
+    red[w] = lo;
+    red[nw + w] = hi;
   }
-}
-
-__global__ void k_confidence(const double* __restrict__ sd, const int32_t* __restrict__ count,
-                             int n, int min_count, const unsigned long long* mm, double* out) {
-  const double lo = __longlong_as_double((long long)mm[0]);
-  const double hi = __longlong_as_double((long long)mm[1]);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if ((count && count[i] < min_count) || !(hi > lo)) {
-      out[i] = 0.0;
-      continue;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 1; k < nw; ++k) {
+      lo = fmin(lo, red[k]);
+      hi = fmax(hi, red[nw + k]);
     }
-    out[i] = (hi - sd[i]) / (hi - lo);
+}
+
+// Extremes of std over the pixels with count >= min_count (all pixels
+// without counts), one (min, max) pair per workgroup.  std >= 0, so a
+// workgroup without such pixels leaves (inf, 0), which orders as empty.
+__global__ __launch_bounds__(256) void k_minmax_part(const double* __restrict__ sd,
+                                                     const int32_t* __restrict__ count, int n,
+                                                     int min_count, double* __restrict__ part) {
+  __shared__ double red[8];
+  double lo = INFINITY, hi = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double v[4];
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v[u] = sd[i + u * stride];
+      c[u] = count ? count[i + u * stride] : min_count;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (c[u] >= min_count) {
+        lo = fmin(lo, v[u]);
+        hi = fmax(hi, v[u]);
+      }
+  }
+  for (; i < n; i += stride) {
+    const double v = sd[i];
+    const int32_t c = count ? count[i] : min_count;
+    if (c >= min_count) {
+      lo = fmin(lo, v);
+      hi = fmax(hi, v);
+    }
+  }
+  block_minmax(lo, hi, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = lo;
+    part[2 * blockIdx.x + 1] = hi;
   }
 }
 
-__global__ void k_init_minmax(unsigned long long* mm) {
-  mm[0] = (unsigned long long)order_bits(INFINITY);
-  mm[1] = 0ull;
+__global__ __launch_bounds__(256) void k_minmax_fold(const double* __restrict__ part, int nparts,
+                                                     double* __restrict__ mm) {
+  __shared__ double red[8];
+  double lo = INFINITY, hi = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    lo = fmin(lo, part[2 * b]);
+    hi = fmax(hi, part[2 * b + 1]);
+  }
+  block_minmax(lo, hi, red);
+  if (threadIdx.x == 0) {
+    mm[0] = lo;
+    mm[1] = hi;
+  }
+}
+
+// Confidence index (Eq. 6) from the folded extremes mm = (s_min, s_max).
+__global__ void k_confidence(const double* __restrict__ sd, const int32_t* __restrict__ count,
+                             int n, int min_count, const double* __restrict__ mm, double* __restrict__ out) {
+  const double lo = mm[0], hi = mm[1];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = sd[i];
+    const bool on = (!count || count[i] >= min_count) && hi > lo;
+    out[i] = on ? (hi - v) / (hi - lo) : 0.0;
+  }
 }
 
 hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int min_count,
-                             double* out, double* scratch2, hipStream_t s) {
-  auto* mm = reinterpret_cast<unsigned long long*>(scratch2);
-  hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm);
-  int blocks = std::max(1, std::min((n + 255) / 256, 1024));
-  hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm);
+                             double* out, double* scratch, hipStream_t s) {
+  const int parts = std::max(1, std::min((n + 255) / 256, kRedBlocks));
+  double* mm = scratch + 2 * kRedBlocks;
+  hipLaunchKernelGGL(k_minmax_part, dim3(parts), dim3(256), 0, s, sd, count, n, min_count, scratch);
+  hipLaunchKernelGGL(k_minmax_fold, dim3(1), dim3(256), 0, s, scratch, parts, mm);
+  const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
   hipLaunchKernelGGL(k_confidence, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm, out);
   return hipGetLastError();
 }
@@ -238,7 +287,7 @@ hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int 
 // Ratio map (Eq. 7): r = std / mean, 0 where |mean| <= eps
 __global__ void k_ratio(const double* __restrict__ sd, const double* __restrict__ mean, int n,
                         double eps, double* out) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double mu = mean[i];
     out[i] = fabs(mu) > eps ? sd[i] / mu : 0.0;
   }
@@ -251,24 +300,37 @@ hipError_t launch_ratio(const double* sd, const double* mean, int n, double eps,
   return hipGetLastError();
 }
 
-// Post-stack Laplacian filter: out = -L img, zero outside the image.
-__global__ void k_lapfilter(const float* __restrict__ img, int nz, int nx, float c0, float4 czv,
-                            float4 cxv, float* __restrict__ out) {
+// Post-stack Laplacian filter: out = -L img, zero outside the image.  A
+// thread filters kLapRows rows of one column, with the column's values in
+// registers, so a pixel costs one new load along z and eight along x.
+constexpr int kLapRows = 16;
+
+__global__ __launch_bounds__(256) void k_lapfilter(const float* __restrict__ img, int nz, int nx,
+                                                   float c0, float4 czv, float4 cxv,
+                                                   float* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int z = blockIdx.y;
-  if (x >= nx || z >= nz) return;
+  const int z0 = blockIdx.y * kLapRows;
+  if (x >= nx) return;
   const float cz[4] = {czv.x, czv.y, czv.z, czv.w};
   const float cx[4] = {cxv.x, cxv.y, cxv.z, cxv.w};
   auto at = [&](int zz, int xx) -> float {
     return (zz >= 0 && zz < nz && xx >= 0 && xx < nx) ? img[(int64_t)zz * nx + xx] : 0.0f;
   };
-  float s = c0 * at(z, x);
+  float col[kLapRows + 8];
 #pragma unroll
-  for (int k = 1; k <= 4; ++k) {
-    s = fmaf(cz[k - 1], at(z - k, x) + at(z + k, x), s);
-    s = fmaf(cx[k - 1], at(z, x - k) + at(z, x + k), s);
+  for (int j = 0; j < kLapRows + 8; ++j) col[j] = at(z0 - 4 + j, x);
+#pragma unroll
+  for (int k = 0; k < kLapRows; ++k) {
+    const int z = z0 + k;
+    if (z >= nz) break;
+    float s = c0 * col[k + 4];
+#pragma unroll
+    for (int q = 1; q <= 4; ++q) {
+      s = fmaf(cz[q - 1], col[k + 4 - q] + col[k + 4 + q], s);
+      s = fmaf(cx[q - 1], at(z, x - q) + at(z, x + q), s);
+    }
+    out[(int64_t)z * nx + x] = -s;
   }
-  out[(int64_t)z * nx + x] = -s;
 }
 
 hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx, float* out,
@@ -280,8 +342,8 @@ hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx
                            (float)(a[4] * iz2));
   float4 cxv = make_float4((float)(a[1] * ix2), (float)(a[2] * ix2), (float)(a[3] * ix2),
                            (float)(a[4] * ix2));
-  hipLaunchKernelGGL(k_lapfilter, dim3((nx + 255) / 256, nz), dim3(256), 0, s, img, nz, nx, c0, czv,
-                     cxv, out);
+  hipLaunchKernelGGL(k_lapfilter, dim3((nx + 255) / 256, (nz + kLapRows - 1) / kLapRows), dim3(256), 0, s,
+                     img, nz, nx, c0, czv, cxv, out);
   return hipGetLastError();
 }
 
@@ -289,30 +351,51 @@ hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx
 // ---------------------------------------------------------------------------
 // Source-normalised image (Eq. 5): out = I / (illum + eps_rel * max illum)
 // ---------------------------------------------------------------------------
-__global__ void k_max_nonneg(const float* __restrict__ a, int n, uint32_t* out) {
+__global__ __launch_bounds__(256) void k_max_part(const float* __restrict__ a, int n, float* __restrict__ part) {
   __shared__ float red[4];
   float m = 0.0f;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) m = fmaxf(m, a[i]);
-  wg_atomic_max(m, out, red);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = a[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m = fmaxf(m, v[u]);
+  }
+  for (; i < n; i += stride) m = fmaxf(m, a[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_max_fold(const float* __restrict__ part, int nparts, float* __restrict__ mx) {
+  __shared__ float red[4];
+  float m = 0.0f;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) m = fmaxf(m, part[b]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) *mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
 __global__ void k_normalize(const float* __restrict__ img, const float* __restrict__ illum, int n,
-                            float eps_rel, const uint32_t* maxbits, float* __restrict__ out) {
-  const float eps = eps_rel * __uint_as_float(*maxbits);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+                            float eps_rel, const float* __restrict__ mx, float* __restrict__ out) {
+  const float eps = eps_rel * *mx;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float d = illum[i] + eps;
     out[i] = d > 0.0f ? img[i] / d : 0.0f;
   }
 }
 
-__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
-
 hipError_t launch_normalize(const float* img, const float* illum, int n, float eps_rel, float* out,
-                            uint32_t* scratch, hipStream_t s) {
-  const int blocks = std::max(1, std::min((n + 255) / 256, 2048));
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, scratch);
-  hipLaunchKernelGGL(k_max_nonneg, dim3(blocks), dim3(256), 0, s, illum, n, scratch);
-  hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, s, img, illum, n, eps_rel, scratch, out);
+                            float* scratch, hipStream_t s) {
+  const int parts = std::max(1, std::min((n + 255) / 256, kRedBlocks));
+  hipLaunchKernelGGL(k_max_part, dim3(parts), dim3(256), 0, s, illum, n, scratch);
+  hipLaunchKernelGGL(k_max_fold, dim3(1), dim3(256), 0, s, scratch, parts, scratch + kRedBlocks);
+  const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, s, img, illum, n, eps_rel, scratch + kRedBlocks, out);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ constexpr int kTileX = 64;       // tile width: one 64-lane wavefront per row
 constexpr int kHalo = 4;         // stencil radius
 constexpr int kLdsW = kTileX + 2 * kHalo;  // 72 floats per LDS row
 constexpr int kTopRows = 9;      // zero rows before padded row 0 (two-step halo + 1)
+constexpr int kRedBlocks = 1024;  // workgroup partials of the maps' two-stage reductions
 constexpr int kRowAlign = 64;    // rows rounded up to the tallest tile
 constexpr int kThreads = 256;    // 4 wavefronts per workgroup
 constexpr int kMaxSlots = 64;    // partial max-abs slots per stored step (spreads the atomics)
@@ -101,8 +102,9 @@ hipError_t launch_stack(float* dst, int dst_nx, int ix0, const float* img, int i
 hipError_t launch_copy_phys(float* dst, const float* field, int nz, int nx, int nb, int pitch,
                             hipStream_t s);
 hipError_t launch_nonfinite(const float* img, int pitch, int nz, int width, uint32_t* flag, hipStream_t s);
+// scratch: at least kRedBlocks + 1 floats of device memory
 hipError_t launch_normalize(const float* img, const float* illum, int n, float eps_rel, float* out,
-                            uint32_t* scratch, hipStream_t s);
+                            float* scratch, hipStream_t s);
 hipError_t launch_chan_merge(double* mean_a, double* m2_a, int32_t* n_a, const double* mean_b,
                              const double* m2_b, const int32_t* n_b, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -110,8 +112,9 @@ hipError_t launch_welford(double* mean, double* m2, int32_t* count, int nx_model
                           int img_pitch, int nz, int width, int ix0, hipStream_t s);
 hipError_t launch_stats_out(const double* mean, const double* m2, const int32_t* count, int64_t n,
                             double* mean_out, double* std_out, int32_t* count_out, hipStream_t s);
+// scratch: at least 2 kRedBlocks + 2 doubles of device memory
 hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int min_count,
-                             double* out, double* scratch2, hipStream_t s);
+                             double* out, double* scratch, hipStream_t s);
 hipError_t launch_ratio(const double* sd, const double* mean, int n, double eps, double* out,
                         hipStream_t s);
 hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx, float* out,

@@ -252,7 +252,7 @@ struct rtm_ctx {
   bool sched_started = false;
   int active_jobs = 0, queued_jobs = 0;
   uint32_t* scratch_u32 = nullptr;     // small device scratch (vmax etc.)
-  double* scratch_f64 = nullptr;
+  double* scratch_f64 = nullptr;      // partials of the maps' reductions (2 kRedBlocks + 2 doubles)
   // last codec call: HIP events around its kernel, algorithmic bytes, 1 encode / 2 decode
   hipEvent_t zc_ev[2] = {nullptr, nullptr};
   int zc_op = 0;
@@ -946,7 +946,8 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   for (auto& e : ctx->zc_ev) HIP_OK(hipEventCreate(&e));
   for (auto& e : ctx->bet_ev) HIP_OK(hipEventCreate(&e));
   ctx->scratch_u32 = static_cast<uint32_t*>(ctx->arena.alloc(256));
-  ctx->scratch_f64 = static_cast<double*>(ctx->arena.alloc(256));
+  ctx->scratch_f64 = static_cast<double*>(ctx->arena.alloc((2 * kRedBlocks + 2) * sizeof(double)));
+  if (!ctx->scratch_u32 || !ctx->scratch_f64) return fail(RTM_E_NOMEM, "arena too small for the context's scratch");
   HIP_OK(hipMemset(ctx->scratch_u32, 0, 256));
   *out = ctx.release();
   return RTM_OK;
@@ -1935,7 +1936,8 @@ extern "C" int rtm_normalize_image(rtm_ctx* ctx, const float* image_dev, const f
   if (!ctx || !image_dev || !illum_dev || !out_dev || n < 1 || !(eps_rel >= 0))
     return fail(RTM_E_INVAL, "bad arguments");
   HIP_OK(hipSetDevice(ctx->device));
-  HIP_OK(launch_normalize(image_dev, illum_dev, n, eps_rel, out_dev, ctx->scratch_u32 + 2, ctx->stream));
+  HIP_OK(launch_normalize(image_dev, illum_dev, n, eps_rel, out_dev, reinterpret_cast<float*>(ctx->scratch_f64),
+                          ctx->stream));
   return RTM_OK;
 }
 

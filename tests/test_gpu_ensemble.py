@@ -214,6 +214,36 @@ def test_explicit_stats_maps_and_filter(rtm):
         assert oracle.rel_l2(host(out), ref) <= 1e-6
 
 
+
+def test_maps_and_filter_at_image_size(rtm):
+    """The Stage-3 maps, the post-stack filter and the source-normalised image
+    at the paper's image size (351 x 1701 = 597051 pixels: every workgroup of
+    the grid-stride launches busy, a ragged last row of blocks), element by
+    element against the oracle; about a quarter of the pixels fall below
+    min_count."""
+    rng = np.random.default_rng(12)
+    nz, nx = 351, 1701
+    std = np.abs(rng.standard_normal((nz, nx)))
+    mean = rng.standard_normal((nz, nx))
+    cnt = rng.integers(0, 8, (nz, nx)).astype(np.int32)
+    img = rng.standard_normal((nz, nx)).astype(np.float32)
+    ill = rng.random((nz, nx)).astype(np.float32)
+    with rtm.Context(0, arena_bytes=64 << 20) as ctx:
+        conf = torch.empty(nz, nx, dtype=torch.float64, device="cuda")
+        ctx.confidence_map(dev(std, torch.float64), dev(cnt, torch.int32), conf, min_count=2)
+        assert np.abs(host(conf) - oracle.confidence_index(std, cnt, min_count=2)).max() <= 1e-15
+        ratio = torch.empty_like(conf)
+        ctx.ratio_map(dev(std, torch.float64), dev(mean, torch.float64), ratio, eps=1e-3)
+        np.testing.assert_allclose(host(ratio), oracle.ratio_map(std, mean, eps=1e-3), rtol=1e-15, atol=0)
+        out = torch.empty(nz, nx, device="cuda")
+        ctx.laplacian_filter(dev(img), 10.0, 12.5, out)
+        ref = oracle.laplacian_filter(img.astype(np.float64), 10.0, 12.5)
+        assert oracle.rel_l2(host(out), ref) <= 1e-6
+        ctx.normalize_image(dev(img), dev(ill), out, eps_rel=1e-3)
+        i64, l64 = img.astype(np.float64), ill.astype(np.float64)
+        assert oracle.rel_l2(host(out), i64 / (l64 + 1e-3 * l64.max())) <= 1e-6
+
+
 def test_nonfinite_fails_only_its_job(rtm):
     """A job whose data hold a NaN fails with RTM_E_NONFINITE; the jobs around
     it finish normally.  A NaN velocity is refused at submit.  On the plain
