@@ -123,7 +123,8 @@ double rtm_cfl_limit(void);
 
 /* ---- context --------------------------------------------------------- */
 
-/* Create a context on HIP device `device`.
+/* Create a context on HIP device `device`: the device memory and streams
+ * every migration of the Monte Carlo loop (Sec. 3, Stage 2) runs in.
  *   arena_dev, arena_bytes: caller-owned device buffer the library
  *     sub-allocates all its working memory from (wavefields, snapshot and
  *     boundary storage, per-job images, statistics).  It must stay alive
@@ -147,7 +148,9 @@ int rtm_ctx_synchronize(rtm_ctx *ctx);
 /* Forward modelling of one shot over the whole model (Eq. 4 with the
  * wavelet as source term; Sec. 2.2).
  *   vel_dev [nz][nx] velocity (m/s); wavelet_dev [nt] source samples w^n;
- *   src: source node; rec_host [nrec]: receiver nodes (copied at call time);
+ *   src: source node; rec_host [nrec]: receiver nodes (copied at call time),
+ *     pairwise distinct (a repeated node is RTM_E_INVAL: every call adds one
+ *     sample per node, so results do not depend on the order of additions);
  *   traces_dev [nt][nrec] out: d[n][r] = u^n(r);
  *   final_field_dev [nz][nx] out (nullable): u^{nt-1} on the model grid.
  * Errors: RTM_E_INVAL (bad sizes/nodes), RTM_E_CFL, RTM_E_NOMEM. */
@@ -167,12 +170,13 @@ int rtm_born(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev, const flo
              float *dtraces_dev);
 
 /* Reverse time migration of one shot on the aperture window
- * [ix0, ix0 + width) of the model (Sec. 2.2, Eq. 5 numerator; Listing 1's
- * per-shot forward + adjoint pair).
+ * [ix0, ix0 + width) of the model (Sec. 2.2, Eq. 5 numerator; the per-shot
+ * forward + adjoint pair of the paper's migration code).
  *   vel_dev [nz][nx]: migration velocity; the window's sponge takes the
  *     window's edge velocities.
  *   data_dev [nt][nrec]: seismogram injected at the receivers.
- *   src, rec_host: nodes inside the window (model coordinates).
+ *   src, rec_host: nodes inside the window (model coordinates); receivers
+ *     pairwise distinct, as in rtm_propagate.
  *   opts: source-wavefield mode, snapshot dtype and stride, flags.
  *   image_dev [nz][nx]: the shot image is ADDED into columns [ix0, ix0+width)
  *     (stack over shots).  illum_dev likewise (nullable; needs RTM_IMG_ILLUM).
@@ -211,16 +215,29 @@ int rtm_migrate_batch(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
                       const float *wavelet_dev, int32_t nshots, const rtm_shot_desc *shots_host,
                       const rtm_img_opts *opts, float *image_dev, float *illum_dev);
 
-/* ---- ensemble / serving path ----------------------------------------- */
+/* ---- ensemble / serving path ------------------------------------------
+ *
+ * Stage 2 migrates the seismograms for every velocity sample of Stage 1,
+ * RTM wrapped in a Monte Carlo loop (Sec. 1; Sec. 2.2, last paragraph), and
+ * the paper farms the migrations out as subgroups, each starting as soon as
+ * the previous one finishes, with every migration checking its own CFL
+ * condition (Sec. 3, Stage 2).  Here the subgroups become jobs of one
+ * device: a scheduler thread admits queued jobs whenever arena memory frees
+ * up and advances every admitted job in the same kernel launches
+ * (continuous batching); finished images feed per-sample statistics on the
+ * device (Sec. 2.3, Stage 3). */
 
-/* Register velocity sample `realization` (copied into the arena; v_max is
- * cached for the per-job CFL check).  Model size must equal the context's
- * first registered model.  Re-registering a realization replaces it (only
- * when no job of it is queued or running). */
+/* Register velocity sample `realization` (Sec. 3, Stage 2: one migration
+ * set per velocity sample).  The velocity is copied into the arena and v_max
+ * cached for the per-job CFL check.  Model size must equal the context's
+ * other registered models.  Re-registering a realization replaces it, only
+ * when no job of it is queued or running (RTM_E_AGAIN otherwise, also when a
+ * job of it was submitted while the call ran). */
 int rtm_model_register(rtm_ctx *ctx, int32_t realization, const float *vel_dev, int32_t nz,
                        int32_t nx, const rtm_grid *grid);
 
-/* One RTM job of a stream (velocity sample x shot x aperture x nt). */
+/* One RTM job of a stream (velocity sample x shot x aperture x nt): one
+ * member of a subgroup of Sec. 3, Stage 2. */
 typedef struct {
     int32_t realization;
     rtm_point src;             /* model coordinates */
@@ -240,9 +257,13 @@ enum {
     RTM_JOB_ACC_STACK = 2u  /* add the job image to its realization's FP32 stack */
 };
 
-/* Queue a job (non-blocking).  Validation and the CFL check (cached v_max)
- * happen here; a job larger than the whole arena returns RTM_E_NOMEM, a
- * full queue RTM_E_AGAIN.  Memory pressure only delays admission. */
+/* Queue a job (non-blocking; Sec. 3, Stage 2: a migration starts as soon as
+ * room frees up).  Validation and the CFL check (cached v_max; each
+ * migration checks its own CFL condition) happen here; a job larger than the
+ * whole arena returns RTM_E_NOMEM, a full queue RTM_E_AGAIN.  Memory pressure
+ * only delays admission: queued jobs are admitted first come, first served,
+ * except that while the oldest waiting job does not fit, later jobs that do
+ * fit may pass it, at most 8 times. */
 int rtm_ensemble_submit(rtm_ctx *ctx, const rtm_job *job, uint64_t *ticket);
 
 /* Job state and timing. */
@@ -255,21 +276,25 @@ typedef struct {
     uint64_t user_tag;
 } rtm_job_info;
 
-/* Non-blocking status query.  When the job is DONE and image_dev is not
+/* Non-blocking status query of a submitted job (Sec. 3, Stage 2).  When
+ * the job is DONE and image_dev is not
  * NULL, its [nz][width] image is copied there (stream-ordered on the
  * context stream).  A DONE/FAILED/CANCELLED job is forgotten after a poll
  * that passes release = 1. */
 int rtm_ensemble_poll(rtm_ctx *ctx, uint64_t ticket, rtm_job_info *info, float *image_dev,
                       int32_t release);
 
-/* Cancel a queued job (running jobs finish).  RTM_E_NOTFOUND if unknown. */
+/* Cancel a queued job (running jobs finish; RTM_E_INVAL once admitted).
+ * RTM_E_NOTFOUND if unknown. */
 int rtm_ensemble_cancel(rtm_ctx *ctx, uint64_t ticket);
 
-/* Block until every submitted job has finished (DONE, FAILED or CANCELLED). */
+/* Block until every submitted job has finished (DONE, FAILED or CANCELLED):
+ * the end of the Monte Carlo loop over samples (Sec. 3, Stage 2). */
 int rtm_ensemble_drain(rtm_ctx *ctx);
 
 /* Running per-pixel statistics of a realization's job images (FP64
- * Welford; a pixel's samples are the images whose window covers it).
+ * Welford; a pixel's samples are the images whose window covers it): the
+ * mean and standard-deviation maps of Stage 3 (Sec. 2.3).
  *   mean_dev, std_dev [nz][nx] double (nullable), count_dev [nz][nx] int32
  *   (nullable).  std is the sample standard deviation (n - 1); 0 where
  *   count < 2.  Stream-ordered after every finished job's update. */
@@ -277,7 +302,8 @@ int rtm_ensemble_stats(rtm_ctx *ctx, int32_t realization, double *mean_dev, doub
                        int32_t *count_dev);
 
 /* FP32 shot stack of a realization (sum of its RTM_JOB_ACC_STACK job
- * images, window-placed) copied to stack_dev [nz][nx]. */
+ * images, window-placed; the stacked section of Fig. 2) copied to
+ * stack_dev [nz][nx]. */
 int rtm_ensemble_stack(rtm_ctx *ctx, int32_t realization, float *stack_dev);
 
 /* ---- ensemble statistics over explicit images (Sec. 2.3) ------------- */

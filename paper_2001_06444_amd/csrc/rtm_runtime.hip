@@ -377,10 +377,8 @@ static int env_tz() {
   return (tz == 16 || tz == 32 || tz == 64) ? tz : 0;
 }
 
-static int choose_tz(rtm_ctx* ctx) {
-  if (int tz = env_tz()) return tz;
-  return ctx->tile_z ? ctx->tile_z : 16;
-}
+// Tile height of the last launch set (forced or tuned).
+static int choose_tz(rtm_ctx* ctx) { return ctx->tile_z ? ctx->tile_z : 16; }
 
 // Every pointer a job's kernels dereference, for the job's mode, must be set
 // before the job reaches a launch.
@@ -595,6 +593,18 @@ static int check_job(const JobGeom& g, rtm_point src, const rtm_point* recs) {
   for (int r = 0; r < g.nrec; ++r)
     if (!inside(recs[r]))
       return fail(RTM_E_INVAL, "receiver %d (%d, %d) outside the window", r, recs[r].iz, recs[r].ix);
+  // Receivers must be distinct nodes: the step kernels add each receiver's
+  // sample into its node with one atomic add per receiver, which is exact
+  // (order-free) only while every node receives at most one sample.
+  if (g.nrec > 1) {
+    std::vector<std::pair<int64_t, int>> key(g.nrec);
+    for (int r = 0; r < g.nrec; ++r) key[r] = {(int64_t)recs[r].iz * g.model_nx + recs[r].ix, r};
+    std::sort(key.begin(), key.end());
+    for (int r = 1; r < g.nrec; ++r)
+      if (key[r].first == key[r - 1].first)
+        return fail(RTM_E_INVAL, "receivers %d and %d are the same node (%d, %d)", key[r - 1].second, key[r].second,
+                    recs[key[r].second].iz, recs[key[r].second].ix);
+  }
   return RTM_OK;
 }
 
@@ -626,8 +636,9 @@ static void tune_file_load(rtm_ctx* ctx) {
   while (fgets(line, sizeof line, f)) {
     char key[400];
     int tz;
-    if (sscanf(line, " \"%399[^\"]\" : %d", key, &tz) == 2 && (tz == 16 || tz == 32 || tz == 64))
-      ctx->tune_cache[key] = tz;
+    if (sscanf(line, " \"%399[^\"]\" : %d", key, &tz) != 2) continue;
+    const bool two = strstr(key, "/step2/") != nullptr;
+    if (two ? (tz == 16 || tz == 24 || tz == 32) : (tz == 16 || tz == 32 || tz == 64)) ctx->tune_cache[key] = tz;
   }
   fclose(f);
 }
@@ -657,7 +668,7 @@ static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* 
                    float* ms_out);
 
 static int autotune_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch) {
-  if (int tz = env_tz()) return tz;
+  if (int tz = env_tz()) return ctx->tile_z = tz;
   std::lock_guard<std::mutex> lk(ctx->tune_mu);
   if (!ctx->tune_file_loaded) tune_file_load(ctx);
   const std::string key = tune_key(g0, batch);
@@ -680,8 +691,10 @@ static int autotune_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const flo
       best_ms = best_of[c];
       best = cand[c];
     }
-  ctx->tune_cache[key] = best;
-  tune_file_save(ctx);
+  if (best_ms < 1e30f) {  // keep only measured choices
+    ctx->tune_cache[key] = best;
+    tune_file_save(ctx);
+  }
   return ctx->tile_z = best;
 }
 
@@ -708,17 +721,16 @@ struct Table {
   std::shared_ptr<std::vector<Tile>> htiles;
 };
 
-// Two-step tile height, both phases: 24 rows by default (on the 100-shot
-// 351 x 1701 faulted-layer survey, 757 against 776 us per backward pair with
-// 16 rows and 373 against 388 us per forward pair with 32; 20 and 28 rows
-// were no faster).  RTM_TILE_Z2 = 16, 24 or 32 sets the height; 0, or any
-// other value, turns two-step launches off.
+// Two-step tile height.  RTM_TILE_Z2 unset: the tuner picks the height of
+// each phase (autotune_tz2); 16, 24 or 32 forces that height for both
+// phases; 0, or any other value, turns two-step launches off.
 static int env_tz2() {
   const char* e = getenv("RTM_TILE_Z2");
-  if (!e) return 24;
+  if (!e) return -1;
   const int v = atoi(e);
   return v == 16 || v == 24 || v == 32 ? v : 0;
 }
+static bool two_step_on() { return env_tz2() != 0; }
 
 // A two-step tile reads 8 rows past its last row, and the staged rows of the
 // last tile column run past the row end into the next row: the last tile
@@ -892,6 +904,134 @@ static int time_tz(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* 
   release_blocks(ctx, t.blocks);
   release_blocks(ctx, scratch);
   return rc;
+}
+
+// Two-step tile heights (forward phase, backward phase) of a batch of
+// reconstruct-mode jobs.  For each height that fits the geometry (16, 24,
+// 32 rows; tz2_fits), scratch jobs of the batch's widest window (B =
+// min(batch, 16) sharing one medium, nt = 24, zero data) run their two-step
+// launches of each phase, timed with HIP events; three rounds, best trial
+// per height, fastest height per phase.  Cached per geometry key in the
+// context and the RTM_AUTOTUNE_CACHE file like the one-step heights.
+static int time_tz2(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch, int tz2,
+                    float* ms_fwd, float* ms_bwd) {
+  const int B = std::max(1, std::min(batch, 16));
+  JobGeom g = g0;
+  g.nt = 24;
+  g.nrec = g.width;
+  g.flags = 0;
+  g.mode = kModeRecon;
+  g.nbuf = 4;
+  std::vector<Block> scratch;
+  void* zero = nullptr;
+  if (!alloc_block(ctx, scratch, (size_t)g.nt * g.width * 4 + 256, &zero)) return RTM_E_NOMEM;
+  HIP_OK(hipMemsetAsync(zero, 0, (size_t)g.nt * g.width * 4 + 256, s));
+  std::vector<rtm_point> recs(g.width);
+  for (int r = 0; r < g.width; ++r) recs[r] = {0, g.ix0 + r};
+  rtm_point src{g.nz / 2, g.ix0 + g.width / 2};
+  std::vector<std::unique_ptr<HostJob>> jobs;
+  std::vector<HostJob*> ptrs;
+  int rc = RTM_OK;
+  for (int b = 0; b < B && rc == RTM_OK; ++b) {
+    auto j = std::make_unique<HostJob>();
+    rc = build_job(ctx, s, g, 16, vel, static_cast<const float*>(zero), src, recs.data(),
+                   static_cast<const float*>(zero), nullptr, *j, jobs.empty() ? nullptr : jobs[0].get());
+    if (rc == RTM_OK) {
+      ptrs.push_back(j.get());
+      jobs.push_back(std::move(j));
+    }
+  }
+  Table t;
+  if (rc == RTM_OK && !tz2_fits(ptrs, tz2)) rc = RTM_E_INVAL;  // this height does not fit: skip it
+  if (rc == RTM_OK) rc = upload_table(ctx, s, ptrs, t, tz2, tz2);
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (rc == RTM_OK) {
+    for (auto& ev : e) (void)hipEventCreate(&ev);
+    const int nf = g.nt - 1, nsteps = 2 * g.nt - 1;
+    hipError_t er = hipSuccess;
+    // forward pairs at steps 0, 2, ..; the first two are not timed
+    int nfw = 0, nbw = 0;
+    for (int st = 0; st + 1 < nf && er == hipSuccess; st += 2) {
+      if (st == 4) er = hipEventRecord(e[0], s);
+      if (er == hipSuccess) er = launch_step2(tz2, kPhFwd, t.jobs, t.fw.tiles, t.fw.recs, t.fw.ntiles, t.ctl, 0, st, s);
+      nfw += st >= 4;
+    }
+    if (er == hipSuccess) er = hipEventRecord(e[1], s);
+    // backward pairs from level nt - 3 down (steps nf + 2, nf + 4, ..)
+    for (int st = nf + 2, k = 0; st + 1 < nsteps && er == hipSuccess; st += 2, ++k) {
+      if (k == 2) er = hipEventRecord(e[2], s);
+      if (er == hipSuccess) er = launch_step2(tz2, kPhBwd, t.jobs, t.bw.tiles, t.bw.recs, t.bw.ntiles, t.ctl, 0, st, s);
+      nbw += k >= 2;
+    }
+    if (er == hipSuccess) er = hipEventRecord(e[3], s);
+    if (er != hipSuccess) rc = fail(RTM_E_DEVICE, "tuning launch failed: %s", hipGetErrorString(er));
+    (void)hipStreamSynchronize(s);
+    float a = 0, b = 0;
+    if (rc == RTM_OK && nfw > 0 && nbw > 0 && hipEventElapsedTime(&a, e[0], e[1]) == hipSuccess &&
+        hipEventElapsedTime(&b, e[2], e[3]) == hipSuccess) {
+      *ms_fwd = a / nfw;
+      *ms_bwd = b / nbw;
+    } else if (rc == RTM_OK) {
+      rc = RTM_E_INVAL;
+    }
+    for (auto ev : e)
+      if (ev) (void)hipEventDestroy(ev);
+  }
+  (void)hipStreamSynchronize(s);
+  for (auto& j : jobs) {
+    release_blocks(ctx, j->blocks);
+    if (j->image_blk.p) ctx->arena.release(j->image_blk.p, j->image_blk.n);
+  }
+  release_blocks(ctx, t.blocks);
+  release_blocks(ctx, scratch);
+  return rc;
+}
+
+static std::string tune_key2(const JobGeom& g, int batch) {
+  int b = batch <= 1 ? 1 : batch <= 4 ? 4 : batch <= 16 ? 16 : 64;
+  char buf[128];
+  snprintf(buf, sizeof buf, "gfx950/step2/nzp%d/nxp%d/b%d", g.nz + 2 * g.nb, g.width + 2 * g.nb, b);
+  return buf;
+}
+
+static void autotune_tz2(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float* vel, int batch, int* tzf,
+                         int* tzb) {
+  const int forced = env_tz2();
+  if (forced >= 0) {
+    *tzf = *tzb = forced;
+    return;
+  }
+  std::lock_guard<std::mutex> lk(ctx->tune_mu);
+  if (!ctx->tune_file_loaded) tune_file_load(ctx);
+  const std::string key = tune_key2(g0, batch);
+  auto f = ctx->tune_cache.find(key + "/fwd"), b = ctx->tune_cache.find(key + "/bwd");
+  if (f != ctx->tune_cache.end() && b != ctx->tune_cache.end()) {
+    *tzf = f->second;
+    *tzb = b->second;
+    return;
+  }
+  const int cand[3] = {16, 24, 32};
+  float bf[3] = {1e30f, 1e30f, 1e30f}, bb[3] = {1e30f, 1e30f, 1e30f};
+  for (int round = 0; round < 3; ++round)
+    for (int c = 0; c < 3; ++c) {
+      float mf = 0, mb = 0;
+      if (time_tz2(ctx, s, g0, vel, batch, cand[c], &mf, &mb) == RTM_OK) {  // no fit / no room: skip
+        bf[c] = std::min(bf[c], mf);
+        bb[c] = std::min(bb[c], mb);
+      }
+    }
+  int kf = 0, kb = 0;  // 16 rows unless a measured height is faster
+  for (int c = 1; c < 3; ++c) {
+    if (bf[c] < bf[kf]) kf = c;
+    if (bb[c] < bb[kb]) kb = c;
+  }
+  *tzf = cand[kf];
+  *tzb = cand[kb];
+  if (bf[kf] < 1e30f && bb[kb] < 1e30f) {  // keep only measured choices
+    ctx->tune_cache[key + "/fwd"] = *tzf;
+    ctx->tune_cache[key + "/bwd"] = *tzb;
+    tune_file_save(ctx);
+  }
 }
 
 // ===========================================================================
@@ -1261,7 +1401,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (int i = 0; i < nshots; ++i) {
     if ((rc = fill_geom_rtm(grid, shots[i].ix0, shots[i].width, opts, shots[i].nrec, geoms[i]))) return rc;
     if (illum_dev) geoms[i].flags |= RTM_IMG_ILLUM;
-    if (geoms[i].mode == kModeRecon && !illum_dev && env_tz2() > 0)
+    if (geoms[i].mode == kModeRecon && !illum_dev && two_step_on())
       geoms[i].nbuf = 4;  // two-step launches
     if ((rc = check_job(geoms[i], shots[i].src, shots[i].rec_host))) return rc;
     if (shots[i].nrec > 0 && !shots[i].data_dev) return fail(RTM_E_INVAL, "shot %d has no data", i);
@@ -1292,6 +1432,9 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (int i = 1; i < nshots; ++i)
     if (geoms[i].width > geoms[widest].width) widest = i;
   const int tz = autotune_tz(ctx, s, geoms[widest], vel_dev, nshots);
+  // two-step heights, tuned before the batch takes its arena blocks
+  int tz2f = 0, tz2b = 0;
+  if (geoms[widest].nbuf == 4) autotune_tz2(ctx, s, geoms[widest], vel_dev, nshots, &tz2f, &tz2b);
   std::vector<std::unique_ptr<HostJob>> jobs;
   std::vector<HostJob*> ptrs;
   auto cleanup = [&]() {
@@ -1319,7 +1462,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     jobs.push_back(std::move(j));
   }
   Table t;
-  if ((rc = upload_table(ctx, s, ptrs, t, env_tz2(), env_tz2()))) {
+  if ((rc = upload_table(ctx, s, ptrs, t, tz2f, tz2b))) {
     cleanup();
     return rc;
   }
@@ -1426,8 +1569,26 @@ extern "C" int rtm_model_register(rtm_ctx* ctx, int32_t realization, const float
     return e != hipSuccess ? fail(RTM_E_DEVICE, "copy failed: %s", hipGetErrorString(e)) : rc;
   }
   lk.lock();
+  // Re-check under the lock: a job of this realization may have been queued,
+  // or a model of another size registered, while the copy ran unlocked.
+  auto again = ctx->models.find(realization);
+  const bool busy = again != ctx->models.end() && again->second.active > 0;
+  bool other_size = false;
+  for (auto& kv : ctx->models)
+    if (kv.first != realization && (kv.second.nz != nz || kv.second.nx != nx)) other_size = true;
+  if (busy || other_size) {
+    ctx->arena.release(vb.p, vb.n);  // the copy and the v_max pass have finished (synchronised)
+    return busy ? fail(RTM_E_AGAIN, "realization %d has jobs in flight", realization)
+                : fail(RTM_E_INVAL, "all registered models must share one size");
+  }
   Model& m = ctx->models[realization];
-  if (m.vel.p) ctx->arena.release(m.vel.p, m.vel.n);
+  if (m.vel.p) {
+    // jobs that read the old velocity have finished, but release it behind
+    // whatever the scheduler stream still holds
+    Deferred d;
+    d.blocks.push_back(m.vel);
+    if (int drc = defer(ctx, ctx->sched_stream, std::move(d))) return drc;
+  }
   m.nz = nz;
   m.nx = nx;
   m.grid = *grid;
@@ -1479,24 +1640,39 @@ extern "C" int rtm_ensemble_submit(rtm_ctx* ctx, const rtm_job* job, uint64_t* t
   return RTM_OK;
 }
 
+// Allocates a realization's statistics (mean, M2, count) and stack on first
+// use.  All-or-nothing: the three statistics blocks are taken together or
+// not at all, so a Model never holds a partial set (a later job would
+// otherwise be admitted and its Welford update write through a null M2).
 static int ensure_stats(rtm_ctx* ctx, hipStream_t s, Model& m, bool stats, bool stack) {
   const size_t n = (size_t)m.nz * m.nx;
   if (stats && !m.mean.p) {
-    m.mean = {arena_alloc(ctx, n * 8), align256(n * 8)};
-    m.m2 = {arena_alloc(ctx, n * 8), align256(n * 8)};
-    m.count = {arena_alloc(ctx, n * 4), align256(n * 4)};
-    if (!m.mean.p || !m.m2.p || !m.count.p) return fail(RTM_E_NOMEM, "arena exhausted (statistics)");
-    HIP_OK(hipMemsetAsync(m.mean.p, 0, n * 8, s));
-    HIP_OK(hipMemsetAsync(m.m2.p, 0, n * 8, s));
-    HIP_OK(hipMemsetAsync(m.count.p, 0, n * 4, s));
+    Block mean{arena_alloc(ctx, n * 8), align256(n * 8)};
+    Block m2{mean.p ? arena_alloc(ctx, n * 8) : nullptr, align256(n * 8)};
+    Block count{m2.p ? arena_alloc(ctx, n * 4) : nullptr, align256(n * 4)};
+    if (!mean.p || !m2.p || !count.p) {
+      ctx->arena.release(mean.p, mean.n);
+      ctx->arena.release(m2.p, m2.n);
+      ctx->arena.release(count.p, count.n);
+      return fail(RTM_E_NOMEM, "arena exhausted (statistics)");
+    }
+    HIP_OK(launch_fill_u32(static_cast<uint32_t*>(mean.p), 0, (int64_t)(n * 2), s));
+    HIP_OK(launch_fill_u32(static_cast<uint32_t*>(m2.p), 0, (int64_t)(n * 2), s));
+    HIP_OK(launch_fill_u32(static_cast<uint32_t*>(count.p), 0, (int64_t)n, s));
+    m.mean = mean;
+    m.m2 = m2;
+    m.count = count;
   }
   if (stack && !m.stack.p) {
-    m.stack = {arena_alloc(ctx, n * 4), align256(n * 4)};
-    if (!m.stack.p) return fail(RTM_E_NOMEM, "arena exhausted (stack)");
-    HIP_OK(hipMemsetAsync(m.stack.p, 0, n * 4, s));
+    Block st{arena_alloc(ctx, n * 4), align256(n * 4)};
+    if (!st.p) return fail(RTM_E_NOMEM, "arena exhausted (stack)");
+    HIP_OK(launch_fill_u32(static_cast<uint32_t*>(st.p), 0, (int64_t)n, s));
+    m.stack = st;
   }
   return RTM_OK;
 }
+
+static bool has_stats(const Model& m) { return m.mean.p && m.m2.p && m.count.p; }
 
 struct SchedTables {
   std::vector<Block> blocks;
@@ -1703,7 +1879,7 @@ static void sched_main(rtm_ctx* ctx) {
         Model& m = ctx->models[ej->spec.realization];
         const int jrc = rc ? rc : (health[fi] ? RTM_E_NONFINITE : RTM_OK);
         if (!jrc) {
-          if ((ej->spec.flags & RTM_JOB_ACC_STATS) && m.mean.p)
+          if ((ej->spec.flags & RTM_JOB_ACC_STATS) && has_stats(m))
             (void)launch_welford(static_cast<double*>(m.mean.p), static_cast<double*>(m.m2.p),
                                  static_cast<int32_t*>(m.count.p), m.nx, j.d.image + j.g.nb, j.d.pitch,
                                  j.g.nz, j.g.width, j.g.ix0, s);
@@ -1819,7 +1995,7 @@ extern "C" int rtm_ensemble_stats(rtm_ctx* ctx, int32_t realization, double* mea
   const int64_t n = (int64_t)m.nz * m.nx;
   HIP_OK(hipSetDevice(ctx->device));
   HIP_OK(hipStreamSynchronize(ctx->sched_stream));
-  if (!m.mean.p) {
+  if (!has_stats(m)) {
     if (mean_dev) HIP_OK(hipMemsetAsync(mean_dev, 0, n * 8, ctx->stream));
     if (std_dev) HIP_OK(hipMemsetAsync(std_dev, 0, n * 8, ctx->stream));
     if (count_dev) HIP_OK(hipMemsetAsync(count_dev, 0, n * 4, ctx->stream));

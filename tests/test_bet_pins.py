@@ -233,3 +233,50 @@ def test_informative_data_lowers_the_misfit():
     first = bet.run(cfg, srcs, recs, tt, 0)["misfit"]
     later = bet.run(cfg, srcs, recs, tt, 400)["misfit"]
     assert np.all(later <= first) and np.median(later) < 0.2 * np.median(first)
+
+
+def _chain_setup():
+    nz, nx, h = 12, 40, 100.0
+    true = np.where(np.arange(nz)[:, None] < 5, 1800.0, 3200.0) * np.ones((1, nx))
+    srcs = [(0, j) for j in range(0, nx, 8)]
+    recs = [(0, j) for j in range(nx)]
+    tt = bet.travel_times(true, h, srcs, recs, single=False).astype(np.float32)
+    return nz, nx, h, srcs, recs, tt
+
+
+def _one_chain(single, chain, seed, iters):
+    nz, nx, h, srcs, recs, tt = _chain_setup()
+    cfg = bet.BetConfig(nz=nz, nx=nx, h=h, chains=1, chain0=chain, k_min=2, k_max=20, k_init=6,
+                        sigma=0.004, move_dz=200.0, move_dx=600.0, seed=seed, burn_in=300, thin=4,
+                        single=single)
+    return bet.run(cfg, srcs, recs, tt, iters, log=True)
+
+
+def _layer_means(runs):
+    """Per-chain pooled mean velocity over the rows above and below the
+    interface (rows 0-4 and 6-11), and the per-chain final k."""
+    m = np.stack([r["mean"] for r in runs])
+    return m[:, :5].mean(axis=(1, 2)), m[:, 6:].mean(axis=(1, 2)), np.array([r["k"][0] for r in runs], float)
+
+
+def test_fast_sweeping_chains_sample_the_fast_marching_posterior():
+    """Sec. 2.1 and Sec. 3 compute first arrivals with fast marching (FaATSO);
+    the sampler's accept decisions use single-precision fast sweeping, which
+    solves the same discrete Godunov equations.  Chains driven by each
+    (common random numbers) must take the same accept decisions, and chains
+    of double-precision fast marching with other random numbers must give
+    the same posterior means (pooled velocity above and below the interface,
+    number of cells) within Monte Carlo error, estimated from the spread of
+    independent chains."""
+    C, iters = 8, 1200
+    fsm = [_one_chain(True, c, 11, iters) for c in range(C)]
+    fmm = [_one_chain(False, c, 11, iters) for c in range(C)]
+    agree = np.mean([(a["log"] == b["log"]).mean() for a, b in zip(fsm, fmm)])
+    assert agree >= 0.99, agree
+    other = [_one_chain(False, c, 12, iters) for c in range(C)]
+    for a, b in zip(_layer_means(fsm), _layer_means(other)):
+        se = np.sqrt(a.var(ddof=1) / C + b.var(ddof=1) / C)
+        assert abs(a.mean() - b.mean()) <= 4.0 * se, (a.mean(), b.mean(), se)
+    # the data resolve the two layers: the sampled means sit near 1800 / 3200 m/s
+    up, lo, _ = _layer_means(fsm)
+    assert 1700 < up.mean() < 2200 and 3000 < lo.mean() < 3500

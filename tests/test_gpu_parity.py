@@ -8,6 +8,7 @@ The FP32 propagation error of the two-layer survey is ~1e-5 at nt = 1000,
 so these bounds leave a 5-10x margin.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -189,10 +190,11 @@ def test_dot_product_oracle_born_vs_gpu_migration(rtm, ctx, mode):
 
 @pytest.mark.parametrize("mode,dtype,stride", [("reconstruct", "fp32", 1), ("store", "fp32", 3),
                                                ("store", "fp16", 2)])
-@pytest.mark.parametrize("tz", [None])
+@pytest.mark.parametrize("tz", [16, 32, 64, None])
 def test_ragged_window_matches_oracle(rtm, ctx, mode, dtype, stride, tz):
     """A window that starts inside the model, spans 2+ tiles with a ragged
-    edge in both directions, receivers on a subset of columns."""
+    edge in both directions, receivers on a subset of columns; with each
+    one-step tile height forced (RTM_TILE_Z) and with the tuner's choice."""
     rng = np.random.default_rng(4)
     nz, nx_model, h, dt, nt, nb = 77, 300, 10.0, 1e-3, 350, 13
     vel = 1800.0 + 400.0 * rng.random((nz, nx_model))
@@ -206,9 +208,20 @@ def test_ragged_window_matches_oracle(rtm, ctx, mode, dtype, stride, tz):
                                 stride=stride)
     g = grid_of(rtm, nz, nx_model, nb, nt, h, dt)
     img = torch.zeros(nz, nx_model, device="cuda")
-    ctx.migrate_shot(g, dev(vel), dev(w), src, rec, dev(d), ix0, width,
-                     rtm.img_opts(mode, dtype, stride), img)
-    out = host(img)
+    old = os.environ.pop("RTM_TILE_Z", None)
+    try:
+        if tz is not None:
+            os.environ["RTM_TILE_Z"] = str(tz)
+        ctx.migrate_shot(g, dev(vel), dev(w), src, rec, dev(d), ix0, width,
+                         rtm.img_opts(mode, dtype, stride), img)
+        out = host(img)
+        used = ctx.stats().tile_z
+    finally:
+        os.environ.pop("RTM_TILE_Z", None)
+        if old is not None:
+            os.environ["RTM_TILE_Z"] = old
+    if tz is not None:
+        assert used == tz
     assert not out[:, :ix0].any() and not out[:, ix0 + width:].any()
     tol = 1e-4 if dtype == "fp32" else 1e-2
     assert oracle.rel_l2(out[:, ix0:ix0 + width], ref) <= tol
@@ -271,6 +284,14 @@ def test_validation_errors(rtm, ctx):
     with pytest.raises(rtm.RTMError) as e:  # window too small to reconstruct
         ctx.migrate_shot(ok, vel, w, (5, 5), [(1, 5)], d, 0, 8, rtm.img_opts(), img)
     assert e.value.code == -1
+    d3 = torch.zeros(50, 4, device="cuda")
+    with pytest.raises(rtm.RTMError) as e:  # three receivers on one node (and one elsewhere)
+        ctx.migrate_shot(ok, vel, w, (5, 5), [(1, 7), (2, 3), (1, 7), (1, 7)], d3, 0, 40, rtm.img_opts(), img)
+    assert e.value.code == -1 and "same node" in str(e.value)
+    tr = torch.zeros(50, 2, device="cuda")
+    with pytest.raises(rtm.RTMError) as e:  # also when modelling
+        ctx.propagate(ok, vel, w, (5, 5), [(3, 3), (3, 3)], tr)
+    assert e.value.code == -1
     assert not host(img).any()  # rejected calls did no device work
     # padded window 8201 x 138192: a wavefield would hold over 2^30 floats,
     # past what the kernels' 32-bit byte offsets address
@@ -291,14 +312,13 @@ def test_validation_errors(rtm, ctx):
 @pytest.mark.parametrize("nt", [2, 3, 4, 5, 37])
 def test_two_step_launches_equal_one_step(rtm, ctx, nt, nb):
     """Reconstruct-mode batches advance two time steps per launch (two-step
-    tiles of 16, 24 or 32 rows, by default 24, or 16 where the last 24-row
-    tile would read past the field allocation; RTM_TILE_Z2=0 forces one step
-    per launch).  Every setting, with short and odd step counts (an odd last
+    tiles of 16, 24 or 32 rows, by default the tuner's choice per phase, or
+    16 where the last 24-row tile would read past the field allocation;
+    RTM_TILE_Z2=0 forces one step per launch).  Every setting, with short and odd step counts (an odd last
     step, the two one-step launches that open the backward phase), must equal
     the plain path bit for bit.  nb = 9 gives 63 padded rows, allocated as 64,
     where 24-row tiles do not fit; nb = 10 gives 65 (a ragged last tile of
     each height)."""
-    import os
     rng = np.random.default_rng(nt)
     nz, nx, h, dt = 45, 131, 10.0, 1e-3
     vel = inputs.smooth_slowness(1700 + 600 * rng.random((nz, nx)), 30.0, h, h)
@@ -326,7 +346,12 @@ def test_two_step_launches_equal_one_step(rtm, ctx, nt, nb):
             assert torch.equal(plain, batch), (nt, tz2, (plain - batch).abs().max().item())
             st = ctx.stats()
             assert st.last_steps_per_launch == (2 if tz2 != "0" and nt >= 4 else 1)
-            rows = {"16": 16, "24": 24 if nb == 10 else 16, "32": 32, "0": 0}[tz2 or "24"]
+            if tz2 is None:  # the tuner's heights, one per phase, among those that fit
+                ok = (16, 24, 32) if nb == 10 else (16, 32)
+                assert (st.last_tile_z2_fwd in ok or nt < 3) and (st.last_tile_z2_bwd in ok or nt < 4), \
+                    (st.last_tile_z2_fwd, st.last_tile_z2_bwd)
+                continue
+            rows = {"16": 16, "24": 24 if nb == 10 else 16, "32": 32, "0": 0}[tz2]
             assert (st.last_tile_z2_fwd, st.last_tile_z2_bwd) == (rows if nt >= 3 else 0, rows if nt >= 4 else 0)
     finally:
         if old is None:

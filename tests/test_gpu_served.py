@@ -1,0 +1,274 @@
+"""The serving engine (rtm_ensemble_*) at the geometry of the ensemble and
+serving workloads, and continuous batching proper.
+
+  - Velocity-ensemble geometry (351 x 1701 at 10 m, nb 50, nt 3000,
+    apertures from the ensemble's width draw): two velocity samples x two
+    shots, reconstruct mode, served together; every image against the FP64
+    oracle (<= 1e-4) and the on-device FP64 mean / std maps against the
+    oracle's two-pass statistics of the oracle images, within the bound
+    that the measured image errors imply.
+  - Serving-stream geometry: two jobs of the Poisson stream (seed 5), one
+    FP32 and one BF16, stored every 4 steps, the BF16 one at least 1200
+    columns wide with nt >= 3000; against the oracle at 1e-4 / 1e-2.
+  - Jobs that arrive while another job runs are admitted before it
+    finishes, and every image equals the image of the same job run alone
+    (rtm_migrate_shot), bit for bit.
+  - Under memory pressure jobs wait (not fail), some job is admitted only
+    after another finished, and every image and the running statistics
+    equal the alone runs.
+
+Receiver data are seeded shot-record stand-ins (inputs.seismogram_like);
+migration is linear in the data, so parity does not need modelled data.
+The oracle runs with checkpointed source wavefields (identical to storing
+them all); each test takes the oracle well under a minute on 16 cores."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_06444_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NZ, NX, NB, H, DT = 351, 1701, 50, 10.0, 1e-3
+
+
+@pytest.fixture(scope="module")
+def rtm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_06444_amd import rtm as _rtm
+
+    return _rtm
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def smooth():
+    base = inputs.ensemble_base(NZ, NX, H)
+    return inputs.smooth_slowness(base, 40.0, H, H)
+
+
+def _sample(smooth, r):
+    """Velocity sample r of the ensemble: smooth model x (1 + 0.05 GRF_r)."""
+    return smooth * (1.0 + 0.05 * inputs.grf(r, NZ, NX, H))
+
+
+def _data(seed, nt, w):
+    return inputs.seismogram_like(seed, nt, w).astype(np.float64) * 1e-2
+
+
+def _serve(rtm, ctx, jobs, flags):
+    """Submits every job at once, drains, returns the [nz][w] images."""
+    keep, tickets = [], []
+    for j in jobs:
+        wv, d = dev(inputs.ricker(j["nt"], DT)), dev(j["data"])
+        keep += [wv, d]
+        tickets.append(ctx.submit(j["r"], j["src"], j["ix0"], j["w"], 1, j["nt"], wv, d, j["opts"], flags=flags))
+    ctx.drain()
+    images = []
+    for t, j in zip(tickets, jobs):
+        info = ctx.poll(t)
+        assert info.state == rtm.JOB_DONE and info.status == 0, (info.state, info.status)
+        img = torch.empty(NZ, j["w"], device="cuda")
+        ctx.poll(t, img, release=True)
+        images.append(host(img))
+    return images
+
+
+def _oracle_image(vel, j, stride=1):
+    rec = [(1, x) for x in range(j["ix0"], j["ix0"] + j["w"])]
+    return oracle.migrate_window(vel, j["ix0"], j["w"], inputs.ricker(j["nt"], DT), j["src"], rec, j["data"],
+                                 dz=H, dx=H, dt=DT, nb=NB, stride=stride, s_mode="checkpoint", ckpt=64)
+
+
+def test_served_ensemble_geometry_matches_oracle(rtm, smooth):
+    shots = inputs.ensemble_shots(16, NX)
+    nt = 3000
+    jobs = []
+    for r in (0, 1):
+        for k in (1, 2):  # widths 469 and 544, both windows from column 0: counts 1..4 per pixel
+            sh = shots[k]
+            jobs.append(dict(r=r, src=sh.src, ix0=sh.ix0, w=sh.width, nt=nt, data=_data(10 * r + k, nt, sh.width),
+                             opts=rtm.img_opts("reconstruct")))
+    vels = {r: _sample(smooth, r) for r in (0, 1)}
+    with rtm.Context(0, arena_bytes=4 << 30) as ctx:
+        g = rtm.make_grid(NZ, NX, NB, nt, H, H, DT)
+        for r, v in vels.items():
+            ctx.model_register(r, dev(v), g)
+        t0 = time.perf_counter()
+        images = _serve(rtm, ctx, jobs, rtm.JOB_ACC_STATS)
+        print(f"served 4 jobs in {time.perf_counter() - t0:.2f} s", flush=True)
+        stats = {}
+        for r in (0, 1):
+            mean = torch.empty(NZ, NX, dtype=torch.float64, device="cuda")
+            std = torch.empty_like(mean)
+            cnt = torch.empty(NZ, NX, dtype=torch.int32, device="cuda")
+            ctx.ensemble_stats(r, mean, std, cnt)
+            stats[r] = (host(mean), host(std), host(cnt).astype(np.int64))
+    refs = [_oracle_image(vels[j["r"]], j) for j in jobs]
+    errs = [oracle.rel_l2(a, b) for a, b in zip(images, refs)]
+    print("image rel L2 vs oracle:", ", ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= 1e-4
+    for r in (0, 1):
+        mine = [(ref, img, (j["ix0"], j["w"])) for ref, img, j in zip(refs, images, jobs) if j["r"] == r]
+        m_ref, s_ref, c_ref = oracle.windowed_stats([m[0] for m in mine], [m[2] for m in mine], NZ, NX)
+        mean, std, cnt = stats[r]
+        assert np.array_equal(cnt, c_ref)
+        # Perturbing the samples of a pixel by a vector e moves their mean by at
+        # most |e| / sqrt(n) and their sample std by at most |e| / sqrt(n - 1);
+        # summed over pixels, the image errors E_j = GPU_j - oracle_j bound the
+        # map errors by sqrt(sum_j |E_j|^2) / sqrt(n_min (- 1)).
+        e2 = math.sqrt(sum(((img - ref) ** 2).sum() for ref, img, _ in mine))
+        covered = c_ref >= 1
+        assert np.sqrt(((mean - m_ref)[covered] ** 2).sum()) <= e2 * (1 + 1e-9) + 1e-300
+        two = c_ref >= 2
+        assert two.any()
+        assert np.sqrt(((std - s_ref)[two] ** 2).sum()) <= e2 * (1 + 1e-9) + 1e-300
+        assert not std[~two].any()
+        print(f"realization {r}: mean rel L2 {oracle.rel_l2(mean[covered], m_ref[covered]):.2e}, "
+              f"std rel L2 {oracle.rel_l2(std[two], s_ref[two]):.2e}", flush=True)
+
+
+def test_served_stream_geometry_matches_oracle(rtm, smooth):
+    stream = inputs.poisson_stream(1300, rate=20.0, seed=5, n_real=256, nx=NX)
+    # the first FP32 job, and the first BF16 job at least 1200 columns wide with nt >= 3000
+    picked = [next(s for s in stream if s.dtype == "fp32"),
+              next(s for s in stream if s.dtype == "bf16" and s.width >= 1200 and s.nt >= 3000)]
+    jobs = [dict(r=s.realization, src=s.src, ix0=s.ix0, w=s.width, nt=s.nt, dtype=s.dtype,
+                 data=_data(100 + i, s.nt, s.width), opts=rtm.img_opts("store", s.dtype, 4))
+            for i, s in enumerate(picked)]
+    vels = {j["r"]: _sample(smooth, j["r"]) for j in jobs}
+    with rtm.Context(0, arena_bytes=6 << 30) as ctx:
+        g = rtm.make_grid(NZ, NX, NB, max(j["nt"] for j in jobs), H, H, DT)
+        for r, v in vels.items():
+            ctx.model_register(r, dev(v), g)
+        images = _serve(rtm, ctx, jobs, rtm.JOB_ACC_STATS)
+    for img, j in zip(images, jobs):
+        e = oracle.rel_l2(img, _oracle_image(vels[j["r"]], j, stride=4))
+        print(f"{j['dtype']} stride 4, {j['w']} columns, nt {j['nt']}: rel L2 {e:.2e}", flush=True)
+        assert e <= (1e-4 if j["dtype"] == "fp32" else 1e-2)
+
+
+# ---------------------------------------------------------------------------
+# continuous batching at a small geometry
+# ---------------------------------------------------------------------------
+SZ, SX, SB = 48, 260, 10
+
+
+def _small_models(n):
+    base = inputs.two_layer(SZ, SX, H, z_interface=250.0)
+    return [inputs.realization(r, base, H, smooth_sigma_m=30.0) for r in range(n)]
+
+
+def _small_job(rng, r, w, nt, mode="reconstruct", dtype="fp32", stride=1):
+    ix = int(rng.integers(0, SX))
+    return dict(r=r, src=(1, ix), ix0=inputs.window_for(ix, w, SX), w=w, nt=nt, mode=mode, dtype=dtype,
+                stride=stride, data=rng.standard_normal((nt, w)) * 1e-3)
+
+
+def _opts(rtm, j):
+    return rtm.img_opts(j["mode"], j["dtype"], j["stride"] if j["mode"] == "store" else 1)
+
+
+def _alone(rtm, ctx, vel, j):
+    g = rtm.make_grid(SZ, SX, SB, j["nt"], H, H, DT)
+    img = torch.zeros(SZ, SX, device="cuda")
+    rec = [(1, x) for x in range(j["ix0"], j["ix0"] + j["w"])]
+    ctx.migrate_shot(g, dev(vel), dev(inputs.ricker(j["nt"], DT, 25.0)), j["src"], rec, dev(j["data"]),
+                     j["ix0"], j["w"], _opts(rtm, j), img)
+    return host(img)[:, j["ix0"]:j["ix0"] + j["w"]]
+
+
+def _submit(rtm, ctx, j, keep, flags=0):
+    w, d = dev(inputs.ricker(j["nt"], DT, 25.0)), dev(j["data"])
+    keep += [w, d]
+    return ctx.submit(j["r"], j["src"], j["ix0"], j["w"], 1, j["nt"], w, d, _opts(rtm, j), flags=flags)
+
+
+def _collect(rtm, ctx, tickets, jobs):
+    infos, images = [], []
+    for t, j in zip(tickets, jobs):
+        info = ctx.poll(t)
+        assert info.state == rtm.JOB_DONE and info.status == 0, (info.state, info.status)
+        img = torch.empty(SZ, j["w"], device="cuda")
+        ctx.poll(t, img, release=True)
+        infos.append(info)
+        images.append(host(img))
+    return infos, images
+
+
+def test_jobs_arriving_while_others_run_are_admitted_and_unchanged(rtm):
+    """A long job is submitted and seen RUNNING; jobs submitted afterwards are
+    admitted before it finishes (their work overlaps on the device), and
+    every image equals that job's image run alone."""
+    rng = np.random.default_rng(21)
+    vels = _small_models(2)
+    long_job = _small_job(rng, 0, 200, 4000)
+    later = [_small_job(rng, 1, 120, 300), _small_job(rng, 0, 90, 200, "store", "bf16", 2),
+             _small_job(rng, 1, 150, 250, "store", "fp32", 3)]
+    with rtm.Context(0, arena_bytes=1 << 30) as ctx:
+        g = rtm.make_grid(SZ, SX, SB, 100, H, H, DT)
+        for r, v in enumerate(vels):
+            ctx.model_register(r, dev(v), g)
+        keep = []
+        t_long = _submit(rtm, ctx, long_job, keep)
+        deadline = time.monotonic() + 60
+        while ctx.poll(t_long).state == rtm.JOB_QUEUED:
+            assert time.monotonic() < deadline
+            time.sleep(0.001)
+        assert ctx.poll(t_long).state == rtm.JOB_RUNNING
+        t_later = [_submit(rtm, ctx, j, keep) for j in later]
+        ctx.drain()
+        infos, images = _collect(rtm, ctx, [t_long] + t_later, [long_job] + later)
+        first = infos[0]
+        for info in infos[1:]:
+            assert first.t_admit < info.t_admit < first.t_done, (first.t_admit, info.t_admit, first.t_done)
+        for j, img in zip([long_job] + later, images):
+            assert np.array_equal(_alone(rtm, ctx, vels[j["r"]], j), img), (j["mode"], j["dtype"])
+
+
+def test_memory_pressure_queues_jobs_and_results_equal_alone(rtm):
+    """An arena that holds two to three of these jobs at a time: every job
+    completes, at least one job is admitted only after another finished, at
+    least one is admitted while another is still running, every image
+    equals its alone run bit for bit, and the running statistics equal the
+    two-pass statistics of the served images."""
+    rng = np.random.default_rng(1)
+    vels = _small_models(1)
+    jobs = [_small_job(rng, 0, int(rng.integers(100, 200)), int(rng.integers(150, 260)),
+                       ["reconstruct", "store"][k % 2], ["fp32", "bf16"][k % 2], 2)
+            for k in range(8)]
+    with rtm.Context(0, arena_bytes=10 << 20) as ctx:
+        g = rtm.make_grid(SZ, SX, SB, 100, H, H, DT)
+        ctx.model_register(0, dev(vels[0]), g)
+        keep = []
+        tickets = [_submit(rtm, ctx, j, keep, rtm.JOB_ACC_STATS) for j in jobs]
+        ctx.drain()
+        infos, images = _collect(rtm, ctx, tickets, jobs)
+        st = ctx.stats()
+        assert st.arena_peak <= st.arena_bytes
+        waited = any(b.t_admit >= a.t_done for a in infos for b in infos if a is not b)
+        overlap = any(a.t_admit < b.t_admit < a.t_done for a in infos for b in infos if a is not b)
+        assert waited and overlap, [(i.t_admit, i.t_done) for i in infos]
+        mean = torch.empty(SZ, SX, dtype=torch.float64, device="cuda")
+        std = torch.empty_like(mean)
+        cnt = torch.empty(SZ, SX, dtype=torch.int32, device="cuda")
+        ctx.ensemble_stats(0, mean, std, cnt)
+        m_ref, s_ref, c_ref = oracle.windowed_stats(images, [(j["ix0"], j["w"]) for j in jobs], SZ, SX)
+        assert np.array_equal(host(cnt), c_ref)
+        assert np.abs(host(mean) - m_ref).max() <= 1e-12 * np.abs(m_ref).max()
+        assert np.abs(host(std) - s_ref).max() <= 1e-12 * np.abs(s_ref).max()
+        for j, img in zip(jobs, images):
+            assert np.array_equal(_alone(rtm, ctx, vels[0], j), img), (j["mode"], j["dtype"])

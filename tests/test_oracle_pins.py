@@ -455,3 +455,73 @@ def test_windowed_stats_and_stack_placement():
     assert np.array_equal(cnt[0], [1, 1, 2, 2, 1, 1, 2, 1, 1, 0])
     assert np.allclose(mean[0], [1, 1, 2, 2, 3, 3, 4, 5, 5, 0])
     assert np.allclose(std[0], [0, 0, math.sqrt(2), math.sqrt(2), 0, 0, math.sqrt(2), 0, 0, 0])
+
+
+# ---------------------------------------------------------------------------
+# Stage-3 maps (Sec. 2.3, Eq. 6 and Eq. 7) and the post-stack filter (Sec. 3)
+# ---------------------------------------------------------------------------
+
+def test_confidence_index_by_hand():
+    """Eq. 6 with extremes over pixels of count >= min_count: std 1, 2, 3 are
+    counted (s_min 1, s_max 3) and the std of 10 at count 1 is not, so the map
+    is (3 - s) / 2 = 1, 1/2, 0 and 0 at the excluded pixel.  Extremes over all
+    pixels would give s_max 10 (1, 8/9, 7/9); a swapped numerator (s - s_min)
+    gives 0, 1/2, 1."""
+    std = np.array([[1.0, 2.0], [3.0, 10.0]])
+    cnt = np.array([[3, 2], [5, 1]])
+    np.testing.assert_array_equal(oracle.confidence_index(std, cnt, min_count=2),
+                                  [[1.0, 0.5], [0.0, 0.0]])
+    # min_count 3 drops the pixel of count 2 as well: extremes 1 and 3 still
+    np.testing.assert_array_equal(oracle.confidence_index(std, cnt, min_count=3),
+                                  [[1.0, 0.0], [0.0, 0.0]])
+    # without counts every pixel takes part: (10 - s) / 9
+    np.testing.assert_allclose(oracle.confidence_index(std), [[1.0, 8 / 9], [7 / 9, 0.0]], rtol=1e-15)
+
+
+def test_confidence_index_degenerate_cases():
+    """s_max == s_min gives 0 everywhere (no spread to rank), as does a map
+    with no pixel at min_count; the result does not depend on the std of the
+    excluded pixels."""
+    std = np.full((3, 4), 2.5)
+    cnt = np.full((3, 4), 4)
+    assert not oracle.confidence_index(std, cnt).any()
+    assert not oracle.confidence_index(np.arange(12.0).reshape(3, 4), np.ones((3, 4), int)).any()
+    a = np.array([[0.5, 1.5, 9.0]])
+    b = np.array([[0.5, 1.5, -7.0]])
+    c = np.array([[2, 2, 0]])
+    np.testing.assert_array_equal(oracle.confidence_index(a, c), oracle.confidence_index(b, c))
+    np.testing.assert_array_equal(oracle.confidence_index(a, c), [[1.0, 0.0, 0.0]])
+
+
+def test_ratio_map_by_hand():
+    """Eq. 7: std / mean, keeping the sign of the mean, and 0 where
+    |mean| <= eps (the rule is strict: |mean| == eps gives 0)."""
+    std = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])
+    mean = np.array([2.0, -4.0, 1e-4, 0.0, 1e-3, -2e-3])
+    np.testing.assert_array_equal(oracle.ratio_map(std, mean, eps=1e-3),
+                                  [0.5, -0.5, 0.0, 0.0, 0.0, -3000.0])
+    # eps 0: only an exact zero mean is masked
+    np.testing.assert_array_equal(oracle.ratio_map(std[:4], mean[:4], eps=0.0),
+                                  [0.5, -0.5, 3.0 / 1e-4, 0.0])
+
+
+def test_laplacian_filter_sign_and_edges():
+    """The filter is minus the 8th-order Laplacian: on z^2 (z = i dz) the
+    interior value is -2, on z^2 + x^2 it is -4.  Outside the image the field
+    is zero, so at a corner of a constant image of 1 only the inner
+    neighbours count: L = a0 (1/dz^2 + 1/dx^2) + (a1 + a2 + a3 + a4)(1/dz^2 +
+    1/dx^2) = (a0 / 2)(1/dz^2 + 1/dx^2), since a0 + 2 sum a_k = 0, and the
+    filter gives +(205 / 144)(1/dz^2 + 1/dx^2)."""
+    nz, nx, dz, dx = 20, 23, 10.0, 12.5
+    z = np.arange(nz)[:, None] * dz
+    x = np.arange(nx)[None, :] * dx
+    inner = (slice(4, nz - 4), slice(4, nx - 4))
+    f = oracle.laplacian_filter(np.broadcast_to(z * z, (nz, nx)).copy(), dz, dx)
+    np.testing.assert_allclose(f[inner], -2.0, rtol=1e-12)
+    f = oracle.laplacian_filter(z * z + x * x, dz, dx)
+    np.testing.assert_allclose(f[inner], -4.0, rtol=1e-12)
+    f = oracle.laplacian_filter(np.ones((nz, nx)), dz, dx)
+    corner = 205.0 / 144.0 * (1 / dz**2 + 1 / dx**2)
+    for iz, ix in ((0, 0), (0, nx - 1), (nz - 1, 0), (nz - 1, nx - 1)):
+        assert f[iz, ix] == pytest.approx(corner, rel=1e-13)
+    assert np.abs(f[inner]).max() < 1e-15 * corner
