@@ -395,6 +395,25 @@ int rtm_codec_encode(rtm_ctx *ctx, const float *x_dev, int32_t count, int32_t ro
                      int32_t mode, double tol, void *stream_dev, int64_t capacity_bytes,
                      int64_t *stream_bytes);
 
+/* rtm_codec_encode for callers that cannot allocate memory (code that must
+ * not call hipMalloc, e.g. under stream capture or in a serving loop with
+ * fixed memory): same arguments, results and stream bytes as
+ * rtm_codec_encode, but the look-back state lives in a 1 MiB device array
+ * the library holds on every device it runs on until the process ends,
+ * instead of the context arena, and the call allocates nothing.
+ *   Limit: at most (2^20 - 256) / 8 = 131040 chunks of 256 8 x 8 blocks
+ *   (about 2.1e9 values per call); larger arrays return RTM_E_INVAL before
+ *   any device work.
+ *   Calls on one device share the array and its last contents (cleared by
+ *   each call before use): two calls overlapping on one device would race,
+ *   so the library serialises these calls per device with a lock held
+ *   until the call's kernels have finished.  Errors as rtm_codec_encode;
+ *   RTM_E_DEVICE if the array's address was not found when the context was
+ *   created. */
+int rtm_codec_encode_noalloc(rtm_ctx *ctx, const float *x_dev, int32_t count, int32_t rows, int32_t cols,
+                             int32_t mode, double tol, void *stream_dev, int64_t capacity_bytes,
+                             int64_t *stream_bytes);
+
 /* Read and validate a stream's header (copies its first 32 bytes to the
  * host).  Any output pointer may be NULL.  Errors: RTM_E_INVAL (not a codec
  * stream, bad header, stream shorter than its index). */

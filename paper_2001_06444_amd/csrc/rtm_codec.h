@@ -40,4 +40,16 @@ struct ZcParams {
 hipError_t launch_zc_encode(const ZcParams& p, hipStream_t s);
 hipError_t launch_zc_decode(const ZcParams& p, hipStream_t s);
 
+// Device scratch of the encoder that allocates nothing (rtm_codec_encode_noalloc):
+// the look-back state of up to kZcNoAllocChunks chunks (8 bytes each) and
+// 64 bytes of ticket, flags and result words, in a file-scope device array
+// each device holds until the process ends.
+constexpr size_t kZcNoAllocBytes = size_t(1) << 20;
+constexpr int64_t kZcNoAllocChunks = (int64_t)(kZcNoAllocBytes - 256) / 8;
+// Looks up the array's address on `device` (which must be current) once and
+// keeps it; later calls return the kept address.
+hipError_t zc_noalloc_scratch_init(int device);
+// The kept address of the array on `device`, or null before a successful init.
+void* zc_noalloc_scratch(int device);
+
 }  // namespace rtm

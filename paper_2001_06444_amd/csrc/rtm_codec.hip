@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "rtm_codec.h"
 
 namespace rtm {
@@ -540,6 +542,38 @@ __global__ __launch_bounds__(kZcChunk, MINW) void k_zc_decode(ZcParams p) {
     }
     wave_sync();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free encoder.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is a stand-in, not a
+// device address): it uses the address hipGetSymbolAddress returns on each
+// device, kept per device below.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kZcNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t zc_noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* zc_noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_zc_encode(const ZcParams& p, hipStream_t s) {

@@ -1068,6 +1068,9 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   HIP_OK(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(RTM_E_INVAL, "device %d not present (%d devices)", device, ndev);
   HIP_OK(hipSetDevice(device));
+  // address of the allocation-free encoder's scratch on this device (looked
+  // up once per device, with the device current)
+  HIP_OK(zc_noalloc_scratch_init(device));
   auto ctx = std::make_unique<rtm_ctx>();
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
@@ -2160,14 +2163,17 @@ extern "C" int64_t rtm_codec_max_bytes(int32_t count, int32_t rows, int32_t cols
   return 4 * (zc_index_words(nblk) + 64 * nblk);
 }
 
-extern "C" int rtm_codec_encode(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows, int32_t cols,
-                                int32_t mode, double tol, void* stream_dev, int64_t capacity_bytes,
-                                int64_t* stream_bytes) {
+// Validation of an encode and its launch parameters (no device work).
+// max_chunks bounds the chunk count (the look-back state holds 8 bytes per
+// chunk); larger arrays are rejected with RTM_E_INVAL.
+static int zc_encode_params(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows, int32_t cols,
+                            int32_t mode, double tol, void* stream_dev, int64_t capacity_bytes,
+                            int64_t* stream_bytes, int64_t max_chunks, ZcParams& p) {
   if (!ctx || !x_dev || !stream_dev || !stream_bytes) return fail(RTM_E_INVAL, "bad arguments");
   *stream_bytes = 0;
   if (reinterpret_cast<uintptr_t>(stream_dev) & 3) return fail(RTM_E_INVAL, "stream must be 4-byte aligned");
   if (reinterpret_cast<uintptr_t>(x_dev) & 3) return fail(RTM_E_INVAL, "array must be 4-byte aligned");
-  ZcParams p{};
+  p = ZcParams{};
   if (mode == RTM_CODEC_TOL) {
     if (!(tol > 0) || !std::isfinite(tol)) return fail(RTM_E_INVAL, "the tolerance must be finite and > 0");
     p.r = 1.0 / (2.0 * tol);
@@ -2180,26 +2186,33 @@ extern "C" int rtm_codec_encode(rtm_ctx* ctx, const float* x_dev, int32_t count,
   }
   p.mode = mode;
   if (int st = zc_geometry(count, rows, cols, p)) return st;
+  if (p.nchunks > max_chunks)
+    return fail(RTM_E_INVAL, "%d chunks of %d blocks exceed the %lld this call holds look-back state for",
+                p.nchunks, kZcChunk, (long long)max_chunks);
   if (capacity_bytes < 4 * p.pay_base)
     return fail(RTM_E_NOMEM, "stream capacity %lld bytes is below the %lld-byte index",
                 (long long)capacity_bytes, (long long)(4 * p.pay_base));
   p.cap_words = capacity_bytes / 4;
-  HIP_OK(hipSetDevice(ctx->device));
-  const size_t scratch_bytes = 8 * (size_t)p.nchunks + 64;
-  void* scratch = arena_alloc(ctx, scratch_bytes);
-  if (!scratch) return fail(RTM_E_NOMEM, "arena exhausted (codec look-back state)");
-  uint32_t* tail = reinterpret_cast<uint32_t*>(static_cast<char*>(scratch) + 8 * (size_t)p.nchunks);
   p.x = x_dev;
   p.out = static_cast<uint32_t*>(stream_dev);
-  p.status = static_cast<uint64_t*>(scratch);
-  p.ticket = tail;
-  p.flags = tail + 1;
-  p.result = tail + 2;
   uint32_t tw[2];
   memcpy(tw, &tol, 8);
   const uint32_t head[8] = {kZcMagic, (uint32_t)mode, (uint32_t)count, (uint32_t)rows,
                             (uint32_t)cols, (uint32_t)kZcChunk, tw[0], tw[1]};
   memcpy(p.head, head, sizeof head);
+  return RTM_OK;
+}
+
+// Runs a validated encode with its look-back state in `scratch` (device
+// memory of at least 8 nchunks + 64 bytes, cleared here by a fill kernel)
+// and waits for it: the stream length comes back to the host.
+static int zc_encode_run(rtm_ctx* ctx, ZcParams& p, void* scratch, int64_t capacity_bytes, int64_t* stream_bytes) {
+  const size_t scratch_bytes = 8 * (size_t)p.nchunks + 64;
+  uint32_t* tail = reinterpret_cast<uint32_t*>(static_cast<char*>(scratch) + 8 * (size_t)p.nchunks);
+  p.status = static_cast<uint64_t*>(scratch);
+  p.ticket = tail;
+  p.flags = tail + 1;
+  p.result = tail + 2;
   hipStream_t s = ctx->stream;
   uint32_t res[4] = {0, 0, 0, 0};
   hipError_t e = launch_fill_u32(static_cast<uint32_t*>(scratch), 0, (int64_t)scratch_bytes / 4, s);
@@ -2208,7 +2221,6 @@ extern "C" int rtm_codec_encode(rtm_ctx* ctx, const float* x_dev, int32_t count,
   if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[1], s);
   if (e == hipSuccess) e = hipMemcpyAsync(res, tail, 16, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  ctx->arena.release(scratch, align256(scratch_bytes));
   if (e != hipSuccess) return fail(RTM_E_DEVICE, "codec encode: %s", hipGetErrorString(e));
   const uint32_t flags = res[1];
   if (flags & kZcSpin) return fail(RTM_E_DEVICE, "codec encode: a chunk prefix did not arrive in time");
@@ -2218,11 +2230,48 @@ extern "C" int rtm_codec_encode(rtm_ctx* ctx, const float* x_dev, int32_t count,
   const int64_t bytes = 4 * (p.pay_base + (int64_t)res[2]);
   *stream_bytes = bytes;
   ctx->zc_op = 1;
-  ctx->zc_bytes = 4 * (uint64_t)count * rows * cols + (uint64_t)bytes;
+  ctx->zc_bytes = 4 * (uint64_t)p.count * p.rows * p.cols + (uint64_t)bytes;
   if (flags & kZcCapacity)
     return fail(RTM_E_NOMEM, "the stream needs %lld bytes, the buffer holds %lld", (long long)bytes,
                 (long long)capacity_bytes);
   return RTM_OK;
+}
+
+extern "C" int rtm_codec_encode(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows, int32_t cols,
+                                int32_t mode, double tol, void* stream_dev, int64_t capacity_bytes,
+                                int64_t* stream_bytes) {
+  ZcParams p;
+  if (int st = zc_encode_params(ctx, x_dev, count, rows, cols, mode, tol, stream_dev, capacity_bytes, stream_bytes,
+                                INT64_MAX, p))
+    return st;
+  HIP_OK(hipSetDevice(ctx->device));
+  const size_t scratch_bytes = 8 * (size_t)p.nchunks + 64;
+  void* scratch = arena_alloc(ctx, scratch_bytes);
+  if (!scratch) return fail(RTM_E_NOMEM, "arena exhausted (codec look-back state)");
+  const int rc = zc_encode_run(ctx, p, scratch, capacity_bytes, stream_bytes);
+  ctx->arena.release(scratch, align256(scratch_bytes));  // the run waited for the stream
+  return rc;
+}
+
+// One lock per device: the allocation-free encoder's calls on a device share
+// its scratch array, and each call returns only after its kernels finished,
+// so holding the lock for the call keeps calls of this process from
+// overlapping on one device.
+static std::mutex g_zc_noalloc_mu[64];
+
+extern "C" int rtm_codec_encode_noalloc(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows,
+                                        int32_t cols, int32_t mode, double tol, void* stream_dev,
+                                        int64_t capacity_bytes, int64_t* stream_bytes) {
+  ZcParams p;
+  if (int st = zc_encode_params(ctx, x_dev, count, rows, cols, mode, tol, stream_dev, capacity_bytes, stream_bytes,
+                                kZcNoAllocChunks, p))
+    return st;
+  void* scratch = zc_noalloc_scratch(ctx->device);
+  if (!scratch || ctx->device < 0 || ctx->device >= 64)
+    return fail(RTM_E_DEVICE, "the encoder's device scratch was not found on device %d", ctx->device);
+  HIP_OK(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> lk(g_zc_noalloc_mu[ctx->device]);
+  return zc_encode_run(ctx, p, scratch, capacity_bytes, stream_bytes);
 }
 
 extern "C" int rtm_codec_info(rtm_ctx* ctx, const void* stream_dev, int64_t stream_bytes, int32_t* mode,

@@ -130,6 +130,8 @@ SIGNATURES = {
     "rtm_codec_max_bytes": ([_I32, _I32, _I32], ctypes.c_int64),
     "rtm_codec_encode": ([_V, _V, _I32, _I32, _I32, _I32, _D, _V, ctypes.c_int64,
                           _P(ctypes.c_int64)], ctypes.c_int),
+    "rtm_codec_encode_noalloc": ([_V, _V, _I32, _I32, _I32, _I32, _D, _V, ctypes.c_int64,
+                                  _P(ctypes.c_int64)], ctypes.c_int),
     "rtm_codec_info": ([_V, _V, ctypes.c_int64, _P(_I32), _P(_I32), _P(_I32), _P(_I32), _P(_D)],
                        ctypes.c_int),
     "rtm_codec_decode": ([_V, _V, ctypes.c_int64, _V, ctypes.c_int64], ctypes.c_int),
@@ -366,6 +368,20 @@ class Context:
         _check(lib().rtm_codec_encode(self.h, _ptr(x), count, rows, cols, mode,
                                       float(tol if tol is not None else 0.0), _ptr(out), out.numel(),
                                       ctypes.byref(n)))
+        return out[: n.value]
+
+    def codec_encode_noalloc(self, x, out, tol=None, lossless=False):
+        """rtm_codec_encode_noalloc: as codec_encode into the caller's uint8
+        device tensor `out`, with nothing allocated by the call."""
+        import torch
+        if x.dtype != torch.float32 or out.dtype != torch.uint8:
+            raise ValueError("float32 input and uint8 output tensors expected")
+        count, rows, cols = (1, *x.shape) if x.dim() == 2 else tuple(x.shape)
+        n = ctypes.c_int64(0)
+        mode = CODEC_LOSSLESS if lossless else CODEC_TOL
+        _check(lib().rtm_codec_encode_noalloc(self.h, _ptr(x), count, rows, cols, mode,
+                                              float(tol if tol is not None else 0.0), _ptr(out), out.numel(),
+                                              ctypes.byref(n)))
         return out[: n.value]
 
     def codec_info(self, stream):
