@@ -13,7 +13,12 @@ are modelled on the GPU before timing.
 Printed: one JSON line with grid-point updates/s of the batched path (the
 value), images/s, the plain one-launch-per-step path for comparison, the
 roofline of the dominant kernel (the backward step) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+timed on a bounded sample of the same workload; beside them, on the same
+GPU, the batched UQ ensemble (64 velocity samples x 16 shots = 1024 RTMs,
+nt 3000, all submitted at once to the serving engine: updates/s, images/s,
+realization images/s) and the served stream (Poisson 20 jobs/s, 1200 timed
+jobs after 100 warm-up: p50/p99 latency and images/s; then all 1300 jobs at
+t = 0 for the saturation rate).
 """
 from __future__ import annotations
 
@@ -64,6 +69,17 @@ def measured_traffic(record="traffic_backward_step.json", sources=STEP_SOURCES, 
     return rec.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name from /proc/cpuinfo (first processor)."""
+    try:
+        for line in pathlib.Path("/proc/cpuinfo").read_text().splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sv, nt_sample: int):
     """FP64 oracle on one shot of the same survey, first nt_sample steps."""
     import numpy as np
@@ -84,6 +100,7 @@ def cpu_baseline(sv, nt_sample: int):
         "value": updates / el,
         "unit": "grid-pt updates/s",
         "cores": oracle.nthreads(),
+        "cpu": cpu_model(),
         "kind": "oracle",
         "sample": (f"1 of {len(sv.shots)} shots (source ix={sh.src[1]}), first {nt_sample} of "
                    f"{sv.nt} time steps, same {sv.nz}x{sv.nx} model, nb={sv.nb}, all receivers; "
@@ -113,12 +130,17 @@ def parse():
     ap.add_argument("--bet-iters", type=int, default=20, help="bet workload: iterations per step")
     ap.add_argument("--bet-h", type=float, default=100.0, choices=[100.0, 50.0],
                     help="bet workload: node spacing (100 m: 36 x 171 nodes, 50 m: 71 x 341)")
-    ap.add_argument("--serve-jobs", type=int, default=300, help="serve workload: timed jobs")
-    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--serve-jobs", type=int, default=1200, help="serve workload: timed jobs")
+    ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--rate", type=float, default=20.0, help="serve workload: jobs/s")
-    ap.add_argument("--default-serve-jobs", type=int, default=100,
-                    help="survey workload: timed jobs of the short served stream reported beside it")
-    ap.add_argument("--no-serve", action="store_true", help="survey workload: skip the short served stream")
+    ap.add_argument("--default-serve-jobs", type=int, default=1200,
+                    help="survey workload: timed jobs of the served stream reported beside it")
+    ap.add_argument("--default-serve-warmup", type=int, default=100,
+                    help="survey workload: warm-up jobs of the served stream reported beside it")
+    ap.add_argument("--no-serve", action="store_true", help="survey workload: skip the served stream")
+    ap.add_argument("--no-ensemble", action="store_true", help="survey workload: skip the velocity ensemble")
+    ap.add_argument("--rates", type=str, default="",
+                    help="serve workload: extra Poisson rates (jobs/s, comma separated) run after the main one")
     return ap.parse_args()
 
 
@@ -303,14 +325,21 @@ def run_survey(args):
                                         "alg_bytes_per_launch": fwd_launch_bytes}},
         "cpu_baseline": base,
     })
-    if not args.no_serve:
-        # the served path on the same GPU: a shorter Poisson stream than
-        # --workload serve runs (percentiles from its timed jobs only)
-        del ctx
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_ensemble:
+        # the batched UQ ensemble on the same GPU: 64 velocity samples x 16
+        # shots = 1024 RTMs, all submitted at once to the serving engine
+        out["ensemble"] = _ensemble(args, args.realizations, 3000, plain_shots=0)
         torch.cuda.empty_cache()
-        res = _serve(args, 10, args.default_serve_jobs, saturation=False)
-        res["workload"] = (f"served stream: Poisson {args.rate} jobs/s, 256 velocity samples, apertures "
-                           "301-1701, nt 2000-4000, store mode stride 4 fp32/bf16")
+    if not args.no_serve:
+        # the served path on the same GPU: the Poisson stream (percentiles from
+        # its timed jobs only), then every job of it again at t = 0
+        n_warm, n_timed = args.default_serve_warmup, args.default_serve_jobs
+        res = _serve(args, n_warm, n_timed, saturation=True)
+        res["workload"] = (f"served stream: Poisson {args.rate} jobs/s, {n_timed} timed jobs after {n_warm} "
+                           "warm-up, 256 velocity samples, apertures 301-1701, nt 2000-4000, store mode "
+                           "stride 4 fp32/bf16, FP64 per-realization mean/std")
         out["served"] = res
     return out
 
@@ -350,11 +379,12 @@ def _job_bytes(nz, width, nb, nt, mode="reconstruct", dtype="fp32", stride=1):
     return b
 
 
-def run_ensemble(args):
-    """64 velocity samples x 16 shots with uneven apertures, all submitted at
-    once to the serving engine (continuous batching, graph replays, tuned
-    tiles); per-realization stacks, then FP64 mean/std over the stacks and
-    the Stage-3 maps."""
+def _ensemble(args, R, nt, plain_shots):
+    """R velocity samples x 16 shots with uneven apertures, all submitted at
+    once to the serving engine (continuous batching, tuned tiles);
+    per-realization stacks, then FP64 mean/std over the stacks and the
+    Stage-3 confidence map.  Returns the rates and, with plain_shots > 0,
+    the same shots through the plain path."""
     import numpy as np
     import torch
 
@@ -362,8 +392,6 @@ def run_ensemble(args):
 
     dev = torch.device("cuda:0")
     nz, nx, h, dt, nb = 351, 1701, 10.0, 1e-3, 50
-    nt = args.nt or 3000
-    R = args.realizations
     base, smooth = _ensemble_setup(nz, nx, h)
     shots = inputs.ensemble_shots(16, nx)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
@@ -418,24 +446,36 @@ def run_ensemble(args):
         f"{updates / el:.3e} updates/s), {failed} failed, tile_z {s1.tile_z}")
     plain_jobs = [dict(vel=t(smooth), wav=wav, src=sh.src, rec=[(1, x) for x in range(sh.ix0, sh.ix0 + sh.width)],
                        data=d, ix0=sh.ix0, width=sh.width, opts=opts, image_shape=(nz, nx))
-                  for sh, d in list(zip(shots, data))[: args.plain_shots]]
+                  for sh, d in list(zip(shots, data))[:plain_shots]]
     plain = _plain_rate(ctx, lambda j: grid, plain_jobs)
     ctx.close()
-    out = _base_record(args, updates / el, el * 1e3, {
+    return {
         "workload": f"velocity ensemble: {R} realizations x {len(shots)} shots on {nz}x{nx} at 10 m, "
                     f"apertures 401-1201 columns, nt={nt}, nb={nb}, reconstruct mode, "
                     f"FP64 mean/std over realization stacks",
-        "realizations": R, "shots": len(shots), "nt": nt, "path": "served engine, all jobs at t=0",
-        "tile_z": s1.tile_z})
-    out.update({"steps": 1, "warmup": 1, "images_per_s": n_img / el,
-                "realization_images_per_s": R / el, "rtm_seconds": t_rtm, "failed_jobs": failed,
-                "plain": plain,
-                "batched_vs_plain": (n_img / el) / plain["images_per_s"] if plain else None,
-                "std_map": {"max": float(std.max()), "mean": float(std.mean())}})
+        "rtms": n_img, "seconds": el, "rtm_seconds": t_rtm,
+        "updates_per_s": updates / el, "images_per_s": n_img / el, "realization_images_per_s": R / el,
+        "failed_jobs": failed, "tile_z": s1.tile_z, "path": "served engine, all jobs at t=0",
+        "plain": plain, "batched_vs_plain": (n_img / el) / plain["images_per_s"] if plain else None,
+        "std_map": {"max": float(std.max()), "mean": float(std.mean())},
+    }
+
+
+def run_ensemble(args):
+    """The velocity ensemble alone (value: its grid-point updates/s)."""
+    nt = args.nt or 3000
+    res = _ensemble(args, args.realizations, nt, args.plain_shots)
+    out = _base_record(args, res["updates_per_s"], res["seconds"] * 1e3, {
+        "workload": res["workload"], "realizations": args.realizations, "shots": 16, "nt": nt,
+        "path": res["path"], "tile_z": res["tile_z"]})
+    out.update({"steps": 1, "warmup": 1, "images_per_s": res["images_per_s"],
+                "realization_images_per_s": res["realization_images_per_s"], "rtm_seconds": res["rtm_seconds"],
+                "failed_jobs": res["failed_jobs"], "plain": res["plain"],
+                "batched_vs_plain": res["batched_vs_plain"], "std_map": res["std_map"]})
     return out
 
 
-def _serve(args, n_warm, n_timed, saturation):
+def _serve(args, n_warm, n_timed, saturation, extra_rates=()):
     """Poisson stream of RTM jobs (velocity sample, shot, aperture, nt, snapshot
     dtype) served by continuous batching; latency = completion - arrival,
     including queueing and the upload of the job's data.  Returns the
@@ -516,11 +556,23 @@ def _serve(args, n_warm, n_timed, saturation):
     log(f"[bench] serve @ {args.rate}/s: p50 {res['latency_ms']['p50']:.0f} ms, "
         f"p99 {res['latency_ms']['p99']:.0f} ms, {res['images_per_s']:.1f} images/s, "
         f"{res['failed_jobs']} failed")
+    for rate in extra_rates:  # the same jobs at another rate: arrival times scaled
+        lat_r, ok_r, t_end_r = serve([a * args.rate / rate for a in arrivals])
+        lr = lat_r[n_warm:]
+        span_r = t_end_r - arrivals[n_warm] * args.rate / rate
+        res.setdefault("other_rates", []).append(
+            {"rate": rate, "latency_ms": {"p50": float(np.percentile(lr, 50)) * 1e3,
+                                          "p99": float(np.percentile(lr, 99)) * 1e3, "max": float(lr.max()) * 1e3},
+             "images_per_s": n_timed / span_r, "failed_jobs": int((~ok_r).sum())})
+        log(f"[bench] serve @ {rate}/s: p50 {np.percentile(lr, 50) * 1e3:.0f} ms, "
+            f"p99 {np.percentile(lr, 99) * 1e3:.0f} ms, {n_timed / span_r:.1f} images/s")
     if saturation:  # every job arrives at t = 0
         u0 = ctx.stats().grid_updates
         lat0, ok0, t_end0 = serve([0.0] * n_all)
-        res["saturation"] = {"seconds": t_end0, "images_per_s": n_all / t_end0,
+        res["saturation"] = {"jobs": n_all, "seconds": t_end0, "images_per_s": n_all / t_end0,
                              "updates_per_s": (ctx.stats().grid_updates - u0) / t_end0,
+                             "latency_ms": {"p50": float(np.percentile(lat0, 50)) * 1e3,
+                                            "p99": float(np.percentile(lat0, 99)) * 1e3},
                              "failed_jobs": int((~ok0).sum())}
         log(f"[bench] saturation: {n_all} jobs in {t_end0:.2f} s, {n_all / t_end0:.1f} images/s, "
             f"{res['saturation']['updates_per_s']:.3e} updates/s")
@@ -530,7 +582,8 @@ def _serve(args, n_warm, n_timed, saturation):
 
 def run_serve(args):
     """The served stream at full length, plus its saturation run."""
-    res = _serve(args, args.serve_warmup, args.serve_jobs, saturation=True)
+    rates = [float(r) for r in args.rates.split(",") if r.strip()]
+    res = _serve(args, args.serve_warmup, args.serve_jobs, saturation=True, extra_rates=rates)
     sat = res["saturation"]
     out = _base_record(args, sat["updates_per_s"], sat["seconds"] * 1e3, {
         "workload": f"served stream: Poisson {args.rate} jobs/s, {args.serve_jobs} timed jobs "
@@ -541,6 +594,7 @@ def run_serve(args):
                 "latency_ms": res["latency_ms"],
                 "served_images_per_s": res["images_per_s"], "saturation_images_per_s": sat["images_per_s"],
                 "failed_jobs": res["failed_jobs"] + sat["failed_jobs"],
+                "other_rates": res.get("other_rates", []),
                 "value_is": "grid-pt updates/s of the saturation run"})
     return out
 

@@ -11,7 +11,7 @@ CSRC = PKG / "csrc"
 OUT = PKG / "librtm.so"
 SOURCES = [CSRC / "rtm_kernels.hip", CSRC / "rtm_aux.hip", CSRC / "rtm_codec.hip", CSRC / "rtm_bet.hip",
            CSRC / "rtm_runtime.hip"]
-HEADERS = [CSRC / "rtm_internal.h", CSRC / "rtm_codec.h", CSRC / "rtm_bet.h", CSRC / "rtm_device.h", CSRC / "rtm_arena.h", ROOT / "include" / "rtm.h"]
+HEADERS = [CSRC / "rtm_internal.h", CSRC / "rtm_codec.h", CSRC / "rtm_bet.h", CSRC / "rtm_device.h", CSRC / "rtm_arena.h", CSRC / "rtm_sched.h", ROOT / "include" / "rtm.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -27,7 +27,9 @@ def build(force: bool = True, verbose: bool = False) -> pathlib.Path:
     if not force and OUT.exists() and OUT.stat().st_mtime >= newest:
         return OUT
     tmp = OUT.with_name(OUT.name + ".tmp")
-    cmd = [HIPCC, *FLAGS, *map(str, SOURCES), "-o", str(tmp), "-lpthread"]
+    # roctx: named ranges of the scheduler and the batched phases for profiler timelines
+    cmd = [HIPCC, *FLAGS, *map(str, SOURCES), "-o", str(tmp), "-lpthread", "-L/opt/rocm/lib",
+           "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

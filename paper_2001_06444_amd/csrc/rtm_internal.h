@@ -44,7 +44,8 @@ struct alignas(16) DevJob {
   int32_t snap_dtype, snap_stride, flags, nsteps;  // snapshots; RTM_IMG_*; steps of the job
   int32_t src_z, src_x, nrec, ring_len;            // padded source node; receivers; ring size
   int32_t start_tick, tiles_x, tiles_z, tiles_x2;  // first global tick; tile grid; two-step tile columns
-  float inv_cell, c0, kfac, pad1;  // 1/(dx dz); a0 (1/dz^2 + 1/dx^2); imaging weight k
+  float inv_cell, c0, kfac;        // 1/(dx dz); a0 (1/dz^2 + 1/dx^2); imaging weight k
+  int32_t two_step;                // served job whose pairable steps run in two-step launches
   float cz[4], cx[4];              // a_k / dz^2, a_k / dx^2, k = 1..4
   const float* c;                  // v^2 dt^2, padded grid (field layout)
   const float* gz;                 // sponge profile per padded row [nzp]
@@ -74,11 +75,27 @@ struct alignas(16) Tile {
 // Launch control block for graph-replayed launches: a launch's global step
 // is ctl->tick + its own offset; k_advance moves ctl->tick after each group.
 struct alignas(16) StepCtl {
-  int32_t tick;    // global step base; job step = tick + offset - start_tick
-  int32_t pad0;
-  int32_t ntiles;  // active tiles (read when a launch passes ntiles < 0)
-  int32_t pad1;
+  int32_t tick;       // global step base; job step = tick + offset - start_tick
+  int32_t ntiles_fw;  // two-step tiles of the forward table (read when a launch passes ntiles < 0)
+  int32_t ntiles;     // one-step tiles (read when a launch passes ntiles < 0)
+  int32_t ntiles_bw;  // two-step tiles of the backward table (likewise)
 };
+
+// Does a two-step launch advance a reconstruct-mode job from its step s
+// (s even for the jobs that take two-step launches) through s + 1?  Forward
+// steps s and s + 1 both before the backward phase, or backward levels
+// m = nt - 1 - (s - nf) and m - 1 with 1 <= m <= nt - 3 (levels nt - 1 and
+// nt - 2 are imaged without reconstruction, and a last single level runs
+// alone).  The one-step launches of the serving engine skip exactly these
+// steps of a job marked two_step; the two-step kernel takes exactly these.
+__host__ __device__ inline bool two_step_pair(int s, int nt, int nsteps) {
+  const int nf = nt - 1;
+  if (s < 0 || s + 1 >= nsteps) return false;
+  if (s + 1 < nf) return true;
+  if (s < nf) return false;
+  const int m = nt - 1 - (s - nf);
+  return m <= nt - 3 && m >= 1;
+}
 
 inline int64_t field_rows(int nzp) { return ((nzp + kRowAlign - 1) / kRowAlign) * kRowAlign + 2 * kTopRows; }
 inline int32_t field_pitch(int nxp) { return ((nxp + kHalo + 63) / 64) * 64; }
@@ -87,11 +104,15 @@ inline int64_t field_origin(int nxp) { return (int64_t)kTopRows * field_pitch(nx
 inline int32_t ring_len_of(int nz, int nx) { return 8 * (nz + nx - 8); }
 
 // ---- kernel launchers (rtm_kernels.hip) ----
+// ntiles < 0: the launch reads the tile count from the control block (its
+// grid is sized for grid_tiles).  skip_pairs: leave the steps of jobs marked
+// two_step that a two-step launch takes (serving engine).
 hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
                        int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
-                       hipStream_t s);
+                       hipStream_t s, int skip_pairs = 0);
 hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, const int2* recs2,
-                        int ntiles, const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s);
+                        int ntiles, int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
+                        hipStream_t s);
 hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s);
 hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* host_job,
                        float* c, float* gz, float* gx, float dt, float sponge_a, hipStream_t s);

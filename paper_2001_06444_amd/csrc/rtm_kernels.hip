@@ -995,13 +995,16 @@ template <int TZ, int PH>
 __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ jobs,
                                                      const Tile* __restrict__ tiles,
                                                      const int2* __restrict__ recs2,
-                                                     const StepCtl* __restrict__ ctl, int ntiles,
+                                                     const StepCtl* __restrict__ ctl, int ntiles_arg,
                                                      int use_ctl_tick, int tick_off) {
   __shared__ Step2Smem<TZ, (PH & kPhBwd) != 0> sm;
   // Steps tick and tick + 1 of every job; same XCD-aware mapping as k_step,
   // except that every other launch walks each XCD's run of tiles backwards:
   // it then starts on the tiles the previous launch wrote last, whose data
-  // are still in the caches (measured: 2 % shorter launches).
+  // are still in the caches (measured: 2 % shorter launches).  The grid may
+  // be sized for more tiles than the table holds (graph replays read the
+  // count from the control block).
+  const int ntiles = ntiles_arg >= 0 ? ntiles_arg : ((PH & kPhFwd) ? ctl->ntiles_fw : ctl->ntiles_bw);
   const int tick = (use_ctl_tick ? ctl->tick : 0) + tick_off;
   const int per = (ntiles + 7) >> 3;
   const int local0 = (int)(blockIdx.x >> 3);
@@ -1012,13 +1015,12 @@ __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ j
   const Tile tl = tiles[t];
   const DevJob& J = jobs[tl.job];
   const int s = tick - J.start_tick;
-  if (J.mode != kModeRecon || s < 0 || s + 1 >= J.nsteps) return;
+  if (J.mode != kModeRecon || J.illum != nullptr || !two_step_pair(s, J.nt, J.nsteps)) return;
   const int nf = J.nt - 1;  // forward steps
   if (s + 1 < nf) {
     if (PH & kPhFwd) forward2_tile<TZ>(J, tl, s, sm);
-  } else if (s >= nf) {
-    const int m = J.nt - 1 - (s - nf);  // levels m and m - 1
-    if ((PH & kPhBwd) && m <= J.nt - 3 && m >= 1 && J.illum == nullptr) backward2_tile<TZ>(J, tl, recs2, m, sm);
+  } else {
+    if (PH & kPhBwd) backward2_tile<TZ>(J, tl, recs2, J.nt - 1 - (s - nf), sm);  // levels m and m - 1
   }
 }
 
@@ -1026,7 +1028,7 @@ template <int TZ, int PH>
 __global__ __launch_bounds__(kThreads) void k_step(const DevJob* __restrict__ jobs,
                                                     const Tile* __restrict__ tiles,
                                                     const StepCtl* __restrict__ ctl, int ntiles_arg,
-                                                    int use_ctl_tick, int tick_off) {
+                                                    int use_ctl_tick, int tick_off, int skip_pairs) {
   __shared__ StepSmem<TZ, (PH & (kPhBwd | kPhBorn)) != 0> sm;
   // Global step: a base read from the control block (advanced by k_advance
   // after every group of graph-replayed launches) plus this launch's offset.
@@ -1044,6 +1046,9 @@ __global__ __launch_bounds__(kThreads) void k_step(const DevJob* __restrict__ jo
   const DevJob& J = jobs[tl.job];
   const int s = tick - J.start_tick;
   if (s < 0 || s >= J.nsteps) return;
+  // serving engine: a job marked two_step starts at an even tick, and the
+  // steps s & ~1, (s & ~1) + 1 that a two-step launch takes are skipped here
+  if (skip_pairs && J.two_step && two_step_pair(s & ~1, J.nt, J.nsteps)) return;
   if (J.mode == kModeBorn) {
     if (PH & kPhBorn) born_tile<TZ>(J, tl, s, sm);
     return;
@@ -1066,24 +1071,29 @@ hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s) {
 template <int TZ>
 static hipError_t launch_step_tz(int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
                                  int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
-                                 hipStream_t s) {
+                                 int skip_pairs, hipStream_t s) {
   const int per = (grid_tiles + 7) / 8;
   dim3 grid(8 * per), block(kThreads);
   if (phases == kPhFwd)
-    hipLaunchKernelGGL((k_step<TZ, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+    hipLaunchKernelGGL((k_step<TZ, kPhFwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off,
+                       skip_pairs);
   else if (phases == kPhBwd)
-    hipLaunchKernelGGL((k_step<TZ, kPhBwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+    hipLaunchKernelGGL((k_step<TZ, kPhBwd>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off,
+                       skip_pairs);
   else if (phases == kPhBorn)
-    hipLaunchKernelGGL((k_step<TZ, kPhBorn>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+    hipLaunchKernelGGL((k_step<TZ, kPhBorn>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off,
+                       skip_pairs);
   else
-    hipLaunchKernelGGL((k_step<TZ, kPhAny>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off);
+    hipLaunchKernelGGL((k_step<TZ, kPhAny>), grid, block, 0, s, jobs, tiles, ctl, ntiles, use_ctl_tick, tick_off,
+                       skip_pairs);
   return hipGetLastError();
 }
 
 hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, const int2* recs2,
-                        int ntiles, const StepCtl* ctl, int use_ctl_tick, int tick_off, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  const int per = (ntiles + 7) / 8;
+                        int ntiles, int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
+                        hipStream_t s) {
+  if (grid_tiles <= 0) return hipSuccess;
+  const int per = (grid_tiles + 7) / 8;
   dim3 grid(8 * per), block(kThreads);
 #define RTM_STEP2(T, P) \
   hipLaunchKernelGGL((k_step2<T, P>), grid, block, 0, s, jobs, tiles, recs2, ctl, ntiles, use_ctl_tick, tick_off)
@@ -1100,11 +1110,14 @@ hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tile
 
 hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
                        int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
-                       hipStream_t s) {
+                       hipStream_t s, int skip_pairs) {
   switch (tz) {
-    case 16: return launch_step_tz<16>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, s);
-    case 32: return launch_step_tz<32>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, s);
-    case 64: return launch_step_tz<64>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, s);
+    case 16:
+      return launch_step_tz<16>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, skip_pairs, s);
+    case 32:
+      return launch_step_tz<32>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, skip_pairs, s);
+    case 64:
+      return launch_step_tz<64>(phases, jobs, tiles, ntiles, grid_tiles, ctl, use_ctl_tick, tick_off, skip_pairs, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -38,8 +39,20 @@
 #include "rtm_bet.h"
 #include "rtm_codec.h"
 #include "rtm_internal.h"
+#include "rtm_sched.h"
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 using namespace rtm;
+
+// Named ranges for profiler timelines (rocprofv3 --marker-trace): the
+// scheduler's admission, launch and finalisation, and the batched phases.
+struct RoctxRange {
+  explicit RoctxRange(const char* name) { roctxRangePushA(name); }
+  ~RoctxRange() { roctxRangePop(); }
+  RoctxRange(const RoctxRange&) = delete;
+  RoctxRange& operator=(const RoctxRange&) = delete;
+};
 using rtm::Arena;
 
 // ===========================================================================
@@ -196,17 +209,15 @@ struct Model {
   float vmax = 0;
   // statistics (allocated on first use)
   Block mean, m2, count, stack;
-  int active = 0;  // queued + running jobs of this model
 };
 
+// What the runtime keeps of a served job beside its JobBook entry (state,
+// timestamps): the request and, once admitted, its working set.
 struct EnsJob {
   uint64_t ticket = 0;
   rtm_job spec{};
-  int state = RTM_JOB_QUEUED;
-  int status = RTM_OK;
-  double t_submit = 0, t_admit = 0, t_done = 0;
   std::unique_ptr<HostJob> job;
-  int bypassed = 0;
+  double gpu_ms = 0;  // share of the launch time of the cycles it ran in (by algorithmic bytes)
 };
 
 struct StatsAcc {
@@ -237,20 +248,17 @@ struct rtm_ctx {
   bool tune_file_loaded = false;
   // counters
   std::atomic<uint64_t> steps_launched{0}, graph_replays{0}, grid_updates{0}, alg_bytes{0};
-  std::atomic<uint64_t> jobs_submitted{0}, jobs_done{0}, jobs_failed{0}, jobs_cancelled{0};
+
   // ensemble
   std::mutex mu;
   std::condition_variable cv, cv_done;
   std::map<int, Model> models;
-  std::unordered_map<uint64_t, std::unique_ptr<EnsJob>> jobs;
-  std::deque<uint64_t> queue;
-  std::vector<uint64_t> running;
-  uint64_t next_ticket = 1;
-  int queue_cap = 1 << 16;
+  std::unordered_map<uint64_t, std::unique_ptr<EnsJob>> jobs;  // payloads, by ticket
+  std::unique_ptr<JobBook> book;  // queue, admission order, states, timestamps
   bool stop = false;
   std::thread sched;
   bool sched_started = false;
-  int active_jobs = 0, queued_jobs = 0;
+  FILE* job_log = nullptr;  // RTM_LOG: one JSON line per job reaching a final state
   uint32_t* scratch_u32 = nullptr;     // small device scratch (vmax etc.)
   double* scratch_f64 = nullptr;      // partials of the maps' reductions (2 kRedBlocks + 2 doubles)
   // last codec call: HIP events around its kernel, algorithmic bytes, 1 encode / 2 decode
@@ -732,6 +740,14 @@ static int env_tz2() {
 }
 static bool two_step_on() { return env_tz2() != 0; }
 
+// Served reconstruct-mode jobs without illumination advance two steps per
+// launch where the scheme allows (four buffers per wavefield); the others,
+// and all jobs when RTM_TILE_Z2 = 0, one step per launch.
+static bool served_two_step(const JobGeom& g) {
+  return g.mode == kModeRecon && !(g.flags & RTM_IMG_ILLUM) && two_step_on();
+}
+
+
 // A two-step tile reads 8 rows past its last row, and the staged rows of the
 // last tile column run past the row end into the next row: the last tile
 // must end within the 64-row rounding of the field allocation, whose 9 zero
@@ -743,6 +759,42 @@ static bool tz2_fits(const std::vector<HostJob*>& js, int tz2) {
     if (z0last + tz2 > field_rows(nzp) - 2 * kTopRows) return false;
   }
   return true;
+}
+
+// Appends the two-step tiles of a job (tz2 rows x 56 columns) with the
+// receivers of each tile's middle region, {index in the middle region,
+// receiver}, to tiles / recs; the tiles name job `job_index`.
+static void append_two_step_tiles(const HostJob& hj, int job_index, int tz2, std::vector<Tile>& tiles,
+                                  std::vector<int2>& recs) {
+  const DevJob& d = hj.d;
+  // receiver nodes (padded coordinates) from the one-step tiles' lists,
+  // whose local index is (row in tile) * 64 + (column in tile)
+  std::vector<std::pair<int, int>> rz(hj.recs.size());  // (row, receiver), sorted by row
+  std::vector<int> rx(hj.recs.size());
+  for (const Tile& one : hj.tiles)
+    for (int q = one.rec_begin; q < one.rec_begin + one.rec_count; ++q) {
+      const int local = hj.recs[q].x, r = hj.recs[q].y;
+      rz[r] = {one.z0 + local / kTileX, r};
+      rx[r] = one.x0 + local % kTileX;
+    }
+  std::sort(rz.begin(), rz.end());
+  for (int z0 = 0; z0 < d.nzp; z0 += tz2)
+    for (int x0 = 0; x0 < d.nxp; x0 += kTileX2) {
+      Tile tl{};
+      tl.job = job_index;
+      tl.z0 = z0;
+      tl.x0 = x0;
+      tl.rec_begin = (int)recs.size();
+      // receivers in the middle region rows [z0 - 4, z0 + tz2 + 4), columns [x0 - 4, x0 + 60)
+      auto lo = std::lower_bound(rz.begin(), rz.end(), std::make_pair(z0 - kHalo, -1));
+      for (auto it = lo; it != rz.end() && it->first < z0 + tz2 + kHalo; ++it) {
+        const int xr = rx[it->second];
+        if (xr >= x0 - kHalo && xr < x0 + kTileX2 + kHalo)
+          recs.push_back(make_int2((it->first - (z0 - kHalo)) * kTileX + (xr - (x0 - kHalo)), it->second));
+      }
+      tl.rec_count = (int)recs.size() - tl.rec_begin;
+      tiles.push_back(tl);
+    }
 }
 
 // tz2f / tz2b > 0 also build the two-step tile tables of the forward and the
@@ -764,38 +816,7 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   for (auto [tw, tz2] : {std::make_pair(&t.fw, tz2f), std::make_pair(&t.bw, tz2b)}) {
     if (!pairs || (tz2 != 16 && tz2 != 24 && tz2 != 32)) continue;
     if (!tz2_fits(js, tz2)) tz2 = 16;
-    for (size_t i = 0; i < js.size(); ++i) {
-      const DevJob& d = js[i]->d;
-      const HostJob& hj = *js[i];
-      // receiver nodes (padded coordinates) from the one-step tiles' lists,
-      // whose local index is (row in tile) * 64 + (column in tile)
-      std::vector<std::pair<int, int>> rz(hj.recs.size());  // (row, receiver), sorted by row
-      std::vector<int> rx(hj.recs.size());
-      for (const Tile& one : hj.tiles)
-        for (int q = one.rec_begin; q < one.rec_begin + one.rec_count; ++q) {
-          const int local = hj.recs[q].x, r = hj.recs[q].y;
-          rz[r] = {one.z0 + local / kTileX, r};
-          rx[r] = one.x0 + local % kTileX;
-        }
-      std::sort(rz.begin(), rz.end());
-      for (int z0 = 0; z0 < d.nzp; z0 += tz2)
-        for (int x0 = 0; x0 < d.nxp; x0 += kTileX2) {
-          Tile tl{};
-          tl.job = (int)i;
-          tl.z0 = z0;
-          tl.x0 = x0;
-          tl.rec_begin = (int)tw->hrecs->size();
-          // receivers in the middle region rows [z0 - 4, z0 + tz2 + 4), columns [x0 - 4, x0 + 60)
-          auto lo = std::lower_bound(rz.begin(), rz.end(), std::make_pair(z0 - kHalo, -1));
-          for (auto it = lo; it != rz.end() && it->first < z0 + tz2 + kHalo; ++it) {
-            const int xr = rx[it->second];
-            if (xr >= x0 - kHalo && xr < x0 + kTileX2 + kHalo)
-              tw->hrecs->push_back(make_int2((it->first - (z0 - kHalo)) * kTileX + (xr - (x0 - kHalo)), it->second));
-          }
-          tl.rec_count = (int)tw->hrecs->size() - tl.rec_begin;
-          tw->htiles->push_back(tl);
-        }
-    }
+    for (size_t i = 0; i < js.size(); ++i) append_two_step_tiles(*js[i], (int)i, tz2, *tw->htiles, *tw->hrecs);
     tw->ntiles = (int)tw->htiles->size();
     tw->tz = tz2;
   }
@@ -953,14 +974,14 @@ static int time_tz2(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float*
     int nfw = 0, nbw = 0;
     for (int st = 0; st + 1 < nf && er == hipSuccess; st += 2) {
       if (st == 4) er = hipEventRecord(e[0], s);
-      if (er == hipSuccess) er = launch_step2(tz2, kPhFwd, t.jobs, t.fw.tiles, t.fw.recs, t.fw.ntiles, t.ctl, 0, st, s);
+      if (er == hipSuccess) er = launch_step2(tz2, kPhFwd, t.jobs, t.fw.tiles, t.fw.recs, t.fw.ntiles, t.fw.ntiles, t.ctl, 0, st, s);
       nfw += st >= 4;
     }
     if (er == hipSuccess) er = hipEventRecord(e[1], s);
     // backward pairs from level nt - 3 down (steps nf + 2, nf + 4, ..)
     for (int st = nf + 2, k = 0; st + 1 < nsteps && er == hipSuccess; st += 2, ++k) {
       if (k == 2) er = hipEventRecord(e[2], s);
-      if (er == hipSuccess) er = launch_step2(tz2, kPhBwd, t.jobs, t.bw.tiles, t.bw.recs, t.bw.ntiles, t.ctl, 0, st, s);
+      if (er == hipSuccess) er = launch_step2(tz2, kPhBwd, t.jobs, t.bw.tiles, t.bw.recs, t.bw.ntiles, t.bw.ntiles, t.ctl, 0, st, s);
       nbw += k >= 2;
     }
     if (er == hipSuccess) er = hipEventRecord(e[3], s);
@@ -1088,6 +1109,10 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   for (auto& e : ctx->ph_ev) HIP_OK(hipEventCreate(&e));
   for (auto& e : ctx->zc_ev) HIP_OK(hipEventCreate(&e));
   for (auto& e : ctx->bet_ev) HIP_OK(hipEventCreate(&e));
+  // A served job must fit the arena beside a few KB of tables; larger ones are
+  // refused at submit.
+  ctx->book = std::make_unique<JobBook>(now_s, arena_bytes > 4096 ? arena_bytes - 4096 : 0);
+  if (const char* path = getenv("RTM_LOG")) ctx->job_log = fopen(path, "a");
   ctx->scratch_u32 = static_cast<uint32_t*>(ctx->arena.alloc(256));
   ctx->scratch_f64 = static_cast<double*>(ctx->arena.alloc((2 * kRedBlocks + 2) * sizeof(double)));
   if (!ctx->scratch_u32 || !ctx->scratch_f64) return fail(RTM_E_NOMEM, "arena too small for the context's scratch");
@@ -1143,6 +1168,7 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
   for (auto e : ctx->zc_ev) (void)hipEventDestroy(e);
   for (auto e : ctx->bet_ev) (void)hipEventDestroy(e);
   if (ctx->own_arena) (void)hipFree(ctx->own_arena);
+  if (ctx->job_log) fclose(ctx->job_log);
   delete ctx;
   return RTM_OK;
 }
@@ -1349,7 +1375,7 @@ static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, in
   if (pairs) K = std::max(2, K & ~1);
   auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`
     if (pairs && left >= 2)
-      return launch_step2(tw.tz, ph, t.jobs, tw.tiles, tw.recs, tw.ntiles, t.ctl, 1, off, s);
+      return launch_step2(tw.tz, ph, t.jobs, tw.tiles, tw.recs, tw.ntiles, tw.ntiles, t.ctl, 1, off, s);
     return launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, off, s);
   };
   int done = 0;
@@ -1472,7 +1498,10 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   const int nt = grid->nt, K = graph_k();
   std::vector<hipGraphExec_t> graphs;
   HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
+  roctxRangePushA("rtm.batch.forward");  // host-side enqueue of the phase
   rc = graph_steps(ctx, s, tz, kPhFwd, t, nt - 1, K, graphs, true);
+  roctxRangePop();
+  roctxRangePushA("rtm.batch.backward");
   if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc && t.bw.ntiles > 0 && nt >= 4) {
     // levels nt - 1 and nt - 2 are imaged without reconstruction: one step each
@@ -1484,6 +1513,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   } else if (!rc) {
     rc = graph_steps(ctx, s, tz, kPhBwd, t, nt, K, graphs, false);  // one step per launch
   }
+  roctxRangePop();
   if (!rc) rc = hipEventRecord(ctx->ph_ev[2], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc) {
     // algorithmic bytes of one forward / one backward launch over all shots
@@ -1556,8 +1586,7 @@ extern "C" int rtm_model_register(rtm_ctx* ctx, int32_t realization, const float
     if (m0.nz != nz || m0.nx != nx)
       return fail(RTM_E_INVAL, "all registered models must share one size (%d x %d)", m0.nz, m0.nx);
   }
-  auto it = ctx->models.find(realization);
-  if (it != ctx->models.end() && it->second.active > 0)
+  if (ctx->book->in_flight(realization) > 0)
     return fail(RTM_E_AGAIN, "realization %d has jobs in flight", realization);
   lk.unlock();
   Block vb;
@@ -1574,8 +1603,7 @@ extern "C" int rtm_model_register(rtm_ctx* ctx, int32_t realization, const float
   lk.lock();
   // Re-check under the lock: a job of this realization may have been queued,
   // or a model of another size registered, while the copy ran unlocked.
-  auto again = ctx->models.find(realization);
-  const bool busy = again != ctx->models.end() && again->second.active > 0;
+  const bool busy = ctx->book->in_flight(realization) > 0;
   bool other_size = false;
   for (auto& kv : ctx->models)
     if (kv.first != realization && (kv.second.nz != nz || kv.second.nx != nx)) other_size = true;
@@ -1619,21 +1647,19 @@ extern "C" int rtm_ensemble_submit(rtm_ctx* ctx, const rtm_job* job, uint64_t* t
   g.nrec = 0;
   if ((rc = check_job(g, job->src, &probe))) return rc;
   g.nrec = job->width;
+  if (served_two_step(g)) g.nbuf = 4;  // as the scheduler builds it
   if ((rc = check_cfl(m.vmax, gr.dt, gr.dz, gr.dx))) return rc;
-  if (footprint(g).total + 4096 > ctx->arena.size())
+  uint64_t t = 0;
+  rc = ctx->book->submit(job->realization, footprint(g).total, &t);
+  if (rc == kSchedNomem)
     return fail(RTM_E_NOMEM, "job needs %zu bytes, larger than the whole arena (%zu)", footprint(g).total,
                 ctx->arena.size());
-  if ((int)ctx->queue.size() >= ctx->queue_cap) return fail(RTM_E_AGAIN, "queue full (%d)", ctx->queue_cap);
+  if (rc == kSchedAgain) return fail(RTM_E_AGAIN, "queue full (%zu jobs)", ctx->book->queued());
   auto ej = std::make_unique<EnsJob>();
-  ej->ticket = ctx->next_ticket++;
+  ej->ticket = t;
   ej->spec = *job;
-  ej->t_submit = now_s();
-  *ticket = ej->ticket;
-  ctx->queue.push_back(ej->ticket);
-  ctx->jobs.emplace(ej->ticket, std::move(ej));
-  m.active++;
-  ctx->jobs_submitted++;
-  ctx->queued_jobs = (int)ctx->queue.size();
+  *ticket = t;
+  ctx->jobs.emplace(t, std::move(ej));
   if (!ctx->sched_started) {
     ctx->sched_started = true;
     ctx->sched = std::thread(sched_main, ctx);
@@ -1677,15 +1703,31 @@ static int ensure_stats(rtm_ctx* ctx, hipStream_t s, Model& m, bool stats, bool 
 
 static bool has_stats(const Model& m) { return m.mean.p && m.m2.p && m.count.p; }
 
+// Device tables of the serving engine's launches.  A job that takes two-step
+// launches (reconstruct mode without illumination, marked two_step) is in
+// the forward or backward two-step table for the cycles in which it has a
+// step pair of that phase, and in the one-step table for the cycles in
+// which it has a step that no pair covers (the first backward levels, an odd
+// phase boundary, a last single level); every other job is in the one-step
+// table.  The tables are rebuilt when the active jobs or these memberships
+// change.
 struct SchedTables {
   std::vector<Block> blocks;
   DevJob* jobs = nullptr;
-  Tile* tiles = nullptr;
+  Tile* tiles = nullptr;                              // one-step tiles
+  Tile* tiles_f = nullptr;                            // two-step tiles, forward phase
+  Tile* tiles_b = nullptr;                            // two-step tiles, backward phase
+  int2* recs_f = nullptr;                             // their receivers
+  int2* recs_b = nullptr;
   StepCtl* ctl = nullptr;
-  int cap_jobs = 0, cap_tiles = 0;
-  std::map<int, hipGraphExec_t> graphs;  // grid-tile bucket -> K-step graph
+  size_t cap_jobs = 0, cap_tiles = 0, cap_f = 0, cap_b = 0, cap_rf = 0, cap_rb = 0;
+  std::map<std::array<int, 3>, hipGraphExec_t> graphs;  // launch buckets (one-step, forward, backward) -> graph
   std::vector<DevJob> hjobs;
-  std::vector<Tile> htiles;
+  std::vector<Tile> htiles, htf, htb;
+  std::vector<int2> hrf, hrb;
+  std::vector<uint8_t> kinds;  // per active job: 1 one-step, 2 forward pairs, 4 backward pairs
+  std::array<int32_t, 3> counts{};  // ntiles_fw, ntiles, ntiles_bw as the control block holds them
+  hipEvent_t ev[2] = {nullptr, nullptr};  // around each cycle's launches
 };
 
 static int tile_bucket(int n) {
@@ -1694,54 +1736,121 @@ static int tile_bucket(int n) {
   return b;
 }
 
+// Launch kinds a job needs in the cycle of ticks [tick, tick + K) (K even,
+// jobs start at even ticks): 1 one-step launches, 2 forward pairs, 4
+// backward pairs.
+static uint8_t cycle_kinds(const DevJob& d, int tick, int K) {
+  if (!d.two_step) return 1;
+  uint8_t k = 0;
+  for (int t = tick; t < tick + K; t += 2) {
+    const int s = t - d.start_tick;
+    if (s < 0 || s >= d.nsteps) continue;
+    if (two_step_pair(s, d.nt, d.nsteps)) k |= (s + 1 < d.nt - 1) ? 2 : 4;
+    else k |= 1;
+  }
+  return k;
+}
+
+template <class T>
+static int grow(rtm_ctx* ctx, SchedTables& Tb, T*& p, size_t& cap, size_t need) {
+  if (need <= cap && p) return RTM_OK;
+  cap = (size_t)tile_bucket((int)std::max<size_t>(need, 1));
+  void* q = nullptr;
+  if (!alloc_block(ctx, Tb.blocks, cap * sizeof(T), &q)) return fail(RTM_E_NOMEM, "arena exhausted (scheduler tables)");
+  p = static_cast<T*>(q);
+  return RTM_OK;
+}
+
+// K steps of every active job: one graph replay of K one-step launches, or,
+// when jobs take two-step launches, K/2 rounds of (forward pairs, backward
+// pairs, one-step launch of the even tick, one-step launch of the odd tick).
 static int sched_cycle(rtm_ctx* ctx, SchedTables& T, std::vector<EnsJob*>& active, bool& changed, int& tick,
-                       int tz, int K) {
+                       int tz, int tzf, int tzb, int K, float* cycle_ms) {
   hipStream_t s = ctx->sched_stream;
-  if (changed) {
+  RoctxRange range("rtm.sched.cycle");
+  *cycle_ms = 0;
+  if (!T.ev[0]) {
+    HIP_OK(hipEventCreate(&T.ev[0]));
+    HIP_OK(hipEventCreate(&T.ev[1]));
+  }
+  std::vector<uint8_t> kinds(active.size());
+  for (size_t i = 0; i < active.size(); ++i) kinds[i] = cycle_kinds(active[i]->job->d, tick, K);
+  if (changed || kinds != T.kinds) {
     T.hjobs.clear();
     T.htiles.clear();
+    T.htf.clear();
+    T.htb.clear();
+    T.hrf.clear();
+    T.hrb.clear();
     for (size_t i = 0; i < active.size(); ++i) {
-      T.hjobs.push_back(active[i]->job->d);
-      for (Tile tl : active[i]->job->tiles) {
-        tl.job = (int)i;
-        T.htiles.push_back(tl);
-      }
+      const HostJob& j = *active[i]->job;
+      T.hjobs.push_back(j.d);
+      if (kinds[i] & 1)
+        for (Tile tl : j.tiles) {
+          tl.job = (int)i;
+          T.htiles.push_back(tl);
+        }
+      if (kinds[i] & 2) append_two_step_tiles(j, (int)i, tzf, T.htf, T.hrf);
+      if (kinds[i] & 4) append_two_step_tiles(j, (int)i, tzb, T.htb, T.hrb);
     }
-    const int nj = (int)T.hjobs.size(), ntl = (int)T.htiles.size();
-    if (nj > T.cap_jobs || ntl > T.cap_tiles) {
+    const bool fits = T.hjobs.size() <= T.cap_jobs && T.htiles.size() <= T.cap_tiles && T.htf.size() <= T.cap_f &&
+                      T.htb.size() <= T.cap_b && T.hrf.size() <= T.cap_rf && T.hrb.size() <= T.cap_rb && T.ctl;
+    if (!fits) {  // new device tables (graphs hold the old pointers: drop them)
       HIP_OK(hipStreamSynchronize(s));
       for (auto& kv : T.graphs) (void)hipGraphExecDestroy(kv.second);
       T.graphs.clear();
       release_blocks(ctx, T.blocks);
-      T.cap_jobs = std::max(64, tile_bucket(nj));
-      T.cap_tiles = tile_bucket(ntl);
-      void* p;
-      if (!alloc_block(ctx, T.blocks, (size_t)T.cap_jobs * sizeof(DevJob), &p)) return fail(RTM_E_NOMEM, "job table");
-      T.jobs = static_cast<DevJob*>(p);
-      if (!alloc_block(ctx, T.blocks, (size_t)T.cap_tiles * sizeof(Tile), &p)) return fail(RTM_E_NOMEM, "tile table");
-      T.tiles = static_cast<Tile*>(p);
-      if (!alloc_block(ctx, T.blocks, sizeof(StepCtl), &p)) return fail(RTM_E_NOMEM, "control block");
-      T.ctl = static_cast<StepCtl*>(p);
+      T.jobs = nullptr;
+      T.tiles = T.tiles_f = T.tiles_b = nullptr;
+      T.recs_f = T.recs_b = nullptr;
+      T.ctl = nullptr;
+      T.cap_jobs = T.cap_tiles = T.cap_f = T.cap_b = T.cap_rf = T.cap_rb = 0;
+      size_t one = 1;
+      if (int rc = grow(ctx, T, T.jobs, T.cap_jobs, std::max<size_t>(T.hjobs.size(), 64))) return rc;
+      if (int rc = grow(ctx, T, T.tiles, T.cap_tiles, T.htiles.size())) return rc;
+      if (int rc = grow(ctx, T, T.tiles_f, T.cap_f, T.htf.size())) return rc;
+      if (int rc = grow(ctx, T, T.tiles_b, T.cap_b, T.htb.size())) return rc;
+      if (int rc = grow(ctx, T, T.recs_f, T.cap_rf, T.hrf.size())) return rc;
+      if (int rc = grow(ctx, T, T.recs_b, T.cap_rb, T.hrb.size())) return rc;
+      if (int rc = grow(ctx, T, T.ctl, one, 1)) return rc;
       StepCtl c{};
       c.tick = tick;
       HIP_OK(hipMemcpyAsync(T.ctl, &c, sizeof c, hipMemcpyHostToDevice, s));
     }
-    HIP_OK(hipMemcpyAsync(T.jobs, T.hjobs.data(), T.hjobs.size() * sizeof(DevJob), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(T.tiles, T.htiles.data(), T.htiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
-    int ntl_i = ntl;
-    HIP_OK(hipMemcpyAsync(&T.ctl->ntiles, &ntl_i, sizeof(int), hipMemcpyHostToDevice, s));
-    HIP_OK(hipStreamSynchronize(s));
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+      return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    HIP_OK(up(T.jobs, T.hjobs.data(), T.hjobs.size() * sizeof(DevJob)));
+    HIP_OK(up(T.tiles, T.htiles.data(), T.htiles.size() * sizeof(Tile)));
+    HIP_OK(up(T.tiles_f, T.htf.data(), T.htf.size() * sizeof(Tile)));
+    HIP_OK(up(T.tiles_b, T.htb.data(), T.htb.size() * sizeof(Tile)));
+    HIP_OK(up(T.recs_f, T.hrf.data(), T.hrf.size() * sizeof(int2)));
+    HIP_OK(up(T.recs_b, T.hrb.data(), T.hrb.size() * sizeof(int2)));
+    T.counts = {(int32_t)T.htf.size(), (int32_t)T.htiles.size(), (int32_t)T.htb.size()};
+    HIP_OK(up(&T.ctl->ntiles_fw, T.counts.data(), sizeof(int32_t) * 3));
+    HIP_OK(hipStreamSynchronize(s));  // the host staging is reused next time
+    T.kinds = kinds;
     changed = false;
   }
-  const int ntl = (int)T.htiles.size();
-  const int bucket = tile_bucket(ntl);
-  auto git = T.graphs.find(bucket);
+  const int n1 = T.counts[1], nf = T.counts[0], nb = T.counts[2];
+  const std::array<int, 3> key = {n1 ? tile_bucket(n1) : 0, nf ? tile_bucket(nf) : 0, nb ? tile_bucket(nb) : 0};
+  auto git = T.graphs.find(key);
   if (git == T.graphs.end()) {
     hipGraph_t g = nullptr;
     HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e0 = hipSuccess;
-    for (int i = 0; i < K && e0 == hipSuccess; ++i)
-      e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, bucket, T.ctl, 1, i, s);
+    if (!key[1] && !key[2]) {
+      for (int i = 0; i < K && e0 == hipSuccess; ++i)
+        e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, key[0], T.ctl, 1, i, s, 1);
+    } else {
+      for (int i = 0; i < K && e0 == hipSuccess; i += 2) {
+        if (key[1]) e0 = launch_step2(tzf, kPhFwd, T.jobs, T.tiles_f, T.recs_f, -1, key[1], T.ctl, 1, i, s);
+        if (e0 == hipSuccess && key[2])
+          e0 = launch_step2(tzb, kPhBwd, T.jobs, T.tiles_b, T.recs_b, -1, key[2], T.ctl, 1, i, s);
+        for (int k = 0; k < 2 && key[0] && e0 == hipSuccess; ++k)
+          e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, key[0], T.ctl, 1, i + k, s, 1);
+      }
+    }
     if (e0 == hipSuccess) e0 = launch_advance(T.ctl, K, s);
     hipError_t e1 = hipStreamEndCapture(s, &g);
     if (e0 != hipSuccess || e1 != hipSuccess) {
@@ -1752,79 +1861,130 @@ static int sched_cycle(rtm_ctx* ctx, SchedTables& T, std::vector<EnsJob*>& activ
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(RTM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    git = T.graphs.emplace(bucket, ex).first;
+    git = T.graphs.emplace(key, ex).first;
   }
+  HIP_OK(hipEventRecord(T.ev[0], s));
   HIP_OK(hipGraphLaunch(git->second, s));
+  HIP_OK(hipEventRecord(T.ev[1], s));
   ctx->graph_replays++;
   ctx->steps_launched += K;
   tick += K;
   HIP_OK(hipStreamSynchronize(s));
+  (void)hipEventElapsedTime(cycle_ms, T.ev[0], T.ev[1]);
   return RTM_OK;
 }
 
+// One JSON line per job reaching a final state, appended to the file named
+// by RTM_LOG (opened at context creation): the job's request, state and
+// status, host timestamps (s), queueing / running / total times (ms), its
+// grid updates and algorithmic HBM bytes, and gpu_ms, its share of the
+// launch time of the scheduler cycles it ran in (each cycle's HIP-event time
+// split over the jobs in it in proportion to their algorithmic bytes per
+// step).  Called with ctx->mu held.
+static void log_job(rtm_ctx* ctx, const SchedEntry& e, const EnsJob& ej) {
+  if (!ctx->job_log) return;
+  static const char* kState[] = {"queued", "running", "done", "failed", "cancelled", "queued"};
+  static const char* kMode[] = {"store", "reconstruct"};
+  static const char* kDtype[] = {"fp32", "bf16", "fp16"};
+  const rtm_job& j = ej.spec;
+  const bool admitted = e.t_admit > 0;
+  const int mode = j.img.src_mode == RTM_SRC_RECONSTRUCT ? 1 : 0;
+  const int dt = j.img.snap_dtype >= 0 && j.img.snap_dtype <= 2 ? j.img.snap_dtype : 0;
+  fprintf(ctx->job_log,
+          "{\"ticket\": %llu, \"user_tag\": %llu, \"realization\": %d, \"state\": \"%s\", \"status\": %d, "
+          "\"src\": [%d, %d], \"ix0\": %d, \"width\": %d, \"nt\": %d, \"mode\": \"%s\", \"snap_dtype\": \"%s\", "
+          "\"snap_stride\": %d, \"t_submit\": %.6f, \"t_admit\": %.6f, \"t_done\": %.6f, \"queue_ms\": %.3f, "
+          "\"run_ms\": %.3f, \"latency_ms\": %.3f, \"gpu_ms\": %.3f, \"grid_updates\": %llu, \"alg_bytes\": %llu}\n",
+          (unsigned long long)e.ticket, (unsigned long long)j.user_tag, j.realization, kState[e.state], e.status,
+          j.src.iz, j.src.ix, j.ix0, j.width, j.nt, kMode[mode], kDtype[dt], mode ? 1 : j.img.snap_stride, e.t_submit,
+          e.t_admit, e.t_done, 1e3 * ((admitted ? e.t_admit : e.t_done) - e.t_submit),
+          admitted ? 1e3 * (e.t_done - e.t_admit) : 0.0, 1e3 * (e.t_done - e.t_submit), ej.gpu_ms,
+          (unsigned long long)(ej.job ? ej.job->updates : 0), (unsigned long long)(ej.job ? ej.job->alg_bytes : 0));
+  fflush(ctx->job_log);
+}
+
+// The scheduler thread.  Each round: an admission pass over the queue (a
+// candidate's working set is built without the context mutex; the JobBook
+// marks it ADMITTING meanwhile), K steps of every admitted job in one graph
+// replay, then the finished jobs' images go through the non-finite check
+// into the statistics and stack, and their memory is released behind the
+// stream.
 static void sched_main(rtm_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   hipStream_t s = ctx->sched_stream;
   SchedTables T;
   std::vector<EnsJob*> active;
   bool changed = false;
-  int tick = 0;
-  int tz = 0;  // tuned on the first admitted job; every job of the scheduler shares it
-  const int K = std::max(1, std::min(graph_k(), 64));
-  const int kMaxBypass = 8;
+  int tick = 0;  // advances by K, so every job starts at an even tick
+  int tz = 0;    // tuned on the first admitted job; every job of the scheduler shares it
+  int tzf = 0, tzb = 0;  // two-step heights, tuned on the first reconstruct-mode job (0: off)
+  bool tz2_tuned = false;
+  const int K = std::max(2, std::min(graph_k(), 64) & ~1);
   for (;;) {
-    // ---- admission (FIFO with bounded bypass) ----
     {
       std::unique_lock<std::mutex> lk(ctx->mu);
       if (ctx->stop) break;
-      if (active.empty() && ctx->queue.empty()) {
+      if (active.empty() && ctx->book->queued() == 0) {
         ctx->cv_done.notify_all();
-        ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty(); });
+        ctx->cv.wait(lk, [&] { return ctx->stop || ctx->book->queued() > 0; });
         continue;
       }
-      bool blocked_head = false;
-      for (auto qi = ctx->queue.begin(); qi != ctx->queue.end();) {
-        EnsJob* ej = ctx->jobs[*qi].get();
-        Model& m = ctx->models[ej->spec.realization];
+    }
+    // ---- admission pass (first come, first served, bounded bypass) ----
+    {
+      RoctxRange range("rtm.sched.admit");
+      AdmitPass pass;
+      for (;;) {
+        uint64_t t = 0;
+        EnsJob* ej = nullptr;
         JobGeom g;
-        rtm_grid gr = m.grid;
-        gr.nt = ej->spec.nt;
-        fill_geom_rtm(&gr, ej->spec.ix0, ej->spec.width, &ej->spec.img, ej->spec.width, g);
-        auto hj = std::make_unique<HostJob>();
-        std::vector<rtm_point> recs(ej->spec.width);
-        for (int r = 0; r < ej->spec.width; ++r) recs[r] = {ej->spec.rec_iz, ej->spec.ix0 + r};
+        const float* vel = nullptr;
         int rc = RTM_OK;
-        bool st = ej->spec.flags & RTM_JOB_ACC_STATS, sk = ej->spec.flags & RTM_JOB_ACC_STACK;
-        rc = ensure_stats(ctx, s, m, st, sk);
-        if (!rc && tz == 0) tz = autotune_tz(ctx, s, g, static_cast<const float*>(m.vel.p), 16);
-        if (!rc)
-          rc = build_job(ctx, s, g, tz, static_cast<const float*>(m.vel.p), ej->spec.wavelet_dev, ej->spec.src,
-                         recs.data(), ej->spec.data_dev, nullptr, *hj, nullptr);
-        if (rc == RTM_E_NOMEM) {
-          if (blocked_head || ++ej->bypassed > kMaxBypass) break;  // keep the head from starving
-          blocked_head = true;
-          ++qi;
-          continue;
+        {
+          std::lock_guard<std::mutex> lk(ctx->mu);
+          if (ctx->stop) break;
+          t = ctx->book->next_candidate(pass);
+          if (!t) break;
+          ej = ctx->jobs.at(t).get();
+          Model& m = ctx->models[ej->spec.realization];
+          rtm_grid gr = m.grid;
+          gr.nt = ej->spec.nt;
+          fill_geom_rtm(&gr, ej->spec.ix0, ej->spec.width, &ej->spec.img, ej->spec.width, g);
+          if (served_two_step(g)) g.nbuf = 4;
+          vel = static_cast<const float*>(m.vel.p);  // stable while the job is in flight
+          rc = ensure_stats(ctx, s, m, ej->spec.flags & RTM_JOB_ACC_STATS, ej->spec.flags & RTM_JOB_ACC_STACK);
         }
-        if (rc) {
-          ej->state = RTM_JOB_FAILED;
-          ej->status = rc;
-          ej->t_done = now_s();
-          m.active--;
-          ctx->jobs_failed++;
-          qi = ctx->queue.erase(qi);
-          continue;
+        // the working set, built without the mutex (polls and submits go on)
+        auto hj = std::make_unique<HostJob>();
+        if (!rc && tz == 0) tz = autotune_tz(ctx, s, g, vel, 16);
+        const bool pairs = served_two_step(g);
+        if (!rc && pairs && !tz2_tuned) {
+          autotune_tz2(ctx, s, g, vel, 16, &tzf, &tzb);
+          tz2_tuned = true;
         }
-        hj->d.start_tick = tick;
-        ej->job = std::move(hj);
-        ej->state = RTM_JOB_RUNNING;
-        ej->t_admit = now_s();
-        active.push_back(ej);
-        changed = true;
-        qi = ctx->queue.erase(qi);
+        if (!rc) {
+          std::vector<rtm_point> recs(ej->spec.width);
+          for (int r = 0; r < ej->spec.width; ++r) recs[r] = {ej->spec.rec_iz, ej->spec.ix0 + r};
+          rc = build_job(ctx, s, g, tz, vel, ej->spec.wavelet_dev, ej->spec.src, recs.data(), ej->spec.data_dev,
+                         nullptr, *hj, nullptr);
+        }
+        // steps that two-step launches take: only with heights whose last tile
+        // stays inside this job's field allocation
+        if (!rc && pairs && tzf > 0 && tzb > 0) {
+          std::vector<HostJob*> one{hj.get()};
+          hj->d.two_step = tz2_fits(one, tzf) && tz2_fits(one, tzb);
+        }
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->book->admit_result(pass, t, rc == RTM_E_NOMEM ? kSchedNomem : rc);
+        if (rc == RTM_OK) {
+          hj->d.start_tick = tick;
+          ej->job = std::move(hj);
+          active.push_back(ej);
+          changed = true;
+        } else if (rc != RTM_E_NOMEM) {
+          log_job(ctx, *ctx->book->find(t), *ej);
+        }
       }
-      ctx->active_jobs = (int)active.size();
-      ctx->queued_jobs = (int)ctx->queue.size();
     }
     if (active.empty()) {
       bool pending;
@@ -1840,20 +2000,18 @@ static void sched_main(rtm_ctx* ctx) {
       // fit (the arena is held by results not yet released): fail it rather
       // than wait forever.
       std::lock_guard<std::mutex> lk(ctx->mu);
-      if (!ctx->queue.empty()) {
-        EnsJob* ej = ctx->jobs[ctx->queue.front()].get();
-        ej->state = RTM_JOB_FAILED;
-        ej->status = RTM_E_NOMEM;
-        ej->t_done = now_s();
-        ctx->models[ej->spec.realization].active--;
-        ctx->jobs_failed++;
-        ctx->queue.pop_front();
-        ctx->queued_jobs = (int)ctx->queue.size();
-      }
+      if (uint64_t t = ctx->book->fail_head(RTM_E_NOMEM)) log_job(ctx, *ctx->book->find(t), *ctx->jobs.at(t));
       continue;
     }
     // ---- K steps of every active job ----
-    int rc = sched_cycle(ctx, T, active, changed, tick, tz, K);
+    float cycle_ms = 0;
+    int rc = sched_cycle(ctx, T, active, changed, tick, tz, tzf, tzb, K, &cycle_ms);
+    if (cycle_ms > 0) {
+      double total = 0;
+      for (EnsJob* ej : active) total += (double)ej->job->alg_bytes / ej->job->d.nsteps;
+      for (EnsJob* ej : active)
+        ej->gpu_ms += total > 0 ? cycle_ms * ((double)ej->job->alg_bytes / ej->job->d.nsteps) / total : 0.0;
+    }
     // ---- finalise finished jobs ----
     std::vector<EnsJob*> still;
     std::vector<EnsJob*> finished;
@@ -1864,6 +2022,7 @@ static void sched_main(rtm_ctx* ctx) {
         still.push_back(ej);
     }
     if (!finished.empty()) {
+      RoctxRange range("rtm.sched.finalize");
       // non-finite check of every finished image before it reaches the statistics
       std::vector<uint32_t> health(finished.size(), 0);
       if (!rc) {
@@ -1876,11 +2035,13 @@ static void sched_main(rtm_ctx* ctx) {
       }
       std::lock_guard<std::mutex> lk(ctx->mu);
       Deferred d;
+      std::vector<int> status(finished.size());
       for (size_t fi = 0; fi < finished.size(); ++fi) {
         EnsJob* ej = finished[fi];
         HostJob& j = *ej->job;
         Model& m = ctx->models[ej->spec.realization];
         const int jrc = rc ? rc : (health[fi] ? RTM_E_NONFINITE : RTM_OK);
+        status[fi] = jrc;
         if (!jrc) {
           if ((ej->spec.flags & RTM_JOB_ACC_STATS) && has_stats(m))
             (void)launch_welford(static_cast<double*>(m.mean.p), static_cast<double*>(m.m2.p),
@@ -1889,38 +2050,32 @@ static void sched_main(rtm_ctx* ctx) {
           if ((ej->spec.flags & RTM_JOB_ACC_STACK) && m.stack.p)
             (void)launch_stack(static_cast<float*>(m.stack.p), m.nx, j.g.ix0, j.d.image + j.g.nb, j.d.pitch,
                                j.g.nz, j.g.width, s);
-        }
-        for (auto& b : j.blocks) d.blocks.push_back(b);
-        j.blocks.clear();
-        ej->state = jrc ? RTM_JOB_FAILED : RTM_JOB_DONE;
-        ej->status = jrc;
-        m.active--;
-        if (jrc) {
-          ctx->jobs_failed++;
-        } else {
-          ctx->jobs_done++;
           ctx->grid_updates += j.updates;
           ctx->alg_bytes += j.alg_bytes;
         }
+        for (auto& b : j.blocks) d.blocks.push_back(b);
+        j.blocks.clear();
       }
-      (void)hipStreamSynchronize(s);
-      const double t = now_s();
-      for (EnsJob* ej : finished) ej->t_done = t;
+      (void)hipStreamSynchronize(s);  // the statistics include the job when it reads DONE
+      for (size_t fi = 0; fi < finished.size(); ++fi) {
+        ctx->book->finish(finished[fi]->ticket, status[fi]);
+        log_job(ctx, *ctx->book->find(finished[fi]->ticket), *finished[fi]);
+      }
       defer(ctx, s, std::move(d));
       active.swap(still);
       changed = true;
-      ctx->active_jobs = (int)active.size();
     }
     ctx->cv_done.notify_all();
   }
   (void)hipStreamSynchronize(s);
   for (auto& kv : T.graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto e : T.ev)
+    if (e) (void)hipEventDestroy(e);
   release_blocks(ctx, T.blocks);
   std::lock_guard<std::mutex> lk(ctx->mu);
   for (EnsJob* ej : active) {
     release_blocks(ctx, ej->job->blocks);
-    ej->state = RTM_JOB_CANCELLED;
-    ej->status = RTM_E_CANCELLED;
+    ctx->book->cancel_running(ej->ticket);
   }
   ctx->cv_done.notify_all();
 }
@@ -1929,21 +2084,23 @@ extern "C" int rtm_ensemble_poll(rtm_ctx* ctx, uint64_t ticket, rtm_job_info* in
                                  int32_t release) {
   if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
   std::unique_lock<std::mutex> lk(ctx->mu);
+  const SchedEntry* e = ctx->book->find(ticket);
   auto it = ctx->jobs.find(ticket);
-  if (it == ctx->jobs.end()) return fail(RTM_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  if (!e || it == ctx->jobs.end()) return fail(RTM_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
   EnsJob& ej = *it->second;
+  const int state = JobBook::visible_state(*e);
   if (info) {
-    info->state = ej.state;
-    info->status = ej.status;
-    info->t_submit = ej.t_submit;
-    info->t_admit = ej.t_admit;
-    info->t_done = ej.t_done;
+    info->state = state;
+    info->status = e->status;
+    info->t_submit = e->t_submit;
+    info->t_admit = e->t_admit;
+    info->t_done = e->t_done;
     info->grid_updates = ej.job ? ej.job->updates : 0;
     info->alg_bytes = ej.job ? ej.job->alg_bytes : 0;
     info->user_tag = ej.spec.user_tag;
   }
-  const bool final = ej.state == RTM_JOB_DONE || ej.state == RTM_JOB_FAILED || ej.state == RTM_JOB_CANCELLED;
-  if (ej.state == RTM_JOB_DONE && image_dev && ej.job && ej.job->image_blk.p) {
+  const bool final = JobBook::final_state(state);
+  if (state == RTM_JOB_DONE && image_dev && ej.job && ej.job->image_blk.p) {
     HIP_OK(hipSetDevice(ctx->device));
     const HostJob& hj = *ej.job;
     HIP_OK(hipMemcpy2DAsync(image_dev, (size_t)hj.g.width * 4, hj.d.image + hj.g.nb, (size_t)hj.d.pitch * 4,
@@ -1952,6 +2109,7 @@ extern "C" int rtm_ensemble_poll(rtm_ctx* ctx, uint64_t ticket, rtm_job_info* in
   if (final && release) {
     Deferred d;
     if (ej.job && ej.job->image_blk.p) d.blocks.push_back(ej.job->image_blk);
+    ctx->book->forget(ticket);
     ctx->jobs.erase(it);
     lk.unlock();
     return defer(ctx, ctx->stream, std::move(d));
@@ -1962,18 +2120,10 @@ extern "C" int rtm_ensemble_poll(rtm_ctx* ctx, uint64_t ticket, rtm_job_info* in
 extern "C" int rtm_ensemble_cancel(rtm_ctx* ctx, uint64_t ticket) {
   if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  auto it = ctx->jobs.find(ticket);
-  if (it == ctx->jobs.end()) return fail(RTM_E_NOTFOUND, "unknown ticket");
-  EnsJob& ej = *it->second;
-  if (ej.state != RTM_JOB_QUEUED) return fail(RTM_E_INVAL, "job is no longer queued");
-  auto qi = std::find(ctx->queue.begin(), ctx->queue.end(), ticket);
-  if (qi != ctx->queue.end()) ctx->queue.erase(qi);
-  ej.state = RTM_JOB_CANCELLED;
-  ej.status = RTM_E_CANCELLED;
-  ej.t_done = now_s();
-  ctx->models[ej.spec.realization].active--;
-  ctx->jobs_cancelled++;
-  ctx->queued_jobs = (int)ctx->queue.size();
+  const int rc = ctx->book->cancel(ticket);
+  if (rc == kSchedNotFound) return fail(RTM_E_NOTFOUND, "unknown ticket");
+  if (rc != kSchedOk) return fail(RTM_E_INVAL, "job is no longer queued");
+  log_job(ctx, *ctx->book->find(ticket), *ctx->jobs.at(ticket));
   ctx->cv_done.notify_all();
   return RTM_OK;
 }
@@ -1981,7 +2131,7 @@ extern "C" int rtm_ensemble_cancel(rtm_ctx* ctx, uint64_t ticket) {
 extern "C" int rtm_ensemble_drain(rtm_ctx* ctx) {
   if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
   std::unique_lock<std::mutex> lk(ctx->mu);
-  ctx->cv_done.wait(lk, [&] { return ctx->queue.empty() && ctx->active_jobs == 0; });
+  ctx->cv_done.wait(lk, [&] { return ctx->book->idle(); });
   lk.unlock();
   HIP_OK(hipSetDevice(ctx->device));
   HIP_OK(hipStreamSynchronize(ctx->sched_stream));
@@ -2665,10 +2815,15 @@ extern "C" int rtm_sqrt_check(rtm_ctx* ctx, uint32_t lo_bits, uint32_t hi_bits, 
 extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
   if (!ctx || !out) return fail(RTM_E_INVAL, "bad arguments");
   memset(out, 0, sizeof *out);
-  out->jobs_submitted = ctx->jobs_submitted;
-  out->jobs_done = ctx->jobs_done;
-  out->jobs_failed = ctx->jobs_failed;
-  out->jobs_cancelled = ctx->jobs_cancelled;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    out->jobs_submitted = ctx->book->submitted();
+    out->jobs_done = ctx->book->done();
+    out->jobs_failed = ctx->book->failed();
+    out->jobs_cancelled = ctx->book->cancelled();
+    out->active_jobs = (int32_t)ctx->book->running();
+    out->queued_jobs = (int32_t)ctx->book->queued();
+  }
   out->steps_launched = ctx->steps_launched;
   out->graph_replays = ctx->graph_replays;
   out->grid_updates = ctx->grid_updates;
@@ -2712,7 +2867,6 @@ extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
     }
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
-  out->active_jobs = ctx->active_jobs;
-  out->queued_jobs = ctx->queued_jobs;
+
   return RTM_OK;
 }

@@ -1,0 +1,312 @@
+// Host-side tests of the serving engine's job bookkeeping (rtm_sched.h),
+// built with the sanitizers by tests/test_host_logic.py.  A mock clock
+// (advanced by the test) stands in for the host clock and a plain byte
+// budget or the arena allocator (rtm_arena.h) for device memory.
+//
+//   rules       first come, first served; bounded bypass of a blocked head;
+//               out-of-memory at submit for a job larger than the capacity;
+//               a full queue; jobs queued (not failed) under memory pressure;
+//               cancel of queued / admitting / running / unknown jobs; the
+//               stalled head failing; a build error failing only its job;
+//               timestamps ordered on the mock clock
+//   threaded    submitters, a scheduler (arena-backed admission, jobs that
+//               finish after a few mock ticks), pollers and a canceller on
+//               one mutex, the runtime's locking protocol (TSan): every job
+//               ends in one final state, counts add up, the arena ends empty
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <random>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "rtm_arena.h"
+#include "rtm_sched.h"
+
+using namespace rtm;
+
+static void check(bool ok, const char* what, long a = 0, long b = 0) {
+  if (!ok) {
+    std::fprintf(stderr, "FAIL: %s (%ld, %ld)\n", what, a, b);
+    std::exit(1);
+  }
+}
+
+struct MockClock {
+  double t = 0;
+  JobBook::Clock fn() {
+    return [this] { return t += 1.0; };  // strictly increasing: every event gets its own time
+  }
+};
+
+// One admission pass with a byte budget: a candidate fits if its bytes fit
+// what is free.  Returns the admitted tickets in order.
+static std::vector<uint64_t> pass(JobBook& b, size_t& free_bytes, int fail_ticket = -1) {
+  std::vector<uint64_t> admitted;
+  AdmitPass p;
+  while (uint64_t t = b.next_candidate(p)) {
+    const SchedEntry* e = b.find(t);
+    check(e && e->state == kJobAdmitting, "candidate is admitting");
+    int rc;
+    if ((long)t == fail_ticket) rc = kSchedInval;
+    else if (e->bytes <= free_bytes) rc = kSchedOk, free_bytes -= e->bytes;
+    else rc = kSchedNomem;
+    b.admit_result(p, t, rc);
+    if (rc == kSchedOk) admitted.push_back(t);
+  }
+  return admitted;
+}
+
+static void rules() {
+  MockClock clk;
+  // FIFO with room for everything
+  {
+    JobBook b(clk.fn(), 1000);
+    std::vector<uint64_t> t(5);
+    for (int i = 0; i < 5; ++i) check(b.submit(i % 2, 10, &t[i]) == kSchedOk, "submit");
+    size_t free_bytes = 1000;
+    auto a = pass(b, free_bytes);
+    check(a == t, "fifo order");
+    for (int i = 1; i < 5; ++i) check(b.find(t[i - 1])->t_admit < b.find(t[i])->t_admit, "admission times in order");
+    check(b.in_flight(0) == 3 && b.in_flight(1) == 2, "in flight per key");
+    for (auto x : t) b.finish(x, kSchedOk);
+    check(b.idle() && b.done() == 5 && b.in_flight(0) == 0, "all done");
+    for (auto x : t) {
+      const SchedEntry* e = b.find(x);
+      check(e->t_submit < e->t_admit && e->t_admit < e->t_done, "timestamps ordered");
+      check(b.forget(x) == kSchedOk, "forget");
+    }
+    check(b.find(t[0]) == nullptr && b.forget(t[0]) == kSchedNotFound, "forgotten");
+  }
+  // out of memory at submit, full queue
+  {
+    JobBook b(clk.fn(), 100, /*queue_cap=*/3);
+    uint64_t t;
+    check(b.submit(0, 101, &t) == kSchedNomem, "larger than the capacity");
+    check(b.submit(0, 100, &t) == kSchedOk, "exactly the capacity");
+    check(b.submit(0, 1, &t) == kSchedOk && b.submit(0, 1, &t) == kSchedOk, "fill the queue");
+    check(b.submit(0, 1, &t) == kSchedAgain, "queue full");
+    check(b.submitted() == 3, "refused jobs are not counted");
+  }
+  // bounded bypass: a head that does not fit lets younger jobs pass at most
+  // max_bypass times, then blocks the queue until memory frees up
+  {
+    const int max_bypass = 3;
+    JobBook b(clk.fn(), 100, 1 << 16, max_bypass);
+    uint64_t head, small;
+    size_t free_bytes = 50;
+    check(b.submit(0, 80, &head) == kSchedOk, "head");
+    for (int round = 0; round < max_bypass; ++round) {
+      check(b.submit(0, 10, &small) == kSchedOk, "small");
+      auto a = pass(b, free_bytes);
+      check(a.size() == 1 && a[0] == small, "small job passes the blocked head", round, (long)a.size());
+      check(b.find(head)->state == kJobQueued && b.find(head)->bypassed == round + 1, "head waits, bypass counted");
+      b.finish(small, kSchedOk);
+      free_bytes += 10;
+    }
+    check(b.submit(0, 10, &small) == kSchedOk, "one more small job");
+    auto a = pass(b, free_bytes);
+    check(a.empty(), "no bypass beyond the bound");
+    check(b.find(small)->state == kJobQueued && b.find(head)->state == kJobQueued, "both still queued");
+    free_bytes = 100;  // memory frees up: the head goes first, then the small job
+    a = pass(b, free_bytes);
+    check(a.size() == 2 && a[0] == head && a[1] == small, "head first once it fits");
+  }
+  // a pass stops at the second job that does not fit (only one blocked job)
+  {
+    JobBook b(clk.fn(), 100);
+    uint64_t t1, t2, t3;
+    b.submit(0, 60, &t1);
+    b.submit(0, 60, &t2);
+    b.submit(0, 5, &t3);
+    size_t free_bytes = 50;
+    auto a = pass(b, free_bytes);
+    check(a.empty(), "second misfit stops the pass");
+    check(b.find(t3)->state == kJobQueued, "younger job not tried past the second misfit");
+  }
+  // queued, not failed, under pressure; admitted when memory frees up
+  {
+    JobBook b(clk.fn(), 100);
+    std::vector<uint64_t> t(4);
+    for (auto& x : t) b.submit(0, 40, &x);
+    size_t free_bytes = 100;
+    auto a = pass(b, free_bytes);
+    check(a.size() == 2, "two fit");
+    check(b.find(t[2])->state == kJobQueued && b.find(t[3])->state == kJobQueued, "the rest wait");
+    check(b.failed() == 0, "nothing failed under pressure");
+    b.finish(t[0], kSchedOk);
+    free_bytes += 40;
+    a = pass(b, free_bytes);
+    check(a.size() == 1 && a[0] == t[2], "next in line admitted");
+    check(b.find(t[2])->t_admit > b.find(t[0])->t_done, "admitted after the other finished");
+  }
+  // cancel: queued -> cancelled; admitting, running, final -> inval; unknown
+  {
+    JobBook b(clk.fn(), 100);
+    uint64_t q, r, x;
+    b.submit(3, 10, &r);
+    b.submit(3, 10, &q);
+    b.submit(3, 10, &x);
+    AdmitPass p;
+    uint64_t c = b.next_candidate(p);
+    check(c == r, "first candidate");
+    check(b.cancel(r) == kSchedInval, "admitting job cannot be cancelled");
+    check(JobBook::visible_state(*b.find(r)) == kJobQueued, "admitting reads as queued");
+    b.admit_result(p, r, kSchedOk);
+    check(b.cancel(r) == kSchedInval, "running job cannot be cancelled");
+    check(b.cancel(q) == kSchedOk && b.find(q)->state == kJobCancelled, "queued job cancelled");
+    check(b.cancel(q) == kSchedInval, "cancelled twice");
+    check(b.cancel(999) == kSchedNotFound, "unknown ticket");
+    c = b.next_candidate(p);
+    check(c == x, "the cancelled job is skipped");
+    b.admit_result(p, x, kSchedOk);
+    check(b.in_flight(3) == 2 && b.cancelled() == 1, "cancel leaves the count of jobs in flight");
+    check(b.forget(r) == kSchedInval, "running job cannot be forgotten");
+  }
+  // stalled head fails; a build error fails only its job
+  {
+    JobBook b(clk.fn(), 100);
+    uint64_t big, ok, bad;
+    b.submit(0, 90, &big);
+    b.submit(1, 10, &bad);
+    b.submit(1, 10, &ok);
+    size_t free_bytes = 50;
+    auto a = pass(b, free_bytes, (int)bad);
+    check(a.size() == 1 && a[0] == ok, "the job after the failed one still runs");
+    check(b.find(bad)->state == kJobFailed && b.find(bad)->status == kSchedInval, "build error fails its job");
+    b.finish(ok, kSchedOk);
+    check(b.fail_head(kSchedNomem) == big, "stalled head fails");
+    check(b.find(big)->state == kJobFailed && b.find(big)->status == kSchedNomem, "out of memory");
+    check(b.idle() && b.fail_head(kSchedNomem) == 0, "nothing left");
+    check(b.failed() == 2 && b.done() == 1 && b.in_flight(0) == 0 && b.in_flight(1) == 0, "counts");
+  }
+  std::printf("rules: ok\n");
+}
+
+// The runtime's locking protocol with real threads: submitters, one
+// scheduler that builds candidates without the lock, pollers, a canceller.
+static void threaded() {
+  constexpr size_t kArena = 1 << 20;
+  std::vector<char> backing(kArena + 256);
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(backing.data()) + 255) & ~uintptr_t(255));
+  Arena arena;
+  arena.init(base, kArena);
+  std::mutex mu;
+  std::condition_variable cv;
+  double now = 0;  // mock clock, advanced under mu
+  JobBook book([&now] { return now += 1e-3; }, kArena);
+  std::map<uint64_t, std::pair<char*, size_t>> blocks;  // running job -> its memory
+  std::vector<uint64_t> all;
+  bool submitting = true;
+  constexpr int kSubmitters = 4, kPerSubmitter = 400;
+
+  std::vector<std::thread> ts;
+  for (int s = 0; s < kSubmitters; ++s)
+    ts.emplace_back([&, s] {
+      std::mt19937_64 rng(100 + s);
+      for (int i = 0; i < kPerSubmitter; ++i) {
+        uint64_t t = 0;
+        const size_t bytes = 4096 + rng() % (kArena / 3);
+        std::lock_guard<std::mutex> lk(mu);
+        if (book.submit(s, bytes, &t) == kSchedOk) all.push_back(t);
+        cv.notify_all();
+      }
+    });
+  ts.emplace_back([&] {  // canceller
+    std::mt19937_64 rng(7);
+    for (int i = 0; i < 300; ++i) {
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!all.empty()) (void)book.cancel(all[rng() % all.size()]);
+      }
+      std::this_thread::yield();
+    }
+  });
+  for (int k = 0; k < 2; ++k)
+    ts.emplace_back([&] {  // pollers
+      for (int i = 0; i < 3000; ++i) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t j = 0; j < all.size(); j += 97) {
+          const SchedEntry* e = book.find(all[j]);
+          if (e && JobBook::final_state(e->state) && e->state == kJobDone)
+            check(e->t_submit <= e->t_admit && e->t_admit <= e->t_done, "poll: timestamps");
+        }
+      }
+    });
+  std::thread sched([&] {
+    std::mt19937_64 rng(9);
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return !book.idle() || !submitting; });
+        if (book.idle() && !submitting) break;
+      }
+      AdmitPass p;
+      for (;;) {
+        uint64_t t;
+        size_t bytes;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          t = book.next_candidate(p);
+          if (!t) break;
+          bytes = book.find(t)->bytes;
+        }
+        char* blk = static_cast<char*>(arena.alloc(bytes));  // the build, without the lock
+        if (blk) std::memset(blk, 0x5A, align256(bytes));
+        std::lock_guard<std::mutex> lk(mu);
+        book.admit_result(p, t, blk ? kSchedOk : kSchedNomem);
+        if (blk) blocks[t] = {blk, bytes};
+      }
+      // some running jobs finish
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto it = blocks.begin(); it != blocks.end();) {
+        if (rng() % 3 == 0) {
+          arena.release(it->second.first, it->second.second);
+          book.finish(it->first, rng() % 50 ? kSchedOk : kSchedInval);
+          it = blocks.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      if (blocks.empty() && book.queued() > 0 && book.running() == 0) {
+        // nothing runs and the arena is empty: the head fits unless it is
+        // being admitted elsewhere (never here), so a stall cannot happen
+        check(arena.used() == 0, "empty arena when nothing runs");
+      }
+    }
+  });
+  for (auto& t : ts) t.join();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    submitting = false;
+    cv.notify_all();
+  }
+  sched.join();
+  check(arena.used() == 0, "arena empty at the end", (long)arena.used());
+  check(book.idle(), "nothing queued or running");
+  check(book.submitted() == all.size(), "submitted");
+  check(book.done() + book.failed() + book.cancelled() == book.submitted(), "every job ended once",
+        (long)(book.done() + book.failed() + book.cancelled()), (long)book.submitted());
+  for (uint64_t t : all) {
+    const SchedEntry* e = book.find(t);
+    check(e && JobBook::final_state(e->state), "final state");
+    if (e->state == kJobCancelled) check(e->t_admit == 0, "cancelled jobs were never admitted");
+    else check(e->t_submit < e->t_admit && e->t_admit < e->t_done, "timestamps ordered");
+  }
+  for (int s = 0; s < kSubmitters; ++s) check(book.in_flight(s) == 0, "nothing in flight");
+  std::printf("threaded: %zu jobs, %llu done, %llu failed, %llu cancelled, arena peak %zu\n", all.size(),
+              (unsigned long long)book.done(), (unsigned long long)book.failed(),
+              (unsigned long long)book.cancelled(), arena.peak());
+}
+
+int main(int argc, char** argv) {
+  if (argc > 1 && std::string(argv[1]) == "threaded") threaded();
+  else rules();
+  return 0;
+}

@@ -272,3 +272,40 @@ def test_memory_pressure_queues_jobs_and_results_equal_alone(rtm):
         assert np.abs(host(std) - s_ref).max() <= 1e-12 * np.abs(s_ref).max()
         for j, img in zip(jobs, images):
             assert np.array_equal(_alone(rtm, ctx, vels[0], j), img), (j["mode"], j["dtype"])
+
+
+def test_job_log_records_every_job(rtm, tmp_path, monkeypatch):
+    """RTM_LOG names a file that receives one JSON line per job reaching a
+    final state: done jobs with ordered timestamps, their updates, bytes and
+    GPU-time share, and a cancelled job."""
+    import json
+
+    path = tmp_path / "jobs.jsonl"
+    monkeypatch.setenv("RTM_LOG", str(path))
+    rng = np.random.default_rng(31)
+    vels = _small_models(1)
+    jobs = [_small_job(rng, 0, 120, 200), _small_job(rng, 0, 90, 150, "store", "fp16", 3)]
+    with rtm.Context(0, arena_bytes=256 << 20) as ctx:
+        g = rtm.make_grid(SZ, SX, SB, 100, H, H, DT)
+        ctx.model_register(0, dev(vels[0]), g)
+        keep = []
+        tickets = [_submit(rtm, ctx, j, keep) for j in jobs]
+        long_job = _small_job(rng, 0, 200, 3000)
+        t_long = _submit(rtm, ctx, long_job, keep)
+        t_cancel = _submit(rtm, ctx, _small_job(rng, 0, 50, 100), keep)
+        try:
+            ctx.cancel(t_cancel)
+            cancelled = True
+        except rtm.RTMError:
+            cancelled = False
+        ctx.drain()
+        for t in tickets + [t_long, t_cancel]:
+            ctx.poll(t, release=True)
+    recs = {r["ticket"]: r for r in map(json.loads, path.read_text().splitlines())}
+    for t, j in zip(tickets + [t_long], jobs + [long_job]):
+        r = recs[t]
+        assert r["state"] == "done" and r["status"] == 0 and r["width"] == j["w"] and r["nt"] == j["nt"]
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+        assert r["grid_updates"] > 0 and r["alg_bytes"] > 0 and r["gpu_ms"] > 0
+        assert abs(r["latency_ms"] - r["queue_ms"] - r["run_ms"]) < 1e-6 * max(1.0, r["latency_ms"]) + 1e-3
+    assert recs[t_cancel]["state"] == ("cancelled" if cancelled else "done")
