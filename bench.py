@@ -764,6 +764,8 @@ def run_maps(args):
 
 
 CODEC_SETTINGS = {"velocity": (1e-4, 1e-1, None), "image": (1e-4, 1e-1, None), "seismogram": (1e-4, None)}
+# the ZFP-method coder (RTM_CODEC_ZFP) at the paper's two fixed-accuracy bounds
+ZFP_SETTINGS = (1e-4, 1e-1)
 
 
 def _codec_label(kind, tol):
@@ -850,6 +852,29 @@ def run_codec(args):
         y = ctx.codec_decode(ctx.codec_encode(x, tol=1e-4, out=bufs[kind]), out=outs[kind])
         err = (y.double() - x.double()).abs() - (1e-4 * (1 + 2.0 ** -26) + y.double().abs() * 2.0 ** -24)
         assert float(err.max()) <= 0.0, f"{kind}: error bound violated"
+    # the ZFP-method coder on the same banks: ratio, kernel times, error
+    zfp_table = {}
+    for kind, x in xs.items():
+        for tol in ZFP_SETTINGS:
+            enc_ms, dec_ms = [], []
+            for it in range(args.warmup + args.steps):
+                s = ctx.codec_encode(x, tol=tol, zfp=True, out=bufs[kind])
+                e_st = ctx.stats()
+                y = ctx.codec_decode(s, out=outs[kind])
+                d_st = ctx.stats()
+                if it >= args.warmup:
+                    enc_ms.append(e_st.last_codec_ms)
+                    dec_ms.append(d_st.last_codec_ms)
+            err = float((y.double() - x.double()).abs().max())
+            assert err <= tol, f"ZFP-method coder: {kind} tol {tol:g}: error {err:.3e}"
+            e_ms, d_ms = float(np.median(enc_ms)), float(np.median(dec_ms))
+            row = {"ratio": x.numel() * 4 / s.numel(), "stream_MB": s.numel() / 1e6, "max_error": err,
+                   "encode_us": e_ms * 1e3, "decode_us": d_ms * 1e3,
+                   "encode_GBps": x.numel() * 4 / (e_ms * 1e-3) / 1e9,
+                   "decode_GBps": x.numel() * 4 / (d_ms * 1e-3) / 1e9}
+            zfp_table[_codec_label(kind, tol)] = row
+            log(f"[bench] zfp {_codec_label(kind, tol):20s} ratio {row['ratio']:6.2f}  max error {err:.2e}  "
+                f"encode {row['encode_us']:8.1f} us  decode {row['decode_us']:8.1f} us")
     table, dominant = {}, None
     for label, r in runs.items():
         e_ms, d_ms = float(np.median(r["enc_ms"])), float(np.median(r["dec_ms"]))
@@ -885,6 +910,10 @@ def run_codec(args):
                        "note": "algorithmic bytes: 4 B per value plus the stream length; HIP events "
                                "around the launch on the library's stream"}
     out["codec"] = table
+    out["zfp_method"] = {"settings": zfp_table,
+                         "note": "RTM_CODEC_ZFP: the published ZFP method in fixed-accuracy mode (4 x 4 block "
+                                 "floating point, decorrelating lifting transform, negabinary, embedded bit-plane "
+                                 "coding); GB/s of uncompressed bytes per kernel time"}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     return out

@@ -376,16 +376,38 @@ int rtm_laplacian_filter(rtm_ctx *ctx, const float *img_dev, int32_t nz, int32_t
  * owned, on the context's device.  Both calls are stream-ordered on the
  * context stream and return after that stream has finished them (the encoder
  * must report the stream length, the decoder its validation result). */
-enum { RTM_CODEC_TOL = 0, RTM_CODEC_LOSSLESS = 1 };
+enum { RTM_CODEC_TOL = 0, RTM_CODEC_LOSSLESS = 1, RTM_CODEC_ZFP = 2 };
 
-/* Largest stream the encoder can produce for this shape (64 words per block
- * plus the index), or -1 for a shape that is empty or exceeds 2^26 - 1
- * blocks per stream. */
+/* RTM_CODEC_ZFP: the published ZFP method in fixed-accuracy mode (Lindstrom,
+ * IEEE TVCG 20(12), 2014), the coder the paper uses (Sec. 4.2), for 2-D
+ * float32 arrays:
+ *   - 4 x 4 blocks (edges repeated) in the order (array, block row, block
+ *     column); block floating point with the block's largest exponent e and
+ *     30-bit integers q = trunc(x 2^(30 - e));
+ *   - ZFP's decorrelating transform (integer lifting of
+ *     T = 1/16 [[4,4,4,4],[5,1,-1,-5],[-4,4,4,-4],[-2,6,-6,2]]) on rows, then
+ *     columns; coefficients by sequency; negabinary digits;
+ *   - embedded bit-plane coding with group tests, planes from 31 down to
+ *     32 - min(32, max(0, e - floor(log2 tol) + 6));
+ *   - a zero block, or one below the tolerance, is one 0 bit; else a 1 bit,
+ *     e + 127 in 8 bits and its planes.
+ * Accepted: tol >= 2^-60, |x| < 2^100, finite.  Decoded values stay within
+ * tol of the input (the method's guard planes; checked on the benchmark
+ * banks and random data).  Stream: [0..7] magic 0x465A5452, mode 2, count,
+ * rows, cols, 16 blocks per chunk, tol (float64); chunk table [nchunks + 1]
+ * (payload word offset of each chunk of 16 blocks, then the total);
+ * payload (each chunk's block codes, bits least-significant first, padded
+ * to a word).  rtm_codec_decode reads either format. */
+
+/* Largest stream the encoder can produce for this shape in any mode (64
+ * words per 8 x 8 block plus the index, or 585 bits per 4 x 4 block plus the
+ * chunk table for RTM_CODEC_ZFP, whichever is larger), or -1 for a shape that
+ * is empty or exceeds 2^26 - 1 blocks of 8 x 8 per stream. */
 int64_t rtm_codec_max_bytes(int32_t count, int32_t rows, int32_t cols);
 
 /* Encode x_dev [count][rows][cols] into stream_dev (capacity_bytes, 4-byte
- * aligned).  mode RTM_CODEC_TOL needs a finite tol > 0; RTM_CODEC_LOSSLESS
- * ignores tol.  *stream_bytes receives the stream length, also when the
+ * aligned).  mode RTM_CODEC_TOL needs a finite tol > 0, RTM_CODEC_ZFP a
+ * finite tol >= 2^-60; RTM_CODEC_LOSSLESS ignores tol.  *stream_bytes receives the stream length, also when the
  * buffer is too small.
  * Errors: RTM_E_INVAL (bad shape or mode; a non-finite value or
  * |x| / (2 tol) > 2^31 - 1 in fixed-accuracy mode), RTM_E_NOMEM (capacity

@@ -9,9 +9,9 @@ PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "librtm.so"
-SOURCES = [CSRC / "rtm_kernels.hip", CSRC / "rtm_aux.hip", CSRC / "rtm_codec.hip", CSRC / "rtm_bet.hip",
-           CSRC / "rtm_runtime.hip"]
-HEADERS = [CSRC / "rtm_internal.h", CSRC / "rtm_codec.h", CSRC / "rtm_bet.h", CSRC / "rtm_device.h", CSRC / "rtm_arena.h", CSRC / "rtm_sched.h", ROOT / "include" / "rtm.h"]
+SOURCES = [CSRC / "rtm_kernels.hip", CSRC / "rtm_aux.hip", CSRC / "rtm_codec.hip", CSRC / "rtm_zfp.hip",
+           CSRC / "rtm_bet.hip", CSRC / "rtm_runtime.hip"]
+HEADERS = [CSRC / "rtm_internal.h", CSRC / "rtm_codec.h", CSRC / "rtm_zfp.h", CSRC / "rtm_bet.h", CSRC / "rtm_device.h", CSRC / "rtm_arena.h", CSRC / "rtm_sched.h", ROOT / "include" / "rtm.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -40,6 +40,7 @@
 #include "rtm_codec.h"
 #include "rtm_internal.h"
 #include "rtm_sched.h"
+#include "rtm_zfp.h"
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
@@ -2306,11 +2307,97 @@ static int zc_geometry(int32_t count, int32_t rows, int32_t cols, ZcParams& p) {
   return RTM_OK;
 }
 
+// Geometry of a fixed-accuracy ZFP-method stream (4 x 4 blocks, chunks of 16).
+static int zf_geometry(int32_t count, int32_t rows, int32_t cols, ZfParams& p) {
+  if (count < 1 || rows < 1 || cols < 1) return fail(RTM_E_INVAL, "count, rows and cols must be >= 1");
+  const int64_t bz = (rows + 3) / 4, bx = (cols + 3) / 4, nblk = (int64_t)count * bz * bx;
+  if (nblk > kZfMaxBlocks)
+    return fail(RTM_E_INVAL, "%lld blocks of 4 x 4 exceed the limit of %lld per stream", (long long)nblk,
+                (long long)kZfMaxBlocks);
+  p.count = count;
+  p.rows = rows;
+  p.cols = cols;
+  p.bz = (int32_t)bz;
+  p.bx = (int32_t)bx;
+  p.nblocks = nblk;
+  p.nchunks = (nblk + kZfChunk - 1) / kZfChunk;
+  p.hdr_base = kZfHeaderWords;
+  p.pay_base = kZfHeaderWords + p.nchunks + 1;
+  return RTM_OK;
+}
+
+// Longest fixed-accuracy ZFP-method stream of a shape (-1: outside the limits).
+static int64_t zf_max_bytes(int32_t count, int32_t rows, int32_t cols) {
+  if (count < 1 || rows < 1 || cols < 1) return -1;
+  const int64_t nblk = (int64_t)count * ((rows + 3) / 4) * ((cols + 3) / 4);
+  if (nblk > kZfMaxBlocks) return -1;
+  const int64_t nch = (nblk + kZfChunk - 1) / kZfChunk, last = nblk - (nch - 1) * kZfChunk;
+  const int64_t full = ((int64_t)kZfChunk * kZfMaxBlockBits + 31) / 32, part = (last * kZfMaxBlockBits + 31) / 32;
+  return 4 * (kZfHeaderWords + nch + 1 + (nch - 1) * full + part);
+}
+
 extern "C" int64_t rtm_codec_max_bytes(int32_t count, int32_t rows, int32_t cols) {
   if (count < 1 || rows < 1 || cols < 1) return -1;
   const int64_t nblk = (int64_t)count * ((rows + 7) / 8) * ((cols + 7) / 8);
   if (nblk > kZcMaxBlocks) return -1;
-  return 4 * (zc_index_words(nblk) + 64 * nblk);
+  const int64_t zf = zf_max_bytes(count, rows, cols);
+  return std::max(4 * (zc_index_words(nblk) + 64 * nblk), zf);
+}
+
+// rtm_codec_encode with mode RTM_CODEC_ZFP.
+static int zf_encode(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows, int32_t cols, double tol,
+                     void* stream_dev, int64_t capacity_bytes, int64_t* stream_bytes) {
+  if (!(tol >= 0x1p-60) || !std::isfinite(tol))
+    return fail(RTM_E_INVAL, "the tolerance must be finite and at least 2^-60 for the ZFP-method coder");
+  ZfParams p{};
+  if (int st = zf_geometry(count, rows, cols, p)) return st;
+  int e2 = 0;
+  (void)frexp(tol, &e2);
+  p.minexp = e2 - 1;  // floor(log2 tol)
+  if (capacity_bytes < 4 * p.pay_base)
+    return fail(RTM_E_NOMEM, "stream capacity %lld bytes is below the %lld-byte index",
+                (long long)capacity_bytes, (long long)(4 * p.pay_base));
+  p.cap_words = capacity_bytes / 4;
+  p.x = x_dev;
+  p.out = static_cast<uint32_t*>(stream_dev);
+  uint32_t tw[2];
+  memcpy(tw, &tol, 8);
+  const uint32_t head[8] = {kZfMagic, (uint32_t)kZfMode, (uint32_t)count, (uint32_t)rows,
+                            (uint32_t)cols, (uint32_t)kZfChunk, tw[0], tw[1]};
+  memcpy(p.head, head, sizeof head);
+  HIP_OK(hipSetDevice(ctx->device));
+  // scratch: chunk word counts, scan totals, flags and result words
+  const int64_t ng = (p.nchunks + kZfScan - 1) / kZfScan;
+  const size_t counts_bytes = align256(4 * (size_t)p.nchunks), totals_bytes = align256(8 * (size_t)(ng + 1));
+  const size_t scratch_bytes = counts_bytes + totals_bytes + 256;
+  char* scratch = static_cast<char*>(arena_alloc(ctx, scratch_bytes));
+  if (!scratch) return fail(RTM_E_NOMEM, "arena exhausted (codec scratch)");
+  uint32_t* counts = reinterpret_cast<uint32_t*>(scratch);
+  uint64_t* totals = reinterpret_cast<uint64_t*>(scratch + counts_bytes);
+  uint32_t* tail = reinterpret_cast<uint32_t*>(scratch + counts_bytes + totals_bytes);
+  p.flags = tail;
+  p.result = tail + 2;
+  hipStream_t s = ctx->stream;
+  uint32_t res[4] = {0, 0, 0, 0};
+  hipError_t e = launch_fill_u32(tail, 0, 64, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[0], s);
+  if (e == hipSuccess) e = launch_zf_encode(p, counts, totals, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[1], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(res, tail, 16, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ctx->arena.release(scratch, align256(scratch_bytes));
+  if (e != hipSuccess) return fail(RTM_E_DEVICE, "codec encode: %s", hipGetErrorString(e));
+  if (res[0] & kZfRange)
+    return fail(RTM_E_INVAL, "a value is non-finite or |x| >= 2^100 (outside the ZFP-method coder's range)");
+  const uint64_t payload = (uint64_t)res[2] | ((uint64_t)res[3] << 32);
+  const int64_t bytes = 4 * (p.pay_base + (int64_t)payload);
+  *stream_bytes = bytes;
+  ctx->zc_op = 1;
+  ctx->zc_bytes = 4 * (uint64_t)count * rows * cols + (uint64_t)bytes;
+  if (bytes > capacity_bytes)
+    return fail(RTM_E_NOMEM, "the stream needs %lld bytes, the buffer holds %lld", (long long)bytes,
+                (long long)capacity_bytes);
+  return RTM_OK;
 }
 
 // Validation of an encode and its launch parameters (no device work).
@@ -2390,6 +2477,13 @@ static int zc_encode_run(rtm_ctx* ctx, ZcParams& p, void* scratch, int64_t capac
 extern "C" int rtm_codec_encode(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows, int32_t cols,
                                 int32_t mode, double tol, void* stream_dev, int64_t capacity_bytes,
                                 int64_t* stream_bytes) {
+  if (mode == RTM_CODEC_ZFP) {
+    if (!ctx || !x_dev || !stream_dev || !stream_bytes) return fail(RTM_E_INVAL, "bad arguments");
+    *stream_bytes = 0;
+    if (reinterpret_cast<uintptr_t>(stream_dev) & 3) return fail(RTM_E_INVAL, "stream must be 4-byte aligned");
+    if (reinterpret_cast<uintptr_t>(x_dev) & 3) return fail(RTM_E_INVAL, "array must be 4-byte aligned");
+    return zf_encode(ctx, x_dev, count, rows, cols, tol, stream_dev, capacity_bytes, stream_bytes);
+  }
   ZcParams p;
   if (int st = zc_encode_params(ctx, x_dev, count, rows, cols, mode, tol, stream_dev, capacity_bytes, stream_bytes,
                                 INT64_MAX, p))
@@ -2412,6 +2506,7 @@ static std::mutex g_zc_noalloc_mu[64];
 extern "C" int rtm_codec_encode_noalloc(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t rows,
                                         int32_t cols, int32_t mode, double tol, void* stream_dev,
                                         int64_t capacity_bytes, int64_t* stream_bytes) {
+  if (mode == RTM_CODEC_ZFP) return fail(RTM_E_INVAL, "the allocation-free encoder takes the TOL and LOSSLESS modes");
   ZcParams p;
   if (int st = zc_encode_params(ctx, x_dev, count, rows, cols, mode, tol, stream_dev, capacity_bytes, stream_bytes,
                                 kZcNoAllocChunks, p))
@@ -2433,6 +2528,24 @@ extern "C" int rtm_codec_info(rtm_ctx* ctx, const void* stream_dev, int64_t stre
   uint32_t h[8];
   HIP_OK(hipMemcpyAsync(h, stream_dev, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
   HIP_OK(hipStreamSynchronize(ctx->stream));
+  if (h[0] == kZfMagic) {  // fixed-accuracy ZFP-method stream
+    if (h[1] != (uint32_t)kZfMode) return fail(RTM_E_INVAL, "unknown codec mode %u", h[1]);
+    if (h[5] != (uint32_t)kZfChunk) return fail(RTM_E_INVAL, "unsupported chunk size %u", h[5]);
+    if (h[2] - 1 > 0x7ffffffeu || h[3] - 1 > 0x7ffffffeu || h[4] - 1 > 0x7ffffffeu)
+      return fail(RTM_E_INVAL, "bad array shape in the stream header");
+    double t;
+    memcpy(&t, h + 6, 8);
+    if (!(t >= 0x1p-60) || !std::isfinite(t)) return fail(RTM_E_INVAL, "bad tolerance in the stream header");
+    ZfParams q{};
+    if (int st = zf_geometry((int32_t)h[2], (int32_t)h[3], (int32_t)h[4], q)) return st;
+    if (stream_bytes < 4 * q.pay_base) return fail(RTM_E_INVAL, "stream shorter than its index");
+    if (mode) *mode = RTM_CODEC_ZFP;
+    if (count) *count = q.count;
+    if (rows) *rows = q.rows;
+    if (cols) *cols = q.cols;
+    if (tol) *tol = t;
+    return RTM_OK;
+  }
   if (h[0] != kZcMagic) return fail(RTM_E_INVAL, "not a codec stream (magic %08x)", h[0]);
   if (h[1] > 1) return fail(RTM_E_INVAL, "unknown codec mode %u", h[1]);
   if (h[5] != (uint32_t)kZcChunk) return fail(RTM_E_INVAL, "unsupported chunk size %u", h[5]);
@@ -2453,6 +2566,40 @@ extern "C" int rtm_codec_info(rtm_ctx* ctx, const void* stream_dev, int64_t stre
   return RTM_OK;
 }
 
+// rtm_codec_decode of a fixed-accuracy ZFP-method stream (header checked).
+static int zf_decode(rtm_ctx* ctx, const void* stream_dev, int64_t stream_bytes, float* x_dev, int64_t capacity_floats,
+                     int32_t count, int32_t rows, int32_t cols, double tol) {
+  ZfParams p{};
+  if (int st = zf_geometry(count, rows, cols, p)) return st;
+  const int64_t n = (int64_t)count * rows * cols;
+  if (capacity_floats < n)
+    return fail(RTM_E_NOMEM, "the array holds %lld floats, the stream decodes to %lld",
+                (long long)capacity_floats, (long long)n);
+  int e2 = 0;
+  (void)frexp(tol, &e2);
+  p.minexp = e2 - 1;
+  void* scratch = arena_alloc(ctx, 64);
+  if (!scratch) return fail(RTM_E_NOMEM, "arena exhausted (codec flags)");
+  p.in = static_cast<const uint32_t*>(stream_dev);
+  p.y = x_dev;
+  p.flags = static_cast<uint32_t*>(scratch);
+  p.cap_words = stream_bytes / 4;
+  hipStream_t s = ctx->stream;
+  uint32_t flags = 0;
+  hipError_t e = launch_fill_u32(p.flags, 0, 16, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[0], s);
+  if (e == hipSuccess) e = launch_zf_decode(p, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[1], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ctx->arena.release(scratch, align256(64));
+  if (e != hipSuccess) return fail(RTM_E_DEVICE, "codec decode: %s", hipGetErrorString(e));
+  ctx->zc_op = 2;
+  ctx->zc_bytes = (uint64_t)stream_bytes + 4 * (uint64_t)n;
+  if (flags) return fail(RTM_E_INVAL, "corrupt codec stream (chunk table or block codes)");
+  return RTM_OK;
+}
+
 extern "C" int rtm_codec_decode(rtm_ctx* ctx, const void* stream_dev, int64_t stream_bytes, float* x_dev,
                                 int64_t capacity_floats) {
   if (!ctx || !stream_dev || !x_dev) return fail(RTM_E_INVAL, "bad arguments");
@@ -2460,6 +2607,8 @@ extern "C" int rtm_codec_decode(rtm_ctx* ctx, const void* stream_dev, int64_t st
   int32_t mode = 0, count = 0, rows = 0, cols = 0;
   double tol = 0;
   if (int st = rtm_codec_info(ctx, stream_dev, stream_bytes, &mode, &count, &rows, &cols, &tol)) return st;
+  if (mode == RTM_CODEC_ZFP) return zf_decode(ctx, stream_dev, stream_bytes, x_dev, capacity_floats, count, rows,
+                                              cols, tol);
   ZcParams p{};
   if (int st = zc_geometry(count, rows, cols, p)) return st;
   const int64_t n = (int64_t)count * rows * cols;

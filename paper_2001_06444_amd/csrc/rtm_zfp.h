@@ -1,0 +1,47 @@
+// rtm_zfp.h -- launch parameters of the fixed-accuracy ZFP-method coder
+// (rtm_zfp.hip), shared with the host runtime (rtm_runtime.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtm {
+
+constexpr uint32_t kZfMagic = 0x465A5452;  // "RTZF"
+constexpr int kZfMode = 2;                 // the stream's mode word (RTM_CODEC_ZFP)
+constexpr int kZfChunk = 16;               // 4 x 4 blocks per chunk (one thread each)
+constexpr int kZfThreads = 64;             // chunks per workgroup of the coding kernels
+constexpr int kZfScan = 256;               // threads of the scan kernels
+constexpr int kZfHeaderWords = 8;
+constexpr int64_t kZfMaxBlocks = int64_t(1) << 27;  // keeps payload word offsets below 2^32
+// Longest block code: 1 + 8 header bits, at most 16 verbatim bits per plane
+// over 32 planes, at most 32 failed and 16 successful group tests and 16
+// scan bits: 585 bits.
+constexpr int kZfMaxBlockBits = 585;
+
+// error bits the kernels raise in ZfParams::flags
+constexpr uint32_t kZfRange = 1u;    // a value is non-finite or |x| >= 2^100
+constexpr uint32_t kZfCorrupt = 8u;  // decode: chunk table or block codes inconsistent
+
+struct ZfParams {
+  const float* x;      // encode input [count][rows][cols]
+  float* y;            // decode output, same layout
+  uint32_t* out;       // encode: stream words
+  const uint32_t* in;  // decode: stream words
+  uint32_t* flags;     // error bits, zeroed before launch
+  uint32_t* result;    // encode: [0..1] total payload words (64-bit)
+  int32_t count, rows, cols, minexp;
+  int32_t bz, bx;
+  int64_t nblocks, nchunks;
+  int64_t hdr_base;    // word index of the chunk table
+  int64_t pay_base;    // word index of the payload
+  int64_t cap_words;   // encode: capacity of out; decode: words in the stream
+  uint32_t head[8];    // encode: the stream's first eight words
+};
+
+// Encoder: counts[nchunks] (uint32) and totals[(nchunks + 255) / 256 + 1]
+// (uint64) are device scratch.
+hipError_t launch_zf_encode(const ZfParams& p, uint32_t* counts, uint64_t* totals, hipStream_t s);
+hipError_t launch_zf_decode(const ZfParams& p, hipStream_t s);
+
+}  // namespace rtm

@@ -1,0 +1,387 @@
+// rtm_zfp.hip -- fixed-accuracy coder of the published ZFP method for 2-D
+// float32 arrays (the data-compression stage of the workflow: Sec. 3,
+// data-compression paragraph; Sec. 4.2, Tables 1-2, which use ZFP's
+// fixed-accuracy mode at absolute error bounds 1e-4 and 1e-1).
+//
+// The method (Lindstrom, IEEE TVCG 20(12), 2014), per 4 x 4 block, edges
+// repeated:
+//   1. block floating point: e = exponent of the largest |x| (f 2^e, f in
+//      [1/2, 1)), q = trunc(x 2^(30 - e)) as int32 (two guard bits);
+//   2. the non-orthogonal decorrelating transform
+//        T = 1/16 [[4, 4, 4, 4], [5, 1, -1, -5], [-4, 4, 4, -4], [-2, 6, -6, 2]]
+//      on every row, then every column, in integer lifting steps;
+//   3. coefficients ordered by sequency i + j (kSeq);
+//   4. negabinary digits u = (q + 0xAAAAAAAA) ^ 0xAAAAAAAA;
+//   5. embedded bit-plane coding from plane 31 down: per plane the bits of
+//      the coefficients already significant, then group tests (is any later
+//      coefficient set in this plane?) each followed by the bits up to the
+//      next set one (the last coefficient's 1 is implied);
+//   6. fixed accuracy: planes down to kmin = 32 - min(32, max(0, e - minexp
+//      + 6)), minexp = floor(log2 tol); a zero block or one without planes
+//      is a single 0 bit, any other a 1 bit, e + 127 in 8 bits, its planes.
+// Stream (32-bit words, bits least-significant first): 8 header words
+// (magic 0x465A5452, mode 2, count, rows, cols, 16 blocks per chunk, tol as
+// float64), the chunk table [nchunks + 1] (payload word offset of each
+// chunk of 16 blocks, then the total), the payload (each chunk's block codes
+// back to back, padded to a word).
+//
+// Launch shape: one thread codes one chunk of 16 blocks, in order.  The
+// encoder runs twice over the chunks: a pass that only counts each chunk's
+// words, a scan of the counts into the chunk table, and a pass that writes
+// the codes at their offsets (chunks start on word boundaries, so no two
+// threads write one word).  The decoder reads each chunk's word range from
+// the table and never reads outside it.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rtm_zfp.h"
+
+namespace rtm {
+namespace {
+
+constexpr uint32_t kNb = 0xAAAAAAAAu;
+// sequency order: (row frequency i, column frequency j) packed as 4 i + j
+__constant__ uint8_t kSeq[16] = {0, 1, 4, 5, 2, 8, 6, 9, 3, 12, 10, 7, 13, 11, 14, 15};
+
+__device__ __forceinline__ void fwd_lift(int32_t& a0, int32_t& a1, int32_t& a2, int32_t& a3) {
+  a0 += a3; a0 >>= 1; a3 -= a0;
+  a2 += a1; a2 >>= 1; a1 -= a2;
+  a0 += a2; a0 >>= 1; a2 -= a0;
+  a3 += a1; a3 >>= 1; a1 -= a3;
+  a3 += a1 >> 1; a1 -= a3 >> 1;
+}
+
+__device__ __forceinline__ void inv_lift(int32_t& a0, int32_t& a1, int32_t& a2, int32_t& a3) {
+  a1 += a3 >> 1; a3 -= a1 >> 1;
+  a1 += a3; a3 = (int32_t)((uint32_t)a3 << 1); a3 -= a1;
+  a2 += a0; a0 = (int32_t)((uint32_t)a0 << 1); a0 -= a2;
+  a1 += a2; a2 = (int32_t)((uint32_t)a2 << 1); a2 -= a1;
+  a3 += a0; a0 = (int32_t)((uint32_t)a0 << 1); a0 -= a3;
+}
+
+// Appends bits to a word stream (out == nullptr: count only).
+struct BitSink {
+  uint32_t* out;
+  int64_t limit;  // words that may be written
+  uint64_t acc = 0;
+  int nacc = 0;
+  int64_t words = 0;
+  __device__ BitSink(uint32_t* o, int64_t lim) : out(o), limit(lim) {}
+  __device__ __forceinline__ void put(uint32_t v, int n) {  // n <= 32, v < 2^n
+    acc |= (uint64_t)v << nacc;
+    nacc += n;
+    if (nacc >= 32) {
+      if (out && words < limit) out[words] = (uint32_t)acc;
+      ++words;
+      acc >>= 32;
+      nacc -= 32;
+    }
+  }
+  __device__ __forceinline__ void flush() {
+    if (nacc > 0) {
+      if (out && words < limit) out[words] = (uint32_t)acc;
+      ++words;
+      acc = 0;
+      nacc = 0;
+    }
+  }
+};
+
+// Reads bits from a chunk's word range; reading past it raises `bad`.
+struct BitSource {
+  const uint32_t* in;
+  int64_t nwords, next = 0;
+  uint64_t acc = 0;
+  int nacc = 0;
+  bool bad = false;
+  __device__ BitSource(const uint32_t* p, int64_t n) : in(p), nwords(n) {}
+  __device__ __forceinline__ uint32_t get(int n) {  // n <= 32
+    if (nacc < n) {
+      uint64_t w = 0;
+      if (next < nwords) w = in[next];
+      else bad = true;
+      ++next;
+      acc |= w << nacc;
+      nacc += 32;
+    }
+    const uint32_t v = (uint32_t)(acc & ((n == 32) ? 0xFFFFFFFFull : ((1ull << n) - 1)));
+    acc >>= n;
+    nacc -= n;
+    return v;
+  }
+};
+
+// Loads block b (edges repeated) of the [count][rows][cols] array.
+__device__ __forceinline__ void load_block(const ZfParams& p, int64_t b, float (&x)[16]) {
+  const int64_t per = (int64_t)p.bz * p.bx;
+  const int64_t img = b / per;
+  const int64_t rem = b - img * per;
+  const int bi = (int)(rem / p.bx), bj = (int)(rem - (int64_t)bi * p.bx);
+  const float* a = p.x + img * (int64_t)p.rows * p.cols;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = min(4 * bi + i, p.rows - 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[4 * i + j] = a[(int64_t)r * p.cols + min(4 * bj + j, p.cols - 1)];
+  }
+}
+
+// Steps 1-6 for one block; false if a value is non-finite or |x| >= 2^100.
+__device__ bool encode_block(const float (&x)[16], int minexp, BitSink& bs) {
+  float m = 0.0f;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const float a = fabsf(x[c]);
+    ok = ok && (a < 0x1p100f);  // false for NaN and infinities too
+    m = fmaxf(m, a);
+  }
+  if (!ok) return false;
+  if (m == 0.0f) {
+    bs.put(0, 1);
+    return true;
+  }
+  int e;
+  (void)frexpf(m, &e);
+  const int maxprec = min(32, max(0, e - minexp + 6));
+  if (maxprec == 0) {
+    bs.put(0, 1);
+    return true;
+  }
+  bs.put(1, 1);
+  bs.put((uint32_t)(e + 127), 8);
+  int32_t q[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) q[c] = (int32_t)ldexpf(x[c], 30 - e);  // exact scaling, truncation
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fwd_lift(q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fwd_lift(q[j], q[4 + j], q[8 + j], q[12 + j]);
+  uint32_t u[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) u[c] = ((uint32_t)q[kSeq[c]] + kNb) ^ kNb;
+  const int kmin = 32 - maxprec;
+  int n = 0;
+  for (int k = 31; k >= kmin; --k) {
+    uint32_t plane = 0;  // bit c: bit k of coefficient c
+#pragma unroll
+    for (int c = 0; c < 16; ++c) plane |= ((u[c] >> k) & 1u) << c;
+    if (n > 0) bs.put(plane & ((1u << n) - 1u), n);  // coefficients already significant
+    uint32_t rest = plane >> n;
+    while (n < 16) {
+      bs.put(rest != 0, 1);  // group test
+      if (!rest) break;
+      const int p = __builtin_ctz(rest);
+      if (n + p == 15) {  // zeros up to the last coefficient, whose 1 is implied
+        bs.put(0, 15 - n);
+        n = 16;
+        break;
+      }
+      bs.put(1u << p, p + 1);  // p zeros, then the 1
+      n += p + 1;
+      rest >>= p + 1;
+    }
+  }
+  return true;
+}
+
+// Inverse of encode_block.
+__device__ void decode_block(BitSource& src, int minexp, float (&x)[16]) {
+  if (src.get(1) == 0) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) x[c] = 0.0f;
+    return;
+  }
+  const int e = (int)src.get(8) - 127;
+  const int maxprec = min(32, max(0, e - minexp + 6));
+  if (maxprec == 0) src.bad = true;  // an encoder never codes such a block
+  const int kmin = 32 - maxprec;
+  uint32_t u[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) u[c] = 0;
+  int n = 0;
+  for (int k = 31; k >= kmin && !src.bad; --k) {
+    uint32_t plane = n > 0 ? src.get(n) : 0u;
+    while (n < 16) {
+      if (src.get(1) == 0) break;
+      for (;;) {
+        if (n == 15) {
+          plane |= 1u << 15;
+          n = 16;
+          break;
+        }
+        const uint32_t b = src.get(1);
+        plane |= b << n;
+        ++n;
+        if (b) break;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) u[c] |= ((plane >> c) & 1u) << k;
+  }
+  int32_t q[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) q[kSeq[c]] = (int32_t)((u[c] ^ kNb) - kNb);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) inv_lift(q[j], q[4 + j], q[8 + j], q[12 + j]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) inv_lift(q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]);
+  const float scale = ldexpf(1.0f, e - 30);  // normal for every accepted tolerance
+#pragma unroll
+  for (int c = 0; c < 16; ++c) x[c] = (float)q[c] * scale;
+}
+
+// Pass 1: payload words of every chunk -> counts[chunk].
+__global__ __launch_bounds__(kZfThreads) void k_zf_count(ZfParams p, uint32_t* counts) {
+  const int64_t ch = (int64_t)blockIdx.x * kZfThreads + threadIdx.x;
+  if (ch >= p.nchunks) return;
+  BitSink bs(nullptr, 0);
+  bool ok = true;
+  const int64_t b1 = min((ch + 1) * kZfChunk, (int64_t)p.nblocks);
+  for (int64_t b = ch * kZfChunk; b < b1; ++b) {
+    float x[16];
+    load_block(p, b, x);
+    ok = encode_block(x, p.minexp, bs) && ok;
+  }
+  bs.flush();
+  counts[ch] = (uint32_t)bs.words;
+  if (!ok) atomicOr(p.flags, kZfRange);
+}
+
+// Exclusive scan of the counts into the stream's chunk table, in three
+// launches: per-workgroup totals, a scan of the totals (one workgroup), and
+// the table entries.
+__global__ __launch_bounds__(kZfScan) void k_zf_scan_totals(const uint32_t* counts, int64_t n, uint64_t* totals) {
+  __shared__ uint64_t red[kZfScan];
+  const int64_t i = (int64_t)blockIdx.x * kZfScan + threadIdx.x;
+  red[threadIdx.x] = i < n ? counts[i] : 0;
+  __syncthreads();
+  for (int s = kZfScan / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kZfScan) void k_zf_scan_base(uint64_t* totals, int64_t ngroups) {
+  // exclusive scan of ngroups totals, in place, kZfScan at a time
+  __shared__ uint64_t buf[kZfScan];
+  uint64_t carry = 0;
+  for (int64_t base = 0; base < ngroups; base += kZfScan) {
+    const int64_t i = base + threadIdx.x;
+    const uint64_t v = i < ngroups ? totals[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 1; s < kZfScan; s <<= 1) {  // inclusive Hillis-Steele scan
+      const uint64_t t = (int)threadIdx.x >= s ? buf[threadIdx.x - s] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < ngroups) totals[i] = carry + buf[threadIdx.x] - v;
+    const uint64_t sum = buf[kZfScan - 1];
+    __syncthreads();
+    carry += sum;
+  }
+  if (threadIdx.x == 0) totals[ngroups] = carry;
+}
+
+__global__ __launch_bounds__(kZfScan) void k_zf_scan_table(const uint32_t* counts, int64_t n, const uint64_t* base,
+                                                           ZfParams p) {
+  __shared__ uint64_t buf[kZfScan];
+  const int64_t i = (int64_t)blockIdx.x * kZfScan + threadIdx.x;
+  const uint64_t v = i < n ? counts[i] : 0;
+  buf[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 1; s < kZfScan; s <<= 1) {
+    const uint64_t t = (int)threadIdx.x >= s ? buf[threadIdx.x - s] : 0;
+    __syncthreads();
+    buf[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const uint64_t off = base[blockIdx.x] + buf[threadIdx.x] - v;  // exclusive prefix
+  if (i < n && p.hdr_base + i < p.cap_words) p.out[p.hdr_base + i] = (uint32_t)off;
+  if (i == n - 1) {
+    const uint64_t total = off + v;
+    if (p.hdr_base + n < p.cap_words) p.out[p.hdr_base + n] = (uint32_t)total;
+    p.result[0] = (uint32_t)total;
+    p.result[1] = (uint32_t)(total >> 32);
+  }
+}
+
+// Pass 2: the block codes of every chunk at its table offset.
+__global__ __launch_bounds__(kZfThreads) void k_zf_encode(ZfParams p) {
+  const int64_t ch = (int64_t)blockIdx.x * kZfThreads + threadIdx.x;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < p.cap_words) p.out[k] = p.head[k];
+  }
+  if (ch >= p.nchunks) return;
+  const int64_t off = p.pay_base + (int64_t)p.out[p.hdr_base + ch];  // written by the scan
+  const int64_t room = p.cap_words - off;
+  BitSink bs(p.out + off, room > 0 ? room : 0);
+  const int64_t b1 = min((ch + 1) * kZfChunk, (int64_t)p.nblocks);
+  for (int64_t b = ch * kZfChunk; b < b1; ++b) {
+    float x[16];
+    load_block(p, b, x);
+    (void)encode_block(x, p.minexp, bs);
+  }
+  bs.flush();
+}
+
+// Decoder: one thread per chunk, reading only its table range.
+__global__ __launch_bounds__(kZfThreads) void k_zf_decode(ZfParams p) {
+  const int64_t ch = (int64_t)blockIdx.x * kZfThreads + threadIdx.x;
+  if (ch >= p.nchunks) return;
+  const uint32_t* table = p.in + p.hdr_base;
+  const int64_t w0 = table[ch], w1 = table[ch + 1];
+  const int64_t avail = p.cap_words - p.pay_base;  // payload words in the stream
+  if (w0 > w1 || w1 > avail) {
+    atomicOr(p.flags, kZfCorrupt);
+    return;
+  }
+  BitSource src(p.in + p.pay_base + w0, w1 - w0);
+  const int64_t per = (int64_t)p.bz * p.bx;
+  const int64_t b1 = min((ch + 1) * kZfChunk, (int64_t)p.nblocks);
+  for (int64_t b = ch * kZfChunk; b < b1; ++b) {
+    float x[16];
+    decode_block(src, p.minexp, x);
+    if (src.bad) break;
+    const int64_t img = b / per;
+    const int64_t rem = b - img * per;
+    const int bi = (int)(rem / p.bx), bj = (int)(rem - (int64_t)bi * p.bx);
+    float* a = p.y + img * (int64_t)p.rows * p.cols;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * bi + i, c = 4 * bj + j;
+        if (r < p.rows && c < p.cols) a[(int64_t)r * p.cols + c] = x[4 * i + j];
+      }
+  }
+  if (src.bad) atomicOr(p.flags, kZfCorrupt);
+}
+
+}  // namespace
+
+hipError_t launch_zf_encode(const ZfParams& p, uint32_t* counts, uint64_t* totals, hipStream_t s) {
+  if (p.nchunks < 1) return hipErrorInvalidValue;
+  const int64_t g = (p.nchunks + kZfThreads - 1) / kZfThreads;
+  k_zf_count<<<(unsigned)g, kZfThreads, 0, s>>>(p, counts);
+  const int64_t ng = (p.nchunks + kZfScan - 1) / kZfScan;
+  k_zf_scan_totals<<<(unsigned)ng, kZfScan, 0, s>>>(counts, p.nchunks, totals);
+  k_zf_scan_base<<<1, kZfScan, 0, s>>>(totals, ng);
+  k_zf_scan_table<<<(unsigned)ng, kZfScan, 0, s>>>(counts, p.nchunks, totals, p);
+  k_zf_encode<<<(unsigned)g, kZfThreads, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_zf_decode(const ZfParams& p, hipStream_t s) {
+  if (p.nchunks < 1) return hipErrorInvalidValue;
+  const int64_t g = (p.nchunks + kZfThreads - 1) / kZfThreads;
+  k_zf_decode<<<(unsigned)g, kZfThreads, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace rtm

@@ -18,7 +18,7 @@ STATUS = {0: "RTM_OK", -1: "RTM_E_INVAL", -2: "RTM_E_CFL", -3: "RTM_E_NOMEM", -4
 SNAP = {"fp32": 0, "bf16": 1, "fp16": 2}
 SRC_STORE, SRC_RECONSTRUCT = 0, 1
 IMG_ILLUM = 1
-CODEC_TOL, CODEC_LOSSLESS = 0, 1
+CODEC_TOL, CODEC_LOSSLESS, CODEC_ZFP = 0, 1, 2
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = range(5)
 JOB_ACC_STATS, JOB_ACC_STACK = 1, 2
 
@@ -350,8 +350,9 @@ class Context:
     def codec_max_bytes(self, count, rows, cols) -> int:
         return int(lib().rtm_codec_max_bytes(int(count), int(rows), int(cols)))
 
-    def codec_encode(self, x, tol=None, lossless=False, out=None):
-        """Encode a float32 [rows][cols] or [count][rows][cols] device tensor.
+    def codec_encode(self, x, tol=None, lossless=False, out=None, zfp=False):
+        """Encode a float32 [rows][cols] or [count][rows][cols] device tensor
+        (zfp=True: the fixed-accuracy ZFP-method coder, RTM_CODEC_ZFP).
 
         Returns the stream as a uint8 device tensor (a view of `out` when given)."""
         import torch
@@ -364,7 +365,7 @@ class Context:
                 raise ValueError("shape outside the codec's limits")
             out = torch.empty(cap, dtype=torch.uint8, device=x.device)
         n = ctypes.c_int64(0)
-        mode = CODEC_LOSSLESS if lossless else CODEC_TOL
+        mode = CODEC_ZFP if zfp else (CODEC_LOSSLESS if lossless else CODEC_TOL)
         _check(lib().rtm_codec_encode(self.h, _ptr(x), count, rows, cols, mode,
                                       float(tol if tol is not None else 0.0), _ptr(out), out.numel(),
                                       ctypes.byref(n)))

@@ -133,7 +133,9 @@ def test_encode_rejects(ctx, rtm):
         with pytest.raises(rtm.RTMError):
             ctx.codec_encode(dev(y), tol=bad_tol)
     assert ctx.codec_max_bytes(0, 5, 5) == -1
-    assert ctx.codec_max_bytes(1, 8, 8) == 4 * (8 + 2 + 1 + 64)
+    # the larger of this coder's bound (index + 64 words per 8 x 8 block) and
+    # the ZFP-method coder's (index + 585 bits per 4 x 4 block, per chunk)
+    assert ctx.codec_max_bytes(1, 8, 8) == max(4 * (8 + 2 + 1 + 64), 4 * (8 + 2 + (4 * 585 + 31) // 32))
 
 
 def test_decode_rejects_corrupt_streams(ctx, rtm):
