@@ -263,18 +263,22 @@ def run_survey(args):
         f"{images_per_s:.1f} images/s")
 
     # dominant kernel: backward step (HIP events around all its launches, work
-    # stream).  The library reports per-time-step figures; a launch advances
-    # `spl` steps, so its algorithmic bytes are spl x the per-step minimum
-    # (16 B per update and the rest, summed over the shots).
+    # stream).  The library reports per-time-step figures over all shots; a
+    # launch advances `spl` steps of one group of shots, so its mean
+    # algorithmic bytes are spl x the per-step minimum (16 B per update and
+    # the rest, summed over the shots) / groups, and its mean duration the
+    # phase time x spl / (steps x groups).
     spl = max(1, s1.last_steps_per_launch)
-    bwd_launch_ms = spl * s1.last_bwd_ms / s1.last_bwd_launches
-    fwd_launch_ms = spl * s1.last_fwd_ms / s1.last_fwd_launches
-    bwd_launch_bytes = spl * s1.last_bwd_launch_bytes
-    fwd_launch_bytes = spl * s1.last_fwd_launch_bytes
+    gfw, gbw = max(1, s1.last_groups_fwd), max(1, s1.last_groups_bwd)
+    bwd_launch_ms = spl * s1.last_bwd_ms / (s1.last_bwd_launches * gbw)
+    fwd_launch_ms = spl * s1.last_fwd_ms / (s1.last_fwd_launches * gfw)
+    bwd_launch_bytes = spl * s1.last_bwd_launch_bytes / gbw
+    fwd_launch_bytes = spl * s1.last_fwd_launch_bytes / gfw
     achieved = bwd_launch_bytes / (bwd_launch_ms * 1e-3) / 1e9
     achieved_fwd = fwd_launch_bytes / (fwd_launch_ms * 1e-3) / 1e9
-    log(f"[bench] backward launch ({spl} steps) {bwd_launch_ms * 1e3:.1f} us, {achieved:.0f} GB/s; "
-        f"forward launch {fwd_launch_ms * 1e3:.1f} us, {achieved_fwd:.0f} GB/s")
+    log(f"[bench] backward launch ({spl} steps, {len(shots) / gbw:.1f} shots) {bwd_launch_ms * 1e3:.1f} us, "
+        f"{achieved:.0f} GB/s; forward launch ({len(shots) / gfw:.1f} shots) {fwd_launch_ms * 1e3:.1f} us, "
+        f"{achieved_fwd:.0f} GB/s")
 
     # ---- plain path: one rtm_migrate_shot per shot, one launch per step ----
     plain = None
@@ -306,8 +310,9 @@ def run_survey(args):
         "workload": f"faulted-layer survey {nz}x{nx} at 10 m, {len(shots)} shots, nt={nt}, "
                     f"nb={nb}, reconstruct mode, stacked",
         "nz": nz, "nx": nx, "nb": nb, "nt": nt, "shots": len(shots), "src_mode": "reconstruct",
-        "path": "batched (hipGraph, all shots per launch)", "tile_z": s1.tile_z,
-        "tile_z2": {"forward": s1.last_tile_z2_fwd, "backward": s1.last_tile_z2_bwd}})
+        "path": "batched (hipGraph, shot groups sized for the memory-side cache)", "tile_z": s1.tile_z,
+        "tile_z2": {"forward": s1.last_tile_z2_fwd, "backward": s1.last_tile_z2_bwd},
+        "shot_groups": {"forward": gfw, "backward": gbw}})
     out.update({
         "images_per_s": images_per_s,
         "plain": plain,
@@ -319,6 +324,7 @@ def run_survey(args):
                                 "per launch" if spl == 2 else "k_step<TZ,2> backward")
                                + " (receiver step + reconstruct + imaging)",
                      "steps_per_launch": spl,
+                     "shots_per_launch": len(shots) / gbw,
                      "alg_bytes_per_launch": bwd_launch_bytes,
                      "launch_us": bwd_launch_ms * 1e3,
                      "forward_launch": {"achieved": achieved_fwd, "launch_us": fwd_launch_ms * 1e3,

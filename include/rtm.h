@@ -198,14 +198,17 @@ typedef struct {
     const float *data_dev;     /* [nt][nrec] */
 } rtm_shot_desc;
 
-/* Migrate nshots shots of one model together: every shot advances in the
- * same kernel launches, two time steps per launch in reconstruct mode
- * without illumination (two-step tiles of 24 rows, or 16 where the last
- * 24-row tile of a shot would read past its field allocation; RTM_TILE_Z2 =
- * 16, 24 or 32 sets the height, 0 keeps one step per launch; results are the
- * same bit for bit; rtm_ctx_stats reports the heights used),
- * launches are replayed from a captured HIP graph, and the one-step tile
- * shape comes from the autotuner.
+/* Migrate nshots shots of one model together (Sec. 3, Stage 2: the shots of
+ * one velocity model): the shots advance in shared kernel launches, two time
+ * steps per launch in reconstruct mode without illumination (two-step tile
+ * heights from the autotuner per phase; RTM_TILE_Z2 = 16, 24 or 32 forces a
+ * height, 0 keeps one step per launch; results are the same bit for bit;
+ * rtm_ctx_stats reports the heights used), launches are replayed from a
+ * captured HIP graph, and the one-step tile shape comes from the autotuner.
+ * All shots are resident at once; each phase runs them in groups of
+ * consecutive shots whose levels fit the memory-side cache (RTM_GROUP_KB,
+ * default 200 MiB of field bytes a launch touches; 0 runs all shots in every
+ * launch), one group after another, which changes no result.
  * Each shot's image is added into image_dev in shot order after all shots
  * finish (deterministic stack).  Shots with the same window (ix0, width)
  * share one c = v^2 dt^2 array and its sponge profiles, built once.  Same
@@ -225,7 +228,9 @@ int rtm_migrate_batch(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
  * device: a scheduler thread admits queued jobs whenever arena memory frees
  * up and advances every admitted job in the same kernel launches
  * (continuous batching); finished images feed per-sample statistics on the
- * device (Sec. 2.3, Stage 3). */
+ * device (Sec. 2.3, Stage 3).  RTM_SERVE_KB (KiB) optionally caps the field
+ * bytes the running jobs' launches touch; admission then waits, in order,
+ * until running jobs finish. */
 
 /* Register velocity sample `realization` (Sec. 3, Stage 2: one migration
  * set per velocity sample).  The velocity is copied into the arena and v_max
@@ -596,6 +601,11 @@ typedef struct {
      * forward and backward phases, 0 for a phase that ran one step per
      * launch */
     int32_t last_tile_z2_fwd, last_tile_z2_bwd;
+    /* last rtm_migrate_batch call: shot groups of its forward and backward
+     * phases (consecutive shots whose levels fit the memory-side cache run
+     * through a phase together, one group after another; each launch covers
+     * one group, so a phase made nsteps x groups launches) */
+    int32_t last_groups_fwd, last_groups_bwd;
 } rtm_ctx_stats_t;
 
 int rtm_ctx_stats(rtm_ctx *ctx, rtm_ctx_stats_t *out);

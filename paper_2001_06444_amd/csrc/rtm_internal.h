@@ -74,11 +74,17 @@ struct alignas(16) Tile {
 
 // Launch control block for graph-replayed launches: a launch's global step
 // is ctl->tick + its own offset; k_advance moves ctl->tick after each group.
+// A launch that passes ntiles < 0 takes its tiles from the control block:
+// ntiles_* tiles from index base_* of the table it is given (the batched
+// path moves the range from one group of shots to the next; the serving
+// engine keeps the bases at 0).
 struct alignas(16) StepCtl {
   int32_t tick;       // global step base; job step = tick + offset - start_tick
-  int32_t ntiles_fw;  // two-step tiles of the forward table (read when a launch passes ntiles < 0)
-  int32_t ntiles;     // one-step tiles (read when a launch passes ntiles < 0)
-  int32_t ntiles_bw;  // two-step tiles of the backward table (likewise)
+  int32_t ntiles_fw;  // two-step tiles of the forward table
+  int32_t ntiles;     // one-step tiles
+  int32_t ntiles_bw;  // two-step tiles of the backward table
+  int32_t base_fw, base, base_bw;  // first tile of each range
+  int32_t pad_;
 };
 
 // Does a two-step launch advance a reconstruct-mode job from its step s
@@ -114,6 +120,7 @@ hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tile
                         int ntiles, int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
                         hipStream_t s);
 hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s);
+hipError_t launch_set_ctl(StepCtl* ctl, StepCtl v, hipStream_t s);  // *ctl = v, in stream order
 hipError_t launch_prep(const float* vel, int model_nx, int ix0, const DevJob* host_job,
                        float* c, float* gz, float* gx, float dt, float sponge_a, hipStream_t s);
 hipError_t launch_vmax(const float* vel, int nz, int model_nx, int ix0, int width,

@@ -1004,7 +1004,11 @@ __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ j
   // are still in the caches (measured: 2 % shorter launches).  The grid may
   // be sized for more tiles than the table holds (graph replays read the
   // count from the control block).
-  const int ntiles = ntiles_arg >= 0 ? ntiles_arg : ((PH & kPhFwd) ? ctl->ntiles_fw : ctl->ntiles_bw);
+  int ntiles = ntiles_arg;
+  if (ntiles_arg < 0) {
+    ntiles = (PH & kPhFwd) ? ctl->ntiles_fw : ctl->ntiles_bw;
+    tiles += (PH & kPhFwd) ? ctl->base_fw : ctl->base_bw;
+  }
   const int tick = (use_ctl_tick ? ctl->tick : 0) + tick_off;
   const int per = (ntiles + 7) >> 3;
   const int local0 = (int)(blockIdx.x >> 3);
@@ -1032,7 +1036,11 @@ __global__ __launch_bounds__(kThreads) void k_step(const DevJob* __restrict__ jo
   __shared__ StepSmem<TZ, (PH & (kPhBwd | kPhBorn)) != 0> sm;
   // Global step: a base read from the control block (advanced by k_advance
   // after every group of graph-replayed launches) plus this launch's offset.
-  const int ntiles = ntiles_arg >= 0 ? ntiles_arg : ctl->ntiles;
+  int ntiles = ntiles_arg;
+  if (ntiles_arg < 0) {
+    ntiles = ctl->ntiles;
+    tiles += ctl->base;
+  }
   const int tick = (use_ctl_tick ? ctl->tick : 0) + tick_off;
   // XCD-aware mapping: workgroups are dealt round-robin to the 8 XCDs, so
   // give XCD k (blockIdx % 8) a contiguous run of tiles; neighbouring tiles,
@@ -1065,6 +1073,13 @@ __global__ void k_advance(StepCtl* ctl, int k) { ctl->tick += k; }
 
 hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, ctl, k);
+  return hipGetLastError();
+}
+
+__global__ void k_set_ctl(StepCtl* ctl, StepCtl v) { *ctl = v; }
+
+hipError_t launch_set_ctl(StepCtl* ctl, StepCtl v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(1), 0, s, ctl, v);
   return hipGetLastError();
 }
 

@@ -237,6 +237,7 @@ struct rtm_ctx {
   int ph_launches[2] = {0, 0};  // time steps of each phase
   int ph_steps_per_launch = 1;
   int ph_tz2[2] = {0, 0};  // two-step tile height of each phase (0: one step per launch)
+  int ph_groups[2] = {1, 1};  // shot groups of each phase (a launch covers one group)
   uint64_t ph_bytes[2] = {0, 0};
   bool ph_valid = false;
   Arena arena;
@@ -724,7 +725,9 @@ struct Table {
     int ntiles = 0, tz = 0;
     std::shared_ptr<std::vector<Tile>> htiles = std::make_shared<std::vector<Tile>>();
     std::shared_ptr<std::vector<int2>> hrecs = std::make_shared<std::vector<int2>>();
+    std::vector<int> first;  // first tile of each job (njobs + 1 entries)
   } fw, bw;
+  std::vector<int> first;  // first one-step tile of each job (njobs + 1 entries)
   std::vector<Block> blocks;
   std::shared_ptr<std::vector<DevJob>> hjobs;
   std::shared_ptr<std::vector<Tile>> htiles;
@@ -806,19 +809,25 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   t.htiles = std::make_shared<std::vector<Tile>>();
   for (size_t i = 0; i < js.size(); ++i) {
     t.hjobs->push_back(js[i]->d);
+    t.first.push_back((int)t.htiles->size());
     for (Tile tl : js[i]->tiles) {
       tl.job = (int)i;
       t.htiles->push_back(tl);
     }
   }
   t.ntiles = (int)t.htiles->size();
+  t.first.push_back(t.ntiles);
   bool pairs = true;
   for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon && !(j->g.flags & RTM_IMG_ILLUM) && j->g.nbuf == 4;
   for (auto [tw, tz2] : {std::make_pair(&t.fw, tz2f), std::make_pair(&t.bw, tz2b)}) {
     if (!pairs || (tz2 != 16 && tz2 != 24 && tz2 != 32)) continue;
     if (!tz2_fits(js, tz2)) tz2 = 16;
-    for (size_t i = 0; i < js.size(); ++i) append_two_step_tiles(*js[i], (int)i, tz2, *tw->htiles, *tw->hrecs);
+    for (size_t i = 0; i < js.size(); ++i) {
+      tw->first.push_back((int)tw->htiles->size());
+      append_two_step_tiles(*js[i], (int)i, tz2, *tw->htiles, *tw->hrecs);
+    }
     tw->ntiles = (int)tw->htiles->size();
+    tw->first.push_back(tw->ntiles);
     tw->tz = tz2;
   }
   void* p;
@@ -1363,41 +1372,47 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
 // Batched path: all shots in every launch, hipGraph replays of K steps
 // ===========================================================================
 // Runs nsteps launches of the step kernel: whole groups of K as replays of a
-// captured graph (K step nodes with offsets 0..K-1, then one k_advance node),
-// the remainder as direct launches followed by one k_advance.
+// captured graph (K step launches with offsets 0..K-1, then one k_advance
+// node), the remainder as direct launches followed by one k_advance.  The
+// launches take their tiles from the control block (a range of the table,
+// sized for up to grid[kind] tiles: one-step, forward and backward two-step),
+// so one captured graph serves every group of shots; `*graph` keeps it.
 // With `two_step` and a two-step table for the phase the launches go two
 // steps each; an odd last step runs as a one-step launch.  The caller starts
 // the backward phase with two one-step launches (levels nt - 1 and nt - 2 are
 // not reconstructed) before it asks for pairs.
-static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, int nsteps, int K,
-                       std::vector<hipGraphExec_t>& graphs, bool two_step) {
+static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, const int (&grid)[3], int nsteps,
+                       int K, hipGraphExec_t* graph, bool two_step) {
   const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
   const bool pairs = two_step && tw.ntiles > 0 && (ph == kPhFwd || ph == kPhBwd);
   if (pairs) K = std::max(2, K & ~1);
   auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`
     if (pairs && left >= 2)
-      return launch_step2(tw.tz, ph, t.jobs, tw.tiles, tw.recs, tw.ntiles, tw.ntiles, t.ctl, 1, off, s);
-    return launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, off, s);
+      return launch_step2(tw.tz, ph, t.jobs, tw.tiles, tw.recs, -1, grid[ph == kPhFwd ? 1 : 2], t.ctl, 1, off, s);
+    return launch_step(tz, ph, t.jobs, t.tiles, -1, grid[0], t.ctl, 1, off, s);
   };
   int done = 0;
   if (nsteps >= K && K > 1) {
-    hipGraph_t g = nullptr;
-    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < K && e == hipSuccess; i += pairs ? 2 : 1) e = one(i, K - i);
-    if (e == hipSuccess) e = launch_advance(t.ctl, K, s);
-    hipError_t e2 = hipStreamEndCapture(s, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return fail(RTM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    if (!*graph) {
+      hipGraph_t g = nullptr;
+      HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < K && e == hipSuccess; i += pairs ? 2 : 1) e = one(i, K - i);
+      if (e == hipSuccess) e = launch_advance(t.ctl, K, s);
+      hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(RTM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      e = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        *graph = nullptr;
+        return fail(RTM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      }
     }
-    hipGraphExec_t ex = nullptr;
-    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(RTM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    graphs.push_back(ex);
     for (; done + K <= nsteps; done += K) {
-      HIP_OK(hipGraphLaunch(ex, s));
+      HIP_OK(hipGraphLaunch(*graph, s));
       ctx->graph_replays++;
     }
   }
@@ -1410,6 +1425,121 @@ static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, in
     HIP_OK(launch_advance(t.ctl, nsteps - done, s));
   }
   ctx->steps_launched += nsteps;
+  return RTM_OK;
+}
+
+// Shot groups of the batched path.  Every launch of a phase reads the levels
+// the previous launch wrote; when the levels of all the shots in a launch fit
+// in the memory-side cache (256 MB on MI355X) with room to spare, the next
+// launch reads them from there instead of HBM.  So the shots run in groups,
+// one group after another through a phase, each group's per-launch working
+// set (the field bytes a launch reads or writes, the image, c once) at most
+// the budget RTM_GROUP_KB (KiB, default 200 MiB; 0: one group).  Measured on
+// the 351 x 1701 survey (nt 1000): 7.7 shots per backward launch and 14.3 per
+// forward launch, 6.5 us and 2.8 us of launch time per shot, against 7.6 and
+// 3.7 us with all 100 shots in every launch; larger groups spill out of the
+// cache (11 shots per backward launch: 7.8 us per shot).  Groups are
+// consecutive runs of jobs of near-equal working set.
+static size_t group_budget() {
+  const char* e = getenv("RTM_GROUP_KB");
+  const long v = e ? atol(e) : 200 << 10;
+  return v <= 0 ? SIZE_MAX : (size_t)v << 10;
+}
+
+// Running-set budget of the serving engine (RTM_SERVE_KB, KiB; unset or 0:
+// none, admission is limited by the arena only).  Unlike the batch path's
+// shot groups it did not pay off on the served workloads (1024-RTM ensemble
+// 3.79e11 updates/s without, 3.90e11 / 3.60e11 at 200 / 400 MiB; 400-job
+// saturation 96.1 images/s without, 86.0 / 98.6), where the jobs in flight
+// sit in different phases and split into several smaller launches.
+static size_t serve_budget() {
+  const char* e = getenv("RTM_SERVE_KB");
+  const long v = e ? atol(e) : 0;
+  return v <= 0 ? SIZE_MAX : (size_t)v << 10;
+}
+
+static size_t launch_working_set(const JobGeom& g, int ph) {
+  const size_t row = (size_t)field_pitch(g.width + 2 * g.nb) * 4;
+  const size_t pad = (size_t)(g.nz + 2 * g.nb) * row, phys = (size_t)g.nz * row;
+  if (ph == kPhFwd) return 4 * pad;  // two levels read, two written
+  // R: two levels read, two written; S likewise on the window, and the image
+  // (reconstruct mode); a stored snapshot and the image (store mode)
+  return 4 * pad + (g.mode == kModeRecon ? 5 * phys : 2 * phys);
+}
+
+static std::vector<std::pair<int, int>> shot_groups(const std::vector<JobGeom>& gs, int ph) {
+  std::vector<std::pair<int, int>> out;
+  const int n = (int)gs.size();
+  if (n == 0) return out;
+  size_t total = 0, medium = 0;
+  for (const JobGeom& g : gs) {
+    total += launch_working_set(g, ph);
+    medium = std::max(medium, (size_t)(g.nz + 2 * g.nb) * field_pitch(g.width + 2 * g.nb) * 4);  // c
+  }
+  const size_t budget = group_budget();
+  if (budget == SIZE_MAX || total + medium <= budget) return {{0, n}};
+  const size_t room = budget > medium ? budget - medium : 1;
+  const int ngroups = (int)std::min<size_t>(n, (total + room - 1) / room);
+  if (ngroups == n) {  // one job per group
+    for (int i = 0; i < n; ++i) out.push_back({i, i + 1});
+    return out;
+  }
+  // job i joins group floor(ngroups x (middle of its share) / total), a
+  // non-decreasing index: runs of near-equal working set
+  size_t before = 0;
+  int last = -1;
+  for (int i = 0; i < n; ++i) {
+    const size_t w = launch_working_set(gs[i], ph);
+    const int gi = (int)std::min<size_t>(ngroups - 1, (2 * before + w) * ngroups / (2 * total));
+    if (gi != last) {
+      out.push_back({i, i + 1});
+      last = gi;
+    } else {
+      out.back().second = i + 1;
+    }
+    before += w;
+  }
+  return out;
+}
+
+// One phase of the batch, group by group: the control block is pointed at
+// the group's tile ranges with the tick at `tick0`, then the group's steps
+// run (a backward phase with two-step tiles opens with two one-step launches).
+static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t,
+                            const std::vector<std::pair<int, int>>& groups, int tick0, int nsteps, int K,
+                            hipGraphExec_t* graph, bool two_step) {
+  const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
+  const bool pairs = two_step && tw.ntiles > 0;
+  int grid[3] = {0, 0, 0};
+  for (auto [a, b] : groups) {
+    grid[0] = std::max(grid[0], t.first[b] - t.first[a]);
+    if (pairs) grid[ph == kPhFwd ? 1 : 2] = std::max(grid[ph == kPhFwd ? 1 : 2], tw.first[b] - tw.first[a]);
+  }
+  for (auto [a, b] : groups) {
+    StepCtl c{};
+    c.tick = tick0;
+    c.ntiles = t.first[b] - t.first[a];
+    c.base = t.first[a];
+    if (pairs && ph == kPhFwd) {
+      c.ntiles_fw = tw.first[b] - tw.first[a];
+      c.base_fw = tw.first[a];
+    } else if (pairs) {
+      c.ntiles_bw = tw.first[b] - tw.first[a];
+      c.base_bw = tw.first[a];
+    }
+    HIP_OK(launch_set_ctl(t.ctl, c, s));
+    int rc = RTM_OK;
+    if (ph == kPhBwd && pairs && nsteps >= 4) {
+      // levels nt - 1 and nt - 2 are imaged without reconstruction: one step each
+      for (int i = 0; i < 2; ++i) HIP_OK(launch_step(tz, kPhBwd, t.jobs, t.tiles, -1, grid[0], t.ctl, 1, i, s));
+      HIP_OK(launch_advance(t.ctl, 2, s));
+      ctx->steps_launched += 2;
+      rc = graph_steps(ctx, s, tz, ph, t, grid, nsteps - 2, K, graph, true);
+    } else {
+      rc = graph_steps(ctx, s, tz, ph, t, grid, nsteps, K, graph, pairs && ph == kPhFwd);
+    }
+    if (rc) return rc;
+  }
   return RTM_OK;
 }
 
@@ -1462,9 +1592,14 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (int i = 1; i < nshots; ++i)
     if (geoms[i].width > geoms[widest].width) widest = i;
   const int tz = autotune_tz(ctx, s, geoms[widest], vel_dev, nshots);
-  // two-step heights, tuned before the batch takes its arena blocks
+  // shot groups of each phase; two-step heights, tuned at the size of the
+  // backward groups (the dominant launches) before the batch takes its
+  // arena blocks
+  const auto gf = shot_groups(geoms, kPhFwd), gb = shot_groups(geoms, kPhBwd);
+  int gmax = 1;
+  for (auto [a, b] : gb) gmax = std::max(gmax, b - a);
   int tz2f = 0, tz2b = 0;
-  if (geoms[widest].nbuf == 4) autotune_tz2(ctx, s, geoms[widest], vel_dev, nshots, &tz2f, &tz2b);
+  if (geoms[widest].nbuf == 4) autotune_tz2(ctx, s, geoms[widest], vel_dev, gmax, &tz2f, &tz2b);
   std::vector<std::unique_ptr<HostJob>> jobs;
   std::vector<HostJob*> ptrs;
   auto cleanup = [&]() {
@@ -1497,23 +1632,14 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     return rc;
   }
   const int nt = grid->nt, K = graph_k();
-  std::vector<hipGraphExec_t> graphs;
+  hipGraphExec_t graphs[2] = {nullptr, nullptr};
   HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
   roctxRangePushA("rtm.batch.forward");  // host-side enqueue of the phase
-  rc = graph_steps(ctx, s, tz, kPhFwd, t, nt - 1, K, graphs, true);
+  rc = run_phase_groups(ctx, s, tz, kPhFwd, t, gf, 0, nt - 1, K, &graphs[0], true);
   roctxRangePop();
   roctxRangePushA("rtm.batch.backward");
   if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
-  if (!rc && t.bw.ntiles > 0 && nt >= 4) {
-    // levels nt - 1 and nt - 2 are imaged without reconstruction: one step each
-    for (int i = 0; i < 2 && !rc; ++i)
-      if (launch_step(tz, kPhBwd, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 1, i, s) != hipSuccess)
-        rc = fail(RTM_E_DEVICE, "step launch failed");
-    if (!rc && launch_advance(t.ctl, 2, s) != hipSuccess) rc = fail(RTM_E_DEVICE, "advance launch failed");
-    if (!rc) rc = graph_steps(ctx, s, tz, kPhBwd, t, nt - 2, K, graphs, true);
-  } else if (!rc) {
-    rc = graph_steps(ctx, s, tz, kPhBwd, t, nt, K, graphs, false);  // one step per launch
-  }
+  if (!rc) rc = run_phase_groups(ctx, s, tz, kPhBwd, t, gb, nt - 1, nt, K, &graphs[1], t.bw.ntiles > 0 && nt >= 4);
   roctxRangePop();
   if (!rc) rc = hipEventRecord(ctx->ph_ev[2], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc) {
@@ -1531,6 +1657,8 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     }
     ctx->ph_launches[0] = nt - 1;
     ctx->ph_launches[1] = nt;
+    ctx->ph_groups[0] = (int)gf.size();
+    ctx->ph_groups[1] = (int)gb.size();
     ctx->ph_steps_per_launch = t.fw.ntiles > 0 && t.bw.ntiles > 0 && nt >= 4 ? 2 : 1;  // both phases ran pairs
     ctx->ph_tz2[0] = t.fw.ntiles > 0 && nt >= 3 ? t.fw.tz : 0;
     ctx->ph_tz2[1] = t.bw.ntiles > 0 && nt >= 4 ? t.bw.tz : 0;
@@ -1563,7 +1691,8 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   d.keep.push_back(t.htiles);
   d.keep.push_back(t.fw.htiles);
   d.keep.push_back(t.bw.htiles);
-  d.graphs = graphs;
+  for (auto g : graphs)
+    if (g) d.graphs.push_back(g);
   int rc2 = defer(ctx, s, std::move(d));
   HIP_OK(hipEventRecord(ctx->ev_out, s));
   HIP_OK(hipStreamWaitEvent(ctx->stream, ctx->ev_out, 0));
@@ -1935,6 +2064,11 @@ static void sched_main(rtm_ctx* ctx) {
     {
       RoctxRange range("rtm.sched.admit");
       AdmitPass pass;
+      // field bytes the running jobs' launches touch: admission stops at
+      // the budget (a job runs alone if it alone exceeds it)
+      size_t running_ws = 0;
+      for (EnsJob* a : active) running_ws += launch_working_set(a->job->g, kPhBwd);
+      const size_t budget = serve_budget();
       for (;;) {
         uint64_t t = 0;
         EnsJob* ej = nullptr;
@@ -1953,6 +2087,12 @@ static void sched_main(rtm_ctx* ctx) {
           fill_geom_rtm(&gr, ej->spec.ix0, ej->spec.width, &ej->spec.img, ej->spec.width, g);
           if (served_two_step(g)) g.nbuf = 4;
           vel = static_cast<const float*>(m.vel.p);  // stable while the job is in flight
+          const size_t ws = launch_working_set(g, kPhBwd);
+          if (running_ws > 0 && budget != SIZE_MAX && running_ws + ws > budget) {
+            ctx->book->admit_result(pass, t, kSchedAgain);  // the running set is full
+            break;
+          }
+          running_ws += ws;
           rc = ensure_stats(ctx, s, m, ej->spec.flags & RTM_JOB_ACC_STATS, ej->spec.flags & RTM_JOB_ACC_STACK);
         }
         // the working set, built without the mutex (polls and submits go on)
@@ -1982,8 +2122,9 @@ static void sched_main(rtm_ctx* ctx) {
           ej->job = std::move(hj);
           active.push_back(ej);
           changed = true;
-        } else if (rc != RTM_E_NOMEM) {
-          log_job(ctx, *ctx->book->find(t), *ej);
+        } else {
+          running_ws -= launch_working_set(g, kPhBwd);  // not admitted
+          if (rc != RTM_E_NOMEM) log_job(ctx, *ctx->book->find(t), *ej);
         }
       }
     }
@@ -2991,6 +3132,8 @@ extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
       out->last_steps_per_launch = ctx->ph_steps_per_launch;
       out->last_tile_z2_fwd = ctx->ph_tz2[0];
       out->last_tile_z2_bwd = ctx->ph_tz2[1];
+      out->last_groups_fwd = ctx->ph_groups[0];
+      out->last_groups_bwd = ctx->ph_groups[1];
       out->last_fwd_launches = ctx->ph_launches[0];
       out->last_bwd_launches = ctx->ph_launches[1];
       out->last_fwd_launch_bytes = ctx->ph_bytes[0];

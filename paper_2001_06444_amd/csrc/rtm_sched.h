@@ -14,7 +14,10 @@
 // Admission is first come, first served with bounded bypass: a pass walks
 // the queue oldest first; the first job that does not fit blocks the pass
 // unless it has been passed over fewer than max_bypass times, in which case
-// younger jobs may try, up to the next one that does not fit.  A job larger
+// younger jobs may try, up to the next one that does not fit.  A candidate
+// refused because the running set is full (the engine keeps the levels of
+// its running jobs within the memory-side cache) ends the pass, with no
+// bypass counted: jobs then start strictly in order.  A job larger
 // than the whole capacity is refused at submit; a queue whose head cannot fit
 // while nothing runs (and nothing is about to be freed) fails its head with
 // out-of-memory rather than wait forever (fail_head).
@@ -117,7 +120,8 @@ class JobBook {
   }
 
   // Outcome of trying a candidate: kSchedOk (admitted: RUNNING), kSchedNomem
-  // (does not fit now: QUEUED again) or another code (the job fails).
+  // (does not fit now: QUEUED again), kSchedAgain (the running set is full:
+  // QUEUED again and the pass ends) or another code (the job fails).
   void admit_result(AdmitPass& p, uint64_t ticket, int rc) {
     SchedEntry& e = jobs_.at(ticket);
     if (rc == kSchedOk) {
@@ -125,6 +129,9 @@ class JobBook {
       e.t_admit = clock_();
       queue_.erase(ticket);
       ++running_;
+    } else if (rc == kSchedAgain) {
+      e.state = kJobQueued;
+      p.stopped = true;
     } else if (rc == kSchedNomem) {
       e.state = kJobQueued;
       if (p.blocked || ++e.bypassed > max_bypass_) p.stopped = true;  // keep the blocked job from starving

@@ -169,6 +169,23 @@ static void rules() {
     check(b.in_flight(3) == 2 && b.cancelled() == 1, "cancel leaves the count of jobs in flight");
     check(b.forget(r) == kSchedInval, "running job cannot be forgotten");
   }
+  // a full running set ends the pass: no bypass, strict order
+  {
+    JobBook b(clk.fn(), 1000);
+    uint64_t t[3];
+    for (auto& x : t) b.submit(0, 10, &x);
+    AdmitPass p;
+    check(b.next_candidate(p) == t[0], "first candidate");
+    b.admit_result(p, t[0], kSchedOk);
+    check(b.next_candidate(p) == t[1], "second candidate");
+    b.admit_result(p, t[1], kSchedAgain);
+    check(b.next_candidate(p) == 0, "running set full: the pass ends");
+    check(b.find(t[1])->state == kJobQueued && b.find(t[1])->bypassed == 0, "queued again, no bypass counted");
+    check(b.find(t[2])->state == kJobQueued, "younger job not tried");
+    size_t free_bytes = 1000;
+    auto a = pass(b, free_bytes);
+    check(a.size() == 2 && a[0] == t[1] && a[1] == t[2], "next pass admits in order");
+  }
   // stalled head fails; a build error fails only its job
   {
     JobBook b(clk.fn(), 100);

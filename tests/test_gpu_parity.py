@@ -362,7 +362,12 @@ def test_two_step_launches_equal_one_step(rtm, ctx, nt, nb):
         assert float(plain.abs().max()) > 0
 
 
-def test_batch_equals_plain_bitwise(rtm, ctx):
+@pytest.mark.parametrize("group_kb", [None, "0", "600", "1"])
+def test_batch_equals_plain_bitwise(rtm, ctx, group_kb):
+    """The batched path equals the plain path bit for bit, whatever the shot
+    groups: RTM_GROUP_KB unset (the default budget: one group at this size),
+    0 (one group), 600 KiB (groups of about two shots) and 1 KiB (one shot
+    per group)."""
     rng = np.random.default_rng(6)
     nz, nx, h, dt, nt, nb = 60, 230, 10.0, 1e-3, 260, 10
     vel = inputs.smooth_slowness(1700 + 600 * rng.random((nz, nx)), 30.0, h, h)
@@ -376,12 +381,29 @@ def test_batch_equals_plain_bitwise(rtm, ctx):
         rec = [(1, x) for x in range(ix0, ix0 + width)]
         d = dev(rng.standard_normal((nt, width)) * 1e-3)
         shots.append(((1, sx), ix0, width, rec, d))
-    for mode, dtype, stride in (("reconstruct", "fp32", 1), ("store", "bf16", 4)):
-        opts = rtm.img_opts(mode, dtype, stride)
-        plain = torch.zeros(nz, nx, device="cuda")
-        for (src, ix0, width, rec, d) in shots:
-            ctx.migrate_shot(g, dev(vel), dev(w), src, rec, d, ix0, width, opts, plain)
-        batch = torch.zeros(nz, nx, device="cuda")
-        ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch)
-        torch.cuda.synchronize()
-        assert torch.equal(plain, batch), (mode, (plain - batch).abs().max().item())
+    old = os.environ.get("RTM_GROUP_KB")
+    try:
+        if group_kb is None:
+            os.environ.pop("RTM_GROUP_KB", None)
+        else:
+            os.environ["RTM_GROUP_KB"] = group_kb
+        for mode, dtype, stride in (("reconstruct", "fp32", 1), ("store", "bf16", 4)):
+            opts = rtm.img_opts(mode, dtype, stride)
+            plain = torch.zeros(nz, nx, device="cuda")
+            for (src, ix0, width, rec, d) in shots:
+                ctx.migrate_shot(g, dev(vel), dev(w), src, rec, d, ix0, width, opts, plain)
+            batch = torch.zeros(nz, nx, device="cuda")
+            ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch)
+            torch.cuda.synchronize()
+            assert torch.equal(plain, batch), (mode, group_kb, (plain - batch).abs().max().item())
+            st = ctx.stats()
+            groups = {None: (1, 1), "0": (1, 1), "1": (6, 6)}.get(group_kb)
+            if groups is not None:
+                assert (st.last_groups_fwd, st.last_groups_bwd) == groups
+            else:  # several shots per group, more groups in the backward phase
+                assert 1 < st.last_groups_fwd <= st.last_groups_bwd < 6, (st.last_groups_fwd, st.last_groups_bwd)
+    finally:
+        if old is None:
+            os.environ.pop("RTM_GROUP_KB", None)
+        else:
+            os.environ["RTM_GROUP_KB"] = old
