@@ -52,9 +52,11 @@ def kernel_source_hash(sources=STEP_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(record="traffic_backward_step.json", sources=STEP_SOURCES, key=None):
+def measured_traffic(record="traffic_backward_step.json", sources=STEP_SOURCES, key=None, launch=None):
     """HBM bytes per launch of a kernel from a committed rocprofv3 counter
-    summary, or None if it is missing or was taken on other code."""
+    summary, or None if it is missing, was taken on other code or, given
+    `launch` (fields the summary must hold with these values: tile height,
+    shots per launch), on another launch configuration."""
     f = ROOT / "profiles" / record
     if not f.exists():
         return None
@@ -64,6 +66,9 @@ def measured_traffic(record="traffic_backward_step.json", sources=STEP_SOURCES, 
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash(sources):
         return None
+    for k, v in (launch or {}).items():
+        if rec.get(k) != v:
+            return None
     if key is not None:
         rec = rec.get("kernels", {}).get(key, {})
     return rec.get("hbm_bytes_per_launch")
@@ -119,7 +124,7 @@ def parse():
     ap.add_argument("--shots", type=int, default=100)
     ap.add_argument("--nt", type=int, default=None, help="default: 4000 survey, 3000 ensemble")
     ap.add_argument("--plain-shots", type=int, default=2)
-    ap.add_argument("--cpu-nt", type=int, default=2000)
+    ap.add_argument("--cpu-nt", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device tensor copy (reference dispatch "
@@ -319,7 +324,8 @@ def run_survey(args):
         "batched_vs_plain": (images_per_s / plain["images_per_s"]) if plain else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(launch={"tile_z2": s1.last_tile_z2_bwd,
+                                                         "groups": gbw, "shots": len(shots)}),
                      "kernel": (f"k_step2<{s1.last_tile_z2_bwd},2> backward, two time steps "
                                 "per launch" if spl == 2 else "k_step<TZ,2> backward")
                                + " (receiver step + reconstruct + imaging)",
@@ -448,8 +454,10 @@ def _ensemble(args, R, nt, plain_shots):
     n_img = R * len(shots)
     failed = sum(1 for tk in tickets if ctx.poll(tk, release=True).state != rtm.JOB_DONE)
     updates = s1.grid_updates - s0.grid_updates
+    alg = s1.alg_bytes - s0.alg_bytes  # per-update minimum bytes of the finished jobs
     log(f"[bench] ensemble: {n_img} RTMs in {el:.2f} s ({n_img / el:.1f} images/s, "
-        f"{updates / el:.3e} updates/s), {failed} failed, tile_z {s1.tile_z}")
+        f"{updates / el:.3e} updates/s, {alg / t_rtm / 1e9:.0f} GB/s of algorithmic bytes over the "
+        f"served phase), {failed} failed, tile_z {s1.tile_z}")
     plain_jobs = [dict(vel=t(smooth), wav=wav, src=sh.src, rec=[(1, x) for x in range(sh.ix0, sh.ix0 + sh.width)],
                        data=d, ix0=sh.ix0, width=sh.width, opts=opts, image_shape=(nz, nx))
                   for sh, d in list(zip(shots, data))[:plain_shots]]
@@ -462,6 +470,12 @@ def _ensemble(args, R, nt, plain_shots):
         "rtms": n_img, "seconds": el, "rtm_seconds": t_rtm,
         "updates_per_s": updates / el, "images_per_s": n_img / el, "realization_images_per_s": R / el,
         "failed_jobs": failed, "tile_z": s1.tile_z, "path": "served engine, all jobs at t=0",
+        # the jobs' algorithmic bytes (per-update minimum) over the wall time of
+        # the served phase, submit to drain: a lower bound on the step kernels'
+        # own rate, gaps between launches included
+        "served_roofline": {"bound": "hbm", "achieved": alg / t_rtm / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": alg / t_rtm / 1e9 / HBM_PEAK_GBS,
+                            "alg_bytes": alg, "seconds": t_rtm},
         "plain": plain, "batched_vs_plain": (n_img / el) / plain["images_per_s"] if plain else None,
         "std_map": {"max": float(std.max()), "mean": float(std.mean())},
     }
