@@ -40,8 +40,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the step kernels' code; the launch configuration they were counted in (tile
+# height, shot groups) is checked against the counter record separately
 STEP_SOURCES = ("paper_2001_06444_amd/csrc/rtm_kernels.hip", "paper_2001_06444_amd/csrc/rtm_device.h",
-                "paper_2001_06444_amd/csrc/rtm_internal.h", "paper_2001_06444_amd/csrc/rtm_runtime.hip")
+                "paper_2001_06444_amd/csrc/rtm_internal.h")
 CODEC_SOURCES = ("paper_2001_06444_amd/csrc/rtm_codec.hip", "paper_2001_06444_amd/csrc/rtm_codec.h")
 
 
