@@ -87,26 +87,38 @@ struct BitSink {
   }
 };
 
-// Reads bits from a chunk's word range; reading past it raises `bad`.
+// Reads bits from a chunk's word range.  The window holds at least 32 bits,
+// zeros past the range; consuming any of those raises `bad`.
 struct BitSource {
   const uint32_t* in;
   int64_t nwords, next = 0;
   uint64_t acc = 0;
-  int nacc = 0;
+  int nacc = 0;   // bits in the window
+  int nreal = 0;  // of which inside the range
   bool bad = false;
   __device__ BitSource(const uint32_t* p, int64_t n) : in(p), nwords(n) {}
-  __device__ __forceinline__ uint32_t get(int n) {  // n <= 32
-    if (nacc < n) {
+  __device__ __forceinline__ uint32_t peek() {  // the next 32 bits
+    if (nacc < 32) {
       uint64_t w = 0;
-      if (next < nwords) w = in[next];
-      else bad = true;
+      if (next < nwords) {
+        w = in[next];
+        nreal += 32;
+      }
       ++next;
       acc |= w << nacc;
       nacc += 32;
     }
-    const uint32_t v = (uint32_t)(acc & ((n == 32) ? 0xFFFFFFFFull : ((1ull << n) - 1)));
+    return (uint32_t)acc;
+  }
+  __device__ __forceinline__ void skip(int n) {  // n <= 32, after peek()
+    if (n > nreal) bad = true;
+    nreal = max(nreal - n, 0);
     acc >>= n;
     nacc -= n;
+  }
+  __device__ __forceinline__ uint32_t get(int n) {  // n <= 32
+    const uint32_t v = peek() & (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u));
+    skip(n);
     return v;
   }
 };
@@ -169,20 +181,78 @@ __device__ bool encode_block(const float (&x)[16], int minexp, BitSink& bs) {
     if (n > 0) bs.put(plane & ((1u << n) - 1u), n);  // coefficients already significant
     uint32_t rest = plane >> n;
     while (n < 16) {
-      bs.put(rest != 0, 1);  // group test
-      if (!rest) break;
+      if (!rest) {
+        bs.put(0, 1);  // group test: no further coefficient turns significant
+        break;
+      }
       const int p = __builtin_ctz(rest);
-      if (n + p == 15) {  // zeros up to the last coefficient, whose 1 is implied
-        bs.put(0, 15 - n);
+      if (n + p == 15) {  // test, then zeros up to the last coefficient, whose 1 is implied
+        bs.put(1, 16 - n);
         n = 16;
         break;
       }
-      bs.put(1u << p, p + 1);  // p zeros, then the 1
+      bs.put(1u | (1u << (p + 1)), p + 2);  // test, p zeros, then the 1
       n += p + 1;
       rest >>= p + 1;
     }
   }
   return true;
+}
+
+// Bits encode_block emits for a block (the same steps, no stream): per bit
+// plane the verbatim bits of the significant coefficients, then one group
+// test per coefficient that turns significant plus the run up to it, and a
+// closing test unless the last coefficient was reached (its 1 implied).
+__device__ int count_block(const float (&x)[16], int minexp, bool& ok) {
+  float m = 0.0f;
+  bool fin = true;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const float a = fabsf(x[c]);
+    fin = fin && (a < 0x1p100f);
+    m = fmaxf(m, a);
+  }
+  if (!fin) {
+    ok = false;
+    return 0;
+  }
+  if (m == 0.0f) return 1;
+  int e;
+  (void)frexpf(m, &e);
+  const int maxprec = min(32, max(0, e - minexp + 6));
+  if (maxprec == 0) return 1;
+  int32_t q[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) q[c] = (int32_t)ldexpf(x[c], 30 - e);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fwd_lift(q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fwd_lift(q[j], q[4 + j], q[8 + j], q[12 + j]);
+  uint32_t u[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) u[c] = ((uint32_t)q[kSeq[c]] + kNb) ^ kNb;
+  const int kmin = 32 - maxprec;
+  int bits = 9, n = 0;
+  for (int k = 31; k >= kmin; --k) {
+    if (n == 16) {  // every coefficient significant: verbatim planes from here on
+      bits += 16 * (k - kmin + 1);
+      break;
+    }
+    uint32_t plane = 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) plane |= ((u[c] >> k) & 1u) << c;
+    const uint32_t rest = plane >> n;
+    bits += n;
+    if (!rest) {
+      bits += 1;
+      continue;
+    }
+    const int ones = __builtin_popcount(rest);
+    const int nf = n + 32 - __builtin_clz(rest);  // one past the highest new significant coefficient
+    bits += nf == 16 ? ones + 15 - n : ones + nf - n + 1;
+    n = nf;
+  }
+  return bits;
 }
 
 // Inverse of encode_block.
@@ -203,18 +273,23 @@ __device__ void decode_block(BitSource& src, int minexp, float (&x)[16]) {
   for (int k = 31; k >= kmin && !src.bad; --k) {
     uint32_t plane = n > 0 ? src.get(n) : 0u;
     while (n < 16) {
-      if (src.get(1) == 0) break;
-      for (;;) {
-        if (n == 15) {
-          plane |= 1u << 15;
-          n = 16;
-          break;
-        }
-        const uint32_t b = src.get(1);
-        plane |= b << n;
-        ++n;
-        if (b) break;
+      uint32_t w = src.peek();
+      if (!(w & 1u)) {  // group test 0: no further coefficient turns significant
+        src.skip(1);
+        break;
       }
+      w >>= 1;  // after the test: zeros, then the 1 of the next significant coefficient
+      const int lim = 15 - n;  // zeros before the last coefficient, whose 1 is implied
+      const int p = w ? __builtin_ctz(w) : 32;
+      if (p >= lim) {
+        src.skip(1 + lim);
+        plane |= 1u << 15;
+        n = 16;
+        break;
+      }
+      src.skip(2 + p);
+      plane |= 1u << (n + p);
+      n += p + 1;
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c) u[c] |= ((plane >> c) & 1u) << k;
@@ -235,16 +310,15 @@ __device__ void decode_block(BitSource& src, int minexp, float (&x)[16]) {
 __global__ __launch_bounds__(kZfThreads) void k_zf_count(ZfParams p, uint32_t* counts) {
   const int64_t ch = (int64_t)blockIdx.x * kZfThreads + threadIdx.x;
   if (ch >= p.nchunks) return;
-  BitSink bs(nullptr, 0);
   bool ok = true;
+  int64_t bits = 0;
   const int64_t b1 = min((ch + 1) * kZfChunk, (int64_t)p.nblocks);
   for (int64_t b = ch * kZfChunk; b < b1; ++b) {
     float x[16];
     load_block(p, b, x);
-    ok = encode_block(x, p.minexp, bs) && ok;
+    bits += count_block(x, p.minexp, ok);
   }
-  bs.flush();
-  counts[ch] = (uint32_t)bs.words;
+  counts[ch] = (uint32_t)((bits + 31) >> 5);  // the words the encoder writes
   if (!ok) atomicOr(p.flags, kZfRange);
 }
 
