@@ -9,8 +9,8 @@ namespace rtm {
 
 constexpr uint32_t kZfMagic = 0x465A5452;  // "RTZF"
 constexpr int kZfMode = 2;                 // the stream's mode word (RTM_CODEC_ZFP)
-constexpr int kZfChunk = 16;               // 4 x 4 blocks per chunk (one thread each)
-constexpr int kZfThreads = 64;             // chunks per workgroup of the coding kernels
+constexpr int kZfChunk = 16;               // 4 x 4 blocks per chunk
+constexpr int kZfThreads = 64;             // lanes (encoder: blocks; decoder: chunks) per workgroup
 constexpr int kZfScan = 256;               // threads of the scan kernels
 constexpr int kZfHeaderWords = 8;
 constexpr int64_t kZfMaxBlocks = int64_t(1) << 27;  // keeps payload word offsets below 2^32
@@ -18,6 +18,8 @@ constexpr int64_t kZfMaxBlocks = int64_t(1) << 27;  // keeps payload word offset
 // over 32 planes, at most 32 failed and 16 successful group tests and 16
 // scan bits: 585 bits.
 constexpr int kZfMaxBlockBits = 585;
+constexpr int kZfBlockWords = (kZfMaxBlockBits + 31) / 32;              // 19
+constexpr int kZfChunkWords = (kZfChunk * kZfMaxBlockBits + 31) / 32;   // 293
 
 // error bits the kernels raise in ZfParams::flags
 constexpr uint32_t kZfRange = 1u;    // a value is non-finite or |x| >= 2^100

@@ -59,34 +59,6 @@ __device__ __forceinline__ void inv_lift(int32_t& a0, int32_t& a1, int32_t& a2, 
   a3 += a0; a0 = (int32_t)((uint32_t)a0 << 1); a0 -= a3;
 }
 
-// Appends bits to a word stream (out == nullptr: count only).
-struct BitSink {
-  uint32_t* out;
-  int64_t limit;  // words that may be written
-  uint64_t acc = 0;
-  int nacc = 0;
-  int64_t words = 0;
-  __device__ BitSink(uint32_t* o, int64_t lim) : out(o), limit(lim) {}
-  __device__ __forceinline__ void put(uint32_t v, int n) {  // n <= 32, v < 2^n
-    acc |= (uint64_t)v << nacc;
-    nacc += n;
-    if (nacc >= 32) {
-      if (out && words < limit) out[words] = (uint32_t)acc;
-      ++words;
-      acc >>= 32;
-      nacc -= 32;
-    }
-  }
-  __device__ __forceinline__ void flush() {
-    if (nacc > 0) {
-      if (out && words < limit) out[words] = (uint32_t)acc;
-      ++words;
-      acc = 0;
-      nacc = 0;
-    }
-  }
-};
-
 // Reads bits from a chunk's word range.  The window holds at least 32 bits,
 // zeros past the range; consuming any of those raises `bad`.
 struct BitSource {
@@ -96,15 +68,17 @@ struct BitSource {
   int nacc = 0;   // bits in the window
   int nreal = 0;  // of which inside the range
   bool bad = false;
-  __device__ BitSource(const uint32_t* p, int64_t n) : in(p), nwords(n) {}
+  uint32_t ahead;  // word `next`, loaded one refill early so that its latency overlaps decoding
+  __device__ BitSource(const uint32_t* p, int64_t n) : in(p), nwords(n), ahead(n > 0 ? p[0] : 0u) {}
   __device__ __forceinline__ uint32_t peek() {  // the next 32 bits
     if (nacc < 32) {
       uint64_t w = 0;
       if (next < nwords) {
-        w = in[next];
+        w = ahead;
         nreal += 32;
       }
       ++next;
+      ahead = next < nwords ? in[next] : 0u;
       acc |= w << nacc;
       nacc += 32;
     }
@@ -139,7 +113,8 @@ __device__ __forceinline__ void load_block(const ZfParams& p, int64_t b, float (
 }
 
 // Steps 1-6 for one block; false if a value is non-finite or |x| >= 2^100.
-__device__ bool encode_block(const float (&x)[16], int minexp, BitSink& bs) {
+template <class Sink>
+__device__ bool encode_block(const float (&x)[16], int minexp, Sink& bs) {
   float m = 0.0f;
   bool ok = true;
 #pragma unroll
@@ -306,19 +281,23 @@ __device__ void decode_block(BitSource& src, int minexp, float (&x)[16]) {
   for (int c = 0; c < 16; ++c) x[c] = (float)q[c] * scale;
 }
 
-// Pass 1: payload words of every chunk -> counts[chunk].
+// Pass 1: payload words of every chunk -> counts[chunk].  One lane per
+// block: the 64 lanes of a workgroup read 64 neighbouring blocks (row by
+// row, 1 KB contiguous), and each 16-lane group sums the bits of one chunk.
 __global__ __launch_bounds__(kZfThreads) void k_zf_count(ZfParams p, uint32_t* counts) {
-  const int64_t ch = (int64_t)blockIdx.x * kZfThreads + threadIdx.x;
-  if (ch >= p.nchunks) return;
+  const int lane = threadIdx.x;
+  const int64_t b = (int64_t)blockIdx.x * kZfThreads + lane;
   bool ok = true;
-  int64_t bits = 0;
-  const int64_t b1 = min((ch + 1) * kZfChunk, (int64_t)p.nblocks);
-  for (int64_t b = ch * kZfChunk; b < b1; ++b) {
+  int bits = 0;
+  if (b < p.nblocks) {
     float x[16];
     load_block(p, b, x);
-    bits += count_block(x, p.minexp, ok);
+    bits = count_block(x, p.minexp, ok);
   }
-  counts[ch] = (uint32_t)((bits + 31) >> 5);  // the words the encoder writes
+#pragma unroll
+  for (int d = kZfChunk / 2; d > 0; d >>= 1) bits += __shfl_xor(bits, d, kZfChunk);
+  const int64_t ch = b / kZfChunk;
+  if ((lane & (kZfChunk - 1)) == 0 && ch < p.nchunks) counts[ch] = (uint32_t)((bits + 31) >> 5);  // words written
   if (!ok) atomicOr(p.flags, kZfRange);
 }
 
@@ -383,25 +362,78 @@ __global__ __launch_bounds__(kZfScan) void k_zf_scan_table(const uint32_t* count
   }
 }
 
-// Pass 2: the block codes of every chunk at its table offset.
+// Appends bits to a lane's own LDS words (at most kZfBlockWords).
+struct LdsSink {
+  uint32_t* out;
+  uint64_t acc = 0;
+  int nacc = 0, words = 0, bits = 0;
+  __device__ explicit LdsSink(uint32_t* o) : out(o) {}
+  __device__ __forceinline__ void put(uint32_t v, int n) {  // n <= 32, v < 2^n
+    acc |= (uint64_t)v << nacc;
+    nacc += n;
+    bits += n;
+    if (nacc >= 32) {
+      out[words++] = (uint32_t)acc;
+      acc >>= 32;
+      nacc -= 32;
+    }
+  }
+  __device__ __forceinline__ void flush() {
+    if (nacc > 0) out[words++] = (uint32_t)acc;
+  }
+};
+
+// Pass 2: the block codes of every chunk at its table offset.  One lane per
+// block: each lane codes its block into its own LDS words; a 16-lane prefix
+// sum of the block lengths places the codes in their chunk, which is
+// assembled in LDS and copied to the stream.  The words equal those of one
+// thread writing the chunk's blocks in order.
 __global__ __launch_bounds__(kZfThreads) void k_zf_encode(ZfParams p) {
-  const int64_t ch = (int64_t)blockIdx.x * kZfThreads + threadIdx.x;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  constexpr int kChunks = kZfThreads / kZfChunk;  // chunks per workgroup
+  __shared__ uint32_t own[kZfThreads * kZfBlockWords];
+  __shared__ uint32_t cbuf[kChunks * kZfChunkWords];
+  const int lane = threadIdx.x;
+  const int64_t b = (int64_t)blockIdx.x * kZfThreads + lane;
+  if (blockIdx.x == 0 && lane == 0) {
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if (k < p.cap_words) p.out[k] = p.head[k];
   }
-  if (ch >= p.nchunks) return;
-  const int64_t off = p.pay_base + (int64_t)p.out[p.hdr_base + ch];  // written by the scan
-  const int64_t room = p.cap_words - off;
-  BitSink bs(p.out + off, room > 0 ? room : 0);
-  const int64_t b1 = min((ch + 1) * kZfChunk, (int64_t)p.nblocks);
-  for (int64_t b = ch * kZfChunk; b < b1; ++b) {
+  for (int i = lane; i < kChunks * kZfChunkWords; i += kZfThreads) cbuf[i] = 0u;
+  LdsSink sink(own + lane * kZfBlockWords);
+  if (b < p.nblocks) {
     float x[16];
     load_block(p, b, x);
-    (void)encode_block(x, p.minexp, bs);
+    (void)encode_block(x, p.minexp, sink);
+    sink.flush();
   }
-  bs.flush();
+  // bit offset of this block in its chunk: exclusive prefix over the 16 lanes
+  const int g = lane & (kZfChunk - 1);
+  int pre = sink.bits;
+#pragma unroll
+  for (int d = 1; d < kZfChunk; d <<= 1) {
+    const int t = __shfl_up(pre, d, kZfChunk);
+    if (g >= d) pre += t;
+  }
+  pre -= sink.bits;
+  __syncthreads();  // chunk buffers zeroed, own words written
+  uint32_t* cb = cbuf + (lane / kZfChunk) * kZfChunkWords;
+  const int w0 = pre >> 5, sh = pre & 31;
+  for (int i = 0; i < sink.words; ++i) {
+    const uint32_t v = own[lane * kZfBlockWords + i];
+    atomicOr(&cb[w0 + i], v << sh);
+    if (sh && (v >> (32 - sh))) atomicOr(&cb[w0 + i + 1], v >> (32 - sh));
+  }
+  __syncthreads();
+  const uint32_t* table = p.out + p.hdr_base;  // written by the scan
+  for (int i = lane; i < kChunks * kZfChunkWords; i += kZfThreads) {
+    const int c = i / kZfChunkWords, w = i - c * kZfChunkWords;
+    const int64_t ch = (int64_t)blockIdx.x * kChunks + c;
+    if (ch >= p.nchunks) continue;
+    const int64_t off = table[ch], nw = (int64_t)table[ch + 1] - off;
+    const int64_t at = p.pay_base + off + w;
+    if (w < nw && at < p.cap_words) p.out[at] = cbuf[i];
+  }
 }
 
 // Decoder: one thread per chunk, reading only its table range.
@@ -441,13 +473,13 @@ __global__ __launch_bounds__(kZfThreads) void k_zf_decode(ZfParams p) {
 
 hipError_t launch_zf_encode(const ZfParams& p, uint32_t* counts, uint64_t* totals, hipStream_t s) {
   if (p.nchunks < 1) return hipErrorInvalidValue;
-  const int64_t g = (p.nchunks + kZfThreads - 1) / kZfThreads;
-  k_zf_count<<<(unsigned)g, kZfThreads, 0, s>>>(p, counts);
+  const int64_t gb = (p.nblocks + kZfThreads - 1) / kZfThreads;  // one lane per block
+  k_zf_count<<<(unsigned)gb, kZfThreads, 0, s>>>(p, counts);
   const int64_t ng = (p.nchunks + kZfScan - 1) / kZfScan;
   k_zf_scan_totals<<<(unsigned)ng, kZfScan, 0, s>>>(counts, p.nchunks, totals);
   k_zf_scan_base<<<1, kZfScan, 0, s>>>(totals, ng);
   k_zf_scan_table<<<(unsigned)ng, kZfScan, 0, s>>>(counts, p.nchunks, totals, p);
-  k_zf_encode<<<(unsigned)g, kZfThreads, 0, s>>>(p);
+  k_zf_encode<<<(unsigned)gb, kZfThreads, 0, s>>>(p);
   return hipGetLastError();
 }
 
