@@ -1052,12 +1052,13 @@ static void autotune_tz2(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const f
       }
     }
   // 24 rows (the best on the survey) unless another height measured at
-  // least 2 % faster, or 24 rows could not be measured: heights within the
-  // trials' noise do not flip from one tuning to the next
+  // least 5 % faster, or 24 rows could not be measured: heights within the
+  // trials' noise (a few per cent on the survey's shot groups, where 16 and
+  // 24 rows run equally fast) do not flip from one tuning to the next
   int kf = 1, kb = 1;
   for (int c : {0, 2}) {
-    if (bf[c] < (bf[kf] < 1e30f ? 0.98f : 1.0f) * bf[kf]) kf = c;
-    if (bb[c] < (bb[kb] < 1e30f ? 0.98f : 1.0f) * bb[kb]) kb = c;
+    if (bf[c] < (bf[kf] < 1e30f ? 0.95f : 1.0f) * bf[kf]) kf = c;
+    if (bb[c] < (bb[kb] < 1e30f ? 0.95f : 1.0f) * bb[kb]) kb = c;
   }
   *tzf = cand[kf];
   *tzb = cand[kb];
