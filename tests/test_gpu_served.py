@@ -274,6 +274,31 @@ def test_memory_pressure_queues_jobs_and_results_equal_alone(rtm):
             assert np.array_equal(_alone(rtm, ctx, vels[0], j), img), (j["mode"], j["dtype"])
 
 
+def test_running_set_cap_runs_jobs_in_order_and_unchanged(rtm, monkeypatch):
+    """RTM_SERVE_KB caps the field bytes of the jobs in flight; with a cap
+    below one job's share every job runs alone: admitted in submission order,
+    each after the previous one finished, and every image equals its alone
+    run bit for bit."""
+    monkeypatch.setenv("RTM_SERVE_KB", "1")
+    rng = np.random.default_rng(41)
+    vels = _small_models(2)
+    jobs = [_small_job(rng, k % 2, int(rng.integers(80, 160)), int(rng.integers(100, 200)),
+                       ["reconstruct", "store"][k % 2], ["fp32", "bf16"][k % 2], 2)
+            for k in range(5)]
+    with rtm.Context(0, arena_bytes=1 << 30) as ctx:
+        g = rtm.make_grid(SZ, SX, SB, 100, H, H, DT)
+        for r, v in enumerate(vels):
+            ctx.model_register(r, dev(v), g)
+        keep = []
+        tickets = [_submit(rtm, ctx, j, keep) for j in jobs]
+        ctx.drain()
+        infos, images = _collect(rtm, ctx, tickets, jobs)
+        for a, b in zip(infos, infos[1:]):
+            assert a.t_admit < b.t_admit and b.t_admit >= a.t_done, (a.t_admit, a.t_done, b.t_admit)
+        for j, img in zip(jobs, images):
+            assert np.array_equal(_alone(rtm, ctx, vels[j["r"]], j), img), (j["mode"], j["dtype"])
+
+
 def test_job_log_records_every_job(rtm, tmp_path, monkeypatch):
     """RTM_LOG names a file that receives one JSON line per job reaching a
     final state: done jobs with ordered timestamps, their updates, bytes and
