@@ -200,7 +200,7 @@ typedef struct {
 
 /* Migrate nshots shots of one model together (Sec. 3, Stage 2: the shots of
  * one velocity model): the shots advance in shared kernel launches, two time
- * steps per launch in reconstruct mode without illumination (two-step tile
+ * steps per launch in reconstruct and store mode without illumination (two-step tile
  * heights from the autotuner per phase; RTM_TILE_Z2 = 16, 24 or 32 forces a
  * height, 0 keeps one step per launch; results are the same bit for bit;
  * rtm_ctx_stats reports the heights used), launches are replayed from a

@@ -45,7 +45,7 @@ struct alignas(16) DevJob {
   int32_t src_z, src_x, nrec, ring_len;            // padded source node; receivers; ring size
   int32_t start_tick, tiles_x, tiles_z, tiles_x2;  // first global tick; tile grid; two-step tile columns
   float inv_cell, c0, kfac;        // 1/(dx dz); a0 (1/dz^2 + 1/dx^2); imaging weight k
-  int32_t two_step;                // served job whose pairable steps run in two-step launches
+  int32_t two_step;                // job whose pairable steps run in two-step launches
   float cz[4], cx[4];              // a_k / dz^2, a_k / dx^2, k = 1..4
   const float* c;                  // v^2 dt^2, padded grid (field layout)
   const float* gz;                 // sponge profile per padded row [nzp]
@@ -87,17 +87,21 @@ struct alignas(16) StepCtl {
   int32_t pad_;
 };
 
-// Does a two-step launch advance a reconstruct-mode job from its step s
-// (s even for the jobs that take two-step launches) through s + 1?  Forward
-// steps s and s + 1 both before the backward phase, or backward levels
-// m = nt - 1 - (s - nf) and m - 1 with 1 <= m <= nt - 3 (levels nt - 1 and
-// nt - 2 are imaged without reconstruction, and a last single level runs
-// alone).  The one-step launches of the serving engine skip exactly these
-// steps of a job marked two_step; the two-step kernel takes exactly these.
-__host__ __device__ inline bool two_step_pair(int s, int nt, int nsteps) {
+// Does a two-step launch advance a reconstruct- or store-mode job from its
+// step s (s even for the jobs that take two-step launches) through s + 1?
+// Forward steps s and s + 1 both before the backward phase, or backward
+// levels m = nt - 1 - (s - nf) and m - 1 with 1 <= m <= nt - 3 (levels
+// nt - 1 and nt - 2 are imaged without reconstruction, and a last single
+// level runs alone).  A store-mode job also keeps its last forward level
+// nt - 2 out of a pair's first step: the snapshot of that level is written
+// by the launch after the one that computes it (its 16-bit scale needs the
+// whole level's maximum), and no forward launch follows.  The one-step
+// launches of the serving engine skip exactly these steps of a job marked
+// two_step; the two-step kernel takes exactly these.
+__host__ __device__ inline bool two_step_pair(int s, int nt, int nsteps, int mode) {
   const int nf = nt - 1;
   if (s < 0 || s + 1 >= nsteps) return false;
-  if (s + 1 < nf) return true;
+  if (s + 1 < nf) return mode != kModeStore || s + 2 < nf;
   if (s < nf) return false;
   const int m = nt - 1 - (s - nf);
   return m <= nt - 3 && m >= 1;
@@ -116,7 +120,8 @@ inline int32_t ring_len_of(int nz, int nx) { return 8 * (nz + nx - 8); }
 hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,
                        int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
                        hipStream_t s, int skip_pairs = 0);
-hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, const int2* recs2,
+// store: the launch covers store-mode jobs (else reconstruct-mode jobs)
+hipError_t launch_step2(int tz, int phases, int store, const DevJob* jobs, const Tile* tiles, const int2* recs2,
                         int ntiles, int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
                         hipStream_t s);
 hipError_t launch_advance(StepCtl* ctl, int k, hipStream_t s);

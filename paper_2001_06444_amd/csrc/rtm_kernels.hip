@@ -211,6 +211,27 @@ struct StepSmem {
   float red[4];
 };
 
+// Snapshot of level lev (a multiple of the stride) at physical row pz, padded
+// column x: FP32, or 16-bit after scaling by sc.
+__device__ __forceinline__ void store_snap(const DevJob& J, int lev, int pz, int x, float u, float sc) {
+  const int64_t off = ((int64_t)(lev / J.snap_stride) * J.nz + pz) * J.pitch + x;
+  if (J.snap_dtype == 0)
+    st_stream(gp(reinterpret_cast<float*>(J.snap)) + off, u);
+  else if (J.snap_dtype == 1)
+    st_stream(gp(reinterpret_cast<uint16_t*>(J.snap)) + off, bf16_rne(u * sc));
+  else
+    st_stream(gp(reinterpret_cast<uint16_t*>(J.snap)) + off, fp16_rne(u * sc));
+}
+
+// Snapshot of level lev at physical row pz, padded column x, as a float
+// (16-bit codes multiplied by dsc).
+__device__ __forceinline__ float load_snap(const DevJob& J, int lev, int pz, int x, float dsc) {
+  const int64_t off = ((int64_t)(lev / J.snap_stride) * J.nz + pz) * J.pitch + x;
+  if (J.snap_dtype == 0) return ld_stream(gp(reinterpret_cast<const float*>(J.snap)) + off) * dsc;
+  const uint16_t q = ld_stream(gp(reinterpret_cast<const uint16_t*>(J.snap)) + off);
+  return (J.snap_dtype == 1 ? bf16_to_f32(q) : fp16_to_f32(q)) * dsc;
+}
+
 template <int TZ, class Smem>
 __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, int n, Smem& sm) {
   constexpr int RZ = TZ / 4;
@@ -246,12 +267,19 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
   const float wsrc = gp(J.wavelet)[n] * J.inv_cell;
   const int mode = J.mode;
   const bool snap_now = mode == kModeStore && (n % J.snap_stride) == 0;
+  // u^{n-1}, when a two-step launch computed it as its first step: that
+  // launch could not scale it (its maximum was not complete), so the launch
+  // after it stores it
+  const bool snap_prev = mode == kModeStore && J.two_step && (n & 1) == 0 && n >= 2 &&
+                         ((n - 1) % J.snap_stride) == 0 && two_step_pair(n - 2, J.nt, J.nsteps, mode);
   const bool want_max = mode == kModeStore && J.snap_dtype != 0 && ((n + 1) % J.snap_stride) == 0 &&
                         (n + 1) <= J.nt - 2;
   // per-snapshot scale from the max-abs of u^n, kept as kMaxSlots partial maxima
-  float sc = 1.0f;
+  float sc = 1.0f, scp = 1.0f;
   if (snap_now && J.snap_dtype != 0)
     sc = snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)n * kMaxSlots + lane])));
+  if (snap_prev && J.snap_dtype != 0)
+    scp = snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)(n - 1) * kMaxSlots + lane])));
   st.store(sm.a);
   __syncthreads();
 
@@ -287,15 +315,8 @@ __device__ __forceinline__ void forward_tile(const DevJob& J, const Tile& tl, in
           int slot = ring_slot(pz, px, J.nz, J.nx);
           if (slot >= 0) st_stream(gp(J.ring) + (int64_t)(n + 1) * J.ring_len + slot, un);
         } else {
-          if (snap_now) {
-            const int64_t off = ((int64_t)(n / J.snap_stride) * J.nz + pz) * pitch + x;
-            if (J.snap_dtype == 0)
-              st_stream(gp(reinterpret_cast<float*>(J.snap)) + off, u);
-            else if (J.snap_dtype == 1)
-              st_stream(gp(reinterpret_cast<uint16_t*>(J.snap)) + off, bf16_rne(u * sc));
-            else
-              st_stream(gp(reinterpret_cast<uint16_t*>(J.snap)) + off, fp16_rne(u * sc));
-          }
+          if (snap_now) store_snap(J, n, pz, x, u, sc);
+          if (snap_prev) store_snap(J, n - 1, pz, x, pv[k], scp);
           vmax = fmaxf(vmax, fabsf(un));
         }
       }
@@ -572,7 +593,7 @@ __device__ __forceinline__ void born_tile(const DevJob& J, const Tile& tl, int n
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per launch (reconstruct mode).  A two-step tile owns output
+// Two time steps per launch (reconstruct and store mode).  A two-step tile owns output
 // rows [z0, z0 + TZ) and columns [x0, x0 + 56).  Its first step covers the
 // middle region, the tile grown by the stencil radius (rows z0 - 4 ..
 // z0 + TZ + 4, columns x0 - 4 .. x0 + 60: one column per lane), from inputs
@@ -632,6 +653,7 @@ struct Step2Smem {
   float b[kBwd ? (TZ + 4 * kHalo) * kLdsW : 4];   // S^{m+1}
   float ma[(TZ + 2 * kHalo) * kTileX];            // middle region: u^{n+1} or R^m
   float mb[kBwd ? (TZ + 2 * kHalo) * kTileX : 4]; // middle region: S^m
+  float red[4];                                   // workgroup max (store mode)
 };
 
 // Boundary-ring save of a forward value at level `lev` (reconstruct mode).
@@ -648,7 +670,7 @@ __device__ __forceinline__ void ring_save(const DevJob& J, int z, int x, int lev
 // zero, a source term or a ring save and the per-node tests drop out; the
 // other tiles take the general path.  Offsets are 32-bit (a field holds
 // fewer than 2^30 floats).
-template <int TZ, bool kFast, class Smem>
+template <int TZ, bool kFast, bool kStore, class Smem>
 __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, int n, Smem& sm) {
   constexpr int RA = (TZ + 2 * kHalo) / 4;  // middle rows per wavefront (first step)
   constexpr int RB = TZ / 4;                // output rows per wavefront (second step)
@@ -690,6 +712,23 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
   const float gxv = (kFast || xin) ? gx[xcl] : 0.0f;
   const float w0 = kFast ? 0.0f : gp(J.wavelet)[n] * J.inv_cell;
   const float w1 = kFast ? 0.0f : gp(J.wavelet)[n + 1] * J.inv_cell;
+  // store mode: snapshots of the levels this launch reads (u^n; u^{n-1} when
+  // the previous two-step launch computed it), each with the scale of its
+  // complete maximum, and the partial maxima of the levels it computes
+  constexpr bool store = kStore && !kFast;
+  const int stride = J.snap_stride;
+  const bool snap0 = store && (n % stride) == 0;
+  const bool snapp = store && n >= 2 && ((n - 1) % stride) == 0 && two_step_pair(n - 2, J.nt, J.nsteps, J.mode);
+  const bool want1 = store && J.snap_dtype != 0 && ((n + 1) % stride) == 0 && n + 1 <= J.nt - 2;
+  const bool want2 = store && J.snap_dtype != 0 && ((n + 2) % stride) == 0 && n + 2 <= J.nt - 2;
+  float sc0 = 1.0f, scp = 1.0f;
+  if (snap0 && J.snap_dtype != 0)
+    sc0 = snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)n * kMaxSlots + lane])));
+  if (snapp && J.snap_dtype != 0)
+    scp = snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)(n - 1) * kMaxSlots + lane])));
+  const int px = x - J.nb;
+  const bool colphys = px >= 0 && px < J.nx;
+  float vmax1 = 0.0f, vmax2 = 0.0f;
   st.store(sm.a);
   __syncthreads();
 
@@ -713,7 +752,16 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
     sm.ma[r * kTileX + lane] = un;
     if (r >= kHalo && r < TZ + kHalo && (kFast || z < J.nzp) && xout) {  // a node of the output tile
       st_cached(at(u1, (uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
-      if (!kFast) ring_save(J, z, x, n + 1, un);
+      if (store) {
+        const int pz = z - J.nb;
+        if (colphys && pz >= 0 && pz < J.nz) {
+          if (snap0) store_snap(J, n, pz, x, zw[k + 4], sc0);
+          if (snapp) store_snap(J, n - 1, pz, x, pva[k], scp);
+          vmax1 = fmaxf(vmax1, fabsf(un));
+        }
+      } else if (!kFast) {
+        ring_save(J, z, x, n + 1, un);
+      }
     }
   }
   __syncthreads();
@@ -732,13 +780,31 @@ __device__ __forceinline__ void forward2_body(const DevJob& J, const Tile& tl, i
     if (xout && (kFast || z < J.nzp)) {
       const float un = leapfrog(G, cvb[k], lap, zm[k + 4], uold);
       st_cached(at(u2, (uint32_t)z * (uint32_t)pitch + (uint32_t)x), un);
-      if (!kFast) ring_save(J, z, x, n + 2, un);
+      if (store) {
+        const int pz = z - J.nb;
+        if (colphys && pz >= 0 && pz < J.nz) vmax2 = fmaxf(vmax2, fabsf(un));
+      } else if (!kFast) {
+        ring_save(J, z, x, n + 2, un);
+      }
+    }
+  }
+  if (want1 || want2) {  // wavefront-uniform: the whole workgroup takes this branch
+    const int slot = ((tl.z0 / TZ) * J.tiles_x2 + tl.x0 / kTileX2) & (kMaxSlots - 1);
+    if (want1) wg_atomic_max(vmax1, &J.maxbits[(int64_t)(n + 1) * kMaxSlots + slot], sm.red);
+    if (want2) {
+      __syncthreads();  // sm.red is reused
+      wg_atomic_max(vmax2, &J.maxbits[(int64_t)(n + 2) * kMaxSlots + slot], sm.red);
     }
   }
 }
 
-template <int TZ, class Smem>
+// kStore: store-mode jobs (general path, snapshots); else reconstruct mode.
+template <int TZ, bool kStore, class Smem>
 __device__ __forceinline__ void forward2_tile(const DevJob& J, const Tile& tl, int n, Smem& sm) {
+  if (kStore) {
+    forward2_body<TZ, false, true>(J, tl, n, sm);
+    return;
+  }
   const int z0 = tl.z0, x0 = tl.x0;
   const bool inside = z0 >= kHalo && z0 + TZ + kHalo <= J.nzp && x0 >= kHalo && x0 + kTileX2 + kHalo <= J.nxp;
   const bool src = J.src_z >= z0 - kHalo && J.src_z < z0 + TZ + kHalo && J.src_x >= x0 - kHalo &&
@@ -748,9 +814,9 @@ __device__ __forceinline__ void forward2_tile(const DevJob& J, const Tile& tl, i
   const bool phys = pz0 < J.nz && pz1 > 0 && px0 < J.nx && px1 > 0;
   const bool interior = pz0 >= 4 && pz1 <= J.nz - 4 && px0 >= 4 && px1 <= J.nx - 4;
   if (inside && !src && !(phys && !interior))
-    forward2_body<TZ, true>(J, tl, n, sm);
+    forward2_body<TZ, true, false>(J, tl, n, sm);
   else
-    forward2_body<TZ, false>(J, tl, n, sm);
+    forward2_body<TZ, false, false>(J, tl, n, sm);
 }
 
 // One two-step backward tile, levels m and m - 1 (reconstruct mode, both
@@ -971,6 +1037,160 @@ __device__ __forceinline__ void backward2_body(const DevJob& J, const Tile& tl, 
   }
 }
 
+// One two-step backward tile of a store-mode job: R^m on the middle region,
+// R^{m-1} on the output tile, and the imaging terms of levels m and m - 1
+// (those on the snapshot stride) with the stored source wavefield, in level
+// order, as two one-step launches apply them.
+template <int TZ, class Smem>
+__device__ __forceinline__ void backward2_store_body(const DevJob& J, const Tile& tl, const int2* __restrict__ recs2,
+                                                     int m, Smem& sm) {
+  constexpr int RA = (TZ + 2 * kHalo) / 4;
+  constexpr int RB = TZ / 4;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
+  const int pitch = J.pitch;
+  const RTM_GLOBAL float* __restrict__ r1 = gp(J.r[(m + 1) & 3]);  // R^{m+1}
+  const RTM_GLOBAL float* __restrict__ r2 = gp(J.r[(m + 2) & 3]);  // R^{m+2}
+  RTM_GLOBAL float* __restrict__ r0 = gp(J.r[m & 3]);              // R^m
+  RTM_GLOBAL float* __restrict__ rn = gp(J.r[(m + 3) & 3]);        // R^{m-1}
+  RTM_GLOBAL float* __restrict__ image = gp(J.image);
+  const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
+  const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
+  const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
+  const int x = tl.x0 - kHalo + lane;
+  const int za0 = tl.z0 - kHalo + w * RA;
+  const int zb0 = tl.z0 + w * RB;
+  const bool xin = x >= 0 && x < J.nxp;
+  const bool xout = lane >= kHalo && lane < kHalo + kTileX2 && x < J.nxp;
+  const uint32_t xcl = (uint32_t)min(max(x, 0), J.nxp - 1);
+  const int px = x - J.nb;
+  const bool colphys = px >= 0 && px < J.nx;
+  const int xph = min(max(x, J.nb), J.nb + J.nx - 1);  // column clamped into the window
+  const int stride = J.snap_stride;
+  const bool tphys = tl.z0 - J.nb < J.nz && tl.z0 + TZ - J.nb > 0 && tl.x0 - J.nb < J.nx &&
+                     tl.x0 + kTileX2 - J.nb > 0;  // the output tile reaches the window
+  const bool img0 = tphys && (m % stride) == 0 && m <= J.nt - 2;              // level m imaged
+  const bool img1 = tphys && ((m - 1) % stride) == 0 && m - 1 <= J.nt - 2;    // level m - 1 imaged
+
+  // ---- every global load first ----
+  TileStageW<TZ + 4 * kHalo> sa;
+  sa.load(r1, pitch, tl.z0 - 2 * kHalo, tl.x0 - 2 * kHalo);
+  float cva[RA], pva[RA], gza[RA];
+#pragma unroll
+  for (int k = 0; k < RA; ++k) {
+    const int zc = min(max(za0 + k, 0), J.nzp - 1);
+    const uint32_t off = (uint32_t)zc * (uint32_t)pitch + xcl;
+    cva[k] = ld_medium(at(cc, off));
+    pva[k] = ld_cached(at(r2, off));
+    gza[k] = gz[zc];
+  }
+  float dsc0 = 1.0f, dsc1 = 1.0f;
+  if (img0 && J.snap_dtype != 0)  // exact: powers of two
+    dsc0 = 1.0f / snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)m * kMaxSlots + lane])));
+  if (img1 && J.snap_dtype != 0)
+    dsc1 = 1.0f / snap_scale_from_max(wave_max(__uint_as_float(gp(J.maxbits)[(int64_t)(m - 1) * kMaxSlots + lane])));
+  float cvb[RB], gzb[RB], ivb[RB], s0b[RB], s1b[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int zc = min(zb0 + k, J.nzp - 1);
+    cvb[k] = ld_medium(at(cc, (uint32_t)zc * (uint32_t)pitch + xcl));
+    gzb[k] = gz[zc];
+    ivb[k] = 0.0f;
+    s0b[k] = 0.0f;
+    s1b[k] = 0.0f;
+  }
+  if (img0 || img1) {
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {  // image and snapshots, at addresses clamped into the window
+      const int pzc = min(max(zb0 + k - J.nb, 0), J.nz - 1);
+      ivb[k] = ld_cached(at(image, (uint32_t)pzc * (uint32_t)pitch + (uint32_t)xph));
+      if (img0) s0b[k] = load_snap(J, m, pzc, xph, dsc0);
+      if (img1) s1b[k] = load_snap(J, m - 1, pzc, xph, dsc1);
+    }
+  }
+  const float gxv = xin ? gx[xcl] : 0.0f;
+  const float kfac = J.kfac;
+  sa.store(sm.a);
+
+  // receiver data of levels m and m - 1, summed into zeroed middle-region
+  // arrays as a one-step launch sums them
+  const bool has_inj = tl.rec_count > 0;
+  float inja[RA], injb[RB];
+#pragma unroll
+  for (int k = 0; k < RA; ++k) inja[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) injb[k] = 0.0f;
+  if (has_inj) {
+    for (int i = threadIdx.x; i < (TZ + 2 * kHalo) * kTileX; i += kThreads) {
+      sm.ma[i] = 0.0f;
+      sm.mb[i] = 0.0f;
+    }
+    __syncthreads();
+    const RTM_GLOBAL float* da = gp(J.data) + (int64_t)m * J.nrec;
+    const RTM_GLOBAL float* db = gp(J.data) + (int64_t)(m - 1) * J.nrec;
+    for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
+      const int2 e = recs2[tl.rec_begin + i];
+      atomicAdd(&sm.ma[e.x], da[e.y]);
+      atomicAdd(&sm.mb[e.x], db[e.y]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RA; ++k) inja[k] = sm.ma[(w * RA + k) * kTileX + lane];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) injb[k] = sm.mb[(w * RB + k + kHalo) * kTileX + lane];
+  }
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
+
+  // ---- first step: R^m on the middle region ----
+  {
+    float zr[RA + 8];
+#pragma unroll
+    for (int j = 0; j < RA + 8; ++j) zr[j] = sm.a[(w * RA + j) * kLdsW + lane + kHalo];
+#pragma clang loop unroll(full)
+    for (int k = 0; k < RA; ++k) {
+      const int r = w * RA + k;
+      const int z = za0 + k;
+      float lap = lap8<RA>(sm.a, r + kHalo, lane + kHalo, zr, k, c0, cz, cx);
+      if (has_inj) lap += inja[k];
+      float rv = leapfrog(gza[k] * gxv, cva[k], lap, zr[k + 4], pva[k]);
+      rv = (xin && z >= 0 && z < J.nzp) ? rv : 0.0f;
+      sm.ma[r * kTileX + lane] = rv;
+      if (r >= kHalo && r < TZ + kHalo && z < J.nzp && xout)  // a node of the output tile
+        st_cached(at(r0, (uint32_t)z * (uint32_t)pitch + (uint32_t)x), rv);
+    }
+  }
+  __syncthreads();
+
+  // ---- second step: R^{m-1} on the output tile, imaging ----
+  {
+    float zr[RB + 8];
+#pragma unroll
+    for (int j = 0; j < RB + 8; ++j) zr[j] = sm.ma[(w * RB + j) * kTileX + lane];
+#pragma clang loop unroll(full)
+    for (int k = 0; k < RB; ++k) {
+      const int z = zb0 + k;
+      float lap = lap8<RB, kTileX>(sm.ma, w * RB + k + kHalo, lane, zr, k, c0, cz, cx);
+      if (has_inj) lap += injb[k];
+      const float rc = sm.a[(w * RB + k + 2 * kHalo) * kLdsW + lane + kHalo];  // R^{m+1}
+      if (xout && z < J.nzp) {
+        const uint32_t off = (uint32_t)z * (uint32_t)pitch + (uint32_t)x;
+        st_cached(at(rn, off), leapfrog(gzb[k] * gxv, cvb[k], lap, zr[k + 4], rc));
+        const int pz = z - J.nb;
+        if ((img0 || img1) && colphys && pz >= 0 && pz < J.nz) {
+          float im = ivb[k];
+          if (img0) im = fmaf(kfac * s0b[k], rc, im);         // level m:     S^m R^{m+1}
+          if (img1) im = fmaf(kfac * s1b[k], zr[k + 4], im);  // level m - 1: S^{m-1} R^m
+          st_cached(at(image, (uint32_t)pz * (uint32_t)pitch + (uint32_t)x), im);
+        }
+      }
+    }
+  }
+}
+
 template <int TZ, class Smem>
 __device__ __forceinline__ void backward2_tile(const DevJob& J, const Tile& tl, const int2* recs2, int m,
                                                Smem& sm) {
@@ -991,7 +1211,9 @@ __device__ __forceinline__ void backward2_tile(const DevJob& J, const Tile& tl, 
     backward2_body<TZ, 0>(J, tl, recs2, m, sm);
 }
 
-template <int TZ, int PH>
+// kStore: a launch over store-mode jobs; else over reconstruct-mode jobs
+// (the two take separate instances, so neither carries the other's code).
+template <int TZ, int PH, bool kStore>
 __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ jobs,
                                                      const Tile* __restrict__ tiles,
                                                      const int2* __restrict__ recs2,
@@ -1019,12 +1241,18 @@ __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ j
   const Tile tl = tiles[t];
   const DevJob& J = jobs[tl.job];
   const int s = tick - J.start_tick;
-  if (J.mode != kModeRecon || J.illum != nullptr || !two_step_pair(s, J.nt, J.nsteps)) return;
+  if (J.mode != (kStore ? kModeStore : kModeRecon) || J.illum != nullptr ||
+      !two_step_pair(s, J.nt, J.nsteps, J.mode))
+    return;
   const int nf = J.nt - 1;  // forward steps
   if (s + 1 < nf) {
-    if (PH & kPhFwd) forward2_tile<TZ>(J, tl, s, sm);
-  } else {
-    if (PH & kPhBwd) backward2_tile<TZ>(J, tl, recs2, J.nt - 1 - (s - nf), sm);  // levels m and m - 1
+    if (PH & kPhFwd) forward2_tile<TZ, kStore>(J, tl, s, sm);
+  } else if (PH & kPhBwd) {
+    const int m = J.nt - 1 - (s - nf);  // levels m and m - 1
+    if (kStore)
+      backward2_store_body<TZ>(J, tl, recs2, m, sm);
+    else
+      backward2_tile<TZ>(J, tl, recs2, m, sm);
   }
 }
 
@@ -1056,7 +1284,7 @@ __global__ __launch_bounds__(kThreads) void k_step(const DevJob* __restrict__ jo
   if (s < 0 || s >= J.nsteps) return;
   // serving engine: a job marked two_step starts at an even tick, and the
   // steps s & ~1, (s & ~1) + 1 that a two-step launch takes are skipped here
-  if (skip_pairs && J.two_step && two_step_pair(s & ~1, J.nt, J.nsteps)) return;
+  if (skip_pairs && J.two_step && two_step_pair(s & ~1, J.nt, J.nsteps, J.mode)) return;
   if (J.mode == kModeBorn) {
     if (PH & kPhBorn) born_tile<TZ>(J, tl, s, sm);
     return;
@@ -1104,23 +1332,29 @@ static hipError_t launch_step_tz(int phases, const DevJob* jobs, const Tile* til
   return hipGetLastError();
 }
 
-hipError_t launch_step2(int tz, int phases, const DevJob* jobs, const Tile* tiles, const int2* recs2,
+hipError_t launch_step2(int tz, int phases, int store, const DevJob* jobs, const Tile* tiles, const int2* recs2,
                         int ntiles, int grid_tiles, const StepCtl* ctl, int use_ctl_tick, int tick_off,
                         hipStream_t s) {
   if (grid_tiles <= 0) return hipSuccess;
   const int per = (grid_tiles + 7) / 8;
   dim3 grid(8 * per), block(kThreads);
-#define RTM_STEP2(T, P) \
-  hipLaunchKernelGGL((k_step2<T, P>), grid, block, 0, s, jobs, tiles, recs2, ctl, ntiles, use_ctl_tick, tick_off)
-  if (tz == 24 && phases == kPhFwd) RTM_STEP2(24, kPhFwd);
-  else if (tz == 24 && phases == kPhBwd) RTM_STEP2(24, kPhBwd);
-  else if (tz == 16 && phases == kPhFwd) RTM_STEP2(16, kPhFwd);
-  else if (tz == 16 && phases == kPhBwd) RTM_STEP2(16, kPhBwd);
-  else if (tz == 32 && phases == kPhFwd) RTM_STEP2(32, kPhFwd);
-  else if (tz == 32 && phases == kPhBwd) RTM_STEP2(32, kPhBwd);
-  else return hipErrorInvalidValue;
+#define RTM_STEP2(T, P, M) \
+  hipLaunchKernelGGL((k_step2<T, P, M>), grid, block, 0, s, jobs, tiles, recs2, ctl, ntiles, use_ctl_tick, tick_off)
+#define RTM_STEP2_TZ(T)                                       \
+  if (tz == T) {                                              \
+    if (phases == kPhFwd && !store) RTM_STEP2(T, kPhFwd, false); \
+    else if (phases == kPhBwd && !store) RTM_STEP2(T, kPhBwd, false); \
+    else if (phases == kPhFwd) RTM_STEP2(T, kPhFwd, true);    \
+    else if (phases == kPhBwd) RTM_STEP2(T, kPhBwd, true);    \
+    else return hipErrorInvalidValue;                         \
+    return hipGetLastError();                                 \
+  }
+  RTM_STEP2_TZ(24)
+  RTM_STEP2_TZ(16)
+  RTM_STEP2_TZ(32)
+#undef RTM_STEP2_TZ
 #undef RTM_STEP2
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_step(int tz, int phases, const DevJob* jobs, const Tile* tiles, int ntiles,

@@ -744,9 +744,20 @@ static int env_tz2() {
 }
 static bool two_step_on() { return env_tz2() != 0; }
 
-// Served reconstruct-mode jobs without illumination advance two steps per
+// Reconstruct- and store-mode jobs without illumination advance two steps per
 // launch where the scheme allows (four buffers per wavefield); the others,
 // and all jobs when RTM_TILE_Z2 = 0, one step per launch.
+static bool pairs_mode(const JobGeom& g) {
+  return (g.mode == kModeRecon || g.mode == kModeStore) && !(g.flags & RTM_IMG_ILLUM);
+}
+// The serving engine pairs reconstruct-mode jobs only.  Its jobs sit in
+// different phases, so a cycle with pairs launches forward pairs, backward
+// pairs and one-step launches for the steps no pair covers; that paid off for
+// the reconstruct-mode ensemble (3.17e11 -> 3.82e11 updates/s) but not for
+// the store-mode stream, whose few small jobs make every launch short
+// (Poisson stream at 20 jobs/s: p50 37 -> 43 ms, saturation 97 -> 77
+// images/s), while the batch path gains on store mode too (100-shot survey,
+// BF16 every 4 steps: 0.60 -> 0.51 s per migration).
 static bool served_two_step(const JobGeom& g) {
   return g.mode == kModeRecon && !(g.flags & RTM_IMG_ILLUM) && two_step_on();
 }
@@ -802,7 +813,7 @@ static void append_two_step_tiles(const HostJob& hj, int job_index, int tz2, std
 }
 
 // tz2f / tz2b > 0 also build the two-step tile tables of the forward and the
-// backward phase (reconstruct-mode jobs only).
+// backward phase (reconstruct- and store-mode jobs without illumination).
 static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, Table& t, int tz2f,
                         int tz2b) {
   t.hjobs = std::make_shared<std::vector<DevJob>>();
@@ -818,7 +829,7 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   t.ntiles = (int)t.htiles->size();
   t.first.push_back(t.ntiles);
   bool pairs = true;
-  for (auto* j : js) pairs = pairs && j->g.mode == kModeRecon && !(j->g.flags & RTM_IMG_ILLUM) && j->g.nbuf == 4;
+  for (auto* j : js) pairs = pairs && pairs_mode(j->g) && j->g.nbuf == 4;
   for (auto [tw, tz2] : {std::make_pair(&t.fw, tz2f), std::make_pair(&t.bw, tz2b)}) {
     if (!pairs || (tz2 != 16 && tz2 != 24 && tz2 != 32)) continue;
     if (!tz2_fits(js, tz2)) tz2 = 16;
@@ -830,6 +841,10 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
     tw->first.push_back(tw->ntiles);
     tw->tz = tz2;
   }
+  // jobs whose forward steps run in pairs (store mode: the launch after a
+  // pair writes the snapshot of the pair's first level)
+  if (t.fw.ntiles > 0)
+    for (DevJob& dj : *t.hjobs) dj.two_step = 1;
   void* p;
   if (!alloc_block(ctx, t.blocks, t.hjobs->size() * sizeof(DevJob), &p)) return fail(RTM_E_NOMEM, "arena exhausted (job table)");
   t.jobs = static_cast<DevJob*>(p);
@@ -984,14 +999,14 @@ static int time_tz2(rtm_ctx* ctx, hipStream_t s, const JobGeom& g0, const float*
     int nfw = 0, nbw = 0;
     for (int st = 0; st + 1 < nf && er == hipSuccess; st += 2) {
       if (st == 4) er = hipEventRecord(e[0], s);
-      if (er == hipSuccess) er = launch_step2(tz2, kPhFwd, t.jobs, t.fw.tiles, t.fw.recs, t.fw.ntiles, t.fw.ntiles, t.ctl, 0, st, s);
+      if (er == hipSuccess) er = launch_step2(tz2, kPhFwd, 0, t.jobs, t.fw.tiles, t.fw.recs, t.fw.ntiles, t.fw.ntiles, t.ctl, 0, st, s);
       nfw += st >= 4;
     }
     if (er == hipSuccess) er = hipEventRecord(e[1], s);
     // backward pairs from level nt - 3 down (steps nf + 2, nf + 4, ..)
     for (int st = nf + 2, k = 0; st + 1 < nsteps && er == hipSuccess; st += 2, ++k) {
       if (k == 2) er = hipEventRecord(e[2], s);
-      if (er == hipSuccess) er = launch_step2(tz2, kPhBwd, t.jobs, t.bw.tiles, t.bw.recs, t.bw.ntiles, t.bw.ntiles, t.ctl, 0, st, s);
+      if (er == hipSuccess) er = launch_step2(tz2, kPhBwd, 0, t.jobs, t.bw.tiles, t.bw.recs, t.bw.ntiles, t.bw.ntiles, t.ctl, 0, st, s);
       nbw += k >= 2;
     }
     if (er == hipSuccess) er = hipEventRecord(e[3], s);
@@ -1389,10 +1404,11 @@ static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, co
                        int K, hipGraphExec_t* graph, bool two_step) {
   const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
   const bool pairs = two_step && tw.ntiles > 0 && (ph == kPhFwd || ph == kPhBwd);
+  const int store = !t.hjobs->empty() && (*t.hjobs)[0].mode == kModeStore;  // one mode per batch
   if (pairs) K = std::max(2, K & ~1);
   auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`
     if (pairs && left >= 2)
-      return launch_step2(tw.tz, ph, t.jobs, tw.tiles, tw.recs, -1, grid[ph == kPhFwd ? 1 : 2], t.ctl, 1, off, s);
+      return launch_step2(tw.tz, ph, store, t.jobs, tw.tiles, tw.recs, -1, grid[ph == kPhFwd ? 1 : 2], t.ctl, 1, off, s);
     return launch_step(tz, ph, t.jobs, t.tiles, -1, grid[0], t.ctl, 1, off, s);
   };
   int done = 0;
@@ -1521,6 +1537,7 @@ static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& 
                             hipGraphExec_t* graph, bool two_step) {
   const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
   const bool pairs = two_step && tw.ntiles > 0;
+  const bool store = !t.hjobs->empty() && (*t.hjobs)[0].mode == kModeStore;  // one mode per batch
   int grid[3] = {0, 0, 0};
   for (auto [a, b] : groups) {
     grid[0] = std::max(grid[0], t.first[b] - t.first[a]);
@@ -1546,6 +1563,17 @@ static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& 
       HIP_OK(launch_advance(t.ctl, 2, s));
       ctx->steps_launched += 2;
       rc = graph_steps(ctx, s, tz, ph, t, grid, nsteps - 2, K, graph, true);
+    } else if (ph == kPhFwd && pairs && store) {
+      // store mode: pairs as long as a forward step follows them (two_step_pair),
+      // then one step per launch
+      const int np = (nsteps - 1) & ~1;
+      rc = graph_steps(ctx, s, tz, ph, t, grid, np, K, graph, true);
+      for (int i = 0; !rc && i < nsteps - np; ++i)
+        HIP_OK(launch_step(tz, kPhFwd, t.jobs, t.tiles, -1, grid[0], t.ctl, 1, i, s));
+      if (!rc && nsteps > np) {
+        HIP_OK(launch_advance(t.ctl, nsteps - np, s));
+        ctx->steps_launched += nsteps - np;
+      }
     } else {
       rc = graph_steps(ctx, s, tz, ph, t, grid, nsteps, K, graph, pairs && ph == kPhFwd);
     }
@@ -1572,7 +1600,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   for (int i = 0; i < nshots; ++i) {
     if ((rc = fill_geom_rtm(grid, shots[i].ix0, shots[i].width, opts, shots[i].nrec, geoms[i]))) return rc;
     if (illum_dev) geoms[i].flags |= RTM_IMG_ILLUM;
-    if (geoms[i].mode == kModeRecon && !illum_dev && two_step_on())
+    if (pairs_mode(geoms[i]) && !illum_dev && two_step_on())
       geoms[i].nbuf = 4;  // two-step launches
     if ((rc = check_job(geoms[i], shots[i].src, shots[i].rec_host))) return rc;
     if (shots[i].nrec > 0 && !shots[i].data_dev) return fail(RTM_E_INVAL, "shot %d has no data", i);
@@ -1845,7 +1873,7 @@ static int ensure_stats(rtm_ctx* ctx, hipStream_t s, Model& m, bool stats, bool 
 static bool has_stats(const Model& m) { return m.mean.p && m.m2.p && m.count.p; }
 
 // Device tables of the serving engine's launches.  A job that takes two-step
-// launches (reconstruct mode without illumination, marked two_step) is in
+// launches (reconstruct or store mode without illumination, marked two_step) is in
 // the forward or backward two-step table for the cycles in which it has a
 // step pair of that phase, and in the one-step table for the cycles in
 // which it has a step that no pair covers (the first backward levels, an odd
@@ -1886,7 +1914,7 @@ static uint8_t cycle_kinds(const DevJob& d, int tick, int K) {
   for (int t = tick; t < tick + K; t += 2) {
     const int s = t - d.start_tick;
     if (s < 0 || s >= d.nsteps) continue;
-    if (two_step_pair(s, d.nt, d.nsteps)) k |= (s + 1 < d.nt - 1) ? 2 : 4;
+    if (two_step_pair(s, d.nt, d.nsteps, d.mode)) k |= (s + 1 < d.nt - 1) ? 2 : 4;
     else k |= 1;
   }
   return k;
@@ -1985,9 +2013,9 @@ static int sched_cycle(rtm_ctx* ctx, SchedTables& T, std::vector<EnsJob*>& activ
         e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, key[0], T.ctl, 1, i, s, 1);
     } else {
       for (int i = 0; i < K && e0 == hipSuccess; i += 2) {
-        if (key[1]) e0 = launch_step2(tzf, kPhFwd, T.jobs, T.tiles_f, T.recs_f, -1, key[1], T.ctl, 1, i, s);
+        if (key[1]) e0 = launch_step2(tzf, kPhFwd, 0, T.jobs, T.tiles_f, T.recs_f, -1, key[1], T.ctl, 1, i, s);
         if (e0 == hipSuccess && key[2])
-          e0 = launch_step2(tzb, kPhBwd, T.jobs, T.tiles_b, T.recs_b, -1, key[2], T.ctl, 1, i, s);
+          e0 = launch_step2(tzb, kPhBwd, 0, T.jobs, T.tiles_b, T.recs_b, -1, key[2], T.ctl, 1, i, s);
         for (int k = 0; k < 2 && key[0] && e0 == hipSuccess; ++k)
           e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, key[0], T.ctl, 1, i + k, s, 1);
       }
@@ -2058,7 +2086,7 @@ static void sched_main(rtm_ctx* ctx) {
   bool changed = false;
   int tick = 0;  // advances by K, so every job starts at an even tick
   int tz = 0;    // tuned on the first admitted job; every job of the scheduler shares it
-  int tzf = 0, tzb = 0;  // two-step heights, tuned on the first reconstruct-mode job (0: off)
+  int tzf = 0, tzb = 0;  // two-step heights, tuned on the first job that takes pairs (0: off)
   bool tz2_tuned = false;
   const int K = std::max(2, std::min(graph_k(), 64) & ~1);
   for (;;) {

@@ -362,6 +362,37 @@ def test_two_step_launches_equal_one_step(rtm, ctx, nt, nb):
         assert float(plain.abs().max()) > 0
 
 
+@pytest.mark.parametrize("nt", [3, 4, 5, 6, 7, 9, 38])
+def test_store_mode_two_step_launches_equal_one_step(rtm, ctx, nt):
+    """Store-mode batches advance two time steps per launch too.  A launch
+    writes the snapshots of the levels it reads (the level it stages, and
+    the one before it when a two-step launch computed that one without its
+    complete maximum), and the last forward level stays out of a pair's first
+    step.  Every stride from 1 to 4 with each snapshot type, with short and
+    odd step counts, must equal the plain path bit for bit."""
+    rng = np.random.default_rng(300 + nt)
+    nz, nx, h, dt, nb = 45, 131, 10.0, 1e-3, 10
+    vel = inputs.smooth_slowness(1700 + 600 * rng.random((nz, nx)), 30.0, h, h)
+    w = inputs.ricker(nt, dt, fp=25)
+    g = grid_of(rtm, nz, nx, nb, nt, h, dt)
+    shots = []
+    for sx, ix0, width in [(20, 0, 131), (70, 10, 97), (100, 0, 131)]:
+        rec = [(2, x) for x in range(ix0, ix0 + width, 3)]
+        shots.append(((3, sx), ix0, width, rec, dev(rng.standard_normal((nt, len(rec))) * 1e-2)))
+    for stride, dtype in ((1, "fp32"), (2, "bf16"), (3, "fp16"), (4, "bf16"), (4, "fp32")):
+        opts = rtm.img_opts("store", dtype, stride)
+        plain = torch.zeros(nz, nx, device="cuda")
+        for (src, ix0, width, rec, d) in shots:
+            ctx.migrate_shot(g, dev(vel), dev(w), src, rec, d, ix0, width, opts, plain)
+        batch = torch.zeros(nz, nx, device="cuda")
+        ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch)
+        torch.cuda.synchronize()
+        assert torch.equal(plain, batch), (nt, stride, dtype, (plain - batch).abs().max().item())
+        assert ctx.stats().last_steps_per_launch == (2 if nt >= 4 else 1)
+        if nt >= 5 and stride <= nt - 2:  # a stored level after level 0 (where S is still zero)
+            assert float(plain.abs().max()) > 0
+
+
 @pytest.mark.parametrize("group_kb", [None, "0", "600", "1"])
 def test_batch_equals_plain_bitwise(rtm, ctx, group_kb):
     """The batched path equals the plain path bit for bit, whatever the shot
