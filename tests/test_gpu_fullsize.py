@@ -4,8 +4,10 @@ shots advancing together in graph-replayed batched launches with the tuned
 tile height.  One shot carries data modelled by the FP64 oracle; the other
 shots carry zero data, so they do all the work of a shot but add exactly
 zero to the stack, which must then equal the oracle's image of that shot.
-The oracle migrates with checkpointed source wavefields (bit-identical to
-storing them all) and takes about a minute on the host's cores."""
+The shots run in two shot groups (a reduced cache budget), as the
+benchmark's shots do.  The oracle migrates with checkpointed source
+wavefields (bit-identical to storing them all) and takes about a minute on
+the host's cores."""
 import numpy as np
 import pytest
 
@@ -25,7 +27,10 @@ def rtm():
     return _rtm
 
 
-def test_faulted_survey_full_size_batched_matches_oracle(rtm):
+def test_faulted_survey_full_size_batched_matches_oracle(rtm, monkeypatch):
+    # two shot groups of two shots each (the benchmark's 100 shots run in 13
+    # backward groups of 7-8 under the default cache budget)
+    monkeypatch.setenv("RTM_GROUP_KB", str(60 << 10))
     sv = inputs.faulted_survey(n_shots=100, nt=4000)
     sh = sv.shots[50]
     kw = dict(dz=sv.h, dx=sv.h, dt=sv.dt, nb=sv.nb, nt=sv.nt)
@@ -56,6 +61,7 @@ def test_faulted_survey_full_size_batched_matches_oracle(rtm):
     print(f"full-size traces rel L2 {et:.3e}; batched reconstruct image rel L2 {e:.3e}; "
           f"tile height {st.tile_z}; graph replays {st.graph_replays}")
     assert st.graph_replays > 0
+    assert (st.last_groups_fwd, st.last_groups_bwd) == (1, 2), (st.last_groups_fwd, st.last_groups_bwd)
     # Traces: FP32 rounding of the update c L u grows with (v dt / h)^2 and with
     # nt; at 4700 m/s (10x the two-layer model's c at 1500 m/s) and nt = 4000
     # (4x), the two-layer bound of 3e-5 scales to ~1e-4: 2e-4 is the bound here.
