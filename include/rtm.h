@@ -228,9 +228,12 @@ int rtm_migrate_batch(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev,
  * device: a scheduler thread admits queued jobs whenever arena memory frees
  * up and advances every admitted job in the same kernel launches
  * (continuous batching); finished images feed per-sample statistics on the
- * device (Sec. 2.3, Stage 3).  RTM_SERVE_KB (KiB) optionally caps the field
- * bytes the running jobs' launches touch; admission then waits, in order,
- * until running jobs finish. */
+ * device (Sec. 2.3, Stage 3).  Reconstruct-mode jobs advance two steps per
+ * launch where they can; RTM_SERVE_STORE_PAIRS=1 does the same for
+ * store-mode jobs (shorter median latency of lone jobs, longer tail under
+ * load).  RTM_SERVE_KB (KiB) optionally caps the field bytes the running
+ * jobs' launches touch; admission then waits, in order, until running jobs
+ * finish. */
 
 /* Register velocity sample `realization` (Sec. 3, Stage 2: one migration
  * set per velocity sample).  The velocity is copied into the arena and v_max

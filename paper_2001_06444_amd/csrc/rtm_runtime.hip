@@ -750,16 +750,21 @@ static bool two_step_on() { return env_tz2() != 0; }
 static bool pairs_mode(const JobGeom& g) {
   return (g.mode == kModeRecon || g.mode == kModeStore) && !(g.flags & RTM_IMG_ILLUM);
 }
-// The serving engine pairs reconstruct-mode jobs only.  Its jobs sit in
-// different phases, so a cycle with pairs launches forward pairs, backward
-// pairs and one-step launches for the steps no pair covers; that paid off for
-// the reconstruct-mode ensemble (3.17e11 -> 3.82e11 updates/s) but not for
-// the store-mode stream, whose few small jobs make every launch short
-// (Poisson stream at 20 jobs/s: p50 37 -> 43 ms, saturation 97 -> 77
-// images/s), while the batch path gains on store mode too (100-shot survey,
-// BF16 every 4 steps: 0.60 -> 0.51 s per migration).
+// The serving engine pairs reconstruct-mode jobs, and store-mode jobs only
+// when RTM_SERVE_STORE_PAIRS=1.  Its jobs sit in different phases, so a cycle
+// with pairs launches forward pairs, backward pairs (one launch per job mode
+// present) and one-step launches for the steps no pair covers.  That paid
+// off for the reconstruct-mode ensemble (3.17e11 -> 3.82e11 updates/s).  On
+// the store-mode stream (Poisson, 20 jobs/s, 300 timed jobs) pairs cut the
+// median latency of the mostly lone jobs (42 -> 36 ms) but lengthen the tail
+// and the saturation run, where many jobs in different phases split every
+// step into more launches (p99 89 -> 133 ms; saturation 101 -> 77 images/s),
+// so store-mode jobs run one step per launch by default.
 static bool served_two_step(const JobGeom& g) {
-  return g.mode == kModeRecon && !(g.flags & RTM_IMG_ILLUM) && two_step_on();
+  const char* e = getenv("RTM_SERVE_STORE_PAIRS");
+  const bool store_pairs = e && atoi(e) == 1;
+  return (g.mode == kModeRecon || (store_pairs && g.mode == kModeStore)) && !(g.flags & RTM_IMG_ILLUM) &&
+         two_step_on();
 }
 
 
@@ -1890,12 +1895,14 @@ struct SchedTables {
   int2* recs_b = nullptr;
   StepCtl* ctl = nullptr;
   size_t cap_jobs = 0, cap_tiles = 0, cap_f = 0, cap_b = 0, cap_rf = 0, cap_rb = 0;
-  std::map<std::array<int, 3>, hipGraphExec_t> graphs;  // launch buckets (one-step, forward, backward) -> graph
+  // launch buckets (one-step, forward, backward; modes present) -> graph
+  std::map<std::array<int, 4>, hipGraphExec_t> graphs;
   std::vector<DevJob> hjobs;
   std::vector<Tile> htiles, htf, htb;
   std::vector<int2> hrf, hrb;
   std::vector<uint8_t> kinds;  // per active job: 1 one-step, 2 forward pairs, 4 backward pairs
   std::array<int32_t, 3> counts{};  // ntiles_fw, ntiles, ntiles_bw as the control block holds them
+  int modes = 0;  // two-step tables: bit 0 forward reconstruct, 1 forward store, 2 backward reconstruct, 3 backward store
   hipEvent_t ev[2] = {nullptr, nullptr};  // around each cycle's launches
 };
 
@@ -1962,6 +1969,12 @@ static int sched_cycle(rtm_ctx* ctx, SchedTables& T, std::vector<EnsJob*>& activ
       if (kinds[i] & 2) append_two_step_tiles(j, (int)i, tzf, T.htf, T.hrf);
       if (kinds[i] & 4) append_two_step_tiles(j, (int)i, tzb, T.htb, T.hrb);
     }
+    T.modes = 0;
+    for (size_t i = 0; i < active.size(); ++i) {
+      const int st = active[i]->job->d.mode == kModeStore ? 1 : 0;
+      if (kinds[i] & 2) T.modes |= 1 << st;
+      if (kinds[i] & 4) T.modes |= 4 << st;
+    }
     const bool fits = T.hjobs.size() <= T.cap_jobs && T.htiles.size() <= T.cap_tiles && T.htf.size() <= T.cap_f &&
                       T.htb.size() <= T.cap_b && T.hrf.size() <= T.cap_rf && T.hrb.size() <= T.cap_rb && T.ctl;
     if (!fits) {  // new device tables (graphs hold the old pointers: drop them)
@@ -2002,7 +2015,8 @@ static int sched_cycle(rtm_ctx* ctx, SchedTables& T, std::vector<EnsJob*>& activ
     changed = false;
   }
   const int n1 = T.counts[1], nf = T.counts[0], nb = T.counts[2];
-  const std::array<int, 3> key = {n1 ? tile_bucket(n1) : 0, nf ? tile_bucket(nf) : 0, nb ? tile_bucket(nb) : 0};
+  const std::array<int, 4> key = {n1 ? tile_bucket(n1) : 0, nf ? tile_bucket(nf) : 0, nb ? tile_bucket(nb) : 0,
+                                  T.modes};
   auto git = T.graphs.find(key);
   if (git == T.graphs.end()) {
     hipGraph_t g = nullptr;
@@ -2013,9 +2027,14 @@ static int sched_cycle(rtm_ctx* ctx, SchedTables& T, std::vector<EnsJob*>& activ
         e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, key[0], T.ctl, 1, i, s, 1);
     } else {
       for (int i = 0; i < K && e0 == hipSuccess; i += 2) {
-        if (key[1]) e0 = launch_step2(tzf, kPhFwd, 0, T.jobs, T.tiles_f, T.recs_f, -1, key[1], T.ctl, 1, i, s);
-        if (e0 == hipSuccess && key[2])
-          e0 = launch_step2(tzb, kPhBwd, 0, T.jobs, T.tiles_b, T.recs_b, -1, key[2], T.ctl, 1, i, s);
+        // one launch per phase and job mode present (each kernel instance
+        // takes the tiles of its mode's jobs and passes over the others)
+        for (int st = 0; st < 2 && e0 == hipSuccess; ++st) {
+          if (key[1] && (key[3] & (1 << st)))
+            e0 = launch_step2(tzf, kPhFwd, st, T.jobs, T.tiles_f, T.recs_f, -1, key[1], T.ctl, 1, i, s);
+          if (e0 == hipSuccess && key[2] && (key[3] & (4 << st)))
+            e0 = launch_step2(tzb, kPhBwd, st, T.jobs, T.tiles_b, T.recs_b, -1, key[2], T.ctl, 1, i, s);
+        }
         for (int k = 0; k < 2 && key[0] && e0 == hipSuccess; ++k)
           e0 = launch_step(tz, kPhAny, T.jobs, T.tiles, -1, key[0], T.ctl, 1, i + k, s, 1);
       }
