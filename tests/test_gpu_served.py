@@ -299,6 +299,30 @@ def test_running_set_cap_runs_jobs_in_order_and_unchanged(rtm, monkeypatch):
             assert np.array_equal(_alone(rtm, ctx, vels[j["r"]], j), img), (j["mode"], j["dtype"])
 
 
+def test_served_store_mode_pairs_equal_alone(rtm, monkeypatch):
+    """RTM_SERVE_STORE_PAIRS=1: served store-mode jobs advance two steps per
+    launch too, beside reconstruct-mode jobs (one pair launch per phase and
+    mode); with odd and even nt, every stride and snapshot type, every image
+    equals its alone run bit for bit."""
+    monkeypatch.setenv("RTM_SERVE_STORE_PAIRS", "1")
+    rng = np.random.default_rng(51)
+    vels = _small_models(2)
+    specs = [("store", "fp32", 1, 151), ("store", "bf16", 4, 200), ("store", "fp16", 3, 177),
+             ("reconstruct", "fp32", 1, 190), ("store", "bf16", 2, 96)]
+    jobs = [_small_job(rng, k % 2, int(rng.integers(90, 170)), nt, mode, dtype, stride)
+            for k, (mode, dtype, stride, nt) in enumerate(specs)]
+    with rtm.Context(0, arena_bytes=1 << 30) as ctx:
+        g = rtm.make_grid(SZ, SX, SB, 100, H, H, DT)
+        for r, v in enumerate(vels):
+            ctx.model_register(r, dev(v), g)
+        keep = []
+        tickets = [_submit(rtm, ctx, j, keep) for j in jobs]
+        ctx.drain()
+        infos, images = _collect(rtm, ctx, tickets, jobs)
+        for j, img in zip(jobs, images):
+            assert np.array_equal(_alone(rtm, ctx, vels[j["r"]], j), img), (j["mode"], j["dtype"], j["stride"])
+
+
 def test_job_log_records_every_job(rtm, tmp_path, monkeypatch):
     """RTM_LOG names a file that receives one JSON line per job reaching a
     final state: done jobs with ordered timestamps, their updates, bytes and
