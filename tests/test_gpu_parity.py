@@ -393,6 +393,34 @@ def test_store_mode_two_step_launches_equal_one_step(rtm, ctx, nt):
             assert float(plain.abs().max()) > 0
 
 
+@pytest.mark.parametrize("mode", ["reconstruct", "store"])
+def test_batch_with_illumination_in_shot_groups_equals_plain(rtm, ctx, mode, monkeypatch):
+    """Illumination batches run one step per launch; in shot groups of one
+    shot (RTM_GROUP_KB=1) image and illumination equal the plain path's bit
+    for bit."""
+    monkeypatch.setenv("RTM_GROUP_KB", "1")
+    rng = np.random.default_rng(17)
+    nz, nx, h, dt, nt, nb = 50, 160, 10.0, 1e-3, 90, 10
+    vel = inputs.smooth_slowness(1700 + 600 * rng.random((nz, nx)), 30.0, h, h)
+    w = inputs.ricker(nt, dt, fp=25)
+    g = grid_of(rtm, nz, nx, nb, nt, h, dt)
+    shots = []
+    for sx, ix0, width in [(25, 0, 100), (80, 30, 120), (130, 60, 100)]:
+        rec = [(1, x) for x in range(ix0, ix0 + width)]
+        shots.append(((2, sx), ix0, width, rec, dev(rng.standard_normal((nt, width)) * 1e-2)))
+    opts = rtm.img_opts(mode, "fp32", 1)
+    plain, plain_il = torch.zeros(nz, nx, device="cuda"), torch.zeros(nz, nx, device="cuda")
+    for (src, ix0, width, rec, d) in shots:
+        ctx.migrate_shot(g, dev(vel), dev(w), src, rec, d, ix0, width, opts, plain, plain_il)
+    batch, batch_il = torch.zeros(nz, nx, device="cuda"), torch.zeros(nz, nx, device="cuda")
+    ctx.migrate_batch(g, dev(vel), dev(w), shots, opts, batch, batch_il)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    assert (st.last_groups_fwd, st.last_groups_bwd, st.last_steps_per_launch) == (3, 3, 1)
+    assert torch.equal(plain, batch) and torch.equal(plain_il, batch_il)
+    assert float(plain_il.abs().max()) > 0
+
+
 @pytest.mark.parametrize("group_kb", [None, "0", "600", "1"])
 def test_batch_equals_plain_bitwise(rtm, ctx, group_kb):
     """The batched path equals the plain path bit for bit, whatever the shot
