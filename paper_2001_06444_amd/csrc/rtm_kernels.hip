@@ -647,13 +647,15 @@ struct TileStageW {  // ROWS x 72 floats from (zs, xs), as 16-byte loads
   }
 };
 
-template <int TZ, bool kBwd>
+// kRecon: the backward pass reconstructs S (reconstruct mode), which needs
+// the staged S^{m+1}; a store-mode backward pair stages R only.
+template <int TZ, bool kBwd, bool kRecon = true>
 struct Step2Smem {
-  float a[(TZ + 4 * kHalo) * kLdsW];              // u^n or R^{m+1}, 8-cell halo
-  float b[kBwd ? (TZ + 4 * kHalo) * kLdsW : 4];   // S^{m+1}
-  float ma[(TZ + 2 * kHalo) * kTileX];            // middle region: u^{n+1} or R^m
-  float mb[kBwd ? (TZ + 2 * kHalo) * kTileX : 4]; // middle region: S^m
-  float red[4];                                   // workgroup max (store mode)
+  float a[(TZ + 4 * kHalo) * kLdsW];                         // u^n or R^{m+1}, 8-cell halo
+  float b[kBwd && kRecon ? (TZ + 4 * kHalo) * kLdsW : 4];    // S^{m+1}
+  float ma[(TZ + 2 * kHalo) * kTileX];                       // middle region: u^{n+1} or R^m
+  float mb[kBwd ? (TZ + 2 * kHalo) * kTileX : 4];            // middle region: S^m (store mode: receiver data)
+  float red[4];                                              // workgroup max (store mode)
 };
 
 // Boundary-ring save of a forward value at level `lev` (reconstruct mode).
@@ -1219,7 +1221,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ j
                                                      const int2* __restrict__ recs2,
                                                      const StepCtl* __restrict__ ctl, int ntiles_arg,
                                                      int use_ctl_tick, int tick_off) {
-  __shared__ Step2Smem<TZ, (PH & kPhBwd) != 0> sm;
+  __shared__ Step2Smem<TZ, (PH & kPhBwd) != 0, !kStore> sm;
   // Steps tick and tick + 1 of every job; same XCD-aware mapping as k_step,
   // except that every other launch walks each XCD's run of tiles backwards:
   // it then starts on the tiles the previous launch wrote last, whose data
