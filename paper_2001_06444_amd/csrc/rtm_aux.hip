@@ -185,9 +185,17 @@ hipError_t launch_stats_out(const double* mean, const double* m2, const int32_t*
 // in two stages: each workgroup of a grid-stride pass writes its partial
 // result and one workgroup folds the partials, so no address is hit by
 // more than one write (with one atomic per wavefront on a single address,
-// the 597k-pixel confidence map spent 95 us in its reduction).  Loads are
-// issued four grid strides at a time, with no branch between a pixel's
-// loads, so each wavefront keeps several in flight.
+// the 597k-pixel confidence map spent 95 us in its reduction).
+// The streaming passes take four pixels per thread and step, as 16-byte
+// loads and stores with two steps' loads in flight, when every array the
+// pass touches is 16-byte aligned (kVec); otherwise, and for the pixels
+// past the last whole group of four, one pixel per step.  The second pass
+// of a map walks the arrays from their end, so it starts on the data the
+// first pass read last, which the memory-side cache still holds (measured
+// on 256 images side by side: the normalised image's second pass 10 %
+// shorter than walking forward; the confidence map's unchanged).  The
+// normalised image is written with non-temporal stores (3 % shorter; the
+// confidence map's double stores were 20 % longer that way).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void block_minmax(double& lo, double& hi, double* red) {
   for (int o = 32; o > 0; o >>= 1) {
@@ -207,39 +215,58 @@ __device__ __forceinline__ void block_minmax(double& lo, double& hi, double* red
     }
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));  // for the non-temporal 16-byte store
+
+static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// Workgroups of a streaming pass over `units` groups (or pixels), at most cap.
+static inline int stream_blocks(int64_t units, int cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((units + 255) / 256, cap));
+}
+
 // Extremes of std over the pixels with count >= min_count (all pixels
 // without counts), one (min, max) pair per workgroup.  std >= 0, so a
 // workgroup without such pixels leaves (inf, 0), which orders as empty.
+// min and max are exact, so the grouping of the pixels leaves the result
+// unchanged.
+template <bool kVec>
 __global__ __launch_bounds__(256) void k_minmax_part(const double* __restrict__ sd,
                                                      const int32_t* __restrict__ count, int n,
                                                      int min_count, double* __restrict__ part) {
   __shared__ double red[8];
   double lo = INFINITY, hi = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    double v[4];
-    int32_t c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      v[u] = sd[i + u * stride];
-      c[u] = count ? count[i + u * stride] : min_count;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (c[u] >= min_count) {
-        lo = fmin(lo, v[u]);
-        hi = fmax(hi, v[u]);
-      }
-  }
-  for (; i < n; i += stride) {
-    const double v = sd[i];
-    const int32_t c = count ? count[i] : min_count;
+  auto take = [&](double v, int32_t c) {
     if (c >= min_count) {
       lo = fmin(lo, v);
       hi = fmax(hi, v);
     }
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t head = 0;  // pixels [0, head) go through the vector loop
+  if (kVec) {
+    const int64_t ng = n >> 2;
+    const double2* __restrict__ s2 = reinterpret_cast<const double2*>(sd);
+    const int4* __restrict__ c4 = reinterpret_cast<const int4*>(count);
+    const int4 all = make_int4(min_count, min_count, min_count, min_count);
+    auto take4 = [&](double2 a, double2 b, int4 c) {
+      take(a.x, c.x);
+      take(a.y, c.y);
+      take(b.x, c.z);
+      take(b.y, c.w);
+    };
+    int64_t g = t0;
+    for (; g + stride < ng; g += 2 * stride) {
+      const int64_t h = g + stride;
+      const double2 a0 = s2[2 * g], a1 = s2[2 * g + 1], b0 = s2[2 * h], b1 = s2[2 * h + 1];
+      const int4 ca = count ? c4[g] : all, cb = count ? c4[h] : all;
+      take4(a0, a1, ca);
+      take4(b0, b1, cb);
+    }
+    if (g < ng) take4(s2[2 * g], s2[2 * g + 1], count ? c4[g] : all);
+    head = ng << 2;
   }
+  for (int64_t i = head + t0; i < n; i += stride) take(sd[i], count ? count[i] : min_count);
   block_minmax(lo, hi, red);
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = lo;
@@ -262,25 +289,62 @@ __global__ __launch_bounds__(256) void k_minmax_fold(const double* __restrict__ 
   }
 }
 
-// Confidence index (Eq. 6) from the folded extremes mm = (s_min, s_max).
-__global__ void k_confidence(const double* __restrict__ sd, const int32_t* __restrict__ count,
-                             int n, int min_count, const double* __restrict__ mm, double* __restrict__ out) {
+// Confidence index (Eq. 6) from the folded extremes mm = (s_min, s_max),
+// walking the arrays from their end.
+template <bool kVec>
+__global__ __launch_bounds__(256) void k_confidence(const double* __restrict__ sd,
+                                                    const int32_t* __restrict__ count, int n, int min_count,
+                                                    const double* __restrict__ mm, double* __restrict__ out) {
   const double lo = mm[0], hi = mm[1];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = sd[i];
-    const bool on = (!count || count[i] >= min_count) && hi > lo;
-    out[i] = on ? (hi - v) / (hi - lo) : 0.0;
+  const bool any = hi > lo;
+  auto conf = [&](double v, int32_t c) { return (c >= min_count && any) ? (hi - v) / (hi - lo) : 0.0; };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ng = kVec ? (n >> 2) : 0;
+  for (int64_t j = t0; j < n - (ng << 2); j += stride) {  // pixels past the last group (all, unaligned)
+    const int64_t i = n - 1 - j;
+    out[i] = conf(sd[i], count ? count[i] : min_count);
+  }
+  if (kVec) {
+    const double2* __restrict__ s2 = reinterpret_cast<const double2*>(sd);
+    const int4* __restrict__ c4 = reinterpret_cast<const int4*>(count);
+    double2* __restrict__ o2 = reinterpret_cast<double2*>(out);
+    const int4 all = make_int4(min_count, min_count, min_count, min_count);
+    auto put4 = [&](int64_t g, double2 a, double2 b, int4 c) {
+      o2[2 * g] = make_double2(conf(a.x, c.x), conf(a.y, c.y));
+      o2[2 * g + 1] = make_double2(conf(b.x, c.z), conf(b.y, c.w));
+    };
+    int64_t j = t0;
+    for (; j + stride < ng; j += 2 * stride) {
+      const int64_t g = ng - 1 - j, h = g - stride;
+      const double2 a0 = s2[2 * g], a1 = s2[2 * g + 1], b0 = s2[2 * h], b1 = s2[2 * h + 1];
+      const int4 ca = count ? c4[g] : all, cb = count ? c4[h] : all;
+      put4(g, a0, a1, ca);
+      put4(h, b0, b1, cb);
+    }
+    if (j < ng) {
+      const int64_t g = ng - 1 - j;
+      put4(g, s2[2 * g], s2[2 * g + 1], count ? c4[g] : all);
+    }
   }
 }
 
 hipError_t launch_confidence(const double* sd, const int32_t* count, int n, int min_count,
                              double* out, double* scratch, hipStream_t s) {
-  const int parts = std::max(1, std::min((n + 255) / 256, kRedBlocks));
+  const bool vec = aligned16(sd) && (!count || aligned16(count)) && aligned16(out);
+  const int64_t units = vec ? (n >> 2) : n;
+  const int parts = stream_blocks(units, kRedBlocks);
   double* mm = scratch + 2 * kRedBlocks;
-  hipLaunchKernelGGL(k_minmax_part, dim3(parts), dim3(256), 0, s, sd, count, n, min_count, scratch);
+  if (vec)
+    hipLaunchKernelGGL(k_minmax_part<true>, dim3(parts), dim3(256), 0, s, sd, count, n, min_count, scratch);
+  else
+    hipLaunchKernelGGL(k_minmax_part<false>, dim3(parts), dim3(256), 0, s, sd, count, n, min_count, scratch);
   hipLaunchKernelGGL(k_minmax_fold, dim3(1), dim3(256), 0, s, scratch, parts, mm);
-  const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_confidence, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm, out);
+  const int blocks = stream_blocks(units, 4096);
+  if (vec)
+    hipLaunchKernelGGL(k_confidence<true>, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm, out);
+  else
+    hipLaunchKernelGGL(k_confidence<false>, dim3(blocks), dim3(256), 0, s, sd, count, n, min_count, mm, out);
   return hipGetLastError();
 }
 
@@ -351,19 +415,27 @@ hipError_t launch_lapfilter(const float* img, int nz, int nx, float dz, float dx
 // ---------------------------------------------------------------------------
 // Source-normalised image (Eq. 5): out = I / (illum + eps_rel * max illum)
 // ---------------------------------------------------------------------------
+template <bool kVec>
 __global__ __launch_bounds__(256) void k_max_part(const float* __restrict__ a, int n, float* __restrict__ part) {
   __shared__ float red[4];
   float m = 0.0f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    float v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = a[i + u * stride];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) m = fmaxf(m, v[u]);
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t head = 0;
+  if (kVec) {
+    const int64_t ng = n >> 2;
+    const float4* __restrict__ a4 = reinterpret_cast<const float4*>(a);
+    auto take4 = [&](float4 v) { m = fmaxf(fmaxf(m, v.x), fmaxf(fmaxf(v.y, v.z), v.w)); };
+    int64_t g = t0;
+    for (; g + stride < ng; g += 2 * stride) {
+      const float4 u = a4[g], v = a4[g + stride];
+      take4(u);
+      take4(v);
+    }
+    if (g < ng) take4(a4[g]);
+    head = ng << 2;
   }
-  for (; i < n; i += stride) m = fmaxf(m, a[i]);
+  for (int64_t i = head + t0; i < n; i += stride) m = fmaxf(m, a[i]);
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -380,22 +452,61 @@ __global__ __launch_bounds__(256) void k_max_fold(const float* __restrict__ part
   if (threadIdx.x == 0) *mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
-__global__ void k_normalize(const float* __restrict__ img, const float* __restrict__ illum, int n,
-                            float eps_rel, const float* __restrict__ mx, float* __restrict__ out) {
+// walks the arrays from their end, after k_max_part walked them from the start
+template <bool kVec>
+__global__ __launch_bounds__(256) void k_normalize(const float* __restrict__ img, const float* __restrict__ illum,
+                                                   int n, float eps_rel, const float* __restrict__ mx,
+                                                   float* __restrict__ out) {
   const float eps = eps_rel * *mx;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float d = illum[i] + eps;
-    out[i] = d > 0.0f ? img[i] / d : 0.0f;
+  auto norm = [&](float im, float il) {
+    const float d = il + eps;
+    return d > 0.0f ? im / d : 0.0f;
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ng = kVec ? (n >> 2) : 0;
+  for (int64_t j = t0; j < n - (ng << 2); j += stride) {
+    const int64_t i = n - 1 - j;
+    out[i] = norm(img[i], illum[i]);
+  }
+  if (kVec) {
+    const float4* __restrict__ i4 = reinterpret_cast<const float4*>(img);
+    const float4* __restrict__ l4 = reinterpret_cast<const float4*>(illum);
+    f4v* __restrict__ o4 = reinterpret_cast<f4v*>(out);
+    auto put4 = [&](int64_t g, float4 u, float4 l) {
+      __builtin_nontemporal_store(f4v{norm(u.x, l.x), norm(u.y, l.y), norm(u.z, l.z), norm(u.w, l.w)}, o4 + g);
+    };
+    int64_t j = t0;
+    for (; j + stride < ng; j += 2 * stride) {
+      const int64_t g = ng - 1 - j, h = g - stride;
+      const float4 ua = i4[g], la = l4[g], ub = i4[h], lb = l4[h];
+      put4(g, ua, la);
+      put4(h, ub, lb);
+    }
+    if (j < ng) {
+      const int64_t g = ng - 1 - j;
+      put4(g, i4[g], l4[g]);
+    }
   }
 }
 
 hipError_t launch_normalize(const float* img, const float* illum, int n, float eps_rel, float* out,
                             float* scratch, hipStream_t s) {
-  const int parts = std::max(1, std::min((n + 255) / 256, kRedBlocks));
-  hipLaunchKernelGGL(k_max_part, dim3(parts), dim3(256), 0, s, illum, n, scratch);
+  const bool vec = aligned16(img) && aligned16(illum) && aligned16(out);
+  const int64_t units = vec ? (n >> 2) : n;
+  const int parts = stream_blocks(units, kRedBlocks);
+  if (vec)
+    hipLaunchKernelGGL(k_max_part<true>, dim3(parts), dim3(256), 0, s, illum, n, scratch);
+  else
+    hipLaunchKernelGGL(k_max_part<false>, dim3(parts), dim3(256), 0, s, illum, n, scratch);
   hipLaunchKernelGGL(k_max_fold, dim3(1), dim3(256), 0, s, scratch, parts, scratch + kRedBlocks);
-  const int blocks = std::max(1, std::min((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, s, img, illum, n, eps_rel, scratch + kRedBlocks, out);
+  const int blocks = stream_blocks(units, 4096);
+  if (vec)
+    hipLaunchKernelGGL(k_normalize<true>, dim3(blocks), dim3(256), 0, s, img, illum, n, eps_rel,
+                       scratch + kRedBlocks, out);
+  else
+    hipLaunchKernelGGL(k_normalize<false>, dim3(blocks), dim3(256), 0, s, img, illum, n, eps_rel,
+                       scratch + kRedBlocks, out);
   return hipGetLastError();
 }
 

@@ -244,6 +244,61 @@ def test_maps_and_filter_at_image_size(rtm):
         assert oracle.rel_l2(host(out), i64 / (l64 + 1e-3 * l64.max())) <= 1e-6
 
 
+def _dev_at(a, dtype, off):
+    """Device copy of a 1-D array starting `off` elements into its allocation
+    (off = 1: the array is not 16-byte aligned)."""
+    t = torch.zeros(len(a) + off, dtype=dtype, device="cuda")
+    t[off:] = torch.as_tensor(np.ascontiguousarray(a), dtype=dtype)
+    return t[off:]
+
+
+@pytest.mark.parametrize("n, off", [(1, 0), (3, 0), (6, 1), (4097, 0), (4097, 1), (9_000_001, 0),
+                                    (9_000_001, 1)])
+def test_maps_ragged_and_unaligned_lengths(rtm, n, off):
+    """The streaming map passes take four pixels per step with 16-byte loads
+    and stores only when every array is 16-byte aligned, and one pixel per
+    step otherwise (off = 1) and for the pixels past the last group of four;
+    9M pixels run both passes' two-steps-in-flight loops.  Every value equals
+    the oracle's: the maps are one IEEE operation chain per pixel (Eqs. 5-7),
+    and their extremes are exact."""
+    rng = np.random.default_rng(n + off)
+    std = np.abs(rng.standard_normal(n))
+    mean = rng.standard_normal(n)
+    cnt = rng.integers(0, 8, n).astype(np.int32)
+    img = rng.standard_normal(n).astype(np.float32)
+    ill = rng.random(n).astype(np.float32)
+    with rtm.Context(0, arena_bytes=64 << 20) as ctx:
+        sd, cd = _dev_at(std, torch.float64, off), _dev_at(cnt, torch.int32, off)
+        conf = _dev_at(np.zeros(n), torch.float64, off)
+        ctx.confidence_map(sd, cd, conf, min_count=2)
+        np.testing.assert_array_equal(host(conf), oracle.confidence_index(std, cnt, min_count=2))
+        ctx.confidence_map(sd, None, conf, min_count=2)
+        np.testing.assert_array_equal(host(conf), oracle.confidence_index(std))
+        ctx.ratio_map(sd, _dev_at(mean, torch.float64, off), conf, eps=1e-3)
+        np.testing.assert_array_equal(host(conf), oracle.ratio_map(std, mean, eps=1e-3))
+        out = _dev_at(np.zeros(n), torch.float32, off)
+        ctx.normalize_image(_dev_at(img, torch.float32, off), _dev_at(ill, torch.float32, off), out, eps_rel=1e-3)
+        d = ill + np.float32(1e-3) * ill.max()  # Eq. 5 in FP32, the precision of the images
+        ref = np.where(d > 0, img / np.where(d > 0, d, np.float32(1)), np.float32(0))
+        np.testing.assert_array_equal(host(out).astype(np.float32), ref)
+
+
+@pytest.mark.parametrize("nz, nx", [(1, 1), (3, 5), (16, 256), (17, 257), (351, 1701), (40, 2000)])
+def test_laplacian_filter_tiles(rtm, nz, nx):
+    """The post-stack filter runs 256-column workgroups whose threads filter
+    16 rows of one column: grids smaller than the stencil's halo, one exact
+    workgroup, a ragged workgroup in each direction and many workgroups,
+    against the oracle."""
+    img = np.random.default_rng(nz * 7919 + nx).standard_normal((nz, nx)).astype(np.float32)
+    with rtm.Context(0, arena_bytes=64 << 20) as ctx:
+        out = torch.full((nz, nx), np.nan, device="cuda")
+        ctx.laplacian_filter(dev(img), 10.0, 12.5, out)
+        ref = oracle.laplacian_filter(img.astype(np.float64), 10.0, 12.5)
+        got = host(out)
+        assert np.isfinite(got).all()
+        assert oracle.rel_l2(got, ref) <= 1e-6
+
+
 def test_nonfinite_fails_only_its_job(rtm):
     """A job whose data hold a NaN fails with RTM_E_NONFINITE; the jobs around
     it finish normally.  A NaN velocity is refused at submit.  On the plain
