@@ -231,6 +231,8 @@ struct rtm_ctx {
   hipStream_t stream = nullptr;        // caller's stream (plain / batched / copies)
   hipStream_t sched_stream = nullptr;  // scheduler thread's stream
   hipStream_t work_stream = nullptr;   // batched path (graph capture needs a non-null stream)
+  hipStream_t work_stream2 = nullptr;  // batched path: second stream of shot groups
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // phase timing of the last batched call (events on work_stream)
   hipEvent_t ph_ev[3] = {nullptr, nullptr, nullptr};
@@ -715,6 +717,7 @@ struct Table {
   DevJob* jobs = nullptr;
   Tile* tiles = nullptr;
   StepCtl* ctl = nullptr;
+  StepCtl* ctl2 = nullptr;  // the batched path's second stream of shot groups
   int ntiles = 0;
   // two-step tiles (tz rows x 56 columns) of the forward and the backward
   // phase, with the receivers of each tile's middle region:
@@ -863,6 +866,11 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
     return fail(RTM_E_NOMEM, "arena exhausted (control block)");
   }
   t.ctl = static_cast<StepCtl*>(p);
+  if (!alloc_block(ctx, t.blocks, sizeof(StepCtl), &p)) {
+    release_blocks(ctx, t.blocks);
+    return fail(RTM_E_NOMEM, "arena exhausted (control block)");
+  }
+  t.ctl2 = static_cast<StepCtl*>(p);
   for (auto* tw : {&t.fw, &t.bw}) {
     if (tw->ntiles == 0) continue;
     if (!alloc_block(ctx, t.blocks, tw->htiles->size() * sizeof(Tile), &p)) {
@@ -884,6 +892,7 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   StepCtl c{};
   c.ntiles = t.ntiles;
   HIP_OK(hipMemcpyAsync(t.ctl, &c, sizeof c, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(t.ctl2, &c, sizeof c, hipMemcpyHostToDevice, s));
   HIP_OK(hipStreamSynchronize(s));  // host-side staging copies are complete
   return RTM_OK;
 }
@@ -1138,6 +1147,9 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   ctx->arena.init(arena_dev, arena_bytes);
   HIP_OK(hipStreamCreateWithFlags(&ctx->sched_stream, hipStreamNonBlocking));
   HIP_OK(hipStreamCreateWithFlags(&ctx->work_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamCreateWithFlags(&ctx->work_stream2, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
   for (auto& e : ctx->ph_ev) HIP_OK(hipEventCreate(&e));
@@ -1193,9 +1205,13 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
     reap(ctx, true);
   }
   (void)hipStreamSynchronize(ctx->work_stream);
+  (void)hipStreamSynchronize(ctx->work_stream2);
   reap(ctx, false);
   (void)hipStreamDestroy(ctx->sched_stream);
   (void)hipStreamDestroy(ctx->work_stream);
+  (void)hipStreamDestroy(ctx->work_stream2);
+  (void)hipEventDestroy(ctx->ev_fork);
+  (void)hipEventDestroy(ctx->ev_join);
   (void)hipEventDestroy(ctx->ev_in);
   (void)hipEventDestroy(ctx->ev_out);
   for (auto e : ctx->ph_ev) (void)hipEventDestroy(e);
@@ -1405,16 +1421,16 @@ extern "C" int rtm_migrate_shot(rtm_ctx* ctx, const rtm_grid* grid, const float*
 // steps each; an odd last step runs as a one-step launch.  The caller starts
 // the backward phase with two one-step launches (levels nt - 1 and nt - 2 are
 // not reconstructed) before it asks for pairs.
-static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, const int (&grid)[3], int nsteps,
-                       int K, hipGraphExec_t* graph, bool two_step) {
+static int graph_steps(rtm_ctx* ctx, hipStream_t s, StepCtl* ctl, int tz, int ph, Table& t, const int (&grid)[3],
+                       int nsteps, int K, hipGraphExec_t* graph, bool two_step) {
   const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
   const bool pairs = two_step && tw.ntiles > 0 && (ph == kPhFwd || ph == kPhBwd);
   const int store = !t.hjobs->empty() && (*t.hjobs)[0].mode == kModeStore;  // one mode per batch
   if (pairs) K = std::max(2, K & ~1);
   auto one = [&](int off, int left) -> hipError_t {  // the launch at offset `off`
     if (pairs && left >= 2)
-      return launch_step2(tw.tz, ph, store, t.jobs, tw.tiles, tw.recs, -1, grid[ph == kPhFwd ? 1 : 2], t.ctl, 1, off, s);
-    return launch_step(tz, ph, t.jobs, t.tiles, -1, grid[0], t.ctl, 1, off, s);
+      return launch_step2(tw.tz, ph, store, t.jobs, tw.tiles, tw.recs, -1, grid[ph == kPhFwd ? 1 : 2], ctl, 1, off, s);
+    return launch_step(tz, ph, t.jobs, t.tiles, -1, grid[0], ctl, 1, off, s);
   };
   int done = 0;
   if (nsteps >= K && K > 1) {
@@ -1423,7 +1439,7 @@ static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, co
       HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipSuccess;
       for (int i = 0; i < K && e == hipSuccess; i += pairs ? 2 : 1) e = one(i, K - i);
-      if (e == hipSuccess) e = launch_advance(t.ctl, K, s);
+      if (e == hipSuccess) e = launch_advance(ctl, K, s);
       hipError_t e2 = hipStreamEndCapture(s, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -1447,7 +1463,7 @@ static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, co
       HIP_OK(one(i, left));
       i += pairs && left >= 2 ? 2 : 1;
     }
-    HIP_OK(launch_advance(t.ctl, nsteps - done, s));
+    HIP_OK(launch_advance(ctl, nsteps - done, s));
   }
   ctx->steps_launched += nsteps;
   return RTM_OK;
@@ -1464,7 +1480,8 @@ static int graph_steps(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t, co
 // forward launch, 6.5 us and 2.8 us of launch time per shot, against 7.6 and
 // 3.7 us with all 100 shots in every launch; larger groups spill out of the
 // cache (11 shots per backward launch: 7.8 us per shot).  Groups are
-// consecutive runs of jobs of near-equal working set.
+// consecutive runs of jobs of near-equal working set.  When two streams run
+// groups side by side, each group takes half the budget.
 static size_t group_budget() {
   const char* e = getenv("RTM_GROUP_KB");
   const long v = e ? atol(e) : 200 << 10;
@@ -1499,7 +1516,7 @@ static size_t served_working_set(const JobGeom& g) {
   return launch_working_set(g, kPhBwd) + (size_t)(g.nz + 2 * g.nb) * field_pitch(g.width + 2 * g.nb) * 4;
 }
 
-static std::vector<std::pair<int, int>> shot_groups(const std::vector<JobGeom>& gs, int ph) {
+static std::vector<std::pair<int, int>> shot_groups(const std::vector<JobGeom>& gs, int ph, int streams) {
   std::vector<std::pair<int, int>> out;
   const int n = (int)gs.size();
   if (n == 0) return out;
@@ -1508,7 +1525,7 @@ static std::vector<std::pair<int, int>> shot_groups(const std::vector<JobGeom>& 
     total += launch_working_set(g, ph);
     medium = std::max(medium, (size_t)(g.nz + 2 * g.nb) * field_pitch(g.width + 2 * g.nb) * 4);  // c
   }
-  const size_t budget = group_budget();
+  const size_t budget = group_budget() == SIZE_MAX ? SIZE_MAX : group_budget() / streams;
   if (budget == SIZE_MAX || total + medium <= budget) return {{0, n}};
   const size_t room = budget > medium ? budget - medium : 1;
   const int ngroups = (int)std::min<size_t>(n, (total + room - 1) / room);
@@ -1534,21 +1551,46 @@ static std::vector<std::pair<int, int>> shot_groups(const std::vector<JobGeom>& 
   return out;
 }
 
-// One phase of the batch, group by group: the control block is pointed at
-// the group's tile ranges with the tick at `tick0`, then the group's steps
-// run (a backward phase with two-step tiles opens with two one-step launches).
-static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& t,
+// Streams the batched path runs its shot groups on (RTM_GROUP_STREAMS: 2,
+// the default, or 1).  With two, groups alternate between the work stream
+// and a second one, each with its own control block and captured graphs, so
+// one group's launches fill the workgroup slots another group's launch
+// leaves idle as it drains; each group then gets half the cache budget.
+// Measured on the 351 x 1701 survey (nt 1000, 200 MiB): 484 against 512 ms
+// per migration of 100 shots; one stream with groups of the same size took
+// 572 ms, so the gain is the overlap, not the smaller groups.
+static int group_streams() {
+  const char* e = getenv("RTM_GROUP_STREAMS");
+  return e && atoi(e) == 1 ? 1 : 2;
+}
+
+// One phase of the batch, group by group: the group's control block is
+// pointed at its tile ranges with the tick at `tick0`, then the group's
+// steps run (a backward phase with two-step tiles opens with two one-step
+// launches).  With a second stream s2 the odd groups run there, forked from
+// s and joined back into it before the call returns (also on an error, so
+// that work deferred on s waits for both).  graph[0] and graph[1] keep the
+// graphs of the two streams.
+static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, hipStream_t s2, int tz, int ph, Table& t,
                             const std::vector<std::pair<int, int>>& groups, int tick0, int nsteps, int K,
-                            hipGraphExec_t* graph, bool two_step) {
+                            hipGraphExec_t (&graph)[2], bool two_step) {
   const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
   const bool pairs = two_step && tw.ntiles > 0;
   const bool store = !t.hjobs->empty() && (*t.hjobs)[0].mode == kModeStore;  // one mode per batch
+  const bool two = s2 && groups.size() >= 2;
   int grid[3] = {0, 0, 0};
   for (auto [a, b] : groups) {
     grid[0] = std::max(grid[0], t.first[b] - t.first[a]);
     if (pairs) grid[ph == kPhFwd ? 1 : 2] = std::max(grid[ph == kPhFwd ? 1 : 2], tw.first[b] - tw.first[a]);
   }
-  for (auto [a, b] : groups) {
+  if (two) {
+    HIP_OK(hipEventRecord(ctx->ev_fork, s));
+    HIP_OK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+  }
+  auto run = [&](int gi, int a, int b) -> int {
+    const int side = two ? (gi & 1) : 0;
+    hipStream_t gs = side ? s2 : s;
+    StepCtl* ctl = side ? t.ctl2 : t.ctl;
     StepCtl c{};
     c.tick = tick0;
     c.ntiles = t.first[b] - t.first[a];
@@ -1560,31 +1602,41 @@ static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, int tz, int ph, Table& 
       c.ntiles_bw = tw.first[b] - tw.first[a];
       c.base_bw = tw.first[a];
     }
-    HIP_OK(launch_set_ctl(t.ctl, c, s));
-    int rc = RTM_OK;
+    HIP_OK(launch_set_ctl(ctl, c, gs));
     if (ph == kPhBwd && pairs && nsteps >= 4) {
       // levels nt - 1 and nt - 2 are imaged without reconstruction: one step each
-      for (int i = 0; i < 2; ++i) HIP_OK(launch_step(tz, kPhBwd, t.jobs, t.tiles, -1, grid[0], t.ctl, 1, i, s));
-      HIP_OK(launch_advance(t.ctl, 2, s));
+      for (int i = 0; i < 2; ++i) HIP_OK(launch_step(tz, kPhBwd, t.jobs, t.tiles, -1, grid[0], ctl, 1, i, gs));
+      HIP_OK(launch_advance(ctl, 2, gs));
       ctx->steps_launched += 2;
-      rc = graph_steps(ctx, s, tz, ph, t, grid, nsteps - 2, K, graph, true);
-    } else if (ph == kPhFwd && pairs && store) {
+      return graph_steps(ctx, gs, ctl, tz, ph, t, grid, nsteps - 2, K, &graph[side], true);
+    }
+    if (ph == kPhFwd && pairs && store) {
       // store mode: pairs as long as a forward step follows them (two_step_pair),
       // then one step per launch
       const int np = (nsteps - 1) & ~1;
-      rc = graph_steps(ctx, s, tz, ph, t, grid, np, K, graph, true);
-      for (int i = 0; !rc && i < nsteps - np; ++i)
-        HIP_OK(launch_step(tz, kPhFwd, t.jobs, t.tiles, -1, grid[0], t.ctl, 1, i, s));
-      if (!rc && nsteps > np) {
-        HIP_OK(launch_advance(t.ctl, nsteps - np, s));
+      const int rc = graph_steps(ctx, gs, ctl, tz, ph, t, grid, np, K, &graph[side], true);
+      if (rc) return rc;
+      for (int i = 0; i < nsteps - np; ++i)
+        HIP_OK(launch_step(tz, kPhFwd, t.jobs, t.tiles, -1, grid[0], ctl, 1, i, gs));
+      if (nsteps > np) {
+        HIP_OK(launch_advance(ctl, nsteps - np, gs));
         ctx->steps_launched += nsteps - np;
       }
-    } else {
-      rc = graph_steps(ctx, s, tz, ph, t, grid, nsteps, K, graph, pairs && ph == kPhFwd);
+      return RTM_OK;
     }
-    if (rc) return rc;
+    return graph_steps(ctx, gs, ctl, tz, ph, t, grid, nsteps, K, &graph[side], pairs && ph == kPhFwd);
+  };
+  int rc = RTM_OK;
+  for (int gi = 0; gi < (int)groups.size() && !rc; ++gi) rc = run(gi, groups[gi].first, groups[gi].second);
+  if (two) {
+    const bool joined = hipEventRecord(ctx->ev_join, s2) == hipSuccess &&
+                        hipStreamWaitEvent(s, ctx->ev_join, 0) == hipSuccess;
+    if (!joined) {
+      (void)hipStreamSynchronize(s2);
+      if (!rc) rc = fail(RTM_E_DEVICE, "joining the second stream failed");
+    }
   }
-  return RTM_OK;
+  return rc;
 }
 
 static int graph_k() {
@@ -1639,7 +1691,8 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   // shot groups of each phase; two-step heights, tuned at the size of the
   // backward groups (the dominant launches) before the batch takes its
   // arena blocks
-  const auto gf = shot_groups(geoms, kPhFwd), gb = shot_groups(geoms, kPhBwd);
+  const int nstreams = group_streams();
+  const auto gf = shot_groups(geoms, kPhFwd, nstreams), gb = shot_groups(geoms, kPhBwd, nstreams);
   int gmax = 1;
   for (auto [a, b] : gb) gmax = std::max(gmax, b - a);
   int tz2f = 0, tz2b = 0;
@@ -1676,14 +1729,15 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     return rc;
   }
   const int nt = grid->nt, K = graph_k();
-  hipGraphExec_t graphs[2] = {nullptr, nullptr};
+  hipGraphExec_t graphs[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [phase][stream]
+  hipStream_t s2 = nstreams == 2 ? ctx->work_stream2 : nullptr;
   HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
   roctxRangePushA("rtm.batch.forward");  // host-side enqueue of the phase
-  rc = run_phase_groups(ctx, s, tz, kPhFwd, t, gf, 0, nt - 1, K, &graphs[0], true);
+  rc = run_phase_groups(ctx, s, s2, tz, kPhFwd, t, gf, 0, nt - 1, K, graphs[0], true);
   roctxRangePop();
   roctxRangePushA("rtm.batch.backward");
   if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
-  if (!rc) rc = run_phase_groups(ctx, s, tz, kPhBwd, t, gb, nt - 1, nt, K, &graphs[1], t.bw.ntiles > 0 && nt >= 4);
+  if (!rc) rc = run_phase_groups(ctx, s, s2, tz, kPhBwd, t, gb, nt - 1, nt, K, graphs[1], t.bw.ntiles > 0 && nt >= 4);
   roctxRangePop();
   if (!rc) rc = hipEventRecord(ctx->ph_ev[2], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc) {
@@ -1735,8 +1789,9 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
   d.keep.push_back(t.htiles);
   d.keep.push_back(t.fw.htiles);
   d.keep.push_back(t.bw.htiles);
-  for (auto g : graphs)
-    if (g) d.graphs.push_back(g);
+  for (auto& gp : graphs)
+    for (auto g : gp)
+      if (g) d.graphs.push_back(g);
   int rc2 = defer(ctx, s, std::move(d));
   HIP_OK(hipEventRecord(ctx->ev_out, s));
   HIP_OK(hipStreamWaitEvent(ctx->stream, ctx->ev_out, 0));

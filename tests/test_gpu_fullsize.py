@@ -4,7 +4,8 @@ shots advancing together in graph-replayed batched launches with the tuned
 tile height.  One shot carries data modelled by the FP64 oracle; the other
 shots carry zero data, so they do all the work of a shot but add exactly
 zero to the stack, which must then equal the oracle's image of that shot.
-The shots run in two shot groups (a reduced cache budget), as the
+The shots run in two shot groups (a reduced cache budget) on the two
+streams the batched path alternates its groups between, as the
 benchmark's shots do.  The oracle migrates with checkpointed source
 wavefields (bit-identical to storing them all) and takes about a minute on
 the host's cores."""
@@ -28,9 +29,11 @@ def rtm():
 
 
 def test_faulted_survey_full_size_batched_matches_oracle(rtm, monkeypatch):
-    # two shot groups of two shots each (the benchmark's 100 shots run in 13
-    # backward groups of 7-8 under the default cache budget)
-    monkeypatch.setenv("RTM_GROUP_KB", str(60 << 10))
+    # two backward shot groups of two shots each, one on each stream (60 MiB
+    # per group; the benchmark's 100 shots run in 27 backward groups of 3-4
+    # under the default cache budget)
+    monkeypatch.setenv("RTM_GROUP_STREAMS", "2")
+    monkeypatch.setenv("RTM_GROUP_KB", str(120 << 10))
     sv = inputs.faulted_survey(n_shots=100, nt=4000)
     sh = sv.shots[50]
     kw = dict(dz=sv.h, dx=sv.h, dt=sv.dt, nb=sv.nb, nt=sv.nt)

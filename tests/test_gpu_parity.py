@@ -421,12 +421,17 @@ def test_batch_with_illumination_in_shot_groups_equals_plain(rtm, ctx, mode, mon
     assert float(plain_il.abs().max()) > 0
 
 
+@pytest.mark.parametrize("streams", ["1", "2"])
 @pytest.mark.parametrize("group_kb", [None, "0", "600", "1"])
-def test_batch_equals_plain_bitwise(rtm, ctx, group_kb):
+def test_batch_equals_plain_bitwise(rtm, ctx, group_kb, streams, monkeypatch):
     """The batched path equals the plain path bit for bit, whatever the shot
-    groups: RTM_GROUP_KB unset (the default budget: one group at this size),
-    0 (one group), 600 KiB (groups of about two shots) and 1 KiB (one shot
-    per group)."""
+    groups and whether they run on one stream or alternate between two:
+    RTM_GROUP_KB unset (the default budget: one group at this size), 0 (one
+    group), 600 KiB per group (groups of about two shots) and 1 KiB (one
+    shot per group)."""
+    monkeypatch.setenv("RTM_GROUP_STREAMS", streams)
+    if group_kb == "600":  # two streams share the budget: the same groups
+        group_kb = str(600 * int(streams))
     rng = np.random.default_rng(6)
     nz, nx, h, dt, nt, nb = 60, 230, 10.0, 1e-3, 260, 10
     vel = inputs.smooth_slowness(1700 + 600 * rng.random((nz, nx)), 30.0, h, h)
@@ -456,7 +461,7 @@ def test_batch_equals_plain_bitwise(rtm, ctx, group_kb):
             torch.cuda.synchronize()
             assert torch.equal(plain, batch), (mode, group_kb, (plain - batch).abs().max().item())
             st = ctx.stats()
-            groups = {None: (1, 1), "0": (1, 1), "1": (6, 6)}.get(group_kb)
+            groups = {None: (1, 1), "0": (1, 1), "1": (6, 6)}.get(group_kb)  # else 600 KiB per group
             if groups is not None:
                 assert (st.last_groups_fwd, st.last_groups_bwd) == groups
             else:  # several shots per group, more groups in the backward phase
