@@ -47,6 +47,16 @@ STEP_SOURCES = ("paper_2001_06444_amd/csrc/rtm_kernels.hip", "paper_2001_06444_a
 CODEC_SOURCES = ("paper_2001_06444_amd/csrc/rtm_codec.hip", "paper_2001_06444_amd/csrc/rtm_codec.h")
 
 
+def group_streams() -> int:
+    """Streams the batched path alternates its shot groups over (the library
+    reads RTM_GROUP_STREAMS the same way: 1 to 4, default 2)."""
+    try:
+        v = int(os.environ.get("RTM_GROUP_STREAMS", "2"))
+    except ValueError:
+        v = 0
+    return max(1, min(v, 4))
+
+
 def kernel_source_hash(sources=STEP_SOURCES) -> str:
     h = hashlib.sha256()
     for p in sources:
@@ -274,7 +284,7 @@ def run_survey(args):
     # default the shot groups alternate between two streams whose launches
     # overlap, so these rates are the figure of the production setting.
     gfw, gbw = max(1, s1.last_groups_fwd), max(1, s1.last_groups_bwd)
-    phase = {"streams": 1 if os.environ.get("RTM_GROUP_STREAMS") == "1" else 2,
+    phase = {"streams": group_streams(),
              "shot_groups": {"forward": gfw, "backward": gbw},
              "tile_z2": {"forward": s1.last_tile_z2_fwd, "backward": s1.last_tile_z2_bwd},
              "backward_GBps": s1.last_bwd_launch_bytes * s1.last_bwd_launches / (s1.last_bwd_ms * 1e-3) / 1e9,

@@ -226,13 +226,18 @@ struct StatsAcc {
   Block mean, m2, count;
 };
 
+// most streams the batched path alternates its shot groups over
+constexpr int kMaxGroupStreams = 4;
+
 struct rtm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;        // caller's stream (plain / batched / copies)
   hipStream_t sched_stream = nullptr;  // scheduler thread's stream
   hipStream_t work_stream = nullptr;   // batched path (graph capture needs a non-null stream)
-  hipStream_t work_stream2 = nullptr;  // batched path: second stream of shot groups
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // batched path: further streams that shot groups alternate over, with
+  // the events that fork them from work_stream and join them back
+  hipStream_t group_stream[kMaxGroupStreams - 1] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kMaxGroupStreams - 1] = {};
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // phase timing of the last batched call (events on work_stream)
   hipEvent_t ph_ev[3] = {nullptr, nullptr, nullptr};
@@ -717,7 +722,7 @@ struct Table {
   DevJob* jobs = nullptr;
   Tile* tiles = nullptr;
   StepCtl* ctl = nullptr;
-  StepCtl* ctl2 = nullptr;  // the batched path's second stream of shot groups
+  StepCtl* side_ctl[kMaxGroupStreams - 1] = {};  // the batched path's further streams of shot groups
   int ntiles = 0;
   // two-step tiles (tz rows x 56 columns) of the forward and the backward
   // phase, with the receivers of each tile's middle region:
@@ -866,11 +871,13 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
     return fail(RTM_E_NOMEM, "arena exhausted (control block)");
   }
   t.ctl = static_cast<StepCtl*>(p);
-  if (!alloc_block(ctx, t.blocks, sizeof(StepCtl), &p)) {
-    release_blocks(ctx, t.blocks);
-    return fail(RTM_E_NOMEM, "arena exhausted (control block)");
+  for (auto& sc : t.side_ctl) {
+    if (!alloc_block(ctx, t.blocks, sizeof(StepCtl), &p)) {
+      release_blocks(ctx, t.blocks);
+      return fail(RTM_E_NOMEM, "arena exhausted (control block)");
+    }
+    sc = static_cast<StepCtl*>(p);
   }
-  t.ctl2 = static_cast<StepCtl*>(p);
   for (auto* tw : {&t.fw, &t.bw}) {
     if (tw->ntiles == 0) continue;
     if (!alloc_block(ctx, t.blocks, tw->htiles->size() * sizeof(Tile), &p)) {
@@ -892,7 +899,7 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   StepCtl c{};
   c.ntiles = t.ntiles;
   HIP_OK(hipMemcpyAsync(t.ctl, &c, sizeof c, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(t.ctl2, &c, sizeof c, hipMemcpyHostToDevice, s));
+  for (StepCtl* sc : t.side_ctl) HIP_OK(hipMemcpyAsync(sc, &c, sizeof c, hipMemcpyHostToDevice, s));
   HIP_OK(hipStreamSynchronize(s));  // host-side staging copies are complete
   return RTM_OK;
 }
@@ -1147,9 +1154,9 @@ extern "C" int rtm_ctx_create(rtm_ctx** out, int device, void* arena_dev, size_t
   ctx->arena.init(arena_dev, arena_bytes);
   HIP_OK(hipStreamCreateWithFlags(&ctx->sched_stream, hipStreamNonBlocking));
   HIP_OK(hipStreamCreateWithFlags(&ctx->work_stream, hipStreamNonBlocking));
-  HIP_OK(hipStreamCreateWithFlags(&ctx->work_stream2, hipStreamNonBlocking));
+  for (auto& gs : ctx->group_stream) HIP_OK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-  HIP_OK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  for (auto& e : ctx->ev_join) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
   for (auto& e : ctx->ph_ev) HIP_OK(hipEventCreate(&e));
@@ -1205,13 +1212,13 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
     reap(ctx, true);
   }
   (void)hipStreamSynchronize(ctx->work_stream);
-  (void)hipStreamSynchronize(ctx->work_stream2);
+  for (auto gs : ctx->group_stream) (void)hipStreamSynchronize(gs);
   reap(ctx, false);
   (void)hipStreamDestroy(ctx->sched_stream);
   (void)hipStreamDestroy(ctx->work_stream);
-  (void)hipStreamDestroy(ctx->work_stream2);
+  for (auto gs : ctx->group_stream) (void)hipStreamDestroy(gs);
   (void)hipEventDestroy(ctx->ev_fork);
-  (void)hipEventDestroy(ctx->ev_join);
+  for (auto e : ctx->ev_join) (void)hipEventDestroy(e);
   (void)hipEventDestroy(ctx->ev_in);
   (void)hipEventDestroy(ctx->ev_out);
   for (auto e : ctx->ph_ev) (void)hipEventDestroy(e);
@@ -1551,46 +1558,49 @@ static std::vector<std::pair<int, int>> shot_groups(const std::vector<JobGeom>& 
   return out;
 }
 
-// Streams the batched path runs its shot groups on (RTM_GROUP_STREAMS: 2,
-// the default, or 1).  With two, groups alternate between the work stream
-// and a second one, each with its own control block and captured graphs, so
-// one group's launches fill the workgroup slots another group's launch
-// leaves idle as it drains; each group then gets half the cache budget.
-// Measured on the 351 x 1701 survey (nt 1000, 200 MiB): 484 against 512 ms
-// per migration of 100 shots; one stream with groups of the same size took
-// 572 ms, so the gain is the overlap, not the smaller groups.
+// Streams the batched path runs its shot groups on (RTM_GROUP_STREAMS, 1 to
+// 4; default 2).  With several, the groups go to the work stream and the
+// context's further group streams in turn, each stream with its own control
+// block and captured graphs, so one group's launches fill the workgroup
+// slots another group's launch leaves idle as it drains; each group then
+// gets its share of the cache budget.  Measured on the 351 x 1701 survey
+// (nt 1000, 200 MiB): 484 ms per migration of 100 shots on two streams
+// against 512 ms on one; one stream with groups of the two-stream size took
+// 572 ms, so the gain is the overlap, not the smaller groups.  Three and
+// four streams (smaller groups again) took 550 and 522 ms.
 static int group_streams() {
   const char* e = getenv("RTM_GROUP_STREAMS");
-  return e && atoi(e) == 1 ? 1 : 2;
+  const int v = e ? atoi(e) : 2;
+  return std::max(1, std::min(v, kMaxGroupStreams));
 }
 
 // One phase of the batch, group by group: the group's control block is
 // pointed at its tile ranges with the tick at `tick0`, then the group's
 // steps run (a backward phase with two-step tiles opens with two one-step
-// launches).  With a second stream s2 the odd groups run there, forked from
-// s and joined back into it before the call returns (also on an error, so
-// that work deferred on s waits for both).  graph[0] and graph[1] keep the
-// graphs of the two streams.
-static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, hipStream_t s2, int tz, int ph, Table& t,
+// launches).  Group i runs on stream i mod nstreams (stream 0: s), the
+// further streams forked from s and joined back into it before the call
+// returns (also on an error, so that work deferred on s waits for them).
+// graph[k] keeps stream k's captured graph.
+static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, int nstreams, int tz, int ph, Table& t,
                             const std::vector<std::pair<int, int>>& groups, int tick0, int nsteps, int K,
-                            hipGraphExec_t (&graph)[2], bool two_step) {
+                            hipGraphExec_t (&graph)[kMaxGroupStreams], bool two_step) {
   const Table::TwoStep& tw = ph == kPhFwd ? t.fw : t.bw;
   const bool pairs = two_step && tw.ntiles > 0;
   const bool store = !t.hjobs->empty() && (*t.hjobs)[0].mode == kModeStore;  // one mode per batch
-  const bool two = s2 && groups.size() >= 2;
+  const int ns = std::max(1, std::min<int>(nstreams, (int)groups.size()));
   int grid[3] = {0, 0, 0};
   for (auto [a, b] : groups) {
     grid[0] = std::max(grid[0], t.first[b] - t.first[a]);
     if (pairs) grid[ph == kPhFwd ? 1 : 2] = std::max(grid[ph == kPhFwd ? 1 : 2], tw.first[b] - tw.first[a]);
   }
-  if (two) {
+  if (ns > 1) {
     HIP_OK(hipEventRecord(ctx->ev_fork, s));
-    HIP_OK(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+    for (int k = 1; k < ns; ++k) HIP_OK(hipStreamWaitEvent(ctx->group_stream[k - 1], ctx->ev_fork, 0));
   }
   auto run = [&](int gi, int a, int b) -> int {
-    const int side = two ? (gi & 1) : 0;
-    hipStream_t gs = side ? s2 : s;
-    StepCtl* ctl = side ? t.ctl2 : t.ctl;
+    const int side = gi % ns;
+    hipStream_t gs = side ? ctx->group_stream[side - 1] : s;
+    StepCtl* ctl = side ? t.side_ctl[side - 1] : t.ctl;
     StepCtl c{};
     c.tick = tick0;
     c.ntiles = t.first[b] - t.first[a];
@@ -1628,12 +1638,13 @@ static int run_phase_groups(rtm_ctx* ctx, hipStream_t s, hipStream_t s2, int tz,
   };
   int rc = RTM_OK;
   for (int gi = 0; gi < (int)groups.size() && !rc; ++gi) rc = run(gi, groups[gi].first, groups[gi].second);
-  if (two) {
-    const bool joined = hipEventRecord(ctx->ev_join, s2) == hipSuccess &&
-                        hipStreamWaitEvent(s, ctx->ev_join, 0) == hipSuccess;
+  for (int k = 1; k < ns; ++k) {
+    hipStream_t gs = ctx->group_stream[k - 1];
+    const bool joined = hipEventRecord(ctx->ev_join[k - 1], gs) == hipSuccess &&
+                        hipStreamWaitEvent(s, ctx->ev_join[k - 1], 0) == hipSuccess;
     if (!joined) {
-      (void)hipStreamSynchronize(s2);
-      if (!rc) rc = fail(RTM_E_DEVICE, "joining the second stream failed");
+      (void)hipStreamSynchronize(gs);
+      if (!rc) rc = fail(RTM_E_DEVICE, "joining a group stream failed");
     }
   }
   return rc;
@@ -1729,15 +1740,14 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     return rc;
   }
   const int nt = grid->nt, K = graph_k();
-  hipGraphExec_t graphs[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [phase][stream]
-  hipStream_t s2 = nstreams == 2 ? ctx->work_stream2 : nullptr;
+  hipGraphExec_t graphs[2][kMaxGroupStreams] = {};  // [phase][stream]
   HIP_OK(hipEventRecord(ctx->ph_ev[0], s));
   roctxRangePushA("rtm.batch.forward");  // host-side enqueue of the phase
-  rc = run_phase_groups(ctx, s, s2, tz, kPhFwd, t, gf, 0, nt - 1, K, graphs[0], true);
+  rc = run_phase_groups(ctx, s, nstreams, tz, kPhFwd, t, gf, 0, nt - 1, K, graphs[0], true);
   roctxRangePop();
   roctxRangePushA("rtm.batch.backward");
   if (!rc) rc = hipEventRecord(ctx->ph_ev[1], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
-  if (!rc) rc = run_phase_groups(ctx, s, s2, tz, kPhBwd, t, gb, nt - 1, nt, K, graphs[1], t.bw.ntiles > 0 && nt >= 4);
+  if (!rc) rc = run_phase_groups(ctx, s, nstreams, tz, kPhBwd, t, gb, nt - 1, nt, K, graphs[1], t.bw.ntiles > 0 && nt >= 4);
   roctxRangePop();
   if (!rc) rc = hipEventRecord(ctx->ph_ev[2], s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
   if (!rc) {

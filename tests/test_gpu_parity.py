@@ -421,11 +421,12 @@ def test_batch_with_illumination_in_shot_groups_equals_plain(rtm, ctx, mode, mon
     assert float(plain_il.abs().max()) > 0
 
 
-@pytest.mark.parametrize("streams", ["1", "2"])
+@pytest.mark.parametrize("streams", ["1", "2", "3"])
 @pytest.mark.parametrize("group_kb", [None, "0", "600", "1"])
 def test_batch_equals_plain_bitwise(rtm, ctx, group_kb, streams, monkeypatch):
     """The batched path equals the plain path bit for bit, whatever the shot
-    groups and whether they run on one stream or alternate between two:
+    groups and whether they run on one stream or alternate between two or
+    three:
     RTM_GROUP_KB unset (the default budget: one group at this size), 0 (one
     group), 600 KiB per group (groups of about two shots) and 1 KiB (one
     shot per group)."""
