@@ -207,8 +207,12 @@ typedef struct {
  * captured HIP graph, and the one-step tile shape comes from the autotuner.
  * All shots are resident at once; each phase runs them in groups of
  * consecutive shots whose levels fit the memory-side cache (RTM_GROUP_KB,
- * default 200 MiB of field bytes a launch touches; 0 runs all shots in every
- * launch), one group after another, which changes no result.
+ * default 200 MiB of field bytes the launches in flight touch; 0 runs all
+ * shots in every launch), the groups dealt in turn to RTM_GROUP_STREAMS
+ * streams (1 to 4, default 2; each group then gets its share of the budget)
+ * whose launches overlap, and groups on one stream one after another; none
+ * of this changes a result.  The call is ordered after the work already on
+ * ctx's stream, and work enqueued there afterwards waits for it.
  * Each shot's image is added into image_dev in shot order after all shots
  * finish (deterministic stack).  Shots with the same window (ix0, width)
  * share one c = v^2 dt^2 array and its sponge profiles, built once.  Same
