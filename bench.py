@@ -760,7 +760,11 @@ def run_born(args):
     out.update({"steps": len(shots), "warmup": 1,
                 "launch": {"us": launch_us, "alg_bytes": launch_bytes, "GB_per_s": gbs,
                            "note": "events around whole calls, launch gaps included; one shot's "
-                                   "working set fits the 256 MB Infinity Cache"}})
+                                   "working set fits the 256 MB Infinity Cache"},
+                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                             "kernel": "k_step<TZ,4> Born step (background and scattered field)",
+                             "alg_bytes_per_launch": launch_bytes, "launch_us": launch_us}})
     return out
 
 # Algorithmic bytes per pixel of the Stage-3 maps and the filter: every input
