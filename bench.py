@@ -719,8 +719,10 @@ def run_small(args):
 
 
 def run_born(args):
-    """Born modelling of survey shots at full size (plain path, one launch per
-    step advancing background and scattered field together)."""
+    """Born modelling of survey shots at full size: the shots one after the
+    other through rtm_born (one launch per step and shot), then the same
+    shots together through rtm_born_batch (one launch per step advancing
+    every shot's background and scattered field)."""
     import numpy as np
     import torch
 
@@ -733,38 +735,60 @@ def run_born(args):
     vm, wav = t(sv.vel_mig), t(sv.wavelet)
     mpert = t(sv.vel_true - sv.vel_mig)
     grid = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
-    ctx = rtm.Context(0, arena_bytes=2 << 30)
-    shots = sv.shots[:: max(1, len(sv.shots) // max(args.shots if args.shots != 100 else 4, 1))][:4]
-    dd = torch.empty(nt, nx, device=dev)
-    ctx.born(grid, vm, wav, shots[0].src, mpert, shots[0].rec, dd)  # warm-up (tiles tuned)
+    ctx = rtm.Context(0, arena_bytes=4 << 30)
+    # 16 shots per launch: a launch's time per shot and step falls from 6.6 us
+    # (one shot, 792 workgroups) to 4.7 us at 12 shots and stays there
+    nsh = 16
+    shots = sv.shots[:: len(sv.shots) // nsh][:nsh]
+    dd = [torch.empty(nt, len(sh.rec), device=dev) for sh in shots]
+    ctx.born(grid, vm, wav, shots[0].src, mpert, shots[0].rec, dd[0])  # warm-up (tiles tuned)
+    ctx.born_batch(grid, vm, wav, mpert, [(sh.src, sh.rec, d) for sh, d in zip(shots, dd)])
     torch.cuda.synchronize()
-    u0 = ctx.stats().grid_updates
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for sh in shots:
-        ctx.born(grid, vm, wav, sh.src, mpert, sh.rec, dd)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    upd = ctx.stats().grid_updates - u0
+
+    def timed(fn):
+        u0 = ctx.stats().grid_updates
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), ctx.stats().grid_updates - u0
+
+    def plain():
+        for sh, d in zip(shots, dd):
+            ctx.born(grid, vm, wav, sh.src, mpert, sh.rec, d)
+
+    ms_p, upd_p = timed(plain)
+    ms_b, upd_b = timed(lambda: ctx.born_batch(grid, vm, wav, mpert,
+                                               [(sh.src, sh.rec, d) for sh, d in zip(shots, dd)]))
     npad, nph = (nz + 2 * nb) * (nx + 2 * nb), nz * nx
-    launch_bytes = npad * 28 + nph * 4 + nx * 4
-    launch_us = ms * 1e3 / (len(shots) * (nt - 1))
-    gbs = launch_bytes / (launch_us * 1e-6) / 1e9
-    log(f"[bench] born: {len(shots)} shots, {upd / (ms * 1e-3):.3e} updates/s, {launch_us:.1f} us/launch, "
-        f"{gbs:.0f} GB/s (working set of one shot: {npad * 4 * 5 / 2**20:.0f} MiB, cache-resident)")
+    nrec = sum(len(sh.rec) for sh in shots)
+    # per step and shot: c 4 B, background 12 B, scattered field 12 B per padded
+    # point, m 4 B per physical point, 4 B per receiver sample; a batched launch
+    # reads c and m once for all its shots
+    plain_bytes = npad * 28 + nph * 4 + nrec / nsh * 4
+    batch_bytes = nsh * npad * 24 + npad * 4 + nph * 4 + nrec * 4
+    plain_us = ms_p * 1e3 / (nsh * (nt - 1))
+    batch_us = ms_b * 1e3 / (nt - 1)
+    gbs_p = plain_bytes / (plain_us * 1e-6) / 1e9
+    gbs_b = batch_bytes / (batch_us * 1e-6) / 1e9
+    log(f"[bench] born, {nsh} shots one by one: {upd_p / (ms_p * 1e-3):.3e} updates/s, {plain_us:.1f} us/launch, "
+        f"{gbs_p:.0f} GB/s")
+    log(f"[bench] born, {nsh} shots batched: {upd_b / (ms_b * 1e-3):.3e} updates/s, {batch_us:.1f} us/launch, "
+        f"{gbs_b:.0f} GB/s")
     ctx.close()
-    out = _base_record(args, upd / (ms * 1e-3), ms / len(shots), {
-        "workload": f"Born modelling, faulted-layer survey {nz}x{nx}, nt={nt}, nb={nb}, "
-                    f"{len(shots)} shots one after the other", "path": "plain (one launch per step)"})
-    out.update({"steps": len(shots), "warmup": 1,
-                "launch": {"us": launch_us, "alg_bytes": launch_bytes, "GB_per_s": gbs,
-                           "note": "events around whole calls, launch gaps included; one shot's "
-                                   "working set fits the 256 MB Infinity Cache"},
-                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                             "kernel": "k_step<TZ,4> Born step (background and scattered field)",
-                             "alg_bytes_per_launch": launch_bytes, "launch_us": launch_us}})
+    out = _base_record(args, upd_b / (ms_b * 1e-3), ms_b, {
+        "workload": f"Born modelling, faulted-layer survey {nz}x{nx}, nt={nt}, nb={nb}, {nsh} shots "
+                    "in shared launches", "path": "batched (one launch per step for all shots)"})
+    out.update({"steps": 1, "warmup": 1,
+                "plain": {"updates_per_s": upd_p / (ms_p * 1e-3), "launch_us": plain_us, "GB_per_s": gbs_p,
+                          "alg_bytes_per_launch": plain_bytes},
+                "batched_vs_plain": ms_p / ms_b,
+                "roofline": {"bound": "hbm", "achieved": gbs_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs_b / HBM_PEAK_GBS, "traffic": None,
+                             "kernel": f"k_step<TZ,4> Born step over {nsh} shots (background and scattered field)",
+                             "alg_bytes_per_launch": batch_bytes, "launch_us": batch_us,
+                             "note": "events around the whole call, launch gaps included"}})
     return out
 
 # Algorithmic bytes per pixel of the Stage-3 maps and the filter: every input

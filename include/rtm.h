@@ -169,6 +169,26 @@ int rtm_born(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev, const flo
              rtm_point src, const float *mpert_dev, int32_t nrec, const rtm_point *rec_host,
              float *dtraces_dev);
 
+/* One shot of a Born batch: source, receivers and its output traces. */
+typedef struct {
+    rtm_point src;
+    int32_t nrec;
+    const rtm_point *rec_host; /* [nrec], model coordinates, pairwise distinct */
+    float *dtraces_dev;        /* [nt][nrec] out: du^n at the receivers */
+} rtm_born_shot;
+
+/* Born modelling of nshots shots of one model and one perturbation (the
+ * linearised operator of rtm_born, Sec. 3 reverse problem) in shared
+ * kernel launches: each launch advances every shot's background and
+ * scattered field by one time step, and the shots read one c array and one
+ * copy of mpert_dev.  Each shot's dtraces equal rtm_born's for that shot
+ * bit for bit.  shots_host [nshots] is read at call time; the other
+ * arguments as in rtm_born.  Stream-ordered on ctx's stream.
+ * Errors: RTM_E_INVAL (no shots, bad nodes, missing dtraces_dev),
+ * RTM_E_CFL, RTM_E_NOMEM (the whole batch must fit the arena). */
+int rtm_born_batch(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev, const float *wavelet_dev,
+                   const float *mpert_dev, int32_t nshots, const rtm_born_shot *shots_host);
+
 /* Reverse time migration of one shot on the aperture window
  * [ix0, ix0 + width) of the model (Sec. 2.2, Eq. 5 numerator; the per-shot
  * forward + adjoint pair of the paper's migration code).

@@ -1233,10 +1233,12 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
 // ===========================================================================
 // Plain path
 // ===========================================================================
-static int run_plain(rtm_ctx* ctx, hipStream_t s, HostJob& j, int tz, Table& t) {
-  std::vector<HostJob*> js{&j};
+// One launch per time step over the tiles of every job in js (jobs of one
+// mode and step count: a single job, or the shots of a Born batch).
+static int run_plain_jobs(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, int tz, Table& t) {
   int rc = upload_table(ctx, s, js, t, 0, 0);
   if (rc) return rc;
+  const HostJob& j = *js[0];
   const int nsteps = j.d.nsteps;
   const int nf = j.g.mode == kModeModel ? nsteps : j.g.nt - 1;
   for (int st = 0; st < nsteps; ++st) {
@@ -1245,6 +1247,10 @@ static int run_plain(rtm_ctx* ctx, hipStream_t s, HostJob& j, int tz, Table& t) 
   }
   ctx->steps_launched += nsteps;
   return RTM_OK;
+}
+
+static int run_plain(rtm_ctx* ctx, hipStream_t s, HostJob& j, int tz, Table& t) {
+  return run_plain_jobs(ctx, s, std::vector<HostJob*>{&j}, tz, t);
 }
 
 static void finish_job_deferred(rtm_ctx* ctx, hipStream_t s, HostJob& j, Table& t, bool keep_image) {
@@ -1302,15 +1308,8 @@ extern "C" int rtm_propagate(rtm_ctx* ctx, const rtm_grid* grid, const float* ve
   return RTM_OK;
 }
 
-extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev, const float* wavelet_dev,
-                        rtm_point src, const float* mpert_dev, int32_t nrec, const rtm_point* rec_host,
-                        float* dtraces_dev) {
-  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
-  int rc = check_grid(grid);
-  if (rc) return rc;
-  if (!vel_dev || !wavelet_dev || !mpert_dev) return fail(RTM_E_INVAL, "vel_dev, wavelet_dev, mpert_dev are required");
-  if (nrec > 0 && !dtraces_dev) return fail(RTM_E_INVAL, "dtraces_dev is required when nrec > 0");
-  JobGeom g;
+// A Born job runs over the whole model.
+static void born_geom(const rtm_grid* grid, int32_t nrec, JobGeom& g) {
   g.nz = grid->nz;
   g.model_nx = grid->nx;
   g.ix0 = 0;
@@ -1323,6 +1322,18 @@ extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev
   g.sponge_a = grid->sponge_a;
   g.mode = kModeBorn;
   g.nrec = nrec;
+}
+
+extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev, const float* wavelet_dev,
+                        rtm_point src, const float* mpert_dev, int32_t nrec, const rtm_point* rec_host,
+                        float* dtraces_dev) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!vel_dev || !wavelet_dev || !mpert_dev) return fail(RTM_E_INVAL, "vel_dev, wavelet_dev, mpert_dev are required");
+  if (nrec > 0 && !dtraces_dev) return fail(RTM_E_INVAL, "dtraces_dev is required when nrec > 0");
+  JobGeom g;
+  born_geom(grid, nrec, g);
   if ((rc = check_job(g, src, rec_host))) return rc;
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
@@ -1345,6 +1356,74 @@ extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev
   ctx->alg_bytes += j.alg_bytes;
   finish_job_deferred(ctx, s, j, t, false);
   return RTM_OK;
+}
+
+// Born modelling of several shots in shared launches: every shot's job reads
+// the first job's c, sponge profiles and perturbation (the Born step only
+// reads them), and each launch advances the Born step of every shot.
+extern "C" int rtm_born_batch(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev, const float* wavelet_dev,
+                              const float* mpert_dev, int32_t nshots, const rtm_born_shot* shots) {
+  if (!ctx) return fail(RTM_E_INVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!vel_dev || !wavelet_dev || !mpert_dev) return fail(RTM_E_INVAL, "vel_dev, wavelet_dev, mpert_dev are required");
+  if (nshots < 1 || !shots) return fail(RTM_E_INVAL, "need at least one shot");
+  std::vector<JobGeom> geoms(nshots);
+  size_t need = 0;
+  for (int i = 0; i < nshots; ++i) {
+    born_geom(grid, shots[i].nrec, geoms[i]);
+    if (shots[i].nrec > 0 && !shots[i].dtraces_dev) return fail(RTM_E_INVAL, "shot %d has no dtraces_dev", i);
+    if ((rc = check_job(geoms[i], shots[i].src, shots[i].rec_host))) return rc;
+    need += footprint(geoms[i]).total - (i ? medium_bytes(geoms[i]) : 0);
+  }
+  if (need > ctx->arena.size())
+    return fail(RTM_E_NOMEM, "batch needs %zu bytes, arena holds %zu", need, ctx->arena.size());
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  float vmax = 0;
+  if ((rc = device_vmax(ctx, s, vel_dev, grid->nz, grid->nx, 0, grid->nx, &vmax))) return rc;
+  if ((rc = check_cfl(vmax, grid->dt, grid->dz, grid->dx))) return rc;
+  const int tz = autotune_tz(ctx, s, geoms[0], vel_dev, nshots);
+  std::vector<std::unique_ptr<HostJob>> jobs;
+  std::vector<HostJob*> ptrs;
+  for (int i = 0; i < nshots; ++i) {
+    auto j = std::make_unique<HostJob>();
+    rc = build_job(ctx, s, geoms[i], tz, vel_dev, wavelet_dev, shots[i].src, shots[i].rec_host, nullptr,
+                   shots[i].dtraces_dev, *j, i ? jobs[0].get() : nullptr);
+    if (rc) {
+      (void)hipStreamSynchronize(s);
+      for (auto& o : jobs) {
+        release_blocks(ctx, o->blocks);
+        if (o->image_blk.p) ctx->arena.release(o->image_blk.p, o->image_blk.n);
+      }
+      return rc;
+    }
+    ptrs.push_back(j.get());
+    jobs.push_back(std::move(j));
+  }
+  // the perturbation, once, in the first job's image buffer (field-aligned
+  // rows, padded columns); the other jobs read it there
+  HostJob& j0 = *jobs[0];
+  rc = hipMemcpy2DAsync(j0.d.image + j0.g.nb, (size_t)j0.d.pitch * 4, mpert_dev, (size_t)j0.g.width * 4,
+                        (size_t)j0.g.width * 4, j0.g.nz, hipMemcpyDeviceToDevice, s) == hipSuccess
+           ? RTM_OK
+           : fail(RTM_E_DEVICE, "perturbation copy failed");
+  for (auto& j : jobs) j->d.image = j0.d.image;
+  Table t;
+  if (!rc) rc = run_plain_jobs(ctx, s, ptrs, tz, t);
+  Deferred d;
+  for (auto& j : jobs) {
+    for (auto& b : j->blocks) d.blocks.push_back(b);
+    j->blocks.clear();
+    if (j->image_blk.p) d.blocks.push_back(j->image_blk);
+    ctx->grid_updates += rc ? 0 : j->updates;
+    ctx->alg_bytes += rc ? 0 : j->alg_bytes;
+  }
+  for (auto& b : t.blocks) d.blocks.push_back(b);
+  d.keep.push_back(t.hjobs);
+  d.keep.push_back(t.htiles);
+  int rc2 = defer(ctx, s, std::move(d));
+  return rc ? rc : rc2;
 }
 
 static int fill_geom_rtm(const rtm_grid* grid, int32_t ix0, int32_t width, const rtm_img_opts* opts, int nrec,

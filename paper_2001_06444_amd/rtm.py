@@ -50,6 +50,11 @@ class ShotDesc(ctypes.Structure):
                 ("data_dev", ctypes.c_void_p)]
 
 
+class BornShot(ctypes.Structure):
+    _fields_ = [("src", Point), ("nrec", ctypes.c_int32), ("rec_host", ctypes.POINTER(Point)),
+                ("dtraces_dev", ctypes.c_void_p)]
+
+
 class Job(ctypes.Structure):
     _fields_ = [("realization", ctypes.c_int32), ("src", Point), ("ix0", ctypes.c_int32),
                 ("width", ctypes.c_int32), ("rec_iz", ctypes.c_int32), ("nt", ctypes.c_int32),
@@ -108,6 +113,7 @@ SIGNATURES = {
     "rtm_ctx_synchronize": ([_V], ctypes.c_int),
     "rtm_propagate": ([_V, _P(Grid), _V, _V, Point, _I32, _P(Point), _V, _V], ctypes.c_int),
     "rtm_born": ([_V, _P(Grid), _V, _V, Point, _V, _I32, _P(Point), _V], ctypes.c_int),
+    "rtm_born_batch": ([_V, _P(Grid), _V, _V, _V, _I32, _P(BornShot)], ctypes.c_int),
     "rtm_stats_merge": ([_V, _V, _V], ctypes.c_int),
     "rtm_normalize_image": ([_V, _V, _V, _I32, _F, _V], ctypes.c_int),
     "rtm_migrate_shot": ([_V, _P(Grid), _V, _V, Point, _I32, _P(Point), _V, _I32, _I32,
@@ -254,6 +260,20 @@ class Context:
         recs, n = _points(rec)
         _check(lib().rtm_born(self.h, ctypes.byref(grid), _ptr(vel), _ptr(wavelet), Point(*src),
                               _ptr(mpert), n, recs, _ptr(dtraces)))
+
+    def born_batch(self, grid: Grid, vel, wavelet, mpert, shots):
+        """shots: sequence of (src, rec_points, dtraces_tensor)."""
+        descs = (BornShot * len(shots))()
+        keep = []
+        for i, (src, rec, dtraces) in enumerate(shots):
+            recs, n = _points(rec)
+            keep.append(recs)
+            descs[i].src = Point(*src)
+            descs[i].nrec = n
+            descs[i].rec_host = ctypes.cast(recs, ctypes.POINTER(Point))
+            descs[i].dtraces_dev = _ptr(dtraces)
+        _check(lib().rtm_born_batch(self.h, ctypes.byref(grid), _ptr(vel), _ptr(wavelet), _ptr(mpert),
+                                    len(shots), descs))
 
     def migrate_shot(self, grid: Grid, vel, wavelet, src, rec, data, ix0, width, opts: ImgOpts,
                      image, illum=None):

@@ -57,6 +57,41 @@ def test_born_matches_oracle(rtm, ctx):
     assert e <= 5e-5
 
 
+def test_born_batch_equals_born_per_shot(rtm, ctx):
+    """Born shots advanced together in shared launches (one c, one copy of the
+    perturbation) give each shot's rtm_born traces bit for bit: sources in
+    the interior, at the model's edge column and inside the first physical
+    row, receiver sets of different sizes, one shot without receivers; and
+    the first shot against the oracle."""
+    vel = _model(4)
+    nz, nx = vel.shape
+    nt, h, dt, nb = 260, 10.0, 1e-3, 10
+    w = inputs.ricker(nt, dt, fp=25)
+    m = np.random.default_rng(5).standard_normal((nz, nx))
+    g = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    specs = [((3, 70), [(1, i) for i in range(0, nx, 2)]),
+             ((0, nx - 1), [(2, i) for i in range(5, 120, 3)]),
+             ((20, 0), [(0, 0), (nz - 1, nx - 1), (10, 75)]),
+             ((12, 33), [])]
+    shots, singles = [], []
+    for src, rec in specs:
+        out = torch.full((nt, max(len(rec), 1)), float("nan"), device="cuda")
+        shots.append((src, rec, out if rec else None))
+        one = torch.full((nt, max(len(rec), 1)), float("nan"), device="cuda")
+        ctx.born(g, dev(vel), dev(w), src, dev(m), rec, one if rec else None)
+        singles.append(one)
+    ctx.born_batch(g, dev(vel), dev(w), dev(m), shots)
+    torch.cuda.synchronize()
+    for (src, rec, out), one in zip(shots, singles):
+        if rec:
+            assert torch.equal(out, one), src
+            assert torch.isfinite(out).all()
+    ref = oracle.born(vel, w, specs[0][0], m, specs[0][1], dz=h, dx=h, dt=dt, nb=nb, nt=nt)
+    assert oracle.rel_l2(host(shots[0][2]), ref) <= 5e-5
+    with pytest.raises(rtm.RTMError):
+        ctx.born_batch(g, dev(vel), dev(w), dev(m), [])
+
+
 @pytest.mark.parametrize("mode", ["store", "reconstruct"])
 def test_gpu_only_dot_product(rtm, ctx, mode):
     """<Born_gpu m, d> = <m, Mig_gpu d> with both operators on the GPU."""
