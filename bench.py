@@ -764,18 +764,23 @@ def run_born(args):
     npad, nph = (nz + 2 * nb) * (nx + 2 * nb), nz * nx
     nrec = sum(len(sh.rec) for sh in shots)
     # per step and shot: c 4 B, background 12 B, scattered field 12 B per padded
-    # point, m 4 B per physical point, 4 B per receiver sample; a batched launch
-    # reads c and m once for all its shots
+    # point, m 4 B per physical point, 4 B per receiver sample (the one-step
+    # minimum, which a two-step launch undercuts); a batched launch reads c
+    # and m once for all its shots
     plain_bytes = npad * 28 + nph * 4 + nrec / nsh * 4
     batch_bytes = nsh * npad * 24 + npad * 4 + nph * 4 + nrec * 4
-    plain_us = ms_p * 1e3 / (nsh * (nt - 1))
-    batch_us = ms_b * 1e3 / (nt - 1)
+    # launches advance two steps (Born pairs) unless RTM_TILE_Z2=0; the
+    # per-launch figures are those of the steps a launch takes
+    spl = 1 if os.environ.get("RTM_TILE_Z2") == "0" else 2
+    plain_us = spl * ms_p * 1e3 / (nsh * (nt - 1))
+    batch_us = spl * ms_b * 1e3 / (nt - 1)
+    plain_bytes, batch_bytes = spl * plain_bytes, spl * batch_bytes
     gbs_p = plain_bytes / (plain_us * 1e-6) / 1e9
     gbs_b = batch_bytes / (batch_us * 1e-6) / 1e9
-    log(f"[bench] born, {nsh} shots one by one: {upd_p / (ms_p * 1e-3):.3e} updates/s, {plain_us:.1f} us/launch, "
-        f"{gbs_p:.0f} GB/s")
-    log(f"[bench] born, {nsh} shots batched: {upd_b / (ms_b * 1e-3):.3e} updates/s, {batch_us:.1f} us/launch, "
-        f"{gbs_b:.0f} GB/s")
+    log(f"[bench] born, {nsh} shots one by one: {upd_p / (ms_p * 1e-3):.3e} updates/s, {plain_us:.1f} us/launch "
+        f"({spl} steps), {gbs_p:.0f} GB/s")
+    log(f"[bench] born, {nsh} shots batched: {upd_b / (ms_b * 1e-3):.3e} updates/s, {batch_us:.1f} us/launch "
+        f"({spl} steps), {gbs_b:.0f} GB/s")
     ctx.close()
     out = _base_record(args, upd_b / (ms_b * 1e-3), ms_b, {
         "workload": f"Born modelling, faulted-layer survey {nz}x{nx}, nt={nt}, nb={nb}, {nsh} shots "
@@ -786,7 +791,9 @@ def run_born(args):
                 "batched_vs_plain": ms_p / ms_b,
                 "roofline": {"bound": "hbm", "achieved": gbs_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": gbs_b / HBM_PEAK_GBS, "traffic": None,
-                             "kernel": f"k_step<TZ,4> Born step over {nsh} shots (background and scattered field)",
+                             "kernel": (f"k_step2<TZ2,4> Born pair (two steps per launch)" if spl == 2 else
+                                        "k_step<TZ,4> Born step") + f" over {nsh} shots (background and scattered field)",
+                             "steps_per_launch": spl,
                              "alg_bytes_per_launch": batch_bytes, "launch_us": batch_us,
                              "note": "events around the whole call, launch gaps included"}})
     return out

@@ -1193,6 +1193,160 @@ __device__ __forceinline__ void backward2_store_body(const DevJob& J, const Tile
   }
 }
 
+// One two-step Born tile: the background u0 and the scattered field du
+// from level n to n + 2, each step the Born step of born_tile (same
+// operations on the same operands), and the receiver samples of du^{n+1}
+// and du^{n+2} for the receivers on the output tile (a receiver in the
+// middle region only is sampled by the tile whose output tile holds it).
+template <int TZ, class Smem>
+__device__ __forceinline__ void born2_body(const DevJob& J, const Tile& tl, const int2* __restrict__ recs2, int n,
+                                           Smem& sm) {
+  constexpr int RA = (TZ + 2 * kHalo) / 4;
+  constexpr int RB = TZ / 4;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
+  const int pitch = J.pitch;
+  const RTM_GLOBAL float* __restrict__ u0 = gp(J.f[n & 3]);        // u0^n
+  const RTM_GLOBAL float* __restrict__ um = gp(J.f[(n + 3) & 3]);  // u0^{n-1}
+  RTM_GLOBAL float* __restrict__ u1 = gp(J.f[(n + 1) & 3]);        // u0^{n+1}
+  RTM_GLOBAL float* __restrict__ u2 = gp(J.f[(n + 2) & 3]);        // u0^{n+2}
+  const RTM_GLOBAL float* __restrict__ d0 = gp(J.r[n & 3]);        // du^n
+  const RTM_GLOBAL float* __restrict__ dm = gp(J.r[(n + 3) & 3]);  // du^{n-1}
+  RTM_GLOBAL float* __restrict__ d1 = gp(J.r[(n + 1) & 3]);        // du^{n+1}
+  RTM_GLOBAL float* __restrict__ d2 = gp(J.r[(n + 2) & 3]);        // du^{n+2}
+  const RTM_GLOBAL float* __restrict__ mp = gp(J.image);           // m, physical window
+  const RTM_GLOBAL float* __restrict__ cc = gp(J.c);
+  const RTM_GLOBAL float* __restrict__ gz = gp(J.gz);
+  const RTM_GLOBAL float* __restrict__ gx = gp(J.gx);
+  const int x = tl.x0 - kHalo + lane;
+  const int za0 = tl.z0 - kHalo + w * RA;
+  const int zb0 = tl.z0 + w * RB;
+  const bool xin = x >= 0 && x < J.nxp;
+  const bool xout = lane >= kHalo && lane < kHalo + kTileX2 && x < J.nxp;
+  const uint32_t xcl = (uint32_t)min(max(x, 0), J.nxp - 1);
+  const int px = x - J.nb;
+  const bool colphys = px >= 0 && px < J.nx;
+  const uint32_t xph = (uint32_t)min(max(x, J.nb), J.nb + J.nx - 1);  // column clamped into the window
+
+  // ---- every global load first ----
+  TileStageW<TZ + 4 * kHalo> sa, sb;
+  sa.load(u0, pitch, tl.z0 - 2 * kHalo, tl.x0 - 2 * kHalo);
+  sb.load(d0, pitch, tl.z0 - 2 * kHalo, tl.x0 - 2 * kHalo);
+  float cva[RA], pva[RA], qva[RA], gza[RA], mva[RA];
+#pragma unroll
+  for (int k = 0; k < RA; ++k) {
+    const int zc = min(max(za0 + k, 0), J.nzp - 1);
+    const uint32_t off = (uint32_t)zc * (uint32_t)pitch + xcl;
+    cva[k] = ld_medium(at(cc, off));
+    pva[k] = ld_cached(at(um, off));
+    qva[k] = ld_cached(at(dm, off));
+    gza[k] = gz[zc];
+    const int pzc = min(max(za0 + k - J.nb, 0), J.nz - 1);
+    mva[k] = ld_medium(at(mp, (uint32_t)pzc * (uint32_t)pitch + xph));
+  }
+  float cvb[RB], gzb[RB], mvb[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int zc = min(zb0 + k, J.nzp - 1);
+    cvb[k] = ld_medium(at(cc, (uint32_t)zc * (uint32_t)pitch + xcl));
+    gzb[k] = gz[zc];
+    const int pzc = min(max(zb0 + k - J.nb, 0), J.nz - 1);
+    mvb[k] = ld_medium(at(mp, (uint32_t)pzc * (uint32_t)pitch + xph));
+  }
+  const float gxv = xin ? gx[xcl] : 0.0f;
+  const float w0 = gp(J.wavelet)[n] * J.inv_cell;
+  const float w1 = gp(J.wavelet)[n + 1] * J.inv_cell;
+  sa.store(sm.a);
+  sb.store(sm.b);
+  __syncthreads();
+
+  const float c0 = J.c0;
+  const float cz[4] = {J.cz[0], J.cz[1], J.cz[2], J.cz[3]};
+  const float cx[4] = {J.cx[0], J.cx[1], J.cx[2], J.cx[3]};
+
+  // ---- first step: u0^{n+1} and du^{n+1} on the middle region ----
+  {
+    float zu[RA + 8], zd[RA + 8];
+#pragma unroll
+    for (int j = 0; j < RA + 8; ++j) {
+      zu[j] = sm.a[(w * RA + j) * kLdsW + lane + kHalo];
+      zd[j] = sm.b[(w * RA + j) * kLdsW + lane + kHalo];
+    }
+#pragma clang loop unroll(full)
+    for (int k = 0; k < RA; ++k) {
+      const int r = w * RA + k;  // middle row (wavefront-uniform)
+      const int z = za0 + k;
+      const float G = gza[k] * gxv;
+      const float u = zu[k + 4];
+      float lu = lap8<RA>(sm.a, r + kHalo, lane + kHalo, zu, k, c0, cz, cx);
+      if (z == J.src_z && x == J.src_x) lu = add_unfused(lu, w0);
+      float un = leapfrog(G, cva[k], lu, u, pva[k]);
+      float ld = lap8<RA>(sm.b, r + kHalo, lane + kHalo, zd, k, c0, cz, cx);
+      const int pz = z - J.nb;
+      if (colphys && pz >= 0 && pz < J.nz) ld = fmaf(mva[k], u, ld);
+      float dn = leapfrog(G, cva[k], ld, zd[k + 4], qva[k]);
+      const bool inside = xin && z >= 0 && z < J.nzp;
+      un = inside ? un : 0.0f;
+      dn = inside ? dn : 0.0f;
+      sm.ma[r * kTileX + lane] = un;
+      sm.mb[r * kTileX + lane] = dn;
+      if (r >= kHalo && r < TZ + kHalo && z < J.nzp && xout) {  // a node of the output tile
+        const uint32_t off = (uint32_t)z * (uint32_t)pitch + (uint32_t)x;
+        st_cached(at(u1, off), un);
+        st_cached(at(d1, off), dn);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- second step: u0^{n+2} and du^{n+2} on the output tile ----
+  float dout[RB];
+  {
+    float zu[RB + 8], zd[RB + 8];
+#pragma unroll
+    for (int j = 0; j < RB + 8; ++j) {
+      zu[j] = sm.ma[(w * RB + j) * kTileX + lane];
+      zd[j] = sm.mb[(w * RB + j) * kTileX + lane];
+    }
+#pragma clang loop unroll(full)
+    for (int k = 0; k < RB; ++k) {
+      const int z = zb0 + k;
+      dout[k] = 0.0f;
+      if (xout && z < J.nzp) {
+        const float G = gzb[k] * gxv;
+        const int lrow = (w * RB + k + 2 * kHalo) * kLdsW + lane + kHalo;  // centre in the staged tiles
+        const float u = zu[k + 4];
+        float lu = lap8<RB, kTileX>(sm.ma, w * RB + k + kHalo, lane, zu, k, c0, cz, cx);
+        if (z == J.src_z && x == J.src_x) lu = add_unfused(lu, w1);
+        const uint32_t off = (uint32_t)z * (uint32_t)pitch + (uint32_t)x;
+        st_cached(at(u2, off), leapfrog(G, cvb[k], lu, u, sm.a[lrow]));
+        float ld = lap8<RB, kTileX>(sm.mb, w * RB + k + kHalo, lane, zd, k, c0, cz, cx);
+        const int pz = z - J.nb;
+        if (colphys && pz >= 0 && pz < J.nz) ld = fmaf(mvb[k], u, ld);
+        const float dn = leapfrog(G, cvb[k], ld, zd[k + 4], sm.b[lrow]);
+        st_cached(at(d2, off), dn);
+        dout[k] = dn;
+      }
+    }
+  }
+
+  // ---- receiver samples of du^{n+1} (middle region array) and du^{n+2} ----
+  if (tl.rec_count > 0 && J.traces != nullptr) {  // workgroup-uniform
+    __syncthreads();  // every wavefront is done with sm.ma
+#pragma unroll
+    for (int k = 0; k < RB; ++k) sm.ma[(w * RB + k + kHalo) * kTileX + lane] = dout[k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < tl.rec_count; i += kThreads) {
+      const int2 e = recs2[tl.rec_begin + i];
+      const int r = e.x / kTileX, c = e.x - r * kTileX;
+      if (r >= kHalo && r < TZ + kHalo && c >= kHalo && c < kHalo + kTileX2) {
+        gp(J.traces)[(int64_t)(n + 1) * J.nrec + e.y] = sm.mb[e.x];
+        gp(J.traces)[(int64_t)(n + 2) * J.nrec + e.y] = sm.ma[e.x];
+      }
+    }
+  }
+}
+
 template <int TZ, class Smem>
 __device__ __forceinline__ void backward2_tile(const DevJob& J, const Tile& tl, const int2* recs2, int m,
                                                Smem& sm) {
@@ -1221,7 +1375,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ j
                                                      const int2* __restrict__ recs2,
                                                      const StepCtl* __restrict__ ctl, int ntiles_arg,
                                                      int use_ctl_tick, int tick_off) {
-  __shared__ Step2Smem<TZ, (PH & kPhBwd) != 0, !kStore> sm;
+  __shared__ Step2Smem<TZ, (PH & (kPhBwd | kPhBorn)) != 0, !kStore> sm;
   // Steps tick and tick + 1 of every job; same XCD-aware mapping as k_step,
   // except that every other launch walks each XCD's run of tiles backwards:
   // it then starts on the tiles the previous launch wrote last, whose data
@@ -1243,6 +1397,10 @@ __global__ __launch_bounds__(kThreads) void k_step2(const DevJob* __restrict__ j
   const Tile tl = tiles[t];
   const DevJob& J = jobs[tl.job];
   const int s = tick - J.start_tick;
+  if constexpr (PH == kPhBorn) {  // Born pairs: steps s, s + 1 (s even) of the job's nsteps
+    if (J.mode == kModeBorn && s >= 0 && (s & 1) == 0 && s + 1 < J.nsteps) born2_body<TZ>(J, tl, recs2, s, sm);
+    return;
+  }
   if (J.mode != (kStore ? kModeStore : kModeRecon) || J.illum != nullptr ||
       !two_step_pair(s, J.nt, J.nsteps, J.mode))
     return;
@@ -1348,6 +1506,7 @@ hipError_t launch_step2(int tz, int phases, int store, const DevJob* jobs, const
     else if (phases == kPhBwd && !store) RTM_STEP2(T, kPhBwd, false); \
     else if (phases == kPhFwd) RTM_STEP2(T, kPhFwd, true);    \
     else if (phases == kPhBwd) RTM_STEP2(T, kPhBwd, true);    \
+    else if (phases == kPhBorn && !store) RTM_STEP2(T, kPhBorn, false); \
     else return hipErrorInvalidValue;                         \
     return hipGetLastError();                                 \
   }

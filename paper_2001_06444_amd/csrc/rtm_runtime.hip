@@ -842,7 +842,7 @@ static int upload_table(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>
   t.ntiles = (int)t.htiles->size();
   t.first.push_back(t.ntiles);
   bool pairs = true;
-  for (auto* j : js) pairs = pairs && pairs_mode(j->g) && j->g.nbuf == 4;
+  for (auto* j : js) pairs = pairs && (pairs_mode(j->g) || j->g.mode == kModeBorn) && j->g.nbuf == 4;
   for (auto [tw, tz2] : {std::make_pair(&t.fw, tz2f), std::make_pair(&t.bw, tz2b)}) {
     if (!pairs || (tz2 != 16 && tz2 != 24 && tz2 != 32)) continue;
     if (!tz2_fits(js, tz2)) tz2 = 16;
@@ -1233,15 +1233,40 @@ extern "C" int rtm_ctx_destroy(rtm_ctx* ctx) {
 // ===========================================================================
 // Plain path
 // ===========================================================================
-// One launch per time step over the tiles of every job in js (jobs of one
-// mode and step count: a single job, or the shots of a Born batch).
-static int run_plain_jobs(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, int tz, Table& t) {
-  int rc = upload_table(ctx, s, js, t, 0, 0);
+// Two-step tile height of Born jobs (RTM_TILE_Z2 forces 16, 24 or 32; 0
+// keeps one step per launch).  A launch with few tiles needs the smaller
+// tiles' extra workgroups more than the larger tiles' smaller halo share:
+// measured on 351 x 1701 (nb 50, nt 4000), one shot per launch (627
+// 24-row tiles) 2.95e11 updates/s at 16 rows, 2.75e11 at 24, 2.72e11 one
+// step per launch; 16 shots per launch (10032 tiles) 3.77e11 at 16 rows,
+// 3.86e11 at 24, 3.62e11 one step per launch.  So 16 rows below 2048
+// 24-row tiles per launch, 24 from there (upload_table falls back to 16
+// where a grid's last 24-row tile would not fit).
+static int born_tz2(const JobGeom& g, int nshots) {
+  const int e = env_tz2();
+  if (e >= 0) return e;
+  const int64_t tiles24 = (int64_t)nshots * ((g.nz + 2 * g.nb + 23) / 24) * ((g.width + 2 * g.nb + kTileX2 - 1) / kTileX2);
+  return tiles24 < 2048 ? 16 : 24;
+}
+
+// The time steps of every job in js (jobs of one mode and step count: a
+// single job, or the shots of a Born batch) over all their tiles: one launch
+// per step, except that Born jobs built with four buffers per field
+// (tz2 > 0) advance two steps per launch, the last step alone when the
+// count is odd.
+static int run_plain_jobs(rtm_ctx* ctx, hipStream_t s, const std::vector<HostJob*>& js, int tz, Table& t,
+                          int tz2 = 0) {
+  int rc = upload_table(ctx, s, js, t, tz2, 0);
   if (rc) return rc;
   const HostJob& j = *js[0];
   const int nsteps = j.d.nsteps;
   const int nf = j.g.mode == kModeModel ? nsteps : j.g.nt - 1;
-  for (int st = 0; st < nsteps; ++st) {
+  int st = 0;
+  if (j.g.mode == kModeBorn && t.fw.ntiles > 0)
+    for (; st + 1 < nsteps; st += 2)
+      HIP_OK(launch_step2(t.fw.tz, kPhBorn, 0, t.jobs, t.fw.tiles, t.fw.recs, t.fw.ntiles, t.fw.ntiles, t.ctl, 0,
+                          st, s));
+  for (; st < nsteps; ++st) {
     const int ph = j.g.mode == kModeBorn ? kPhBorn : (st < nf ? kPhFwd : kPhBwd);
     HIP_OK(launch_step(tz, ph, t.jobs, t.tiles, t.ntiles, t.ntiles, t.ctl, 0, st, s));
   }
@@ -1322,6 +1347,7 @@ static void born_geom(const rtm_grid* grid, int32_t nrec, JobGeom& g) {
   g.sponge_a = grid->sponge_a;
   g.mode = kModeBorn;
   g.nrec = nrec;
+  if (env_tz2() != 0) g.nbuf = 4;  // two steps per launch
 }
 
 extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev, const float* wavelet_dev,
@@ -1348,7 +1374,7 @@ extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev
   HIP_OK(hipMemcpy2DAsync(j.d.image + g.nb, (size_t)j.d.pitch * 4, mpert_dev, (size_t)g.width * 4,
                           (size_t)g.width * 4, g.nz, hipMemcpyDeviceToDevice, s));
   Table t;
-  if ((rc = run_plain(ctx, s, j, tz, t))) {
+  if ((rc = run_plain_jobs(ctx, s, std::vector<HostJob*>{&j}, tz, t, born_tz2(g, 1)))) {
     finish_job_deferred(ctx, s, j, t, false);
     return rc;
   }
@@ -1410,7 +1436,7 @@ extern "C" int rtm_born_batch(rtm_ctx* ctx, const rtm_grid* grid, const float* v
            : fail(RTM_E_DEVICE, "perturbation copy failed");
   for (auto& j : jobs) j->d.image = j0.d.image;
   Table t;
-  if (!rc) rc = run_plain_jobs(ctx, s, ptrs, tz, t);
+  if (!rc) rc = run_plain_jobs(ctx, s, ptrs, tz, t, born_tz2(geoms[0], nshots));
   Deferred d;
   for (auto& j : jobs) {
     for (auto& b : j->blocks) d.blocks.push_back(b);

@@ -57,6 +57,38 @@ def test_born_matches_oracle(rtm, ctx):
     assert e <= 5e-5
 
 
+@pytest.mark.parametrize("tz2", ["16", "24", "32"])
+@pytest.mark.parametrize("nt, nb", [(2, 10), (3, 10), (38, 10), (39, 9)])
+def test_born_two_step_launches_equal_one_step(rtm, ctx, tz2, nt, nb, monkeypatch):
+    """Born modelling two steps per launch (each tile's first step over its
+    middle region, the second from LDS) gives the traces of one step per
+    launch bit for bit: every forced two-step height; nt = 2 (one step, no
+    pair), odd and even step counts (a last single step); nb 9 (a grid whose
+    last 24-row tile does not fit takes 16 rows); the source at a tile corner,
+    receivers on both sides of two-step tile edges (rows 23-25, columns
+    55-57 and 111-113 of the padded grid) and at the grid's corners."""
+    vel = _model(7, nz=45, nx=130)
+    nz, nx = vel.shape
+    h, dt = 10.0, 1e-3
+    w = inputs.ricker(nt, dt, fp=25)
+    m = np.random.default_rng(8).standard_normal((nz, nx))
+    g = rtm.make_grid(nz, nx, nb, nt, h, h, dt)
+    rec = sorted({(z - nb, x - nb) for z in (23, 24, 25) for x in (55, 56, 57, 111, 112, 113)
+                  if 0 <= z - nb < nz and 0 <= x - nb < nx} | {(0, 0), (nz - 1, nx - 1), (0, nx - 1)})
+    src = (24 - nb, 56 - nb)
+    out = {}
+    for key in ("0", tz2):
+        monkeypatch.setenv("RTM_TILE_Z2", key)
+        dd = torch.full((nt, len(rec)), float("nan"), device="cuda")
+        ctx.born(g, dev(vel), dev(w), src, dev(m), rec, dd)
+        out[key] = dd
+    torch.cuda.synchronize()
+    assert torch.isfinite(out["0"]).all()
+    assert torch.equal(out["0"], out[tz2]), (tz2, nt, nb)
+    if nt > 3:
+        assert float(out[tz2].abs().max()) > 0
+
+
 def test_born_batch_equals_born_per_shot(rtm, ctx):
     """Born shots advanced together in shared launches (one c, one copy of the
     perturbation) give each shot's rtm_born traces bit for bit: sources in
