@@ -2957,7 +2957,10 @@ static int zf_decode(rtm_ctx* ctx, const void* stream_dev, int64_t stream_bytes,
   uint32_t flags = 0;
   hipError_t e = launch_fill_u32(p.flags, 0, 16, s);
   if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[0], s);
-  if (e == hipSuccess) e = launch_zf_decode(p, s);
+  // LDS budget of the decoder's staged payload (RTM_ZFP_STAGE_BYTES; unset: from
+  // the stream's mean payload per workgroup; 0: no staging)
+  const char* sb = getenv("RTM_ZFP_STAGE_BYTES");
+  if (e == hipSuccess) e = launch_zf_decode(p, sb ? std::max(0ll, atoll(sb)) : -1ll, s);
   if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[1], s);
   if (e == hipSuccess) e = hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

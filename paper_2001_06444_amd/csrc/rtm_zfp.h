@@ -20,6 +20,7 @@ constexpr int64_t kZfMaxBlocks = int64_t(1) << 27;  // keeps payload word offset
 constexpr int kZfMaxBlockBits = 585;
 constexpr int kZfBlockWords = (kZfMaxBlockBits + 31) / 32;              // 19
 constexpr int kZfChunkWords = (kZfChunk * kZfMaxBlockBits + 31) / 32;   // 293
+constexpr int64_t kZfMaxStageBytes = 65536;  // decoder: LDS budget per workgroup, at most
 
 // error bits the kernels raise in ZfParams::flags
 constexpr uint32_t kZfRange = 1u;    // a value is non-finite or |x| >= 2^100
@@ -44,6 +45,9 @@ struct ZfParams {
 // Encoder: counts[nchunks] (uint32) and totals[(nchunks + 255) / 256 + 1]
 // (uint64) are device scratch.
 hipError_t launch_zf_encode(const ZfParams& p, uint32_t* counts, uint64_t* totals, hipStream_t s);
-hipError_t launch_zf_decode(const ZfParams& p, hipStream_t s);
+// Decoder: stage_bytes is the LDS budget per workgroup for the staged
+// payload (0: every lane reads global memory; negative: chosen from the
+// stream's mean payload per workgroup); at most kZfMaxStageBytes.
+hipError_t launch_zf_decode(const ZfParams& p, int64_t stage_bytes, hipStream_t s);
 
 }  // namespace rtm

@@ -121,6 +121,46 @@ def test_errors(ctx, rtm):
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("stage", ["0", "1600", "4096", "20000", None])
+def test_decode_staged_and_global_workgroups(ctx, rtm, monkeypatch, stage):
+    """The decoder's workgroups copy their chunks' payload into LDS when it
+    fits the budget (RTM_ZFP_STAGE_BYTES; unset: chosen from the stream) and
+    read global memory otherwise.  Zero regions code to a few words per
+    workgroup and noisy ones to hundreds, so the small budgets mix staged and
+    unstaged workgroups in one launch.  Every budget decodes the oracle's
+    array bit for bit, and a corrupt chunk table or a chunk cut short is
+    reported under every budget."""
+    if stage is None:
+        monkeypatch.delenv("RTM_ZFP_STAGE_BYTES", raising=False)
+    else:
+        monkeypatch.setenv("RTM_ZFP_STAGE_BYTES", stage)
+    rng = np.random.default_rng(11)
+    x = np.zeros((2, 203, 261), np.float32)
+    x[0, 60:150] = rng.standard_normal((90, 261)).astype(np.float32)
+    x[1, :, 100:] = np.sin(np.arange(203) / 7.0)[:, None].astype(np.float32)
+    x[1, 150:, :40] = 1e-3 * rng.standard_normal((53, 40)).astype(np.float32)
+    tol = 1e-4
+    ref = zfp.encode(x, tol)
+    _, _, nblocks, nchunks = zfp.geometry(*x.shape)
+    assert nchunks > 4 * 64  # several workgroups
+    y = ctx.codec_decode(torch.as_tensor(ref.view(np.uint8)).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y.cpu().numpy().view(np.uint32), zfp.decode(ref).view(np.uint32))
+    table = 8  # word index of the chunk table
+    for c in (3, 64, 200):  # inside the first workgroup, at a workgroup's start, further on
+        bad = ref.copy()
+        bad[table + c + 1] -= 1  # chunk c one word short; chunk c + 1 starts a word early
+        assert bad[table + c + 1] >= bad[table + c]
+        with pytest.raises(rtm.RTMError) as e:
+            ctx.codec_decode(torch.as_tensor(bad.view(np.uint8)).cuda())
+        assert e.value.code == -1
+        bad = ref.copy()
+        bad[table + c] = bad[table + c + 1] + 1  # table not monotone
+        with pytest.raises(rtm.RTMError) as e:
+            ctx.codec_decode(torch.as_tensor(bad.view(np.uint8)).cuda())
+        assert e.value.code == -1
+
+
 @pytest.mark.parametrize("kind", ["velocity", "image", "seismogram"])
 def test_full_size_bank_sampled(ctx, kind):
     """Banks of the benchmark's sizes (a few arrays of each): sampled chunks'
