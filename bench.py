@@ -86,6 +86,29 @@ def measured_traffic(record="traffic_backward_step.json", sources=STEP_SOURCES, 
     return rec.get("hbm_bytes_per_launch")
 
 
+def copy_rate_gbs(gib: int = 1, reps: int = 5) -> float:
+    """Device-to-device copy rate (GB/s of bytes read + written) of a `gib`
+    GiB float32 tensor copy, best of `reps` (HIP events): the measured
+    denominator of the roofline beside the nominal 8 TB/s."""
+    import torch
+
+    n = gib << 28
+    src = torch.ones(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (best * 1e-3) / 1e9
+
+
 def cpu_model() -> str:
     """The host CPU's model name from /proc/cpuinfo (first processor)."""
     try:
@@ -351,6 +374,9 @@ def run_survey(args):
         base = cpu_baseline(sv, args.cpu_nt)
         log(f"[bench] oracle: {base['value']:.3e} updates/s on {base['cores']} threads")
 
+    copy_gbs = copy_rate_gbs()
+    log(f"[bench] device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + written); backward launch "
+        f"{achieved / copy_gbs:.2f}x of it")
     ctx.close()
     out = _base_record(args, value, ms_per_step, {
         "workload": f"faulted-layer survey {nz}x{nx} at 10 m, {len(shots)} shots, nt={nt}, "
@@ -366,6 +392,7 @@ def run_survey(args):
         "batched_vs_plain": (images_per_s / plain["images_per_s"]) if plain else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "traffic": measured_traffic(launch={"tile_z2": k1.last_tile_z2_bwd,
                                                          "groups": kbw, "shots": len(shots)}),
                      "kernel": (f"k_step2<{k1.last_tile_z2_bwd},2> backward, two time steps "
