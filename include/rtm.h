@@ -478,7 +478,10 @@ int rtm_codec_info(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes, i
  * count * rows * cols floats (capacity_floats).  Reads never leave the
  * stream; a stream whose widths, chunk table or length disagree returns
  * RTM_E_INVAL (x_dev then holds partial output).  RTM_E_NOMEM: x_dev too
- * small. */
+ * small.  For ZFP-method streams the environment variable
+ * RTM_ZFP_STAGE_BYTES sets the LDS budget per decoder workgroup for its
+ * staged payload (0: none; unset: chosen from the stream's mean payload);
+ * the result does not depend on it. */
 int rtm_codec_decode(rtm_ctx *ctx, const void *stream_dev, int64_t stream_bytes, float *x_dev,
                      int64_t capacity_floats);
 
