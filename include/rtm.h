@@ -179,11 +179,18 @@ typedef struct {
 
 /* Born modelling of nshots shots of one model and one perturbation (the
  * linearised operator of rtm_born, Sec. 3 reverse problem) in shared
- * kernel launches: each launch advances every shot's background and
- * scattered field by one time step, and the shots read one c array and one
- * copy of mpert_dev.  Each shot's dtraces equal rtm_born's for that shot
- * bit for bit.  shots_host [nshots] is read at call time; the other
- * arguments as in rtm_born.  Stream-ordered on ctx's stream.
+ * kernel launches: each launch advances the background and scattered field
+ * of every shot of a shot group by two time steps (one with RTM_TILE_Z2=0),
+ * and the shots read one c array and one copy of mpert_dev.  Shot groups
+ * are consecutive shots whose fields fit the memory-side cache budget
+ * (RTM_GROUP_KB, KiB, default 200 MiB; 0 or less: one group), each running
+ * all its steps before the next; groups alternate between ctx's stream and
+ * the library's further group streams (RTM_GROUP_STREAMS, 1-4, default 2),
+ * which are forked from ctx's stream and joined back into it, and the
+ * budget is shared among them.  Each shot's dtraces equal rtm_born's for
+ * that shot bit for bit, whatever the groups.  shots_host [nshots] is read
+ * at call time; the other arguments as in rtm_born.  Stream-ordered on ctx's
+ * stream; rtm_ctx_stats reports the group count.
  * Errors: RTM_E_INVAL (no shots, bad nodes, missing dtraces_dev),
  * RTM_E_CFL, RTM_E_NOMEM (the whole batch must fit the arena). */
 int rtm_born_batch(rtm_ctx *ctx, const rtm_grid *grid, const float *vel_dev, const float *wavelet_dev,
@@ -636,6 +643,10 @@ typedef struct {
      * through a phase together, one group after another; each launch covers
      * one group, so a phase made nsteps x groups launches) */
     int32_t last_groups_fwd, last_groups_bwd;
+    /* last rtm_born_batch call: shot groups (consecutive shots whose fields
+     * fit the memory-side cache advance through all their steps together,
+     * one group after another) */
+    int32_t last_born_groups;
 } rtm_ctx_stats_t;
 
 int rtm_ctx_stats(rtm_ctx *ctx, rtm_ctx_stats_t *out);

@@ -245,6 +245,7 @@ struct rtm_ctx {
   int ph_steps_per_launch = 1;
   int ph_tz2[2] = {0, 0};  // two-step tile height of each phase (0: one step per launch)
   int ph_groups[2] = {1, 1};  // shot groups of each phase (a launch covers one group)
+  int born_groups = 0;        // shot groups of the last Born batch
   uint64_t ph_bytes[2] = {0, 0};
   bool ph_valid = false;
   Arena arena;
@@ -740,6 +741,17 @@ struct Table {
   std::shared_ptr<std::vector<DevJob>> hjobs;
   std::shared_ptr<std::vector<Tile>> htiles;
 };
+
+// The host arrays a table's uploads read, kept alive until the work that
+// follows them has run.
+static void keep_table(Deferred& d, const Table& t) {
+  d.keep.push_back(t.hjobs);
+  d.keep.push_back(t.htiles);
+  d.keep.push_back(t.fw.htiles);
+  d.keep.push_back(t.fw.hrecs);
+  d.keep.push_back(t.bw.htiles);
+  d.keep.push_back(t.bw.hrecs);
+}
 
 // Two-step tile height.  RTM_TILE_Z2 unset: the tuner picks the height of
 // each phase (autotune_tz2); 16, 24 or 32 forces that height for both
@@ -1284,8 +1296,7 @@ static void finish_job_deferred(rtm_ctx* ctx, hipStream_t s, HostJob& j, Table& 
   for (auto& b : t.blocks) d.blocks.push_back(b);
   t.blocks.clear();
   if (!keep_image && j.image_blk.p) d.blocks.push_back(j.image_blk);
-  d.keep.push_back(t.hjobs);
-  d.keep.push_back(t.htiles);
+  keep_table(d, t);
   defer(ctx, s, std::move(d));
 }
 
@@ -1384,6 +1395,28 @@ extern "C" int rtm_born(rtm_ctx* ctx, const rtm_grid* grid, const float* vel_dev
   return RTM_OK;
 }
 
+static size_t group_budget();
+static int group_streams();
+
+// Shot groups of a Born batch: consecutive runs of near-equal size whose
+// launches' working set (per shot two fields, two levels read and two
+// written per launch; c and the perturbation once) fits the cache budget
+// (RTM_GROUP_KB, as for the migration batch), shared by the streams whose
+// groups run side by side.
+static std::vector<std::pair<int, int>> born_groups(const JobGeom& g, int nshots, int streams) {
+  const size_t pad = (size_t)(g.nz + 2 * g.nb) * field_pitch(g.width + 2 * g.nb) * 4;
+  const size_t per = 8 * pad, shared = 2 * pad;
+  const size_t budget = group_budget() == SIZE_MAX ? SIZE_MAX : group_budget() / streams;
+  int ngroups = 1;
+  if (budget != SIZE_MAX && shared + per * (size_t)nshots > budget) {
+    const size_t fit = budget > shared + per ? (budget - shared) / per : 1;
+    ngroups = (int)std::min<size_t>(nshots, ((size_t)nshots + fit - 1) / fit);
+  }
+  std::vector<std::pair<int, int>> out;
+  for (int i = 0; i < ngroups; ++i) out.push_back({nshots * i / ngroups, nshots * (i + 1) / ngroups});
+  return out;
+}
+
 // Born modelling of several shots in shared launches: every shot's job reads
 // the first job's c, sponge profiles and perturbation (the Born step only
 // reads them), and each launch advances the Born step of every shot.
@@ -1435,8 +1468,37 @@ extern "C" int rtm_born_batch(rtm_ctx* ctx, const rtm_grid* grid, const float* v
            ? RTM_OK
            : fail(RTM_E_DEVICE, "perturbation copy failed");
   for (auto& j : jobs) j->d.image = j0.d.image;
-  Table t;
-  if (!rc) rc = run_plain_jobs(ctx, s, ptrs, tz, t, born_tz2(geoms[0], nshots));
+  // Shot groups sized for the memory-side cache, as the migration batch
+  // runs them: each group advances all its steps before the next starts, so
+  // the levels a launch writes are still cached when the group's next launch
+  // reads them; the groups alternate between the context stream and the
+  // further group streams (RTM_GROUP_STREAMS), forked from it and joined
+  // back into it, so one group's launches fill what another's leave idle.
+  // Every group has its own tables and control block.
+  const int nreq = group_streams();
+  const std::vector<std::pair<int, int>> groups = born_groups(geoms[0], nshots, nreq);
+  const int ns = std::max(1, std::min<int>(nreq, (int)groups.size()));
+  std::vector<Table> tables(groups.size());
+  if (!rc && ns > 1) {
+    rc = hipEventRecord(ctx->ev_fork, s) == hipSuccess ? RTM_OK : fail(RTM_E_DEVICE, "event record");
+    for (int k = 1; k < ns && !rc; ++k)
+      if (hipStreamWaitEvent(ctx->group_stream[k - 1], ctx->ev_fork, 0) != hipSuccess)
+        rc = fail(RTM_E_DEVICE, "stream wait");
+  }
+  for (size_t gi = 0; gi < groups.size() && !rc; ++gi) {
+    const auto [a, b] = groups[gi];
+    const int side = (int)(gi % ns);
+    std::vector<HostJob*> grp(ptrs.begin() + a, ptrs.begin() + b);
+    rc = run_plain_jobs(ctx, side ? ctx->group_stream[side - 1] : s, grp, tz, tables[gi], born_tz2(geoms[0], b - a));
+  }
+  for (int k = 1; k < ns; ++k) {  // also after an error: deferred work on s waits for the group streams
+    hipStream_t gs = ctx->group_stream[k - 1];
+    if (hipEventRecord(ctx->ev_join[k - 1], gs) != hipSuccess || hipStreamWaitEvent(s, ctx->ev_join[k - 1], 0) != hipSuccess) {
+      (void)hipStreamSynchronize(gs);
+      if (!rc) rc = fail(RTM_E_DEVICE, "joining a group stream failed");
+    }
+  }
+  if (!rc) ctx->born_groups = (int)groups.size();
   Deferred d;
   for (auto& j : jobs) {
     for (auto& b : j->blocks) d.blocks.push_back(b);
@@ -1445,9 +1507,10 @@ extern "C" int rtm_born_batch(rtm_ctx* ctx, const rtm_grid* grid, const float* v
     ctx->grid_updates += rc ? 0 : j->updates;
     ctx->alg_bytes += rc ? 0 : j->alg_bytes;
   }
-  for (auto& b : t.blocks) d.blocks.push_back(b);
-  d.keep.push_back(t.hjobs);
-  d.keep.push_back(t.htiles);
+  for (auto& t : tables) {
+    for (auto& b : t.blocks) d.blocks.push_back(b);
+    keep_table(d, t);
+  }
   int rc2 = defer(ctx, s, std::move(d));
   return rc ? rc : rc2;
 }
@@ -1900,10 +1963,7 @@ extern "C" int rtm_migrate_batch(rtm_ctx* ctx, const rtm_grid* grid, const float
     ctx->alg_bytes += rc ? 0 : j->alg_bytes;
   }
   for (auto& b : t.blocks) d.blocks.push_back(b);
-  d.keep.push_back(t.hjobs);
-  d.keep.push_back(t.htiles);
-  d.keep.push_back(t.fw.htiles);
-  d.keep.push_back(t.bw.htiles);
+  keep_table(d, t);
   for (auto& gp : graphs)
     for (auto g : gp)
       if (g) d.graphs.push_back(g);
@@ -3353,6 +3413,7 @@ extern "C" int rtm_ctx_stats(rtm_ctx* ctx, rtm_ctx_stats_t* out) {
   out->arena_used = ctx->arena.used();
   out->arena_peak = ctx->arena.peak();
   out->tile_z = choose_tz(ctx);
+  out->last_born_groups = ctx->born_groups;
   if (ctx->ph_valid) {
     float a = 0, b = 0;
     if (hipEventSynchronize(ctx->ph_ev[2]) == hipSuccess &&

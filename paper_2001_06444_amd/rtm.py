@@ -82,7 +82,8 @@ class CtxStats(ctypes.Structure):
         ("last_codec_bytes", ctypes.c_uint64),
         ("last_bet_eikonal_ms", ctypes.c_float), ("last_bet_iteration_ms", ctypes.c_float),
         ("last_tile_z2_fwd", ctypes.c_int32), ("last_tile_z2_bwd", ctypes.c_int32),
-        ("last_groups_fwd", ctypes.c_int32), ("last_groups_bwd", ctypes.c_int32)]
+        ("last_groups_fwd", ctypes.c_int32), ("last_groups_bwd", ctypes.c_int32),
+        ("last_born_groups", ctypes.c_int32)]
 
 
 class BetConfig(ctypes.Structure):

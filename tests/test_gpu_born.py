@@ -89,12 +89,21 @@ def test_born_two_step_launches_equal_one_step(rtm, ctx, tz2, nt, nb, monkeypatc
         assert float(out[tz2].abs().max()) > 0
 
 
-def test_born_batch_equals_born_per_shot(rtm, ctx):
+@pytest.mark.parametrize("streams", ["1", "2"])
+@pytest.mark.parametrize("group_kb", [None, "1", "1000"])
+def test_born_batch_equals_born_per_shot(rtm, ctx, group_kb, streams, monkeypatch):
     """Born shots advanced together in shared launches (one c, one copy of the
     perturbation) give each shot's rtm_born traces bit for bit: sources in
     the interior, at the model's edge column and inside the first physical
     row, receiver sets of different sizes, one shot without receivers; and
-    the first shot against the oracle."""
+    the first shot against the oracle.  The cache budget (RTM_GROUP_KB) puts
+    the shots in one launch group, one group per shot, or two groups, run on
+    one stream or alternating between two (RTM_GROUP_STREAMS)."""
+    if group_kb is None:
+        monkeypatch.delenv("RTM_GROUP_KB", raising=False)
+    else:
+        monkeypatch.setenv("RTM_GROUP_KB", group_kb)
+    monkeypatch.setenv("RTM_GROUP_STREAMS", streams)
     vel = _model(4)
     nz, nx = vel.shape
     nt, h, dt, nb = 260, 10.0, 1e-3, 10
@@ -114,6 +123,8 @@ def test_born_batch_equals_born_per_shot(rtm, ctx):
         singles.append(one)
     ctx.born_batch(g, dev(vel), dev(w), dev(m), shots)
     torch.cuda.synchronize()
+    ngroups = ctx.stats().last_born_groups
+    assert ngroups == {None: 1, "1": 4}.get(group_kb, ngroups) and 1 <= ngroups <= 4, ngroups
     for (src, rec, out), one in zip(shots, singles):
         if rec:
             assert torch.equal(out, one), src
