@@ -784,8 +784,9 @@ static bool pairs_mode(const JobGeom& g) {
 // timed jobs: p50 40 against 37 ms, p99 102 against 80 ms; saturation
 // unchanged): the later jobs admitted beside a paired one add launches.
 // At saturation the pair kernels took as long as the one-step kernel for
-// the same work, and the changing launch kinds made every cycle rebuild
-// the tables (GPU busy 74 % of the wall time against 97 %).
+// the same work, and the GPU was busy 74 % of the wall time against 97 %,
+// most likely waiting on table rebuilds, which the jobs' changing launch
+// kinds trigger in most cycles.
 static bool served_two_step(const JobGeom& g) {
   const char* e = getenv("RTM_SERVE_STORE_PAIRS");
   const bool store_pairs = e && atoi(e) == 1;
