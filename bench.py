@@ -659,15 +659,25 @@ def _serve(args, n_warm, n_timed, saturation, extra_rates=()):
         log(f"[bench] serve @ {rate}/s: p50 {np.percentile(lr, 50) * 1e3:.0f} ms, "
             f"p99 {np.percentile(lr, 99) * 1e3:.0f} ms, {n_timed / span_r:.1f} images/s")
     if saturation:  # every job arrives at t = 0
-        u0 = ctx.stats().grid_updates
+        st0 = ctx.stats()
+        u0, a0 = st0.grid_updates, st0.alg_bytes
         lat0, ok0, t_end0 = serve([0.0] * n_all)
+        st1 = ctx.stats()
+        # the jobs' algorithmic bytes (per-update minimum of every job, each
+        # with its own c) over the run's wall time
+        alg = st1.alg_bytes - a0
         res["saturation"] = {"jobs": n_all, "seconds": t_end0, "images_per_s": n_all / t_end0,
-                             "updates_per_s": (ctx.stats().grid_updates - u0) / t_end0,
+                             "updates_per_s": (st1.grid_updates - u0) / t_end0,
                              "latency_ms": {"p50": float(np.percentile(lat0, 50)) * 1e3,
                                             "p99": float(np.percentile(lat0, 99)) * 1e3},
-                             "failed_jobs": int((~ok0).sum())}
+                             "failed_jobs": int((~ok0).sum()),
+                             "served_roofline": {"bound": "hbm", "achieved": alg / t_end0 / 1e9,
+                                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                                 "frac": alg / t_end0 / 1e9 / HBM_PEAK_GBS,
+                                                 "alg_bytes": alg, "seconds": t_end0}}
         log(f"[bench] saturation: {n_all} jobs in {t_end0:.2f} s, {n_all / t_end0:.1f} images/s, "
-            f"{res['saturation']['updates_per_s']:.3e} updates/s")
+            f"{res['saturation']['updates_per_s']:.3e} updates/s, {alg / t_end0 / 1e9:.0f} GB/s of "
+            "algorithmic bytes")
     ctx.close()
     return res
 
