@@ -843,7 +843,9 @@ def run_born(args):
                           "alg_bytes_per_launch": plain_bytes},
                 "batched_vs_plain": ms_p / ms_b,
                 "roofline": {"bound": "hbm", "achieved": gbs_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": gbs_b / HBM_PEAK_GBS, "traffic": None,
+                             "frac": gbs_b / HBM_PEAK_GBS,
+                             "traffic": measured_traffic("traffic_born_pair.json",
+                                                         launch={"groups": ngr, "shots": nsh}),
                              "kernel": (f"k_step2<TZ2,4> Born pair (two steps per launch)" if spl == 2 else
                                         "k_step<TZ,4> Born step") + f" over {nsh / ngr:.1f} shots (background and "
                                        "scattered field)",
