@@ -2809,22 +2809,23 @@ static int zf_encode(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t ro
                             (uint32_t)cols, (uint32_t)kZfChunk, tw[0], tw[1]};
   memcpy(p.head, head, sizeof head);
   HIP_OK(hipSetDevice(ctx->device));
-  // scratch: chunk word counts, scan totals, flags and result words
-  const int64_t ng = (p.nchunks + kZfScan - 1) / kZfScan;
-  const size_t counts_bytes = align256(4 * (size_t)p.nchunks), totals_bytes = align256(8 * (size_t)(ng + 1));
-  const size_t scratch_bytes = counts_bytes + totals_bytes + 256;
+  // scratch: the look-back state (one word per encoder workgroup), the
+  // workgroup ticket, flags and result words, all zeroed
+  const int64_t nwg = (p.nblocks + kZfEncThreads - 1) / kZfEncThreads;
+  const size_t status_bytes = align256(8 * (size_t)nwg);
+  const size_t scratch_bytes = status_bytes + 256;
   char* scratch = static_cast<char*>(arena_alloc(ctx, scratch_bytes));
   if (!scratch) return fail(RTM_E_NOMEM, "arena exhausted (codec scratch)");
-  uint32_t* counts = reinterpret_cast<uint32_t*>(scratch);
-  uint64_t* totals = reinterpret_cast<uint64_t*>(scratch + counts_bytes);
-  uint32_t* tail = reinterpret_cast<uint32_t*>(scratch + counts_bytes + totals_bytes);
+  uint32_t* tail = reinterpret_cast<uint32_t*>(scratch + status_bytes);
+  p.status = reinterpret_cast<uint64_t*>(scratch);
   p.flags = tail;
   p.result = tail + 2;
+  p.ticket = tail + 4;
   hipStream_t s = ctx->stream;
   uint32_t res[4] = {0, 0, 0, 0};
-  hipError_t e = launch_fill_u32(tail, 0, 64, s);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(scratch), 0, (int64_t)(scratch_bytes / 4), s);
   if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[0], s);
-  if (e == hipSuccess) e = launch_zf_encode(p, counts, totals, s);
+  if (e == hipSuccess) e = launch_zf_encode(p, s);
   if (e == hipSuccess) e = hipEventRecord(ctx->zc_ev[1], s);
   if (e == hipSuccess) e = hipMemcpyAsync(res, tail, 16, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -2832,6 +2833,7 @@ static int zf_encode(rtm_ctx* ctx, const float* x_dev, int32_t count, int32_t ro
   if (e != hipSuccess) return fail(RTM_E_DEVICE, "codec encode: %s", hipGetErrorString(e));
   if (res[0] & kZfRange)
     return fail(RTM_E_INVAL, "a value is non-finite or |x| >= 2^100 (outside the ZFP-method coder's range)");
+  if (res[0] & kZfSpin) return fail(RTM_E_DEVICE, "codec encode: a chunk offset did not arrive in time");
   const uint64_t payload = (uint64_t)res[2] | ((uint64_t)res[3] << 32);
   const int64_t bytes = 4 * (p.pay_base + (int64_t)payload);
   *stream_bytes = bytes;

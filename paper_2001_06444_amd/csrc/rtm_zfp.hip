@@ -25,10 +25,11 @@
 // chunk of 16 blocks, then the total), the payload (each chunk's block codes
 // back to back, padded to a word).
 //
-// Launch shape: the encoder runs one lane per block, twice: a pass that only
-// counts each chunk's words, a scan of the counts into the chunk table, and
-// a pass that writes the codes at their offsets (chunks start on word
-// boundaries, so no two workgroups write one word).  The decoder runs one
+// Launch shape: the encoder runs one lane per block in one pass: each
+// workgroup finds where its chunks' codes start by a decoupled look-back
+// over the workgroups before it, then writes its chunk-table entries and
+// codes (chunks start on word boundaries, so no two workgroups write one
+// word).  The decoder runs one
 // lane per chunk of 16 blocks, in order, and reads each chunk's word range
 // from the table, never outside it; a workgroup's chunks are consecutive, so
 // their payload is one word range, which k_zf_decode_staged first copies
@@ -207,62 +208,6 @@ __device__ bool encode_block(const float (&x)[16], int minexp, Sink& bs) {
   return true;
 }
 
-// Bits encode_block emits for a block (the same steps, no stream): per bit
-// plane the verbatim bits of the significant coefficients, then one group
-// test per coefficient that turns significant plus the run up to it, and a
-// closing test unless the last coefficient was reached (its 1 implied).
-__device__ int count_block(const float (&x)[16], int minexp, bool& ok) {
-  float m = 0.0f;
-  bool fin = true;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const float a = fabsf(x[c]);
-    fin = fin && (a < 0x1p100f);
-    m = fmaxf(m, a);
-  }
-  if (!fin) {
-    ok = false;
-    return 0;
-  }
-  if (m == 0.0f) return 1;
-  int e;
-  (void)frexpf(m, &e);
-  const int maxprec = min(32, max(0, e - minexp + 6));
-  if (maxprec == 0) return 1;
-  int32_t q[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) q[c] = (int32_t)ldexpf(x[c], 30 - e);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) fwd_lift(q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) fwd_lift(q[j], q[4 + j], q[8 + j], q[12 + j]);
-  uint32_t u[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) u[c] = ((uint32_t)q[kSeq[c]] + kNb) ^ kNb;
-  const int kmin = 32 - maxprec;
-  swap_planes(u);  // u[j]: plane j in the low half, plane j + 16 in the high half
-  int bits = 9, n = 0;
-#pragma unroll
-  for (int k = 31; k >= 0; --k) {  // unrolled, so that the plane is a register
-    if (k >= kmin && n < 16) {
-      const uint32_t plane = k >= 16 ? u[k - 16] >> 16 : u[k] & 0xFFFFu;
-      const uint32_t rest = plane >> n;
-      bits += n;
-      if (!rest) {
-        bits += 1;
-      } else {
-        const int ones = __builtin_popcount(rest);
-        const int nf = n + 32 - __builtin_clz(rest);  // one past the highest new significant coefficient
-        bits += nf == 16 ? ones + 15 - n : ones + nf - n + 1;
-        n = nf;
-      }
-    } else if (k >= kmin) {
-      bits += 16;  // every coefficient significant: verbatim planes from here on
-    }
-  }
-  return bits;
-}
-
 // Inverse of encode_block.  (Collecting the planes and transposing them
 // with swap_planes instead of setting each coefficient's bit per plane
 // measured no faster: the decoder's time goes to the serial bit reads.)
@@ -317,87 +262,6 @@ __device__ void decode_block(Src& src, int minexp, float (&x)[16]) {
   for (int c = 0; c < 16; ++c) x[c] = (float)q[c] * scale;
 }
 
-// Pass 1: payload words of every chunk -> counts[chunk].  One lane per
-// block: the 64 lanes of a workgroup read 64 neighbouring blocks (row by
-// row, 1 KB contiguous), and each 16-lane group sums the bits of one chunk.
-__global__ __launch_bounds__(kZfThreads) void k_zf_count(ZfParams p, uint32_t* counts) {
-  const int lane = threadIdx.x;
-  const int64_t b = (int64_t)blockIdx.x * kZfThreads + lane;
-  bool ok = true;
-  int bits = 0;
-  if (b < p.nblocks) {
-    float x[16];
-    load_block(p, b, x);
-    bits = count_block(x, p.minexp, ok);
-  }
-#pragma unroll
-  for (int d = kZfChunk / 2; d > 0; d >>= 1) bits += __shfl_xor(bits, d, kZfChunk);
-  const int64_t ch = b / kZfChunk;
-  if ((lane & (kZfChunk - 1)) == 0 && ch < p.nchunks) counts[ch] = (uint32_t)((bits + 31) >> 5);  // words written
-  if (!ok) atomicOr(p.flags, kZfRange);
-}
-
-// Exclusive scan of the counts into the stream's chunk table, in three
-// launches: per-workgroup totals, a scan of the totals (one workgroup), and
-// the table entries.
-__global__ __launch_bounds__(kZfScan) void k_zf_scan_totals(const uint32_t* counts, int64_t n, uint64_t* totals) {
-  __shared__ uint64_t red[kZfScan];
-  const int64_t i = (int64_t)blockIdx.x * kZfScan + threadIdx.x;
-  red[threadIdx.x] = i < n ? counts[i] : 0;
-  __syncthreads();
-  for (int s = kZfScan / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) totals[blockIdx.x] = red[0];
-}
-
-__global__ __launch_bounds__(kZfScan) void k_zf_scan_base(uint64_t* totals, int64_t ngroups) {
-  // exclusive scan of ngroups totals, in place, kZfScan at a time
-  __shared__ uint64_t buf[kZfScan];
-  uint64_t carry = 0;
-  for (int64_t base = 0; base < ngroups; base += kZfScan) {
-    const int64_t i = base + threadIdx.x;
-    const uint64_t v = i < ngroups ? totals[i] : 0;
-    buf[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = 1; s < kZfScan; s <<= 1) {  // inclusive Hillis-Steele scan
-      const uint64_t t = (int)threadIdx.x >= s ? buf[threadIdx.x - s] : 0;
-      __syncthreads();
-      buf[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < ngroups) totals[i] = carry + buf[threadIdx.x] - v;
-    const uint64_t sum = buf[kZfScan - 1];
-    __syncthreads();
-    carry += sum;
-  }
-  if (threadIdx.x == 0) totals[ngroups] = carry;
-}
-
-__global__ __launch_bounds__(kZfScan) void k_zf_scan_table(const uint32_t* counts, int64_t n, const uint64_t* base,
-                                                           ZfParams p) {
-  __shared__ uint64_t buf[kZfScan];
-  const int64_t i = (int64_t)blockIdx.x * kZfScan + threadIdx.x;
-  const uint64_t v = i < n ? counts[i] : 0;
-  buf[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = 1; s < kZfScan; s <<= 1) {
-    const uint64_t t = (int)threadIdx.x >= s ? buf[threadIdx.x - s] : 0;
-    __syncthreads();
-    buf[threadIdx.x] += t;
-    __syncthreads();
-  }
-  const uint64_t off = base[blockIdx.x] + buf[threadIdx.x] - v;  // exclusive prefix
-  if (i < n && p.hdr_base + i < p.cap_words) p.out[p.hdr_base + i] = (uint32_t)off;
-  if (i == n - 1) {
-    const uint64_t total = off + v;
-    if (p.hdr_base + n < p.cap_words) p.out[p.hdr_base + n] = (uint32_t)total;
-    p.result[0] = (uint32_t)total;
-    p.result[1] = (uint32_t)(total >> 32);
-  }
-}
-
 // Appends bits to a lane's own LDS words (at most kZfBlockWords).
 struct LdsSink {
   uint32_t* out;
@@ -419,56 +283,132 @@ struct LdsSink {
   }
 };
 
-// Pass 2: the block codes of every chunk at its table offset.  One lane per
-// block: each lane codes its block into its own LDS words; a 16-lane prefix
-// sum of the block lengths places the codes in their chunk, which is
-// assembled in LDS and copied to the stream.  The words equal those of one
-// thread writing the chunk's blocks in order.
-__global__ __launch_bounds__(kZfThreads) void k_zf_encode(ZfParams p) {
-  constexpr int kChunks = kZfThreads / kZfChunk;  // chunks per workgroup
-  __shared__ uint32_t own[kZfThreads * kZfBlockWords];
+// Status word of a workgroup in the encoder's look-back: a flag in the top
+// two bits, payload words in the rest.
+constexpr uint64_t kZfAgg = 1ull << 62;  // the workgroup's own payload words published
+constexpr uint64_t kZfInc = 2ull << 62;  // its inclusive prefix published
+constexpr uint64_t kZfValMask = (1ull << 62) - 1;
+constexpr int kZfSpinLimit = 1 << 22;
+
+// The encoder, one pass.  A workgroup of four wavefronts codes 256
+// consecutive blocks (16 chunks), one lane per block, each into the lane's
+// own LDS words; the workgroups take their block ranges in the order of an
+// atomic ticket.  A 16-lane prefix sum of the blocks' bit lengths places
+// each code in its chunk.  Wavefront 0 publishes the workgroup's payload
+// words and finds where they start by a decoupled look-back over the
+// workgroups before it (64 of their status words per round, summed down to
+// the nearest published inclusive prefix; a workgroup waits only on
+// workgroups that took their tickets earlier and publish their own words
+// before they wait, and a wait that exceeds its bound raises kZfSpin
+// instead of hanging), then writes the chunk-table entries.  The chunks'
+// codes, assembled in LDS meanwhile, go to their offsets.  The words equal
+// those of one thread writing the blocks in order.
+__global__ __launch_bounds__(kZfEncThreads) void k_zf_encode(ZfParams p) {
+  constexpr int kT = kZfEncThreads, kChunks = kT / kZfChunk;  // chunks per workgroup
+  __shared__ uint32_t own[kT * kZfBlockWords];
   __shared__ uint32_t cbuf[kChunks * kZfChunkWords];
-  const int lane = threadIdx.x;
-  const int64_t b = (int64_t)blockIdx.x * kZfThreads + lane;
-  if (blockIdx.x == 0 && lane == 0) {
+  __shared__ uint32_t s_wg;
+  __shared__ uint32_t s_words[kChunks];
+  __shared__ uint64_t s_off[kChunks];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t == 0) s_wg = atomicAdd(p.ticket, 1u);
+  for (int i = t; i < kChunks * kZfChunkWords; i += kT) cbuf[i] = 0u;
+  __syncthreads();
+  const int64_t wg = s_wg;
+  const int64_t b = wg * kT + t;
+  if (wg == 0 && t == 0) {
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if (k < p.cap_words) p.out[k] = p.head[k];
   }
-  for (int i = lane; i < kChunks * kZfChunkWords; i += kZfThreads) cbuf[i] = 0u;
-  LdsSink sink(own + lane * kZfBlockWords);
+  LdsSink sink(own + t * kZfBlockWords);
+  bool ok = true;
   if (b < p.nblocks) {
     float x[16];
     load_block(p, b, x);
-    (void)encode_block(x, p.minexp, sink);
+    ok = encode_block(x, p.minexp, sink);
     sink.flush();
   }
+  if (!ok) atomicOr(p.flags, kZfRange);
   // bit offset of this block in its chunk: exclusive prefix over the 16 lanes
   const int g = lane & (kZfChunk - 1);
   int pre = sink.bits;
 #pragma unroll
   for (int d = 1; d < kZfChunk; d <<= 1) {
-    const int t = __shfl_up(pre, d, kZfChunk);
-    if (g >= d) pre += t;
+    const int v = __shfl_up(pre, d, kZfChunk);
+    if (g >= d) pre += v;
   }
+  const int chunk_bits = __shfl(pre, (lane & ~(kZfChunk - 1)) + kZfChunk - 1, 64);
   pre -= sink.bits;
-  __syncthreads();  // chunk buffers zeroed, own words written
-  uint32_t* cb = cbuf + (lane / kZfChunk) * kZfChunkWords;
+  if (g == 0) s_words[t / kZfChunk] = (uint32_t)((chunk_bits + 31) >> 5);
+  __syncthreads();
+
+  // ---- decoupled look-back over the preceding workgroups (wavefront 0) ----
+  if (wave == 0) {
+    uint32_t agg = 0;
+#pragma unroll
+    for (int q = 0; q < kChunks; ++q) agg += s_words[q];
+    if (lane == 0)
+      __hip_atomic_store(p.status + wg, (wg == 0 ? kZfInc : kZfAgg) | agg, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    int64_t end_j = wg;  // workgroups [0, end_j) are still to be summed
+    int spins = 0;
+    while (end_j > 0) {
+      const int64_t j = end_j - 1 - lane;
+      const uint64_t st = j >= 0 ? __hip_atomic_load(p.status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : kZfInc;  // before workgroup 0: an inclusive prefix of 0
+      const uint64_t inc = __ballot((st >> 62) == 2);
+      const int first = inc ? __builtin_ctzll(inc) : 64;  // nearest published prefix
+      const uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+      if (__ballot((st >> 62) == 0) & upto) {  // a workgroup in range has published nothing yet
+        if (++spins > kZfSpinLimit) {
+          if (lane == 0) atomicOr(p.flags, kZfSpin);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      uint64_t part = lane <= first ? (st & kZfValMask) : 0ull;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      excl += part;
+      if (first < 64) break;
+      end_j -= 64;
+    }
+    if (lane == 0) {
+      if (wg > 0)
+        __hip_atomic_store(p.status + wg, kZfInc | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t off = excl;
+      for (int q = 0; q < kChunks; ++q) {
+        const int64_t ch = wg * kChunks + q;
+        s_off[q] = off;
+        if (ch < p.nchunks) p.out[p.hdr_base + ch] = (uint32_t)off;  // the table lies below pay_base <= cap_words
+        off += s_words[q];
+      }
+      if (wg == (p.nchunks - 1) / kChunks) {  // the last chunk's workgroup writes the total
+        p.out[p.hdr_base + p.nchunks] = (uint32_t)off;
+        p.result[0] = (uint32_t)off;
+        p.result[1] = (uint32_t)(off >> 32);
+      }
+    }
+  }
+
+  // ---- the chunks' codes, assembled in LDS, at their offsets ----
+  uint32_t* cb = cbuf + (t / kZfChunk) * kZfChunkWords;
   const int w0 = pre >> 5, sh = pre & 31;
   for (int i = 0; i < sink.words; ++i) {
-    const uint32_t v = own[lane * kZfBlockWords + i];
+    const uint32_t v = own[t * kZfBlockWords + i];
     atomicOr(&cb[w0 + i], v << sh);
     if (sh && (v >> (32 - sh))) atomicOr(&cb[w0 + i + 1], v >> (32 - sh));
   }
-  __syncthreads();
-  const uint32_t* table = p.out + p.hdr_base;  // written by the scan
-  for (int i = lane; i < kChunks * kZfChunkWords; i += kZfThreads) {
+  __syncthreads();  // the codes assembled and the offsets written
+  for (int i = t; i < kChunks * kZfChunkWords; i += kT) {
     const int c = i / kZfChunkWords, w = i - c * kZfChunkWords;
-    const int64_t ch = (int64_t)blockIdx.x * kChunks + c;
-    if (ch >= p.nchunks) continue;
-    const int64_t off = table[ch], nw = (int64_t)table[ch + 1] - off;
-    const int64_t at = p.pay_base + off + w;
-    if (w < nw && at < p.cap_words) p.out[at] = cbuf[i];
+    const int64_t ch = wg * kChunks + c;
+    if (ch >= p.nchunks || w >= (int)s_words[c]) continue;
+    const int64_t at = p.pay_base + (int64_t)s_off[c] + w;
+    if (at < p.cap_words) p.out[at] = cbuf[i];
   }
 }
 
@@ -578,15 +518,10 @@ __global__ __launch_bounds__(kZfThreads) void k_zf_decode_staged(ZfParams p, int
 
 }  // namespace
 
-hipError_t launch_zf_encode(const ZfParams& p, uint32_t* counts, uint64_t* totals, hipStream_t s) {
+hipError_t launch_zf_encode(const ZfParams& p, hipStream_t s) {
   if (p.nchunks < 1) return hipErrorInvalidValue;
-  const int64_t gb = (p.nblocks + kZfThreads - 1) / kZfThreads;  // one lane per block
-  k_zf_count<<<(unsigned)gb, kZfThreads, 0, s>>>(p, counts);
-  const int64_t ng = (p.nchunks + kZfScan - 1) / kZfScan;
-  k_zf_scan_totals<<<(unsigned)ng, kZfScan, 0, s>>>(counts, p.nchunks, totals);
-  k_zf_scan_base<<<1, kZfScan, 0, s>>>(totals, ng);
-  k_zf_scan_table<<<(unsigned)ng, kZfScan, 0, s>>>(counts, p.nchunks, totals, p);
-  k_zf_encode<<<(unsigned)gb, kZfThreads, 0, s>>>(p);
+  const int64_t g = (p.nblocks + kZfEncThreads - 1) / kZfEncThreads;  // one lane per block
+  k_zf_encode<<<(unsigned)g, kZfEncThreads, 0, s>>>(p);
   return hipGetLastError();
 }
 
